@@ -1,0 +1,912 @@
+/*
+ * ibmx_oracle.c -- plain, sequential FP64 CPU oracle of the direct-forcing
+ * IBM outer forcing loop and of the collision pair pass of Yao et al.,
+ * "Particle-resolved simulations of four-way coupled, polydispersed,
+ * particle-laden flows" (arXiv 2109.03972).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  It shares no
+ * source, header, table or helper with the HIP library; the two meet only
+ * in the seeded input arrays.  It is written for a reader who checks it
+ * against the paper: no blocking, no fusion, no reordering.
+ *
+ * Conventions (all arrays row-major, caller-owned, host memory):
+ *   grid field     double [3][nz][ny][nx], x fastest; node (i,j,k) sits at
+ *                  origin + (i + 1/2, j + 1/2, k + 1/2) h (cell centres of the
+ *                  collocated finite-volume grid, Sec. 2.2.1).  A non-periodic
+ *                  axis has walls at origin and origin + n h.
+ *   particle data  double [3][np] (component-major).
+ *   markers        CSR offsets moff[np+1]; body offsets o_l = X_l - x_p as
+ *                  double [3][nm]; dV[p] is the marker volume of particle p.
+ *
+ * Return codes: 0 ok, -1 invalid argument, -2 an active marker's delta
+ * support leaves the grid through a wall, -6 list capacity exceeded.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define R_OK 0
+#define R_EINVAL (-1)
+#define R_EDOMAIN (-2)
+#define R_ECAPACITY (-6)
+
+/* ------------------------------------------------------------------------ */
+/* Regularized delta functions                                              */
+/* ------------------------------------------------------------------------ */
+
+/* Three-point function phi_3 of Roma et al. (Sec. 2.1, eq. 3pt-stencil). */
+double ref_phi3(double r)
+{
+    double a = fabs(r);
+    if (a <= 0.5)
+        return (1.0 + sqrt(1.0 - 3.0 * a * a)) / 3.0;
+    if (a <= 1.5)
+        return (5.0 - 3.0 * a - sqrt(1.0 - 3.0 * (1.0 - a) * (1.0 - a))) / 6.0;
+    return 0.0;
+}
+
+/* d phi_3 / d r, differentiated from the same formula. */
+double ref_dphi3(double r)
+{
+    double a = fabs(r);
+    double s = (r < 0.0) ? -1.0 : 1.0;
+    if (a <= 0.5) {
+        if (a == 0.0)
+            return 0.0;
+        return -r / sqrt(1.0 - 3.0 * r * r);
+    }
+    if (a <= 1.5) {
+        double b = 1.0 - a;
+        double q = sqrt(1.0 - 3.0 * b * b);
+        if (q == 0.0)
+            return 0.0;
+        return s * (-0.5 - 0.5 * b / q);
+    }
+    return 0.0;
+}
+
+/* Four-point function phi_4 of Peskin (Sec. 2.2.3, eq. 4pt-stencil).  The
+ * printed range of the first branch reads -2 <= r <= 1; the branch is the
+ * mirror of the last one, i.e. -2 <= r <= -1. */
+double ref_phi4(double r)
+{
+    if (r >= -2.0 && r <= -1.0)
+        return (5.0 + 2.0 * r - sqrt(-7.0 - 12.0 * r - 4.0 * r * r)) / 8.0;
+    if (r > -1.0 && r <= 0.0)
+        return (3.0 + 2.0 * r + sqrt(1.0 - 4.0 * r - 4.0 * r * r)) / 8.0;
+    if (r > 0.0 && r <= 1.0)
+        return (3.0 - 2.0 * r + sqrt(1.0 + 4.0 * r - 4.0 * r * r)) / 8.0;
+    if (r > 1.0 && r <= 2.0)
+        return (5.0 - 2.0 * r - sqrt(-7.0 + 12.0 * r - 4.0 * r * r)) / 8.0;
+    return 0.0;
+}
+
+double ref_dphi4(double r)
+{
+    if (r >= -2.0 && r <= -1.0) {
+        double q = sqrt(-7.0 - 12.0 * r - 4.0 * r * r);
+        return q == 0.0 ? 0.0 : (2.0 - (-12.0 - 8.0 * r) / (2.0 * q)) / 8.0;
+    }
+    if (r > -1.0 && r <= 0.0) {
+        double q = sqrt(1.0 - 4.0 * r - 4.0 * r * r);
+        return (2.0 + (-4.0 - 8.0 * r) / (2.0 * q)) / 8.0;
+    }
+    if (r > 0.0 && r <= 1.0) {
+        double q = sqrt(1.0 + 4.0 * r - 4.0 * r * r);
+        return (-2.0 + (4.0 - 8.0 * r) / (2.0 * q)) / 8.0;
+    }
+    if (r > 1.0 && r <= 2.0) {
+        double q = sqrt(-7.0 + 12.0 * r - 4.0 * r * r);
+        return q == 0.0 ? 0.0 : (-2.0 - (12.0 - 8.0 * r) / (2.0 * q)) / 8.0;
+    }
+    return 0.0;
+}
+
+static double phi_k(int kernel, double r) { return kernel == 4 ? ref_phi4(r) : ref_phi3(r); }
+static double dphi_k(int kernel, double r) { return kernel == 4 ? ref_dphi4(r) : ref_dphi3(r); }
+
+/* ------------------------------------------------------------------------ */
+/* Delta support of one marker                                              */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int cnt[3];          /* nodes per axis with nonzero weight window      */
+    long idx[3][4];      /* wrapped node index per axis                    */
+    double w[3][4];      /* phi(r) per axis                                */
+    double dw[3][4];     /* phi'(r) per axis                               */
+} support_t;
+
+/* Nodes whose 1-D delta weight can be nonzero: |x_i - X| / h < W/2, with
+ * x_i = origin + (i + 1/2) h.  The product of the three 1-D weights is
+ * delta_h,3D(x - X) h^3 (Sec. 2.1).  Periodic axes wrap the index; a node
+ * beyond a wall makes the marker invalid. */
+static int marker_support(const int *n, double h, const double *origin, const int *periodic,
+                          int kernel, const double *X, support_t *sp)
+{
+    double half = (kernel == 4) ? 2.0 : 1.5;
+    for (int a = 0; a < 3; ++a) {
+        double s = (X[a] - origin[a]) / h;          /* position in units of h */
+        long lo = (long)floor(s - 0.5 - half) + 1;   /* first i with i+1/2-s > -half */
+        int c = 0;
+        for (long i = lo; i < lo + 6; ++i) {
+            double r = ((double)i + 0.5) - s;
+            if (!(r < half))
+                break;
+            if (!(r > -half))
+                continue;
+            long ii = i;
+            if (periodic[a]) {
+                ii = i % n[a];
+                if (ii < 0)
+                    ii += n[a];
+            } else if (i < 0 || i >= n[a]) {
+                return R_EDOMAIN;
+            }
+            sp->idx[a][c] = ii;
+            sp->w[a][c] = phi_k(kernel, r);
+            sp->dw[a][c] = dphi_k(kernel, r);
+            ++c;
+        }
+        sp->cnt[a] = c;
+    }
+    return R_OK;
+}
+
+static int check_markers(const int *n, double h, const double *origin, const int *periodic,
+                         int kernel, int np, const int *moff, const double *body,
+                         const double *xp, const unsigned char *mask)
+{
+    int nm = moff[np];
+    for (int p = 0; p < np; ++p) {
+        if (moff[p + 1] < moff[p])
+            return R_EINVAL;
+        for (int l = moff[p]; l < moff[p + 1]; ++l) {
+            if (mask && !mask[l])
+                continue;
+            double X[3];
+            support_t sp;
+            for (int a = 0; a < 3; ++a)
+                X[a] = xp[a * np + p] + body[a * nm + l];
+            int st = marker_support(n, h, origin, periodic, kernel, X, &sp);
+            if (st != R_OK)
+                return st;
+        }
+    }
+    return R_OK;
+}
+
+static void cross(const double *a, const double *b, double *o)
+{
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* U_l = sum_x w(x - X_l) g(x) for one marker (Sec. 2.2.2, step 1). */
+static void interp3(const support_t *sp, long nx, long ny, long N, const double *g, double *U)
+{
+    U[0] = U[1] = U[2] = 0.0;
+    for (int k = 0; k < sp->cnt[2]; ++k)
+        for (int j = 0; j < sp->cnt[1]; ++j)
+            for (int i = 0; i < sp->cnt[0]; ++i) {
+                double w = sp->w[2][k] * sp->w[1][j] * sp->w[0][i];
+                long node = sp->idx[0][i] + nx * (sp->idx[1][j] + ny * sp->idx[2][k]);
+                for (int c = 0; c < 3; ++c)
+                    U[c] += w * g[c * N + node];
+            }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Outer forcing loop (Sec. 2.2.2)                                          */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * For m = 1..n_iter:
+ *   U^{m-1}_l = sum_x u^{m-1}(x) delta_h(x - X_l) h^3             (step 1)
+ *   F^{m-1}_l = (U^d_l - U^{m-1}_l) / c,  c = 2 alpha_k dt,
+ *               U^d_l = u_p + omega_p x (X_l - x_p)              (step 2)
+ *   f^{m-1}(x) = sum_l F^{m-1}_l delta_h(x - X_l) dV_l            (step 3)
+ *   u^m = u^{m-1} + c f^{m-1}                                     (step 4)
+ * Outputs: u <- u^{n_iter} (in place); f_tot += sum_m f^{m-1};
+ * S_p = sum_m sum_l F_l dV_l and T_p = sum_m sum_l (X_l - x_p) x F_l dV_l
+ * (the sums of Sec. 2.1, eq. basic-particle; the hydrodynamic force and
+ * torque are -rho_f S_p and -rho_f T_p); resid[m-1] = sqrt(sum_l dV_l
+ * |U^d_l - U^{m-1}_l|^2), the no-slip error of Sec. 2.2.2 weighted by the
+ * marker volumes; resid[n_iter] (if final_resid) measures u^{n_iter}.
+ * U_dbg (optional) receives U^{m-1}_l as [n_iter][3][nm] for active markers.
+ * Markers with mask[l] == 0 take no part (Sec. 2.3, disabling markers).
+ */
+int ref_forcing(const int *n, double h, const double *origin, const int *periodic,
+                int kernel, int n_iter, double c, int final_resid,
+                int np, const int *moff, const double *body, const double *dV,
+                const double *xp, const double *up, const double *wp,
+                const unsigned char *mask,
+                double *u, double *f_tot, double *S, double *T,
+                double *resid, double *U_dbg)
+{
+    if (!n || n[0] <= 0 || n[1] <= 0 || n[2] <= 0 || !(h > 0.0) || n_iter < 1 ||
+        !(c != 0.0) || np < 0 || (kernel != 3 && kernel != 4))
+        return R_EINVAL;
+    int st = check_markers(n, h, origin, periodic, kernel, np, moff, body, xp, mask);
+    if (st != R_OK)
+        return st;
+    long nx = n[0], ny = n[1], N = (long)n[0] * n[1] * n[2];
+    int nm = moff[np];
+    double h3 = h * h * h;
+    double *fm = (double *)malloc(sizeof(double) * 3 * (size_t)N);
+    if (!fm)
+        return R_EINVAL;
+    for (int i = 0; i < 3 * np; ++i) {
+        S[i] = 0.0;
+        T[i] = 0.0;
+    }
+    for (int m = 1; m <= n_iter; ++m) {
+        memset(fm, 0, sizeof(double) * 3 * (size_t)N);
+        double rsq = 0.0;
+        for (int p = 0; p < np; ++p) {
+            double upp[3], wpp[3];
+            for (int a = 0; a < 3; ++a) {
+                upp[a] = up[a * np + p];
+                wpp[a] = wp[a * np + p];
+            }
+            for (int l = moff[p]; l < moff[p + 1]; ++l) {
+                if (mask && !mask[l])
+                    continue;
+                double o[3], X[3], U[3], Ud[3], wxo[3], F[3], oxF[3];
+                support_t sp;
+                for (int a = 0; a < 3; ++a) {
+                    o[a] = body[a * nm + l];
+                    X[a] = xp[a * np + p] + o[a];
+                }
+                marker_support(n, h, origin, periodic, kernel, X, &sp);
+                interp3(&sp, nx, ny, N, u, U);                       /* step 1 */
+                if (U_dbg)
+                    for (int a = 0; a < 3; ++a)
+                        U_dbg[((size_t)(m - 1) * 3 + a) * nm + l] = U[a];
+                cross(wpp, o, wxo);
+                for (int a = 0; a < 3; ++a) {
+                    Ud[a] = upp[a] + wxo[a];
+                    double r = Ud[a] - U[a];
+                    rsq += dV[p] * r * r;
+                    F[a] = r / c;                                    /* step 2 */
+                    S[a * np + p] += F[a] * dV[p];
+                }
+                cross(o, F, oxF);
+                for (int a = 0; a < 3; ++a)
+                    T[a * np + p] += oxF[a] * dV[p];
+                for (int k = 0; k < sp.cnt[2]; ++k)                   /* step 3 */
+                    for (int j = 0; j < sp.cnt[1]; ++j)
+                        for (int i = 0; i < sp.cnt[0]; ++i) {
+                            double w = sp.w[2][k] * sp.w[1][j] * sp.w[0][i];
+                            long node = sp.idx[0][i] + nx * (sp.idx[1][j] + ny * sp.idx[2][k]);
+                            for (int a = 0; a < 3; ++a)
+                                fm[a * N + node] += F[a] * (w / h3) * dV[p];
+                        }
+            }
+        }
+        if (resid)
+            resid[m - 1] = sqrt(rsq);
+        for (long x = 0; x < 3 * N; ++x) {                           /* step 4 */
+            u[x] += c * fm[x];
+            f_tot[x] += fm[x];
+        }
+    }
+    if (final_resid && resid) {
+        double rsq = 0.0;
+        for (int p = 0; p < np; ++p)
+            for (int l = moff[p]; l < moff[p + 1]; ++l) {
+                if (mask && !mask[l])
+                    continue;
+                double o[3], X[3], U[3], wpp[3], wxo[3];
+                support_t sp;
+                for (int a = 0; a < 3; ++a) {
+                    o[a] = body[a * nm + l];
+                    X[a] = xp[a * np + p] + o[a];
+                    wpp[a] = wp[a * np + p];
+                }
+                marker_support(n, h, origin, periodic, kernel, X, &sp);
+                interp3(&sp, nx, ny, N, u, U);
+                cross(wpp, o, wxo);
+                for (int a = 0; a < 3; ++a) {
+                    double r = up[a * np + p] + wxo[a] - U[a];
+                    rsq += dV[p] * r * r;
+                }
+            }
+        resid[n_iter] = sqrt(rsq);
+    }
+    free(fm);
+    return R_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Adjoint of the forcing loop                                              */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Reverse-mode derivative of ref_forcing with the marker mask, the body
+ * offsets, dV and c held fixed.  Given dL/du^{n} (g_u, may be NULL), dL/df_tot
+ * (g_f, may be NULL), dL/dS (g_S) and dL/dT (g_T, may be NULL), writes dL/du^0
+ * (gu0), dL/dx_p (gxp), dL/du_p (gup) and dL/domega_p (gwp).
+ *
+ * The forward loop is replayed first, storing every u^{m-1} and F^{m-1}.
+ * Going backwards through each pass m, with ub = dL/du^m and
+ * fb = c ub + g_f (the cotangent of f^{m-1}):
+ *   Fb_l  = dV_l/h^3 (I fb)_l + dV_l (g_S,p + g_T,p x o_l)
+ *   Ub_l  = -Fb_l / c           (cotangent of U^{m-1}_l)
+ *   Udb_l = +Fb_l / c           (cotangent of U^d_l)
+ *   ub   <- ub + I^T Ub         (cotangent of u^{m-1})
+ *   Xb_l += sum_x grad_X w(x - X_l) [Ub_l . u^{m-1}(x) + dV_l/h^3 fb(x) . F_l]
+ * and finally gup_p = sum_l Udb_l, gwp_p = sum_l o_l x Udb_l, gxp_p =
+ * sum_l Xb_l (X_l = x_p + o_l), gu0 = ub.
+ */
+int ref_forcing_adjoint(const int *n, double h, const double *origin, const int *periodic,
+                        int kernel, int n_iter, double c,
+                        int np, const int *moff, const double *body, const double *dV,
+                        const double *xp, const double *up, const double *wp,
+                        const unsigned char *mask, const double *u0,
+                        const double *g_f, const double *g_u, const double *g_S, const double *g_T,
+                        double *gu0, double *gxp, double *gup, double *gwp)
+{
+    if (!n || n[0] <= 0 || n[1] <= 0 || n[2] <= 0 || !(h > 0.0) || n_iter < 1 ||
+        !(c != 0.0) || np < 0 || (kernel != 3 && kernel != 4))
+        return R_EINVAL;
+    int st = check_markers(n, h, origin, periodic, kernel, np, moff, body, xp, mask);
+    if (st != R_OK)
+        return st;
+    long nx = n[0], ny = n[1], N = (long)n[0] * n[1] * n[2];
+    int nm = moff[np];
+    double h3 = h * h * h;
+    size_t G = 3 * (size_t)N;
+    double *us = (double *)malloc(sizeof(double) * G * (size_t)(n_iter + 1));
+    double *Fs = (double *)malloc(sizeof(double) * 3 * (size_t)nm * n_iter);
+    double *fb = (double *)malloc(sizeof(double) * G);
+    double *dub = (double *)malloc(sizeof(double) * G);
+    double *ftmp = (double *)malloc(sizeof(double) * G);
+    double *S = (double *)malloc(sizeof(double) * 3 * (size_t)(np ? np : 1));
+    double *T = (double *)malloc(sizeof(double) * 3 * (size_t)(np ? np : 1));
+    if (!us || !Fs || !fb || !dub || !ftmp || !S || !T) {
+        free(us); free(Fs); free(fb); free(dub); free(ftmp); free(S); free(T);
+        return R_EINVAL;
+    }
+    /* forward replay: one pass at a time, keeping u^{m-1} and F^{m-1} */
+    memcpy(us, u0, sizeof(double) * G);
+    for (int m = 1; m <= n_iter; ++m) {
+        double *um1 = us + (size_t)(m - 1) * G;
+        double *um = us + (size_t)m * G;
+        memcpy(um, um1, sizeof(double) * G);
+        memset(ftmp, 0, sizeof(double) * G);
+        /* a single pass of the forward loop writes u^m and the markers' F */
+        for (int p = 0; p < np; ++p)
+            for (int l = moff[p]; l < moff[p + 1]; ++l) {
+                if (mask && !mask[l])
+                    continue;
+                double o[3], X[3], U[3], wpp[3], wxo[3];
+                support_t sp;
+                for (int a = 0; a < 3; ++a) {
+                    o[a] = body[a * nm + l];
+                    X[a] = xp[a * np + p] + o[a];
+                    wpp[a] = wp[a * np + p];
+                }
+                marker_support(n, h, origin, periodic, kernel, X, &sp);
+                interp3(&sp, nx, ny, N, um1, U);
+                cross(wpp, o, wxo);
+                double F[3];
+                for (int a = 0; a < 3; ++a) {
+                    F[a] = (up[a * np + p] + wxo[a] - U[a]) / c;
+                    Fs[((size_t)(m - 1) * 3 + a) * nm + l] = F[a];
+                }
+                for (int k = 0; k < sp.cnt[2]; ++k)
+                    for (int j = 0; j < sp.cnt[1]; ++j)
+                        for (int i = 0; i < sp.cnt[0]; ++i) {
+                            double w = sp.w[2][k] * sp.w[1][j] * sp.w[0][i];
+                            long node = sp.idx[0][i] + nx * (sp.idx[1][j] + ny * sp.idx[2][k]);
+                            for (int a = 0; a < 3; ++a)
+                                ftmp[a * N + node] += F[a] * (w / h3) * dV[p];
+                        }
+            }
+        for (size_t x = 0; x < G; ++x)
+            um[x] += c * ftmp[x];
+    }
+    /* reverse sweep */
+    for (size_t x = 0; x < G; ++x)
+        gu0[x] = g_u ? g_u[x] : 0.0;
+    for (int i = 0; i < 3 * np; ++i) {
+        gxp[i] = 0.0;
+        gup[i] = 0.0;
+        gwp[i] = 0.0;
+    }
+    for (int m = n_iter; m >= 1; --m) {
+        const double *um1 = us + (size_t)(m - 1) * G;
+        for (size_t x = 0; x < G; ++x)
+            fb[x] = c * gu0[x] + (g_f ? g_f[x] : 0.0);
+        memset(dub, 0, sizeof(double) * G);
+        for (int p = 0; p < np; ++p) {
+            double gS[3], gT[3];
+            for (int a = 0; a < 3; ++a) {
+                gS[a] = g_S ? g_S[a * np + p] : 0.0;
+                gT[a] = g_T ? g_T[a * np + p] : 0.0;
+            }
+            for (int l = moff[p]; l < moff[p + 1]; ++l) {
+                if (mask && !mask[l])
+                    continue;
+                double o[3], X[3], IF[3], F[3], gTxo[3], Fb[3], Ub[3], Udb[3], oxUdb[3];
+                support_t sp;
+                for (int a = 0; a < 3; ++a) {
+                    o[a] = body[a * nm + l];
+                    X[a] = xp[a * np + p] + o[a];
+                    F[a] = Fs[((size_t)(m - 1) * 3 + a) * nm + l];
+                }
+                marker_support(n, h, origin, periodic, kernel, X, &sp);
+                interp3(&sp, nx, ny, N, fb, IF);
+                cross(gT, o, gTxo);
+                for (int a = 0; a < 3; ++a) {
+                    Fb[a] = dV[p] / h3 * IF[a] + dV[p] * (gS[a] + gTxo[a]);
+                    Ub[a] = -Fb[a] / c;
+                    Udb[a] = Fb[a] / c;
+                    gup[a * np + p] += Udb[a];
+                }
+                cross(o, Udb, oxUdb);
+                for (int a = 0; a < 3; ++a)
+                    gwp[a * np + p] += oxUdb[a];
+                double Xb[3] = {0.0, 0.0, 0.0};
+                for (int k = 0; k < sp.cnt[2]; ++k)
+                    for (int j = 0; j < sp.cnt[1]; ++j)
+                        for (int i = 0; i < sp.cnt[0]; ++i) {
+                            double wx = sp.w[0][i], wy = sp.w[1][j], wz = sp.w[2][k];
+                            long node = sp.idx[0][i] + nx * (sp.idx[1][j] + ny * sp.idx[2][k]);
+                            double w = wz * wy * wx;
+                            /* r = (x - X)/h, so d w / d X_a = -(1/h) phi'(r_a) prod_others */
+                            double gw[3] = {-sp.dw[0][i] * wy * wz / h,
+                                            -wx * sp.dw[1][j] * wz / h,
+                                            -wx * wy * sp.dw[2][k] / h};
+                            double s1 = 0.0, s2 = 0.0;
+                            for (int a = 0; a < 3; ++a) {
+                                s1 += Ub[a] * um1[a * N + node];
+                                s2 += fb[a * N + node] * F[a];
+                            }
+                            for (int a = 0; a < 3; ++a)
+                                Xb[a] += gw[a] * (s1 + dV[p] / h3 * s2);
+                            for (int a = 0; a < 3; ++a)
+                                dub[a * N + node] += w * Ub[a];
+                        }
+                for (int a = 0; a < 3; ++a)
+                    gxp[a * np + p] += Xb[a];
+            }
+        }
+        for (size_t x = 0; x < G; ++x)
+            gu0[x] += dub[x];
+    }
+    free(us); free(Fs); free(fb); free(dub); free(ftmp); free(S); free(T);
+    return R_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Pair pass: cell list, pair and wall lists, collision forces, marker mask */
+/* ------------------------------------------------------------------------ */
+
+/* Position wrapped into [origin, origin + L) on a periodic axis. */
+static double wrap_pos(double x, double o, double L)
+{
+    double t = floor((x - o) / L);
+    return x - t * L;
+}
+
+/* Minimum-image displacement on a periodic axis. */
+static double min_image(double d, double L)
+{
+    while (d > 0.5 * L)
+        d = d - L;
+    while (d < -0.5 * L)
+        d = d + L;
+    return d;
+}
+
+static void wrapped_centre(const int *n, double h, const double *origin, const int *periodic,
+                           int np, const double *xp, int p, double *x)
+{
+    for (int a = 0; a < 3; ++a) {
+        double L = n[a] * h;
+        x[a] = periodic[a] ? wrap_pos(xp[a * np + p], origin[a], L) : xp[a * np + p];
+    }
+}
+
+/* Pair displacement x_q - x_p (minimum image) and squared distance, summed
+ * in the order dx^2 + dy^2 + dz^2. */
+static double pair_disp(const int *n, double h, const double *origin, const int *periodic,
+                        int np, const double *xp, int p, int q, double *d)
+{
+    double a_[3], b_[3];
+    wrapped_centre(n, h, origin, periodic, np, xp, p, a_);
+    wrapped_centre(n, h, origin, periodic, np, xp, q, b_);
+    for (int a = 0; a < 3; ++a) {
+        d[a] = b_[a] - a_[a];
+        if (periodic[a])
+            d[a] = min_image(d[a], n[a] * h);
+    }
+    double d2 = d[0] * d[0];
+    d2 = d2 + d[1] * d[1];
+    d2 = d2 + d[2] * d[2];
+    return d2;
+}
+
+/* Uniform cell grid for the neighbour search: per axis nc = max(1,
+ * floor(L / (2 R_max + gap_cut))) cells of edge L / nc, so every pair
+ * within reach lies in neighbouring cells.  cell = floor((x - origin) / edge)
+ * of the wrapped centre, clamped to [0, nc - 1].  Particles are listed per
+ * cell in increasing id (a stable counting sort). */
+int ref_cell_list(const int *n, double h, const double *origin, const int *periodic,
+                  int np, const double *xp, const double *radius, double gap_cut,
+                  int *nc, int cap_cells, int *cell_of, int *cell_start, int *cell_particles)
+{
+    if (np < 0)
+        return R_EINVAL;
+    double rmax = 0.0;
+    for (int p = 0; p < np; ++p)
+        if (radius[p] > rmax)
+            rmax = radius[p];
+    double edge[3];
+    for (int a = 0; a < 3; ++a) {
+        double L = n[a] * h;
+        int k = (int)floor(L / (2.0 * rmax + gap_cut));
+        nc[a] = k < 1 ? 1 : k;
+        edge[a] = L / nc[a];
+    }
+    long ncell = (long)nc[0] * nc[1] * nc[2];
+    if (ncell > cap_cells)
+        return R_ECAPACITY;
+    for (long cidx = 0; cidx <= ncell; ++cidx)
+        cell_start[cidx] = 0;
+    for (int p = 0; p < np; ++p) {
+        double x[3];
+        int ci[3];
+        wrapped_centre(n, h, origin, periodic, np, xp, p, x);
+        for (int a = 0; a < 3; ++a) {
+            double t = floor((x[a] - origin[a]) / edge[a]);
+            int v = (int)t;
+            if (t < 0.0)
+                v = 0;
+            if (t > (double)(nc[a] - 1))
+                v = nc[a] - 1;
+            ci[a] = v;
+        }
+        cell_of[p] = ci[0] + nc[0] * (ci[1] + nc[1] * ci[2]);
+        cell_start[cell_of[p] + 1] += 1;
+    }
+    for (long cidx = 0; cidx < ncell; ++cidx)
+        cell_start[cidx + 1] += cell_start[cidx];
+    int *fill = (int *)calloc((size_t)ncell, sizeof(int));
+    if (!fill)
+        return R_EINVAL;
+    for (int p = 0; p < np; ++p) {
+        int cc = cell_of[p];
+        cell_particles[cell_start[cc] + fill[cc]] = p;
+        fill[cc] += 1;
+    }
+    free(fill);
+    return R_OK;
+}
+
+/* All pairs i < j with centre distance below R_i + R_j + gap_cut (compared
+ * squared), in lexicographic (i, j) order -- the brute-force definition of
+ * the set the sum over q != p in eq. f_int runs over.  gap = d - R_i - R_j
+ * is the separation zeta_n of Sec. 2.3. */
+int ref_pairs_brute(const int *n, double h, const double *origin, const int *periodic,
+                    int np, const double *xp, const double *radius, double gap_cut,
+                    int cap, int *pairs, double *gap, int *npairs)
+{
+    int cnt = 0;
+    for (int i = 0; i < np; ++i)
+        for (int j = i + 1; j < np; ++j) {
+            double d[3];
+            double d2 = pair_disp(n, h, origin, periodic, np, xp, i, j, d);
+            double cut = radius[i] + radius[j] + gap_cut;
+            if (d2 < cut * cut) {
+                if (cnt < cap) {
+                    pairs[cnt] = i;
+                    pairs[cap + cnt] = j;
+                    gap[cnt] = sqrt(d2) - radius[i] - radius[j];
+                }
+                ++cnt;
+            }
+        }
+    *npairs = cnt;
+    return cnt > cap ? R_ECAPACITY : R_OK;
+}
+
+/* Wall entries (particle, side) with side = 2 axis + (0 lower, 1 upper) for
+ * every non-periodic axis, listed when the surface gap to the wall is below
+ * gap_cut, in (particle, side) order. */
+int ref_walls(const int *n, double h, const double *origin, const int *periodic,
+              int np, const double *xp, const double *radius, double gap_cut,
+              int cap, int *walls, double *gap, int *nwall)
+{
+    int cnt = 0;
+    for (int p = 0; p < np; ++p)
+        for (int a = 0; a < 3; ++a) {
+            if (periodic[a])
+                continue;
+            double L = n[a] * h;
+            double x = xp[a * np + p];
+            for (int side = 0; side < 2; ++side) {
+                double dist = side == 0 ? (x - origin[a]) : (origin[a] + L - x);
+                double g = dist - radius[p];
+                if (g < gap_cut) {
+                    if (cnt < cap) {
+                        walls[cnt] = p;
+                        walls[cap + cnt] = 2 * a + side;
+                        gap[cnt] = g;
+                    }
+                    ++cnt;
+                }
+            }
+        }
+    *nwall = cnt;
+    return cnt > cap ? R_ECAPACITY : R_OK;
+}
+
+typedef struct {
+    double rho_f, nu_f, eps_sep, lub_C, zeta_min_factor, e_dry, T_c, mu_s, mu_k, nu_poi, dt, h;
+} coll_params;
+
+/*
+ * Collision force on particle p from a partner across the contact plane
+ * with unit normal nvec (pointing from p to the partner).  Inputs: surface
+ * gap zeta, relative contact-point velocity g (Sec. 2.3: g_cp), effective
+ * radius and mass, the tangential spring displacement of the previous call
+ * (zt_old, zero for a new contact).  Returns F (force on p) and the updated
+ * spring zt_new.
+ *
+ *   regime (Sec. 2.3, eq. f_int cases): contact if zeta < 0, lubrication if
+ *   0 <= zeta < eps_sep, nothing otherwise.
+ *   lubrication: F = -6 pi rho_f nu_f R_eff^2 psi / max(zeta_min, zeta) g_n,
+ *     psi = erf(6 - C max(zeta_min, zeta)/h)/2 + 1/2 (Sec. 2.3, lubrication).
+ *   normal contact: linear spring-dashpot F_n = -k_n |zeta| n - d_n g_n, with
+ *     k_n, d_n the damped-oscillator coefficients giving restitution e_dry
+ *     over the contact time T_c (the linear form of eq. ode).
+ *   tangential contact (Sec. 2.3, tangential model): spring-dashpot
+ *     F_dp = -k_t zeta_t - d_t g_t, capped by Coulomb friction; mu_s while
+ *     sticking, mu_k when slipping, with the spring reset on slip.
+ */
+static void contact_law(const coll_params *P, double zeta, const double *nvec, const double *g,
+                        double Reff, double meff, double zmin, const double *zt_old,
+                        double *F, double *Ft_out, double *zt_new)
+{
+    double gn = g[0] * nvec[0] + g[1] * nvec[1] + g[2] * nvec[2];
+    double gnv[3], gtv[3];
+    for (int a = 0; a < 3; ++a) {
+        gnv[a] = gn * nvec[a];
+        gtv[a] = g[a] - gnv[a];
+        F[a] = 0.0;
+        Ft_out[a] = 0.0;
+        zt_new[a] = 0.0;
+    }
+    if (zeta >= P->eps_sep)
+        return;
+    if (zeta >= 0.0) {
+        double zz = zeta > zmin ? zeta : zmin;
+        double psi = 0.5 * erf(6.0 - P->lub_C * zz / P->h) + 0.5;
+        double coef = 6.0 * M_PI * P->rho_f * P->nu_f * Reff * Reff * psi / zz;
+        for (int a = 0; a < 3; ++a)
+            F[a] = -coef * gnv[a];
+        return;
+    }
+    double le = log(P->e_dry);
+    double kn = meff * (M_PI * M_PI + le * le) / (P->T_c * P->T_c);
+    double dn = -2.0 * meff * le / P->T_c;
+    double Fn[3];
+    for (int a = 0; a < 3; ++a)
+        Fn[a] = -kn * fabs(zeta) * nvec[a] - dn * gnv[a];
+    double kt = 2.0 * (1.0 - P->nu_poi) / (2.0 - P->nu_poi) * kn;
+    double dt_ = 2.0 * sqrt(meff * kt) * (-le) / sqrt(M_PI * M_PI + le * le);
+    /* spring: previous displacement projected on the current tangent plane,
+     * plus g_t dt */
+    double zon = zt_old[0] * nvec[0] + zt_old[1] * nvec[1] + zt_old[2] * nvec[2];
+    double zt[3], Fdp[3];
+    for (int a = 0; a < 3; ++a) {
+        zt[a] = (zt_old[a] - zon * nvec[a]) + gtv[a] * P->dt;
+        Fdp[a] = -kt * zt[a] - dt_ * gtv[a];
+    }
+    double nFdp = sqrt(Fdp[0] * Fdp[0] + Fdp[1] * Fdp[1] + Fdp[2] * Fdp[2]);
+    double nFn = sqrt(Fn[0] * Fn[0] + Fn[1] * Fn[1] + Fn[2] * Fn[2]);
+    double Ft[3];
+    if (nFdp <= P->mu_s * nFn) {
+        for (int a = 0; a < 3; ++a)
+            Ft[a] = Fdp[a];
+    } else {
+        for (int a = 0; a < 3; ++a) {
+            Ft[a] = P->mu_k * nFn * Fdp[a] / nFdp;
+            zt[a] = -(Ft[a] + dt_ * gtv[a]) / kt;
+        }
+    }
+    for (int a = 0; a < 3; ++a) {
+        F[a] = Fn[a] + Ft[a];
+        Ft_out[a] = Ft[a];
+        zt_new[a] = zt[a];
+    }
+}
+
+static int find_pair(int n_in, const int *pairs_in, int i, int j)
+{
+    for (int k = 0; k < n_in; ++k)
+        if (pairs_in[k] == i && pairs_in[n_in + k] == j)
+            return k;
+    return -1;
+}
+
+/*
+ * Collision force and torque on every particle (eq. f_int): the sum over
+ * listed pairs and walls of F_n + F_t, and of R_cp n x F_t.  For a pair
+ * (p, q), n = (x_q - x_p)/d, the contact-point lever arms are
+ * R_p,cp = (d + R_p - R_q)/2 and R_q,cp = (d + R_q - R_p)/2 (Sec. 2.3), and
+ * g = (u_p - u_q) + R_p,cp omega_p x n + R_q,cp omega_q x n.  p receives F,
+ * q receives -F; both receive the torque R_cp n x F_t.  R_eff =
+ * R_p R_q/(R_p + R_q), m_eff = m_p m_q/(m_p + m_q), zeta_min = factor *
+ * min(R_p, R_q).  A wall is the limit R_q, m_q -> infinity at rest: R_eff =
+ * R_p, m_eff = m_p, lever arm R_pw,cp = |x_w - x_p| (Sec. 2.3).
+ * Spring history is looked up by the (i, j) key of the previous call's list
+ * (and by (p, side) for walls).
+ */
+int ref_pair_forces(const int *n, double h, const double *origin, const int *periodic,
+                    int np, const double *xp, const double *radius, const double *mass,
+                    const double *up, const double *wp, const double *cpar /* [11] */,
+                    int npairs, const int *pairs, int nwall, const int *walls,
+                    int npairs_in, const int *pairs_in, const double *hist_in,
+                    int nwall_in, const int *walls_in, const double *whist_in,
+                    double *Fc, double *Tc, double *hist_out, double *whist_out)
+{
+    coll_params P = {cpar[0], cpar[1], cpar[2], cpar[3], cpar[4], cpar[5], cpar[6],
+                     cpar[7], cpar[8], cpar[9], cpar[10], h};
+    for (int i = 0; i < 3 * np; ++i) {
+        Fc[i] = 0.0;
+        Tc[i] = 0.0;
+    }
+    for (int k = 0; k < npairs; ++k) {
+        int p = pairs[k], q = pairs[npairs + k];
+        double dvec[3];
+        double d = sqrt(pair_disp(n, h, origin, periodic, np, xp, p, q, dvec));
+        double Rp = radius[p], Rq = radius[q];
+        double zeta = d - Rp - Rq;
+        double nvec[3] = {dvec[0] / d, dvec[1] / d, dvec[2] / d};
+        double Rpc = 0.5 * (d + Rp - Rq), Rqc = 0.5 * (d + Rq - Rp);
+        double wpn[3], wqn[3], g[3];
+        double wpp[3] = {wp[p], wp[np + p], wp[2 * np + p]};
+        double wqq[3] = {wp[q], wp[np + q], wp[2 * np + q]};
+        cross(wpp, nvec, wpn);
+        cross(wqq, nvec, wqn);
+        for (int a = 0; a < 3; ++a)
+            g[a] = (up[a * np + p] - up[a * np + q]) + Rpc * wpn[a] + Rqc * wqn[a];
+        double Reff = Rp * Rq / (Rp + Rq);
+        double meff = mass[p] * mass[q] / (mass[p] + mass[q]);
+        double zmin = P.zeta_min_factor * (Rp < Rq ? Rp : Rq);
+        double zold[3] = {0.0, 0.0, 0.0};
+        int kin = find_pair(npairs_in, pairs_in, p, q);
+        if (kin >= 0)
+            for (int a = 0; a < 3; ++a)
+                zold[a] = hist_in[a * npairs_in + kin];
+        double F[3], Ft[3], zt[3], nxFt[3];
+        contact_law(&P, zeta, nvec, g, Reff, meff, zmin, zold, F, Ft, zt);
+        cross(nvec, Ft, nxFt);
+        for (int a = 0; a < 3; ++a) {
+            Fc[a * np + p] += F[a];
+            Fc[a * np + q] -= F[a];
+            Tc[a * np + p] += Rpc * nxFt[a];
+            Tc[a * np + q] += Rqc * nxFt[a];
+            hist_out[a * npairs + k] = zt[a];
+        }
+    }
+    for (int k = 0; k < nwall; ++k) {
+        int p = walls[k], side = walls[nwall + k];
+        int ax = side / 2, up_side = side % 2;
+        double L = n[ax] * h;
+        double x = xp[ax * np + p];
+        double dist = up_side == 0 ? (x - origin[ax]) : (origin[ax] + L - x);
+        double Rp = radius[p];
+        double zeta = dist - Rp;
+        double nvec[3] = {0.0, 0.0, 0.0};
+        nvec[ax] = up_side == 0 ? -1.0 : 1.0;
+        double wpp[3] = {wp[p], wp[np + p], wp[2 * np + p]};
+        double wpn[3], g[3];
+        cross(wpp, nvec, wpn);
+        for (int a = 0; a < 3; ++a)
+            g[a] = up[a * np + p] + dist * wpn[a];
+        double zold[3] = {0.0, 0.0, 0.0};
+        for (int kk = 0; kk < nwall_in; ++kk)
+            if (walls_in[kk] == p && walls_in[nwall_in + kk] == side)
+                for (int a = 0; a < 3; ++a)
+                    zold[a] = whist_in[a * nwall_in + kk];
+        double F[3], Ft[3], zt[3], nxFt[3];
+        contact_law(&P, zeta, nvec, g, Rp, mass[p], P.zeta_min_factor * Rp, zold, F, Ft, zt);
+        cross(nvec, Ft, nxFt);
+        for (int a = 0; a < 3; ++a) {
+            Fc[a * np + p] += F[a];
+            Tc[a * np + p] += dist * nxFt[a];
+            whist_out[a * nwall + k] = zt[a];
+        }
+    }
+    return R_OK;
+}
+
+/* SplitMix64 output function (Steele, Lea & Flood, OOPSLA 2014). */
+uint64_t ref_splitmix64(uint64_t x)
+{
+    uint64_t z = x + 0x9e3779b97f4a7c15ULL;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+/*
+ * Marker disabling (Sec. 2.3): markers leave the forcing when a particle is
+ * closer than eps_sep to a wall or closer than 2 eps_sep to another
+ * particle; for a particle pair only one of the two, chosen at random, loses
+ * markers.  The random choice for pair (p, q), p < q, is the low bit of
+ * splitmix64(seed ^ (p << 32 | q)): 0 picks p, 1 picks q.
+ *   mode 1 (local): the chosen particle loses the markers X_l with
+ *     |X_l - x_partner| < R_partner + 2 eps_sep (compared squared); a
+ *     particle near a wall loses the markers closer than eps_sep to it.
+ *   mode 2 (whole): the chosen particle (or the particle near a wall) loses
+ *     all its markers.
+ *   mode 0: nothing is disabled.
+ * mask[l] = 1 keeps marker l, 0 disables it.
+ */
+int ref_marker_mask(const int *n, double h, const double *origin, const int *periodic,
+                    int np, const int *moff, const double *body, const double *xp,
+                    const double *radius, double eps_sep, int mode, uint64_t seed,
+                    int npairs, const int *pairs, const double *pgap,
+                    int nwall, const int *walls, const double *wgap, unsigned char *mask)
+{
+    int nm = moff[np];
+    for (int l = 0; l < nm; ++l)
+        mask[l] = 1;
+    if (mode == 0)
+        return R_OK;
+    for (int k = 0; k < npairs; ++k) {
+        if (!(pgap[k] < 2.0 * eps_sep))
+            continue;
+        int p = pairs[k], q = pairs[npairs + k];
+        uint64_t key = ((uint64_t)(uint32_t)p << 32) | (uint64_t)(uint32_t)q;
+        int chosen = (ref_splitmix64(seed ^ key) & 1ULL) == 0 ? p : q;
+        int partner = chosen == p ? q : p;
+        double xc[3], xq[3];
+        wrapped_centre(n, h, origin, periodic, np, xp, chosen, xc);
+        wrapped_centre(n, h, origin, periodic, np, xp, partner, xq);
+        double lim = radius[partner] + 2.0 * eps_sep;
+        for (int l = moff[chosen]; l < moff[chosen + 1]; ++l) {
+            if (mode == 2) {
+                mask[l] = 0;
+                continue;
+            }
+            double d[3];
+            for (int a = 0; a < 3; ++a) {
+                d[a] = (xc[a] + body[a * nm + l]) - xq[a];
+                if (periodic[a])
+                    d[a] = min_image(d[a], n[a] * h);
+            }
+            double d2 = d[0] * d[0];
+            d2 = d2 + d[1] * d[1];
+            d2 = d2 + d[2] * d[2];
+            if (d2 < lim * lim)
+                mask[l] = 0;
+        }
+    }
+    for (int k = 0; k < nwall; ++k) {
+        if (!(wgap[k] < eps_sep))
+            continue;
+        int p = walls[k], side = walls[nwall + k];
+        int ax = side / 2, up_side = side % 2;
+        double L = n[ax] * h;
+        for (int l = moff[p]; l < moff[p + 1]; ++l) {
+            if (mode == 2) {
+                mask[l] = 0;
+                continue;
+            }
+            double X = xp[ax * np + p] + body[ax * nm + l];
+            double dist = up_side == 0 ? (X - origin[ax]) : (origin[ax] + L - X);
+            if (dist < eps_sep)
+                mask[l] = 0;
+        }
+    }
+    return R_OK;
+}
