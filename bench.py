@@ -1,0 +1,198 @@
+"""Benchmark of the forcing-loop hot path on one MI355X.
+
+One step = the pair pass (cell/pair/wall lists, collision forces, marker
+mask) + one ibmx_forcing call (marker geometry, then n_iter passes of
+interpolate -> force -> spread -> update) on the resident synthetic workload.
+The reported value is whole-step throughput in marker-updates/s
+(active markers x passes / step time).  Also reported: the FP64 instance of
+the same kernels, per-kernel durations from HIP events recorded by the
+library on its own stream, the roofline of the dominant kernel, and the CPU
+oracle timed on a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, public figure
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(kind: str, s: int, n_act: int, shell: int) -> float:
+    """Bytes the kernel must move per launch (one forcing pass).
+
+    interp: per active marker the record (packed node 4 B, fractions 3s,
+            body offset 3s) plus the spreading amplitude it writes (3s); per
+            shell node one read of the three velocity components (3s).
+    spread: per active marker the record (4 B + 3s) and the amplitude (3s);
+            per shell node a read-modify-write of u and of f_tot (4 x 3s).
+    """
+    if kind == "interp":
+        return n_act * (4 + 9 * s) + shell * 3 * s
+    if kind == "spread":
+        return n_act * (4 + 6 * s) + shell * 12 * s
+    raise KeyError(kind)
+
+
+def run_gpu(case, precision, steps, warmup, profile=True):
+    import torch
+    from paper_2109_03972_amd import ibmx
+
+    dev = torch.device("cuda:0")
+    T = torch.float64 if precision == "f64" else torch.float32
+    f64 = torch.float64
+    D = {k: torch.as_tensor(getattr(case, k), dtype=f64).to(dev).contiguous()
+         for k in ("xp", "up", "wp", "radius", "mass", "body", "dV")}
+    u = case.field(device=dev).to(T).contiguous()
+    f = torch.zeros_like(u)
+    plan = ibmx.Plan.from_case(case, precision)
+    plan.set_markers(D["body"], D["dV"])
+    n_iter = int(case.params["n_iter"])
+    mask = torch.empty(case.nm, dtype=torch.uint8, device=dev)
+    resid = torch.zeros(n_iter + 1, dtype=f64, device=dev)
+    res = plan.pairs(D["xp"], D["radius"], D["mass"], D["up"], D["wp"], mask=mask)
+    plan.check("pairs")
+    t = ibmx.trim_pairs(res)
+    prev = dict(pairs=t["pairs"].contiguous(), hist=t["hist"].contiguous(),
+                walls=t["walls"].contiguous(), whist=t["whist"].contiguous())
+    caps = dict(pair_cap=res["pair_cap"], wall_cap=res["wall_cap"])
+
+    def step():
+        r = plan.pairs(D["xp"], D["radius"], D["mass"], D["up"], D["wp"], prev=prev, mask=mask,
+                       **caps)
+        plan.forcing(u, f, D["xp"], D["up"], D["wp"], mask=mask, resid=resid)
+        return r
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.check("warmup")
+    if profile:
+        plan.profile(True)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record()
+    for _ in range(steps):
+        step()
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    plan.check("timed steps")
+    ms = start.elapsed_time(stop) / steps
+    st = plan.stats()
+    if profile:
+        plan.profile(False)
+    out = dict(ms_per_step=ms, wall_s=wall, stats=st, n_iter=n_iter,
+               resid=resid.cpu().numpy().tolist())
+    del u, f, D
+    plan.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(case, mask_np):
+    """Oracle (plain FP64, single thread) timed on one forcing pass over all
+    markers of the workload on its full grid."""
+    import numpy as np
+    import oracle
+    u0 = case.field().numpy()
+    case.u0 = u0
+    t0 = time.perf_counter()
+    oracle.forcing(case, mask=mask_np, n_iter=1, final_resid=False)
+    t = time.perf_counter() - t0
+    n_act = int(mask_np.sum()) if mask_np is not None else case.nm
+    case.u0 = None
+    del u0
+    return dict(value=n_act / t, unit="marker-updates/s", cores=1, kind="oracle",
+                sample=f"1 forcing pass over all {n_act} active markers of the workload on its "
+                       f"full {case.n[0]}x{case.n[1]}x{case.n[2]} grid ({t:.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="polydisperse_bed_512")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (--gpus 1); the forcing loop is not "
+              "sharded across GPUs", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2109_03972_amd import synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    log(f"bench: generating {args.workload}")
+    case = synth.make_case(args.workload, lazy_field=True)
+    log(f"bench: {case.np_} particles, {case.nm} markers, grid {case.n}")
+
+    log("bench: FP32 run")
+    r32 = run_gpu(case, "f32", args.steps, args.warmup)
+    st = r32["stats"]
+    n_act, shell, n_iter = int(st["n_active"]), int(st["shell_nodes"]), r32["n_iter"]
+    value = n_act * n_iter / (r32["ms_per_step"] * 1e-3)
+    km, kn = st["kernel_ms"], st["kernel_launches"]
+    per_launch = {k: (km[k] / kn[k] if kn[k] else None) for k in km}
+    dom = max(("interp", "spread"), key=lambda k: km[k])
+    bytes_launch = algorithmic_bytes(dom, 4, n_act, shell)
+    achieved = bytes_launch / (per_launch[dom] * 1e-3) / 1e9
+    roof = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
+                unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                bytes_per_launch=bytes_launch, ms_per_launch=per_launch[dom])
+    log(f"bench: FP32 {r32['ms_per_step']:.3f} ms/step, {value:.3e} marker-updates/s")
+
+    fp64 = None
+    if not args.no_fp64:
+        log("bench: FP64 run")
+        r64 = run_gpu(case, "f64", args.steps, args.warmup)
+        v64 = n_act * n_iter / (r64["ms_per_step"] * 1e-3)
+        fp64 = dict(value=v64, ms_per_step=r64["ms_per_step"], speedup_f32_over_f64=value / v64,
+                    kernel_ms_per_launch={k: (r64["stats"]["kernel_ms"][k] / n if n else None)
+                                          for k, n in r64["stats"]["kernel_launches"].items()})
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("bench: CPU oracle baseline")
+        import oracle
+        pl = oracle.pairs(case)
+        mask_np = oracle.marker_mask(case, pl)
+        cpu = cpu_baseline(case, mask_np)
+
+    line = dict(
+        metric="marker-updates/s per forcing iter (FP32 batched vs FP64) at stated tol; HBM GB/s",
+        value=value, unit="marker-updates/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+        ms_per_step=r32["ms_per_step"], higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype="f32", data="synthetic",
+        config=dict(workload=args.workload, grid=list(case.n), particles=case.np_,
+                    markers=case.nm, active_markers=n_act, shell_nodes=shell, n_iter=n_iter,
+                    precision="FP32 grid/delta, FP64 geometry, particle sums and pair pass",
+                    step="pair pass + marker geometry + n_iter forcing passes"),
+        roofline=roof, cpu_baseline=cpu, fp64=fp64,
+        kernel_ms_per_launch=per_launch,
+        pass_rate=n_act / (((per_launch["interp"] or 0) + (per_launch["spread"] or 0)) * 1e-3),
+    )
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

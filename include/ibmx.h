@@ -1,0 +1,288 @@
+/*
+ * ibmx.h -- C ABI of the MI355X (gfx950) library for the data-parallel hot
+ * path of the collocated-grid direct-forcing immersed boundary method with
+ * polydisperse collision models of Yao et al., arXiv 2109.03972:
+ *
+ *   - the outer forcing loop (Sec. 2.2.2): interpolate the collocated
+ *     velocity to every particle's Lagrangian markers through the
+ *     regularized delta (Sec. 2.1, eq. 3pt-stencil; Sec. 2.2.3 for the
+ *     four-point variant), form the marker force from the rigid-body
+ *     velocity u_p + omega_p x (X_l - x_p), spread it back to the grid,
+ *     update the velocity, and sum each particle's force and torque
+ *     (eq. basic-particle);
+ *   - the pair pass (Sec. 2.3): cell list, pair and wall lists, the
+ *     lubrication / normal / tangential collision forces and torques
+ *     (eq. f_int), and the marker-disable mask.
+ *
+ * Conventions shared by every entry point
+ *   * Grid fields are T[3][nz][ny][nx] (x fastest), T = double for
+ *     IBMX_F64 and float for IBMX_F32.  Node (i,j,k) sits at
+ *     origin + (i + 1/2, j + 1/2, k + 1/2) h (cell centres of the collocated
+ *     finite-volume grid).  A non-periodic axis has walls at origin and
+ *     origin + n h.
+ *   * Particle arrays are double[3][np] (all x, then all y, then all z).
+ *   * Markers are stored per particle in CSR order: marker_offset[np + 1]
+ *     (host, int32); body offsets o_l = X_l - x_p are double[3][nm].
+ *   * Every pointer passed to a compute call is a DEVICE pointer unless
+ *     named *_host.  The caller owns every buffer; the library only reads
+ *     or writes it inside the call, asynchronously on the plan's stream, so
+ *     buffers must stay valid until the stream reaches the call.
+ *   * Compute calls allocate nothing and never synchronise the stream; they
+ *     can be captured into a HIP graph.  Errors that only the device can see
+ *     (a delta support crossing a wall, a list capacity exceeded) are
+ *     recorded in the plan and returned by ibmx_plan_status().
+ *   * No exception, abort or exit crosses this interface.
+ */
+#ifndef IBMX_H
+#define IBMX_H
+
+#include <stdint.h>
+
+#if defined(IBMX_BUILD)
+#define IBMX_API __attribute__((visibility("default")))
+#else
+#define IBMX_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    IBMX_OK = 0,
+    IBMX_EINVAL = -1,       /* bad argument, size or CSR                      */
+    IBMX_EDOMAIN = -2,      /* an active marker's delta support leaves the
+                               grid through a wall (deferred)                 */
+    IBMX_ENOMEM = -3,       /* device allocation failed (plan creation only)  */
+    IBMX_EDEVICE = -4,      /* a HIP runtime call failed                      */
+    IBMX_ESTATE = -5,       /* plan not ready (markers not set)               */
+    IBMX_ECAPACITY = -6,    /* pair or wall list longer than its capacity
+                               (deferred; counts are still written)           */
+    IBMX_EUNSUPPORTED = -7  /* option not built (e.g. Hertz normal contact)   */
+} ibmx_status;
+
+typedef enum {
+    IBMX_F64 = 0,           /* grid, delta weights and marker forces in FP64  */
+    IBMX_F32 = 1            /* grid, delta weights and marker forces in FP32;
+                               marker geometry, per-particle force and torque
+                               sums, residuals and all pair-pass arithmetic
+                               stay FP64                                      */
+} ibmx_precision;
+
+/* Uniform collocated grid.  n[a] >= 1, h > 0, n[0]*n[1]*n[2] < 2^31. */
+typedef struct {
+    int32_t n[3];
+    int32_t periodic[3];    /* 1 periodic, 0 walls                            */
+    double h;
+    double origin[3];
+} ibmx_grid;
+
+/* Method parameters (units of the caller; the paper's values in brackets). */
+typedef struct {
+    int32_t kernel;          /* 3: three-point delta (Sec. 2.1), 4: four-point
+                                (Sec. 2.2.3)                                   */
+    int32_t n_iter;          /* interpolate-force-spread-update passes per
+                                call (n_f + 1 in the paper's count)           */
+    double two_alpha_dt;     /* c = 2 alpha_k dt of the current RK sub-step    */
+    double rho_f;            /* fluid density                                  */
+    double nu_f;             /* kinematic viscosity                            */
+    double eps_sep;          /* lubrication / disable threshold [1.5h, 2h]     */
+    double lub_C;            /* psi blending constant [5.5 three-point, 4]    */
+    double zeta_min_factor;  /* zeta_min = factor * min(R_p, R_q) [3e-3]       */
+    double e_dry;            /* dry restitution coefficient [0.97]            */
+    double T_c;              /* contact duration [10 dt]                       */
+    double mu_s;             /* static friction [0.11]                         */
+    double mu_k;             /* kinetic friction [0.8]                         */
+    double nu_poi;           /* Poisson ratio of the particles                 */
+    double dt;               /* time step for the tangential spring            */
+    double gap_cut;          /* pair/wall list cut-off on the surface gap      */
+    int32_t disable_mode;    /* 0 none, 1 local markers, 2 whole particle      */
+    int32_t normal_model;    /* 0 linear spring-dashpot (1 Hertz: not built)   */
+    uint64_t disable_seed;   /* seed of the per-pair random choice             */
+} ibmx_params;
+
+typedef struct ibmx_plan_s *ibmx_plan;
+
+/* Counters of the last forcing call (read by ibmx_plan_stats, which
+ * synchronises the plan's stream). */
+typedef struct {
+    int64_t n_markers;        /* markers in the plan                           */
+    int64_t n_active;         /* markers taking part in the last call          */
+    int64_t shell_nodes;      /* distinct grid nodes with nonzero delta weight
+                                 from some active marker (last call)           */
+    int64_t tiles;            /* spatial tiles of the spreading pass          */
+    int64_t halo_entries;     /* (marker, neighbour tile) spreading entries    */
+    int32_t tile[3];          /* tile edge in nodes                            */
+    int32_t block;            /* threads per workgroup of the marker passes   */
+    /* Kernel timings accumulated while profiling is on (ibmx_plan_profile):
+     * total milliseconds and launch counts per kernel class
+     * IBMX_K_GEOMETRY .. IBMX_K_PAIRS. */
+    double kernel_ms[8];
+    int64_t kernel_launches[8];
+} ibmx_stats;
+
+/* Kernel classes of ibmx_stats.kernel_ms. */
+enum {
+    IBMX_K_GEOMETRY = 0,      /* marker geometry, binning and sorting          */
+    IBMX_K_INTERP = 1,        /* interpolation + marker force + particle sums  */
+    IBMX_K_SPREAD = 2,        /* spreading + velocity update                   */
+    IBMX_K_BACKWARD = 3,      /* adjoint passes                                */
+    IBMX_K_PAIRS = 4,         /* pair pass (lists, forces, mask)               */
+    IBMX_K_OTHER = 5          /* fills, residual finish                        */
+};
+
+/*
+ * Create a plan for a grid, a parameter set and a fixed marker layout.
+ *   out                 receives the handle.
+ *   grid, params        copied.
+ *   np                  number of particles (>= 0).
+ *   marker_offset_host  host int32[np + 1], nondecreasing, [0] = 0.
+ *   precision           IBMX_F64 or IBMX_F32.
+ *   hip_stream          hipStream_t (NULL = default stream) used by every
+ *                       call on this plan.
+ * Allocates all device workspace.  Returns EINVAL, ENOMEM, EDEVICE or
+ * EUNSUPPORTED (kernel other than 3/4, normal_model != 0).
+ */
+IBMX_API ibmx_status ibmx_plan_create(ibmx_plan *out, const ibmx_grid *grid, const ibmx_params *params,
+                             int32_t np, const int32_t *marker_offset_host,
+                             ibmx_precision precision, void *hip_stream);
+
+/* Release the plan and its workspace (synchronises its stream). */
+IBMX_API ibmx_status ibmx_plan_destroy(ibmx_plan plan);
+
+/* Attach the marker set: body offsets double[3][nm] and the marker volume
+ * dV_l of each particle double[np] (Sec. 2.1: N_l dV_l is the shell volume).
+ * Pointers are kept, not copied: they must stay valid while the plan is
+ * used. */
+IBMX_API ibmx_status ibmx_plan_set_markers(ibmx_plan plan, const double *body_offset, const double *dV);
+
+/* Change the parameters (n_iter may not exceed the value the plan was
+ * created with). */
+IBMX_API ibmx_status ibmx_plan_set_params(ibmx_plan plan, const ibmx_params *params);
+
+/* Change the stream used by later calls. */
+IBMX_API ibmx_status ibmx_plan_set_stream(ibmx_plan plan, void *hip_stream);
+
+/* Synchronise the plan's stream and return (and clear) the first deferred
+ * device error of the calls since the last ibmx_plan_status: EDOMAIN,
+ * ECAPACITY, or EDEVICE. */
+IBMX_API ibmx_status ibmx_plan_status(ibmx_plan plan);
+
+/* Synchronise and report the counters of the last forcing call. */
+IBMX_API ibmx_status ibmx_plan_stats(ibmx_plan plan, ibmx_stats *out);
+
+/* Turn per-kernel timing on (enable = 1) or off (0).  While on, every kernel
+ * launch of this plan is bracketed by a pair of HIP events recorded on the
+ * plan's stream; ibmx_plan_stats sums their elapsed times per kernel class.
+ * Turning it on clears the accumulated timings.  Do not capture a plan with
+ * profiling on into a HIP graph. */
+IBMX_API ibmx_status ibmx_plan_profile(ibmx_plan plan, int32_t enable);
+
+/*
+ * Outer forcing loop (Sec. 2.2.2), params.n_iter passes:
+ *   U_l   = sum_x u(x) delta_h(x - X_l) h^3            X_l = x_p + o_l
+ *   F_l   = (u_p + omega_p x o_l - U_l) / c
+ *   f(x)  = sum_l F_l delta_h(x - X_l) dV_l
+ *   u    <- u + c f
+ * u            T[3][nz][ny][nx], in/out: u^0 in, u^{n_iter} out.
+ * f_tot        T[3][nz][ny][nx], accumulate-into: f_tot += sum of the
+ *              passes' f.  Only nodes in the delta support of active markers
+ *              are read or written.
+ * xp, up, wp   double[3][np]: centres, velocities, angular velocities.
+ * marker_active uint8[nm] or NULL (all active): 0 drops marker l from every
+ *              pass (the disable rule of Sec. 2.3, see ibmx_pairs).
+ * S_out, T_out double[3][np], overwritten: sum over passes and active
+ *              markers of F_l dV_l and of o_l x F_l dV_l.  The hydrodynamic
+ *              force and torque of eq. basic-particle are -rho_f times these.
+ * resid_out    double[n_iter + 1] or NULL: resid[m] = sqrt(sum_l dV_l
+ *              |u_p + omega_p x o_l - U_l^m|^2) before pass m + 1; the last
+ *              entry is measured on the final velocity.
+ * U_debug      T[n_iter][3][nm] or NULL: the interpolated U_l of each pass
+ *              (entries of inactive markers are not written).
+ * Deferred error: EDOMAIN if an active marker's support crosses a wall (the
+ * marker is then skipped).
+ */
+IBMX_API ibmx_status ibmx_forcing(ibmx_plan plan, void *u, void *f_tot,
+                         const double *xp, const double *up, const double *wp,
+                         const uint8_t *marker_active,
+                         double *S_out, double *T_out, double *resid_out, void *U_debug);
+
+/*
+ * Reverse-mode derivative of ibmx_forcing with respect to u^0, x_p, u_p and
+ * omega_p, holding the mask, body offsets, dV and c fixed (the adjoint of
+ * each pass swaps interpolation and spreading; the delta gradient gives the
+ * position terms).  Inputs are the forward inputs (u0 = the velocity BEFORE
+ * the forward call) and the cotangents g_f = dL/df_tot (T grid or NULL),
+ * g_u = dL/du^{n_iter} (T grid or NULL), g_S = dL/dS_out and g_T = dL/dT_out
+ * (double[3][np] or NULL).  Outputs (overwritten): gu0 (T grid), gxp, gup,
+ * gwp (double[3][np]).  The forward passes are recomputed, not stored by the
+ * forward call; plan workspace holds the per-marker pass data.
+ */
+IBMX_API ibmx_status ibmx_forcing_backward(ibmx_plan plan, const void *u0,
+                                  const double *xp, const double *up, const double *wp,
+                                  const uint8_t *marker_active,
+                                  const void *g_f, const void *g_u,
+                                  const double *g_S, const double *g_T,
+                                  void *gu0, double *gxp, double *gup, double *gwp);
+
+/*
+ * Pair pass (Sec. 2.3), all FP64:
+ *  - cell list: nc[a] = max(1, floor(L_a / (2 R_max + gap_cut))) cells per
+ *    axis; cell of p = floor((x_p - origin)/edge) of the periodically wrapped
+ *    centre, clamped; cell_start int32[ncell + 1], cell_particles int32[np]
+ *    listed by (cell, id);
+ *  - pair list: every i < j with minimum-image centre distance below
+ *    R_i + R_j + gap_cut, int32[2][pair_cap] in (i, j) order; pair_gap
+ *    double[pair_cap] = d - R_i - R_j;
+ *  - wall list: (p, side) with side = 2 axis + (0 lower, 1 upper) for walls
+ *    closer than gap_cut, int32[2][wall_cap] in (p, side) order, wall_gap;
+ *  - collision force and torque (eq. f_int): Fc, Tc double[3][np]
+ *    (overwritten): lubrication for 0 <= gap < eps_sep, linear spring-dashpot
+ *    normal contact and capped tangential spring-dashpot for gap < 0;
+ *  - spring history: hist_in double[3][npairs_in] keyed by pairs_in (the
+ *    previous call's pair list, may be empty), whist_in likewise for walls;
+ *    hist_out double[3][pair_cap], whist_out double[3][wall_cap];
+ *  - marker_active uint8[nm] (overwritten): the disable rule of
+ *    params.disable_mode (1: the randomly chosen particle of each pair closer
+ *    than 2 eps_sep loses the markers within 2 eps_sep of its partner's
+ *    surface; markers closer than eps_sep to a wall are off; 2: whole
+ *    particles).  The random choice for (p, q), p < q, is the low bit of
+ *    SplitMix64(seed ^ (p << 32 | q)): 0 picks p.
+ * radius_max (host) bounds every radius; it sizes the cell grid.  A radius
+ * above it is reported as a deferred EINVAL.
+ * counts_out int32[2] (device): number of pairs and of wall entries found.
+ * cell_cap is the capacity of cell_start (ncell + 1 entries).
+ * Deferred error: ECAPACITY if a list exceeds its capacity (entries beyond
+ * it are dropped, forces of dropped entries are not applied).
+ * The body offsets set with ibmx_plan_set_markers are needed for the mask.
+ */
+IBMX_API ibmx_status ibmx_pairs(ibmx_plan plan, const double *xp, const double *radius,
+                       double radius_max, const double *mass, const double *up, const double *wp,
+                       int32_t npairs_in, const int32_t *pairs_in, const double *hist_in,
+                       int32_t nwall_in, const int32_t *walls_in, const double *whist_in,
+                       int32_t *cell_start, int32_t cell_cap, int32_t *cell_particles,
+                       int32_t *pairs_out, double *pair_gap, double *hist_out, int32_t pair_cap,
+                       int32_t *walls_out, double *wall_gap, double *whist_out, int32_t wall_cap,
+                       int32_t *counts_out, double *Fc, double *Tc, uint8_t *marker_active);
+
+/*
+ * Autotune the forcing launch (tile edge, threads per workgroup) on the
+ * given inputs: times each candidate with the real call and keeps the
+ * fastest in the plan.  u and f_tot are used as scratch (their contents are
+ * restored); reports the choice through ibmx_plan_stats.
+ */
+IBMX_API ibmx_status ibmx_tune(ibmx_plan plan, void *u, void *f_tot,
+                      const double *xp, const double *up, const double *wp,
+                      const uint8_t *marker_active);
+
+/* Static description of a status code. */
+IBMX_API const char *ibmx_status_string(ibmx_status status);
+
+/* Library version string. */
+IBMX_API const char *ibmx_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IBMX_H */

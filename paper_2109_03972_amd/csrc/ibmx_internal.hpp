@@ -1,0 +1,163 @@
+// Internal declarations of the ibmx HIP library (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ibmx.h"
+
+#define IBMX_WAVE 64
+
+// ---------------------------------------------------------------------------
+// grid constants passed by value to kernels
+// ---------------------------------------------------------------------------
+struct GridC {
+    int n[3];
+    int periodic[3];
+    double h;
+    double inv_h3;
+    double origin[3];
+    long long nodes;   // nx * ny * nz
+    int shift[3];      // bit offsets of the packed base-node coordinates
+};
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+struct ibmx_plan_s {
+    ibmx_grid grid;
+    ibmx_params prm;
+    GridC g;
+    int np;
+    int nm;
+    int n_iter_cap;
+    ibmx_precision prec;
+    hipStream_t stream;
+    int device;
+
+    // caller-owned marker data
+    const double *body;
+    const double *dV;
+
+    // plan-owned device workspace
+    int *d_moff;          // [np + 1]
+    int *d_pid;           // [nm] marker -> particle
+    int *d_err;           // [1] first deferred error (0 = none)
+    double *d_acc;        // [n_iter_cap + 1] residual accumulators
+    long long *d_count;   // [8] counters (active markers, shell nodes, ...)
+
+    // marker records (sorted by spreading tile)
+    int *rec_node;        // [nm] packed base node (bx | by << 10 ... see forcing)
+    int *rec_src;         // [nm] original marker index
+    int *rec_pid;         // [nm] particle
+    void *rec_t;          // T[3][nm] fractional offsets
+    void *rec_o;          // T[3][nm] body offsets
+    void *rec_G;          // T[3][nm] spreading amplitude F dV / h^3
+    int *m_key;           // [nm] per-marker tile slot / rank scratch
+    int *m_rank;          // [nm]
+
+    // tiles
+    int tile[3];          // tile edge (nodes)
+    int ntile[3];
+    int ntiles;
+    int *tile_count;      // [ntiles + 1]
+    int *tile_start;      // [ntiles + 1]
+    int *tile_cursor;     // [ntiles]
+    int *halo_count;      // [ntiles + 1]
+    int *halo_start;      // [ntiles + 1]
+    int *halo_cursor;     // [ntiles]
+    int *halo_list;       // [halo_cap]
+    long long halo_cap;
+    int block;            // threads per workgroup of marker passes
+
+    // backward workspace (allocated on first use)
+    void *bw_u;           // T grid scratch
+    void *bw_F;           // T[n_iter][3][nm]
+    void *bw_J;           // T[n_iter][9][nm]
+    double *bw_part;      // [9][np] per-particle gradient accumulators
+    size_t bw_bytes;
+
+    // pair-pass workspace
+    int *p_cell_of;       // [np]
+    int *p_cursor;        // [max cells]
+    int *p_count;         // [np + 1]
+    int *p_off;           // [np + 1]
+    int p_cell_cap;
+    int *p_wcount;        // [np + 1]
+    int *p_woff;          // [np + 1]
+
+    // last-call statistics
+    ibmx_stats stats;
+
+    // per-kernel timing (ibmx_plan_profile)
+    int prof;
+    int ev_cap;
+    int ev_used;
+    hipEvent_t *ev;       // [2 * ev_cap]
+    int *ev_kind;         // [ev_cap]
+    double acc_ms[8];
+    long long acc_n[8];
+    unsigned *shell_bits; // [(nodes + 31) / 32] touched-node bitmap (profiling)
+};
+
+// Brackets the kernel launches of one scope with a pair of HIP events when
+// profiling is on.
+struct ProfScope {
+    ibmx_plan p;
+    int idx;
+    ProfScope(ibmx_plan p_, int kind) : p(p_), idx(-1)
+    {
+        if (p->prof && p->ev_used < p->ev_cap) {
+            idx = p->ev_used++;
+            p->ev_kind[idx] = kind;
+            (void)hipEventRecord(p->ev[2 * idx], p->stream);
+        }
+    }
+    ~ProfScope()
+    {
+        if (idx >= 0)
+            (void)hipEventRecord(p->ev[2 * idx + 1], p->stream);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// host helpers
+// ---------------------------------------------------------------------------
+#define IBMX_HIP_CHECK(expr)                                  \
+    do {                                                      \
+        hipError_t _e = (expr);                               \
+        if (_e != hipSuccess)                                 \
+            return IBMX_EDEVICE;                              \
+    } while (0)
+
+ibmx_status ibmx_launch_check();
+void ibmx_exclusive_scan(const int *in, int *out, int n, hipStream_t s);
+void ibmx_fill_i32(int *p, int v, long long n, hipStream_t s);
+void ibmx_fill_f64(double *p, double v, long long n, hipStream_t s);
+void ibmx_fill_u8(uint8_t *p, uint8_t v, long long n, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T dev_sqrt(T x);
+template <>
+__device__ __forceinline__ float dev_sqrt<float>(float x) { return __builtin_sqrtf(x); }
+template <>
+__device__ __forceinline__ double dev_sqrt<double>(double x) { return __builtin_sqrt(x); }
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = IBMX_WAVE / 2; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, IBMX_WAVE);
+    return v;
+}
+
+__device__ __forceinline__ int wave_sum_i(int v)
+{
+#pragma unroll
+    for (int off = IBMX_WAVE / 2; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, IBMX_WAVE);
+    return v;
+}

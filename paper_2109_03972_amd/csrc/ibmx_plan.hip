@@ -1,0 +1,366 @@
+// Plan life cycle: validation, workspace allocation, deferred status.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "ibmx_internal.hpp"
+
+namespace {
+
+int bits_for(int n)
+{
+    int b = 0;
+    while ((1 << b) < n)
+        ++b;
+    return b < 1 ? 1 : b;
+}
+
+void free_plan(ibmx_plan p)
+{
+    if (!p)
+        return;
+    void *ptrs[] = {p->d_moff, p->d_pid, p->d_err, p->d_acc, p->d_count, p->rec_node,
+                    p->rec_src, p->rec_pid, p->rec_t, p->rec_o, p->rec_G, p->m_key,
+                    p->m_rank, p->tile_count, p->tile_start, p->tile_cursor, p->halo_count,
+                    p->halo_start, p->halo_cursor, p->halo_list, p->bw_u, p->bw_F, p->bw_J,
+                    p->bw_part, p->p_cell_of, p->p_cursor, p->p_count, p->p_off, p->p_wcount,
+                    p->p_woff, p->shell_bits};
+    for (void *q : ptrs)
+        if (q)
+            (void)hipFree(q);
+    if (p->ev) {
+        for (int i = 0; i < 2 * p->ev_cap; ++i)
+            (void)hipEventDestroy(p->ev[i]);
+        free(p->ev);
+        free(p->ev_kind);
+    }
+    free(p);
+}
+
+ibmx_status check_params(const ibmx_grid *g, const ibmx_params *prm)
+{
+    if (!g || !prm)
+        return IBMX_EINVAL;
+    long long nodes = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (g->n[a] < 1 || (g->periodic[a] != 0 && g->periodic[a] != 1))
+            return IBMX_EINVAL;
+        nodes *= g->n[a];
+    }
+    if (nodes >= (1LL << 31))
+        return IBMX_EINVAL;
+    if (bits_for(g->n[0]) + bits_for(g->n[1]) + bits_for(g->n[2]) > 32)
+        return IBMX_EUNSUPPORTED;
+    if (!(g->h > 0.0) || !isfinite(g->h))
+        return IBMX_EINVAL;
+    if (prm->kernel != 3 && prm->kernel != 4)
+        return IBMX_EUNSUPPORTED;
+    if (prm->normal_model != 0)
+        return IBMX_EUNSUPPORTED;
+    if (prm->n_iter < 1 || prm->n_iter > 64)
+        return IBMX_EINVAL;
+    if (!(prm->two_alpha_dt != 0.0) || !isfinite(prm->two_alpha_dt))
+        return IBMX_EINVAL;
+    if (prm->disable_mode < 0 || prm->disable_mode > 2)
+        return IBMX_EINVAL;
+    if (!(prm->eps_sep >= 0.0) || !(prm->gap_cut >= 0.0) || !(prm->T_c > 0.0) ||
+        !(prm->e_dry > 0.0 && prm->e_dry <= 1.0) || !(prm->dt > 0.0))
+        return IBMX_EINVAL;
+    // periodic axes must hold at least the delta support twice over
+    for (int a = 0; a < 3; ++a)
+        if (g->periodic[a] && g->n[a] < 2 * prm->kernel)
+            return IBMX_EINVAL;
+    return IBMX_OK;
+}
+
+}  // namespace
+
+ibmx_status ibmx_plan_alloc_tiles(ibmx_plan p, int tx, int ty, int tz);
+
+extern "C" ibmx_status ibmx_plan_create(ibmx_plan *out, const ibmx_grid *grid,
+                                        const ibmx_params *params, int32_t np,
+                                        const int32_t *moff_host, ibmx_precision precision,
+                                        void *hip_stream)
+{
+    if (!out)
+        return IBMX_EINVAL;
+    *out = nullptr;
+    ibmx_status st = check_params(grid, params);
+    if (st != IBMX_OK)
+        return st;
+    if (np < 0 || (np > 0 && !moff_host) || (precision != IBMX_F64 && precision != IBMX_F32))
+        return IBMX_EINVAL;
+    long long nm = 0;
+    if (np > 0) {
+        if (moff_host[0] != 0)
+            return IBMX_EINVAL;
+        for (int i = 0; i < np; ++i)
+            if (moff_host[i + 1] < moff_host[i])
+                return IBMX_EINVAL;
+        nm = moff_host[np];
+    }
+    if (nm >= (1LL << 31) - 64)
+        return IBMX_EINVAL;
+
+    ibmx_plan p = (ibmx_plan)calloc(1, sizeof(ibmx_plan_s));
+    if (!p)
+        return IBMX_ENOMEM;
+    p->grid = *grid;
+    p->prm = *params;
+    p->np = np;
+    p->nm = (int)nm;
+    p->n_iter_cap = params->n_iter;
+    p->prec = precision;
+    p->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&p->device) != hipSuccess) {
+        free(p);
+        return IBMX_EDEVICE;
+    }
+    GridC &g = p->g;
+    long long nodes = 1;
+    for (int a = 0; a < 3; ++a) {
+        g.n[a] = grid->n[a];
+        g.periodic[a] = grid->periodic[a];
+        g.origin[a] = grid->origin[a];
+        nodes *= grid->n[a];
+    }
+    g.h = grid->h;
+    g.inv_h3 = 1.0 / (grid->h * grid->h * grid->h);
+    g.nodes = nodes;
+    g.shift[0] = 0;
+    g.shift[1] = bits_for(g.n[0]);
+    g.shift[2] = g.shift[1] + bits_for(g.n[1]);
+
+    const size_t Ts = precision == IBMX_F64 ? sizeof(double) : sizeof(float);
+    const size_t nmz = nm > 0 ? (size_t)nm : 1;
+    const size_t npz = np > 0 ? (size_t)np : 1;
+    bool ok = true;
+    auto A = [&](void **q, size_t bytes) {
+        if (ok && hipMalloc(q, bytes) != hipSuccess)
+            ok = false;
+    };
+    A((void **)&p->d_moff, sizeof(int) * (npz + 1));
+    A((void **)&p->d_pid, sizeof(int) * nmz);
+    A((void **)&p->d_err, sizeof(int) * 4);
+    A((void **)&p->d_acc, sizeof(double) * (p->n_iter_cap + 2));
+    A((void **)&p->d_count, sizeof(long long) * 8);
+    A((void **)&p->rec_node, sizeof(int) * nmz);
+    A((void **)&p->rec_src, sizeof(int) * nmz);
+    A((void **)&p->rec_pid, sizeof(int) * nmz);
+    A(&p->rec_t, Ts * 3 * nmz);
+    A(&p->rec_o, Ts * 3 * nmz);
+    A(&p->rec_G, Ts * 3 * nmz);
+    A((void **)&p->m_key, sizeof(int) * nmz);
+    A((void **)&p->m_rank, sizeof(int) * nmz);
+    A((void **)&p->p_cell_of, sizeof(int) * npz);
+    A((void **)&p->p_count, sizeof(int) * (npz + 1));
+    A((void **)&p->p_off, sizeof(int) * (npz + 1));
+    A((void **)&p->p_wcount, sizeof(int) * (npz + 1));
+    A((void **)&p->p_woff, sizeof(int) * (npz + 1));
+    if (!ok) {
+        free_plan(p);
+        return IBMX_ENOMEM;
+    }
+    // marker -> particle map from the CSR offsets
+    int *pid = (int *)malloc(sizeof(int) * nmz);
+    int *moff = (int *)malloc(sizeof(int) * (npz + 1));
+    if (!pid || !moff) {
+        free(pid);
+        free(moff);
+        free_plan(p);
+        return IBMX_ENOMEM;
+    }
+    moff[0] = 0;
+    for (int i = 0; i < np; ++i) {
+        moff[i + 1] = moff_host[i + 1];
+        for (int l = moff_host[i]; l < moff_host[i + 1]; ++l)
+            pid[l] = i;
+    }
+    if (np == 0)
+        moff[1] = 0;
+    hipError_t e1 = hipMemcpy(p->d_pid, pid, sizeof(int) * (size_t)nm, hipMemcpyHostToDevice);
+    hipError_t e2 = hipMemcpy(p->d_moff, moff, sizeof(int) * (size_t)(np + 1), hipMemcpyHostToDevice);
+    free(pid);
+    free(moff);
+    if (e1 != hipSuccess || e2 != hipSuccess || hipMemset(p->d_err, 0, sizeof(int) * 4) != hipSuccess ||
+        hipMemset(p->d_count, 0, sizeof(long long) * 8) != hipSuccess) {
+        free_plan(p);
+        return IBMX_EDEVICE;
+    }
+    p->block = 256;
+    p->stats.n_markers = nm;
+    // default spreading tiles: 16^3 nodes (clamped to the grid)
+    st = ibmx_plan_alloc_tiles(p, 16, 16, 16);
+    if (st != IBMX_OK) {
+        free_plan(p);
+        return st;
+    }
+    *out = p;
+    return IBMX_OK;
+}
+
+ibmx_status ibmx_plan_alloc_tiles(ibmx_plan p, int tx, int ty, int tz)
+{
+    int t[3] = {tx, ty, tz};
+    int nt[3];
+    long long ntiles = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (t[a] < 2)
+            return IBMX_EINVAL;
+        if (t[a] > p->g.n[a])
+            t[a] = p->g.n[a];
+        nt[a] = (p->g.n[a] + t[a] - 1) / t[a];
+        ntiles *= nt[a];
+    }
+    if (ntiles > (1LL << 28))
+        return IBMX_EINVAL;
+    bool same = p->tile_count && ntiles == p->ntiles;
+    if (!same) {
+        void *ptrs[] = {p->tile_count, p->tile_start, p->tile_cursor, p->halo_count,
+                        p->halo_start, p->halo_cursor};
+        for (void *q : ptrs)
+            if (q)
+                (void)hipFree(q);
+        p->tile_count = p->tile_start = p->tile_cursor = nullptr;
+        p->halo_count = p->halo_start = p->halo_cursor = nullptr;
+        size_t b = sizeof(int) * (size_t)(ntiles + 1);
+        if (hipMalloc((void **)&p->tile_count, b) != hipSuccess ||
+            hipMalloc((void **)&p->tile_start, b) != hipSuccess ||
+            hipMalloc((void **)&p->tile_cursor, b) != hipSuccess ||
+            hipMalloc((void **)&p->halo_count, b) != hipSuccess ||
+            hipMalloc((void **)&p->halo_start, b) != hipSuccess ||
+            hipMalloc((void **)&p->halo_cursor, b) != hipSuccess)
+            return IBMX_ENOMEM;
+    }
+    // every marker reaches at most 7 tiles besides its own
+    long long cap = 7LL * (p->nm > 0 ? p->nm : 1);
+    if (!p->halo_list || p->halo_cap < cap) {
+        if (p->halo_list)
+            (void)hipFree(p->halo_list);
+        p->halo_list = nullptr;
+        if (hipMalloc((void **)&p->halo_list, sizeof(int) * (size_t)cap) != hipSuccess)
+            return IBMX_ENOMEM;
+        p->halo_cap = cap;
+    }
+    for (int a = 0; a < 3; ++a) {
+        p->tile[a] = t[a];
+        p->ntile[a] = nt[a];
+        p->stats.tile[a] = t[a];
+    }
+    p->ntiles = (int)ntiles;
+    p->stats.tiles = ntiles;
+    return IBMX_OK;
+}
+
+extern "C" ibmx_status ibmx_plan_destroy(ibmx_plan p)
+{
+    if (!p)
+        return IBMX_EINVAL;
+    (void)hipStreamSynchronize(p->stream);
+    free_plan(p);
+    return IBMX_OK;
+}
+
+extern "C" ibmx_status ibmx_plan_set_markers(ibmx_plan p, const double *body, const double *dV)
+{
+    if (!p || (p->nm > 0 && !body) || (p->np > 0 && !dV))
+        return IBMX_EINVAL;
+    p->body = body;
+    p->dV = dV;
+    return IBMX_OK;
+}
+
+extern "C" ibmx_status ibmx_plan_set_params(ibmx_plan p, const ibmx_params *prm)
+{
+    if (!p)
+        return IBMX_EINVAL;
+    ibmx_status st = check_params(&p->grid, prm);
+    if (st != IBMX_OK)
+        return st;
+    if (prm->n_iter > p->n_iter_cap)
+        return IBMX_EINVAL;
+    p->prm = *prm;
+    return IBMX_OK;
+}
+
+extern "C" ibmx_status ibmx_plan_set_stream(ibmx_plan p, void *stream)
+{
+    if (!p)
+        return IBMX_EINVAL;
+    p->stream = (hipStream_t)stream;
+    return IBMX_OK;
+}
+
+extern "C" ibmx_status ibmx_plan_status(ibmx_plan p)
+{
+    if (!p)
+        return IBMX_EINVAL;
+    if (hipStreamSynchronize(p->stream) != hipSuccess)
+        return IBMX_EDEVICE;
+    int err = 0;
+    if (hipMemcpy(&err, p->d_err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+        return IBMX_EDEVICE;
+    if (err != 0 && hipMemset(p->d_err, 0, sizeof(int)) != hipSuccess)
+        return IBMX_EDEVICE;
+    return (ibmx_status)err;
+}
+
+extern "C" ibmx_status ibmx_plan_stats(ibmx_plan p, ibmx_stats *out)
+{
+    if (!p || !out)
+        return IBMX_EINVAL;
+    if (hipStreamSynchronize(p->stream) != hipSuccess)
+        return IBMX_EDEVICE;
+    long long c[8];
+    if (hipMemcpy(c, p->d_count, sizeof(c), hipMemcpyDeviceToHost) != hipSuccess)
+        return IBMX_EDEVICE;
+    p->stats.n_active = c[0];
+    p->stats.shell_nodes = c[1];
+    p->stats.halo_entries = c[2];
+    p->stats.block = p->block;
+    for (int i = 0; i < p->ev_used; ++i) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, p->ev[2 * i], p->ev[2 * i + 1]) != hipSuccess)
+            return IBMX_EDEVICE;
+        p->acc_ms[p->ev_kind[i]] += ms;
+        p->acc_n[p->ev_kind[i]] += 1;
+    }
+    p->ev_used = 0;
+    for (int k = 0; k < 8; ++k) {
+        p->stats.kernel_ms[k] = p->acc_ms[k];
+        p->stats.kernel_launches[k] = p->acc_n[k];
+    }
+    *out = p->stats;
+    return IBMX_OK;
+}
+
+extern "C" ibmx_status ibmx_plan_profile(ibmx_plan p, int32_t enable)
+{
+    if (!p)
+        return IBMX_EINVAL;
+    if (hipStreamSynchronize(p->stream) != hipSuccess)
+        return IBMX_EDEVICE;
+    if (enable && !p->ev) {
+        const int cap = 8192;
+        p->ev = (hipEvent_t *)calloc(2 * cap, sizeof(hipEvent_t));
+        p->ev_kind = (int *)calloc(cap, sizeof(int));
+        if (!p->ev || !p->ev_kind)
+            return IBMX_ENOMEM;
+        for (int i = 0; i < 2 * cap; ++i)
+            if (hipEventCreate(&p->ev[i]) != hipSuccess)
+                return IBMX_EDEVICE;
+        p->ev_cap = cap;
+    }
+    if (enable && !p->shell_bits) {
+        size_t words = (size_t)((p->g.nodes + 31) / 32);
+        if (hipMalloc((void **)&p->shell_bits, sizeof(unsigned) * words) != hipSuccess)
+            return IBMX_ENOMEM;
+    }
+    p->ev_used = 0;
+    for (int k = 0; k < 8; ++k) {
+        p->acc_ms[k] = 0.0;
+        p->acc_n[k] = 0;
+    }
+    p->prof = enable ? 1 : 0;
+    return IBMX_OK;
+}

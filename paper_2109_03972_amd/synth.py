@@ -336,6 +336,9 @@ def _exercise_contacts(rng, xp, radius, L, periodic, zlim, frac, depth=0.05):
         newc = pos[i] + d[j] + nvec * (radius[i] + radius[j] + zeta)
         if newc[2] - radius[i] < zlim[0] or newc[2] + radius[i] > zlim[1]:
             continue
+        if any((not per[a]) and (newc[a] - radius[i] < 0.0 or newc[a] + radius[i] > L[a])
+               for a in range(2)):
+            continue
         for a in range(3):
             if per[a]:
                 newc[a] = newc[a] % L[a]
