@@ -7,6 +7,8 @@
 #include "../../include/ibmx.h"
 
 #define IBMX_WAVE 64
+#define IBMX_BIN_SLOTS_LOG2 9
+#define IBMX_BIN_SLOTS (1 << IBMX_BIN_SLOTS_LOG2)   // tiles one particle may touch
 
 // ---------------------------------------------------------------------------
 // grid constants passed by value to kernels
@@ -19,6 +21,14 @@ struct GridC {
     double origin[3];
     long long nodes;   // nx * ny * nz
     int shift[3];      // bit offsets of the packed base-node coordinates
+};
+
+// spatial tiles of the spreading pass: B[a] nodes per tile (the last tile of
+// an axis may be shorter but never narrower than the delta support)
+struct TileC {
+    int B[3];
+    int nt[3];
+    int ntiles;
 };
 
 // ---------------------------------------------------------------------------
@@ -57,9 +67,8 @@ struct ibmx_plan_s {
     int *m_rank;          // [nm]
 
     // tiles
-    int tile[3];          // tile edge (nodes)
-    int ntile[3];
-    int ntiles;
+    TileC tc;
+    int *bin_tab;         // [np][2][IBMX_BIN_SLOTS] per-particle tile tables
     int *tile_count;      // [ntiles + 1]
     int *tile_start;      // [ntiles + 1]
     int *tile_cursor;     // [ntiles]
@@ -97,7 +106,6 @@ struct ibmx_plan_s {
     int *ev_kind;         // [ev_cap]
     double acc_ms[8];
     long long acc_n[8];
-    unsigned *shell_bits; // [(nodes + 31) / 32] touched-node bitmap (profiling)
 };
 
 // Brackets the kernel launches of one scope with a pair of HIP events when
@@ -131,6 +139,9 @@ struct ProfScope {
     } while (0)
 
 ibmx_status ibmx_launch_check();
+ibmx_status ibmx_plan_alloc_tiles(ibmx_plan p, int tx, int ty, int tz);
+size_t ibmx_spread_lds_bytes(ibmx_plan p);
+ibmx_status ibmx_spread_allow_lds(ibmx_plan p);
 void ibmx_exclusive_scan(const int *in, int *out, int n, hipStream_t s);
 void ibmx_fill_i32(int *p, int v, long long n, hipStream_t s);
 void ibmx_fill_f64(double *p, double v, long long n, hipStream_t s);

@@ -24,7 +24,7 @@ void free_plan(ibmx_plan p)
                     p->m_rank, p->tile_count, p->tile_start, p->tile_cursor, p->halo_count,
                     p->halo_start, p->halo_cursor, p->halo_list, p->bw_u, p->bw_F, p->bw_J,
                     p->bw_part, p->p_cell_of, p->p_cursor, p->p_count, p->p_off, p->p_wcount,
-                    p->p_woff, p->shell_bits};
+                    p->p_woff, p->bin_tab};
     for (void *q : ptrs)
         if (q)
             (void)hipFree(q);
@@ -75,9 +75,7 @@ ibmx_status check_params(const ibmx_grid *g, const ibmx_params *prm)
 
 }  // namespace
 
-ibmx_status ibmx_plan_alloc_tiles(ibmx_plan p, int tx, int ty, int tz);
-
-extern "C" ibmx_status ibmx_plan_create(ibmx_plan *out, const ibmx_grid *grid,
+ extern "C" ibmx_status ibmx_plan_create(ibmx_plan *out, const ibmx_grid *grid,
                                         const ibmx_params *params, int32_t np,
                                         const int32_t *moff_host, ibmx_precision precision,
                                         void *hip_stream)
@@ -157,6 +155,7 @@ extern "C" ibmx_status ibmx_plan_create(ibmx_plan *out, const ibmx_grid *grid,
     A((void **)&p->p_off, sizeof(int) * (npz + 1));
     A((void **)&p->p_wcount, sizeof(int) * (npz + 1));
     A((void **)&p->p_woff, sizeof(int) * (npz + 1));
+    A((void **)&p->bin_tab, sizeof(int) * 2 * IBMX_BIN_SLOTS * npz);
     if (!ok) {
         free_plan(p);
         return IBMX_ENOMEM;
@@ -189,8 +188,8 @@ extern "C" ibmx_status ibmx_plan_create(ibmx_plan *out, const ibmx_grid *grid,
     }
     p->block = 256;
     p->stats.n_markers = nm;
-    // default spreading tiles: 16^3 nodes (clamped to the grid)
-    st = ibmx_plan_alloc_tiles(p, 16, 16, 16);
+    // default spreading tiles: 16^3 nodes (FP32) / 16x16x8 (FP64), 48 KB of LDS
+    st = ibmx_plan_alloc_tiles(p, 16, 16, precision == IBMX_F64 ? 8 : 16);
     if (st != IBMX_OK) {
         free_plan(p);
         return st;
@@ -204,18 +203,28 @@ ibmx_status ibmx_plan_alloc_tiles(ibmx_plan p, int tx, int ty, int tz)
     int t[3] = {tx, ty, tz};
     int nt[3];
     long long ntiles = 1;
+    const int W = 4;   // widest delta support
     for (int a = 0; a < 3; ++a) {
-        if (t[a] < 2)
+        if (t[a] < W)
             return IBMX_EINVAL;
-        if (t[a] > p->g.n[a])
+        if (t[a] >= p->g.n[a]) {
             t[a] = p->g.n[a];
+        } else {
+            // a short last tile must still hold a whole support
+            while (t[a] > W && p->g.n[a] % t[a] != 0 && p->g.n[a] % t[a] < W)
+                --t[a];
+            if (p->g.n[a] % t[a] != 0 && p->g.n[a] % t[a] < W)
+                t[a] = p->g.n[a];
+        }
         nt[a] = (p->g.n[a] + t[a] - 1) / t[a];
         ntiles *= nt[a];
     }
     if (ntiles > (1LL << 28))
         return IBMX_EINVAL;
-    bool same = p->tile_count && ntiles == p->ntiles;
-    if (!same) {
+    const size_t Ts = p->prec == IBMX_F64 ? sizeof(double) : sizeof(float);
+    if ((size_t)3 * t[0] * t[1] * t[2] * Ts > 160 * 1024)
+        return IBMX_EUNSUPPORTED;
+    if (!p->tile_count || ntiles > p->tc.ntiles) {
         void *ptrs[] = {p->tile_count, p->tile_start, p->tile_cursor, p->halo_count,
                         p->halo_start, p->halo_cursor};
         for (void *q : ptrs)
@@ -243,13 +252,13 @@ ibmx_status ibmx_plan_alloc_tiles(ibmx_plan p, int tx, int ty, int tz)
         p->halo_cap = cap;
     }
     for (int a = 0; a < 3; ++a) {
-        p->tile[a] = t[a];
-        p->ntile[a] = nt[a];
+        p->tc.B[a] = t[a];
+        p->tc.nt[a] = nt[a];
         p->stats.tile[a] = t[a];
     }
-    p->ntiles = (int)ntiles;
+    p->tc.ntiles = (int)ntiles;
     p->stats.tiles = ntiles;
-    return IBMX_OK;
+    return ibmx_spread_allow_lds(p);
 }
 
 extern "C" ibmx_status ibmx_plan_destroy(ibmx_plan p)
@@ -351,11 +360,7 @@ extern "C" ibmx_status ibmx_plan_profile(ibmx_plan p, int32_t enable)
                 return IBMX_EDEVICE;
         p->ev_cap = cap;
     }
-    if (enable && !p->shell_bits) {
-        size_t words = (size_t)((p->g.nodes + 31) / 32);
-        if (hipMalloc((void **)&p->shell_bits, sizeof(unsigned) * words) != hipSuccess)
-            return IBMX_ENOMEM;
-    }
+
     p->ev_used = 0;
     for (int k = 0; k < 8; ++k) {
         p->acc_ms[k] = 0.0;
