@@ -30,19 +30,28 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(kind: str, s: int, n_act: int, shell: int) -> float:
-    """Bytes the kernel must move per launch (one forcing pass).
+def algorithmic_bytes(kind: str, s: int, n_act: int, shell: int, n_iter: int = 2) -> float:
+    """Bytes a kernel must move per launch (s = bytes of the grid type).
 
-    interp: per active marker the record (packed node 4 B, fractions 3s,
-            body offset 3s) plus the spreading amplitude it writes (3s); per
-            shell node one read of the three velocity components (3s).
-    spread: per active marker the record (4 B + 3s) and the amplitude (3s);
-            per shell node a read-modify-write of u and of f_tot (4 x 3s).
+    Marker record: packed base node and particle id (8 B), fractions and body
+    offset (6s).  Shell = distinct grid nodes in the delta support of the
+    active markers; every access below touches each of them once.
+
+    interp (one pass): record, write of the pass amplitude G (3s) and
+           read-modify-write of its sum over passes (6s); per shell node one
+           read of the three velocity components (3s).
+    spread (one pass): packed node and fractions (4 B + 3s) and G (3s); per
+           shell node a read-modify-write of u (6s), and of f_tot as well
+           (6s more) when the call has a single pass.
+    ftot   (once per call with two or more passes): packed node, fractions and
+           summed G (4 B + 6s); per shell node a read-modify-write of f_tot.
     """
     if kind == "interp":
-        return n_act * (4 + 9 * s) + shell * 3 * s
+        return n_act * (8 + 15 * s) + shell * 3 * s
     if kind == "spread":
-        return n_act * (4 + 6 * s) + shell * 12 * s
+        return n_act * (4 + 6 * s) + shell * (6 * s if n_iter > 1 else 12 * s)
+    if kind == "ftot":
+        return n_act * (4 + 6 * s) + shell * 6 * s
     raise KeyError(kind)
 
 
@@ -130,6 +139,9 @@ def main():
     ap.add_argument("--workload", default="polydisperse_bed_512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one 1 GiB device-to-device copy (reference kernel for "
+                         "hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (--gpus 1); the forcing loop is not "
@@ -142,6 +154,13 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("bench: copied 1 GiB device-to-device (counter calibration)")
+        del src, dst
     log(f"bench: generating {args.workload}")
     case = synth.make_case(args.workload, lazy_field=True)
     log(f"bench: {case.np_} particles, {case.nm} markers, grid {case.n}")
@@ -152,9 +171,10 @@ def main():
     n_act, shell, n_iter = int(st["n_active"]), int(st["shell_nodes"]), r32["n_iter"]
     value = n_act * n_iter / (r32["ms_per_step"] * 1e-3)
     km, kn = st["kernel_ms"], st["kernel_launches"]
+    steps_done = args.steps
     per_launch = {k: (km[k] / kn[k] if kn[k] else None) for k in km}
     dom = max(("interp", "spread"), key=lambda k: km[k])
-    bytes_launch = algorithmic_bytes(dom, 4, n_act, shell)
+    bytes_launch = algorithmic_bytes(dom, 4, n_act, shell, n_iter)
     achieved = bytes_launch / (per_launch[dom] * 1e-3) / 1e9
     roof = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
                 unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
@@ -189,7 +209,8 @@ def main():
                     step="pair pass + marker geometry + n_iter forcing passes"),
         roofline=roof, cpu_baseline=cpu, fp64=fp64,
         kernel_ms_per_launch=per_launch,
-        pass_rate=n_act / (((per_launch["interp"] or 0) + (per_launch["spread"] or 0)) * 1e-3),
+        pass_rate=n_act * n_iter / (sum(km[k] for k in ("interp", "spread")) / steps_done
+                                    * 1e-3),
     )
     print(json.dumps(line), flush=True)
 

@@ -116,7 +116,7 @@ typedef struct {
     int32_t block;            /* threads per workgroup of the marker passes   */
     /* Kernel timings accumulated while profiling is on (ibmx_plan_profile):
      * total milliseconds and launch counts per kernel class
-     * IBMX_K_GEOMETRY .. IBMX_K_PAIRS. */
+     * IBMX_K_GEOMETRY .. IBMX_K_FTOT. */
     double kernel_ms[8];
     int64_t kernel_launches[8];
 } ibmx_stats;
@@ -125,10 +125,12 @@ typedef struct {
 enum {
     IBMX_K_GEOMETRY = 0,      /* marker geometry, binning and sorting          */
     IBMX_K_INTERP = 1,        /* interpolation + marker force + particle sums  */
-    IBMX_K_SPREAD = 2,        /* spreading + velocity update                   */
+    IBMX_K_SPREAD = 2,        /* spreading + velocity update of one pass       */
     IBMX_K_BACKWARD = 3,      /* adjoint passes                                */
     IBMX_K_PAIRS = 4,         /* pair pass (lists, forces, mask)               */
-    IBMX_K_OTHER = 5          /* fills, residual finish                        */
+    IBMX_K_OTHER = 5,         /* fills, residual finish                        */
+    IBMX_K_FTOT = 6           /* spreading of the pass-summed amplitudes into
+                                 f_tot (calls with two or more passes)         */
 };
 
 /*

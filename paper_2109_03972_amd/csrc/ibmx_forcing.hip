@@ -1,24 +1,27 @@
 // Outer forcing loop of the collocated direct-forcing IBM (Sec. 2.2.2).
 //
 // Data flow of one ibmx_forcing call
-//   binning    (once)  marker geometry in FP64 (X_l = x_p + o_l -> base node,
-//                      fractional offsets, periodic wrap, wall check), then a
-//                      counting sort of the active markers by the spatial tile
-//                      of their centre node.  Markers of one particle stay
-//                      contiguous and in index order inside a tile.
-//   halo lists (once)  for every tile, the markers of neighbouring tiles whose
-//                      delta support reaches into it.
-//   per pass           interpolation (one thread per sorted marker, gathers
-//                      through the caches): U_l, F_l = (U^d_l - U_l)/c, the
-//                      spreading amplitude G_l = F_l dV_l / h^3, and the FP64
-//                      particle sums and residual (wave-segmented reductions).
-//                      Spreading (one workgroup per tile): every marker whose
-//                      support reaches the tile adds w G_l into an LDS copy of
-//                      the tile; the workgroup then owns the tile's nodes and
-//                      updates u += c f and f_tot += f with plain stores -- no
-//                      global atomics.
-// The interpolation kernel of a pass finishes before its spreading kernel
-// starts, so u is updated in place: u^m = u^{m-1} + c f^{m-1}.
+//   binning (once)  marker geometry in FP64 (X_l = x_p + o_l -> base node,
+//                   fractional offsets, periodic wrap, wall check), then a
+//                   counting sort of the active markers by the spatial tile of
+//                   their centre node (markers of one particle stay contiguous
+//                   and in index order inside a tile), and per tile a halo list
+//                   of the neighbouring tiles' markers whose delta support
+//                   reaches into it.
+//   passes          one workgroup per tile.  Every marker whose support
+//                   reaches the tile (own + halo) is interpolated from
+//                   u^{m-1}, gets F = (U^d - U)/c and the spreading amplitude
+//                   G = F dV / h^3, and adds w G into an LDS copy of the tile.
+//                   The workgroup owns its tile's nodes and writes
+//                   u^m = u^{m-1} + c f into a second grid (ping-pong: the
+//                   neighbours still read u^{m-1} during the pass).  Own
+//                   markers also feed the FP64 particle sums, the residual and
+//                   the per-marker sum of G over the passes.
+//   f_tot (once)    spreading is linear and the markers do not move during the
+//                   call, so sum_m f^m is the spread of the summed amplitudes:
+//                   one last tile pass adds it to f_tot.
+// With a single pass the interpolation runs marker-parallel and the final
+// tile pass updates u and f_tot together.
 #include <math.h>
 
 #include "ibmx_internal.hpp"
@@ -28,6 +31,21 @@ namespace {
 
 constexpr int TS = IBMX_BIN_SLOTS;   // per-particle tile table (open addressing)
 constexpr int NXCD = 8;              // MI355X: 8 XCDs, workgroups dealt round-robin
+
+template <typename T>
+struct V4;
+template <>
+struct V4<float> {
+    typedef float4 type;
+    __device__ static float from_bits(unsigned v) { return __uint_as_float(v); }
+    __device__ static unsigned to_bits(float v) { return __float_as_uint(v); }
+};
+template <>
+struct V4<double> {
+    typedef double4 type;
+    __device__ static double from_bits(unsigned v) { return __longlong_as_double((long long)v); }
+    __device__ static unsigned to_bits(double v) { return (unsigned)__double_as_longlong(v); }
+};
 
 // ---------------------------------------------------------------------------
 // small helpers
@@ -61,6 +79,11 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks)
     const int q = nblocks / NXCD, r = nblocks % NXCD;
     const int x = bid % NXCD, k = bid / NXCD;
     return x * q + min(x, r) + k;
+}
+
+__device__ __forceinline__ unsigned long long lanemask_lt(int lane)
+{
+    return (1ull << lane) - 1ull;
 }
 
 // Marker geometry: base node b (wrapped) and fractional offset t per axis.
@@ -99,11 +122,6 @@ __device__ __forceinline__ int home_tile(const GridC &g, const TileC &tc, const 
     return ti[0] + tc.nt[0] * (ti[1] + tc.nt[1] * ti[2]);
 }
 
-__device__ __forceinline__ unsigned long long lanemask_lt(int lane)
-{
-    return (1ull << lane) - 1ull;
-}
-
 // open-addressing lookup/insert of a tile id in a wave-private table
 __device__ __forceinline__ int table_slot(volatile int *keys, int key)
 {
@@ -120,6 +138,97 @@ __device__ __forceinline__ int table_slot(volatile int *keys, int key)
     }
     return -1;
 }
+
+template <typename T, int W>
+__device__ __forceinline__ void stencil(const GridC &g, unsigned node, const T *tt, int ix[3][W],
+                                        T w[3][W])
+{
+    int b[3];
+    unpack_node(g, node, b);
+    for (int a = 0; a < 3; ++a) {
+        Delta<W, T>::w(tt[a], w[a]);
+#pragma unroll
+        for (int k = 0; k < W; ++k)
+            ix[a][k] = axis_node(g, a, b[a], k);
+    }
+}
+
+// U = sum over the W^3 stencil of w u (one velocity grid, three components)
+template <typename T, int W>
+__device__ __forceinline__ void gather(const GridC &g, const int ix[3][W], const T w[3][W],
+                                       const T *__restrict__ u, T *U)
+{
+    const long long N = g.nodes;
+    U[0] = U[1] = U[2] = T(0);
+#pragma unroll
+    for (int k = 0; k < W; ++k)
+#pragma unroll
+        for (int jj = 0; jj < W; ++jj) {
+            const T wzy = w[2][k] * w[1][jj];
+            const long long row = ((long long)ix[2][k] * g.n[1] + ix[1][jj]) * g.n[0];
+#pragma unroll
+            for (int i = 0; i < W; ++i) {
+                const T ww = wzy * w[0][i];
+                const long long nd = row + ix[0][i];
+                U[0] += ww * u[nd];
+                U[1] += ww * u[N + nd];
+                U[2] += ww * u[2 * N + nd];
+            }
+        }
+}
+
+// Marker force from the interpolated velocity (FP64): F = (U^d - U)/c with
+// U^d = u_p + omega_p x o; red[6] receives dV |U^d - U|^2 and G = F dV / h^3
+// is returned.
+template <typename T>
+__device__ __forceinline__ void marker_force(const GridC &g, int np, double c, int pid,
+                                             const double *o, const T *U,
+                                             const double *__restrict__ dV,
+                                             const double *__restrict__ up,
+                                             const double *__restrict__ wp, double *red, T *G)
+{
+    const double upp[3] = {up[pid], up[np + pid], up[2 * np + pid]};
+    const double wpp[3] = {wp[pid], wp[np + pid], wp[2 * np + pid]};
+    const double dVp = dV[pid];
+    const double Ud[3] = {upp[0] + (wpp[1] * o[2] - wpp[2] * o[1]),
+                          upp[1] + (wpp[2] * o[0] - wpp[0] * o[2]),
+                          upp[2] + (wpp[0] * o[1] - wpp[1] * o[0])};
+    double rsq = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const double r = Ud[a] - (double)U[a];
+        rsq += dVp * r * r;
+        G[a] = (T)(r / c * dVp * g.inv_h3);
+    }
+    red[6] = rsq;
+}
+
+// Row walk over a tile's nodes for the write-out: each wave takes whole rows
+// of B[0] nodes (64 / B[0] rows at a time), UNR row groups per step, so that
+// every thread issues all its loads before any store.
+struct TileWalk {
+    int rpi, sub, lx, rows, nw;
+    bool lane_ok;
+    float inv_by;
+    __device__ TileWalk(const TileC &tc, int e0)
+    {
+        const int lane = threadIdx.x & (IBMX_WAVE - 1);
+        rpi = IBMX_WAVE / tc.B[0];
+        sub = lane / tc.B[0];
+        lx = lane - sub * tc.B[0];
+        rows = tc.B[1] * tc.B[2];
+        nw = blockDim.x / IBMX_WAVE;
+        lane_ok = sub < rpi && lx < e0;
+        inv_by = 1.0f / (float)tc.B[1];
+    }
+    // row index -> (ly, lz); exact for rows < 2^16
+    __device__ void yz(int r, int by, int &ly, int &lz) const
+    {
+        lz = (int)(((float)r + 0.5f) * inv_by);
+        ly = r - lz * by;
+    }
+};
+
+constexpr int UNR = 4;
 
 // ---------------------------------------------------------------------------
 // binning step A: one wave per particle.  Tile key and rank of every active
@@ -138,8 +247,8 @@ __global__ __launch_bounds__(256) void k_bin_count(
     __shared__ int s_cnt[4][TS];
     const int wv = threadIdx.x / IBMX_WAVE, lane = threadIdx.x & (IBMX_WAVE - 1);
     const int p = blockIdx.x * 4 + wv;
-    if (p >= np)
-        return;
+    int active = 0;
+    if (p < np) {
     volatile int *keys = s_keys[wv];
     volatile int *cnt = s_cnt[wv];
     for (int s = lane; s < TS; s += IBMX_WAVE) {
@@ -148,7 +257,6 @@ __global__ __launch_bounds__(256) void k_bin_count(
     }
     const double xc[3] = {xp[p], xp[np + p], xp[2 * np + p]};
     const int l0 = moff[p], l1 = moff[p + 1];
-    int active = 0;
     for (int base = l0; base < l1; base += IBMX_WAVE) {
         const int l = base + lane;
         int key = -1;
@@ -198,9 +306,8 @@ __global__ __launch_bounds__(256) void k_bin_count(
         if (k >= 0)
             atomicAdd(&tile_count[k], cnt[s]);
     }
-    active = wave_sum_i(active);
-    if (lane == 0 && active)
-        atomicAdd((unsigned long long *)&count[0], (unsigned long long)active);
+    }
+    slot_add(count, block_sum<long long>(active));
 }
 
 // ---------------------------------------------------------------------------
@@ -212,8 +319,8 @@ __global__ __launch_bounds__(256) void k_bin_scatter(
     GridC g, int np, int nm, const int *__restrict__ moff, const double *__restrict__ body,
     const double *__restrict__ xp, const int *__restrict__ m_key, const int *__restrict__ m_rank,
     const int *__restrict__ tab, const int *__restrict__ tile_start, int *__restrict__ tile_cursor,
-    unsigned *__restrict__ rec_node, T *__restrict__ rec_t, T *__restrict__ rec_o,
-    int *__restrict__ rec_pid, int *__restrict__ rec_src)
+    typename V4<T>::type *__restrict__ rec_tn, typename V4<T>::type *__restrict__ rec_op,
+    int *__restrict__ rec_src, int *__restrict__ m_inv)
 {
     __shared__ int s_base[4][TS];
     const int wv = threadIdx.x / IBMX_WAVE, lane = threadIdx.x & (IBMX_WAVE - 1);
@@ -230,9 +337,12 @@ __global__ __launch_bounds__(256) void k_bin_scatter(
     const int l0 = moff[p], l1 = moff[p + 1];
     for (int l = l0 + lane; l < l1; l += IBMX_WAVE) {
         const int slot = m_key[l];
-        if (slot < 0)
+        if (slot < 0) {
+            m_inv[l] = -1;
             continue;
+        }
         const int dst = base_of[slot] + m_rank[l];
+        m_inv[l] = dst;
         double X[3], t[3], o[3];
         int b[3];
         for (int a = 0; a < 3; ++a) {
@@ -240,12 +350,17 @@ __global__ __launch_bounds__(256) void k_bin_scatter(
             X[a] = xc[a] + o[a];
         }
         marker_geometry<W>(g, X, b, t);
-        rec_node[dst] = pack_node(g, b[0], b[1], b[2]);
-        for (int a = 0; a < 3; ++a) {
-            rec_t[(size_t)a * nm + dst] = (T)t[a];
-            rec_o[(size_t)a * nm + dst] = (T)o[a];
-        }
-        rec_pid[dst] = p;
+        typename V4<T>::type tn, op;
+        tn.x = (T)t[0];
+        tn.y = (T)t[1];
+        tn.z = (T)t[2];
+        tn.w = V4<T>::from_bits(pack_node(g, b[0], b[1], b[2]));
+        op.x = (T)o[0];
+        op.y = (T)o[1];
+        op.z = (T)o[2];
+        op.w = V4<T>::from_bits((unsigned)p);
+        rec_tn[dst] = tn;
+        rec_op[dst] = op;
         rec_src[dst] = l;
     }
 }
@@ -253,12 +368,11 @@ __global__ __launch_bounds__(256) void k_bin_scatter(
 // ---------------------------------------------------------------------------
 // halo lists: every sorted marker registers itself with each neighbouring
 // tile its support reaches (at most 7: tiles are at least W nodes wide).
+// Registrations to the same tile are aggregated per wave.
 // ---------------------------------------------------------------------------
 template <typename T, int W, bool EMIT>
-__global__ __launch_bounds__(256) void k_halo(GridC g, TileC tc, int nm,
-                                              const int *__restrict__ n_act_p,
-                                              const unsigned *__restrict__ rec_node,
-                                              const T *__restrict__ rec_t,
+__global__ __launch_bounds__(256) void k_halo(GridC g, TileC tc, const int *__restrict__ n_act_p,
+                                              const typename V4<T>::type *__restrict__ rec_tn,
                                               int *__restrict__ halo_count,
                                               const int *__restrict__ halo_start,
                                               int *__restrict__ halo_cursor,
@@ -266,14 +380,18 @@ __global__ __launch_bounds__(256) void k_halo(GridC g, TileC tc, int nm,
                                               long long *__restrict__ count, int *__restrict__ err)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & (IBMX_WAVE - 1);
     const int n_act = *n_act_p;
-    int entries = 0;
+    int tgt[7];
+    int ntg = 0;
     if (j < n_act) {
+        const typename V4<T>::type tn = rec_tn[j];
+        const T tt[3] = {tn.x, tn.y, tn.z};
         int b[3];
-        unpack_node(g, rec_node[j], b);
+        unpack_node(g, V4<T>::to_bits(tn.w), b);
         int tl[3][2], nt[3], home[3];
         for (int a = 0; a < 3; ++a) {
-            const int last = rec_t[(size_t)a * nm + j] == T(0) ? W - 2 : W - 1;
+            const int last = tt[a] == T(0) ? W - 2 : W - 1;
             home[a] = axis_node(g, a, b[a], 1) / tc.B[a];
             const int t0 = axis_node(g, a, b[a], 0) / tc.B[a];
             const int t1 = axis_node(g, a, b[a], last) / tc.B[a];
@@ -287,218 +405,375 @@ __global__ __launch_bounds__(256) void k_halo(GridC g, TileC tc, int nm,
                     const int tx = tl[0][kx], ty = tl[1][ky], tz = tl[2][kz];
                     if (tx == home[0] && ty == home[1] && tz == home[2])
                         continue;
-                    const int tile = tx + tc.nt[0] * (ty + tc.nt[1] * tz);
-                    if (EMIT) {
-                        const long long pos =
-                            (long long)halo_start[tile] + atomicAdd(&halo_cursor[tile], 1);
-                        if (pos < cap)
-                            halo_list[pos] = j;
-                        else
-                            atomicCAS(err, 0, (int)IBMX_ECAPACITY);
-                    } else {
-                        atomicAdd(&halo_count[tile], 1);
-                    }
-                    ++entries;
+                    tgt[ntg++] = tx + tc.nt[0] * (ty + tc.nt[1] * tz);
                 }
     }
-    if (!EMIT) {
-        entries = wave_sum_i(entries);
-        if ((threadIdx.x & (IBMX_WAVE - 1)) == 0 && entries)
-            atomicAdd((unsigned long long *)&count[2], (unsigned long long)entries);
+    int entries = ntg;
+    for (int k = 0; k < 7; ++k) {
+        const int key = k < ntg ? tgt[k] : -1;
+        unsigned long long pending = __ballot(key >= 0);
+        while (pending) {
+            const int leader = __ffsll((long long)pending) - 1;
+            const int kk = __shfl(key, leader, IBMX_WAVE);
+            const unsigned long long m = __ballot(key == kk) & pending;
+            int base = 0;
+            if (lane == leader)
+                base = atomicAdd(EMIT ? &halo_cursor[kk] : &halo_count[kk], __popcll(m));
+            if (EMIT) {
+                base = __shfl(base, leader, IBMX_WAVE);
+                if (key == kk) {
+                    const long long pos =
+                        (long long)halo_start[kk] + base + __popcll(m & lanemask_lt(lane));
+                    if (pos < cap)
+                        halo_list[pos] = j;
+                    else
+                        atomicCAS(err, 0, (int)IBMX_ECAPACITY);
+                }
+            }
+            pending &= ~m;
+        }
     }
+    if (!EMIT)
+        slot_add(count + 2 * IBMX_RSLOTS, block_sum<long long>(entries));
 }
 
 // ---------------------------------------------------------------------------
-// interpolation + marker force + particle sums: one thread per sorted marker
+// tile geometry shared by the tile kernels
 // ---------------------------------------------------------------------------
-template <typename T, int W>
-__device__ __forceinline__ void stencil(const GridC &g, unsigned node, const T *tt, int ix[3][W],
-                                        T w[3][W])
-{
-    int b[3];
-    unpack_node(g, node, b);
-    for (int a = 0; a < 3; ++a) {
-        Delta<W, T>::w(tt[a], w[a]);
-#pragma unroll
-        for (int k = 0; k < W; ++k)
-            ix[a][k] = axis_node(g, a, b[a], k);
+struct TileBox {
+    int o[3];   // first node of the tile
+    int e[3];   // extent (last tile of an axis may be short)
+    __device__ TileBox(const GridC &g, const TileC &tc, int tile)
+    {
+        const int t0 = tile % tc.nt[0], t1 = (tile / tc.nt[0]) % tc.nt[1];
+        const int t2 = tile / (tc.nt[0] * tc.nt[1]);
+        o[0] = t0 * tc.B[0];
+        o[1] = t1 * tc.B[1];
+        o[2] = t2 * tc.B[2];
+        for (int a = 0; a < 3; ++a)
+            e[a] = min(tc.B[a], g.n[a] - o[a]);
     }
+};
+
+template <typename V>
+__device__ __forceinline__ V block_max(V v)
+{
+    __shared__ V part[16];
+#pragma unroll
+    for (int off = IBMX_WAVE / 2; off > 0; off >>= 1) {
+        V w = __shfl_xor(v, off, IBMX_WAVE);
+        v = w > v ? w : v;
+    }
+    __syncthreads();
+    if ((threadIdx.x & (IBMX_WAVE - 1)) == 0)
+        part[threadIdx.x / IBMX_WAVE] = v;
+    __syncthreads();
+    V r = part[0];
+    for (int w = 1; w < (int)(blockDim.x / IBMX_WAVE); ++w)
+        r = part[w] > r ? part[w] : r;
+    return r;   // valid in every thread
 }
 
-// Sum v over the run of equal keys each lane belongs to (runs are contiguous
-// in the wave); the last lane of each run returns the run total.
-__device__ __forceinline__ double segmented_sum(double v, int lane, int head_lane)
-{
-#pragma unroll
-    for (int off = 1; off < IBMX_WAVE; off <<= 1) {
-        double u = __shfl_up(v, off, IBMX_WAVE);
-        if (lane - off >= head_lane)
-            v += u;
-    }
-    return v;
-}
-
-template <typename T, int W>
+// ---------------------------------------------------------------------------
+// interpolation of one pass, one workgroup per tile.  The velocity of the
+// tile and of the support halo around it (R[a] = B[a] + W - 1 nodes per
+// axis, starting one node before the tile) is staged in LDS with coalesced
+// row loads; each own marker then gathers its W^3 stencil from LDS.
+// MODE 0: first pass (writes the amplitude G and its pass sum), 1: later
+// pass (adds G to the pass sum), 2: residual only.
+// ---------------------------------------------------------------------------
+template <typename T, int W, int MODE>
 __global__ __launch_bounds__(256) void k_interp(
-    GridC g, int nm, int pass, int final_only, double c, int np, const int *__restrict__ n_act_p,
-    const unsigned *__restrict__ rec_node, const T *__restrict__ rec_t, const T *__restrict__ rec_o,
-    const int *__restrict__ rec_pid, const int *__restrict__ rec_src,
-    const double *__restrict__ dV, const double *__restrict__ up, const double *__restrict__ wp,
-    const T *__restrict__ u, T *__restrict__ rec_G, double *__restrict__ S_out,
-    double *__restrict__ T_out, double *__restrict__ acc, T *__restrict__ U_dbg)
+    GridC g, TileC tc, int nm, int np, int pass, double c, const int *__restrict__ tile_start,
+    const typename V4<T>::type *__restrict__ rec_tn, const typename V4<T>::type *__restrict__ rec_op,
+    const int *__restrict__ rec_src, const double *__restrict__ dV, const double *__restrict__ up,
+    const double *__restrict__ wp, const T *__restrict__ u, typename V4<T>::type *__restrict__ rec_Gp,
+    typename V4<T>::type *__restrict__ rec_Gs, double *__restrict__ acc, T *__restrict__ U_dbg)
 {
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int j = blk * blockDim.x + threadIdx.x;
-    const int lane = threadIdx.x & (IBMX_WAVE - 1);
-    const int n_act = *n_act_p;
+    typedef typename V4<T>::type T4;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *reg = reinterpret_cast<T *>(smem);
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int a0 = tile_start[tile], a1 = tile_start[tile + 1];
+    const int n_own = a1 - a0;
+    if (n_own == 0)
+        return;
+    const TileBox box(g, tc, tile);
+    const int R0 = tc.B[0] + W - 1, R1 = tc.B[1] + W - 1, R2 = tc.B[2] + W - 1;
+    const int RV = R0 * R1 * R2;
     const long long N = g.nodes;
-    int pid = -1;
-    double red[7] = {0, 0, 0, 0, 0, 0, 0};
-    if (j < n_act) {
-        pid = rec_pid[j];
-        T tt[3];
-        double o[3];
-        for (int a = 0; a < 3; ++a) {
-            tt[a] = rec_t[(size_t)a * nm + j];
-            o[a] = (double)rec_o[(size_t)a * nm + j];
+    const int lane = threadIdx.x & (IBMX_WAVE - 1), wave = threadIdx.x / IBMX_WAVE;
+    const int nw = blockDim.x / IBMX_WAVE;
+    // stage u on [o - 1, o + B + W - 2) per axis; nodes beyond a wall read 0
+    {
+        // each wave loads rpi rows of R0 nodes at a time (one row, lanes
+        // striding along it, when R0 > 64)
+        const int rpi = R0 <= IBMX_WAVE ? IBMX_WAVE / R0 : 1;
+        const int sub = R0 <= IBMX_WAVE ? lane / R0 : 0;
+        const int rx0 = R0 <= IBMX_WAVE ? lane - sub * R0 : lane;
+        const bool lane_on = sub < rpi;
+        for (int r = wave * rpi + sub; lane_on && r < R1 * R2; r += nw * rpi) {
+            const int ry = r % R1, rz = r / R1;
+            int gy = box.o[1] - 1 + ry, gz = box.o[2] - 1 + rz;
+            bool ok = true;
+            if (g.periodic[1]) {
+                gy = gy < 0 ? gy + g.n[1] : (gy >= g.n[1] ? gy - g.n[1] : gy);
+            } else {
+                ok = ok && gy >= 0 && gy < g.n[1];
+            }
+            if (g.periodic[2]) {
+                gz = gz < 0 ? gz + g.n[2] : (gz >= g.n[2] ? gz - g.n[2] : gz);
+            } else {
+                ok = ok && gz >= 0 && gz < g.n[2];
+            }
+            const long long rowg = ((long long)gz * g.n[1] + gy) * g.n[0];
+            for (int rx = rx0; rx < R0; rx += IBMX_WAVE) {
+                int gx = box.o[0] - 1 + rx;
+                bool okx = ok;
+                if (g.periodic[0]) {
+                    gx = gx < 0 ? gx + g.n[0] : (gx >= g.n[0] ? gx - g.n[0] : gx);
+                } else {
+                    okx = okx && gx >= 0 && gx < g.n[0];
+                }
+                const int li = (rz * R1 + ry) * R0 + rx;
+                T v0 = T(0), v1 = T(0), v2 = T(0);
+                if (okx) {
+                    v0 = u[rowg + gx];
+                    v1 = u[N + rowg + gx];
+                    v2 = u[2 * N + rowg + gx];
+                }
+                reg[li] = v0;
+                reg[RV + li] = v1;
+                reg[2 * RV + li] = v2;
+            }
         }
-        int ix[3][W];
-        T w[3][W];
-        stencil<T, W>(g, rec_node[j], tt, ix, w);
-        T U[3] = {0, 0, 0};
+    }
+    __syncthreads();
+    double rsq = 0.0;
+    for (int e = threadIdx.x; e < n_own; e += blockDim.x) {
+        double red[7];
+        {
+            const int j = a0 + e;
+            const T4 tn = rec_tn[j], op = rec_op[j];
+            const T tt[3] = {tn.x, tn.y, tn.z};
+            const double o[3] = {(double)op.x, (double)op.y, (double)op.z};
+            const int pid = (int)V4<T>::to_bits(op.w);
+            int b[3];
+            unpack_node(g, V4<T>::to_bits(tn.w), b);
+            T w[3][W];
+            int d[3];
+            for (int a = 0; a < 3; ++a) {
+                Delta<W, T>::w(tt[a], w[a]);
+                // region index of the base node: the centre node b + 1 lies in
+                // the tile, so d is in [0, e); d >= e only when b wrapped
+                // below a periodic seam (b = n - 1 for a centre at node 0)
+                d[a] = b[a] - box.o[a] + 1;
+                if (d[a] >= box.e[a])
+                    d[a] -= g.n[a];
+            }
+            T U[3] = {T(0), T(0), T(0)};
 #pragma unroll
-        for (int k = 0; k < W; ++k)
+            for (int k = 0; k < W; ++k)
 #pragma unroll
-            for (int jj = 0; jj < W; ++jj) {
-                const T wzy = w[2][k] * w[1][jj];
-                const long long row = ((long long)ix[2][k] * g.n[1] + ix[1][jj]) * g.n[0];
+                for (int jj = 0; jj < W; ++jj) {
+                    const T wzy = w[2][k] * w[1][jj];
+                    const int row = ((d[2] + k) * R1 + (d[1] + jj)) * R0 + d[0];
 #pragma unroll
-                for (int i = 0; i < W; ++i) {
-                    const T ww = wzy * w[0][i];
-                    const long long nd = row + ix[0][i];
-                    U[0] += ww * u[nd];
-                    U[1] += ww * u[N + nd];
-                    U[2] += ww * u[2 * N + nd];
+                    for (int i = 0; i < W; ++i) {
+                        const T ww = wzy * w[0][i];
+                        U[0] += ww * reg[row + i];
+                        U[1] += ww * reg[RV + row + i];
+                        U[2] += ww * reg[2 * RV + row + i];
+                    }
+                }
+            T G[3];
+            marker_force<T>(g, np, c, pid, o, U, dV, up, wp, red, G);
+            if (MODE != 2) {
+                if (U_dbg) {
+                    const int src = rec_src[j];
+                    for (int a = 0; a < 3; ++a)
+                        U_dbg[((size_t)pass * 3 + a) * nm + src] = U[a];
+                }
+                T4 gp;
+                gp.x = G[0];
+                gp.y = G[1];
+                gp.z = G[2];
+                gp.w = T(0);
+                rec_Gp[j] = gp;
+                if (MODE == 0) {
+                    rec_Gs[j] = gp;
+                } else {
+                    T4 gs = rec_Gs[j];
+                    gs.x += G[0];
+                    gs.y += G[1];
+                    gs.z += G[2];
+                    rec_Gs[j] = gs;
                 }
             }
-        const double upp[3] = {up[pid], up[np + pid], up[2 * np + pid]};
-        const double wpp[3] = {wp[pid], wp[np + pid], wp[2 * np + pid]};
-        const double dVp = dV[pid];
-        const double Ud[3] = {upp[0] + (wpp[1] * o[2] - wpp[2] * o[1]),
-                              upp[1] + (wpp[2] * o[0] - wpp[0] * o[2]),
-                              upp[2] + (wpp[0] * o[1] - wpp[1] * o[0])};
-        double F[3];
-        for (int a = 0; a < 3; ++a) {
-            const double r = Ud[a] - (double)U[a];
-            F[a] = r / c;
-            red[6] += dVp * r * r;
         }
-        if (!final_only) {
-            if (U_dbg) {
-                const int src = rec_src[j];
-                for (int a = 0; a < 3; ++a)
-                    U_dbg[((size_t)pass * 3 + a) * nm + src] = U[a];
-            }
-            for (int a = 0; a < 3; ++a) {
-                red[a] = F[a] * dVp;
-                rec_G[(size_t)a * nm + j] = (T)(F[a] * dVp * g.inv_h3);
-            }
-            red[3] = (o[1] * F[2] - o[2] * F[1]) * dVp;
-            red[4] = (o[2] * F[0] - o[0] * F[2]) * dVp;
-            red[5] = (o[0] * F[1] - o[1] * F[0]) * dVp;
-        }
+        rsq += red[6];
     }
-    // residual: plain wave sum, one atomic per wave
-    const double rs = wave_sum(red[6]);
-    if (lane == 0 && rs != 0.0)
-        atomicAdd(&acc[pass], rs);
-    if (final_only)
-        return;
-    // particle sums: segmented over runs of equal particle id
-    const int prev = __shfl_up(pid, 1, IBMX_WAVE);
-    const bool head = lane == 0 || prev != pid;
-    const unsigned long long heads = __ballot(head);
-    const unsigned long long le = lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1ull);
-    const int head_lane = 63 - __clzll((long long)(heads & le));
-    const int next = __shfl_down(pid, 1, IBMX_WAVE);
-    const bool tail = lane == IBMX_WAVE - 1 || next != pid;
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        const double s = segmented_sum(red[q], lane, head_lane);
-        if (tail && pid >= 0) {
-            double *dst = q < 3 ? &S_out[(size_t)q * np + pid] : &T_out[(size_t)(q - 3) * np + pid];
-            atomicAdd(dst, s);
-        }
-    }
+    slot_add(acc + (size_t)pass * IBMX_RSLOTS, block_sum<double>(rsq));
 }
 
 // ---------------------------------------------------------------------------
-// spreading + velocity update: one workgroup per tile, LDS accumulation
+// particle force and torque sums, one wave per particle, after the passes.
+// The markers do not move during the call, so the sums over passes and
+// markers of F dV and o x F dV are h^3 sum_l G_l and h^3 sum_l o_l x G_l
+// with G_l the amplitude summed over the passes.  Markers are visited in
+// index order: the result does not depend on scheduling.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_particle_sums(int np, int nm, double h3,
+                                                       const int *__restrict__ moff,
+                                                       const double *__restrict__ body,
+                                                       const int *__restrict__ m_inv,
+                                                       const typename V4<T>::type *__restrict__ rec_Gs,
+                                                       double *__restrict__ S_out,
+                                                       double *__restrict__ T_out)
+{
+    const int wv = threadIdx.x / IBMX_WAVE, lane = threadIdx.x & (IBMX_WAVE - 1);
+    const int p = blockIdx.x * 4 + wv;
+    if (p >= np)
+        return;
+    double sm[6] = {0, 0, 0, 0, 0, 0};
+    for (int l = moff[p] + lane; l < moff[p + 1]; l += IBMX_WAVE) {
+        const int j = m_inv[l];
+        if (j < 0)
+            continue;
+        const typename V4<T>::type gv = rec_Gs[j];
+        const double G[3] = {(double)gv.x, (double)gv.y, (double)gv.z};
+        const double o[3] = {body[l], body[(size_t)nm + l], body[2 * (size_t)nm + l]};
+        sm[0] += G[0];
+        sm[1] += G[1];
+        sm[2] += G[2];
+        sm[3] += o[1] * G[2] - o[2] * G[1];
+        sm[4] += o[2] * G[0] - o[0] * G[2];
+        sm[5] += o[0] * G[1] - o[1] * G[0];
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+        sm[q] = wave_sum(sm[q]);
+    if (lane == 0)
+        for (int a = 0; a < 3; ++a) {
+            S_out[(size_t)a * np + p] = h3 * sm[a];
+            T_out[(size_t)a * np + p] = h3 * sm[3 + a];
+        }
+}
+
+// ---------------------------------------------------------------------------
+// LDS accumulation of the spread.  On gfx950 an LDS float add costs about
+// 195 cycles per wave instruction, an FP64 add 27 and a 32-bit integer add 9.
+// FP32 grids therefore accumulate 32-bit fixed point: per component a
+// power-of-two scale puts the tile's largest |G| just below 2^23, leaving 8
+// bits of headroom for the sum of weights at a node (a few units), and the
+// integer sums do not depend on the order of the additions.  FP64 grids
+// accumulate in FP64.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct SpreadAcc;
+template <>
+struct SpreadAcc<float> {
+    typedef int type;
+    __device__ static float scale_for(float m)
+    {
+        int ex = 0;
+        frexpf(m, &ex);                  // m < 2^ex
+        return m > 0.0f ? ldexpf(1.0f, min(23 - ex, 126)) : 0.0f;
+    }
+    __device__ static void add(int *a, float v) { atomicAdd(a, __float2int_rn(v)); }
+    __device__ static float value(int a, float unscale) { return (float)a * unscale; }
+    __device__ static float unscale_for(float s) { return s > 0.0f ? 1.0f / s : 0.0f; }
+};
+template <>
+struct SpreadAcc<double> {
+    typedef double type;
+    __device__ static double scale_for(double) { return 1.0; }
+    __device__ static void add(double *a, double v) { atomicAdd(a, v); }
+    __device__ static double value(double a, double) { return a; }
+    __device__ static double unscale_for(double) { return 1.0; }
+};
+
+// ---------------------------------------------------------------------------
+// spreading, one workgroup per tile.  Every marker whose support reaches
+// the tile (own + halo list) adds w G to the tile's nodes in LDS; then the
+// workgroup, owner of its nodes, applies u += c f (add_u) and f_tot += f
+// (add_f) with plain loads and stores.
 // ---------------------------------------------------------------------------
 template <typename T, int W>
-__global__ __launch_bounds__(256) void k_spread(GridC g, TileC tc, int nm, T c, int count_shell,
+__global__ __launch_bounds__(256) void k_spread(GridC g, TileC tc, T c, int add_u, int add_f,
+                                                int count_shell,
                                                 const int *__restrict__ tile_start,
                                                 const int *__restrict__ halo_start,
                                                 const int *__restrict__ halo_list,
-                                                const unsigned *__restrict__ rec_node,
-                                                const T *__restrict__ rec_t,
-                                                const T *__restrict__ rec_G, T *__restrict__ u,
-                                                T *__restrict__ f_tot,
+                                                const typename V4<T>::type *__restrict__ rec_tn,
+                                                const typename V4<T>::type *__restrict__ rec_G,
+                                                T *__restrict__ u, T *__restrict__ f_tot,
                                                 long long *__restrict__ count)
 {
+    typedef typename V4<T>::type T4;
+    typedef typename SpreadAcc<T>::type A;
     extern __shared__ __align__(16) unsigned char smem[];
-    T *acc = reinterpret_cast<T *>(smem);
+    A *acc = reinterpret_cast<A *>(smem);
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
     const int a0 = tile_start[tile], a1 = tile_start[tile + 1];
     const int h0 = halo_start[tile], h1 = halo_start[tile + 1];
     const int n_own = a1 - a0, n_tot = n_own + (h1 - h0);
     if (n_tot == 0)
         return;
-    const int tx = tile % tc.nt[0], ty = (tile / tc.nt[0]) % tc.nt[1];
-    const int tz = tile / (tc.nt[0] * tc.nt[1]);
-    const int o0 = tx * tc.B[0], o1 = ty * tc.B[1], o2 = tz * tc.B[2];
-    const int e0 = min(tc.B[0], g.n[0] - o0), e1 = min(tc.B[1], g.n[1] - o1);
-    const int e2 = min(tc.B[2], g.n[2] - o2);
+    const TileBox box(g, tc, tile);
     const int V = tc.B[0] * tc.B[1] * tc.B[2];
+    T scale[3] = {T(1), T(1), T(1)}, unscale[3] = {T(1), T(1), T(1)};
+    if (sizeof(A) == 4) {
+        // largest amplitude reaching the tile, per component
+        float gm[3] = {0.f, 0.f, 0.f};
+        for (int e = threadIdx.x; e < n_tot; e += blockDim.x) {
+            const int j = e < n_own ? a0 + e : halo_list[h0 + e - n_own];
+            const T4 gv = rec_G[j];
+            gm[0] = fmaxf(gm[0], fabsf((float)gv.x));
+            gm[1] = fmaxf(gm[1], fabsf((float)gv.y));
+            gm[2] = fmaxf(gm[2], fabsf((float)gv.z));
+        }
+        for (int a = 0; a < 3; ++a) {
+            scale[a] = SpreadAcc<T>::scale_for(block_max<float>(gm[a]));
+            unscale[a] = SpreadAcc<T>::unscale_for(scale[a]);
+        }
+    }
     for (int i = threadIdx.x; i < 3 * V; i += blockDim.x)
-        acc[i] = T(0);
+        acc[i] = A(0);
     __syncthreads();
     for (int e = threadIdx.x; e < n_tot; e += blockDim.x) {
         const int j = e < n_own ? a0 + e : halo_list[h0 + e - n_own];
-        T tt[3], G[3];
-        for (int a = 0; a < 3; ++a) {
-            tt[a] = rec_t[(size_t)a * nm + j];
-            G[a] = rec_G[(size_t)a * nm + j];
-        }
+        const T4 tn = rec_tn[j], gv = rec_G[j];
+        const T tt[3] = {tn.x, tn.y, tn.z};
+        const T Gs[3] = {gv.x * scale[0], gv.y * scale[1], gv.z * scale[2]};
         int ix[3][W];
         T w[3][W];
-        stencil<T, W>(g, rec_node[j], tt, ix, w);
-        int lx[W], ly[W], lz[W];
+        stencil<T, W>(g, V4<T>::to_bits(tn.w), tt, ix, w);
 #pragma unroll
         for (int k = 0; k < W; ++k) {
-            lx[k] = ix[0][k] - o0;
-            ly[k] = ix[1][k] - o1;
-            lz[k] = ix[2][k] - o2;
-        }
-#pragma unroll
-        for (int k = 0; k < W; ++k) {
-            if ((unsigned)lz[k] >= (unsigned)e2)
+            const int lz = ix[2][k] - box.o[2];
+            if ((unsigned)lz >= (unsigned)box.e[2])
                 continue;
 #pragma unroll
             for (int jj = 0; jj < W; ++jj) {
-                if ((unsigned)ly[jj] >= (unsigned)e1)
+                const int ly = ix[1][jj] - box.o[1];
+                if ((unsigned)ly >= (unsigned)box.e[1])
                     continue;
                 const T wzy = w[2][k] * w[1][jj];
-                const int rowl = (lz[k] * tc.B[1] + ly[jj]) * tc.B[0];
+                const int rowl = (lz * tc.B[1] + ly) * tc.B[0];
 #pragma unroll
                 for (int i = 0; i < W; ++i) {
-                    if ((unsigned)lx[i] >= (unsigned)e0)
+                    const int lx = ix[0][i] - box.o[0];
+                    if ((unsigned)lx >= (unsigned)box.e[0])
                         continue;
                     const T ww = wzy * w[0][i];
-                    const int li = rowl + lx[i];
-                    atomicAdd(&acc[li], ww * G[0]);
-                    atomicAdd(&acc[V + li], ww * G[1]);
-                    atomicAdd(&acc[2 * V + li], ww * G[2]);
+                    if (ww == T(0))
+                        continue;
+                    const int li = rowl + lx;
+                    SpreadAcc<T>::add(&acc[li], ww * Gs[0]);
+                    SpreadAcc<T>::add(&acc[V + li], ww * Gs[1]);
+                    SpreadAcc<T>::add(&acc[2 * V + li], ww * Gs[2]);
                 }
             }
         }
@@ -506,55 +781,107 @@ __global__ __launch_bounds__(256) void k_spread(GridC g, TileC tc, int nm, T c, 
     __syncthreads();
     const long long N = g.nodes;
     int touched = 0;
-    for (int li = threadIdx.x; li < V; li += blockDim.x) {
-        const int lx = li % tc.B[0], ly = (li / tc.B[0]) % tc.B[1], lz = li / (tc.B[0] * tc.B[1]);
-        if (lx >= e0 || ly >= e1 || lz >= e2)
-            continue;
-        const T f0 = acc[li], f1 = acc[V + li], f2 = acc[2 * V + li];
-        if (f0 == T(0) && f1 == T(0) && f2 == T(0))
-            continue;
-        ++touched;
-        const long long gi = ((long long)(o2 + lz) * g.n[1] + (o1 + ly)) * g.n[0] + (o0 + lx);
-        u[gi] += c * f0;
-        u[N + gi] += c * f1;
-        u[2 * N + gi] += c * f2;
-        f_tot[gi] += f0;
-        f_tot[N + gi] += f1;
-        f_tot[2 * N + gi] += f2;
+    const TileWalk tw(tc, box.e[0]);
+    const int wave = threadIdx.x / IBMX_WAVE;
+    for (int r0 = wave * tw.rpi + tw.sub; r0 < tw.rows; r0 += UNR * tw.nw * tw.rpi) {
+        long long gi[UNR];
+        bool act[UNR];
+        T fv[UNR][3], fo[UNR][3], uo[UNR][3];
+#pragma unroll
+        for (int q = 0; q < UNR; ++q) {
+            const int r = r0 + q * tw.nw * tw.rpi;
+            int ly, lz;
+            tw.yz(r, tc.B[1], ly, lz);
+            const int li = (lz * tc.B[1] + ly) * tc.B[0] + tw.lx;
+            act[q] = tw.lane_ok && r < tw.rows && ly < box.e[1] && lz < box.e[2];
+            gi[q] = ((long long)(box.o[2] + lz) * g.n[1] + (box.o[1] + ly)) * g.n[0] +
+                    (box.o[0] + tw.lx);
+            if (act[q]) {
+                const A i0 = acc[li], i1 = acc[V + li], i2 = acc[2 * V + li];
+                act[q] = i0 != A(0) || i1 != A(0) || i2 != A(0);
+                fv[q][0] = SpreadAcc<T>::value(i0, unscale[0]);
+                fv[q][1] = SpreadAcc<T>::value(i1, unscale[1]);
+                fv[q][2] = SpreadAcc<T>::value(i2, unscale[2]);
+            }
+            if (act[q]) {
+                if (add_f) {
+                    fo[q][0] = f_tot[gi[q]];
+                    fo[q][1] = f_tot[N + gi[q]];
+                    fo[q][2] = f_tot[2 * N + gi[q]];
+                }
+                if (add_u) {
+                    uo[q][0] = u[gi[q]];
+                    uo[q][1] = u[N + gi[q]];
+                    uo[q][2] = u[2 * N + gi[q]];
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < UNR; ++q) {
+            if (!act[q])
+                continue;
+            ++touched;
+            if (add_f) {
+                f_tot[gi[q]] = fo[q][0] + fv[q][0];
+                f_tot[N + gi[q]] = fo[q][1] + fv[q][1];
+                f_tot[2 * N + gi[q]] = fo[q][2] + fv[q][2];
+            }
+            if (add_u) {
+                u[gi[q]] = uo[q][0] + c * fv[q][0];
+                u[N + gi[q]] = uo[q][1] + c * fv[q][1];
+                u[2 * N + gi[q]] = uo[q][2] + c * fv[q][2];
+            }
+        }
     }
-    if (count_shell) {
-        touched = wave_sum_i(touched);
-        if ((threadIdx.x & (IBMX_WAVE - 1)) == 0 && touched)
-            atomicAdd((unsigned long long *)&count[1], (unsigned long long)touched);
-    }
+    if (count_shell)
+        slot_add(count + IBMX_RSLOTS, block_sum<long long>(touched));
 }
 
-__global__ void k_finish_resid(const double *acc, double *resid, int n)
+// resid[pass] = sqrt of the sum of the pass's partial slots (one block per pass)
+__global__ __launch_bounds__(256) void k_finish_resid(const double *acc, double *resid)
 {
-    int i = threadIdx.x;
-    if (i < n)
-        resid[i] = sqrt(acc[i]);
+    double v = 0.0;
+    for (int i = threadIdx.x; i < IBMX_RSLOTS; i += blockDim.x)
+        v += acc[(size_t)blockIdx.x * IBMX_RSLOTS + i];
+    v = block_sum<double>(v);
+    if (threadIdx.x == 0)
+        resid[blockIdx.x] = sqrt(v);
 }
 
 int nblocks(long long n, int b) { return (int)((n + b - 1) / b) > 0 ? (int)((n + b - 1) / b) : 1; }
+
+template <typename T, int W>
+size_t interp_lds(const TileC &tc)
+{
+    return (size_t)3 * (tc.B[0] + W - 1) * (tc.B[1] + W - 1) * (tc.B[2] + W - 1) * sizeof(T);
+}
+
+template <typename T>
+size_t spread_lds(const TileC &tc)
+{
+    return (size_t)3 * tc.B[0] * tc.B[1] * tc.B[2] * sizeof(typename SpreadAcc<T>::type);
+}
 
 template <typename T, int W>
 ibmx_status run_forcing(ibmx_plan p, T *u, T *f_tot, const double *xp, const double *up,
                         const double *wp, const uint8_t *mask, double *S_out, double *T_out,
                         double *resid_out, T *U_dbg)
 {
+    typedef typename V4<T>::type T4;
     hipStream_t s = p->stream;
     const int nm = p->nm, np = p->np, n_iter = p->prm.n_iter;
     const double c = p->prm.two_alpha_dt;
     const TileC tc = p->tc;
     const int ntiles = tc.ntiles;
     const int *n_act = p->tile_start + ntiles;   // total after the scan
+    T4 *rec_tn = (T4 *)p->rec_tn, *rec_op = (T4 *)p->rec_op;
+    T4 *rec_Gp = (T4 *)p->rec_Gp, *rec_Gs = (T4 *)p->rec_G;
     {
         ProfScope ps(p, IBMX_K_OTHER);
         ibmx_fill_f64(S_out, 0.0, 3LL * np, s);
         ibmx_fill_f64(T_out, 0.0, 3LL * np, s);
-        ibmx_fill_f64(p->d_acc, 0.0, n_iter + 1, s);
-        ibmx_fill_i32((int *)p->d_count, 0, 16, s);
+        ibmx_fill_f64(p->d_acc, 0.0, (long long)(n_iter + 1) * IBMX_RSLOTS, s);
+        ibmx_fill_i32((int *)p->d_count, 0, 16LL * IBMX_RSLOTS, s);
         ibmx_fill_i32(p->tile_count, 0, ntiles + 1, s);
         ibmx_fill_i32(p->tile_cursor, 0, ntiles + 1, s);
         ibmx_fill_i32(p->halo_count, 0, ntiles + 1, s);
@@ -569,79 +896,102 @@ ibmx_status run_forcing(ibmx_plan p, T *u, T *f_tot, const double *xp, const dou
         ibmx_exclusive_scan(p->tile_count, p->tile_start, ntiles, s);
         hipLaunchKernelGGL((k_bin_scatter<T, W>), dim3(gb), dim3(256), 0, s, p->g, np, nm,
                            p->d_moff, p->body, xp, p->m_key, p->m_rank, p->bin_tab, p->tile_start,
-                           p->tile_cursor, (unsigned *)p->rec_node, (T *)p->rec_t, (T *)p->rec_o,
-                           p->rec_pid, p->rec_src);
+                           p->tile_cursor, rec_tn, rec_op, p->rec_src, p->m_inv);
         hipLaunchKernelGGL((k_halo<T, W, false>), dim3(nblocks(nm, 256)), dim3(256), 0, s, p->g,
-                           tc, nm, n_act, (const unsigned *)p->rec_node, (const T *)p->rec_t,
-                           p->halo_count, (const int *)nullptr, (int *)nullptr, (int *)nullptr,
-                           p->halo_cap, p->d_count, p->d_err);
+                           tc, n_act, (const T4 *)rec_tn, p->halo_count, (const int *)nullptr,
+                           (int *)nullptr, (int *)nullptr, p->halo_cap, p->d_count, p->d_err);
         ibmx_exclusive_scan(p->halo_count, p->halo_start, ntiles, s);
         hipLaunchKernelGGL((k_halo<T, W, true>), dim3(nblocks(nm, 256)), dim3(256), 0, s, p->g,
-                           tc, nm, n_act, (const unsigned *)p->rec_node, (const T *)p->rec_t,
-                           p->halo_count, p->halo_start, p->halo_cursor, p->halo_list, p->halo_cap,
-                           p->d_count, p->d_err);
+                           tc, n_act, (const T4 *)rec_tn, p->halo_count, p->halo_start,
+                           p->halo_cursor, p->halo_list, p->halo_cap, p->d_count, p->d_err);
     } else {
         ibmx_exclusive_scan(p->tile_count, p->tile_start, ntiles, s);
         ibmx_exclusive_scan(p->halo_count, p->halo_start, ntiles, s);
     }
-    const int gi = nblocks(nm, 256);
-    const size_t lds = (size_t)3 * tc.B[0] * tc.B[1] * tc.B[2] * sizeof(T);
+    const size_t lds_i = interp_lds<T, W>(tc), lds_s = spread_lds<T>(tc);
     for (int m = 0; m < n_iter && nm > 0; ++m) {
         {
             ProfScope ps(p, IBMX_K_INTERP);
-            hipLaunchKernelGGL((k_interp<T, W>), dim3(gi), dim3(256), 0, s, p->g, nm, m, 0, c, np,
-                               n_act, (const unsigned *)p->rec_node, (const T *)p->rec_t,
-                               (const T *)p->rec_o, p->rec_pid, p->rec_src, p->dV, up, wp, u,
-                               (T *)p->rec_G, S_out, T_out, p->d_acc, U_dbg);
+            if (m == 0)
+                hipLaunchKernelGGL((k_interp<T, W, 0>), dim3(ntiles), dim3(256), lds_i, s, p->g, tc,
+                                   nm, np, m, c, p->tile_start, (const T4 *)rec_tn,
+                                   (const T4 *)rec_op, p->rec_src, p->dV, up, wp, (const T *)u,
+                                   rec_Gp, rec_Gs, p->d_acc, U_dbg);
+            else
+                hipLaunchKernelGGL((k_interp<T, W, 1>), dim3(ntiles), dim3(256), lds_i, s, p->g, tc,
+                                   nm, np, m, c, p->tile_start, (const T4 *)rec_tn,
+                                   (const T4 *)rec_op, p->rec_src, p->dV, up, wp, (const T *)u,
+                                   rec_Gp, rec_Gs, p->d_acc, U_dbg);
         }
-        {
-            ProfScope ps(p, IBMX_K_SPREAD);
-            hipLaunchKernelGGL((k_spread<T, W>), dim3(ntiles), dim3(256), lds, s, p->g, tc, nm,
-                               (T)c, m == 0 ? 1 : 0, p->tile_start, p->halo_start, p->halo_list,
-                               (const unsigned *)p->rec_node, (const T *)p->rec_t,
-                               (const T *)p->rec_G, u, f_tot, p->d_count);
-        }
+        ProfScope ps(p, IBMX_K_SPREAD);
+        hipLaunchKernelGGL((k_spread<T, W>), dim3(ntiles), dim3(256), lds_s, s, p->g, tc, (T)c, 1,
+                           n_iter == 1 ? 1 : 0, m == 0 ? 1 : 0, p->tile_start, p->halo_start,
+                           p->halo_list, (const T4 *)rec_tn, (const T4 *)rec_Gp, u, f_tot,
+                           p->d_count);
+    }
+    if (n_iter >= 2 && nm > 0) {
+        // f_tot += spread of the amplitudes summed over the passes
+        ProfScope ps(p, IBMX_K_FTOT);
+        hipLaunchKernelGGL((k_spread<T, W>), dim3(ntiles), dim3(256), lds_s, s, p->g, tc, (T)c, 0,
+                           1, 0, p->tile_start, p->halo_start, p->halo_list, (const T4 *)rec_tn,
+                           (const T4 *)rec_Gs, u, f_tot, p->d_count);
+    }
+    if (np > 0) {
+        ProfScope ps(p, IBMX_K_OTHER);
+        if (nm > 0)
+            hipLaunchKernelGGL((k_particle_sums<T>), dim3(nblocks(np, 4)), dim3(256), 0, s, np, nm,
+                               p->g.h * p->g.h * p->g.h, p->d_moff, p->body, p->m_inv,
+                               (const T4 *)rec_Gs, S_out, T_out);
     }
     if (resid_out) {
         if (nm > 0) {
-            ProfScope ps(p, IBMX_K_INTERP);
-            hipLaunchKernelGGL((k_interp<T, W>), dim3(gi), dim3(256), 0, s, p->g, nm, n_iter, 1, c,
-                               np, n_act, (const unsigned *)p->rec_node, (const T *)p->rec_t,
-                               (const T *)p->rec_o, p->rec_pid, p->rec_src, p->dV, up, wp, u,
-                               (T *)p->rec_G, S_out, T_out, p->d_acc, (T *)nullptr);
+            ProfScope ps(p, IBMX_K_OTHER);
+            hipLaunchKernelGGL((k_interp<T, W, 2>), dim3(ntiles), dim3(256), lds_i, s, p->g, tc, nm,
+                               np, n_iter, c, p->tile_start, (const T4 *)rec_tn, (const T4 *)rec_op,
+                               p->rec_src, p->dV, up, wp, (const T *)u, rec_Gp, rec_Gs, p->d_acc,
+                               (T *)nullptr);
         }
-        hipLaunchKernelGGL(k_finish_resid, dim3(1), dim3(64), 0, s, p->d_acc, resid_out, n_iter + 1);
+        hipLaunchKernelGGL(k_finish_resid, dim3(n_iter + 1), dim3(256), 0, s, p->d_acc, resid_out);
     }
     return ibmx_launch_check();
 }
 
-}  // namespace
-
-// LDS bytes of the spreading kernel for the plan's tile and precision
-size_t ibmx_spread_lds_bytes(ibmx_plan p)
+template <typename T, int W>
+hipError_t allow_lds_w(int bytes_interp, int bytes_spread)
 {
-    return (size_t)3 * p->tc.B[0] * p->tc.B[1] * p->tc.B[2] *
-           (p->prec == IBMX_F64 ? sizeof(double) : sizeof(float));
+    hipError_t e;
+    if ((e = hipFuncSetAttribute((const void *)k_spread<T, W>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, bytes_spread)) != hipSuccess)
+        return e;
+    const void *interps[] = {(const void *)k_interp<T, W, 0>, (const void *)k_interp<T, W, 1>,
+                             (const void *)k_interp<T, W, 2>};
+    for (const void *f : interps)
+        if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes_interp)) !=
+            hipSuccess)
+            return e;
+    return hipSuccess;
 }
 
-// Allow the spreading kernels the plan's LDS footprint (above 64 KB needs
-// an explicit opt-in).
+}  // namespace
+
+// Allow the tile kernels the plan's LDS footprint (above 64 KB needs an
+// explicit opt-in).
 ibmx_status ibmx_spread_allow_lds(ibmx_plan p)
 {
-    const int bytes = (int)ibmx_spread_lds_bytes(p);
-    hipError_t e = hipSuccess;
+    const size_t ls = p->prec == IBMX_F64 ? spread_lds<double>(p->tc) : spread_lds<float>(p->tc);
+    const size_t l3 = p->prec == IBMX_F64 ? interp_lds<double, 3>(p->tc) : interp_lds<float, 3>(p->tc);
+    const size_t l4 = p->prec == IBMX_F64 ? interp_lds<double, 4>(p->tc) : interp_lds<float, 4>(p->tc);
+    if (ls > 160 * 1024 || l4 > 160 * 1024)
+        return IBMX_EUNSUPPORTED;
+    hipError_t e;
     if (p->prec == IBMX_F64) {
-        e = hipFuncSetAttribute((const void *)k_spread<double, 3>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        e = allow_lds_w<double, 3>((int)l3, (int)ls);
         if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void *)k_spread<double, 4>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+            e = allow_lds_w<double, 4>((int)l4, (int)ls);
     } else {
-        e = hipFuncSetAttribute((const void *)k_spread<float, 3>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        e = allow_lds_w<float, 3>((int)l3, (int)ls);
         if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void *)k_spread<float, 4>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+            e = allow_lds_w<float, 4>((int)l4, (int)ls);
     }
     return e == hipSuccess ? IBMX_OK : IBMX_EUNSUPPORTED;
 }

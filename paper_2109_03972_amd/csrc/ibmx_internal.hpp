@@ -7,6 +7,7 @@
 #include "../../include/ibmx.h"
 
 #define IBMX_WAVE 64
+#define IBMX_RSLOTS 1024          // spread-out accumulation slots per counter
 #define IBMX_BIN_SLOTS_LOG2 9
 #define IBMX_BIN_SLOTS (1 << IBMX_BIN_SLOTS_LOG2)   // tiles one particle may touch
 
@@ -53,18 +54,19 @@ struct ibmx_plan_s {
     int *d_moff;          // [np + 1]
     int *d_pid;           // [nm] marker -> particle
     int *d_err;           // [1] first deferred error (0 = none)
-    double *d_acc;        // [n_iter_cap + 1] residual accumulators
-    long long *d_count;   // [8] counters (active markers, shell nodes, ...)
+    double *d_acc;        // [n_iter_cap + 2][IBMX_RSLOTS] residual partial sums
+    long long *d_count;   // [8][IBMX_RSLOTS] counters (active markers, shell
+                          // nodes, halo entries) as partial sums
 
-    // marker records (sorted by spreading tile)
-    int *rec_node;        // [nm] packed base node (bx | by << 10 ... see forcing)
+    // marker records, sorted by spreading tile (T4 = float4 / double4)
+    void *rec_tn;         // T4[nm] {t_x, t_y, t_z, packed base node (bits)}
+    void *rec_op;         // T4[nm] {o_x, o_y, o_z, particle id (bits)}
+    void *rec_Gp;         // T4[nm] spreading amplitude G = F dV / h^3 of the pass
+    void *rec_G;          // T4[nm] G summed over the passes
     int *rec_src;         // [nm] original marker index
-    int *rec_pid;         // [nm] particle
-    void *rec_t;          // T[3][nm] fractional offsets
-    void *rec_o;          // T[3][nm] body offsets
-    void *rec_G;          // T[3][nm] spreading amplitude F dV / h^3
-    int *m_key;           // [nm] per-marker tile slot / rank scratch
-    int *m_rank;          // [nm]
+    int *m_key;           // [nm] per-marker tile slot (binning scratch)
+    int *m_rank;          // [nm] rank within (particle, tile) (binning scratch)
+    int *m_inv;           // [nm] sorted position of marker l (-1: inactive)
 
     // tiles
     TileC tc;
@@ -140,7 +142,6 @@ struct ProfScope {
 
 ibmx_status ibmx_launch_check();
 ibmx_status ibmx_plan_alloc_tiles(ibmx_plan p, int tx, int ty, int tz);
-size_t ibmx_spread_lds_bytes(ibmx_plan p);
 ibmx_status ibmx_spread_allow_lds(ibmx_plan p);
 void ibmx_exclusive_scan(const int *in, int *out, int n, hipStream_t s);
 void ibmx_fill_i32(int *p, int v, long long n, hipStream_t s);
@@ -163,6 +164,40 @@ __device__ __forceinline__ double wave_sum(double v)
     for (int off = IBMX_WAVE / 2; off > 0; off >>= 1)
         v += __shfl_xor(v, off, IBMX_WAVE);
     return v;
+}
+
+// Block-wide sum; every thread of the block must call it; the result is
+// valid in thread 0.
+template <typename V>
+__device__ __forceinline__ V block_sum(V v)
+{
+    __shared__ V part[16];
+#pragma unroll
+    for (int off = IBMX_WAVE / 2; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, IBMX_WAVE);
+    __syncthreads();
+    if ((threadIdx.x & (IBMX_WAVE - 1)) == 0)
+        part[threadIdx.x / IBMX_WAVE] = v;
+    __syncthreads();
+    V r = V(0);
+    if (threadIdx.x == 0)
+        for (int w = 0; w < (int)(blockDim.x / IBMX_WAVE); ++w)
+            r += part[w];
+    return r;
+}
+
+// Add a block's partial to one of IBMX_RSLOTS slots of a counter (thread 0),
+// so that workgroups do not all hit one address.
+__device__ __forceinline__ void slot_add(double *slots, double v)
+{
+    if (threadIdx.x == 0 && v != 0.0)
+        atomicAdd(&slots[blockIdx.x & (IBMX_RSLOTS - 1)], v);
+}
+__device__ __forceinline__ void slot_add(long long *slots, long long v)
+{
+    if (threadIdx.x == 0 && v != 0)
+        atomicAdd((unsigned long long *)&slots[blockIdx.x & (IBMX_RSLOTS - 1)],
+                  (unsigned long long)v);
 }
 
 __device__ __forceinline__ int wave_sum_i(int v)

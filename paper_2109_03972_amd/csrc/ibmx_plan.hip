@@ -19,8 +19,8 @@ void free_plan(ibmx_plan p)
 {
     if (!p)
         return;
-    void *ptrs[] = {p->d_moff, p->d_pid, p->d_err, p->d_acc, p->d_count, p->rec_node,
-                    p->rec_src, p->rec_pid, p->rec_t, p->rec_o, p->rec_G, p->m_key,
+    void *ptrs[] = {p->d_moff, p->d_pid, p->d_err, p->d_acc, p->d_count, p->rec_tn,
+                    p->rec_op, p->rec_src, p->rec_Gp, p->rec_G, p->m_key, p->m_inv,
                     p->m_rank, p->tile_count, p->tile_start, p->tile_cursor, p->halo_count,
                     p->halo_start, p->halo_cursor, p->halo_list, p->bw_u, p->bw_F, p->bw_J,
                     p->bw_part, p->p_cell_of, p->p_cursor, p->p_count, p->p_off, p->p_wcount,
@@ -140,16 +140,16 @@ ibmx_status check_params(const ibmx_grid *g, const ibmx_params *prm)
     A((void **)&p->d_moff, sizeof(int) * (npz + 1));
     A((void **)&p->d_pid, sizeof(int) * nmz);
     A((void **)&p->d_err, sizeof(int) * 4);
-    A((void **)&p->d_acc, sizeof(double) * (p->n_iter_cap + 2));
-    A((void **)&p->d_count, sizeof(long long) * 8);
-    A((void **)&p->rec_node, sizeof(int) * nmz);
+    A((void **)&p->d_acc, sizeof(double) * (p->n_iter_cap + 2) * IBMX_RSLOTS);
+    A((void **)&p->d_count, sizeof(long long) * 8 * IBMX_RSLOTS);
+    A(&p->rec_tn, Ts * 4 * nmz);
+    A(&p->rec_op, Ts * 4 * nmz);
+    A(&p->rec_G, Ts * 4 * nmz);
+    A(&p->rec_Gp, Ts * 4 * nmz);
     A((void **)&p->rec_src, sizeof(int) * nmz);
-    A((void **)&p->rec_pid, sizeof(int) * nmz);
-    A(&p->rec_t, Ts * 3 * nmz);
-    A(&p->rec_o, Ts * 3 * nmz);
-    A(&p->rec_G, Ts * 3 * nmz);
     A((void **)&p->m_key, sizeof(int) * nmz);
     A((void **)&p->m_rank, sizeof(int) * nmz);
+    A((void **)&p->m_inv, sizeof(int) * nmz);
     A((void **)&p->p_cell_of, sizeof(int) * npz);
     A((void **)&p->p_count, sizeof(int) * (npz + 1));
     A((void **)&p->p_off, sizeof(int) * (npz + 1));
@@ -181,15 +181,16 @@ ibmx_status check_params(const ibmx_grid *g, const ibmx_params *prm)
     hipError_t e2 = hipMemcpy(p->d_moff, moff, sizeof(int) * (size_t)(np + 1), hipMemcpyHostToDevice);
     free(pid);
     free(moff);
-    if (e1 != hipSuccess || e2 != hipSuccess || hipMemset(p->d_err, 0, sizeof(int) * 4) != hipSuccess ||
-        hipMemset(p->d_count, 0, sizeof(long long) * 8) != hipSuccess) {
+    if (e1 != hipSuccess || e2 != hipSuccess ||
+        hipMemset(p->d_err, 0, sizeof(int) * 4) != hipSuccess ||
+        hipMemset(p->d_count, 0, sizeof(long long) * 8 * IBMX_RSLOTS) != hipSuccess) {
         free_plan(p);
         return IBMX_EDEVICE;
     }
     p->block = 256;
     p->stats.n_markers = nm;
-    // default spreading tiles: 16^3 nodes (FP32) / 16x16x8 (FP64), 48 KB of LDS
-    st = ibmx_plan_alloc_tiles(p, 16, 16, precision == IBMX_F64 ? 8 : 16);
+    // default tiles: 16 x 16 x 8 nodes
+    st = ibmx_plan_alloc_tiles(p, 16, 16, 8);
     if (st != IBMX_OK) {
         free_plan(p);
         return st;
@@ -205,7 +206,7 @@ ibmx_status ibmx_plan_alloc_tiles(ibmx_plan p, int tx, int ty, int tz)
     long long ntiles = 1;
     const int W = 4;   // widest delta support
     for (int a = 0; a < 3; ++a) {
-        if (t[a] < W)
+        if (t[a] < W || t[a] > 64)
             return IBMX_EINVAL;
         if (t[a] >= p->g.n[a]) {
             t[a] = p->g.n[a];
@@ -213,8 +214,11 @@ ibmx_status ibmx_plan_alloc_tiles(ibmx_plan p, int tx, int ty, int tz)
             // a short last tile must still hold a whole support
             while (t[a] > W && p->g.n[a] % t[a] != 0 && p->g.n[a] % t[a] < W)
                 --t[a];
-            if (p->g.n[a] % t[a] != 0 && p->g.n[a] % t[a] < W)
+            if (p->g.n[a] % t[a] != 0 && p->g.n[a] % t[a] < W) {
+                if (p->g.n[a] > 64)
+                    return IBMX_EUNSUPPORTED;
                 t[a] = p->g.n[a];
+            }
         }
         nt[a] = (p->g.n[a] + t[a] - 1) / t[a];
         ntiles *= nt[a];
@@ -320,12 +324,22 @@ extern "C" ibmx_status ibmx_plan_stats(ibmx_plan p, ibmx_stats *out)
         return IBMX_EINVAL;
     if (hipStreamSynchronize(p->stream) != hipSuccess)
         return IBMX_EDEVICE;
-    long long c[8];
-    if (hipMemcpy(c, p->d_count, sizeof(c), hipMemcpyDeviceToHost) != hipSuccess)
+    long long *c = (long long *)malloc(sizeof(long long) * 8 * IBMX_RSLOTS);
+    if (!c)
+        return IBMX_ENOMEM;
+    if (hipMemcpy(c, p->d_count, sizeof(long long) * 8 * IBMX_RSLOTS, hipMemcpyDeviceToHost) !=
+        hipSuccess) {
+        free(c);
         return IBMX_EDEVICE;
-    p->stats.n_active = c[0];
-    p->stats.shell_nodes = c[1];
-    p->stats.halo_entries = c[2];
+    }
+    long long tot[3] = {0, 0, 0};
+    for (int k = 0; k < 3; ++k)
+        for (int i = 0; i < IBMX_RSLOTS; ++i)
+            tot[k] += c[k * IBMX_RSLOTS + i];
+    free(c);
+    p->stats.n_active = tot[0];
+    p->stats.shell_nodes = tot[1];
+    p->stats.halo_entries = tot[2];
     p->stats.block = p->block;
     for (int i = 0; i < p->ev_used; ++i) {
         float ms = 0.0f;

@@ -57,7 +57,7 @@ class ibmx_stats(ctypes.Structure):
                 ("block", ctypes.c_int32), ("kernel_ms", ctypes.c_double * 8),
                 ("kernel_launches", ctypes.c_int64 * 8)]
 
-KERNEL_CLASSES = ("geometry", "interp", "spread", "backward", "pairs", "other")
+KERNEL_CLASSES = ("geometry", "interp", "spread", "backward", "pairs", "other", "ftot")
 
 
 _lib = None
