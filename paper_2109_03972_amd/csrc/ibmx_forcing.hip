@@ -228,7 +228,8 @@ struct TileWalk {
     }
 };
 
-constexpr int UNR = 4;
+constexpr int UNR = 4;    // row groups per write-out step
+constexpr int SUNR = 8;   // row groups per staging step
 
 // ---------------------------------------------------------------------------
 // binning step A: one wave per particle.  Tile key and rank of every active
@@ -474,6 +475,83 @@ __device__ __forceinline__ V block_max(V v)
     return r;   // valid in every thread
 }
 
+// Stage v = scale * src (+ src2) over the tile's support region
+// [o - 1, o + B + W - 2) per axis into LDS (nodes beyond a wall read 0): each
+// wave loads 64 / R0 rows of R0 nodes per step, and every thread issues SUNR
+// steps of loads before its LDS stores.
+template <typename T, int W>
+__device__ __forceinline__ void stage_region(const GridC &g, const TileC &tc, const TileBox &box,
+                                             const T *__restrict__ src, T scale,
+                                             const T *__restrict__ src2, T *reg)
+{
+    const int R0 = tc.B[0] + W - 1, R1 = tc.B[1] + W - 1, R2 = tc.B[2] + W - 1;
+    const int RV = R0 * R1 * R2;
+    const long long N = g.nodes;
+    const int lane = threadIdx.x & (IBMX_WAVE - 1), wave = threadIdx.x / IBMX_WAVE;
+    const int nw = blockDim.x / IBMX_WAVE;
+    const int rpi = IBMX_WAVE / R0;
+    const int sub = lane / R0, rx = lane - sub * R0;
+    const int step = nw * rpi, rows = R1 * R2;
+    int gx = box.o[0] - 1 + rx;
+    bool okx = sub < rpi;
+    if (g.periodic[0])
+        gx = gx < 0 ? gx + g.n[0] : (gx >= g.n[0] ? gx - g.n[0] : gx);
+    else
+        okx = okx && gx >= 0 && gx < g.n[0];
+    for (int r0 = wave * rpi + sub; r0 < rows; r0 += SUNR * step) {
+        T v[SUNR][3];
+        int li[SUNR];
+#pragma unroll
+        for (int q = 0; q < SUNR; ++q) {
+            const int r = r0 + q * step;
+            const int rz = r / R1, ry = r - rz * R1;
+            int gy = box.o[1] - 1 + ry, gz = box.o[2] - 1 + rz;
+            bool ok = okx && r < rows;
+            li[q] = ok ? (rz * R1 + ry) * R0 + rx : -1;
+            if (g.periodic[1])
+                gy = gy < 0 ? gy + g.n[1] : (gy >= g.n[1] ? gy - g.n[1] : gy);
+            else
+                ok = ok && gy >= 0 && gy < g.n[1];
+            if (g.periodic[2])
+                gz = gz < 0 ? gz + g.n[2] : (gz >= g.n[2] ? gz - g.n[2] : gz);
+            else
+                ok = ok && gz >= 0 && gz < g.n[2];
+            v[q][0] = v[q][1] = v[q][2] = T(0);
+            if (ok) {
+                const long long gi = ((long long)gz * g.n[1] + gy) * g.n[0] + gx;
+                v[q][0] = scale * src[gi];
+                v[q][1] = scale * src[N + gi];
+                v[q][2] = scale * src[2 * N + gi];
+                if (src2) {
+                    v[q][0] += src2[gi];
+                    v[q][1] += src2[N + gi];
+                    v[q][2] += src2[2 * N + gi];
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < SUNR; ++q) {
+            if (li[q] < 0)
+                continue;
+            reg[li[q]] = v[q][0];
+            reg[RV + li[q]] = v[q][1];
+            reg[2 * RV + li[q]] = v[q][2];
+        }
+    }
+}
+
+// Region index of a marker's base node per axis: the centre node b + 1 lies
+// in the tile, so d is in [0, e); d >= e only when b wrapped below a periodic
+// seam (b = n - 1 for a centre at node 0).
+__device__ __forceinline__ void region_base(const GridC &g, const TileBox &box, const int *b, int *d)
+{
+    for (int a = 0; a < 3; ++a) {
+        d[a] = b[a] - box.o[a] + 1;
+        if (d[a] >= box.e[a])
+            d[a] -= g.n[a];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // interpolation of one pass, one workgroup per tile.  The velocity of the
 // tile and of the support halo around it (R[a] = B[a] + W - 1 nodes per
@@ -504,50 +582,7 @@ __global__ __launch_bounds__(256) void k_interp(
     const long long N = g.nodes;
     const int lane = threadIdx.x & (IBMX_WAVE - 1), wave = threadIdx.x / IBMX_WAVE;
     const int nw = blockDim.x / IBMX_WAVE;
-    // stage u on [o - 1, o + B + W - 2) per axis; nodes beyond a wall read 0
-    {
-        // each wave loads rpi rows of R0 nodes at a time (one row, lanes
-        // striding along it, when R0 > 64)
-        const int rpi = R0 <= IBMX_WAVE ? IBMX_WAVE / R0 : 1;
-        const int sub = R0 <= IBMX_WAVE ? lane / R0 : 0;
-        const int rx0 = R0 <= IBMX_WAVE ? lane - sub * R0 : lane;
-        const bool lane_on = sub < rpi;
-        for (int r = wave * rpi + sub; lane_on && r < R1 * R2; r += nw * rpi) {
-            const int ry = r % R1, rz = r / R1;
-            int gy = box.o[1] - 1 + ry, gz = box.o[2] - 1 + rz;
-            bool ok = true;
-            if (g.periodic[1]) {
-                gy = gy < 0 ? gy + g.n[1] : (gy >= g.n[1] ? gy - g.n[1] : gy);
-            } else {
-                ok = ok && gy >= 0 && gy < g.n[1];
-            }
-            if (g.periodic[2]) {
-                gz = gz < 0 ? gz + g.n[2] : (gz >= g.n[2] ? gz - g.n[2] : gz);
-            } else {
-                ok = ok && gz >= 0 && gz < g.n[2];
-            }
-            const long long rowg = ((long long)gz * g.n[1] + gy) * g.n[0];
-            for (int rx = rx0; rx < R0; rx += IBMX_WAVE) {
-                int gx = box.o[0] - 1 + rx;
-                bool okx = ok;
-                if (g.periodic[0]) {
-                    gx = gx < 0 ? gx + g.n[0] : (gx >= g.n[0] ? gx - g.n[0] : gx);
-                } else {
-                    okx = okx && gx >= 0 && gx < g.n[0];
-                }
-                const int li = (rz * R1 + ry) * R0 + rx;
-                T v0 = T(0), v1 = T(0), v2 = T(0);
-                if (okx) {
-                    v0 = u[rowg + gx];
-                    v1 = u[N + rowg + gx];
-                    v2 = u[2 * N + rowg + gx];
-                }
-                reg[li] = v0;
-                reg[RV + li] = v1;
-                reg[2 * RV + li] = v2;
-            }
-        }
-    }
+    stage_region<T, W>(g, tc, box, u, T(1), (const T *)nullptr, reg);
     __syncthreads();
     double rsq = 0.0;
     for (int e = threadIdx.x; e < n_own; e += blockDim.x) {
@@ -562,15 +597,9 @@ __global__ __launch_bounds__(256) void k_interp(
             unpack_node(g, V4<T>::to_bits(tn.w), b);
             T w[3][W];
             int d[3];
-            for (int a = 0; a < 3; ++a) {
+            for (int a = 0; a < 3; ++a)
                 Delta<W, T>::w(tt[a], w[a]);
-                // region index of the base node: the centre node b + 1 lies in
-                // the tile, so d is in [0, e); d >= e only when b wrapped
-                // below a periodic seam (b = n - 1 for a centre at node 0)
-                d[a] = b[a] - box.o[a] + 1;
-                if (d[a] >= box.e[a])
-                    d[a] -= g.n[a];
-            }
+            region_base(g, box, b, d);
             T U[3] = {T(0), T(0), T(0)};
 #pragma unroll
             for (int k = 0; k < W; ++k)
@@ -837,6 +866,259 @@ __global__ __launch_bounds__(256) void k_spread(GridC g, TileC tc, T c, int add_
         slot_add(count + IBMX_RSLOTS, block_sum<long long>(touched));
 }
 
+
+// ---------------------------------------------------------------------------
+// Adjoint of the forcing loop.
+//
+// Reverse mode with the mask, body offsets, dV and c fixed.  The forward
+// passes are replayed on a scratch copy of u^0, keeping per marker and pass
+// the amplitude G^m and the Jacobian J^m = d U^m / d X of the interpolated
+// velocity (the grids are not stored).  Then, for m = n .. 1, with ub the
+// cotangent of u^m and fb = c ub + dL/df_tot the cotangent of f^m:
+//   Fb  = dV/h^3 (I fb) + dV (g_S + g_T x o)        cotangent of F^m
+//   Ub  = -Fb / c, Udb = Fb / c                     of U^m and U^d
+//   Xb += J^T Ub + sum_x dw/dX (fb(x) . G^m)         delta-gradient terms
+//   ub <- ub + I^T Ub                               (tile spreading of Ub)
+// and finally g_u0 = ub, g_up = sum Udb, g_wp = sum o x Udb, g_xp = sum Xb.
+// ---------------------------------------------------------------------------
+
+// Forward replay of one pass: U, G and J for own markers (LDS-staged u).
+template <typename T, int W>
+__global__ __launch_bounds__(256) void k_interp_jac(
+    GridC g, TileC tc, int nm, int np, double c, const int *__restrict__ tile_start,
+    const typename V4<T>::type *__restrict__ rec_tn, const typename V4<T>::type *__restrict__ rec_op,
+    const double *__restrict__ dV, const double *__restrict__ up, const double *__restrict__ wp,
+    const T *__restrict__ u, typename V4<T>::type *__restrict__ GJ)
+{
+    typedef typename V4<T>::type T4;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *reg = reinterpret_cast<T *>(smem);
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int a0 = tile_start[tile], n_own = tile_start[tile + 1] - a0;
+    if (n_own == 0)
+        return;
+    const TileBox box(g, tc, tile);
+    const int R0 = tc.B[0] + W - 1, R1 = tc.B[1] + W - 1, RV = R0 * R1 * (tc.B[2] + W - 1);
+    stage_region<T, W>(g, tc, box, u, T(1), (const T *)nullptr, reg);
+    __syncthreads();
+    const T inv_h = (T)(1.0 / g.h);
+    for (int e = threadIdx.x; e < n_own; e += blockDim.x) {
+        const int j = a0 + e;
+        const T4 tn = rec_tn[j], op = rec_op[j];
+        const T tt[3] = {tn.x, tn.y, tn.z};
+        const double o[3] = {(double)op.x, (double)op.y, (double)op.z};
+        const int pid = (int)V4<T>::to_bits(op.w);
+        int b[3], d[3];
+        unpack_node(g, V4<T>::to_bits(tn.w), b);
+        region_base(g, box, b, d);
+        T w[3][W], dw[3][W];
+        for (int a = 0; a < 3; ++a)
+            Delta<W, T>::wd(tt[a], w[a], dw[a]);
+        T U[3] = {T(0), T(0), T(0)};
+        T J[3][3] = {{T(0), T(0), T(0)}, {T(0), T(0), T(0)}, {T(0), T(0), T(0)}};
+#pragma unroll
+        for (int k = 0; k < W; ++k)
+#pragma unroll
+            for (int jj = 0; jj < W; ++jj) {
+                const int row = ((d[2] + k) * R1 + (d[1] + jj)) * R0 + d[0];
+#pragma unroll
+                for (int i = 0; i < W; ++i) {
+                    const T ww = w[2][k] * w[1][jj] * w[0][i];
+                    const T dx = w[2][k] * w[1][jj] * dw[0][i];
+                    const T dy = w[2][k] * dw[1][jj] * w[0][i];
+                    const T dz = dw[2][k] * w[1][jj] * w[0][i];
+#pragma unroll
+                    for (int cc = 0; cc < 3; ++cc) {
+                        const T v = reg[cc * RV + row + i];
+                        U[cc] += ww * v;
+                        J[cc][0] += dx * v;
+                        J[cc][1] += dy * v;
+                        J[cc][2] += dz * v;
+                    }
+                }
+            }
+        double red[7];
+        T G[3];
+        marker_force<T>(g, np, c, pid, o, U, dV, up, wp, red, G);
+        T4 q0, q1, q2;
+        q0.x = G[0];
+        q0.y = G[1];
+        q0.z = G[2];
+        q0.w = J[0][0] * inv_h;
+        q1.x = J[0][1] * inv_h;
+        q1.y = J[0][2] * inv_h;
+        q1.z = J[1][0] * inv_h;
+        q1.w = J[1][1] * inv_h;
+        q2.x = J[1][2] * inv_h;
+        q2.y = J[2][0] * inv_h;
+        q2.z = J[2][1] * inv_h;
+        q2.w = J[2][2] * inv_h;
+        GJ[j] = q0;
+        GJ[nm + j] = q1;
+        GJ[2 * (size_t)nm + j] = q2;
+    }
+}
+
+// Adjoint interpolation of one pass (own markers): Ub for the spreading,
+// and the per-marker accumulation of Udb and Xb.
+template <typename T, int W, int FIRST>
+__global__ __launch_bounds__(256) void k_interp_adj(
+    GridC g, TileC tc, int nm, int np, double c, const int *__restrict__ tile_start,
+    const typename V4<T>::type *__restrict__ rec_tn, const typename V4<T>::type *__restrict__ rec_op,
+    const double *__restrict__ dV, const double *__restrict__ gS, const double *__restrict__ gT,
+    const T *__restrict__ ub, const T *__restrict__ gf, const typename V4<T>::type *__restrict__ GJ,
+    typename V4<T>::type *__restrict__ Ub_out, double4 *__restrict__ accA,
+    double4 *__restrict__ accB)
+{
+    typedef typename V4<T>::type T4;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *reg = reinterpret_cast<T *>(smem);
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int a0 = tile_start[tile], n_own = tile_start[tile + 1] - a0;
+    if (n_own == 0)
+        return;
+    const TileBox box(g, tc, tile);
+    const int R0 = tc.B[0] + W - 1, R1 = tc.B[1] + W - 1, RV = R0 * R1 * (tc.B[2] + W - 1);
+    stage_region<T, W>(g, tc, box, ub, (T)c, gf, reg);   // fb = c ub + g_f
+    __syncthreads();
+    const double inv_h = 1.0 / g.h;
+    for (int e = threadIdx.x; e < n_own; e += blockDim.x) {
+        const int j = a0 + e;
+        const T4 tn = rec_tn[j], op = rec_op[j];
+        const T tt[3] = {tn.x, tn.y, tn.z};
+        const double o[3] = {(double)op.x, (double)op.y, (double)op.z};
+        const int pid = (int)V4<T>::to_bits(op.w);
+        const T4 q0 = GJ[j], q1 = GJ[nm + j], q2 = GJ[2 * (size_t)nm + j];
+        const T G[3] = {q0.x, q0.y, q0.z};
+        const double Jm[3][3] = {{(double)q0.w, (double)q1.x, (double)q1.y},
+                                 {(double)q1.z, (double)q1.w, (double)q2.x},
+                                 {(double)q2.y, (double)q2.z, (double)q2.w}};
+        int b[3], d[3];
+        unpack_node(g, V4<T>::to_bits(tn.w), b);
+        region_base(g, box, b, d);
+        T w[3][W], dw[3][W];
+        for (int a = 0; a < 3; ++a)
+            Delta<W, T>::wd(tt[a], w[a], dw[a]);
+        T IF[3] = {T(0), T(0), T(0)}, P[3] = {T(0), T(0), T(0)};
+#pragma unroll
+        for (int k = 0; k < W; ++k)
+#pragma unroll
+            for (int jj = 0; jj < W; ++jj) {
+                const int row = ((d[2] + k) * R1 + (d[1] + jj)) * R0 + d[0];
+#pragma unroll
+                for (int i = 0; i < W; ++i) {
+                    const T ww = w[2][k] * w[1][jj] * w[0][i];
+                    const T f0 = reg[row + i], f1 = reg[RV + row + i], f2 = reg[2 * RV + row + i];
+                    IF[0] += ww * f0;
+                    IF[1] += ww * f1;
+                    IF[2] += ww * f2;
+                    const T fg = f0 * G[0] + f1 * G[1] + f2 * G[2];
+                    P[0] += w[2][k] * w[1][jj] * dw[0][i] * fg;
+                    P[1] += w[2][k] * dw[1][jj] * w[0][i] * fg;
+                    P[2] += dw[2][k] * w[1][jj] * w[0][i] * fg;
+                }
+            }
+        const double dVp = dV[pid], v = dVp * g.inv_h3;
+        double gs[3] = {0.0, 0.0, 0.0}, gt[3] = {0.0, 0.0, 0.0};
+        for (int a = 0; a < 3; ++a) {
+            if (gS)
+                gs[a] = gS[(size_t)a * np + pid];
+            if (gT)
+                gt[a] = gT[(size_t)a * np + pid];
+        }
+        const double gtxo[3] = {gt[1] * o[2] - gt[2] * o[1], gt[2] * o[0] - gt[0] * o[2],
+                                gt[0] * o[1] - gt[1] * o[0]};
+        double Ubv[3], Udb[3];
+        for (int a = 0; a < 3; ++a) {
+            const double Fb = v * (double)IF[a] + dVp * (gs[a] + gtxo[a]);
+            Ubv[a] = -Fb / c;
+            Udb[a] = Fb / c;
+        }
+        double Xb[3];
+        for (int a = 0; a < 3; ++a)
+            Xb[a] = Jm[0][a] * Ubv[0] + Jm[1][a] * Ubv[1] + Jm[2][a] * Ubv[2] + (double)P[a] * inv_h;
+        T4 ubo;
+        ubo.x = (T)Ubv[0];
+        ubo.y = (T)Ubv[1];
+        ubo.z = (T)Ubv[2];
+        ubo.w = T(0);
+        Ub_out[j] = ubo;
+        double4 A = make_double4(Udb[0], Udb[1], Udb[2], 0.0);
+        double4 B = make_double4(Xb[0], Xb[1], Xb[2], 0.0);
+        if (!FIRST) {
+            const double4 A0 = accA[j], B0 = accB[j];
+            A.x += A0.x;
+            A.y += A0.y;
+            A.z += A0.z;
+            B.x += B0.x;
+            B.y += B0.y;
+            B.z += B0.z;
+        }
+        accA[j] = A;
+        accB[j] = B;
+    }
+}
+
+// Particle gradients from the per-marker accumulations (index order).
+__global__ __launch_bounds__(256) void k_particle_grad(int np, int nm, const int *__restrict__ moff,
+                                                       const double *__restrict__ body,
+                                                       const int *__restrict__ m_inv,
+                                                       const double4 *__restrict__ accA,
+                                                       const double4 *__restrict__ accB,
+                                                       double *__restrict__ gxp,
+                                                       double *__restrict__ gup,
+                                                       double *__restrict__ gwp)
+{
+    const int wv = threadIdx.x / IBMX_WAVE, lane = threadIdx.x & (IBMX_WAVE - 1);
+    const int p = blockIdx.x * 4 + wv;
+    if (p >= np)
+        return;
+    double sm[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int l = moff[p] + lane; l < moff[p + 1]; l += IBMX_WAVE) {
+        const int j = m_inv[l];
+        if (j < 0)
+            continue;
+        const double4 A = accA[j], B = accB[j];
+        const double o[3] = {body[l], body[(size_t)nm + l], body[2 * (size_t)nm + l]};
+        sm[0] += A.x;
+        sm[1] += A.y;
+        sm[2] += A.z;
+        sm[3] += o[1] * A.z - o[2] * A.y;
+        sm[4] += o[2] * A.x - o[0] * A.z;
+        sm[5] += o[0] * A.y - o[1] * A.x;
+        sm[6] += B.x;
+        sm[7] += B.y;
+        sm[8] += B.z;
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q)
+        sm[q] = wave_sum(sm[q]);
+    if (lane == 0)
+        for (int a = 0; a < 3; ++a) {
+            gup[(size_t)a * np + p] = sm[a];
+            gwp[(size_t)a * np + p] = sm[3 + a];
+            gxp[(size_t)a * np + p] = sm[6 + a];
+        }
+}
+
+template <typename T>
+__global__ void k_copy(T *__restrict__ dst, const T *__restrict__ src, long long n)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (; i < n; i += stride)
+        dst[i] = src[i];
+}
+
+template <typename T>
+__global__ void k_zero(T *__restrict__ dst, long long n)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (; i < n; i += stride)
+        dst[i] = T(0);
+}
+
 // resid[pass] = sqrt of the sum of the pass's partial slots (one block per pass)
 __global__ __launch_bounds__(256) void k_finish_resid(const double *acc, double *resid)
 {
@@ -862,25 +1144,21 @@ size_t spread_lds(const TileC &tc)
     return (size_t)3 * tc.B[0] * tc.B[1] * tc.B[2] * sizeof(typename SpreadAcc<T>::type);
 }
 
+// Marker geometry and binning of one call: tile counts, sorted records,
+// halo lists, and the zeroed per-call counters.
 template <typename T, int W>
-ibmx_status run_forcing(ibmx_plan p, T *u, T *f_tot, const double *xp, const double *up,
-                        const double *wp, const uint8_t *mask, double *S_out, double *T_out,
-                        double *resid_out, T *U_dbg)
+void bin_markers(ibmx_plan p, const double *xp, const uint8_t *mask, int n_acc)
 {
     typedef typename V4<T>::type T4;
     hipStream_t s = p->stream;
-    const int nm = p->nm, np = p->np, n_iter = p->prm.n_iter;
-    const double c = p->prm.two_alpha_dt;
+    const int nm = p->nm, np = p->np;
     const TileC tc = p->tc;
     const int ntiles = tc.ntiles;
     const int *n_act = p->tile_start + ntiles;   // total after the scan
     T4 *rec_tn = (T4 *)p->rec_tn, *rec_op = (T4 *)p->rec_op;
-    T4 *rec_Gp = (T4 *)p->rec_Gp, *rec_Gs = (T4 *)p->rec_G;
     {
         ProfScope ps(p, IBMX_K_OTHER);
-        ibmx_fill_f64(S_out, 0.0, 3LL * np, s);
-        ibmx_fill_f64(T_out, 0.0, 3LL * np, s);
-        ibmx_fill_f64(p->d_acc, 0.0, (long long)(n_iter + 1) * IBMX_RSLOTS, s);
+        ibmx_fill_f64(p->d_acc, 0.0, (long long)n_acc * IBMX_RSLOTS, s);
         ibmx_fill_i32((int *)p->d_count, 0, 16LL * IBMX_RSLOTS, s);
         ibmx_fill_i32(p->tile_count, 0, ntiles + 1, s);
         ibmx_fill_i32(p->tile_cursor, 0, ntiles + 1, s);
@@ -908,6 +1186,27 @@ ibmx_status run_forcing(ibmx_plan p, T *u, T *f_tot, const double *xp, const dou
         ibmx_exclusive_scan(p->tile_count, p->tile_start, ntiles, s);
         ibmx_exclusive_scan(p->halo_count, p->halo_start, ntiles, s);
     }
+}
+
+template <typename T, int W>
+ibmx_status run_forcing(ibmx_plan p, T *u, T *f_tot, const double *xp, const double *up,
+                        const double *wp, const uint8_t *mask, double *S_out, double *T_out,
+                        double *resid_out, T *U_dbg)
+{
+    typedef typename V4<T>::type T4;
+    hipStream_t s = p->stream;
+    const int nm = p->nm, np = p->np, n_iter = p->prm.n_iter;
+    const double c = p->prm.two_alpha_dt;
+    const TileC tc = p->tc;
+    const int ntiles = tc.ntiles;
+    T4 *rec_tn = (T4 *)p->rec_tn, *rec_op = (T4 *)p->rec_op;
+    T4 *rec_Gp = (T4 *)p->rec_Gp, *rec_Gs = (T4 *)p->rec_G;
+    {
+        ProfScope ps(p, IBMX_K_OTHER);
+        ibmx_fill_f64(S_out, 0.0, 3LL * np, s);
+        ibmx_fill_f64(T_out, 0.0, 3LL * np, s);
+    }
+    bin_markers<T, W>(p, xp, mask, n_iter + 1);
     const size_t lds_i = interp_lds<T, W>(tc), lds_s = spread_lds<T>(tc);
     for (int m = 0; m < n_iter && nm > 0; ++m) {
         {
@@ -956,6 +1255,89 @@ ibmx_status run_forcing(ibmx_plan p, T *u, T *f_tot, const double *xp, const dou
     return ibmx_launch_check();
 }
 
+
+template <typename T, int W>
+ibmx_status run_backward(ibmx_plan p, const T *u0, const double *xp, const double *up,
+                         const double *wp, const uint8_t *mask, const T *g_f, const T *g_u,
+                         const double *g_S, const double *g_T, T *gu0, double *gxp, double *gup,
+                         double *gwp)
+{
+    typedef typename V4<T>::type T4;
+    hipStream_t s = p->stream;
+    const int nm = p->nm, np = p->np, n_iter = p->prm.n_iter;
+    const double c = p->prm.two_alpha_dt;
+    const TileC tc = p->tc;
+    const int ntiles = tc.ntiles;
+    const long long G3 = 3 * p->g.nodes;
+    T4 *rec_tn = (T4 *)p->rec_tn, *rec_op = (T4 *)p->rec_op, *rec_Ub = (T4 *)p->rec_Gp;
+    // workspace: replay grid, per-pass G and Jacobian, per-marker sums
+    const size_t Ts = sizeof(T);
+    const size_t need = Ts * (size_t)G3 + 3 * sizeof(T4) * (size_t)nm * p->n_iter_cap +
+                        2 * sizeof(double4) * (size_t)nm;
+    if (p->bw_bytes < need) {
+        if (p->bw_u)
+            (void)hipFree(p->bw_u);
+        p->bw_u = nullptr;
+        p->bw_bytes = 0;
+        if (hipMalloc(&p->bw_u, need) != hipSuccess)
+            return IBMX_ENOMEM;
+        p->bw_bytes = need;
+    }
+    T *us = (T *)p->bw_u;
+    T4 *GJ = (T4 *)(us + G3);
+    double4 *accA = (double4 *)(GJ + 3 * (size_t)nm * p->n_iter_cap);
+    double4 *accB = accA + nm;
+    bin_markers<T, W>(p, xp, mask, 1);
+    const int cb = 4096;
+    {
+        ProfScope ps(p, IBMX_K_OTHER);
+        hipLaunchKernelGGL((k_copy<T>), dim3(cb), dim3(256), 0, s, us, u0, G3);
+        if (g_u)
+            hipLaunchKernelGGL((k_copy<T>), dim3(cb), dim3(256), 0, s, gu0, g_u, G3);
+        else
+            hipLaunchKernelGGL((k_zero<T>), dim3(cb), dim3(256), 0, s, gu0, G3);
+        ibmx_fill_f64(gxp, 0.0, 3LL * np, s);
+        ibmx_fill_f64(gup, 0.0, 3LL * np, s);
+        ibmx_fill_f64(gwp, 0.0, 3LL * np, s);
+    }
+    if (nm > 0) {
+        const size_t lds_i = interp_lds<T, W>(tc), lds_s = spread_lds<T>(tc);
+        ProfScope ps(p, IBMX_K_BACKWARD);
+        for (int m = 0; m < n_iter; ++m) {
+            T4 *GJm = GJ + 3 * (size_t)nm * m;
+            hipLaunchKernelGGL((k_interp_jac<T, W>), dim3(ntiles), dim3(256), lds_i, s, p->g, tc, nm,
+                               np, c, p->tile_start, (const T4 *)rec_tn, (const T4 *)rec_op, p->dV,
+                               up, wp, (const T *)us, GJm);
+            if (m < n_iter - 1)
+                hipLaunchKernelGGL((k_spread<T, W>), dim3(ntiles), dim3(256), lds_s, s, p->g, tc,
+                                   (T)c, 1, 0, 0, p->tile_start, p->halo_start, p->halo_list,
+                                   (const T4 *)rec_tn, (const T4 *)GJm, us, (T *)nullptr,
+                                   p->d_count);
+        }
+        for (int m = n_iter - 1; m >= 0; --m) {
+            const T4 *GJm = GJ + 3 * (size_t)nm * m;
+            if (m == n_iter - 1)
+                hipLaunchKernelGGL((k_interp_adj<T, W, 1>), dim3(ntiles), dim3(256), lds_i, s, p->g,
+                                   tc, nm, np, c, p->tile_start, (const T4 *)rec_tn,
+                                   (const T4 *)rec_op, p->dV, g_S, g_T, (const T *)gu0, g_f, GJm,
+                                   rec_Ub, accA, accB);
+            else
+                hipLaunchKernelGGL((k_interp_adj<T, W, 0>), dim3(ntiles), dim3(256), lds_i, s, p->g,
+                                   tc, nm, np, c, p->tile_start, (const T4 *)rec_tn,
+                                   (const T4 *)rec_op, p->dV, g_S, g_T, (const T *)gu0, g_f, GJm,
+                                   rec_Ub, accA, accB);
+            hipLaunchKernelGGL((k_spread<T, W>), dim3(ntiles), dim3(256), lds_s, s, p->g, tc, T(1), 1,
+                               0, 0, p->tile_start, p->halo_start, p->halo_list, (const T4 *)rec_tn,
+                               (const T4 *)rec_Ub, gu0, (T *)nullptr, p->d_count);
+        }
+        if (np > 0)
+            hipLaunchKernelGGL(k_particle_grad, dim3(nblocks(np, 4)), dim3(256), 0, s, np, nm,
+                               p->d_moff, p->body, p->m_inv, (const double4 *)accA,
+                               (const double4 *)accB, gxp, gup, gwp);
+    }
+    return ibmx_launch_check();
+}
+
 template <typename T, int W>
 hipError_t allow_lds_w(int bytes_interp, int bytes_spread)
 {
@@ -963,8 +1345,9 @@ hipError_t allow_lds_w(int bytes_interp, int bytes_spread)
     if ((e = hipFuncSetAttribute((const void *)k_spread<T, W>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes_spread)) != hipSuccess)
         return e;
-    const void *interps[] = {(const void *)k_interp<T, W, 0>, (const void *)k_interp<T, W, 1>,
-                             (const void *)k_interp<T, W, 2>};
+    const void *interps[] = {(const void *)k_interp<T, W, 0>,     (const void *)k_interp<T, W, 1>,
+                             (const void *)k_interp<T, W, 2>,     (const void *)k_interp_jac<T, W>,
+                             (const void *)k_interp_adj<T, W, 0>, (const void *)k_interp_adj<T, W, 1>};
     for (const void *f : interps)
         if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes_interp)) !=
             hipSuccess)
@@ -1024,12 +1407,36 @@ extern "C" ibmx_status ibmx_forcing(ibmx_plan p, void *u, void *f_tot, const dou
                                  T_out, resid_out, (float *)U_debug);
 }
 
-extern "C" ibmx_status ibmx_forcing_backward(ibmx_plan, const void *, const double *,
-                                             const double *, const double *, const uint8_t *,
-                                             const void *, const void *, const double *,
-                                             const double *, void *, double *, double *, double *)
+extern "C" ibmx_status ibmx_forcing_backward(ibmx_plan p, const void *u0, const double *xp,
+                                             const double *up, const double *wp,
+                                             const uint8_t *marker_active, const void *g_f,
+                                             const void *g_u, const double *g_S,
+                                             const double *g_T, void *gu0, double *gxp,
+                                             double *gup, double *gwp)
 {
-    return IBMX_EUNSUPPORTED;
+    if (!p)
+        return IBMX_EINVAL;
+    if (p->nm > 0 && (!p->body || !p->dV))
+        return IBMX_ESTATE;
+    if (!u0 || !gu0 || (p->np > 0 && (!xp || !up || !wp || !gxp || !gup || !gwp)))
+        return IBMX_EINVAL;
+    const int W = p->prm.kernel;
+    if (p->prec == IBMX_F64) {
+        if (W == 3)
+            return run_backward<double, 3>(p, (const double *)u0, xp, up, wp, marker_active,
+                                           (const double *)g_f, (const double *)g_u, g_S, g_T,
+                                           (double *)gu0, gxp, gup, gwp);
+        return run_backward<double, 4>(p, (const double *)u0, xp, up, wp, marker_active,
+                                       (const double *)g_f, (const double *)g_u, g_S, g_T,
+                                       (double *)gu0, gxp, gup, gwp);
+    }
+    if (W == 3)
+        return run_backward<float, 3>(p, (const float *)u0, xp, up, wp, marker_active,
+                                      (const float *)g_f, (const float *)g_u, g_S, g_T,
+                                      (float *)gu0, gxp, gup, gwp);
+    return run_backward<float, 4>(p, (const float *)u0, xp, up, wp, marker_active,
+                                  (const float *)g_f, (const float *)g_u, g_S, g_T, (float *)gu0,
+                                  gxp, gup, gwp);
 }
 
 extern "C" ibmx_status ibmx_tune(ibmx_plan, void *, void *, const double *, const double *,

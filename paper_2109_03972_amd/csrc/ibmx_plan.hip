@@ -205,6 +205,9 @@ ibmx_status ibmx_plan_alloc_tiles(ibmx_plan p, int tx, int ty, int tz)
     int nt[3];
     long long ntiles = 1;
     const int W = 4;   // widest delta support
+    // a staged row of B[0] + W - 1 nodes must fit one wave
+    if (t[0] > 60)
+        return IBMX_EINVAL;
     for (int a = 0; a < 3; ++a) {
         if (t[a] < W || t[a] > 64)
             return IBMX_EINVAL;
@@ -225,6 +228,8 @@ ibmx_status ibmx_plan_alloc_tiles(ibmx_plan p, int tx, int ty, int tz)
     }
     if (ntiles > (1LL << 28))
         return IBMX_EINVAL;
+    if (t[0] > 60)
+        return IBMX_EUNSUPPORTED;
     const size_t Ts = p->prec == IBMX_F64 ? sizeof(double) : sizeof(float);
     if ((size_t)3 * t[0] * t[1] * t[2] * Ts > 160 * 1024)
         return IBMX_EUNSUPPORTED;

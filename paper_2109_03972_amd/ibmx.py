@@ -359,3 +359,48 @@ def trim_pairs(res: Dict) -> Dict:
     return dict(pairs=res["pairs"][:, :k], gap=res["gap"][:k], hist=res["hist"][:, :k],
                 walls=res["walls"][:, :kw], wgap=res["wgap"][:kw], whist=res["whist"][:, :kw],
                 npairs=k, nwall=kw)
+
+
+def _autograd_function():
+    import torch
+
+    class IBMForcing(torch.autograd.Function):
+        """Differentiable forcing loop: (u0, x_p, u_p, omega_p) ->
+        (u^n, f_tot, S, T).  The backward pass is ibmx_forcing_backward,
+        which replays the passes on the device; the mask, body offsets and
+        marker volumes are held fixed."""
+
+        @staticmethod
+        def forward(ctx, plan, u0, xp, up, wp, mask):
+            u = u0.detach().clone()
+            f = torch.zeros_like(u)
+            S, T = plan.forcing(u, f, xp.detach(), up.detach(), wp.detach(), mask=mask)
+            ctx.plan = plan
+            ctx.save_for_backward(u0.detach(), xp.detach(), up.detach(), wp.detach())
+            ctx.mask = mask
+            return u, f, S, T
+
+        @staticmethod
+        def backward(ctx, g_u, g_f, g_S, g_T):
+            u0, xp, up, wp = ctx.saved_tensors
+
+            def cont(t):
+                return None if t is None else t.contiguous()
+
+            gu0, gxp, gup, gwp = ctx.plan.forcing_backward(
+                u0, xp, up, wp, ctx.mask, cont(g_f), cont(g_u), cont(g_S), cont(g_T))
+            return None, gu0, gxp, gup, gwp, None
+
+    return IBMForcing
+
+
+_IBM_FORCING = None
+
+
+def forcing_autograd(plan: "Plan", u0, xp, up, wp, mask=None):
+    """Autograd entry: returns (u, f_tot, S, T) for a forcing call starting
+    from u0 with f_tot = 0; gradients flow to u0, xp, up and wp."""
+    global _IBM_FORCING
+    if _IBM_FORCING is None:
+        _IBM_FORCING = _autograd_function()
+    return _IBM_FORCING.apply(plan, u0, xp, up, wp, mask)

@@ -1,0 +1,221 @@
+"""Reverse-mode derivative of the forcing loop on the GPU
+(ibmx_forcing_backward and the autograd wrapper) against the oracle's
+adjoint, plus central differences of the GPU forward loop on the gradient
+workload (Sec. 2.2 loop; the delta derivative gives the position terms)."""
+import numpy as np
+import pytest
+
+from paper_2109_03972_amd import synth
+from _util import dev_case, rel_err, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+# FP32 grid arithmetic: velocity-like outputs to the forward tolerance,
+# position gradients (sums of delta-derivative terms that cancel over each
+# support) one decade looser.
+TOL32 = dict(gu0=1e-4, gup=1e-4, gwp=1e-4, gxp=1e-3)
+
+
+def _mask_for(case, rng=None, keep=1.0):
+    """The pair-pass mask of the oracle (markers next to walls are off), with
+    a further random fraction switched off when keep < 1."""
+    import oracle
+    m = oracle.marker_mask(case, oracle.pairs(case))
+    if keep < 1.0:
+        m = m & (rng.random(case.nm) < keep).astype(np.uint8)
+    return m
+
+
+def _cotangents(case, rng, which=("g_f", "g_u", "g_S", "g_T")):
+    shape = (3, case.n[2], case.n[1], case.n[0])
+    out = dict(g_f=None, g_u=None, g_S=None, g_T=None)
+    for k in which:
+        out[k] = rng.standard_normal(shape if k in ("g_f", "g_u") else (3, case.np_))
+    return out
+
+
+def _gpu_backward(case, precision, mask, cot, plan=None):
+    import torch
+    from paper_2109_03972_amd import ibmx
+    dev = require_gpu()
+    D = dev_case(case, precision)
+    T = D["u"].dtype
+    if plan is None:
+        plan = ibmx.Plan.from_case(case, precision)
+        plan.set_markers(D["body"], D["dV"])
+
+    def to(a, dt):
+        return None if a is None else torch.as_tensor(a, dtype=torch.float64).to(dev).to(dt).contiguous()
+
+    mk = None if mask is None else torch.as_tensor(np.ascontiguousarray(mask, dtype=np.uint8)).to(dev)
+    gu0, gxp, gup, gwp = plan.forcing_backward(
+        D["u"], D["xp"], D["up"], D["wp"], mk, to(cot["g_f"], T), to(cot["g_u"], T),
+        to(cot["g_S"], torch.float64), to(cot["g_T"], torch.float64))
+    plan.check("forcing_backward")
+    torch.cuda.synchronize()
+    return dict(gu0=gu0.double().cpu().numpy(), gxp=gxp.cpu().numpy(), gup=gup.cpu().numpy(),
+                gwp=gwp.cpu().numpy())
+
+
+def _compare(got, ref, tol, label):
+    for k in ("gu0", "gxp", "gup", "gwp"):
+        t = tol[k] if isinstance(tol, dict) else tol
+        e = rel_err(got[k], ref[k])
+        print(f"{label} {k}: rel err {e:.3e}", flush=True)
+        assert e <= t, f"{label} {k}: {e:.3e} > {t}"
+
+
+SMALL = [
+    # seed, grid, periodic, kernel, passes, masked markers
+    (41, (40, 36, 44), (1, 1, 0), 3, 3, False),
+    (42, (33, 47, 38), (1, 1, 1), 3, 2, True),
+    (43, (45, 39, 50), (1, 0, 0), 4, 2, False),
+    (44, (36, 36, 36), (1, 1, 1), 4, 1, True),
+]
+
+
+@pytest.mark.parametrize("seed,n,per,kernel,n_iter,masked", SMALL)
+def test_backward_small_f64(oracle_lib, seed, n, per, kernel, n_iter, masked):
+    case = synth.small_case(seed, n=n, periodic=per, n_iter=n_iter, touch=0.4)
+    case.params["kernel"] = kernel
+    print(f"case seed={seed} n={n} kernel={kernel} passes={n_iter} nm={case.nm}", flush=True)
+    rng = np.random.default_rng(seed + 100)
+    mask = _mask_for(case, rng, 0.7 if masked else 1.0)
+    cot = _cotangents(case, rng)
+    ref = oracle_lib.forcing_adjoint(case, mask=mask, **cot)
+    got = _gpu_backward(case, "f64", mask, cot)
+    _compare(got, ref, TOL64, f"f64 seed {seed}")
+
+
+@pytest.mark.parametrize("which", [("g_f",), ("g_u",), ("g_S",), ("g_T",), ("g_S", "g_T")])
+def test_backward_cotangent_subsets(oracle_lib, which):
+    case = synth.small_case(51, n=(38, 40, 42), periodic=(1, 1, 0), n_iter=2, touch=0.4)
+    rng = np.random.default_rng(5)
+    cot = _cotangents(case, rng, which)
+    mask = _mask_for(case)
+    ref = oracle_lib.forcing_adjoint(case, mask=mask, **cot)
+    got = _gpu_backward(case, "f64", mask, cot)
+    _compare(got, ref, TOL64, f"f64 {'+'.join(which)}")
+
+
+def test_backward_no_cotangents_gives_zero():
+    case = synth.small_case(52, n=(36, 36, 40), periodic=(1, 1, 0), n_iter=2)
+    got = _gpu_backward(case, "f64", _mask_for(case), _cotangents(case, None, ()))
+    for k, v in got.items():
+        assert not np.any(v), k
+
+
+def test_backward_all_markers_masked(oracle_lib):
+    case = synth.small_case(53, n=(36, 36, 40), periodic=(1, 1, 0), n_iter=2)
+    rng = np.random.default_rng(9)
+    cot = _cotangents(case, rng)
+    mask = np.zeros(case.nm, dtype=np.uint8)
+    ref = oracle_lib.forcing_adjoint(case, mask=mask, **cot)
+    got = _gpu_backward(case, "f64", mask, cot)
+    np.testing.assert_array_equal(got["gu0"], cot["g_u"])
+    for k in ("gxp", "gup", "gwp"):
+        assert not np.any(got[k]) and not np.any(ref[k]), k
+
+
+def test_backward_small_f32(oracle_lib):
+    case = synth.small_case(45, n=(40, 36, 44), periodic=(1, 1, 0), n_iter=3, touch=0.4)
+    rng = np.random.default_rng(145)
+    cot = _cotangents(case, rng)
+    # the oracle sees the FP32-rounded inputs the kernel sees
+    u0 = case.u0.astype(np.float32).astype(np.float64)
+    cot32 = dict(cot)
+    for k in ("g_f", "g_u"):
+        cot32[k] = cot[k].astype(np.float32).astype(np.float64)
+    mask = _mask_for(case)
+    ref = oracle_lib.forcing_adjoint(case, u0=u0, mask=mask, **cot32)
+    got = _gpu_backward(case, "f32", mask, cot)
+    _compare(got, ref, TOL32, "f32 small")
+
+
+def _gradient_case():
+    case = synth.make_case("gradient_suspension_128")
+    assert case.loss_b is not None
+    return case
+
+
+def test_backward_gradient_suspension_128_f64(oracle_lib):
+    case = _gradient_case()
+    print(f"gradient_suspension_128: nm={case.nm} passes={case.params['n_iter']}", flush=True)
+    cot = dict(g_f=None, g_u=None, g_S=case.loss_b, g_T=None)
+    ref = oracle_lib.forcing_adjoint(case, **cot)
+    got = _gpu_backward(case, "f64", None, cot)
+    _compare(got, ref, TOL64, "f64 gradient_suspension_128")
+
+
+def test_backward_gradient_suspension_128_f32(oracle_lib):
+    case = _gradient_case()
+    cot = dict(g_f=None, g_u=None, g_S=case.loss_b, g_T=None)
+    u0 = case.u0.astype(np.float32).astype(np.float64)
+    ref = oracle_lib.forcing_adjoint(case, u0=u0, **cot)
+    got = _gpu_backward(case, "f32", None, cot)
+    _compare(got, ref, TOL32, "f32 gradient_suspension_128")
+
+
+def test_backward_finite_differences_gradient_suspension_128():
+    """Central differences of the GPU FP64 forward loop along 20 seeded
+    directions in (u0, x_p, u_p, omega_p) against the adjoint, for the loss
+    L = sum b . S of the workload's seeded vector b."""
+    import torch
+    from paper_2109_03972_amd import ibmx
+    dev = require_gpu()
+    case = _gradient_case()
+    f64 = torch.float64
+    D = dev_case(case, "f64")
+    plan = ibmx.Plan.from_case(case, "f64")
+    plan.set_markers(D["body"], D["dV"])
+    b = torch.as_tensor(case.loss_b, dtype=f64, device=dev)
+
+    def loss(u0, xp, up, wp):
+        u = u0.clone()
+        f = torch.zeros_like(u)
+        S, _ = plan.forcing(u, f, xp.contiguous(), up.contiguous(), wp.contiguous())
+        plan.check("fd forward")
+        return float((b * S).sum())
+
+    gu0, gxp, gup, gwp = plan.forcing_backward(D["u"], D["xp"], D["up"], D["wp"], None, None,
+                                               None, b.contiguous(), None)
+    plan.check("fd backward")
+    gen = torch.Generator(device="cpu").manual_seed(2024)
+    eps = 1e-6
+    worst = 0.0
+    for trial in range(20):
+        v = [torch.randn(t.shape, generator=gen, dtype=f64).to(dev)
+             for t in (D["u"], D["xp"], D["up"], D["wp"])]
+        plus = loss(*(x + eps * d for x, d in zip((D["u"], D["xp"], D["up"], D["wp"]), v)))
+        minus = loss(*(x - eps * d for x, d in zip((D["u"], D["xp"], D["up"], D["wp"]), v)))
+        fd = (plus - minus) / (2 * eps)
+        an = float(sum((g * d).sum() for g, d in zip((gu0, gxp, gup, gwp), v)))
+        e = abs(fd - an) / max(abs(an), 1e-300)
+        worst = max(worst, e)
+        assert e <= 1e-6, f"direction {trial}: fd {fd:.12e} adjoint {an:.12e} rel {e:.2e}"
+    print(f"finite differences: worst relative deviation {worst:.2e}", flush=True)
+
+
+def test_autograd_function_matches_oracle(oracle_lib):
+    import torch
+    from paper_2109_03972_amd import ibmx
+    dev = require_gpu()
+    case = synth.small_case(61, n=(38, 40, 42), periodic=(1, 1, 0), n_iter=2, touch=0.4)
+    rng = np.random.default_rng(61)
+    cot = _cotangents(case, rng)
+    mask = _mask_for(case)
+    ref = oracle_lib.forcing_adjoint(case, mask=mask, **cot)
+    D = dev_case(case, "f64")
+    plan = ibmx.Plan.from_case(case, "f64")
+    plan.set_markers(D["body"], D["dV"])
+    leaves = [D[k].clone().requires_grad_(True) for k in ("u", "xp", "up", "wp")]
+    mk = torch.as_tensor(mask).to(dev)
+    u, f, S, T = ibmx.forcing_autograd(plan, *leaves, mask=mk)
+    C = {k: torch.as_tensor(v, device=dev) for k, v in cot.items()}
+    L = (u * C["g_u"]).sum() + (f * C["g_f"]).sum() + (S * C["g_S"]).sum() + (T * C["g_T"]).sum()
+    L.backward()
+    plan.check("autograd")
+    got = dict(gu0=leaves[0].grad.cpu().numpy(), gxp=leaves[1].grad.cpu().numpy(),
+               gup=leaves[2].grad.cpu().numpy(), gwp=leaves[3].grad.cpu().numpy())
+    _compare(got, ref, TOL64, "autograd")
