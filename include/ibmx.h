@@ -27,8 +27,11 @@
  *     named *_host.  The caller owns every buffer; the library only reads
  *     or writes it inside the call, asynchronously on the plan's stream, so
  *     buffers must stay valid until the stream reaches the call.
- *   * Compute calls allocate nothing and never synchronise the stream; they
- *     can be captured into a HIP graph.  Errors that only the device can see
+ *   * Compute calls never synchronise the stream and, apart from the first
+ *     ibmx_forcing_backward call on a plan (which sizes its replay
+ *     workspace) and ibmx_tune, allocate nothing; ibmx_forcing and
+ *     ibmx_pairs can be captured into a HIP graph (ibmx_forcing_graph does
+ *     that for the forcing loop).  Errors that only the device can see
  *     (a delta support crossing a wall, a list capacity exceeded) are
  *     recorded in the plan and returned by ibmx_plan_status().
  *   * No exception, abort or exit crosses this interface.
@@ -129,8 +132,10 @@ enum {
     IBMX_K_BACKWARD = 3,      /* adjoint passes                                */
     IBMX_K_PAIRS = 4,         /* pair pass (lists, forces, mask)               */
     IBMX_K_OTHER = 5,         /* fills, residual finish                        */
-    IBMX_K_FTOT = 6           /* spreading of the pass-summed amplitudes into
+    IBMX_K_FTOT = 6,          /* spreading of the pass-summed amplitudes into
                                  f_tot (calls with two or more passes)         */
+    IBMX_K_GRAPH = 7          /* whole forcing call replayed as a HIP graph
+                                 (ibmx_forcing_graph)                          */
 };
 
 /*
@@ -268,10 +273,29 @@ IBMX_API ibmx_status ibmx_pairs(ibmx_plan plan, const double *xp, const double *
                        int32_t *counts_out, double *Fc, double *Tc, uint8_t *marker_active);
 
 /*
- * Autotune the forcing launch (tile edge, threads per workgroup) on the
- * given inputs: times each candidate with the real call and keeps the
- * fastest in the plan.  u and f_tot are used as scratch (their contents are
- * restored); reports the choice through ibmx_plan_stats.
+ * ibmx_forcing through a HIP graph (the batching form of the loop: one graph
+ * launch per call).  The first call, and any call whose pointer arguments
+ * differ from the captured ones or that follows a change of the plan's
+ * parameters, tiles or markers, captures ibmx_forcing's launches
+ * into a graph kept by the plan (on a private capture stream, so the plan's
+ * stream may be the default stream); every call then launches that graph on
+ * the plan's stream.  Same arguments, results and deferred errors as
+ * ibmx_forcing.  With profiling on, the whole call is timed as IBMX_K_GRAPH.
+ */
+IBMX_API ibmx_status ibmx_forcing_graph(ibmx_plan plan, void *u, void *f_tot,
+                               const double *xp, const double *up, const double *wp,
+                               const uint8_t *marker_active,
+                               double *S_out, double *T_out, double *resid_out, void *U_debug);
+
+/*
+ * Autotune the tile shape of the forcing passes on the given inputs: runs
+ * ibmx_forcing with each candidate shape that fits the LDS (edges 4..32,
+ * x-edge <= 32), times it with HIP events on the plan's stream and keeps the
+ * fastest in the plan.  Candidates that raise a deferred error are skipped.
+ * u and f_tot are restored after every trial, so the call leaves them
+ * unchanged.  Allocates and frees its own scratch (copies of u and f_tot)
+ * and synchronises the stream; not capturable.  The choice is reported by
+ * ibmx_plan_stats (tile, block).
  */
 IBMX_API ibmx_status ibmx_tune(ibmx_plan plan, void *u, void *f_tot,
                       const double *xp, const double *up, const double *wp,

@@ -1439,8 +1439,3 @@ extern "C" ibmx_status ibmx_forcing_backward(ibmx_plan p, const void *u0, const 
                                   gxp, gup, gwp);
 }
 
-extern "C" ibmx_status ibmx_tune(ibmx_plan, void *, void *, const double *, const double *,
-                                 const double *, const uint8_t *)
-{
-    return IBMX_EUNSUPPORTED;
-}

@@ -81,12 +81,16 @@ struct ibmx_plan_s {
     long long halo_cap;
     int block;            // threads per workgroup of marker passes
 
-    // backward workspace (allocated on first use)
-    void *bw_u;           // T grid scratch
-    void *bw_F;           // T[n_iter][3][nm]
-    void *bw_J;           // T[n_iter][9][nm]
-    double *bw_part;      // [9][np] per-particle gradient accumulators
+    // backward workspace (allocated by the first backward call): replay
+    // grid T[3][nodes], per-pass amplitude and Jacobian T4[n_iter][3][nm],
+    // per-marker cotangent sums double4[2][nm]
+    void *bw_u;
     size_t bw_bytes;
+
+    // captured forcing call (ibmx_forcing_graph)
+    hipStream_t cap_stream;
+    hipGraphExec_t gexec;
+    const void *gkey[10];
 
     // pair-pass workspace
     int *p_cell_of;       // [np]
@@ -143,6 +147,7 @@ struct ProfScope {
 ibmx_status ibmx_launch_check();
 ibmx_status ibmx_plan_alloc_tiles(ibmx_plan p, int tx, int ty, int tz);
 ibmx_status ibmx_spread_allow_lds(ibmx_plan p);
+void ibmx_plan_drop_graph(ibmx_plan p);
 void ibmx_exclusive_scan(const int *in, int *out, int n, hipStream_t s);
 void ibmx_fill_i32(int *p, int v, long long n, hipStream_t s);
 void ibmx_fill_f64(double *p, double v, long long n, hipStream_t s);

@@ -22,12 +22,14 @@ void free_plan(ibmx_plan p)
     void *ptrs[] = {p->d_moff, p->d_pid, p->d_err, p->d_acc, p->d_count, p->rec_tn,
                     p->rec_op, p->rec_src, p->rec_Gp, p->rec_G, p->m_key, p->m_inv,
                     p->m_rank, p->tile_count, p->tile_start, p->tile_cursor, p->halo_count,
-                    p->halo_start, p->halo_cursor, p->halo_list, p->bw_u, p->bw_F, p->bw_J,
-                    p->bw_part, p->p_cell_of, p->p_cursor, p->p_count, p->p_off, p->p_wcount,
+                    p->halo_start, p->halo_cursor, p->halo_list, p->bw_u, p->p_cell_of, p->p_cursor, p->p_count, p->p_off, p->p_wcount,
                     p->p_woff, p->bin_tab};
     for (void *q : ptrs)
         if (q)
             (void)hipFree(q);
+    ibmx_plan_drop_graph(p);
+    if (p->cap_stream)
+        (void)hipStreamDestroy(p->cap_stream);
     if (p->ev) {
         for (int i = 0; i < 2 * p->ev_cap; ++i)
             (void)hipEventDestroy(p->ev[i]);
@@ -267,6 +269,7 @@ ibmx_status ibmx_plan_alloc_tiles(ibmx_plan p, int tx, int ty, int tz)
     }
     p->tc.ntiles = (int)ntiles;
     p->stats.tiles = ntiles;
+    ibmx_plan_drop_graph(p);
     return ibmx_spread_allow_lds(p);
 }
 
@@ -285,6 +288,7 @@ extern "C" ibmx_status ibmx_plan_set_markers(ibmx_plan p, const double *body, co
         return IBMX_EINVAL;
     p->body = body;
     p->dV = dV;
+    ibmx_plan_drop_graph(p);
     return IBMX_OK;
 }
 
@@ -298,6 +302,7 @@ extern "C" ibmx_status ibmx_plan_set_params(ibmx_plan p, const ibmx_params *prm)
     if (prm->n_iter > p->n_iter_cap)
         return IBMX_EINVAL;
     p->prm = *prm;
+    ibmx_plan_drop_graph(p);
     return IBMX_OK;
 }
 

@@ -23,7 +23,7 @@ F64, F32 = 0, 1
 API = (
     "ibmx_plan_create", "ibmx_plan_destroy", "ibmx_plan_set_markers", "ibmx_plan_set_params",
     "ibmx_plan_set_stream", "ibmx_plan_status", "ibmx_plan_stats", "ibmx_plan_profile",
-    "ibmx_forcing",
+    "ibmx_forcing", "ibmx_forcing_graph",
     "ibmx_forcing_backward", "ibmx_pairs", "ibmx_tune", "ibmx_status_string", "ibmx_version",
 )
 
@@ -57,7 +57,7 @@ class ibmx_stats(ctypes.Structure):
                 ("block", ctypes.c_int32), ("kernel_ms", ctypes.c_double * 8),
                 ("kernel_launches", ctypes.c_int64 * 8)]
 
-KERNEL_CLASSES = ("geometry", "interp", "spread", "backward", "pairs", "other", "ftot")
+KERNEL_CLASSES = ("geometry", "interp", "spread", "backward", "pairs", "other", "ftot", "graph")
 
 
 _lib = None
@@ -90,6 +90,8 @@ def lib():
         L.ibmx_plan_profile.argtypes = [P, i32]
         L.ibmx_forcing.restype = St
         L.ibmx_forcing.argtypes = [P] * 11
+        L.ibmx_forcing_graph.restype = St
+        L.ibmx_forcing_graph.argtypes = [P] * 11
         L.ibmx_forcing_backward.restype = St
         L.ibmx_forcing_backward.argtypes = [P] * 14
         L.ibmx_pairs.restype = St
@@ -245,8 +247,10 @@ class Plan:
         _check(lib().ibmx_plan_profile(self.handle, 1 if enable else 0), "ibmx_plan_profile")
 
     # -- compute calls ---------------------------------------------------------
-    def forcing(self, u, f_tot, xp, up, wp, mask=None, S=None, T=None, resid=None, U_debug=None):
-        """ibmx_forcing: updates u in place, accumulates into f_tot, returns (S, T)."""
+    def forcing(self, u, f_tot, xp, up, wp, mask=None, S=None, T=None, resid=None, U_debug=None,
+                graph=False):
+        """ibmx_forcing (ibmx_forcing_graph with graph=True): updates u in
+        place, accumulates into f_tot, returns (S, T)."""
         import torch
         grid_shape = (3, self.n[2], self.n[1], self.n[0])
         _want(u, self.dtype, grid_shape, "u")
@@ -264,9 +268,10 @@ class Plan:
         _want(resid, torch.float64, (int(self.params["n_iter"]) + 1,), "resid")
         _want(U_debug, self.dtype, (int(self.params["n_iter"]), 3, self.nm), "U_debug")
         self._sync_stream()
-        st = lib().ibmx_forcing(self.handle, _ptr(u), _ptr(f_tot), _ptr(xp), _ptr(up), _ptr(wp),
-                                _ptr(mask), _ptr(S), _ptr(T), _ptr(resid), _ptr(U_debug))
-        _check(st, "ibmx_forcing")
+        fn = lib().ibmx_forcing_graph if graph else lib().ibmx_forcing
+        st = fn(self.handle, _ptr(u), _ptr(f_tot), _ptr(xp), _ptr(up), _ptr(wp), _ptr(mask),
+                _ptr(S), _ptr(T), _ptr(resid), _ptr(U_debug))
+        _check(st, "ibmx_forcing_graph" if graph else "ibmx_forcing")
         return S, T
 
     def forcing_backward(self, u0, xp, up, wp, mask, g_f, g_u, g_S, g_T, gu0=None):

@@ -1,0 +1,132 @@
+"""Batching form of the forcing loop: graph capture and replay
+(ibmx_forcing_graph) and the tile-shape autotuner (ibmx_tune), checked
+against eager calls and the oracle."""
+import numpy as np
+import pytest
+
+from paper_2109_03972_amd import synth
+from _util import dev_case, rel_err, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(case, precision):
+    from paper_2109_03972_amd import ibmx
+    D = dev_case(case, precision)
+    plan = ibmx.Plan.from_case(case, precision)
+    plan.set_markers(D["body"], D["dV"])
+    return plan, D
+
+
+def _mask(case, dev):
+    import oracle
+    import torch
+    m = oracle.marker_mask(case, oracle.pairs(case))
+    return m, torch.as_tensor(m).to(dev)
+
+
+def _run(plan, D, u0, mk, graph, resid=None):
+    import torch
+    D["u"].copy_(u0)
+    D["f"].zero_()
+    S, T = plan.forcing(D["u"], D["f"], D["xp"], D["up"], D["wp"], mask=mk, resid=resid,
+                        graph=graph)
+    plan.check("graph" if graph else "eager")
+    torch.cuda.synchronize()
+    return dict(u=D["u"].double().cpu().numpy(), f_tot=D["f"].double().cpu().numpy(),
+                S=S.cpu().numpy(), T=T.cpu().numpy())
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_graph_replays_match_eager_and_oracle(oracle_lib, precision):
+    import torch
+    dev = require_gpu()
+    case = synth.small_case(71, n=(40, 36, 44), periodic=(1, 1, 0), n_iter=3, touch=0.4)
+    m_np, mk = _mask(case, dev)
+    plan, D = _setup(case, precision)
+    u0 = D["u"].clone()
+    resid = torch.zeros(int(case.params["n_iter"]) + 1, dtype=torch.float64, device=dev)
+    eager = _run(plan, D, u0, mk, False, resid)
+    ref = oracle_lib.forcing(case, mask=m_np)
+    tol = 1e-12 if precision == "f64" else 1e-4
+    for rep in range(4):
+        got = _run(plan, D, u0, mk, True, resid)
+        # eager torch work between replays
+        _ = (D["u"] * 2.0).sum().item()
+        for k in ("u", "f_tot", "S", "T"):
+            e = rel_err(got[k], ref[k])
+            assert e <= tol, f"replay {rep} {k}: {e:.3e}"
+            if precision == "f32":
+                # integer fixed-point spreading and ordered sums: replays are
+                # bit-identical to the eager call
+                np.testing.assert_array_equal(got[k], eager[k], err_msg=f"replay {rep} {k}")
+
+
+def test_graph_recaptures_on_new_pointers_and_params(oracle_lib):
+    import torch
+    dev = require_gpu()
+    case = synth.small_case(72, n=(38, 40, 42), periodic=(1, 1, 0), n_iter=2, touch=0.4)
+    m_np, mk = _mask(case, dev)
+    plan, D = _setup(case, "f64")
+    u0 = D["u"].clone()
+    got = _run(plan, D, u0, mk, True)
+    ref = oracle_lib.forcing(case, mask=m_np)
+    assert rel_err(got["u"], ref["u"]) <= 1e-12
+    # other output buffers: a new capture
+    D2 = dict(D)
+    D2["u"] = torch.empty_like(D["u"])
+    D2["f"] = torch.empty_like(D["f"])
+    got2 = _run(plan, D2, u0, mk, True)
+    for k in ("u", "f_tot", "S", "T"):
+        assert rel_err(got2[k], ref[k]) <= 1e-12, k
+    # fewer passes: the captured graph is dropped with the old parameters
+    prm = dict(case.params)
+    prm["n_iter"] = 1
+    plan.set_params(prm)
+    got3 = _run(plan, D2, u0, mk, True)
+    ref3 = oracle_lib.forcing(case, mask=m_np, n_iter=1)
+    for k in ("u", "f_tot", "S", "T"):
+        assert rel_err(got3[k], ref3[k]) <= 1e-12, k
+
+
+def test_graph_profiled_as_one_class():
+    dev = require_gpu()
+    case = synth.small_case(73, n=(36, 36, 40), periodic=(1, 1, 0), n_iter=2)
+    _, mk = _mask(case, dev)
+    plan, D = _setup(case, "f32")
+    u0 = D["u"].clone()
+    _run(plan, D, u0, mk, True)
+    plan.profile(True)
+    for _ in range(3):
+        _run(plan, D, u0, mk, True)
+    st = plan.stats()
+    plan.profile(False)
+    assert st["kernel_launches"]["graph"] == 3
+    assert st["kernel_ms"]["graph"] > 0.0
+    assert st["kernel_launches"]["interp"] == 0
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_tune_keeps_inputs_and_results(oracle_lib, precision):
+    import torch
+    dev = require_gpu()
+    case = synth.make_case("suspension_128")
+    m_np, mk = _mask(case, dev)
+    plan, D = _setup(case, precision)
+    u_before = D["u"].clone()
+    D["f"].fill_(0.25)
+    f_before = D["f"].clone()
+    st = plan.tune(D["u"], D["f"], D["xp"], D["up"], D["wp"], mask=mk)
+    plan.check("tune")
+    print(f"{precision}: tuned tile {st['tile']} block {st['block']}", flush=True)
+    assert torch.equal(D["u"], u_before) and torch.equal(D["f"], f_before)
+    assert all(4 <= t <= 32 for t in st["tile"])
+    got = _run(plan, D, u_before, mk, False)
+    got_g = _run(plan, D, u_before, mk, True)
+    ref = oracle_lib.forcing(case, mask=m_np)
+    tol = dict(f64=dict(u=1e-12, f_tot=1e-12, S=1e-12, T=1e-12),
+               f32=dict(u=1e-4, f_tot=1e-4, S=1e-4, T=1e-4))[precision]
+    for res in (got, got_g):
+        for k in ("u", "f_tot", "S", "T"):
+            e = rel_err(res[k], ref[k])
+            assert e <= tol[k], f"{k}: {e:.3e}"
