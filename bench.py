@@ -3,6 +3,9 @@
 One step = the pair pass (cell/pair/wall lists, collision forces, marker
 mask) + one ibmx_forcing call (marker geometry, then n_iter passes of
 interpolate -> force -> spread -> update) on the resident synthetic workload.
+The tile shape is autotuned first (ibmx_tune, untimed).  The steps are timed
+twice: as eager calls with per-kernel HIP events (the headline value and the
+roofline), then with the forcing call replayed as one HIP graph.
 The reported value is whole-step throughput in marker-updates/s
 (active markers x passes / step time).  Also reported: the FP64 instance of
 the same kernels, per-kernel durations from HIP events recorded by the
@@ -55,7 +58,7 @@ def algorithmic_bytes(kind: str, s: int, n_act: int, shell: int, n_iter: int = 2
     raise KeyError(kind)
 
 
-def run_gpu(case, precision, steps, warmup, profile=True):
+def run_gpu(case, precision, steps, warmup, profile=True, tune=True, tile=None):
     import torch
     from paper_2109_03972_amd import ibmx
 
@@ -77,36 +80,52 @@ def run_gpu(case, precision, steps, warmup, profile=True):
     prev = dict(pairs=t["pairs"].contiguous(), hist=t["hist"].contiguous(),
                 walls=t["walls"].contiguous(), whist=t["whist"].contiguous())
     caps = dict(pair_cap=res["pair_cap"], wall_cap=res["wall_cap"])
+    tuned = None
+    if tile is not None:
+        plan.set_tiles(*tile)
+    elif tune:
+        tuned = plan.tune(u, f, D["xp"], D["up"], D["wp"], mask=mask)["tile"]
+        plan.check("tune")
+        log(f"bench: {precision} tuned tile {tuned}")
 
-    def step():
+    def step(graph):
         r = plan.pairs(D["xp"], D["radius"], D["mass"], D["up"], D["wp"], prev=prev, mask=mask,
                        **caps)
-        plan.forcing(u, f, D["xp"], D["up"], D["wp"], mask=mask, resid=resid)
+        plan.forcing(u, f, D["xp"], D["up"], D["wp"], mask=mask, resid=resid, graph=graph)
         return r
 
-    for _ in range(warmup):
-        step()
-    torch.cuda.synchronize()
-    plan.check("warmup")
-    if profile:
-        plan.profile(True)
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    start.record()
-    for _ in range(steps):
-        step()
-    stop.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    plan.check("timed steps")
-    ms = start.elapsed_time(stop) / steps
-    st = plan.stats()
-    if profile:
-        plan.profile(False)
-    out = dict(ms_per_step=ms, wall_s=wall, stats=st, n_iter=n_iter,
-               resid=resid.cpu().numpy().tolist())
+    def timed(graph, prof):
+        # a graph call captures on its first use: keep that out of the timing
+        for _ in range(max(warmup, 1) if graph else warmup):
+            step(graph)
+        torch.cuda.synchronize()
+        plan.check("warmup")
+        if prof:
+            plan.profile(True)
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        start.record()
+        for _ in range(steps):
+            step(graph)
+        stop.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        plan.check("timed steps")
+        st = plan.stats() if prof else None
+        if prof:
+            plan.profile(False)
+        return start.elapsed_time(stop) / steps, wall, st
+
+    # eager calls with per-kernel events (roofline), then the same steps
+    # with the forcing call replayed as one HIP graph
+    ms, wall, st = timed(False, profile)
+    ms_graph, _, _ = timed(True, False)
+    if not profile:
+        st = plan.stats()
+    out = dict(ms_per_step=ms, ms_per_step_graph=ms_graph, wall_s=wall, stats=st, n_iter=n_iter,
+               resid=resid.cpu().numpy().tolist(), tile=tuned or list(plan.stats()["tile"]))
     del u, f, D
     plan.close()
     torch.cuda.empty_cache()
@@ -139,6 +158,9 @@ def main():
     ap.add_argument("--workload", default="polydisperse_bed_512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default tile shape")
+    ap.add_argument("--tile", default=None,
+                    help="FP32 tile shape tx,ty,tz instead of tuning (for counter runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 1 GiB device-to-device copy (reference kernel for "
                          "hardware byte counters)")
@@ -166,14 +188,16 @@ def main():
     log(f"bench: {case.np_} particles, {case.nm} markers, grid {case.n}")
 
     log("bench: FP32 run")
-    r32 = run_gpu(case, "f32", args.steps, args.warmup)
+    tile = None if args.tile is None else [int(v) for v in args.tile.split(",")]
+    r32 = run_gpu(case, "f32", args.steps, args.warmup, tune=not args.no_tune, tile=tile)
     st = r32["stats"]
     n_act, shell, n_iter = int(st["n_active"]), int(st["shell_nodes"]), r32["n_iter"]
     value = n_act * n_iter / (r32["ms_per_step"] * 1e-3)
+    value_graph = n_act * n_iter / (r32["ms_per_step_graph"] * 1e-3)
     km, kn = st["kernel_ms"], st["kernel_launches"]
     steps_done = args.steps
     per_launch = {k: (km[k] / kn[k] if kn[k] else None) for k in km}
-    dom = max(("interp", "spread"), key=lambda k: km[k])
+    dom = max(("interp", "spread", "ftot"), key=lambda k: km[k] / max(kn[k], 1))
     bytes_launch = algorithmic_bytes(dom, 4, n_act, shell, n_iter)
     achieved = bytes_launch / (per_launch[dom] * 1e-3) / 1e9
     roof = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
@@ -184,9 +208,10 @@ def main():
     fp64 = None
     if not args.no_fp64:
         log("bench: FP64 run")
-        r64 = run_gpu(case, "f64", args.steps, args.warmup)
+        r64 = run_gpu(case, "f64", args.steps, args.warmup, tune=not args.no_tune)
         v64 = n_act * n_iter / (r64["ms_per_step"] * 1e-3)
         fp64 = dict(value=v64, ms_per_step=r64["ms_per_step"], speedup_f32_over_f64=value / v64,
+                    ms_per_step_graph=r64["ms_per_step_graph"], tile=r64["tile"],
                     kernel_ms_per_launch={k: (r64["stats"]["kernel_ms"][k] / n if n else None)
                                           for k, n in r64["stats"]["kernel_launches"].items()})
 
@@ -206,9 +231,11 @@ def main():
         config=dict(workload=args.workload, grid=list(case.n), particles=case.np_,
                     markers=case.nm, active_markers=n_act, shell_nodes=shell, n_iter=n_iter,
                     precision="FP32 grid/delta, FP64 geometry, particle sums and pair pass",
-                    step="pair pass + marker geometry + n_iter forcing passes"),
+                    step="pair pass + marker geometry + n_iter forcing passes",
+                    tile=r32["tile"]),
         roofline=roof, cpu_baseline=cpu, fp64=fp64,
         kernel_ms_per_launch=per_launch,
+        graph=dict(ms_per_step=r32["ms_per_step_graph"], value=value_graph),
         pass_rate=n_act * n_iter / (sum(km[k] for k in ("interp", "spread")) / steps_done
                                     * 1e-3),
     )

@@ -170,6 +170,15 @@ IBMX_API ibmx_status ibmx_plan_set_params(ibmx_plan plan, const ibmx_params *par
 /* Change the stream used by later calls. */
 IBMX_API ibmx_status ibmx_plan_set_stream(ibmx_plan plan, void *hip_stream);
 
+/* Set the tile shape (nodes per tile along x, y, z) of the forcing passes,
+ * as ibmx_tune does for its choice.  Edges are 4..64 with x <= 60 (EINVAL
+ * otherwise).  An edge whose last tile would be shorter than 4 nodes is
+ * replaced by the nearest edge (smaller first) that divides the axis or
+ * leaves at least 4; an edge of at least the axis length becomes the axis
+ * length.  EUNSUPPORTED if the tile's LDS footprint is too large for the
+ * precision.  Synchronises the stream; reallocates tile workspace. */
+IBMX_API ibmx_status ibmx_plan_set_tiles(ibmx_plan plan, int32_t tx, int32_t ty, int32_t tz);
+
 /* Synchronise the plan's stream and return (and clear) the first deferred
  * device error of the calls since the last ibmx_plan_status: EDOMAIN,
  * ECAPACITY, or EDEVICE. */

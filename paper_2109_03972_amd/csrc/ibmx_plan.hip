@@ -213,17 +213,26 @@ ibmx_status ibmx_plan_alloc_tiles(ibmx_plan p, int tx, int ty, int tz)
     for (int a = 0; a < 3; ++a) {
         if (t[a] < W || t[a] > 64)
             return IBMX_EINVAL;
-        if (t[a] >= p->g.n[a]) {
-            t[a] = p->g.n[a];
-        } else {
-            // a short last tile must still hold a whole support
-            while (t[a] > W && p->g.n[a] % t[a] != 0 && p->g.n[a] % t[a] < W)
-                --t[a];
-            if (p->g.n[a] % t[a] != 0 && p->g.n[a] % t[a] < W) {
-                if (p->g.n[a] > 64)
-                    return IBMX_EUNSUPPORTED;
-                t[a] = p->g.n[a];
+        const int n = p->g.n[a];
+        // a short last tile must still hold a whole support: take the
+        // nearest edge (smaller first) that leaves no remainder or one >= W
+        auto fits = [&](int e) { return n % e == 0 || n % e >= W; };
+        if (t[a] >= n) {
+            t[a] = n;
+        } else if (!fits(t[a])) {
+            int e = -1;
+            for (int d = 1; d < 64 && e < 0; ++d) {
+                if (t[a] - d >= W && fits(t[a] - d))
+                    e = t[a] - d;
+                else if (t[a] + d <= 64 && t[a] + d < n && fits(t[a] + d))
+                    e = t[a] + d;
             }
+            if (e < 0) {
+                if (n > 64)
+                    return IBMX_EUNSUPPORTED;
+                e = n;
+            }
+            t[a] = e;
         }
         nt[a] = (p->g.n[a] + t[a] - 1) / t[a];
         ntiles *= nt[a];
@@ -304,6 +313,19 @@ extern "C" ibmx_status ibmx_plan_set_params(ibmx_plan p, const ibmx_params *prm)
     p->prm = *prm;
     ibmx_plan_drop_graph(p);
     return IBMX_OK;
+}
+
+extern "C" ibmx_status ibmx_plan_set_tiles(ibmx_plan p, int32_t tx, int32_t ty, int32_t tz)
+{
+    if (!p)
+        return IBMX_EINVAL;
+    if (hipStreamSynchronize(p->stream) != hipSuccess)
+        return IBMX_EDEVICE;
+    const int old[3] = {p->tc.B[0], p->tc.B[1], p->tc.B[2]};
+    const ibmx_status st = ibmx_plan_alloc_tiles(p, tx, ty, tz);
+    if (st != IBMX_OK)
+        (void)ibmx_plan_alloc_tiles(p, old[0], old[1], old[2]);
+    return st;
 }
 
 extern "C" ibmx_status ibmx_plan_set_stream(ibmx_plan p, void *stream)

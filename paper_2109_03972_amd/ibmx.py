@@ -22,7 +22,8 @@ F64, F32 = 0, 1
 # every entry point declared in include/ibmx.h
 API = (
     "ibmx_plan_create", "ibmx_plan_destroy", "ibmx_plan_set_markers", "ibmx_plan_set_params",
-    "ibmx_plan_set_stream", "ibmx_plan_status", "ibmx_plan_stats", "ibmx_plan_profile",
+    "ibmx_plan_set_stream", "ibmx_plan_set_tiles", "ibmx_plan_status", "ibmx_plan_stats",
+    "ibmx_plan_profile",
     "ibmx_forcing", "ibmx_forcing_graph",
     "ibmx_forcing_backward", "ibmx_pairs", "ibmx_tune", "ibmx_status_string", "ibmx_version",
 )
@@ -82,6 +83,8 @@ def lib():
         L.ibmx_plan_set_params.argtypes = [P, ctypes.POINTER(ibmx_params)]
         L.ibmx_plan_set_stream.restype = St
         L.ibmx_plan_set_stream.argtypes = [P, P]
+        L.ibmx_plan_set_tiles.restype = St
+        L.ibmx_plan_set_tiles.argtypes = [P, i32, i32, i32]
         L.ibmx_plan_status.restype = St
         L.ibmx_plan_status.argtypes = [P]
         L.ibmx_plan_stats.restype = St
@@ -228,6 +231,10 @@ class Plan:
         self.params = dict(params)
         self._prm = make_params(self.params)
         _check(lib().ibmx_plan_set_params(self.handle, ctypes.byref(self._prm)), "ibmx_plan_set_params")
+
+    def set_tiles(self, tx: int, ty: int, tz: int):
+        _check(lib().ibmx_plan_set_tiles(self.handle, int(tx), int(ty), int(tz)),
+               "ibmx_plan_set_tiles")
 
     def status(self) -> int:
         return int(lib().ibmx_plan_status(self.handle))

@@ -130,3 +130,31 @@ def test_tune_keeps_inputs_and_results(oracle_lib, precision):
         for k in ("u", "f_tot", "S", "T"):
             e = rel_err(res[k], ref[k])
             assert e <= tol[k], f"{k}: {e:.3e}"
+
+
+@pytest.mark.parametrize("tile", [(8, 8, 8), (32, 16, 4), (16, 8, 16), (4, 4, 4)])
+def test_tile_shapes_parity(oracle_lib, tile):
+    dev = require_gpu()
+    case = synth.small_case(74, n=(41, 37, 45), periodic=(1, 1, 0), n_iter=2, touch=0.4)
+    m_np, mk = _mask(case, dev)
+    ref = oracle_lib.forcing(case, mask=m_np)
+    for precision, tol in (("f64", 1e-12), ("f32", 1e-4)):
+        plan, D = _setup(case, precision)
+        plan.set_tiles(*tile)
+        got = _run(plan, D, D["u"].clone(), mk, False)
+        print(precision, tile, plan.stats()["tile"], flush=True)
+        for k in ("u", "f_tot", "S", "T"):
+            e = rel_err(got[k], ref[k])
+            assert e <= tol, f"{precision} tile {tile} {k}: {e:.3e}"
+
+
+def test_set_tiles_rejects_bad_shapes():
+    from paper_2109_03972_amd import ibmx
+    require_gpu()
+    case = synth.small_case(75, n=(36, 36, 40), periodic=(1, 1, 0), n_iter=1)
+    plan, _ = _setup(case, "f64")
+    before = plan.stats()["tile"]
+    for bad in ((3, 16, 16), (16, 16, 65), (61, 8, 8)):
+        with pytest.raises(ibmx.IbmxError):
+            plan.set_tiles(*bad)
+        assert plan.stats()["tile"] == before
