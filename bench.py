@@ -58,6 +58,45 @@ def algorithmic_bytes(kind: str, s: int, n_act: int, shell: int, n_iter: int = 2
     raise KeyError(kind)
 
 
+COUNTER_FILES = {
+    "polydisperse_bed_512": "profiles/k_interp_k_spread_polydisperse_bed_512_f32_hbm_counters.md",
+}
+KERNEL_SOURCES = ("paper_2109_03972_amd/csrc/ibmx_forcing.hip",
+                  "paper_2109_03972_amd/csrc/ibmx_internal.hpp",
+                  "paper_2109_03972_amd/csrc/ibmx_delta.hpp", "paper_2109_03972_amd/build_lib.py")
+
+
+def measured_traffic(workload: str, kind: str, tile) -> "float | None":
+    """HBM bytes per launch of a kernel class from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE passes, copy-calibrated), or None when
+    there is none for this workload and tile, or the kernel sources changed
+    since the counters were taken."""
+    import hashlib
+    rel = COUNTER_FILES.get(workload)
+    if rel is None or not os.path.exists(os.path.join(ROOT, rel)):
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    fields = {}
+    with open(os.path.join(ROOT, rel)) as fh:
+        for line in fh:
+            if ":" in line and line.split(":", 1)[0] in (
+                    "traffic_per_launch_bytes", "tile", "kernel_sources_sha256"):
+                k, v = line.split(":", 1)
+                fields[k] = v.strip()
+    if fields.get("kernel_sources_sha256") != h.hexdigest():
+        return None
+    if fields.get("tile") != ",".join(str(int(t)) for t in tile):
+        return None
+    for item in fields.get("traffic_per_launch_bytes", "").split():
+        k, _, v = item.partition("=")
+        if k == kind:
+            return float(v)
+    return None
+
+
 def run_gpu(case, precision, steps, warmup, profile=True, tune=True, tile=None):
     import torch
     from paper_2109_03972_amd import ibmx
@@ -200,9 +239,12 @@ def main():
     dom = max(("interp", "spread", "ftot"), key=lambda k: km[k] / max(kn[k], 1))
     bytes_launch = algorithmic_bytes(dom, 4, n_act, shell, n_iter)
     achieved = bytes_launch / (per_launch[dom] * 1e-3) / 1e9
+    traffic = measured_traffic(args.workload, dom, r32["tile"])
     roof = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
-                unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                 bytes_per_launch=bytes_launch, ms_per_launch=per_launch[dom])
+    if traffic is not None:
+        roof["traffic_GBs"] = round(traffic / (per_launch[dom] * 1e-3) / 1e9, 1)
     log(f"bench: FP32 {r32['ms_per_step']:.3f} ms/step, {value:.3e} marker-updates/s")
 
     fp64 = None
