@@ -157,10 +157,18 @@ def test_backward_gradient_suspension_128_f32(oracle_lib):
     _compare(got, ref, TOL32, "f32 gradient_suspension_128")
 
 
+def _paper_loss_cotangents(case, f_tot):
+    """Cotangents of the differentiation workload's loss
+    L = 1/2 sum_x |f_tot(x)|^2 + sum_p b_p . F_p, with the hydrodynamic force
+    F_p = -rho_f S_p."""
+    rho = float(case.params["rho_f"])
+    return dict(g_f=f_tot, g_u=None, g_S=-rho * case.loss_b, g_T=None)
+
+
 def test_backward_finite_differences_gradient_suspension_128():
     """Central differences of the GPU FP64 forward loop along 20 seeded
-    directions in (u0, x_p, u_p, omega_p) against the adjoint, for the loss
-    L = sum b . S of the workload's seeded vector b."""
+    directions in (u0, x_p, u_p, omega_p) against the adjoint, for the
+    workload's loss 1/2 |f_tot|^2 + b . F_p."""
     import torch
     from paper_2109_03972_amd import ibmx
     dev = require_gpu()
@@ -170,31 +178,64 @@ def test_backward_finite_differences_gradient_suspension_128():
     plan = ibmx.Plan.from_case(case, "f64")
     plan.set_markers(D["body"], D["dV"])
     b = torch.as_tensor(case.loss_b, dtype=f64, device=dev)
+    rho = float(case.params["rho_f"])
 
-    def loss(u0, xp, up, wp):
+    def forward(u0, xp, up, wp):
         u = u0.clone()
         f = torch.zeros_like(u)
         S, _ = plan.forcing(u, f, xp.contiguous(), up.contiguous(), wp.contiguous())
         plan.check("fd forward")
-        return float((b * S).sum())
+        return f, S
 
-    gu0, gxp, gup, gwp = plan.forcing_backward(D["u"], D["xp"], D["up"], D["wp"], None, None,
-                                               None, b.contiguous(), None)
+    def loss(*args):
+        f, S = forward(*args)
+        return float(0.5 * (f * f).sum() - rho * (b * S).sum())
+
+    base = (D["u"], D["xp"], D["up"], D["wp"])
+    f0, _ = forward(*base)
+    gu0, gxp, gup, gwp = plan.forcing_backward(D["u"], D["xp"], D["up"], D["wp"], None,
+                                               f0.contiguous(), None, (-rho * b).contiguous(),
+                                               None)
     plan.check("fd backward")
     gen = torch.Generator(device="cpu").manual_seed(2024)
     eps = 1e-6
     worst = 0.0
     for trial in range(20):
-        v = [torch.randn(t.shape, generator=gen, dtype=f64).to(dev)
-             for t in (D["u"], D["xp"], D["up"], D["wp"])]
-        plus = loss(*(x + eps * d for x, d in zip((D["u"], D["xp"], D["up"], D["wp"]), v)))
-        minus = loss(*(x - eps * d for x, d in zip((D["u"], D["xp"], D["up"], D["wp"]), v)))
+        v = [torch.randn(t.shape, generator=gen, dtype=f64).to(dev) for t in base]
+        plus = loss(*(x + eps * d for x, d in zip(base, v)))
+        minus = loss(*(x - eps * d for x, d in zip(base, v)))
         fd = (plus - minus) / (2 * eps)
         an = float(sum((g * d).sum() for g, d in zip((gu0, gxp, gup, gwp), v)))
         e = abs(fd - an) / max(abs(an), 1e-300)
         worst = max(worst, e)
         assert e <= 1e-6, f"direction {trial}: fd {fd:.12e} adjoint {an:.12e} rel {e:.2e}"
     print(f"finite differences: worst relative deviation {worst:.2e}", flush=True)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_autograd_paper_loss_gradient_suspension_128(oracle_lib, precision):
+    """The workload's loss through the autograd wrapper, FP64 against the
+    oracle's adjoint to 1e-10 and the FP32 production run against the same
+    FP64 gradients (end to end, FP64 inputs) to the FP32 field bound."""
+    import torch
+    from paper_2109_03972_amd import ibmx
+    dev = require_gpu()
+    case = _gradient_case()
+    fwd = oracle_lib.forcing(case, final_resid=False)
+    ref = oracle_lib.forcing_adjoint(case, **_paper_loss_cotangents(case, fwd["f_tot"]))
+    D = dev_case(case, precision)
+    plan = ibmx.Plan.from_case(case, precision)
+    plan.set_markers(D["body"], D["dV"])
+    leaves = [D[k].clone().requires_grad_(True) for k in ("u", "xp", "up", "wp")]
+    u, f, S, T = ibmx.forcing_autograd(plan, *leaves)
+    b = torch.as_tensor(case.loss_b, dtype=torch.float64, device=dev)
+    L = 0.5 * (f.double() * f.double()).sum() - float(case.params["rho_f"]) * (b * S).sum()
+    L.backward()
+    plan.check("autograd paper loss")
+    got = dict(gu0=leaves[0].grad.double().cpu().numpy(), gxp=leaves[1].grad.cpu().numpy(),
+               gup=leaves[2].grad.cpu().numpy(), gwp=leaves[3].grad.cpu().numpy())
+    tol = TOL64 if precision == "f64" else 1e-4
+    _compare(got, ref, tol, f"{precision} paper loss")
 
 
 def test_autograd_function_matches_oracle(oracle_lib):

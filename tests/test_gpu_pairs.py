@@ -56,7 +56,8 @@ def _check(case, got, prev_host=None):
     return ref_l, ref_f
 
 
-@pytest.mark.parametrize("name", ["suspension_128", "bidisperse_bed_256x256x512"])
+@pytest.mark.parametrize("name", ["suspension_128", "bidisperse_bed_256x256x512",
+                                  "polydisperse_bed_512"])
 def test_workload_pairs(name):
     c = synth.make_case(name, lazy_field=True)
     got = _gpu_pairs(c)
