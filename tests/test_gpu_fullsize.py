@@ -38,7 +38,7 @@ def _gpu_run(case, precision, u0_dev64, mask_dev, want_U):
     plan.set_markers(D["body"], D["dV"])
     plan.set_tiles(*BENCH_TILE[precision])
     n_iter = int(case.params["n_iter"])
-    u = u0_dev64.to(T).contiguous()
+    u = u0_dev64.to(T).clone()   # the call updates u in place; keep u0
     f = torch.zeros_like(u)
     resid = torch.zeros(n_iter + 1, dtype=f64, device=dev)
     U = torch.zeros((n_iter, 3, case.nm), dtype=T, device=dev) if want_U else None
