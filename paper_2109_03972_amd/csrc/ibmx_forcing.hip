@@ -177,29 +177,22 @@ __device__ __forceinline__ void gather(const GridC &g, const int ix[3][W], const
         }
 }
 
-// Marker force from the interpolated velocity (FP64): F = (U^d - U)/c with
-// U^d = u_p + omega_p x o; red[6] receives dV |U^d - U|^2 and G = F dV / h^3
-// is returned.
+// Marker force from the interpolated velocity: F = (U^d - U)/c in FP64 with
+// U^d = u_p + omega_p x o and dV taken from the marker's record; rsq
+// receives dV |U^d - U|^2 and G = F dV / h^3 is returned.
 template <typename T>
-__device__ __forceinline__ void marker_force(const GridC &g, int np, double c, int pid,
-                                             const double *o, const T *U,
-                                             const double *__restrict__ dV,
-                                             const double *__restrict__ up,
-                                             const double *__restrict__ wp, double *red, T *G)
+__device__ __forceinline__ void marker_force(const GridC &g, double c,
+                                             const typename V4<T>::type &ud, const T *U,
+                                             double &rsq, T *G)
 {
-    const double upp[3] = {up[pid], up[np + pid], up[2 * np + pid]};
-    const double wpp[3] = {wp[pid], wp[np + pid], wp[2 * np + pid]};
-    const double dVp = dV[pid];
-    const double Ud[3] = {upp[0] + (wpp[1] * o[2] - wpp[2] * o[1]),
-                          upp[1] + (wpp[2] * o[0] - wpp[0] * o[2]),
-                          upp[2] + (wpp[0] * o[1] - wpp[1] * o[0])};
-    double rsq = 0.0;
+    const double dVp = (double)ud.w;
+    const double Ud[3] = {(double)ud.x, (double)ud.y, (double)ud.z};
+    rsq = 0.0;
     for (int a = 0; a < 3; ++a) {
         const double r = Ud[a] - (double)U[a];
         rsq += dVp * r * r;
         G[a] = (T)(r / c * dVp * g.inv_h3);
     }
-    red[6] = rsq;
 }
 
 // Row walk over a tile's nodes for the write-out: each wave takes whole rows
@@ -229,7 +222,7 @@ struct TileWalk {
 };
 
 constexpr int UNR = 4;    // row groups per write-out step
-constexpr int SUNR = 8;   // row groups per staging step
+constexpr int SUNR = 16;  // row groups per staging step
 
 // ---------------------------------------------------------------------------
 // binning step A: one wave per particle.  Tile key and rank of every active
@@ -318,9 +311,10 @@ __global__ __launch_bounds__(256) void k_bin_count(
 template <typename T, int W>
 __global__ __launch_bounds__(256) void k_bin_scatter(
     GridC g, int np, int nm, const int *__restrict__ moff, const double *__restrict__ body,
-    const double *__restrict__ xp, const int *__restrict__ m_key, const int *__restrict__ m_rank,
+    const double *__restrict__ xp, const double *__restrict__ up, const double *__restrict__ wp,
+    const double *__restrict__ dV, const int *__restrict__ m_key, const int *__restrict__ m_rank,
     const int *__restrict__ tab, const int *__restrict__ tile_start, int *__restrict__ tile_cursor,
-    typename V4<T>::type *__restrict__ rec_tn, typename V4<T>::type *__restrict__ rec_op,
+    typename V4<T>::type *__restrict__ rec_tn, typename V4<T>::type *__restrict__ rec_ud,
     int *__restrict__ rec_src, int *__restrict__ m_inv)
 {
     __shared__ int s_base[4][TS];
@@ -335,6 +329,9 @@ __global__ __launch_bounds__(256) void k_bin_scatter(
         base_of[s] = k >= 0 ? tile_start[k] + atomicAdd(&tile_cursor[k], mytab[TS + s]) : 0;
     }
     const double xc[3] = {xp[p], xp[np + p], xp[2 * np + p]};
+    const double upp[3] = {up[p], up[np + p], up[2 * np + p]};
+    const double wpp[3] = {wp[p], wp[np + p], wp[2 * np + p]};
+    const double dVp = dV[p];
     const int l0 = moff[p], l1 = moff[p + 1];
     for (int l = l0 + lane; l < l1; l += IBMX_WAVE) {
         const int slot = m_key[l];
@@ -351,17 +348,18 @@ __global__ __launch_bounds__(256) void k_bin_scatter(
             X[a] = xc[a] + o[a];
         }
         marker_geometry<W>(g, X, b, t);
-        typename V4<T>::type tn, op;
+        typename V4<T>::type tn, ud;
         tn.x = (T)t[0];
         tn.y = (T)t[1];
         tn.z = (T)t[2];
         tn.w = V4<T>::from_bits(pack_node(g, b[0], b[1], b[2]));
-        op.x = (T)o[0];
-        op.y = (T)o[1];
-        op.z = (T)o[2];
-        op.w = V4<T>::from_bits((unsigned)p);
+        // rigid-body velocity at the marker, U^d = u_p + omega_p x o (FP64)
+        ud.x = (T)(upp[0] + (wpp[1] * o[2] - wpp[2] * o[1]));
+        ud.y = (T)(upp[1] + (wpp[2] * o[0] - wpp[0] * o[2]));
+        ud.z = (T)(upp[2] + (wpp[0] * o[1] - wpp[1] * o[0]));
+        ud.w = (T)dVp;
         rec_tn[dst] = tn;
-        rec_op[dst] = op;
+        rec_ud[dst] = ud;
         rec_src[dst] = l;
     }
 }
@@ -556,17 +554,48 @@ __device__ __forceinline__ void region_base(const GridC &g, const TileBox &box, 
 // interpolation of one pass, one workgroup per tile.  The velocity of the
 // tile and of the support halo around it (R[a] = B[a] + W - 1 nodes per
 // axis, starting one node before the tile) is staged in LDS with coalesced
-// row loads; each own marker then gathers its W^3 stencil from LDS.
+// row loads; each own marker then gathers its W^3 stencil from LDS.  The
+// first marker records of every thread are loaded before the staging so
+// that their latency overlaps it.
 // MODE 0: first pass (writes the amplitude G and its pass sum), 1: later
 // pass (adds G to the pass sum), 2: residual only.
+// tile_max (FP32 passes, may be null): per tile, the largest |G| of the
+// pass and the largest |pass sum| over its own markers, as float4
+// [2][ntiles]; the spreading derives its fixed-point scale from them.
 // ---------------------------------------------------------------------------
+template <typename V>
+__device__ __forceinline__ void block_max6(V *v)   // result in thread 0
+{
+    __shared__ V part[6][16];
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+#pragma unroll
+        for (int off = IBMX_WAVE / 2; off > 0; off >>= 1) {
+            const V w = __shfl_xor(v[q], off, IBMX_WAVE);
+            v[q] = w > v[q] ? w : v[q];
+        }
+    const int lane = threadIdx.x & (IBMX_WAVE - 1), wave = threadIdx.x / IBMX_WAVE;
+    __syncthreads();
+    if (lane == 0)
+        for (int q = 0; q < 6; ++q)
+            part[q][wave] = v[q];
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 6; ++q) {
+            V m = part[q][0];
+            for (int w = 1; w < (int)(blockDim.x / IBMX_WAVE); ++w)
+                m = part[q][w] > m ? part[q][w] : m;
+            v[q] = m;
+        }
+}
+
 template <typename T, int W, int MODE>
 __global__ __launch_bounds__(256) void k_interp(
-    GridC g, TileC tc, int nm, int np, int pass, double c, const int *__restrict__ tile_start,
-    const typename V4<T>::type *__restrict__ rec_tn, const typename V4<T>::type *__restrict__ rec_op,
-    const int *__restrict__ rec_src, const double *__restrict__ dV, const double *__restrict__ up,
-    const double *__restrict__ wp, const T *__restrict__ u, typename V4<T>::type *__restrict__ rec_Gp,
-    typename V4<T>::type *__restrict__ rec_Gs, double *__restrict__ acc, T *__restrict__ U_dbg)
+    GridC g, TileC tc, int nm, int pass, double c, const int *__restrict__ tile_start,
+    const typename V4<T>::type *__restrict__ rec_tn, const typename V4<T>::type *__restrict__ rec_ud,
+    const int *__restrict__ rec_src, const T *__restrict__ u,
+    typename V4<T>::type *__restrict__ rec_Gp, typename V4<T>::type *__restrict__ rec_Gs,
+    double *__restrict__ acc, T *__restrict__ U_dbg, float4 *__restrict__ tile_max)
 {
     typedef typename V4<T>::type T4;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -574,75 +603,101 @@ __global__ __launch_bounds__(256) void k_interp(
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
     const int a0 = tile_start[tile], a1 = tile_start[tile + 1];
     const int n_own = a1 - a0;
-    if (n_own == 0)
+    if (n_own == 0) {
+        if (MODE != 2 && tile_max && threadIdx.x == 0) {
+            tile_max[tile] = make_float4(0.f, 0.f, 0.f, 0.f);
+            tile_max[tc.ntiles + tile] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
         return;
+    }
     const TileBox box(g, tc, tile);
     const int R0 = tc.B[0] + W - 1, R1 = tc.B[1] + W - 1, R2 = tc.B[2] + W - 1;
     const int RV = R0 * R1 * R2;
-    const long long N = g.nodes;
-    const int lane = threadIdx.x & (IBMX_WAVE - 1), wave = threadIdx.x / IBMX_WAVE;
-    const int nw = blockDim.x / IBMX_WAVE;
+    // first records of this thread, in flight during the staging
+    T4 tn = {}, ud = {}, gs = {};
+    if ((int)threadIdx.x < n_own) {
+        tn = rec_tn[a0 + threadIdx.x];
+        ud = rec_ud[a0 + threadIdx.x];
+        if (MODE == 1)
+            gs = rec_Gs[a0 + threadIdx.x];
+    }
     stage_region<T, W>(g, tc, box, u, T(1), (const T *)nullptr, reg);
     __syncthreads();
     double rsq = 0.0;
+    float gmax[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     for (int e = threadIdx.x; e < n_own; e += blockDim.x) {
-        double red[7];
-        {
-            const int j = a0 + e;
-            const T4 tn = rec_tn[j], op = rec_op[j];
-            const T tt[3] = {tn.x, tn.y, tn.z};
-            const double o[3] = {(double)op.x, (double)op.y, (double)op.z};
-            const int pid = (int)V4<T>::to_bits(op.w);
-            int b[3];
-            unpack_node(g, V4<T>::to_bits(tn.w), b);
-            T w[3][W];
-            int d[3];
-            for (int a = 0; a < 3; ++a)
-                Delta<W, T>::w(tt[a], w[a]);
-            region_base(g, box, b, d);
-            T U[3] = {T(0), T(0), T(0)};
+        const int j = a0 + e;
+        const T4 ctn = tn, cud = ud;
+        T4 cgs = gs;
+        if (e + (int)blockDim.x < n_own) {
+            tn = rec_tn[j + blockDim.x];
+            ud = rec_ud[j + blockDim.x];
+            if (MODE == 1)
+                gs = rec_Gs[j + blockDim.x];
+        }
+        const T tt[3] = {ctn.x, ctn.y, ctn.z};
+        int b[3];
+        unpack_node(g, V4<T>::to_bits(ctn.w), b);
+        T w[3][W];
+        int d[3];
+        for (int a = 0; a < 3; ++a)
+            Delta<W, T>::w(tt[a], w[a]);
+        region_base(g, box, b, d);
+        T U[3] = {T(0), T(0), T(0)};
 #pragma unroll
-            for (int k = 0; k < W; ++k)
+        for (int k = 0; k < W; ++k)
 #pragma unroll
-                for (int jj = 0; jj < W; ++jj) {
-                    const T wzy = w[2][k] * w[1][jj];
-                    const int row = ((d[2] + k) * R1 + (d[1] + jj)) * R0 + d[0];
+            for (int jj = 0; jj < W; ++jj) {
+                const T wzy = w[2][k] * w[1][jj];
+                const int row = ((d[2] + k) * R1 + (d[1] + jj)) * R0 + d[0];
 #pragma unroll
-                    for (int i = 0; i < W; ++i) {
-                        const T ww = wzy * w[0][i];
-                        U[0] += ww * reg[row + i];
-                        U[1] += ww * reg[RV + row + i];
-                        U[2] += ww * reg[2 * RV + row + i];
-                    }
-                }
-            T G[3];
-            marker_force<T>(g, np, c, pid, o, U, dV, up, wp, red, G);
-            if (MODE != 2) {
-                if (U_dbg) {
-                    const int src = rec_src[j];
-                    for (int a = 0; a < 3; ++a)
-                        U_dbg[((size_t)pass * 3 + a) * nm + src] = U[a];
-                }
-                T4 gp;
-                gp.x = G[0];
-                gp.y = G[1];
-                gp.z = G[2];
-                gp.w = T(0);
-                rec_Gp[j] = gp;
-                if (MODE == 0) {
-                    rec_Gs[j] = gp;
-                } else {
-                    T4 gs = rec_Gs[j];
-                    gs.x += G[0];
-                    gs.y += G[1];
-                    gs.z += G[2];
-                    rec_Gs[j] = gs;
+                for (int i = 0; i < W; ++i) {
+                    const T ww = wzy * w[0][i];
+                    U[0] += ww * reg[row + i];
+                    U[1] += ww * reg[RV + row + i];
+                    U[2] += ww * reg[2 * RV + row + i];
                 }
             }
+        T G[3];
+        double r2;
+        marker_force<T>(g, c, cud, U, r2, G);
+        rsq += r2;
+        if (MODE != 2) {
+            if (U_dbg) {
+                const int src = rec_src[j];
+                for (int a = 0; a < 3; ++a)
+                    U_dbg[((size_t)pass * 3 + a) * nm + src] = U[a];
+            }
+            T4 gp;
+            gp.x = G[0];
+            gp.y = G[1];
+            gp.z = G[2];
+            gp.w = T(0);
+            rec_Gp[j] = gp;
+            if (MODE == 0) {
+                cgs = gp;
+            } else {
+                cgs.x += G[0];
+                cgs.y += G[1];
+                cgs.z += G[2];
+            }
+            rec_Gs[j] = cgs;
+            gmax[0] = fmaxf(gmax[0], fabsf((float)G[0]));
+            gmax[1] = fmaxf(gmax[1], fabsf((float)G[1]));
+            gmax[2] = fmaxf(gmax[2], fabsf((float)G[2]));
+            gmax[3] = fmaxf(gmax[3], fabsf((float)cgs.x));
+            gmax[4] = fmaxf(gmax[4], fabsf((float)cgs.y));
+            gmax[5] = fmaxf(gmax[5], fabsf((float)cgs.z));
         }
-        rsq += red[6];
     }
     slot_add(acc + (size_t)pass * IBMX_RSLOTS, block_sum<double>(rsq));
+    if (MODE != 2 && tile_max) {
+        block_max6<float>(gmax);
+        if (threadIdx.x == 0) {
+            tile_max[tile] = make_float4(gmax[0], gmax[1], gmax[2], 0.f);
+            tile_max[tc.ntiles + tile] = make_float4(gmax[3], gmax[4], gmax[5], 0.f);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -737,6 +792,7 @@ __global__ __launch_bounds__(256) void k_spread(GridC g, TileC tc, T c, int add_
                                                 const int *__restrict__ halo_list,
                                                 const typename V4<T>::type *__restrict__ rec_tn,
                                                 const typename V4<T>::type *__restrict__ rec_G,
+                                                const float4 *__restrict__ tile_max,
                                                 T *__restrict__ u, T *__restrict__ f_tot,
                                                 long long *__restrict__ count)
 {
@@ -753,7 +809,52 @@ __global__ __launch_bounds__(256) void k_spread(GridC g, TileC tc, T c, int add_
     const TileBox box(g, tc, tile);
     const int V = tc.B[0] * tc.B[1] * tc.B[2];
     T scale[3] = {T(1), T(1), T(1)}, unscale[3] = {T(1), T(1), T(1)};
-    if (sizeof(A) == 4) {
+    for (int i = threadIdx.x; i < 3 * V; i += blockDim.x)
+        acc[i] = A(0);
+    if (sizeof(A) == 4 && tile_max) {
+        // bound on the amplitudes reaching the tile: the largest |G| of the
+        // own markers of the tile and of its 26 neighbours (a support of at
+        // most W <= B nodes reaches one tile further at most)
+        __shared__ float s_gm[3];
+        if (threadIdx.x < IBMX_WAVE) {
+            float m[3] = {0.f, 0.f, 0.f};
+            if (threadIdx.x < 27) {
+                const int dd[3] = {(int)threadIdx.x % 3 - 1, ((int)threadIdx.x / 3) % 3 - 1,
+                                   (int)threadIdx.x / 9 - 1};
+                int t[3] = {tile % tc.nt[0], (tile / tc.nt[0]) % tc.nt[1],
+                            tile / (tc.nt[0] * tc.nt[1])};
+                bool ok = true;
+                for (int a = 0; a < 3; ++a) {
+                    t[a] += dd[a];
+                    if (t[a] < 0 || t[a] >= tc.nt[a]) {
+                        if (g.periodic[a])
+                            t[a] = t[a] < 0 ? t[a] + tc.nt[a] : t[a] - tc.nt[a];
+                        else
+                            ok = false;
+                    }
+                }
+                if (ok) {
+                    const float4 v = tile_max[t[0] + tc.nt[0] * (t[1] + tc.nt[1] * t[2])];
+                    m[0] = v.x;
+                    m[1] = v.y;
+                    m[2] = v.z;
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int off = IBMX_WAVE / 2; off > 0; off >>= 1)
+                    m[a] = fmaxf(m[a], __shfl_xor(m[a], off, IBMX_WAVE));
+            if (threadIdx.x == 0)
+                for (int a = 0; a < 3; ++a)
+                    s_gm[a] = m[a];
+        }
+        __syncthreads();
+        for (int a = 0; a < 3; ++a) {
+            scale[a] = SpreadAcc<T>::scale_for(s_gm[a]);
+            unscale[a] = SpreadAcc<T>::unscale_for(scale[a]);
+        }
+    } else if (sizeof(A) == 4) {
         // largest amplitude reaching the tile, per component
         float gm[3] = {0.f, 0.f, 0.f};
         for (int e = threadIdx.x; e < n_tot; e += blockDim.x) {
@@ -768,8 +869,6 @@ __global__ __launch_bounds__(256) void k_spread(GridC g, TileC tc, T c, int add_
             unscale[a] = SpreadAcc<T>::unscale_for(scale[a]);
         }
     }
-    for (int i = threadIdx.x; i < 3 * V; i += blockDim.x)
-        acc[i] = A(0);
     __syncthreads();
     for (int e = threadIdx.x; e < n_tot; e += blockDim.x) {
         const int j = e < n_own ? a0 + e : halo_list[h0 + e - n_own];
@@ -885,9 +984,8 @@ __global__ __launch_bounds__(256) void k_spread(GridC g, TileC tc, T c, int add_
 // Forward replay of one pass: U, G and J for own markers (LDS-staged u).
 template <typename T, int W>
 __global__ __launch_bounds__(256) void k_interp_jac(
-    GridC g, TileC tc, int nm, int np, double c, const int *__restrict__ tile_start,
-    const typename V4<T>::type *__restrict__ rec_tn, const typename V4<T>::type *__restrict__ rec_op,
-    const double *__restrict__ dV, const double *__restrict__ up, const double *__restrict__ wp,
+    GridC g, TileC tc, int nm, double c, const int *__restrict__ tile_start,
+    const typename V4<T>::type *__restrict__ rec_tn, const typename V4<T>::type *__restrict__ rec_ud,
     const T *__restrict__ u, typename V4<T>::type *__restrict__ GJ)
 {
     typedef typename V4<T>::type T4;
@@ -904,10 +1002,8 @@ __global__ __launch_bounds__(256) void k_interp_jac(
     const T inv_h = (T)(1.0 / g.h);
     for (int e = threadIdx.x; e < n_own; e += blockDim.x) {
         const int j = a0 + e;
-        const T4 tn = rec_tn[j], op = rec_op[j];
+        const T4 tn = rec_tn[j], ud = rec_ud[j];
         const T tt[3] = {tn.x, tn.y, tn.z};
-        const double o[3] = {(double)op.x, (double)op.y, (double)op.z};
-        const int pid = (int)V4<T>::to_bits(op.w);
         int b[3], d[3];
         unpack_node(g, V4<T>::to_bits(tn.w), b);
         region_base(g, box, b, d);
@@ -937,9 +1033,9 @@ __global__ __launch_bounds__(256) void k_interp_jac(
                     }
                 }
             }
-        double red[7];
+        double r2;
         T G[3];
-        marker_force<T>(g, np, c, pid, o, U, dV, up, wp, red, G);
+        marker_force<T>(g, c, ud, U, r2, G);
         T4 q0, q1, q2;
         q0.x = G[0];
         q0.y = G[1];
@@ -964,7 +1060,8 @@ __global__ __launch_bounds__(256) void k_interp_jac(
 template <typename T, int W, int FIRST>
 __global__ __launch_bounds__(256) void k_interp_adj(
     GridC g, TileC tc, int nm, int np, double c, const int *__restrict__ tile_start,
-    const typename V4<T>::type *__restrict__ rec_tn, const typename V4<T>::type *__restrict__ rec_op,
+    const typename V4<T>::type *__restrict__ rec_tn, const int *__restrict__ rec_src,
+    const double *__restrict__ body, const int *__restrict__ pid_of,
     const double *__restrict__ dV, const double *__restrict__ gS, const double *__restrict__ gT,
     const T *__restrict__ ub, const T *__restrict__ gf, const typename V4<T>::type *__restrict__ GJ,
     typename V4<T>::type *__restrict__ Ub_out, double4 *__restrict__ accA,
@@ -984,10 +1081,11 @@ __global__ __launch_bounds__(256) void k_interp_adj(
     const double inv_h = 1.0 / g.h;
     for (int e = threadIdx.x; e < n_own; e += blockDim.x) {
         const int j = a0 + e;
-        const T4 tn = rec_tn[j], op = rec_op[j];
+        const T4 tn = rec_tn[j];
+        const int l = rec_src[j];
         const T tt[3] = {tn.x, tn.y, tn.z};
-        const double o[3] = {(double)op.x, (double)op.y, (double)op.z};
-        const int pid = (int)V4<T>::to_bits(op.w);
+        const double o[3] = {body[l], body[(size_t)nm + l], body[2 * (size_t)nm + l]};
+        const int pid = pid_of[l];
         const T4 q0 = GJ[j], q1 = GJ[nm + j], q2 = GJ[2 * (size_t)nm + j];
         const T G[3] = {q0.x, q0.y, q0.z};
         const double Jm[3][3] = {{(double)q0.w, (double)q1.x, (double)q1.y},
@@ -1147,7 +1245,8 @@ size_t spread_lds(const TileC &tc)
 // Marker geometry and binning of one call: tile counts, sorted records,
 // halo lists, and the zeroed per-call counters.
 template <typename T, int W>
-void bin_markers(ibmx_plan p, const double *xp, const uint8_t *mask, int n_acc)
+void bin_markers(ibmx_plan p, const double *xp, const double *up, const double *wp,
+                 const uint8_t *mask, int n_acc)
 {
     typedef typename V4<T>::type T4;
     hipStream_t s = p->stream;
@@ -1155,7 +1254,7 @@ void bin_markers(ibmx_plan p, const double *xp, const uint8_t *mask, int n_acc)
     const TileC tc = p->tc;
     const int ntiles = tc.ntiles;
     const int *n_act = p->tile_start + ntiles;   // total after the scan
-    T4 *rec_tn = (T4 *)p->rec_tn, *rec_op = (T4 *)p->rec_op;
+    T4 *rec_tn = (T4 *)p->rec_tn, *rec_ud = (T4 *)p->rec_ud;
     {
         ProfScope ps(p, IBMX_K_OTHER);
         ibmx_fill_f64(p->d_acc, 0.0, (long long)n_acc * IBMX_RSLOTS, s);
@@ -1173,8 +1272,8 @@ void bin_markers(ibmx_plan p, const double *xp, const uint8_t *mask, int n_acc)
                            p->d_err, p->d_count);
         ibmx_exclusive_scan(p->tile_count, p->tile_start, ntiles, s);
         hipLaunchKernelGGL((k_bin_scatter<T, W>), dim3(gb), dim3(256), 0, s, p->g, np, nm,
-                           p->d_moff, p->body, xp, p->m_key, p->m_rank, p->bin_tab, p->tile_start,
-                           p->tile_cursor, rec_tn, rec_op, p->rec_src, p->m_inv);
+                           p->d_moff, p->body, xp, up, wp, p->dV, p->m_key, p->m_rank, p->bin_tab,
+                           p->tile_start, p->tile_cursor, rec_tn, rec_ud, p->rec_src, p->m_inv);
         hipLaunchKernelGGL((k_halo<T, W, false>), dim3(nblocks(nm, 256)), dim3(256), 0, s, p->g,
                            tc, n_act, (const T4 *)rec_tn, p->halo_count, (const int *)nullptr,
                            (int *)nullptr, (int *)nullptr, p->halo_cap, p->d_count, p->d_err);
@@ -1199,41 +1298,44 @@ ibmx_status run_forcing(ibmx_plan p, T *u, T *f_tot, const double *xp, const dou
     const double c = p->prm.two_alpha_dt;
     const TileC tc = p->tc;
     const int ntiles = tc.ntiles;
-    T4 *rec_tn = (T4 *)p->rec_tn, *rec_op = (T4 *)p->rec_op;
+    T4 *rec_tn = (T4 *)p->rec_tn, *rec_ud = (T4 *)p->rec_ud;
     T4 *rec_Gp = (T4 *)p->rec_Gp, *rec_Gs = (T4 *)p->rec_G;
+    // per-tile amplitude bounds for the FP32 fixed-point spreading
+    float4 *tmax = sizeof(T) == 4 ? p->tile_gmax : nullptr;
+    const float4 *tmax_pass = tmax, *tmax_sum = tmax ? tmax + ntiles : nullptr;
     {
         ProfScope ps(p, IBMX_K_OTHER);
         ibmx_fill_f64(S_out, 0.0, 3LL * np, s);
         ibmx_fill_f64(T_out, 0.0, 3LL * np, s);
     }
-    bin_markers<T, W>(p, xp, mask, n_iter + 1);
+    bin_markers<T, W>(p, xp, up, wp, mask, n_iter + 1);
     const size_t lds_i = interp_lds<T, W>(tc), lds_s = spread_lds<T>(tc);
     for (int m = 0; m < n_iter && nm > 0; ++m) {
         {
             ProfScope ps(p, IBMX_K_INTERP);
             if (m == 0)
                 hipLaunchKernelGGL((k_interp<T, W, 0>), dim3(ntiles), dim3(256), lds_i, s, p->g, tc,
-                                   nm, np, m, c, p->tile_start, (const T4 *)rec_tn,
-                                   (const T4 *)rec_op, p->rec_src, p->dV, up, wp, (const T *)u,
-                                   rec_Gp, rec_Gs, p->d_acc, U_dbg);
+                                   nm, m, c, p->tile_start, (const T4 *)rec_tn, (const T4 *)rec_ud,
+                                   p->rec_src, (const T *)u, rec_Gp, rec_Gs, p->d_acc, U_dbg,
+                                   tmax);
             else
                 hipLaunchKernelGGL((k_interp<T, W, 1>), dim3(ntiles), dim3(256), lds_i, s, p->g, tc,
-                                   nm, np, m, c, p->tile_start, (const T4 *)rec_tn,
-                                   (const T4 *)rec_op, p->rec_src, p->dV, up, wp, (const T *)u,
-                                   rec_Gp, rec_Gs, p->d_acc, U_dbg);
+                                   nm, m, c, p->tile_start, (const T4 *)rec_tn, (const T4 *)rec_ud,
+                                   p->rec_src, (const T *)u, rec_Gp, rec_Gs, p->d_acc, U_dbg,
+                                   tmax);
         }
         ProfScope ps(p, IBMX_K_SPREAD);
         hipLaunchKernelGGL((k_spread<T, W>), dim3(ntiles), dim3(256), lds_s, s, p->g, tc, (T)c, 1,
                            n_iter == 1 ? 1 : 0, m == 0 ? 1 : 0, p->tile_start, p->halo_start,
-                           p->halo_list, (const T4 *)rec_tn, (const T4 *)rec_Gp, u, f_tot,
-                           p->d_count);
+                           p->halo_list, (const T4 *)rec_tn, (const T4 *)rec_Gp, tmax_pass, u,
+                           f_tot, p->d_count);
     }
     if (n_iter >= 2 && nm > 0) {
         // f_tot += spread of the amplitudes summed over the passes
         ProfScope ps(p, IBMX_K_FTOT);
         hipLaunchKernelGGL((k_spread<T, W>), dim3(ntiles), dim3(256), lds_s, s, p->g, tc, (T)c, 0,
                            1, 0, p->tile_start, p->halo_start, p->halo_list, (const T4 *)rec_tn,
-                           (const T4 *)rec_Gs, u, f_tot, p->d_count);
+                           (const T4 *)rec_Gs, tmax_sum, u, f_tot, p->d_count);
     }
     if (np > 0) {
         ProfScope ps(p, IBMX_K_OTHER);
@@ -1246,9 +1348,9 @@ ibmx_status run_forcing(ibmx_plan p, T *u, T *f_tot, const double *xp, const dou
         if (nm > 0) {
             ProfScope ps(p, IBMX_K_OTHER);
             hipLaunchKernelGGL((k_interp<T, W, 2>), dim3(ntiles), dim3(256), lds_i, s, p->g, tc, nm,
-                               np, n_iter, c, p->tile_start, (const T4 *)rec_tn, (const T4 *)rec_op,
-                               p->rec_src, p->dV, up, wp, (const T *)u, rec_Gp, rec_Gs, p->d_acc,
-                               (T *)nullptr);
+                               n_iter, c, p->tile_start, (const T4 *)rec_tn, (const T4 *)rec_ud,
+                               p->rec_src, (const T *)u, rec_Gp, rec_Gs, p->d_acc, (T *)nullptr,
+                               (float4 *)nullptr);
         }
         hipLaunchKernelGGL(k_finish_resid, dim3(n_iter + 1), dim3(256), 0, s, p->d_acc, resid_out);
     }
@@ -1269,7 +1371,7 @@ ibmx_status run_backward(ibmx_plan p, const T *u0, const double *xp, const doubl
     const TileC tc = p->tc;
     const int ntiles = tc.ntiles;
     const long long G3 = 3 * p->g.nodes;
-    T4 *rec_tn = (T4 *)p->rec_tn, *rec_op = (T4 *)p->rec_op, *rec_Ub = (T4 *)p->rec_Gp;
+    T4 *rec_tn = (T4 *)p->rec_tn, *rec_ud = (T4 *)p->rec_ud, *rec_Ub = (T4 *)p->rec_Gp;
     // workspace: replay grid, per-pass G and Jacobian, per-marker sums
     const size_t Ts = sizeof(T);
     const size_t need = Ts * (size_t)G3 + 3 * sizeof(T4) * (size_t)nm * p->n_iter_cap +
@@ -1287,7 +1389,7 @@ ibmx_status run_backward(ibmx_plan p, const T *u0, const double *xp, const doubl
     T4 *GJ = (T4 *)(us + G3);
     double4 *accA = (double4 *)(GJ + 3 * (size_t)nm * p->n_iter_cap);
     double4 *accB = accA + nm;
-    bin_markers<T, W>(p, xp, mask, 1);
+    bin_markers<T, W>(p, xp, up, wp, mask, 1);
     const int cb = 4096;
     {
         ProfScope ps(p, IBMX_K_OTHER);
@@ -1306,29 +1408,30 @@ ibmx_status run_backward(ibmx_plan p, const T *u0, const double *xp, const doubl
         for (int m = 0; m < n_iter; ++m) {
             T4 *GJm = GJ + 3 * (size_t)nm * m;
             hipLaunchKernelGGL((k_interp_jac<T, W>), dim3(ntiles), dim3(256), lds_i, s, p->g, tc, nm,
-                               np, c, p->tile_start, (const T4 *)rec_tn, (const T4 *)rec_op, p->dV,
-                               up, wp, (const T *)us, GJm);
+                               c, p->tile_start, (const T4 *)rec_tn, (const T4 *)rec_ud,
+                               (const T *)us, GJm);
             if (m < n_iter - 1)
                 hipLaunchKernelGGL((k_spread<T, W>), dim3(ntiles), dim3(256), lds_s, s, p->g, tc,
                                    (T)c, 1, 0, 0, p->tile_start, p->halo_start, p->halo_list,
-                                   (const T4 *)rec_tn, (const T4 *)GJm, us, (T *)nullptr,
-                                   p->d_count);
+                                   (const T4 *)rec_tn, (const T4 *)GJm, (const float4 *)nullptr,
+                                   us, (T *)nullptr, p->d_count);
         }
         for (int m = n_iter - 1; m >= 0; --m) {
             const T4 *GJm = GJ + 3 * (size_t)nm * m;
             if (m == n_iter - 1)
                 hipLaunchKernelGGL((k_interp_adj<T, W, 1>), dim3(ntiles), dim3(256), lds_i, s, p->g,
                                    tc, nm, np, c, p->tile_start, (const T4 *)rec_tn,
-                                   (const T4 *)rec_op, p->dV, g_S, g_T, (const T *)gu0, g_f, GJm,
-                                   rec_Ub, accA, accB);
+                                   p->rec_src, p->body, p->d_pid, p->dV, g_S, g_T,
+                                   (const T *)gu0, g_f, GJm, rec_Ub, accA, accB);
             else
                 hipLaunchKernelGGL((k_interp_adj<T, W, 0>), dim3(ntiles), dim3(256), lds_i, s, p->g,
                                    tc, nm, np, c, p->tile_start, (const T4 *)rec_tn,
-                                   (const T4 *)rec_op, p->dV, g_S, g_T, (const T *)gu0, g_f, GJm,
-                                   rec_Ub, accA, accB);
+                                   p->rec_src, p->body, p->d_pid, p->dV, g_S, g_T,
+                                   (const T *)gu0, g_f, GJm, rec_Ub, accA, accB);
             hipLaunchKernelGGL((k_spread<T, W>), dim3(ntiles), dim3(256), lds_s, s, p->g, tc, T(1), 1,
                                0, 0, p->tile_start, p->halo_start, p->halo_list, (const T4 *)rec_tn,
-                               (const T4 *)rec_Ub, gu0, (T *)nullptr, p->d_count);
+                               (const T4 *)rec_Ub, (const float4 *)nullptr, gu0, (T *)nullptr,
+                               p->d_count);
         }
         if (np > 0)
             hipLaunchKernelGGL(k_particle_grad, dim3(nblocks(np, 4)), dim3(256), 0, s, np, nm,

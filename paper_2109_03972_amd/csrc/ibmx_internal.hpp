@@ -60,7 +60,8 @@ struct ibmx_plan_s {
 
     // marker records, sorted by spreading tile (T4 = float4 / double4)
     void *rec_tn;         // T4[nm] {t_x, t_y, t_z, packed base node (bits)}
-    void *rec_op;         // T4[nm] {o_x, o_y, o_z, particle id (bits)}
+    void *rec_ud;         // T4[nm] {U^d_x, U^d_y, U^d_z, dV}: rigid-body velocity
+                          // u_p + omega_p x o at the marker and its volume
     void *rec_Gp;         // T4[nm] spreading amplitude G = F dV / h^3 of the pass
     void *rec_G;          // T4[nm] G summed over the passes
     int *rec_src;         // [nm] original marker index
@@ -70,6 +71,7 @@ struct ibmx_plan_s {
 
     // tiles
     TileC tc;
+    long long tile_cap;   // tiles the tile arrays are sized for
     int *bin_tab;         // [np][2][IBMX_BIN_SLOTS] per-particle tile tables
     int *tile_count;      // [ntiles + 1]
     int *tile_start;      // [ntiles + 1]
@@ -78,6 +80,8 @@ struct ibmx_plan_s {
     int *halo_start;      // [ntiles + 1]
     int *halo_cursor;     // [ntiles]
     int *halo_list;       // [halo_cap]
+    float4 *tile_gmax;    // [2][ntiles] largest |G| of the pass and |pass sum|
+                          // over each tile's own markers (FP32 spreading scale)
     long long halo_cap;
     int block;            // threads per workgroup of marker passes
 

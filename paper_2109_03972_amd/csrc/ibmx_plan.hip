@@ -19,11 +19,12 @@ void free_plan(ibmx_plan p)
 {
     if (!p)
         return;
-    void *ptrs[] = {p->d_moff, p->d_pid, p->d_err, p->d_acc, p->d_count, p->rec_tn,
-                    p->rec_op, p->rec_src, p->rec_Gp, p->rec_G, p->m_key, p->m_inv,
-                    p->m_rank, p->tile_count, p->tile_start, p->tile_cursor, p->halo_count,
-                    p->halo_start, p->halo_cursor, p->halo_list, p->bw_u, p->p_cell_of, p->p_cursor, p->p_count, p->p_off, p->p_wcount,
-                    p->p_woff, p->bin_tab};
+    void *ptrs[] = {p->d_moff,      p->d_pid,       p->d_err,        p->d_acc,     p->d_count,
+                    p->rec_tn,      p->rec_ud,      p->rec_src,      p->rec_Gp,    p->rec_G,
+                    p->m_key,       p->m_inv,       p->m_rank,       p->tile_count, p->tile_start,
+                    p->tile_cursor, p->halo_count,  p->halo_start,   p->halo_cursor,
+                    p->halo_list,   p->tile_gmax,   p->bw_u,         p->p_cell_of, p->p_cursor,
+                    p->p_count,     p->p_off,       p->p_wcount,     p->p_woff,    p->bin_tab};
     for (void *q : ptrs)
         if (q)
             (void)hipFree(q);
@@ -145,7 +146,7 @@ ibmx_status check_params(const ibmx_grid *g, const ibmx_params *prm)
     A((void **)&p->d_acc, sizeof(double) * (p->n_iter_cap + 2) * IBMX_RSLOTS);
     A((void **)&p->d_count, sizeof(long long) * 8 * IBMX_RSLOTS);
     A(&p->rec_tn, Ts * 4 * nmz);
-    A(&p->rec_op, Ts * 4 * nmz);
+    A(&p->rec_ud, Ts * 4 * nmz);
     A(&p->rec_G, Ts * 4 * nmz);
     A(&p->rec_Gp, Ts * 4 * nmz);
     A((void **)&p->rec_src, sizeof(int) * nmz);
@@ -244,22 +245,26 @@ ibmx_status ibmx_plan_alloc_tiles(ibmx_plan p, int tx, int ty, int tz)
     const size_t Ts = p->prec == IBMX_F64 ? sizeof(double) : sizeof(float);
     if ((size_t)3 * t[0] * t[1] * t[2] * Ts > 160 * 1024)
         return IBMX_EUNSUPPORTED;
-    if (!p->tile_count || ntiles > p->tc.ntiles) {
+    if (!p->tile_count || ntiles > p->tile_cap) {
         void *ptrs[] = {p->tile_count, p->tile_start, p->tile_cursor, p->halo_count,
-                        p->halo_start, p->halo_cursor};
+                        p->halo_start, p->halo_cursor, p->tile_gmax};
         for (void *q : ptrs)
             if (q)
                 (void)hipFree(q);
         p->tile_count = p->tile_start = p->tile_cursor = nullptr;
         p->halo_count = p->halo_start = p->halo_cursor = nullptr;
+        p->tile_gmax = nullptr;
+        p->tc.ntiles = 0;
         size_t b = sizeof(int) * (size_t)(ntiles + 1);
         if (hipMalloc((void **)&p->tile_count, b) != hipSuccess ||
             hipMalloc((void **)&p->tile_start, b) != hipSuccess ||
             hipMalloc((void **)&p->tile_cursor, b) != hipSuccess ||
             hipMalloc((void **)&p->halo_count, b) != hipSuccess ||
             hipMalloc((void **)&p->halo_start, b) != hipSuccess ||
-            hipMalloc((void **)&p->halo_cursor, b) != hipSuccess)
+            hipMalloc((void **)&p->halo_cursor, b) != hipSuccess ||
+            hipMalloc((void **)&p->tile_gmax, sizeof(float4) * 2 * (size_t)ntiles) != hipSuccess)
             return IBMX_ENOMEM;
+        p->tile_cap = ntiles;
     }
     // every marker reaches at most 7 tiles besides its own
     long long cap = 7LL * (p->nm > 0 ? p->nm : 1);
