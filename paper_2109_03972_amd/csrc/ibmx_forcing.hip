@@ -474,13 +474,13 @@ __device__ __forceinline__ V block_max(V v)
 }
 
 // Stage v = scale * src (+ src2) over the tile's support region
-// [o - 1, o + B + W - 2) per axis into LDS (nodes beyond a wall read 0): each
-// wave loads 64 / R0 rows of R0 nodes per step, and every thread issues SUNR
-// steps of loads before its LDS stores.
+// [o - 1, o + B + W - 2) per axis into LDS (nodes beyond a wall read 0),
+// element by element: each wave loads 64 / R0 rows of R0 nodes per step, and
+// every thread issues SUNR steps of loads before its LDS stores.
 template <typename T, int W>
-__device__ __forceinline__ void stage_region(const GridC &g, const TileC &tc, const TileBox &box,
-                                             const T *__restrict__ src, T scale,
-                                             const T *__restrict__ src2, T *reg)
+__device__ __forceinline__ void stage_region_rows(const GridC &g, const TileC &tc,
+                                                  const TileBox &box, const T *__restrict__ src,
+                                                  T scale, const T *__restrict__ src2, T *reg)
 {
     const int R0 = tc.B[0] + W - 1, R1 = tc.B[1] + W - 1, R2 = tc.B[2] + W - 1;
     const int RV = R0 * R1 * R2;
@@ -536,6 +536,131 @@ __device__ __forceinline__ void stage_region(const GridC &g, const TileC &tc, co
             reg[2 * RV + li[q]] = v[q][2];
         }
     }
+}
+
+// 16-byte packet of grid values (4 floats or 2 doubles)
+template <typename T>
+struct alignas(16) Pack16 {
+    T e[16 / sizeof(T)];
+};
+
+// The same staging with 16-byte loads: every row of the region is covered by
+// the aligned packets of [floor_E(o - 1), ceil_E(o + B + W - 2)) (E values
+// per packet); packets inside the grid are loaded whole, packets crossing an
+// edge value by value (wrapped on a periodic axis, 0 beyond a wall).  Needs
+// n_x and the field pointers to be multiples of E values / 16 bytes.
+constexpr int VUNR = 5;   // row groups per vector staging step
+template <typename T, int W>
+__device__ __forceinline__ void stage_region_vec(const GridC &g, const TileC &tc,
+                                                 const TileBox &box, const T *__restrict__ src,
+                                                 T scale, const T *__restrict__ src2, T *reg)
+{
+    constexpr int E = 16 / (int)sizeof(T);
+    const int R0 = tc.B[0] + W - 1, R1 = tc.B[1] + W - 1, R2 = tc.B[2] + W - 1;
+    const int RV = R0 * R1 * R2;
+    const long long N = g.nodes;
+    const int xs = box.o[0] - 1, xe = box.o[0] + R0 - 1;   // needed x range
+    const int X0 = xs >= 0 ? xs - xs % E : -E;               // xs >= -1
+    const int nch = (xe + E - 1 - X0) / E;                 // packets per row (xe > 0)
+    const int lane = threadIdx.x & (IBMX_WAVE - 1), wave = threadIdx.x / IBMX_WAVE;
+    const int nw = blockDim.x / IBMX_WAVE;
+    const int rpi = IBMX_WAVE / nch;
+    const int sub = lane / nch, ch = lane - sub * nch;
+    const int step = nw * rpi, rows = R1 * R2;
+    const int x = X0 + ch * E;
+    const bool lane_ok = sub < rpi;
+    const bool whole = x >= 0 && x + E <= g.n[0];
+    for (int r0 = wave * rpi + sub; r0 < rows; r0 += VUNR * step) {
+        Pack16<T> v[VUNR][3];
+        int rb[VUNR];
+#pragma unroll
+        for (int q = 0; q < VUNR; ++q) {
+            const int r = r0 + q * step;
+            const int rz = r / R1, ry = r - rz * R1;
+            int gy = box.o[1] - 1 + ry, gz = box.o[2] - 1 + rz;
+            bool ok = lane_ok && r < rows;
+            if (g.periodic[1])
+                gy = gy < 0 ? gy + g.n[1] : (gy >= g.n[1] ? gy - g.n[1] : gy);
+            else
+                ok = ok && gy >= 0 && gy < g.n[1];
+            if (g.periodic[2])
+                gz = gz < 0 ? gz + g.n[2] : (gz >= g.n[2] ? gz - g.n[2] : gz);
+            else
+                ok = ok && gz >= 0 && gz < g.n[2];
+            rb[q] = lane_ok && r < rows ? (rz * R1 + ry) * R0 : -1;
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int k = 0; k < E; ++k)
+                    v[q][c].e[k] = T(0);
+            if (!ok)
+                continue;
+            const long long row = ((long long)gz * g.n[1] + gy) * g.n[0];
+            if (whole) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    v[q][c] = *reinterpret_cast<const Pack16<T> *>(src + c * N + row + x);
+                    if (src2) {
+                        const Pack16<T> w2 =
+                            *reinterpret_cast<const Pack16<T> *>(src2 + c * N + row + x);
+#pragma unroll
+                        for (int k = 0; k < E; ++k)
+                            v[q][c].e[k] = scale * v[q][c].e[k] + w2.e[k];
+                    } else if (scale != T(1)) {
+#pragma unroll
+                        for (int k = 0; k < E; ++k)
+                            v[q][c].e[k] = scale * v[q][c].e[k];
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < E; ++k) {
+                    int gx = x + k;
+                    if (gx < xs || gx >= xe)
+                        continue;
+                    if (g.periodic[0])
+                        gx = gx < 0 ? gx + g.n[0] : (gx >= g.n[0] ? gx - g.n[0] : gx);
+                    else if (gx < 0 || gx >= g.n[0])
+                        continue;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        T val = scale * src[c * N + row + gx];
+                        if (src2)
+                            val += src2[c * N + row + gx];
+                        v[q][c].e[k] = val;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < VUNR; ++q) {
+            if (rb[q] < 0)
+                continue;
+#pragma unroll
+            for (int k = 0; k < E; ++k) {
+                const int lx = x + k - xs;
+                if (lx < 0 || lx >= R0)
+                    continue;
+                reg[rb[q] + lx] = v[q][0].e[k];
+                reg[RV + rb[q] + lx] = v[q][1].e[k];
+                reg[2 * RV + rb[q] + lx] = v[q][2].e[k];
+            }
+        }
+    }
+}
+
+template <typename T, int W>
+__device__ __forceinline__ void stage_region(const GridC &g, const TileC &tc, const TileBox &box,
+                                             const T *__restrict__ src, T scale,
+                                             const T *__restrict__ src2, T *reg)
+{
+    constexpr int E = 16 / (int)sizeof(T);
+    const bool vec = g.n[0] % E == 0 && ((size_t)src & 15) == 0 &&
+                     (!src2 || ((size_t)src2 & 15) == 0);
+    if (vec)
+        stage_region_vec<T, W>(g, tc, box, src, scale, src2, reg);
+    else
+        stage_region_rows<T, W>(g, tc, box, src, scale, src2, reg);
 }
 
 // Region index of a marker's base node per axis: the centre node b + 1 lies
@@ -909,8 +1034,8 @@ __global__ __launch_bounds__(256) void k_spread(GridC g, TileC tc, T c, int add_
     __syncthreads();
     const long long N = g.nodes;
     int touched = 0;
-    const TileWalk tw(tc, box.e[0]);
     const int wave = threadIdx.x / IBMX_WAVE;
+    const TileWalk tw(tc, box.e[0]);
     for (int r0 = wave * tw.rpi + tw.sub; r0 < tw.rows; r0 += UNR * tw.nw * tw.rpi) {
         long long gi[UNR];
         bool act[UNR];

@@ -132,10 +132,13 @@ def test_tune_keeps_inputs_and_results(oracle_lib, precision):
             assert e <= tol[k], f"{k}: {e:.3e}"
 
 
-@pytest.mark.parametrize("tile", [(8, 8, 8), (32, 16, 4), (16, 8, 16), (4, 4, 4)])
-def test_tile_shapes_parity(oracle_lib, tile):
+@pytest.mark.parametrize("n", [(41, 37, 45), (48, 40, 44)])
+@pytest.mark.parametrize("tile", [(8, 8, 8), (32, 16, 4), (16, 8, 16), (4, 4, 4), (12, 16, 8)])
+def test_tile_shapes_parity(oracle_lib, tile, n):
+    """Tile shapes on a grid whose x extent is not a multiple of 4 (element
+    staging and write-out) and on one that is (16-byte packets)."""
     dev = require_gpu()
-    case = synth.small_case(74, n=(41, 37, 45), periodic=(1, 1, 0), n_iter=2, touch=0.4)
+    case = synth.small_case(74, n=n, periodic=(1, 1, 0), n_iter=2, touch=0.4)
     m_np, mk = _mask(case, dev)
     ref = oracle_lib.forcing(case, mask=m_np)
     for precision, tol in (("f64", 1e-12), ("f32", 1e-4)):
