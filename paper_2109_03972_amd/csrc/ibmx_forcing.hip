@@ -225,23 +225,90 @@ constexpr int UNR = 4;    // row groups per write-out step
 constexpr int SUNR = 16;  // row groups per staging step
 
 // ---------------------------------------------------------------------------
-// binning step A: one wave per particle.  Tile key and rank of every active
-// marker among the particle's markers of the same tile (in index order), and
-// the per-tile counts.
+// halo entries: a marker registers itself with every neighbouring tile its
+// support reaches (at most 7: tiles are at least W nodes wide); a last
+// support node of zero weight (t == 0) does not count.
 // ---------------------------------------------------------------------------
-template <int W>
+template <typename T, int W>
+__device__ __forceinline__ int halo_tiles(const GridC &g, const TileC &tc, const int *b,
+                                          const T *tt, int *tgt)
+{
+    int tl[3][2], nt[3], home[3];
+    for (int a = 0; a < 3; ++a) {
+        const int last = tt[a] == T(0) ? W - 2 : W - 1;
+        home[a] = axis_node(g, a, b[a], 1) / tc.B[a];
+        const int t0 = axis_node(g, a, b[a], 0) / tc.B[a];
+        const int t1 = axis_node(g, a, b[a], last) / tc.B[a];
+        tl[a][0] = t0;
+        tl[a][1] = t1;
+        nt[a] = t1 == t0 ? 1 : 2;
+    }
+    int ntg = 0;
+    for (int kz = 0; kz < nt[2]; ++kz)
+        for (int ky = 0; ky < nt[1]; ++ky)
+            for (int kx = 0; kx < nt[0]; ++kx) {
+                const int tx = tl[0][kx], ty = tl[1][ky], tz = tl[2][kz];
+                if (tx == home[0] && ty == home[1] && tz == home[2])
+                    continue;
+                tgt[ntg++] = tx + tc.nt[0] * (ty + tc.nt[1] * tz);
+            }
+    return ntg;
+}
+
+// Wave-aggregated halo registration of every lane's tiles: the count pass
+// adds to ctr[tile]; the emit pass reserves positions with ctr = cursor and
+// writes the lane's record index j into the tile's halo list.
+template <bool EMIT>
+__device__ __forceinline__ void halo_register(const int *tgt, int ntg, int j, int *ctr,
+                                              const int *__restrict__ halo_start,
+                                              int *__restrict__ halo_list, long long cap,
+                                              int *__restrict__ err)
+{
+    const int lane = threadIdx.x & (IBMX_WAVE - 1);
+    for (int k = 0; k < 7; ++k) {
+        const int key = k < ntg ? tgt[k] : -1;
+        unsigned long long pending = __ballot(key >= 0);
+        while (pending) {
+            const int leader = __ffsll((long long)pending) - 1;
+            const int kk = __shfl(key, leader, IBMX_WAVE);
+            const unsigned long long m = __ballot(key == kk) & pending;
+            int base = 0;
+            if (lane == leader)
+                base = atomicAdd(&ctr[kk], __popcll(m));
+            if (EMIT) {
+                base = __shfl(base, leader, IBMX_WAVE);
+                if (key == kk) {
+                    const long long pos =
+                        (long long)halo_start[kk] + base + __popcll(m & lanemask_lt(lane));
+                    if (pos < cap)
+                        halo_list[pos] = j;
+                    else
+                        atomicCAS(err, 0, (int)IBMX_ECAPACITY);
+                }
+            }
+            pending &= ~m;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// binning step A: one wave per particle.  Tile key and rank of every active
+// marker among the particle's markers of the same tile (in index order), the
+// per-tile marker counts and the per-tile halo entry counts.
+// ---------------------------------------------------------------------------
+template <typename T, int W>
 __global__ __launch_bounds__(256) void k_bin_count(
     GridC g, TileC tc, int np, int nm, const int *__restrict__ moff,
     const double *__restrict__ body, const double *__restrict__ xp,
     const uint8_t *__restrict__ mask, int *__restrict__ m_key, int *__restrict__ m_rank,
-    int *__restrict__ tab, int *__restrict__ tile_count, int *__restrict__ err,
-    long long *__restrict__ count)
+    int *__restrict__ tab, int *__restrict__ tile_count, int *__restrict__ halo_count,
+    int *__restrict__ err, long long *__restrict__ count)
 {
     __shared__ int s_keys[4][TS];
     __shared__ int s_cnt[4][TS];
     const int wv = threadIdx.x / IBMX_WAVE, lane = threadIdx.x & (IBMX_WAVE - 1);
     const int p = blockIdx.x * 4 + wv;
-    int active = 0;
+    int active = 0, entries = 0;
     if (p < np) {
     volatile int *keys = s_keys[wv];
     volatile int *cnt = s_cnt[wv];
@@ -254,17 +321,24 @@ __global__ __launch_bounds__(256) void k_bin_count(
     for (int base = l0; base < l1; base += IBMX_WAVE) {
         const int l = base + lane;
         int key = -1;
+        int tgt[7];
+        int ntg = 0;
         if (l < l1 && (!mask || mask[l])) {
             double X[3], t[3];
             int b[3];
             for (int a = 0; a < 3; ++a)
                 X[a] = xc[a] + body[(size_t)a * nm + l];
-            if (marker_geometry<W>(g, X, b, t))
+            if (marker_geometry<W>(g, X, b, t)) {
                 key = home_tile(g, tc, b);
-            else
+                const T tt[3] = {(T)t[0], (T)t[1], (T)t[2]};
+                ntg = halo_tiles<T, W>(g, tc, b, tt, tgt);
+            } else {
                 atomicCAS(err, 0, (int)IBMX_EDOMAIN);
+            }
         }
         active += key >= 0;
+        entries += ntg;
+        halo_register<false>(tgt, ntg, 0, halo_count, nullptr, nullptr, 0, nullptr);
         unsigned long long pending = __ballot(key >= 0);
         while (pending) {
             const int leader = __ffsll((long long)pending) - 1;
@@ -302,11 +376,13 @@ __global__ __launch_bounds__(256) void k_bin_count(
     }
     }
     slot_add(count, block_sum<long long>(active));
+    slot_add(count + 2 * IBMX_RSLOTS, block_sum<long long>(entries));
 }
 
 // ---------------------------------------------------------------------------
 // binning step B: one wave per particle.  Reserve the particle's segment in
-// every tile it touches and write the sorted marker records.
+// every tile it touches, write the sorted marker records and register each
+// record in the halo lists of the neighbouring tiles its support reaches.
 // ---------------------------------------------------------------------------
 template <typename T, int W>
 __global__ __launch_bounds__(256) void k_bin_scatter(
@@ -315,7 +391,9 @@ __global__ __launch_bounds__(256) void k_bin_scatter(
     const double *__restrict__ dV, const int *__restrict__ m_key, const int *__restrict__ m_rank,
     const int *__restrict__ tab, const int *__restrict__ tile_start, int *__restrict__ tile_cursor,
     typename V4<T>::type *__restrict__ rec_tn, typename V4<T>::type *__restrict__ rec_ud,
-    int *__restrict__ rec_src, int *__restrict__ m_inv)
+    int *__restrict__ rec_src, int *__restrict__ m_inv, const TileC tc,
+    const int *__restrict__ halo_start, int *__restrict__ halo_cursor, int *__restrict__ halo_list,
+    long long halo_cap, int *__restrict__ err)
 {
     __shared__ int s_base[4][TS];
     const int wv = threadIdx.x / IBMX_WAVE, lane = threadIdx.x & (IBMX_WAVE - 1);
@@ -333,107 +411,41 @@ __global__ __launch_bounds__(256) void k_bin_scatter(
     const double wpp[3] = {wp[p], wp[np + p], wp[2 * np + p]};
     const double dVp = dV[p];
     const int l0 = moff[p], l1 = moff[p + 1];
-    for (int l = l0 + lane; l < l1; l += IBMX_WAVE) {
-        const int slot = m_key[l];
+    for (int l = l0 + lane; l - lane < l1; l += IBMX_WAVE) {
+        const int slot = l < l1 ? m_key[l] : -1;
+        int tgt[7];
+        int ntg = 0, dst = -1;
         if (slot < 0) {
-            m_inv[l] = -1;
-            continue;
-        }
-        const int dst = base_of[slot] + m_rank[l];
-        m_inv[l] = dst;
-        double X[3], t[3], o[3];
-        int b[3];
-        for (int a = 0; a < 3; ++a) {
-            o[a] = body[(size_t)a * nm + l];
-            X[a] = xc[a] + o[a];
-        }
-        marker_geometry<W>(g, X, b, t);
-        typename V4<T>::type tn, ud;
-        tn.x = (T)t[0];
-        tn.y = (T)t[1];
-        tn.z = (T)t[2];
-        tn.w = V4<T>::from_bits(pack_node(g, b[0], b[1], b[2]));
-        // rigid-body velocity at the marker, U^d = u_p + omega_p x o (FP64)
-        ud.x = (T)(upp[0] + (wpp[1] * o[2] - wpp[2] * o[1]));
-        ud.y = (T)(upp[1] + (wpp[2] * o[0] - wpp[0] * o[2]));
-        ud.z = (T)(upp[2] + (wpp[0] * o[1] - wpp[1] * o[0]));
-        ud.w = (T)dVp;
-        rec_tn[dst] = tn;
-        rec_ud[dst] = ud;
-        rec_src[dst] = l;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// halo lists: every sorted marker registers itself with each neighbouring
-// tile its support reaches (at most 7: tiles are at least W nodes wide).
-// Registrations to the same tile are aggregated per wave.
-// ---------------------------------------------------------------------------
-template <typename T, int W, bool EMIT>
-__global__ __launch_bounds__(256) void k_halo(GridC g, TileC tc, const int *__restrict__ n_act_p,
-                                              const typename V4<T>::type *__restrict__ rec_tn,
-                                              int *__restrict__ halo_count,
-                                              const int *__restrict__ halo_start,
-                                              int *__restrict__ halo_cursor,
-                                              int *__restrict__ halo_list, long long cap,
-                                              long long *__restrict__ count, int *__restrict__ err)
-{
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int lane = threadIdx.x & (IBMX_WAVE - 1);
-    const int n_act = *n_act_p;
-    int tgt[7];
-    int ntg = 0;
-    if (j < n_act) {
-        const typename V4<T>::type tn = rec_tn[j];
-        const T tt[3] = {tn.x, tn.y, tn.z};
-        int b[3];
-        unpack_node(g, V4<T>::to_bits(tn.w), b);
-        int tl[3][2], nt[3], home[3];
-        for (int a = 0; a < 3; ++a) {
-            const int last = tt[a] == T(0) ? W - 2 : W - 1;
-            home[a] = axis_node(g, a, b[a], 1) / tc.B[a];
-            const int t0 = axis_node(g, a, b[a], 0) / tc.B[a];
-            const int t1 = axis_node(g, a, b[a], last) / tc.B[a];
-            tl[a][0] = t0;
-            tl[a][1] = t1;
-            nt[a] = t1 == t0 ? 1 : 2;
-        }
-        for (int kz = 0; kz < nt[2]; ++kz)
-            for (int ky = 0; ky < nt[1]; ++ky)
-                for (int kx = 0; kx < nt[0]; ++kx) {
-                    const int tx = tl[0][kx], ty = tl[1][ky], tz = tl[2][kz];
-                    if (tx == home[0] && ty == home[1] && tz == home[2])
-                        continue;
-                    tgt[ntg++] = tx + tc.nt[0] * (ty + tc.nt[1] * tz);
-                }
-    }
-    int entries = ntg;
-    for (int k = 0; k < 7; ++k) {
-        const int key = k < ntg ? tgt[k] : -1;
-        unsigned long long pending = __ballot(key >= 0);
-        while (pending) {
-            const int leader = __ffsll((long long)pending) - 1;
-            const int kk = __shfl(key, leader, IBMX_WAVE);
-            const unsigned long long m = __ballot(key == kk) & pending;
-            int base = 0;
-            if (lane == leader)
-                base = atomicAdd(EMIT ? &halo_cursor[kk] : &halo_count[kk], __popcll(m));
-            if (EMIT) {
-                base = __shfl(base, leader, IBMX_WAVE);
-                if (key == kk) {
-                    const long long pos =
-                        (long long)halo_start[kk] + base + __popcll(m & lanemask_lt(lane));
-                    if (pos < cap)
-                        halo_list[pos] = j;
-                    else
-                        atomicCAS(err, 0, (int)IBMX_ECAPACITY);
-                }
+            if (l < l1)
+                m_inv[l] = -1;
+        } else {
+            dst = base_of[slot] + m_rank[l];
+            m_inv[l] = dst;
+            double X[3], t[3], o[3];
+            int b[3];
+            for (int a = 0; a < 3; ++a) {
+                o[a] = body[(size_t)a * nm + l];
+                X[a] = xc[a] + o[a];
             }
-            pending &= ~m;
+            marker_geometry<W>(g, X, b, t);
+            typename V4<T>::type tn, ud;
+            tn.x = (T)t[0];
+            tn.y = (T)t[1];
+            tn.z = (T)t[2];
+            tn.w = V4<T>::from_bits(pack_node(g, b[0], b[1], b[2]));
+            // rigid-body velocity at the marker, U^d = u_p + omega_p x o (FP64)
+            ud.x = (T)(upp[0] + (wpp[1] * o[2] - wpp[2] * o[1]));
+            ud.y = (T)(upp[1] + (wpp[2] * o[0] - wpp[0] * o[2]));
+            ud.z = (T)(upp[2] + (wpp[0] * o[1] - wpp[1] * o[0]));
+            ud.w = (T)dVp;
+            rec_tn[dst] = tn;
+            rec_ud[dst] = ud;
+            rec_src[dst] = l;
+            const T tt[3] = {tn.x, tn.y, tn.z};
+            ntg = halo_tiles<T, W>(g, tc, b, tt, tgt);
         }
+        halo_register<true>(tgt, ntg, dst, halo_cursor, halo_start, halo_list, halo_cap, err);
     }
-    if (!EMIT)
-        slot_add(count + 2 * IBMX_RSLOTS, block_sum<long long>(entries));
 }
 
 // ---------------------------------------------------------------------------
@@ -1378,7 +1390,6 @@ void bin_markers(ibmx_plan p, const double *xp, const double *up, const double *
     const int nm = p->nm, np = p->np;
     const TileC tc = p->tc;
     const int ntiles = tc.ntiles;
-    const int *n_act = p->tile_start + ntiles;   // total after the scan
     T4 *rec_tn = (T4 *)p->rec_tn, *rec_ud = (T4 *)p->rec_ud;
     {
         ProfScope ps(p, IBMX_K_OTHER);
@@ -1392,23 +1403,18 @@ void bin_markers(ibmx_plan p, const double *xp, const double *up, const double *
     if (np > 0 && nm > 0) {
         ProfScope ps(p, IBMX_K_GEOMETRY);
         const int gb = nblocks(np, 4);
-        hipLaunchKernelGGL((k_bin_count<W>), dim3(gb), dim3(256), 0, s, p->g, tc, np, nm, p->d_moff,
-                           p->body, xp, mask, p->m_key, p->m_rank, p->bin_tab, p->tile_count,
-                           p->d_err, p->d_count);
-        ibmx_exclusive_scan(p->tile_count, p->tile_start, ntiles, s);
+        hipLaunchKernelGGL((k_bin_count<T, W>), dim3(gb), dim3(256), 0, s, p->g, tc, np, nm,
+                           p->d_moff, p->body, xp, mask, p->m_key, p->m_rank, p->bin_tab,
+                           p->tile_count, p->halo_count, p->d_err, p->d_count);
+        ibmx_exclusive_scan(p->tile_count, p->tile_start, ntiles, p->scan_aux, s);
+        ibmx_exclusive_scan(p->halo_count, p->halo_start, ntiles, p->scan_aux, s);
         hipLaunchKernelGGL((k_bin_scatter<T, W>), dim3(gb), dim3(256), 0, s, p->g, np, nm,
                            p->d_moff, p->body, xp, up, wp, p->dV, p->m_key, p->m_rank, p->bin_tab,
-                           p->tile_start, p->tile_cursor, rec_tn, rec_ud, p->rec_src, p->m_inv);
-        hipLaunchKernelGGL((k_halo<T, W, false>), dim3(nblocks(nm, 256)), dim3(256), 0, s, p->g,
-                           tc, n_act, (const T4 *)rec_tn, p->halo_count, (const int *)nullptr,
-                           (int *)nullptr, (int *)nullptr, p->halo_cap, p->d_count, p->d_err);
-        ibmx_exclusive_scan(p->halo_count, p->halo_start, ntiles, s);
-        hipLaunchKernelGGL((k_halo<T, W, true>), dim3(nblocks(nm, 256)), dim3(256), 0, s, p->g,
-                           tc, n_act, (const T4 *)rec_tn, p->halo_count, p->halo_start,
-                           p->halo_cursor, p->halo_list, p->halo_cap, p->d_count, p->d_err);
+                           p->tile_start, p->tile_cursor, rec_tn, rec_ud, p->rec_src, p->m_inv,
+                           tc, p->halo_start, p->halo_cursor, p->halo_list, p->halo_cap, p->d_err);
     } else {
-        ibmx_exclusive_scan(p->tile_count, p->tile_start, ntiles, s);
-        ibmx_exclusive_scan(p->halo_count, p->halo_start, ntiles, s);
+        ibmx_exclusive_scan(p->tile_count, p->tile_start, ntiles, p->scan_aux, s);
+        ibmx_exclusive_scan(p->halo_count, p->halo_start, ntiles, p->scan_aux, s);
     }
 }
 

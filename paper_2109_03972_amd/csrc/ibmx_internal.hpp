@@ -80,6 +80,8 @@ struct ibmx_plan_s {
     int *halo_start;      // [ntiles + 1]
     int *halo_cursor;     // [ntiles]
     int *halo_list;       // [halo_cap]
+    int *scan_aux;        // exclusive-scan workspace (ibmx_scan_aux_size ints)
+    long long scan_cap;   // elements the workspace serves
     float4 *tile_gmax;    // [2][ntiles] largest |G| of the pass and |pass sum|
                           // over each tile's own markers (FP32 spreading scale)
     long long halo_cap;
@@ -152,7 +154,11 @@ ibmx_status ibmx_launch_check();
 ibmx_status ibmx_plan_alloc_tiles(ibmx_plan p, int tx, int ty, int tz);
 ibmx_status ibmx_spread_allow_lds(ibmx_plan p);
 void ibmx_plan_drop_graph(ibmx_plan p);
-void ibmx_exclusive_scan(const int *in, int *out, int n, hipStream_t s);
+ibmx_status ibmx_plan_scan_reserve(ibmx_plan p, long long n);
+// exclusive scan of n ints, out[n] = total; aux holds ibmx_scan_aux_size(n)
+// ints of workspace
+int ibmx_scan_aux_size(long long n);
+void ibmx_exclusive_scan(const int *in, int *out, int n, int *aux, hipStream_t s);
 void ibmx_fill_i32(int *p, int v, long long n, hipStream_t s);
 void ibmx_fill_f64(double *p, double v, long long n, hipStream_t s);
 void ibmx_fill_u8(uint8_t *p, uint8_t v, long long n, hipStream_t s);

@@ -136,14 +136,20 @@ __global__ void k_cell_sort(int ncell, const int *start, int *cellp)
 }
 
 // ---------------------------------------------------------------------------
-// pair search over the neighbouring cells (deduplicated when nc < 3)
+// pair search over the neighbouring cells (deduplicated when nc < 3), one
+// wave per particle i: the candidates of the (up to 27) cells are numbered
+// 0 .. total-1 through a wave prefix sum of the cell sizes and dealt to the
+// lanes; hits j > i are counted (EMIT = false) or written in candidate order
+// to the scratch half of pairs_out, then sorted and completed by lane 0.
 // ---------------------------------------------------------------------------
 template <bool EMIT>
-__global__ void k_pairs(PairC P, int np, const double *xp, const double *radius,
-                        const int *cell_start, const int *cellp, int *count, const int *off,
-                        int cap, int *pairs_out, double *gap_out)
+__global__ __launch_bounds__(256) void k_pairs(PairC P, int np, const double *xp,
+                                               const double *radius, const int *cell_start,
+                                               const int *cellp, int *count, const int *off,
+                                               int cap, int *pairs_out, double *gap_out)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & (IBMX_WAVE - 1);
+    const int i = blockIdx.x * (blockDim.x / IBMX_WAVE) + threadIdx.x / IBMX_WAVE;
     if (i >= np)
         return;
     double xi[3];
@@ -167,36 +173,67 @@ __global__ void k_pairs(PairC P, int np, const double *xp, const double *radius,
                 offs[a][noff[a]++] = v;
         }
     }
+    const int ncells = noff[0] * noff[1] * noff[2];
+    // lane k < ncells holds cell k's range and the number of candidates before it
+    int c_first = 0, c_len = 0;
+    if (lane < ncells) {
+        const int kx = lane % noff[0], ky = (lane / noff[0]) % noff[1], kz = lane / (noff[0] * noff[1]);
+        const int c = offs[0][kx] + P.nc[0] * (offs[1][ky] + P.nc[1] * offs[2][kz]);
+        c_first = cell_start[c];
+        c_len = cell_start[c + 1] - c_first;
+    }
+    int c_pre = c_len;   // inclusive wave scan
+    for (int d = 1; d < IBMX_WAVE; d <<= 1) {
+        const int v = __shfl_up(c_pre, d, IBMX_WAVE);
+        if (lane >= d)
+            c_pre += v;
+    }
+    const int total = __shfl(c_pre, IBMX_WAVE - 1, IBMX_WAVE);
+    c_pre -= c_len;   // exclusive
     const double Ri = radius[i];
-    int cnt = 0;
     const int base = EMIT ? off[i] : 0;
-    for (int kz = 0; kz < noff[2]; ++kz)
-        for (int ky = 0; ky < noff[1]; ++ky)
-            for (int kx = 0; kx < noff[0]; ++kx) {
-                int c = offs[0][kx] + P.nc[0] * (offs[1][ky] + P.nc[1] * offs[2][kz]);
-                for (int q = cell_start[c]; q < cell_start[c + 1]; ++q) {
-                    int j = cellp[q];
-                    if (j <= i)
-                        continue;
-                    double xj[3], d[3];
-                    centre(P, np, xp, j, xj);
-                    double d2 = disp2(P, xi, xj, d);
-                    double cut = Ri + radius[j];
-                    cut = cut + P.gap_cut;
-                    if (d2 < cut * cut) {
-                        if (EMIT && base + cnt < cap)
-                            pairs_out[cap + base + cnt] = j;   // partner ids, sorted below
-                        ++cnt;
-                    }
-                }
+    int cnt = 0;
+    for (int t0 = 0; t0 < total; t0 += IBMX_WAVE) {
+        const int t = t0 + lane;
+        // the cell k holding candidate t: the last k with c_pre[k] <= t
+        int first = 0, pre = 0;
+        for (int k = 0; k < ncells; ++k) {
+            const int pk = __shfl(c_pre, k, IBMX_WAVE);
+            const int fk = __shfl(c_first, k, IBMX_WAVE);
+            if (pk <= t) {
+                pre = pk;
+                first = fk;
             }
+        }
+        bool hit = false;
+        int j = -1;
+        if (t < total) {
+            j = cellp[first + (t - pre)];
+            if (j > i) {
+                double xj[3], d[3];
+                centre(P, np, xp, j, xj);
+                const double d2 = disp2(P, xi, xj, d);
+                double cut = Ri + radius[j];
+                cut = cut + P.gap_cut;
+                hit = d2 < cut * cut;
+            }
+        }
+        const unsigned long long m = __ballot(hit);
+        if (EMIT && hit) {
+            const int pos = cnt + __popcll(m & ((1ULL << lane) - 1ULL));
+            if (base + pos < cap)
+                pairs_out[cap + base + pos] = j;   // partner ids, sorted below
+        }
+        cnt += __popcll(m);
+    }
     if (!EMIT) {
-        count[i] = cnt;
+        if (lane == 0)
+            count[i] = cnt;
         return;
     }
     // sort the partners of i, then write i and the gaps in that order
-    int n = min(cnt, cap - base);
-    if (n <= 0)
+    const int n = min(cnt, cap - base);
+    if (n <= 0 || lane != 0)
         return;
     sort_segment(pairs_out + cap + base, n);
     for (int k = 0; k < n; ++k) {
@@ -432,13 +469,18 @@ __device__ __forceinline__ unsigned long long splitmix64(unsigned long long x)
     return z ^ (z >> 31);
 }
 
-__global__ void k_mask_pairs(PairC P, int np, int nm, const int *moff, const double *body,
-                             const double *xp, const double *radius, int mode,
-                             unsigned long long seed, const int *counts, int cap, const int *pairs,
-                             const double *gap, uint8_t *mask)
+// one wave per pair (wall entry); lanes take the chosen particle's markers
+__global__ __launch_bounds__(256) void k_mask_pairs(PairC P, int np, int nm, const int *moff,
+                                                    const double *body, const double *xp,
+                                                    const double *radius, int mode,
+                                                    unsigned long long seed, const int *counts,
+                                                    int cap, const int *pairs, const double *gap,
+                                                    uint8_t *mask)
 {
     const int npairs = min(counts[0], cap);
-    for (int k = blockIdx.x; k < npairs; k += gridDim.x) {
+    const int lane = threadIdx.x & (IBMX_WAVE - 1);
+    const int wpb = blockDim.x / IBMX_WAVE;
+    for (int k = blockIdx.x * wpb + threadIdx.x / IBMX_WAVE; k < npairs; k += gridDim.x * wpb) {
         if (!(gap[k] < 2.0 * P.eps_sep))
             continue;
         int p = pairs[k], q = pairs[cap + k];
@@ -451,7 +493,7 @@ __global__ void k_mask_pairs(PairC P, int np, int nm, const int *moff, const dou
         centre(P, np, xp, partner, xq);
         double lim = radius[partner] + 2.0 * P.eps_sep;
         double lim2 = lim * lim;
-        for (int l = moff[chosen] + threadIdx.x; l < moff[chosen + 1]; l += blockDim.x) {
+        for (int l = moff[chosen] + lane; l < moff[chosen + 1]; l += IBMX_WAVE) {
             if (mode == 2) {
                 mask[l] = 0;
                 continue;
@@ -471,18 +513,21 @@ __global__ void k_mask_pairs(PairC P, int np, int nm, const int *moff, const dou
     }
 }
 
-__global__ void k_mask_walls(PairC P, int np, int nm, const int *moff, const double *body,
-                             const double *xp, int mode, const int *counts, int cap,
-                             const int *walls, const double *wgap, uint8_t *mask)
+__global__ __launch_bounds__(256) void k_mask_walls(PairC P, int np, int nm, const int *moff,
+                                                    const double *body, const double *xp, int mode,
+                                                    const int *counts, int cap, const int *walls,
+                                                    const double *wgap, uint8_t *mask)
 {
     const int nwall = min(counts[1], cap);
-    for (int k = blockIdx.x; k < nwall; k += gridDim.x) {
+    const int lane = threadIdx.x & (IBMX_WAVE - 1);
+    const int wpb = blockDim.x / IBMX_WAVE;
+    for (int k = blockIdx.x * wpb + threadIdx.x / IBMX_WAVE; k < nwall; k += gridDim.x * wpb) {
         if (!(wgap[k] < P.eps_sep))
             continue;
         int p = walls[k], side = walls[cap + k];
         int ax = side / 2, upper = side % 2;
         double top = P.origin[ax] + P.L[ax];
-        for (int l = moff[p] + threadIdx.x; l < moff[p + 1]; l += blockDim.x) {
+        for (int l = moff[p] + lane; l < moff[p + 1]; l += IBMX_WAVE) {
             if (mode == 2) {
                 mask[l] = 0;
                 continue;
@@ -560,6 +605,8 @@ extern "C" ibmx_status ibmx_pairs(ibmx_plan p, const double *xp, const double *r
             return IBMX_ENOMEM;
         p->p_cell_cap = (int)ncell;
     }
+    if (ibmx_plan_scan_reserve(p, ncell) != IBMX_OK)
+        return IBMX_ENOMEM;
     hipStream_t s = p->stream;
     ProfScope ps(p, IBMX_K_PAIRS);
     // cell list
@@ -568,23 +615,23 @@ extern "C" ibmx_status ibmx_pairs(ibmx_plan p, const double *xp, const double *r
     if (np > 0)
         hipLaunchKernelGGL(k_cell_count, dim3(blocks(np)), dim3(256), 0, s, P, np, xp, radius,
                            rmax, p->p_cell_of, cell_start, p->d_err);
-    ibmx_exclusive_scan(cell_start, cell_start, (int)ncell, s);
+    ibmx_exclusive_scan(cell_start, cell_start, (int)ncell, p->scan_aux, s);
     if (np > 0) {
         hipLaunchKernelGGL(k_cell_scatter, dim3(blocks(np)), dim3(256), 0, s, np, p->p_cell_of,
                            cell_start, p->p_cursor, cell_particles);
         hipLaunchKernelGGL(k_cell_sort, dim3(blocks(ncell)), dim3(256), 0, s, (int)ncell,
                            cell_start, cell_particles);
         // pair and wall lists
-        hipLaunchKernelGGL(k_pairs<false>, dim3(blocks(np)), dim3(256), 0, s, P, np, xp, radius,
+        hipLaunchKernelGGL(k_pairs<false>, dim3(blocks(np, 4)), dim3(256), 0, s, P, np, xp, radius,
                            cell_start, cell_particles, p->p_count, (const int *)nullptr, 0,
                            (int *)nullptr, (double *)nullptr);
         hipLaunchKernelGGL(k_walls<false>, dim3(blocks(np)), dim3(256), 0, s, P, np, xp, radius,
                            p->p_wcount, (const int *)nullptr, 0, (int *)nullptr, (double *)nullptr);
     }
-    ibmx_exclusive_scan(p->p_count, p->p_off, np, s);
-    ibmx_exclusive_scan(p->p_wcount, p->p_woff, np, s);
+    ibmx_exclusive_scan(p->p_count, p->p_off, np, p->scan_aux, s);
+    ibmx_exclusive_scan(p->p_wcount, p->p_woff, np, p->scan_aux, s);
     if (np > 0) {
-        hipLaunchKernelGGL(k_pairs<true>, dim3(blocks(np)), dim3(256), 0, s, P, np, xp, radius,
+        hipLaunchKernelGGL(k_pairs<true>, dim3(blocks(np, 4)), dim3(256), 0, s, P, np, xp, radius,
                            cell_start, cell_particles, p->p_count, p->p_off, pair_cap, pairs_out,
                            pair_gap);
         hipLaunchKernelGGL(k_walls<true>, dim3(blocks(np)), dim3(256), 0, s, P, np, xp, radius,
@@ -608,12 +655,14 @@ extern "C" ibmx_status ibmx_pairs(ibmx_plan p, const double *xp, const double *r
         ibmx_fill_u8(marker_active, 1, nm, s);
         if (prm.disable_mode != 0) {
             if (pair_cap > 0)
-                hipLaunchKernelGGL(k_mask_pairs, dim3(min(pair_cap, 2048)), dim3(256), 0, s, P, np, nm,
+                hipLaunchKernelGGL(k_mask_pairs, dim3(min(blocks(pair_cap, 4), 8192)), dim3(256), 0, s,
+                                   P, np, nm,
                                    p->d_moff, p->body, xp, radius, prm.disable_mode,
                                    (unsigned long long)prm.disable_seed, counts_out, pair_cap,
                                    pairs_out, pair_gap, marker_active);
             if (wall_cap > 0)
-                hipLaunchKernelGGL(k_mask_walls, dim3(min(wall_cap, 2048)), dim3(256), 0, s, P, np, nm,
+                hipLaunchKernelGGL(k_mask_walls, dim3(min(blocks(wall_cap, 4), 8192)), dim3(256), 0, s,
+                                   P, np, nm,
                                    p->d_moff, p->body, xp, prm.disable_mode, counts_out, wall_cap,
                                    walls_out, wall_gap, marker_active);
         }

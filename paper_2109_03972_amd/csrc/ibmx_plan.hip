@@ -23,7 +23,7 @@ void free_plan(ibmx_plan p)
                     p->rec_tn,      p->rec_ud,      p->rec_src,      p->rec_Gp,    p->rec_G,
                     p->m_key,       p->m_inv,       p->m_rank,       p->tile_count, p->tile_start,
                     p->tile_cursor, p->halo_count,  p->halo_start,   p->halo_cursor,
-                    p->halo_list,   p->tile_gmax,   p->bw_u,         p->p_cell_of, p->p_cursor,
+                    p->halo_list,   p->tile_gmax,   p->scan_aux,     p->bw_u,         p->p_cell_of, p->p_cursor,
                     p->p_count,     p->p_off,       p->p_wcount,     p->p_woff,    p->bin_tab};
     for (void *q : ptrs)
         if (q)
@@ -193,7 +193,9 @@ ibmx_status check_params(const ibmx_grid *g, const ibmx_params *prm)
     p->block = 256;
     p->stats.n_markers = nm;
     // default tiles: 16 x 16 x 8 nodes
-    st = ibmx_plan_alloc_tiles(p, 16, 16, 8);
+    st = ibmx_plan_scan_reserve(p, np);
+    if (st == IBMX_OK)
+        st = ibmx_plan_alloc_tiles(p, 16, 16, 8);
     if (st != IBMX_OK) {
         free_plan(p);
         return st;
@@ -284,7 +286,24 @@ ibmx_status ibmx_plan_alloc_tiles(ibmx_plan p, int tx, int ty, int tz)
     p->tc.ntiles = (int)ntiles;
     p->stats.tiles = ntiles;
     ibmx_plan_drop_graph(p);
+    if (ibmx_plan_scan_reserve(p, ntiles) != IBMX_OK)
+        return IBMX_ENOMEM;
     return ibmx_spread_allow_lds(p);
+}
+
+// Grow the scan workspace to serve scans of up to n elements.
+ibmx_status ibmx_plan_scan_reserve(ibmx_plan p, long long n)
+{
+    if (p->scan_aux && p->scan_cap >= n)
+        return IBMX_OK;
+    if (p->scan_aux)
+        (void)hipFree(p->scan_aux);
+    p->scan_aux = nullptr;
+    p->scan_cap = 0;
+    if (hipMalloc((void **)&p->scan_aux, sizeof(int) * (size_t)ibmx_scan_aux_size(n)) != hipSuccess)
+        return IBMX_ENOMEM;
+    p->scan_cap = n;
+    return IBMX_OK;
 }
 
 extern "C" ibmx_status ibmx_plan_destroy(ibmx_plan p)
