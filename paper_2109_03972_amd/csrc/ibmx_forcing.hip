@@ -221,7 +221,7 @@ struct TileWalk {
     }
 };
 
-constexpr int UNR = 4;    // row groups per write-out step
+constexpr int UNR = 2;    // row groups per write-out step
 constexpr int SUNR = 16;  // row groups per staging step
 
 // ---------------------------------------------------------------------------
