@@ -485,6 +485,38 @@ __device__ __forceinline__ V block_max(V v)
     return r;   // valid in every thread
 }
 
+// LDS layout of a staged region of RV nodes: (x, y) pairs of every node,
+// then the z components, so that a node is read with two LDS loads
+template <typename T>
+struct V2;
+template <>
+struct V2<float> {
+    typedef float2 type;
+};
+template <>
+struct V2<double> {
+    typedef double2 type;
+};
+
+template <typename T>
+__device__ __forceinline__ void reg_put(T *reg, int RV, int idx, T x, T y, T z)
+{
+    typename V2<T>::type xy;
+    xy.x = x;
+    xy.y = y;
+    reinterpret_cast<typename V2<T>::type *>(reg)[idx] = xy;
+    reg[2 * RV + idx] = z;
+}
+
+template <typename T>
+__device__ __forceinline__ void reg_get(const T *reg, int RV, int idx, T &x, T &y, T &z)
+{
+    const typename V2<T>::type xy = reinterpret_cast<const typename V2<T>::type *>(reg)[idx];
+    x = xy.x;
+    y = xy.y;
+    z = reg[2 * RV + idx];
+}
+
 // Stage v = scale * src (+ src2) over the tile's support region
 // [o - 1, o + B + W - 2) per axis into LDS (nodes beyond a wall read 0),
 // element by element: each wave loads 64 / R0 rows of R0 nodes per step, and
@@ -543,9 +575,7 @@ __device__ __forceinline__ void stage_region_rows(const GridC &g, const TileC &t
         for (int q = 0; q < SUNR; ++q) {
             if (li[q] < 0)
                 continue;
-            reg[li[q]] = v[q][0];
-            reg[RV + li[q]] = v[q][1];
-            reg[2 * RV + li[q]] = v[q][2];
+            reg_put<T>(reg, RV, li[q], v[q][0], v[q][1], v[q][2]);
         }
     }
 }
@@ -653,9 +683,7 @@ __device__ __forceinline__ void stage_region_vec(const GridC &g, const TileC &tc
                 const int lx = x + k - xs;
                 if (lx < 0 || lx >= R0)
                     continue;
-                reg[rb[q] + lx] = v[q][0].e[k];
-                reg[RV + rb[q] + lx] = v[q][1].e[k];
-                reg[2 * RV + rb[q] + lx] = v[q][2].e[k];
+                reg_put<T>(reg, RV, rb[q] + lx, v[q][0].e[k], v[q][1].e[k], v[q][2].e[k]);
             }
         }
     }
@@ -790,9 +818,11 @@ __global__ __launch_bounds__(256) void k_interp(
 #pragma unroll
                 for (int i = 0; i < W; ++i) {
                     const T ww = wzy * w[0][i];
-                    U[0] += ww * reg[row + i];
-                    U[1] += ww * reg[RV + row + i];
-                    U[2] += ww * reg[2 * RV + row + i];
+                    T vx, vy, vz;
+                    reg_get<T>(reg, RV, row + i, vx, vy, vz);
+                    U[0] += ww * vx;
+                    U[1] += ww * vy;
+                    U[2] += ww * vz;
                 }
             }
         T G[3];
@@ -1160,9 +1190,11 @@ __global__ __launch_bounds__(256) void k_interp_jac(
                     const T dx = w[2][k] * w[1][jj] * dw[0][i];
                     const T dy = w[2][k] * dw[1][jj] * w[0][i];
                     const T dz = dw[2][k] * w[1][jj] * w[0][i];
+                    T vv[3];
+                    reg_get<T>(reg, RV, row + i, vv[0], vv[1], vv[2]);
 #pragma unroll
                     for (int cc = 0; cc < 3; ++cc) {
-                        const T v = reg[cc * RV + row + i];
+                        const T v = vv[cc];
                         U[cc] += ww * v;
                         J[cc][0] += dx * v;
                         J[cc][1] += dy * v;
@@ -1243,7 +1275,8 @@ __global__ __launch_bounds__(256) void k_interp_adj(
 #pragma unroll
                 for (int i = 0; i < W; ++i) {
                     const T ww = w[2][k] * w[1][jj] * w[0][i];
-                    const T f0 = reg[row + i], f1 = reg[RV + row + i], f2 = reg[2 * RV + row + i];
+                    T f0, f1, f2;
+                    reg_get<T>(reg, RV, row + i, f0, f1, f2);
                     IF[0] += ww * f0;
                     IF[1] += ww * f1;
                     IF[2] += ww * f2;
