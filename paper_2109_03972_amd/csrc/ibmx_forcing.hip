@@ -255,14 +255,9 @@ __device__ __forceinline__ int halo_tiles(const GridC &g, const TileC &tc, const
     return ntg;
 }
 
-// Wave-aggregated halo registration of every lane's tiles: the count pass
-// adds to ctr[tile]; the emit pass reserves positions with ctr = cursor and
-// writes the lane's record index j into the tile's halo list.
-template <bool EMIT>
-__device__ __forceinline__ void halo_register(const int *tgt, int ntg, int j, int *ctr,
-                                              const int *__restrict__ halo_start,
-                                              int *__restrict__ halo_list, long long cap,
-                                              int *__restrict__ err)
+// Wave-aggregated halo counting: adds every lane's halo tiles to count[tile]
+// (one atomic per distinct tile and round, results unused).
+__device__ __forceinline__ void halo_count_wave(const int *tgt, int ntg, int *__restrict__ count)
 {
     const int lane = threadIdx.x & (IBMX_WAVE - 1);
     for (int k = 0; k < 7; ++k) {
@@ -272,22 +267,61 @@ __device__ __forceinline__ void halo_register(const int *tgt, int ntg, int j, in
             const int leader = __ffsll((long long)pending) - 1;
             const int kk = __shfl(key, leader, IBMX_WAVE);
             const unsigned long long m = __ballot(key == kk) & pending;
-            int base = 0;
             if (lane == leader)
-                base = atomicAdd(&ctr[kk], __popcll(m));
-            if (EMIT) {
-                base = __shfl(base, leader, IBMX_WAVE);
-                if (key == kk) {
-                    const long long pos =
-                        (long long)halo_start[kk] + base + __popcll(m & lanemask_lt(lane));
-                    if (pos < cap)
-                        halo_list[pos] = j;
-                    else
-                        atomicCAS(err, 0, (int)IBMX_ECAPACITY);
-                }
-            }
+                atomicAdd(&count[kk], __popcll(m));
             pending &= ~m;
         }
+    }
+}
+
+// Halo emission of a wave's records: the lanes' (round, tile) groups are
+// collected in the wave's LDS lists first, then every group reserves its
+// positions with one atomic on cursor[tile] -- all groups at once, so the
+// atomics' round trips overlap -- and the lanes write their record index j.
+constexpr int HGROUPS = 7 * IBMX_WAVE;
+__device__ __forceinline__ void halo_emit_wave(const int *tgt, int ntg, int j,
+                                               int *__restrict__ cursor,
+                                               const int *__restrict__ halo_start,
+                                               int *__restrict__ halo_list, long long cap,
+                                               int *__restrict__ err, volatile int *g_key,
+                                               volatile int *g_pos)
+{
+    const int lane = threadIdx.x & (IBMX_WAVE - 1);
+    int grp[7], rank[7];
+    int ng = 0;
+    for (int k = 0; k < 7; ++k) {
+        const int key = k < ntg ? tgt[k] : -1;
+        grp[k] = -1;
+        rank[k] = 0;
+        unsigned long long pending = __ballot(key >= 0);
+        while (pending) {
+            const int leader = __ffsll((long long)pending) - 1;
+            const int kk = __shfl(key, leader, IBMX_WAVE);
+            const unsigned long long m = __ballot(key == kk) & pending;
+            if (key == kk) {
+                grp[k] = ng;
+                rank[k] = __popcll(m & lanemask_lt(lane));
+            }
+            if (lane == leader) {
+                g_key[ng] = kk;
+                g_pos[ng] = __popcll(m);
+            }
+            ++ng;
+            pending &= ~m;
+        }
+    }
+    for (int q = lane; q < ng; q += IBMX_WAVE) {
+        const int key = g_key[q];
+        g_pos[q] = halo_start[key] + atomicAdd(&cursor[key], g_pos[q]);
+    }
+    for (int k = 0; k < 7; ++k) {
+        if (grp[k] < 0)
+            continue;
+        const long long pos = (long long)g_pos[grp[k]] + rank[k];
+        if (pos < cap)
+            halo_list[pos] = j;
+        else
+            atomicCAS(err, 0, (int)IBMX_ECAPACITY);
     }
 }
 
@@ -338,7 +372,7 @@ __global__ __launch_bounds__(256) void k_bin_count(
         }
         active += key >= 0;
         entries += ntg;
-        halo_register<false>(tgt, ntg, 0, halo_count, nullptr, nullptr, 0, nullptr);
+        halo_count_wave(tgt, ntg, halo_count);
         unsigned long long pending = __ballot(key >= 0);
         while (pending) {
             const int leader = __ffsll((long long)pending) - 1;
@@ -396,6 +430,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter(
     long long halo_cap, int *__restrict__ err)
 {
     __shared__ int s_base[4][TS];
+    __shared__ int s_gkey[4][HGROUPS], s_gpos[4][HGROUPS];
     const int wv = threadIdx.x / IBMX_WAVE, lane = threadIdx.x & (IBMX_WAVE - 1);
     const int p = blockIdx.x * 4 + wv;
     if (p >= np)
@@ -444,7 +479,8 @@ __global__ __launch_bounds__(256) void k_bin_scatter(
             const T tt[3] = {tn.x, tn.y, tn.z};
             ntg = halo_tiles<T, W>(g, tc, b, tt, tgt);
         }
-        halo_register<true>(tgt, ntg, dst, halo_cursor, halo_start, halo_list, halo_cap, err);
+        halo_emit_wave(tgt, ntg, dst, halo_cursor, halo_start, halo_list, halo_cap, err,
+                       s_gkey[wv], s_gpos[wv]);
     }
 }
 
