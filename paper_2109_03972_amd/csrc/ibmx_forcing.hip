@@ -1011,6 +1011,14 @@ __global__ __launch_bounds__(256) void k_spread(GridC g, TileC tc, T c, int add_
         return;
     const TileBox box(g, tc, tile);
     const int V = tc.B[0] * tc.B[1] * tc.B[2];
+    // first record of this thread, in flight during the set-up
+    T4 ptn = {}, pgv = {};
+    if ((int)threadIdx.x < n_tot) {
+        const int e = threadIdx.x;
+        const int j = e < n_own ? a0 + e : halo_list[h0 + e - n_own];
+        ptn = rec_tn[j];
+        pgv = rec_G[j];
+    }
     T scale[3] = {T(1), T(1), T(1)}, unscale[3] = {T(1), T(1), T(1)};
     for (int i = threadIdx.x; i < 3 * V; i += blockDim.x)
         acc[i] = A(0);
@@ -1074,8 +1082,13 @@ __global__ __launch_bounds__(256) void k_spread(GridC g, TileC tc, T c, int add_
     }
     __syncthreads();
     for (int e = threadIdx.x; e < n_tot; e += blockDim.x) {
-        const int j = e < n_own ? a0 + e : halo_list[h0 + e - n_own];
-        const T4 tn = rec_tn[j], gv = rec_G[j];
+        const T4 tn = ptn, gv = pgv;
+        if (e + (int)blockDim.x < n_tot) {
+            const int en = e + blockDim.x;
+            const int jn = en < n_own ? a0 + en : halo_list[h0 + en - n_own];
+            ptn = rec_tn[jn];
+            pgv = rec_G[jn];
+        }
         const T tt[3] = {tn.x, tn.y, tn.z};
         const T Gs[3] = {gv.x * scale[0], gv.y * scale[1], gv.z * scale[2]};
         int ix[3][W];
