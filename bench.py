@@ -36,13 +36,14 @@ def log(*a):
 def algorithmic_bytes(kind: str, s: int, n_act: int, shell: int, n_iter: int = 2) -> float:
     """Bytes a kernel must move per launch (s = bytes of the grid type).
 
-    Marker record: packed base node and particle id (8 B), fractions and body
-    offset (6s).  Shell = distinct grid nodes in the delta support of the
-    active markers; every access below touches each of them once.
+    Marker records: packed base node and fractions (4 + 3s), rigid-body
+    velocity and volume (4s).  Shell = distinct grid nodes in the delta
+    support of the active markers; every access below touches each of them
+    once.
 
-    interp (one pass): record, write of the pass amplitude G (3s) and
-           read-modify-write of its sum over passes (6s); per shell node one
-           read of the three velocity components (3s).
+    interp (one pass): records (4 + 7s), write of the pass amplitude G (3s)
+           and read-modify-write of its sum over passes (6s); per shell node
+           one read of the three velocity components (3s).
     spread (one pass): packed node and fractions (4 B + 3s) and G (3s); per
            shell node a read-modify-write of u (6s), and of f_tot as well
            (6s more) when the call has a single pass.
@@ -50,7 +51,7 @@ def algorithmic_bytes(kind: str, s: int, n_act: int, shell: int, n_iter: int = 2
            summed G (4 B + 6s); per shell node a read-modify-write of f_tot.
     """
     if kind == "interp":
-        return n_act * (8 + 15 * s) + shell * 3 * s
+        return n_act * (4 + 16 * s) + shell * 3 * s
     if kind == "spread":
         return n_act * (4 + 6 * s) + shell * (6 * s if n_iter > 1 else 12 * s)
     if kind == "ftot":
