@@ -172,6 +172,27 @@ def run_gpu(case, precision, steps, warmup, profile=True, tune=True, tile=None):
     return out
 
 
+def copy_bandwidth(torch, gib: float = 2.0, reps: int = 5) -> float:
+    """Achievable HBM bandwidth for reference: a device-to-device copy of a
+    2 GiB buffer, (read + written bytes) / time, best of a few."""
+    n = int(gib * (1 << 30)) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = float("inf")
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        torch.cuda.synchronize()
+        best = min(best, a.elapsed_time(b) * 1e-3)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * n * 4 / best / 1e9
+
+
 def cpu_baseline(case, mask_np):
     """Oracle (plain FP64, single thread) timed on one forcing pass over all
     markers of the workload on its full grid."""
@@ -223,6 +244,8 @@ def main():
         torch.cuda.synchronize()
         log("bench: copied 1 GiB device-to-device (counter calibration)")
         del src, dst
+    copy_gbs = copy_bandwidth(torch)
+    log(f"bench: device copy {copy_gbs:.0f} GB/s (read + write)")
     log(f"bench: generating {args.workload}")
     case = synth.make_case(args.workload, lazy_field=True)
     log(f"bench: {case.np_} particles, {case.nm} markers, grid {case.n}")
@@ -243,7 +266,8 @@ def main():
     traffic = measured_traffic(args.workload, dom, r32["tile"])
     roof = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
                 unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                bytes_per_launch=bytes_launch, ms_per_launch=per_launch[dom])
+                bytes_per_launch=bytes_launch, ms_per_launch=per_launch[dom],
+                copy_GBs=round(copy_gbs, 1))
     if traffic is not None:
         roof["traffic_GBs"] = round(traffic / (per_launch[dom] * 1e-3) / 1e9, 1)
     log(f"bench: FP32 {r32['ms_per_step']:.3f} ms/step, {value:.3e} marker-updates/s")

@@ -300,7 +300,7 @@ IBMX_API ibmx_status ibmx_forcing_graph(ibmx_plan plan, void *u, void *f_tot,
  * Autotune the tile shape of the forcing passes on the given inputs: runs
  * ibmx_forcing with each candidate shape that fits the LDS (edges 4..32,
  * x-edge <= 32), times it with HIP events on the plan's stream and keeps the
- * fastest in the plan.  Candidates that raise a deferred error are skipped.
+ * fastest in the plan (a candidate must beat the earlier ones by 2%).  Candidates that raise a deferred error are skipped.
  * u and f_tot are restored after every trial, so the call leaves them
  * unchanged.  Allocates and frees its own scratch (copies of u and f_tot)
  * and synchronises the stream; not capturable.  The choice is reported by

@@ -177,7 +177,9 @@ extern "C" ibmx_status ibmx_tune(ibmx_plan p, void *u, void *f_tot, const double
         }
         if (st != IBMX_OK)
             break;
-        if (ok && t_min < best_ms) {
+        // a later candidate must win by 2% (timing noise keeps the earlier,
+        // larger shapes)
+        if (ok && t_min < 0.98f * best_ms) {
             best_ms = t_min;
             for (int a = 0; a < 3; ++a)
                 best[a] = cand[a];
