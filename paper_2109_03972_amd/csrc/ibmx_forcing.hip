@@ -760,7 +760,7 @@ __device__ __forceinline__ void region_base(const GridC &g, const TileBox &box, 
 // that their latency overlaps it.
 // MODE 0: first pass (writes the amplitude G and its pass sum), 1: later
 // pass (adds G to the pass sum), 2: residual only.
-// tile_max (FP32 passes, may be null): per tile, the largest |G| of the
+// tile_max (may be null): per tile, the largest |G| of the
 // pass and the largest |pass sum| over its own markers, as float4
 // [2][ntiles]; the spreading derives its fixed-point scale from them.
 // ---------------------------------------------------------------------------
@@ -949,36 +949,91 @@ __global__ __launch_bounds__(256) void k_particle_sums(int np, int nm, double h3
 }
 
 // ---------------------------------------------------------------------------
-// LDS accumulation of the spread.  On gfx950 an LDS float add costs about
-// 195 cycles per wave instruction, an FP64 add 27 and a 32-bit integer add 9.
-// FP32 grids therefore accumulate 32-bit fixed point: per component a
-// power-of-two scale puts the tile's largest |G| just below 2^23, leaving 8
-// bits of headroom for the sum of weights at a node (a few units), and the
-// integer sums do not depend on the order of the additions.  FP64 grids
-// accumulate in FP64.
+// LDS accumulation of the spread in fixed point.  On gfx950 an LDS float add
+// costs about 195 cycles per wave instruction, an FP64 add 27, a 32-bit
+// integer add 9 and a 64-bit integer add 15, so both precisions accumulate
+// integers: per component a power-of-two scale puts the largest |G| that can
+// reach the tile just below 2^23 (FP32) or 2^56 (FP64), which leaves 8 or 7
+// bits of headroom for the sum at a node (terms carry weights <= 8/27 and a
+// node lies in a few dozen supports at most), and the integer sums do not
+// depend on the order of the additions.  The rounding of each term is at most
+// 2^-24 (FP32) or 2^-57 (FP64) of the largest |G|.  FP32 keeps (x, y) of a node
+// in one 64-bit word, y 2^32 + x as a two's-complement sum (exact while both
+// partial sums fit 32 bits), and z in a 32-bit word: two atomics per node.
 // ---------------------------------------------------------------------------
 template <typename T>
 struct SpreadAcc;
 template <>
 struct SpreadAcc<float> {
-    typedef int type;
+    static constexpr int BYTES = 12;   // per node
     __device__ static float scale_for(float m)
     {
         int ex = 0;
         frexpf(m, &ex);                  // m < 2^ex
         return m > 0.0f ? ldexpf(1.0f, min(23 - ex, 126)) : 0.0f;
     }
-    __device__ static void add(int *a, float v) { atomicAdd(a, __float2int_rn(v)); }
-    __device__ static float value(int a, float unscale) { return (float)a * unscale; }
     __device__ static float unscale_for(float s) { return s > 0.0f ? 1.0f / s : 0.0f; }
+    __device__ static void zero(unsigned char *lds, int V)
+    {
+        int *a = reinterpret_cast<int *>(lds);
+        for (int i = threadIdx.x; i < 3 * V; i += blockDim.x)
+            a[i] = 0;
+    }
+    __device__ static void add(unsigned char *lds, int V, int li, float vx, float vy, float vz)
+    {
+        const int x = __float2int_rn(vx), y = __float2int_rn(vy), z = __float2int_rn(vz);
+        const unsigned long long xy =
+            ((unsigned long long)(unsigned)y << 32) + (unsigned long long)(long long)x;
+        atomicAdd(&reinterpret_cast<unsigned long long *>(lds)[li], xy);
+        atomicAdd(&reinterpret_cast<int *>(lds)[2 * V + li], z);
+    }
+    // values of node li; false when all three sums are zero
+    __device__ static bool get(const unsigned char *lds, int V, int li, const float *unscale,
+                               float *f)
+    {
+        const long long sxy = reinterpret_cast<const long long *>(lds)[li];
+        const int x = (int)(unsigned)(unsigned long long)sxy;
+        const int y = (int)((sxy - (long long)x) >> 32);
+        const int z = reinterpret_cast<const int *>(lds)[2 * V + li];
+        f[0] = (float)x * unscale[0];
+        f[1] = (float)y * unscale[1];
+        f[2] = (float)z * unscale[2];
+        return (x | y | z) != 0;
+    }
 };
 template <>
 struct SpreadAcc<double> {
-    typedef double type;
-    __device__ static double scale_for(double) { return 1.0; }
-    __device__ static void add(double *a, double v) { atomicAdd(a, v); }
-    __device__ static double value(double a, double) { return a; }
-    __device__ static double unscale_for(double) { return 1.0; }
+    static constexpr int BYTES = 24;
+    __device__ static double scale_for(float m)
+    {
+        int ex = 0;
+        frexpf(m, &ex);
+        return m > 0.0f ? ldexp(1.0, min(56 - ex, 1000)) : 0.0;
+    }
+    __device__ static double unscale_for(double s) { return s > 0.0 ? 1.0 / s : 0.0; }
+    __device__ static void zero(unsigned char *lds, int V)
+    {
+        long long *a = reinterpret_cast<long long *>(lds);
+        for (int i = threadIdx.x; i < 3 * V; i += blockDim.x)
+            a[i] = 0;
+    }
+    __device__ static void add(unsigned char *lds, int V, int li, double vx, double vy, double vz)
+    {
+        unsigned long long *a = reinterpret_cast<unsigned long long *>(lds);
+        atomicAdd(&a[li], (unsigned long long)__double2ll_rn(vx));
+        atomicAdd(&a[V + li], (unsigned long long)__double2ll_rn(vy));
+        atomicAdd(&a[2 * V + li], (unsigned long long)__double2ll_rn(vz));
+    }
+    __device__ static bool get(const unsigned char *lds, int V, int li, const double *unscale,
+                               double *f)
+    {
+        const long long *a = reinterpret_cast<const long long *>(lds);
+        const long long x = a[li], y = a[V + li], z = a[2 * V + li];
+        f[0] = (double)x * unscale[0];
+        f[1] = (double)y * unscale[1];
+        f[2] = (double)z * unscale[2];
+        return (x | y | z) != 0;
+    }
 };
 
 // ---------------------------------------------------------------------------
@@ -1000,9 +1055,8 @@ __global__ __launch_bounds__(256) void k_spread(GridC g, TileC tc, T c, int add_
                                                 long long *__restrict__ count)
 {
     typedef typename V4<T>::type T4;
-    typedef typename SpreadAcc<T>::type A;
     extern __shared__ __align__(16) unsigned char smem[];
-    A *acc = reinterpret_cast<A *>(smem);
+    unsigned char *acc = smem;
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
     const int a0 = tile_start[tile], a1 = tile_start[tile + 1];
     const int h0 = halo_start[tile], h1 = halo_start[tile + 1];
@@ -1020,9 +1074,8 @@ __global__ __launch_bounds__(256) void k_spread(GridC g, TileC tc, T c, int add_
         pgv = rec_G[j];
     }
     T scale[3] = {T(1), T(1), T(1)}, unscale[3] = {T(1), T(1), T(1)};
-    for (int i = threadIdx.x; i < 3 * V; i += blockDim.x)
-        acc[i] = A(0);
-    if (sizeof(A) == 4 && tile_max) {
+    SpreadAcc<T>::zero(acc, V);
+    if (tile_max) {
         // bound on the amplitudes reaching the tile: the largest |G| of the
         // own markers of the tile and of its 26 neighbours (a support of at
         // most W <= B nodes reaches one tile further at most)
@@ -1065,7 +1118,7 @@ __global__ __launch_bounds__(256) void k_spread(GridC g, TileC tc, T c, int add_
             scale[a] = SpreadAcc<T>::scale_for(s_gm[a]);
             unscale[a] = SpreadAcc<T>::unscale_for(scale[a]);
         }
-    } else if (sizeof(A) == 4) {
+    } else {
         // largest amplitude reaching the tile, per component
         float gm[3] = {0.f, 0.f, 0.f};
         for (int e = threadIdx.x; e < n_tot; e += blockDim.x) {
@@ -1115,9 +1168,7 @@ __global__ __launch_bounds__(256) void k_spread(GridC g, TileC tc, T c, int add_
                     if (ww == T(0))
                         continue;
                     const int li = rowl + lx;
-                    SpreadAcc<T>::add(&acc[li], ww * Gs[0]);
-                    SpreadAcc<T>::add(&acc[V + li], ww * Gs[1]);
-                    SpreadAcc<T>::add(&acc[2 * V + li], ww * Gs[2]);
+                    SpreadAcc<T>::add(acc, V, li, ww * Gs[0], ww * Gs[1], ww * Gs[2]);
                 }
             }
         }
@@ -1140,13 +1191,8 @@ __global__ __launch_bounds__(256) void k_spread(GridC g, TileC tc, T c, int add_
             act[q] = tw.lane_ok && r < tw.rows && ly < box.e[1] && lz < box.e[2];
             gi[q] = ((long long)(box.o[2] + lz) * g.n[1] + (box.o[1] + ly)) * g.n[0] +
                     (box.o[0] + tw.lx);
-            if (act[q]) {
-                const A i0 = acc[li], i1 = acc[V + li], i2 = acc[2 * V + li];
-                act[q] = i0 != A(0) || i1 != A(0) || i2 != A(0);
-                fv[q][0] = SpreadAcc<T>::value(i0, unscale[0]);
-                fv[q][1] = SpreadAcc<T>::value(i1, unscale[1]);
-                fv[q][2] = SpreadAcc<T>::value(i2, unscale[2]);
-            }
+            if (act[q])
+                act[q] = SpreadAcc<T>::get(acc, V, li, unscale, fv[q]);
             if (act[q]) {
                 if (add_f) {
                     fo[q][0] = f_tot[gi[q]];
@@ -1458,7 +1504,7 @@ size_t interp_lds(const TileC &tc)
 template <typename T>
 size_t spread_lds(const TileC &tc)
 {
-    return (size_t)3 * tc.B[0] * tc.B[1] * tc.B[2] * sizeof(typename SpreadAcc<T>::type);
+    return (size_t)SpreadAcc<T>::BYTES * tc.B[0] * tc.B[1] * tc.B[2];
 }
 
 // Marker geometry and binning of one call: tile counts, sorted records,
@@ -1514,7 +1560,7 @@ ibmx_status run_forcing(ibmx_plan p, T *u, T *f_tot, const double *xp, const dou
     T4 *rec_tn = (T4 *)p->rec_tn, *rec_ud = (T4 *)p->rec_ud;
     T4 *rec_Gp = (T4 *)p->rec_Gp, *rec_Gs = (T4 *)p->rec_G;
     // per-tile amplitude bounds for the FP32 fixed-point spreading
-    float4 *tmax = sizeof(T) == 4 ? p->tile_gmax : nullptr;
+    float4 *tmax = p->tile_gmax;
     const float4 *tmax_pass = tmax, *tmax_sum = tmax ? tmax + ntiles : nullptr;
     {
         ProfScope ps(p, IBMX_K_OTHER);

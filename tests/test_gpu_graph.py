@@ -56,10 +56,9 @@ def test_graph_replays_match_eager_and_oracle(oracle_lib, precision):
         for k in ("u", "f_tot", "S", "T"):
             e = rel_err(got[k], ref[k])
             assert e <= tol, f"replay {rep} {k}: {e:.3e}"
-            if precision == "f32":
-                # integer fixed-point spreading and ordered sums: replays are
-                # bit-identical to the eager call
-                np.testing.assert_array_equal(got[k], eager[k], err_msg=f"replay {rep} {k}")
+            # integer fixed-point spreading and ordered sums: replays are
+            # bit-identical to the eager call in both precisions
+            np.testing.assert_array_equal(got[k], eager[k], err_msg=f"replay {rep} {k}")
 
 
 def test_graph_recaptures_on_new_pointers_and_params(oracle_lib):
