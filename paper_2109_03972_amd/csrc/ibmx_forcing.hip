@@ -29,7 +29,6 @@
 
 namespace {
 
-constexpr int TS = IBMX_BIN_SLOTS;   // per-particle tile table (open addressing)
 constexpr int NXCD = 8;              // MI355X: 8 XCDs, workgroups dealt round-robin
 
 template <typename T>
@@ -122,22 +121,6 @@ __device__ __forceinline__ int home_tile(const GridC &g, const TileC &tc, const 
     return ti[0] + tc.nt[0] * (ti[1] + tc.nt[1] * ti[2]);
 }
 
-// open-addressing lookup/insert of a tile id in a wave-private table
-__device__ __forceinline__ int table_slot(volatile int *keys, int key)
-{
-    unsigned h = ((unsigned)key * 2654435761u) >> (32 - IBMX_BIN_SLOTS_LOG2);
-    for (int probe = 0; probe < TS; ++probe) {
-        int s = (int)((h + probe) & (TS - 1));
-        int k = keys[s];
-        if (k == key)
-            return s;
-        if (k < 0) {
-            keys[s] = key;
-            return s;
-        }
-    }
-    return -1;
-}
 
 template <typename T, int W>
 __device__ __forceinline__ void stencil(const GridC &g, unsigned node, const T *tt, int ix[3][W],
@@ -325,163 +308,144 @@ __device__ __forceinline__ void halo_emit_wave(const int *tgt, int ntg, int j,
     }
 }
 
-// ---------------------------------------------------------------------------
-// binning step A: one wave per particle.  Tile key and rank of every active
-// marker among the particle's markers of the same tile (in index order), the
-// per-tile marker counts and the per-tile halo entry counts.
-// ---------------------------------------------------------------------------
-template <typename T, int W>
-__global__ __launch_bounds__(256) void k_bin_count(
-    GridC g, TileC tc, int np, int nm, const int *__restrict__ moff,
-    const double *__restrict__ body, const double *__restrict__ xp,
-    const uint8_t *__restrict__ mask, int *__restrict__ m_key, int *__restrict__ m_rank,
-    int *__restrict__ tab, int *__restrict__ tile_count, int *__restrict__ halo_count,
-    int *__restrict__ err, long long *__restrict__ count)
+// Reservation of one slot per lane with key >= 0 in the segment of tile
+// key: lanes with equal keys form a group, every group reserves its slots
+// with one atomic on cursor[key] -- all groups of the wave at once, so the
+// atomics' round trips overlap -- and the lane gets start[key] + base + its
+// rank in the group (-1 for key < 0).
+__device__ __forceinline__ int reserve_wave(int key, int *__restrict__ cursor,
+                                            const int *__restrict__ start, volatile int *g_key,
+                                            volatile int *g_pos)
 {
-    __shared__ int s_keys[4][TS];
-    __shared__ int s_cnt[4][TS];
-    const int wv = threadIdx.x / IBMX_WAVE, lane = threadIdx.x & (IBMX_WAVE - 1);
-    const int p = blockIdx.x * 4 + wv;
-    int active = 0, entries = 0;
-    if (p < np) {
-    volatile int *keys = s_keys[wv];
-    volatile int *cnt = s_cnt[wv];
-    for (int s = lane; s < TS; s += IBMX_WAVE) {
-        keys[s] = -1;
-        cnt[s] = 0;
-    }
-    const double xc[3] = {xp[p], xp[np + p], xp[2 * np + p]};
-    const int l0 = moff[p], l1 = moff[p + 1];
-    for (int base = l0; base < l1; base += IBMX_WAVE) {
-        const int l = base + lane;
-        int key = -1;
-        int tgt[7];
-        int ntg = 0;
-        if (l < l1 && (!mask || mask[l])) {
-            double X[3], t[3];
-            int b[3];
-            for (int a = 0; a < 3; ++a)
-                X[a] = xc[a] + body[(size_t)a * nm + l];
-            if (marker_geometry<W>(g, X, b, t)) {
-                key = home_tile(g, tc, b);
-                const T tt[3] = {(T)t[0], (T)t[1], (T)t[2]};
-                ntg = halo_tiles<T, W>(g, tc, b, tt, tgt);
-            } else {
-                atomicCAS(err, 0, (int)IBMX_EDOMAIN);
-            }
+    const int lane = threadIdx.x & (IBMX_WAVE - 1);
+    int grp = -1, rank = 0, ng = 0;
+    unsigned long long pending = __ballot(key >= 0);
+    while (pending) {
+        const int leader = __ffsll((long long)pending) - 1;
+        const int kk = __shfl(key, leader, IBMX_WAVE);
+        const unsigned long long m = __ballot(key == kk) & pending;
+        if (key == kk) {
+            grp = ng;
+            rank = __popcll(m & lanemask_lt(lane));
         }
-        active += key >= 0;
-        entries += ntg;
-        halo_count_wave(tgt, ntg, halo_count);
-        unsigned long long pending = __ballot(key >= 0);
-        while (pending) {
-            const int leader = __ffsll((long long)pending) - 1;
-            const int k = __shfl(key, leader, IBMX_WAVE);
-            const unsigned long long m = __ballot(key == k) & pending;
-            int slot = 0;
-            if (lane == leader)
-                slot = table_slot(keys, k);
-            slot = __shfl(slot, leader, IBMX_WAVE);
-            if (slot < 0) {
-                if (lane == leader)
-                    atomicCAS(err, 0, (int)IBMX_EUNSUPPORTED);
-                if (key == k)
-                    m_key[l] = -1;
-            } else {
-                if (key == k) {
-                    m_key[l] = slot;
-                    m_rank[l] = cnt[slot] + __popcll(m & lanemask_lt(lane));
-                }
-                if (lane == leader)
-                    cnt[slot] = cnt[slot] + __popcll(m);
-            }
-            pending &= ~m;
+        if (lane == leader) {
+            g_key[ng] = kk;
+            g_pos[ng] = __popcll(m);
         }
-        if (key < 0 && l < l1)
-            m_key[l] = -1;
+        ++ng;
+        pending &= ~m;
     }
-    int *mytab = tab + (size_t)p * 2 * TS;
-    for (int s = lane; s < TS; s += IBMX_WAVE) {
-        int k = keys[s];
-        mytab[s] = k;
-        mytab[TS + s] = cnt[s];
-        if (k >= 0)
-            atomicAdd(&tile_count[k], cnt[s]);
+    for (int q = lane; q < ng; q += IBMX_WAVE) {
+        const int k = g_key[q];
+        g_pos[q] = start[k] + atomicAdd(&cursor[k], g_pos[q]);
     }
-    }
-    slot_add(count, block_sum<long long>(active));
-    slot_add(count + 2 * IBMX_RSLOTS, block_sum<long long>(entries));
+    return grp >= 0 ? g_pos[grp] + rank : -1;
 }
 
 // ---------------------------------------------------------------------------
-// binning step B: one wave per particle.  Reserve the particle's segment in
-// every tile it touches, write the sorted marker records and register each
-// record in the halo lists of the neighbouring tiles its support reaches.
+// binning step A: one thread per marker.  Home tile of every active marker
+// (m_key, -1 when masked), and the per-tile marker and halo entry counts,
+// aggregated over the lanes of a wave that share a tile.
+// ---------------------------------------------------------------------------
+template <typename T, int W>
+__global__ __launch_bounds__(256) void k_bin_count(
+    GridC g, TileC tc, int np, int nm, const int *__restrict__ pid_of,
+    const double *__restrict__ body, const double *__restrict__ xp,
+    const uint8_t *__restrict__ mask, int *__restrict__ m_key, int *__restrict__ tile_count,
+    int *__restrict__ halo_count, int *__restrict__ err, long long *__restrict__ count)
+{
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & (IBMX_WAVE - 1);
+    int key = -1, ntg = 0;
+    int tgt[7];
+    if (l < nm && (!mask || mask[l])) {
+        const int p = pid_of[l];
+        double X[3], t[3];
+        int b[3];
+        for (int a = 0; a < 3; ++a)
+            X[a] = xp[(size_t)a * np + p] + body[(size_t)a * nm + l];
+        if (marker_geometry<W>(g, X, b, t)) {
+            key = home_tile(g, tc, b);
+            const T tt[3] = {(T)t[0], (T)t[1], (T)t[2]};
+            ntg = halo_tiles<T, W>(g, tc, b, tt, tgt);
+        } else {
+            atomicCAS(err, 0, (int)IBMX_EDOMAIN);
+        }
+    }
+    if (l < nm)
+        m_key[l] = key;
+    unsigned long long pending = __ballot(key >= 0);
+    while (pending) {
+        const int leader = __ffsll((long long)pending) - 1;
+        const int kk = __shfl(key, leader, IBMX_WAVE);
+        const unsigned long long m = __ballot(key == kk) & pending;
+        if (lane == leader)
+            atomicAdd(&tile_count[kk], __popcll(m));
+        pending &= ~m;
+    }
+    halo_count_wave(tgt, ntg, halo_count);
+    slot_add(count, block_sum<long long>(key >= 0 ? 1 : 0));
+    slot_add(count + 2 * IBMX_RSLOTS, block_sum<long long>(ntg));
+}
+
+// ---------------------------------------------------------------------------
+// binning step B: one thread per marker.  Reserve the marker's slot in its
+// home tile's segment, write the sorted records and register the record in
+// the halo lists of the neighbouring tiles its support reaches.  The order
+// of the markers inside a tile's segment follows the reservations; no result
+// depends on it (the spreading sums integers, the particle sums go by marker
+// index).
 // ---------------------------------------------------------------------------
 template <typename T, int W>
 __global__ __launch_bounds__(256) void k_bin_scatter(
-    GridC g, int np, int nm, const int *__restrict__ moff, const double *__restrict__ body,
-    const double *__restrict__ xp, const double *__restrict__ up, const double *__restrict__ wp,
-    const double *__restrict__ dV, const int *__restrict__ m_key, const int *__restrict__ m_rank,
-    const int *__restrict__ tab, const int *__restrict__ tile_start, int *__restrict__ tile_cursor,
-    typename V4<T>::type *__restrict__ rec_tn, typename V4<T>::type *__restrict__ rec_ud,
-    int *__restrict__ rec_src, int *__restrict__ m_inv, const TileC tc,
-    const int *__restrict__ halo_start, int *__restrict__ halo_cursor, int *__restrict__ halo_list,
-    long long halo_cap, int *__restrict__ err)
+    GridC g, TileC tc, int np, int nm, const int *__restrict__ pid_of,
+    const double *__restrict__ body, const double *__restrict__ xp,
+    const double *__restrict__ up, const double *__restrict__ wp, const double *__restrict__ dV,
+    const int *__restrict__ m_key, const int *__restrict__ tile_start,
+    int *__restrict__ tile_cursor, typename V4<T>::type *__restrict__ rec_tn,
+    typename V4<T>::type *__restrict__ rec_ud, int *__restrict__ rec_src,
+    int *__restrict__ m_inv, const int *__restrict__ halo_start, int *__restrict__ halo_cursor,
+    int *__restrict__ halo_list, long long halo_cap, int *__restrict__ err)
 {
-    __shared__ int s_base[4][TS];
     __shared__ int s_gkey[4][HGROUPS], s_gpos[4][HGROUPS];
-    const int wv = threadIdx.x / IBMX_WAVE, lane = threadIdx.x & (IBMX_WAVE - 1);
-    const int p = blockIdx.x * 4 + wv;
-    if (p >= np)
-        return;
-    volatile int *base_of = s_base[wv];
-    const int *mytab = tab + (size_t)p * 2 * TS;
-    for (int s = lane; s < TS; s += IBMX_WAVE) {
-        int k = mytab[s];
-        base_of[s] = k >= 0 ? tile_start[k] + atomicAdd(&tile_cursor[k], mytab[TS + s]) : 0;
-    }
-    const double xc[3] = {xp[p], xp[np + p], xp[2 * np + p]};
-    const double upp[3] = {up[p], up[np + p], up[2 * np + p]};
-    const double wpp[3] = {wp[p], wp[np + p], wp[2 * np + p]};
-    const double dVp = dV[p];
-    const int l0 = moff[p], l1 = moff[p + 1];
-    for (int l = l0 + lane; l - lane < l1; l += IBMX_WAVE) {
-        const int slot = l < l1 ? m_key[l] : -1;
-        int tgt[7];
-        int ntg = 0, dst = -1;
-        if (slot < 0) {
-            if (l < l1)
-                m_inv[l] = -1;
-        } else {
-            dst = base_of[slot] + m_rank[l];
-            m_inv[l] = dst;
-            double X[3], t[3], o[3];
-            int b[3];
-            for (int a = 0; a < 3; ++a) {
-                o[a] = body[(size_t)a * nm + l];
-                X[a] = xc[a] + o[a];
-            }
-            marker_geometry<W>(g, X, b, t);
-            typename V4<T>::type tn, ud;
-            tn.x = (T)t[0];
-            tn.y = (T)t[1];
-            tn.z = (T)t[2];
-            tn.w = V4<T>::from_bits(pack_node(g, b[0], b[1], b[2]));
-            // rigid-body velocity at the marker, U^d = u_p + omega_p x o (FP64)
-            ud.x = (T)(upp[0] + (wpp[1] * o[2] - wpp[2] * o[1]));
-            ud.y = (T)(upp[1] + (wpp[2] * o[0] - wpp[0] * o[2]));
-            ud.z = (T)(upp[2] + (wpp[0] * o[1] - wpp[1] * o[0]));
-            ud.w = (T)dVp;
-            rec_tn[dst] = tn;
-            rec_ud[dst] = ud;
-            rec_src[dst] = l;
-            const T tt[3] = {tn.x, tn.y, tn.z};
-            ntg = halo_tiles<T, W>(g, tc, b, tt, tgt);
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    const int wv = threadIdx.x / IBMX_WAVE;
+    const int key = l < nm ? m_key[l] : -1;
+    const int dst = reserve_wave(key, tile_cursor, tile_start, s_gkey[wv], s_gpos[wv]);
+    int tgt[7];
+    int ntg = 0;
+    if (key >= 0) {
+        m_inv[l] = dst;
+        const int p = pid_of[l];
+        double X[3], t[3], o[3];
+        int b[3];
+        for (int a = 0; a < 3; ++a) {
+            o[a] = body[(size_t)a * nm + l];
+            X[a] = xp[(size_t)a * np + p] + o[a];
         }
-        halo_emit_wave(tgt, ntg, dst, halo_cursor, halo_start, halo_list, halo_cap, err,
-                       s_gkey[wv], s_gpos[wv]);
+        marker_geometry<W>(g, X, b, t);
+        const double upp[3] = {up[p], up[np + p], up[2 * np + p]};
+        const double wpp[3] = {wp[p], wp[np + p], wp[2 * np + p]};
+        typename V4<T>::type tn, ud;
+        tn.x = (T)t[0];
+        tn.y = (T)t[1];
+        tn.z = (T)t[2];
+        tn.w = V4<T>::from_bits(pack_node(g, b[0], b[1], b[2]));
+        // rigid-body velocity at the marker, U^d = u_p + omega_p x o (FP64)
+        ud.x = (T)(upp[0] + (wpp[1] * o[2] - wpp[2] * o[1]));
+        ud.y = (T)(upp[1] + (wpp[2] * o[0] - wpp[0] * o[2]));
+        ud.z = (T)(upp[2] + (wpp[0] * o[1] - wpp[1] * o[0]));
+        ud.w = (T)dV[p];
+        rec_tn[dst] = tn;
+        rec_ud[dst] = ud;
+        rec_src[dst] = l;
+        const T tt[3] = {tn.x, tn.y, tn.z};
+        ntg = halo_tiles<T, W>(g, tc, b, tt, tgt);
+    } else if (l < nm) {
+        m_inv[l] = -1;
     }
+    halo_emit_wave(tgt, ntg, dst, halo_cursor, halo_start, halo_list, halo_cap, err, s_gkey[wv],
+                   s_gpos[wv]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1530,16 +1494,16 @@ void bin_markers(ibmx_plan p, const double *xp, const double *up, const double *
     }
     if (np > 0 && nm > 0) {
         ProfScope ps(p, IBMX_K_GEOMETRY);
-        const int gb = nblocks(np, 4);
+        const int gb = nblocks(nm, 256);
         hipLaunchKernelGGL((k_bin_count<T, W>), dim3(gb), dim3(256), 0, s, p->g, tc, np, nm,
-                           p->d_moff, p->body, xp, mask, p->m_key, p->m_rank, p->bin_tab,
-                           p->tile_count, p->halo_count, p->d_err, p->d_count);
+                           p->d_pid, p->body, xp, mask, p->m_key, p->tile_count, p->halo_count,
+                           p->d_err, p->d_count);
         ibmx_exclusive_scan(p->tile_count, p->tile_start, ntiles, p->scan_aux, s);
         ibmx_exclusive_scan(p->halo_count, p->halo_start, ntiles, p->scan_aux, s);
-        hipLaunchKernelGGL((k_bin_scatter<T, W>), dim3(gb), dim3(256), 0, s, p->g, np, nm,
-                           p->d_moff, p->body, xp, up, wp, p->dV, p->m_key, p->m_rank, p->bin_tab,
-                           p->tile_start, p->tile_cursor, rec_tn, rec_ud, p->rec_src, p->m_inv,
-                           tc, p->halo_start, p->halo_cursor, p->halo_list, p->halo_cap, p->d_err);
+        hipLaunchKernelGGL((k_bin_scatter<T, W>), dim3(gb), dim3(256), 0, s, p->g, tc, np, nm,
+                           p->d_pid, p->body, xp, up, wp, p->dV, p->m_key, p->tile_start,
+                           p->tile_cursor, rec_tn, rec_ud, p->rec_src, p->m_inv, p->halo_start,
+                           p->halo_cursor, p->halo_list, p->halo_cap, p->d_err);
     } else {
         ibmx_exclusive_scan(p->tile_count, p->tile_start, ntiles, p->scan_aux, s);
         ibmx_exclusive_scan(p->halo_count, p->halo_start, ntiles, p->scan_aux, s);

@@ -8,8 +8,6 @@
 
 #define IBMX_WAVE 64
 #define IBMX_RSLOTS 1024          // spread-out accumulation slots per counter
-#define IBMX_BIN_SLOTS_LOG2 9
-#define IBMX_BIN_SLOTS (1 << IBMX_BIN_SLOTS_LOG2)   // tiles one particle may touch
 
 // ---------------------------------------------------------------------------
 // grid constants passed by value to kernels
@@ -66,13 +64,11 @@ struct ibmx_plan_s {
     void *rec_G;          // T4[nm] G summed over the passes
     int *rec_src;         // [nm] original marker index
     int *m_key;           // [nm] per-marker tile slot (binning scratch)
-    int *m_rank;          // [nm] rank within (particle, tile) (binning scratch)
     int *m_inv;           // [nm] sorted position of marker l (-1: inactive)
 
     // tiles
     TileC tc;
     long long tile_cap;   // tiles the tile arrays are sized for
-    int *bin_tab;         // [np][2][IBMX_BIN_SLOTS] per-particle tile tables
     int *tile_count;      // [ntiles + 1]
     int *tile_start;      // [ntiles + 1]
     int *tile_cursor;     // [ntiles]

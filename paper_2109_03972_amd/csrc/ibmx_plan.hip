@@ -21,10 +21,10 @@ void free_plan(ibmx_plan p)
         return;
     void *ptrs[] = {p->d_moff,      p->d_pid,       p->d_err,        p->d_acc,     p->d_count,
                     p->rec_tn,      p->rec_ud,      p->rec_src,      p->rec_Gp,    p->rec_G,
-                    p->m_key,       p->m_inv,       p->m_rank,       p->tile_count, p->tile_start,
+                    p->m_key,       p->m_inv,       p->tile_count, p->tile_start,
                     p->tile_cursor, p->halo_count,  p->halo_start,   p->halo_cursor,
                     p->halo_list,   p->tile_gmax,   p->scan_aux,     p->bw_u,         p->p_cell_of, p->p_cursor,
-                    p->p_count,     p->p_off,       p->p_wcount,     p->p_woff,    p->bin_tab};
+                    p->p_count,     p->p_off,       p->p_wcount,     p->p_woff};
     for (void *q : ptrs)
         if (q)
             (void)hipFree(q);
@@ -151,14 +151,12 @@ ibmx_status check_params(const ibmx_grid *g, const ibmx_params *prm)
     A(&p->rec_Gp, Ts * 4 * nmz);
     A((void **)&p->rec_src, sizeof(int) * nmz);
     A((void **)&p->m_key, sizeof(int) * nmz);
-    A((void **)&p->m_rank, sizeof(int) * nmz);
     A((void **)&p->m_inv, sizeof(int) * nmz);
     A((void **)&p->p_cell_of, sizeof(int) * npz);
     A((void **)&p->p_count, sizeof(int) * (npz + 1));
     A((void **)&p->p_off, sizeof(int) * (npz + 1));
     A((void **)&p->p_wcount, sizeof(int) * (npz + 1));
     A((void **)&p->p_woff, sizeof(int) * (npz + 1));
-    A((void **)&p->bin_tab, sizeof(int) * 2 * IBMX_BIN_SLOTS * npz);
     if (!ok) {
         free_plan(p);
         return IBMX_ENOMEM;
