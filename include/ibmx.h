@@ -217,6 +217,9 @@ IBMX_API ibmx_status ibmx_plan_profile(ibmx_plan plan, int32_t enable);
  *              (entries of inactive markers are not written).
  * Deferred error: EDOMAIN if an active marker's support crosses a wall (the
  * marker is then skipped).
+ * The spreading accumulates in integer fixed point (per-tile power-of-two
+ * scales), so the results do not depend on the order of the additions: a
+ * call repeated on the same inputs gives the same bits.
  */
 IBMX_API ibmx_status ibmx_forcing(ibmx_plan plan, void *u, void *f_tot,
                          const double *xp, const double *up, const double *wp,
