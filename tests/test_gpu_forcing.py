@@ -86,3 +86,36 @@ def test_wall_crossing_support_is_reported():
     c.xp[2, 0] = c.radius[0] + 0.2      # its lowest markers sit 0.2h from the wall
     got = gpu_forcing(c, "f64")
     assert got["status"] == -2
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_no_particles(precision):
+    """A plan with no particles: the forcing call leaves u and f_tot alone
+    and the residuals are zero; the pair pass finds nothing."""
+    import torch
+    from paper_2109_03972_amd import ibmx
+    from tests._util import require_gpu
+    dev = require_gpu()
+    c = synth.small_case(108, n=(32, 32, 36), periodic=(1, 1, 0), n_iter=2)
+    empty = synth.Case(name="empty", n=c.n, h=c.h, origin=c.origin, periodic=c.periodic,
+                       xp=np.zeros((3, 0)), up=np.zeros((3, 0)), wp=np.zeros((3, 0)),
+                       radius=np.zeros(0), mass=np.zeros(0), moff=np.zeros(1, dtype=np.int32),
+                       body=np.zeros((3, 0)), dV=np.zeros(0), u0=c.u0, params=c.params)
+    T = torch.float64 if precision == "f64" else torch.float32
+    f64 = torch.float64
+    plan = ibmx.Plan.from_case(empty, precision)
+    z = torch.zeros((3, 0), dtype=f64, device=dev)
+    plan.set_markers(z, torch.zeros(0, dtype=f64, device=dev))
+    u = torch.as_tensor(c.u0, device=dev).to(T).contiguous()
+    u_before = u.clone()
+    f = torch.zeros_like(u)
+    resid = torch.full((3,), 7.0, dtype=f64, device=dev)
+    S, Tq = plan.forcing(u, f, z, z, z, resid=resid)
+    plan.check("no particles")
+    assert torch.equal(u, u_before) and not f.any()
+    assert S.shape == (3, 0) and Tq.shape == (3, 0)
+    assert not resid.any()
+    res = plan.pairs(z, torch.zeros(0, dtype=f64, device=dev), torch.zeros(0, dtype=f64, device=dev),
+                     z, z, radius_max=1.0)
+    plan.check("no particles pairs")
+    assert res["counts"].cpu().tolist() == [0, 0]
