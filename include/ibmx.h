@@ -10,7 +10,7 @@
  *     velocity u_p + omega_p x (X_l - x_p), spread it back to the grid,
  *     update the velocity, and sum each particle's force and torque
  *     (eq. basic-particle);
- *   - the pair pass (Sec. 2.3): cell list, pair and wall lists, the
+ *   - the pair pass (Secs. 2.2.5-2.2.8): cell list, pair and wall lists, the
  *     lubrication / normal / tangential collision forces and torques
  *     (eq. f_int), and the marker-disable mask.
  *
@@ -206,7 +206,7 @@ IBMX_API ibmx_status ibmx_plan_profile(ibmx_plan plan, int32_t enable);
  *              are read or written.
  * xp, up, wp   double[3][np]: centres, velocities, angular velocities.
  * marker_active uint8[nm] or NULL (all active): 0 drops marker l from every
- *              pass (the disable rule of Sec. 2.3, see ibmx_pairs).
+ *              pass (the disable rule of Sec. 2.2.5, see ibmx_pairs).
  * S_out, T_out double[3][np], overwritten: sum over passes and active
  *              markers of F_l dV_l and of o_l x F_l dV_l.  The hydrodynamic
  *              force and torque of eq. basic-particle are -rho_f times these.
@@ -245,7 +245,7 @@ IBMX_API ibmx_status ibmx_forcing_backward(ibmx_plan plan, const void *u0,
                                   void *gu0, double *gxp, double *gup, double *gwp);
 
 /*
- * Pair pass (Sec. 2.3), all FP64:
+ * Pair pass (Secs. 2.2.5-2.2.8), all FP64:
  *  - cell list: nc[a] = max(1, floor(L_a / (2 R_max + gap_cut))) cells per
  *    axis; cell of p = floor((x_p - origin)/edge) of the periodically wrapped
  *    centre, clamped; cell_start int32[ncell + 1], cell_particles int32[np]

@@ -61,6 +61,12 @@ def lib():
                                       i, P, P, i, P, P, P, P, P, P]
         L.ref_marker_mask.restype = i
         L.ref_marker_mask.argtypes = [P, d, P, P, i, P, P, P, P, d, i, u64, i, P, P, i, P, P, P]
+        L.ref_particle_integrals.restype = i
+        L.ref_particle_integrals.argtypes = [P, d, P, P, i, P, P, P, P, P, P]
+        L.ref_cell_alpha.restype = d
+        L.ref_cell_alpha.argtypes = [P, d, d]
+        L.ref_grid_mean.restype = i
+        L.ref_grid_mean.argtypes = [P, P, P]
         _lib = L
     return _lib
 
@@ -262,3 +268,41 @@ class OracleError(RuntimeError):
     def __init__(self, code):
         super().__init__(f"oracle returned status {code}")
         self.code = code
+
+
+def particle_integrals(case, u=None, xp=None, radius=None, want_alpha=False):
+    """Level-set volume fraction integrals of the fluid velocity over each
+    particle: returns dict(Iu, Ir[, alpha])."""
+    n, h, origin, per = _grid(case)
+    u_ = _f64(case.u0 if u is None else u)
+    xp_ = _f64(case.xp if xp is None else xp)
+    rad = _f64(case.radius if radius is None else radius)
+    npart = xp_.shape[1]
+    Iu = np.zeros((3, npart))
+    Ir = np.zeros((3, npart))
+    alpha = np.zeros(u_.shape[1:]) if want_alpha else None
+    st = lib().ref_particle_integrals(_p(n), h, _p(origin), _p(per), npart, _p(xp_), _p(rad),
+                                      _p(u_), _p(Iu), _p(Ir), _p(alpha))
+    if st != OK:
+        raise OracleError(st)
+    out = dict(Iu=Iu, Ir=Ir)
+    if want_alpha:
+        out["alpha"] = alpha
+    return out
+
+
+def cell_alpha(c0, h: float, R: float) -> float:
+    """Level-set volume fraction of one cell (lowest corner c0 relative to the
+    sphere centre)."""
+    c = np.ascontiguousarray(c0, dtype=np.float64)
+    return float(lib().ref_cell_alpha(_p(c), float(h), float(R)))
+
+
+def grid_mean(case, f):
+    n, _, _, _ = _grid(case)
+    f_ = _f64(f)
+    mean = np.zeros(3)
+    st = lib().ref_grid_mean(_p(n), _p(f_), _p(mean))
+    if st != OK:
+        raise OracleError(st)
+    return mean

@@ -216,7 +216,7 @@ static void interp3(const support_t *sp, long nx, long ny, long N, const double 
  * |U^d_l - U^{m-1}_l|^2), the no-slip error of Sec. 2.2.2 weighted by the
  * marker volumes; resid[n_iter] (if final_resid) measures u^{n_iter}.
  * U_dbg (optional) receives U^{m-1}_l as [n_iter][3][nm] for active markers.
- * Markers with mask[l] == 0 take no part (Sec. 2.3, disabling markers).
+ * Markers with mask[l] == 0 take no part (Sec. 2.2.5, disabling markers).
  */
 int ref_forcing(const int *n, double h, const double *origin, const int *periodic,
                 int kernel, int n_iter, double c, int final_resid,
@@ -591,7 +591,7 @@ int ref_cell_list(const int *n, double h, const double *origin, const int *perio
 /* All pairs i < j with centre distance below R_i + R_j + gap_cut (compared
  * squared), in lexicographic (i, j) order -- the brute-force definition of
  * the set the sum over q != p in eq. f_int runs over.  gap = d - R_i - R_j
- * is the separation zeta_n of Sec. 2.3. */
+ * is the separation zeta_n of Secs. 2.2.6-2.2.7. */
 int ref_pairs_brute(const int *n, double h, const double *origin, const int *periodic,
                     int np, const double *xp, const double *radius, double gap_cut,
                     int cap, int *pairs, double *gap, int *npairs)
@@ -653,19 +653,19 @@ typedef struct {
 /*
  * Collision force on particle p from a partner across the contact plane
  * with unit normal nvec (pointing from p to the partner).  Inputs: surface
- * gap zeta, relative contact-point velocity g (Sec. 2.3: g_cp), effective
+ * gap zeta, relative contact-point velocity g (Sec. 2.2.8: g_cp), effective
  * radius and mass, the tangential spring displacement of the previous call
  * (zt_old, zero for a new contact).  Returns F (force on p) and the updated
  * spring zt_new.
  *
- *   regime (Sec. 2.3, eq. f_int cases): contact if zeta < 0, lubrication if
+ *   regime (Secs. 2.2.6-2.2.8, eq. f_int cases): contact if zeta < 0, lubrication if
  *   0 <= zeta < eps_sep, nothing otherwise.
  *   lubrication: F = -6 pi rho_f nu_f R_eff^2 psi / max(zeta_min, zeta) g_n,
- *     psi = erf(6 - C max(zeta_min, zeta)/h)/2 + 1/2 (Sec. 2.3, lubrication).
+ *     psi = erf(6 - C max(zeta_min, zeta)/h)/2 + 1/2 (Sec. 2.2.6, lubrication).
  *   normal contact: linear spring-dashpot F_n = -k_n |zeta| n - d_n g_n, with
  *     k_n, d_n the damped-oscillator coefficients giving restitution e_dry
  *     over the contact time T_c (the linear form of eq. ode).
- *   tangential contact (Sec. 2.3, tangential model): spring-dashpot
+ *   tangential contact (Sec. 2.2.8, tangential model): spring-dashpot
  *     F_dp = -k_t zeta_t - d_t g_t, capped by Coulomb friction; mu_s while
  *     sticking, mu_k when slipping, with the spring reset on slip.
  */
@@ -739,12 +739,12 @@ static int find_pair(int n_in, const int *pairs_in, int i, int j)
  * Collision force and torque on every particle (eq. f_int): the sum over
  * listed pairs and walls of F_n + F_t, and of R_cp n x F_t.  For a pair
  * (p, q), n = (x_q - x_p)/d, the contact-point lever arms are
- * R_p,cp = (d + R_p - R_q)/2 and R_q,cp = (d + R_q - R_p)/2 (Sec. 2.3), and
+ * R_p,cp = (d + R_p - R_q)/2 and R_q,cp = (d + R_q - R_p)/2 (Sec. 2.2.8), and
  * g = (u_p - u_q) + R_p,cp omega_p x n + R_q,cp omega_q x n.  p receives F,
  * q receives -F; both receive the torque R_cp n x F_t.  R_eff =
  * R_p R_q/(R_p + R_q), m_eff = m_p m_q/(m_p + m_q), zeta_min = factor *
  * min(R_p, R_q).  A wall is the limit R_q, m_q -> infinity at rest: R_eff =
- * R_p, m_eff = m_p, lever arm R_pw,cp = |x_w - x_p| (Sec. 2.3).
+ * R_p, m_eff = m_p, lever arm R_pw,cp = |x_w - x_p| (Sec. 2.2.8).
  * Spring history is looked up by the (i, j) key of the previous call's list
  * (and by (p, side) for walls).
  */
@@ -838,7 +838,7 @@ uint64_t ref_splitmix64(uint64_t x)
 }
 
 /*
- * Marker disabling (Sec. 2.3): markers leave the forcing when a particle is
+ * Marker disabling (Sec. 2.2.5): markers leave the forcing when a particle is
  * closer than eps_sep to a wall or closer than 2 eps_sep to another
  * particle; for a particle pair only one of the two, chosen at random, loses
  * markers.  The random choice for pair (p, q), p < q, is the low bit of
@@ -907,6 +907,116 @@ int ref_marker_mask(const int *n, double h, const double *origin, const int *per
             if (dist < eps_sep)
                 mask[l] = 0;
         }
+    }
+    return R_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Level-set volume fraction and the fluid integrals over each particle      */
+/* (Sec. 2.2.9, direct computation of the fluid inertia inside a particle)   */
+/* ------------------------------------------------------------------------ */
+
+/* Volume fraction of a cell in a sphere of radius R from the signed corner
+ * distances phi_m = |x_m - x_p| - R (negative inside): alpha = sum over the
+ * eight corners of -phi_m H(-phi_m), divided by sum |phi_m|.  A cell whose
+ * corners all lie on the surface (zero denominator) counts as empty. */
+static double level_set_alpha(const double *c0, double h, double R)
+{
+    double num = 0.0, den = 0.0;
+    for (int m = 0; m < 8; ++m) {
+        double d[3] = {c0[0] + (m & 1) * h, c0[1] + ((m >> 1) & 1) * h, c0[2] + ((m >> 2) & 1) * h};
+        double phi = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) - R;
+        if (phi <= 0.0)
+            num += -phi;
+        den += fabs(phi);
+    }
+    return den > 0.0 ? num / den : 0.0;
+}
+
+/* The same volume fraction for one cell with lowest corner c0 (relative to
+ * the particle centre): exposed for the pins. */
+double ref_cell_alpha(const double *c0, double h, double R) { return level_set_alpha(c0, h, R); }
+
+/* For every particle p, over the cells whose box meets [x_p - R_p, x_p + R_p]
+ * per axis (x_p wrapped into the domain on periodic axes; cells beyond a wall
+ * are skipped):
+ *   Iu_p = sum alpha h^3 u(cell),  Ir_p = sum alpha h^3 (r x u(cell)),
+ * with r = cell centre - x_p (the cell index not wrapped, so r is the
+ * displacement to the image of the cell next to the particle).  Iu and Ir
+ * are double[3][np]; alpha_out (may be NULL) receives sum_p alpha per cell,
+ * double[nz][ny][nx].  Particles are assumed smaller than half a periodic
+ * axis (no cell is met twice by one particle). */
+int ref_particle_integrals(const int *n, double h, const double *origin, const int *periodic,
+                           int np, const double *xp, const double *radius, const double *u,
+                           double *Iu, double *Ir, double *alpha_out)
+{
+    if (!n || !(h > 0.0) || np < 0 || (np > 0 && (!xp || !radius || !u || !Iu || !Ir)))
+        return R_EINVAL;
+    long nx = n[0], ny = n[1], N = (long)n[0] * n[1] * n[2];
+    if (alpha_out)
+        for (long i = 0; i < N; ++i)
+            alpha_out[i] = 0.0;
+    for (int p = 0; p < np; ++p) {
+        double x[3];
+        wrapped_centre(n, h, origin, periodic, np, xp, p, x);
+        double R = radius[p];
+        long lo[3], hi[3];
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = (long)floor((x[a] - R - origin[a]) / h);
+            hi[a] = (long)floor((x[a] + R - origin[a]) / h);
+        }
+        double su[3] = {0.0, 0.0, 0.0}, sr[3] = {0.0, 0.0, 0.0};
+        for (long k = lo[2]; k <= hi[2]; ++k)
+            for (long j = lo[1]; j <= hi[1]; ++j)
+                for (long i = lo[0]; i <= hi[0]; ++i) {
+                    long idx3[3] = {i, j, k};
+                    int inside = 1;
+                    for (int a = 0; a < 3; ++a) {
+                        if (periodic[a]) {
+                            idx3[a] = ((idx3[a] % n[a]) + n[a]) % n[a];
+                        } else if (idx3[a] < 0 || idx3[a] >= n[a]) {
+                            inside = 0;
+                        }
+                    }
+                    if (!inside)
+                        continue;
+                    /* lowest corner and centre of the cell, relative to x_p */
+                    double c0[3] = {origin[0] + i * h - x[0], origin[1] + j * h - x[1],
+                                    origin[2] + k * h - x[2]};
+                    double alpha = level_set_alpha(c0, h, R);
+                    if (alpha == 0.0)
+                        continue;
+                    long g = (idx3[2] * ny + idx3[1]) * nx + idx3[0];
+                    double uc[3] = {u[g], u[N + g], u[2 * N + g]};
+                    double r[3] = {c0[0] + 0.5 * h, c0[1] + 0.5 * h, c0[2] + 0.5 * h};
+                    double rxu[3];
+                    cross(r, uc, rxu);
+                    double w = alpha * h * h * h;
+                    for (int a = 0; a < 3; ++a) {
+                        su[a] += w * uc[a];
+                        sr[a] += w * rxu[a];
+                    }
+                    if (alpha_out)
+                        alpha_out[g] += alpha;
+                }
+        for (int a = 0; a < 3; ++a) {
+            Iu[a * np + p] = su[a];
+            Ir[a * np + p] = sr[a];
+        }
+    }
+    return R_OK;
+}
+
+/* Volume average of a grid field per component (Sec. 2.2.4, the mean IBM
+ * force of a triply periodic domain is minus this average of f_IBM). */
+int ref_grid_mean(const int *n, const double *f, double *mean)
+{
+    long N = (long)n[0] * n[1] * n[2];
+    for (int a = 0; a < 3; ++a) {
+        double s = 0.0;
+        for (long i = 0; i < N; ++i)
+            s += f[a * N + i];
+        mean[a] = s / (double)N;
     }
     return R_OK;
 }

@@ -1,4 +1,4 @@
-// Pair pass of the collision models (Sec. 2.3), FP64 throughout.
+// Pair pass of the collision models (Secs. 2.2.5-2.2.8), FP64 throughout.
 //
 //   cell list   uniform cells of edge >= 2 R_max + gap_cut, particles listed
 //               per cell by id (counting sort, then a per-cell sort);

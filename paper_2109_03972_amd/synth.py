@@ -62,7 +62,7 @@ def default_params() -> Dict[str, float]:
 
     nu_f follows the paper's bed (nu dt / h^2 = 0.0247, Sec. 3.5); e_dry,
     mu_s, mu_k and zeta_min = 3e-3 r_p follow Sec. 3.4-3.5; eps_sep = 1.5h and
-    C = 5.5 are the three-point values (Sec. 2.3); T_c = 10 dt (Sec. 2.3).
+    C = 5.5 are the three-point values (Secs. 2.2.5-2.2.6); T_c = 10 dt (Sec. 2.2.7).
     ``c`` is 2 alpha_k dt with the first low-storage RK3 coefficient 4/15.
     """
     return dict(

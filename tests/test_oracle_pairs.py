@@ -1,4 +1,4 @@
-"""Pins of the oracle's pair pass (Sec. 2.3): neighbour lists, collision
+"""Pins of the oracle's pair pass (Secs. 2.2.5-2.2.8): neighbour lists, collision
 forces and marker disabling."""
 import math
 
@@ -196,7 +196,7 @@ def test_lubrication_textbook_limits(oracle_lib):
 
 def test_tangential_coulomb_cap(oracle_lib):
     """A sphere pressed into a wall and sliding fast: the tangential force is
-    capped at mu_k |F_n| and opposes the sliding (Sec. 2.3 tangential model);
+    capped at mu_k |F_n| and opposes the sliding (Sec. 2.2.8 tangential model);
     a slowly creeping contact sticks with |F_t| <= mu_s |F_n|."""
     R = 4.0
     x = np.array([[10.0], [10.0], [R - 0.02]])
@@ -220,7 +220,7 @@ def _splitmix64(x):
 
 
 def test_marker_mask_rules(oracle_lib):
-    """Marker disabling (Sec. 2.3): for each pair closer than 2 eps_sep
+    """Marker disabling (Sec. 2.2.5): for each pair closer than 2 eps_sep
     exactly one particle loses markers (those within 2 eps_sep of the partner's
     surface); markers closer than eps_sep to a wall are off; nothing else."""
     c = synth.make_case("bidisperse_bed_256x256x512", lazy_field=True)
