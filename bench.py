@@ -162,9 +162,29 @@ def run_gpu(case, precision, steps, warmup, profile=True, tune=True, tile=None):
     # with the forcing call replayed as one HIP graph
     ms, wall, st = timed(False, profile)
     ms_graph, _, _ = timed(True, False)
+
+    # the particle solver's fluid integrals and the mean IBM force, timed on
+    # their own (not part of the step)
+    def time_call(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    extras = dict(
+        particle_integrals_ms=time_call(lambda: plan.particle_integrals(u, D["xp"], D["radius"])),
+        grid_mean_ms=time_call(lambda: plan.grid_mean(f)))
+    plan.check("integrals")
     if not profile:
         st = plan.stats()
     out = dict(ms_per_step=ms, ms_per_step_graph=ms_graph, wall_s=wall, stats=st, n_iter=n_iter,
+               extras=extras,
                resid=resid.cpu().numpy().tolist(), tile=tuned or list(plan.stats()["tile"]))
     del u, f, D
     plan.close()
@@ -303,6 +323,11 @@ def main():
         roofline=roof, cpu_baseline=cpu, fp64=fp64,
         kernel_ms_per_launch=per_launch,
         graph=dict(ms_per_step=r32["ms_per_step_graph"], value=value_graph),
+        particle_integrals=dict(
+            ms=r32["extras"]["particle_integrals_ms"],
+            note="level-set fluid integrals over all particles (one call, FP32 grid, "
+                 "FP64 geometry and sums); not part of the step"),
+        grid_mean_ms=r32["extras"]["grid_mean_ms"],
         pass_rate=n_act * n_iter / (sum(km[k] for k in ("interp", "spread")) / steps_done
                                     * 1e-3),
     )

@@ -313,6 +313,40 @@ IBMX_API ibmx_status ibmx_tune(ibmx_plan plan, void *u, void *f_tot,
                       const double *xp, const double *up, const double *wp,
                       const uint8_t *marker_active);
 
+/*
+ * Fluid integrals over every particle for the rate-of-change term of the
+ * particle equations (Sec. 2.2.9), with the level-set volume fraction of
+ * each cell: from the signed distances phi_m = |x_m - x_p| - R_p of the
+ * cell's eight corners x_m (negative inside),
+ *   alpha = sum_m -phi_m H(-phi_m) / sum_m |phi_m|   (0 if all phi_m = 0),
+ *   Iu[a][p] = sum_cells alpha h^3 u_a(cell),
+ *   Ir[a][p] = sum_cells alpha h^3 (r x u)_a(cell),  r = cell centre - x_p,
+ * over the cells whose box meets [x_p - R_p, x_p + R_p] per axis (x_p
+ * wrapped into the domain on periodic axes; cells beyond a wall are
+ * skipped; r is the displacement to the image of the cell next to the
+ * particle).  Cell (i, j, k) is the box [origin + (i, j, k) h,
+ * origin + (i + 1, j + 1, k + 1) h] around node (i, j, k).
+ * u            T[3][nz][ny][nx] (the plan's precision); geometry and sums
+ *              are FP64, summed in a fixed order.
+ * xp, radius   double[3][np], double[np].
+ * Iu, Ir       double[3][np], overwritten.
+ * alpha_out    T[nz][ny][nx] or NULL: sum over particles of alpha per cell,
+ *              overwritten (added with atomics where particles overlap).
+ * Particles must be smaller than half a periodic axis.
+ */
+IBMX_API ibmx_status ibmx_particle_integrals(ibmx_plan plan, const void *u, const double *xp,
+                                    const double *radius, double *Iu, double *Ir,
+                                    void *alpha_out);
+
+/*
+ * Volume average per component of a T[3][nz][ny][nx] grid field, in FP64:
+ * mean[a] = sum_x f_a(x) / (nx ny nz), double[3] on the device.  For the
+ * IBM force of a triply periodic domain, minus this average is the mean
+ * forcing removed from the momentum equation (Sec. 2.2.4, eq. fe_IBM).
+ * Partial sums over fixed chunks, added in a fixed order.
+ */
+IBMX_API ibmx_status ibmx_grid_mean(ibmx_plan plan, const void *f, double *mean);
+
 /* Static description of a status code. */
 IBMX_API const char *ibmx_status_string(ibmx_status status);
 

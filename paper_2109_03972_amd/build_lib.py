@@ -18,7 +18,8 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libibmx.so")
 BUILD = os.path.join(ROOT, "_build", "ibmx")
 
-SOURCES = ["ibmx_util.hip", "ibmx_plan.hip", "ibmx_forcing.hip", "ibmx_graph.hip", "ibmx_pairs.hip"]
+SOURCES = ["ibmx_util.hip", "ibmx_plan.hip", "ibmx_forcing.hip", "ibmx_graph.hip", "ibmx_pairs.hip",
+           "ibmx_particle.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -76,6 +76,7 @@ struct ibmx_plan_s {
     int *halo_start;      // [ntiles + 1]
     int *halo_cursor;     // [ntiles]
     int *halo_list;       // [halo_cap]
+    double *mean_part;    // [3][ibmx_mean_blocks()] partial sums of ibmx_grid_mean
     int *scan_aux;        // exclusive-scan workspace (ibmx_scan_aux_size ints)
     long long scan_cap;   // elements the workspace serves
     float4 *tile_gmax;    // [2][ntiles] largest |G| of the pass and |pass sum|
@@ -151,6 +152,7 @@ ibmx_status ibmx_plan_alloc_tiles(ibmx_plan p, int tx, int ty, int tz);
 ibmx_status ibmx_spread_allow_lds(ibmx_plan p);
 void ibmx_plan_drop_graph(ibmx_plan p);
 ibmx_status ibmx_plan_scan_reserve(ibmx_plan p, long long n);
+int ibmx_mean_blocks();
 // exclusive scan of n ints, out[n] = total; aux holds ibmx_scan_aux_size(n)
 // ints of workspace
 int ibmx_scan_aux_size(long long n);

@@ -23,7 +23,7 @@ void free_plan(ibmx_plan p)
                     p->rec_tn,      p->rec_ud,      p->rec_src,      p->rec_Gp,    p->rec_G,
                     p->m_key,       p->m_inv,       p->tile_count, p->tile_start,
                     p->tile_cursor, p->halo_count,  p->halo_start,   p->halo_cursor,
-                    p->halo_list,   p->tile_gmax,   p->scan_aux,     p->bw_u,         p->p_cell_of, p->p_cursor,
+                    p->halo_list,   p->tile_gmax,   p->scan_aux,     p->mean_part,    p->bw_u,         p->p_cell_of, p->p_cursor,
                     p->p_count,     p->p_off,       p->p_wcount,     p->p_woff};
     for (void *q : ptrs)
         if (q)
@@ -145,6 +145,7 @@ ibmx_status check_params(const ibmx_grid *g, const ibmx_params *prm)
     A((void **)&p->d_err, sizeof(int) * 4);
     A((void **)&p->d_acc, sizeof(double) * (p->n_iter_cap + 2) * IBMX_RSLOTS);
     A((void **)&p->d_count, sizeof(long long) * 8 * IBMX_RSLOTS);
+    A((void **)&p->mean_part, sizeof(double) * 3 * ibmx_mean_blocks());
     A(&p->rec_tn, Ts * 4 * nmz);
     A(&p->rec_ud, Ts * 4 * nmz);
     A(&p->rec_G, Ts * 4 * nmz);

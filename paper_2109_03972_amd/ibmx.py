@@ -25,7 +25,8 @@ API = (
     "ibmx_plan_set_stream", "ibmx_plan_set_tiles", "ibmx_plan_status", "ibmx_plan_stats",
     "ibmx_plan_profile",
     "ibmx_forcing", "ibmx_forcing_graph",
-    "ibmx_forcing_backward", "ibmx_pairs", "ibmx_tune", "ibmx_status_string", "ibmx_version",
+    "ibmx_forcing_backward", "ibmx_pairs", "ibmx_tune", "ibmx_particle_integrals",
+    "ibmx_grid_mean", "ibmx_status_string", "ibmx_version",
 )
 
 
@@ -102,6 +103,10 @@ def lib():
                                  P, P, P, P, i32, P, P, P, i32, P, P, P, P]
         L.ibmx_tune.restype = St
         L.ibmx_tune.argtypes = [P] * 7
+        L.ibmx_particle_integrals.restype = St
+        L.ibmx_particle_integrals.argtypes = [P] * 7
+        L.ibmx_grid_mean.restype = St
+        L.ibmx_grid_mean.argtypes = [P] * 3
         L.ibmx_status_string.restype = ctypes.c_char_p
         L.ibmx_status_string.argtypes = [St]
         L.ibmx_version.restype = ctypes.c_char_p
@@ -355,6 +360,32 @@ class Plan:
         return dict(cell_start=cell_start, cell_particles=cellp, pairs=pairs, gap=pgap, hist=hist,
                     walls=walls, wgap=wgap, whist=whist, counts=counts, Fc=Fc, Tc=Tc, mask=mask,
                     pair_cap=pair_cap, wall_cap=wall_cap)
+
+    def particle_integrals(self, u, xp, radius, alpha=None):
+        """ibmx_particle_integrals: returns (Iu, Ir), double[3][np]; fills the
+        optional alpha grid (the plan's precision, [nz][ny][nx])."""
+        import torch
+        grid_shape = (3, self.n[2], self.n[1], self.n[0])
+        _want(u, self.dtype, grid_shape, "u")
+        _want(xp, torch.float64, (3, self.np), "xp")
+        _want(radius, torch.float64, (self.np,), "radius")
+        _want(alpha, self.dtype, grid_shape[1:], "alpha")
+        Iu = torch.empty((3, self.np), dtype=torch.float64, device=u.device)
+        Ir = torch.empty_like(Iu)
+        self._sync_stream()
+        st = lib().ibmx_particle_integrals(self.handle, _ptr(u), _ptr(xp), _ptr(radius), _ptr(Iu),
+                                           _ptr(Ir), _ptr(alpha))
+        _check(st, "ibmx_particle_integrals")
+        return Iu, Ir
+
+    def grid_mean(self, f):
+        """ibmx_grid_mean: per-component volume average (double[3] on the device)."""
+        import torch
+        _want(f, self.dtype, (3, self.n[2], self.n[1], self.n[0]), "f")
+        mean = torch.empty(3, dtype=torch.float64, device=f.device)
+        self._sync_stream()
+        _check(lib().ibmx_grid_mean(self.handle, _ptr(f), _ptr(mean)), "ibmx_grid_mean")
+        return mean
 
     def tune(self, u, f_tot, xp, up, wp, mask=None):
         self._sync_stream()

@@ -161,3 +161,28 @@ def _subcase(case, sample):
                      body=np.ascontiguousarray(case.body[:, idx]), dV=case.dV[sample],
                      u0=None, params=dict(case.params))
     return sub, idx
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_polydisperse_bed_particle_integrals(bed512, precision):
+    """Particle integrals of the 512^3 bed against the oracle, all 20000
+    particles."""
+    import torch
+    from paper_2109_03972_amd import ibmx
+    case, _, u0 = bed512
+    f64 = torch.float64
+    T = f64 if precision == "f64" else torch.float32
+    plan = ibmx.Plan.from_case(case, precision)
+    dev = u0.device
+    xp = torch.as_tensor(case.xp, dtype=f64).to(dev).contiguous()
+    rad = torch.as_tensor(case.radius, dtype=f64).to(dev).contiguous()
+    u = u0.to(T).contiguous()
+    Iu, Ir = plan.particle_integrals(u, xp, rad)
+    plan.check("bed integrals")
+    u_np = u.double().cpu().numpy()
+    ref = oracle.particle_integrals(case, u=u_np)
+    del u_np
+    for k, got in (("Iu", Iu), ("Ir", Ir)):
+        e = rel_err(got.cpu().numpy(), ref[k])
+        print(f"bed512 {precision} {k}: {e:.2e}", flush=True)
+        assert e <= 1e-11
