@@ -7,7 +7,7 @@
 namespace {
 
 constexpr int PI_THREADS = 256;
-constexpr int MEAN_BLOCKS = 1024;
+constexpr int MEAN_BLOCKS = 4096;
 
 // Volume fraction of the cell whose lowest corner is c0 (relative to the
 // particle centre) in a sphere of radius R: the signed corner distances
@@ -31,8 +31,9 @@ __device__ __forceinline__ double cell_alpha(const double *c0, double h, double 
 // bounding box.  Cells whose centre lies deeper than half a cell diagonal
 // inside (outside) the surface have every corner inside (outside) and take
 // alpha = 1 (0) without the corner distances, which is what the corner
-// formula gives for them.  FP64 sums: per thread in cell order, per wave by a
-// fixed shuffle tree, over the waves in wave order.
+// formula gives for them; the test compares squared distances.  FP64 sums:
+// per thread in cell order, per wave by a fixed shuffle tree, over the waves
+// in wave order.
 template <typename T>
 __global__ __launch_bounds__(PI_THREADS) void k_particle_integrals(GridC g, int np,
                                                                    const double *__restrict__ xp,
@@ -48,28 +49,30 @@ __global__ __launch_bounds__(PI_THREADS) void k_particle_integrals(GridC g, int 
     const double h = g.h, h3 = h * h * h, half_diag = 0.5 * sqrt(3.0) * h;
     const double R = radius[p];
     double x[3];
-    long long lo[3], ext[3];
+    int lo[3], ext[3];
     for (int a = 0; a < 3; ++a) {
         x[a] = xp[(size_t)a * np + p];
         if (g.periodic[a]) {
             const double L = g.n[a] * h;
             x[a] = x[a] - floor((x[a] - g.origin[a]) / L) * L;
         }
-        lo[a] = (long long)floor((x[a] - R - g.origin[a]) / h);
-        ext[a] = (long long)floor((x[a] + R - g.origin[a]) / h) - lo[a] + 1;
+        lo[a] = (int)floor((x[a] - R - g.origin[a]) / h);
+        ext[a] = (int)floor((x[a] + R - g.origin[a]) / h) - lo[a] + 1;
     }
-    const long long total = ext[0] * ext[1] * ext[2];
+    const int total = ext[0] * ext[1] * ext[2], exy = ext[0] * ext[1];
+    const double r_in = R - half_diag, r_out = R + half_diag;
+    const double r_in2 = r_in > 0.0 ? r_in * r_in : -1.0, r_out2 = r_out * r_out;
     const long long N = g.nodes;
     double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (long long q = threadIdx.x; q < total; q += blockDim.x) {
-        const long long c[3] = {lo[0] + q % ext[0], lo[1] + (q / ext[0]) % ext[1],
-                                lo[2] + q / (ext[0] * ext[1])};
-        long long gc[3];
+    for (int q = threadIdx.x; q < total; q += blockDim.x) {
+        const int qz = q / exy, qr = q - qz * exy, qy = qr / ext[0];
+        const int c[3] = {lo[0] + qr - qy * ext[0], lo[1] + qy, lo[2] + qz};
+        int gc[3];
         bool in = true;
         for (int a = 0; a < 3; ++a) {
             gc[a] = c[a];
             if (g.periodic[a])
-                gc[a] = ((gc[a] % g.n[a]) + g.n[a]) % g.n[a];
+                gc[a] = gc[a] < 0 ? gc[a] + g.n[a] : (gc[a] >= g.n[a] ? gc[a] - g.n[a] : gc[a]);
             else if (gc[a] < 0 || gc[a] >= g.n[a])
                 in = false;
         }
@@ -78,17 +81,17 @@ __global__ __launch_bounds__(PI_THREADS) void k_particle_integrals(GridC g, int 
         const double c0[3] = {g.origin[0] + c[0] * h - x[0], g.origin[1] + c[1] * h - x[1],
                               g.origin[2] + c[2] * h - x[2]};
         const double r[3] = {c0[0] + 0.5 * h, c0[1] + 0.5 * h, c0[2] + 0.5 * h};
-        const double dc = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+        const double dc2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
         double alpha;
-        if (dc + half_diag <= R)
+        if (dc2 <= r_in2)
             alpha = 1.0;
-        else if (dc - half_diag >= R)
+        else if (dc2 >= r_out2)
             continue;
         else
             alpha = cell_alpha(c0, h, R);
         if (alpha == 0.0)
             continue;
-        const long long gi = (gc[2] * g.n[1] + gc[1]) * g.n[0] + gc[0];
+        const long long gi = ((long long)gc[2] * g.n[1] + gc[1]) * g.n[0] + gc[0];
         const double uc[3] = {(double)u[gi], (double)u[N + gi], (double)u[2 * N + gi]};
         const double w = alpha * h3;
         s[0] += w * uc[0];
@@ -131,10 +134,29 @@ __global__ __launch_bounds__(256) void k_mean_partial(const T *__restrict__ f, l
     const long long lo = (long long)blockIdx.x * chunk;
     const long long hi = lo + chunk < N ? lo + chunk : N;
     const int wv = threadIdx.x / IBMX_WAVE, lane = threadIdx.x & (IBMX_WAVE - 1);
+    constexpr int E = 16 / (int)sizeof(T);
     for (int a = 0; a < 3; ++a) {
+        const T *fa = f + (size_t)a * N;
         double s = 0.0;
-        for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x)
-            s += (double)f[(size_t)a * N + i];
+        if (((size_t)fa & 15) == 0 && lo % E == 0) {
+            // 16-byte packets over the chunk, elements for its tail
+            const long long nv = (hi - lo) / E;
+            struct alignas(16) Packet {
+                T e[E];
+            };
+            const Packet *pk = reinterpret_cast<const Packet *>(fa + lo);
+            for (long long v = threadIdx.x; v < nv; v += blockDim.x) {
+                const Packet q = pk[v];
+#pragma unroll
+                for (int k = 0; k < E; ++k)
+                    s += (double)q.e[k];
+            }
+            for (long long i = lo + nv * E + threadIdx.x; i < hi; i += blockDim.x)
+                s += (double)fa[i];
+        } else {
+            for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x)
+                s += (double)fa[i];
+        }
         s = wave_sum(s);
         if (lane == 0)
             wsum[wv] = s;
