@@ -181,6 +181,12 @@ def run_gpu(case, precision, steps, warmup, profile=True, tune=True, tile=None):
         particle_integrals_ms=time_call(lambda: plan.particle_integrals(u, D["xp"], D["radius"])),
         grid_mean_ms=time_call(lambda: plan.grid_mean(f)))
     plan.check("integrals")
+    # reverse-mode derivative of one forcing call (replay + adjoint passes)
+    g_S = torch.ones((3, case.np_), dtype=f64, device=dev)
+    extras["backward_ms"] = time_call(
+        lambda: plan.forcing_backward(u, D["xp"], D["up"], D["wp"], mask, f, None, g_S, None),
+        reps=2)
+    plan.check("backward")
     if not profile:
         st = plan.stats()
     out = dict(ms_per_step=ms, ms_per_step_graph=ms_graph, wall_s=wall, stats=st, n_iter=n_iter,
@@ -328,6 +334,9 @@ def main():
             note="level-set fluid integrals over all particles (one call, FP32 grid, "
                  "FP64 geometry and sums); not part of the step"),
         grid_mean_ms=r32["extras"]["grid_mean_ms"],
+        backward=dict(ms=r32["extras"]["backward_ms"],
+                      note="ibmx_forcing_backward of one call (FP32): binning, replay of the "
+                           "passes with the Jacobians, adjoint passes; not part of the step"),
         pass_rate=n_act * n_iter / (sum(km[k] for k in ("interp", "spread")) / steps_done
                                     * 1e-3),
     )
