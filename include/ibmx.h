@@ -27,13 +27,18 @@
  *     named *_host.  The caller owns every buffer; the library only reads
  *     or writes it inside the call, asynchronously on the plan's stream, so
  *     buffers must stay valid until the stream reaches the call.
- *   * Compute calls never synchronise the stream and, apart from the first
- *     ibmx_forcing_backward call on a plan (which sizes its replay
- *     workspace) and ibmx_tune, allocate nothing; ibmx_forcing and
- *     ibmx_pairs can be captured into a HIP graph (ibmx_forcing_graph does
- *     that for the forcing loop).  Errors that only the device can see
- *     (a delta support crossing a wall, a list capacity exceeded) are
+ *   * Compute calls never synchronise the stream and allocate nothing, with
+ *     three exceptions that allocate (and so may synchronise the device):
+ *     the first ibmx_forcing_backward call on a plan sizes its replay
+ *     workspace, ibmx_pairs grows its cell workspace the first time the
+ *     cell grid (set by radius_max and gap_cut) has more cells than on
+ *     earlier calls, and ibmx_tune.  ibmx_forcing can be captured into a
+ *     HIP graph (ibmx_forcing_graph does that), and so can ibmx_pairs once
+ *     its cell workspace has been sized.  Errors that only the device can
+ *     see (a delta support crossing a wall, a list capacity exceeded) are
  *     recorded in the plan and returned by ibmx_plan_status().
+ *   * A plan is used by one host thread at a time; calls on one plan are
+ *     ordered by its stream.
  *   * No exception, abort or exit crosses this interface.
  */
 #ifndef IBMX_H
