@@ -8,6 +8,7 @@ code with the HIP library.  ``build()`` compiles ``ibmx_oracle.c`` with gcc
 from __future__ import annotations
 
 import ctypes
+import functools
 import os
 import subprocess
 from typing import Optional
@@ -56,6 +57,11 @@ def lib():
         L.ref_pairs_brute.argtypes = [P, d, P, P, i, P, P, d, i, P, P, P]
         L.ref_walls.restype = i
         L.ref_walls.argtypes = [P, d, P, P, i, P, P, d, i, P, P, P]
+        L.ref_actm_coefficients.restype = i
+        L.ref_actm_coefficients.argtypes = [d, d, P, P]
+        L.ref_particle_substeps.restype = i
+        L.ref_particle_substeps.argtypes = [P, d, P, P, i, P, P, P, P, P, P, P, P, d, i, i, P, i,
+                                            P, P, P, P, P]
         L.ref_pair_forces.restype = i
         L.ref_pair_forces.argtypes = [P, d, P, P, i, P, P, P, P, P, P, i, P, i, P,
                                       i, P, P, i, P, P, P, P, P, P]
@@ -209,15 +215,36 @@ def pairs(case, xp=None, gap_cut=None, cap=None):
                 walls=np.ascontiguousarray(wl[:, :kw]), wgap=wg[:kw].copy())
 
 
+HIST = 4   # history rows per contact: tangential spring (3), impact speed
+
+
+@functools.lru_cache(maxsize=None)
+def actm_coefficients(e: float, p: float = 1.5):
+    """(K, D) of the normal collision ODE in contact-time units (Sec. 2.2.7,
+    eq. ode): z'' + D z' + K z^p = 0 closes at t = 1 with rebound -e."""
+    K = ctypes.c_double()
+    D = ctypes.c_double()
+    st = lib().ref_actm_coefficients(float(e), float(p), ctypes.byref(K), ctypes.byref(D))
+    if st != OK:
+        raise OracleError(st)
+    return K.value, D.value
+
+
 def collision_params(prm) -> np.ndarray:
+    model = int(prm.get("normal_model", 0))
+    K, D = actm_coefficients(float(prm["e_dry"])) if model == 1 else (0.0, 0.0)
+    g = prm.get("gravity", (0.0, 0.0, 0.0))
     return np.array([prm["rho_f"], prm["nu_f"], prm["eps_sep"], prm["lub_C"], prm["zeta_min_factor"],
-                     prm["e_dry"], prm["T_c"], prm["mu_s"], prm["mu_k"], prm["nu_poi"], prm["dt"]],
+                     prm["e_dry"], prm["T_c"], prm["mu_s"], prm["mu_k"], prm["nu_poi"], prm["dt"],
+                     model, prm.get("St_crit", 5.0), prm.get("kn_grav_eps", 1e-3),
+                     g[0], g[1], g[2], K, D, int(prm.get("st_switch", 0))],
                     dtype=np.float64)
 
 
 def pair_forces(case, plist, xp=None, up=None, wp=None, prev=None, params=None):
     """Collision force/torque for the lists in ``plist`` (from ``pairs``).
-    ``prev`` = dict(pairs, hist, walls, whist) of a previous call or None."""
+    ``prev`` = dict(pairs, hist, walls, whist) of a previous call or None;
+    histories are [4][n] (tangential spring, impact speed)."""
     n, h, origin, per = _grid(case)
     npart = case.np_
     xp_ = _f64(case.xp if xp is None else xp)
@@ -228,14 +255,15 @@ def pair_forces(case, plist, xp=None, up=None, wp=None, prev=None, params=None):
     wl = _i32(plist["walls"])
     npairs, nwall = pr.shape[1], wl.shape[1]
     if prev is None:
-        prev = dict(pairs=np.zeros((2, 0), np.int32), hist=np.zeros((3, 0)),
-                    walls=np.zeros((2, 0), np.int32), whist=np.zeros((3, 0)))
+        prev = dict(pairs=np.zeros((2, 0), np.int32), hist=np.zeros((HIST, 0)),
+                    walls=np.zeros((2, 0), np.int32), whist=np.zeros((HIST, 0)))
     ppr, phs = _i32(prev["pairs"]), _f64(prev["hist"])
     pwl, pwh = _i32(prev["walls"]), _f64(prev["whist"])
+    assert phs.shape[0] == HIST and pwh.shape[0] == HIST
     Fc = np.zeros((3, npart))
     Tc = np.zeros((3, npart))
-    hist = np.zeros((3, npairs))
-    whist = np.zeros((3, nwall))
+    hist = np.zeros((HIST, npairs))
+    whist = np.zeros((HIST, nwall))
     st = lib().ref_pair_forces(_p(n), h, _p(origin), _p(per), npart, _p(xp_), _p(_f64(case.radius)),
                                _p(_f64(case.mass)), _p(up_), _p(wp_), _p(cp),
                                npairs, _p(pr), nwall, _p(wl),
@@ -244,6 +272,37 @@ def pair_forces(case, plist, xp=None, up=None, wp=None, prev=None, params=None):
     if st != OK:
         raise OracleError(st)
     return dict(Fc=Fc, Tc=Tc, hist=hist, whist=whist)
+
+
+def particle_substeps(case, plist, dt_total, n_sub, Fh=None, Th=None, hist=None, whist=None,
+                      xp=None, up=None, wp=None, params=None):
+    """Advance (x_p, u_p, omega_p) by dt_total in n_sub Runge-Kutta
+    sub-steps (Sec. 2.2.10) on the fixed lists ``plist``; histories aligned
+    with the lists ([4][n], zero = no history).  Returns the new state, the
+    committed histories and the collision force/torque at the final state."""
+    n, h, origin, per = _grid(case)
+    npart = case.np_
+    xp_ = _f64(case.xp if xp is None else xp).copy()
+    up_ = _f64(case.up if up is None else up).copy()
+    wp_ = _f64(case.wp if wp is None else wp).copy()
+    cp = collision_params(params or case.params)
+    pr = _i32(plist["pairs"])
+    wl = _i32(plist["walls"])
+    npairs, nwall = pr.shape[1], wl.shape[1]
+    hs = np.zeros((HIST, npairs)) if hist is None else _f64(hist).copy()
+    wh = np.zeros((HIST, nwall)) if whist is None else _f64(whist).copy()
+    assert hs.shape == (HIST, npairs) and wh.shape == (HIST, nwall)
+    Fh_ = None if Fh is None else _f64(Fh)
+    Th_ = None if Th is None else _f64(Th)
+    Fc = np.zeros((3, npart))
+    Tc = np.zeros((3, npart))
+    st = lib().ref_particle_substeps(_p(n), h, _p(origin), _p(per), npart, _p(xp_), _p(up_), _p(wp_),
+                                     _p(_f64(case.radius)), _p(_f64(case.mass)), _p(cp), _p(Fh_),
+                                     _p(Th_), float(dt_total), int(n_sub), npairs, _p(pr), nwall,
+                                     _p(wl), _p(hs), _p(wh), _p(Fc), _p(Tc))
+    if st != OK:
+        raise OracleError(st)
+    return dict(xp=xp_, up=up_, wp=wp_, hist=hs, whist=wh, Fc=Fc, Tc=Tc)
 
 
 def marker_mask(case, plist, xp=None, mode=None, seed=None, eps_sep=None):

@@ -646,32 +646,211 @@ int ref_walls(const int *n, double h, const double *origin, const int *periodic,
     return cnt > cap ? R_ECAPACITY : R_OK;
 }
 
+/*
+ * ACTM coefficients of the normal contact (Sec. 2.2.7, eq. ode).  In the
+ * units z = zeta / (u_in T_c), t = time / T_c the normal overlap of a
+ * contact obeys
+ *     z'' + D z' + K z^p = 0,   z(0) = 0,  z'(0) = 1,
+ * with k_n = K m_eff / (u_in^(p-1) T_c^(p+1)) and d_n = D m_eff / T_c, so the
+ * two end conditions of the paper (the overlap closes at T_c, the rebound
+ * speed is e_dry times the impact speed) fix K and D for given e_dry: the
+ * contact must end at t = 1 with z'(1) = -e.  p = 3/2 is the Hertz law of
+ * eq. hertz-contact; p = 1 gives the linear spring-dashpot, whose closed
+ * form pins this solver.
+ *
+ * contact_run integrates the equation with classical RK4 at a fixed step
+ * until z returns to zero (force zero once z <= 0), locates the crossing
+ * on the cubic Hermite interpolant of the last step and takes one partial
+ * RK4 step to it.  Returns 0 if the overlap does not close before t_max.
+ */
+static double actm_force(double K, double p, double z)
+{
+    if (z <= 0.0)
+        return 0.0;
+    if (p == 1.0)
+        return K * z;
+    if (p == 1.5)
+        return K * z * sqrt(z);
+    return K * pow(z, p);
+}
+
+static void actm_step(double K, double D, double p, double h, double z, double v, double *zn,
+                      double *vn)
+{
+    double k1z = v, k1v = -D * v - actm_force(K, p, z);
+    double z2 = z + 0.5 * h * k1z, v2 = v + 0.5 * h * k1v;
+    double k2z = v2, k2v = -D * v2 - actm_force(K, p, z2);
+    double z3 = z + 0.5 * h * k2z, v3 = v + 0.5 * h * k2v;
+    double k3z = v3, k3v = -D * v3 - actm_force(K, p, z3);
+    double z4 = z + h * k3z, v4 = v + h * k3v;
+    double k4z = v4, k4v = -D * v4 - actm_force(K, p, z4);
+    *zn = z + h / 6.0 * (k1z + 2.0 * k2z + 2.0 * k3z + k4z);
+    *vn = v + h / 6.0 * (k1v + 2.0 * k2v + 2.0 * k3v + k4v);
+}
+
+static int contact_run(double K, double D, double p, double h, double t_max, double *T,
+                       double *v_end)
+{
+    double t = 0.0, z = 0.0, v = 1.0;
+    long nmax = (long)(t_max / h) + 1;
+    for (long s = 0; s < nmax; ++s) {
+        double zn, vn;
+        actm_step(K, D, p, h, z, v, &zn, &vn);
+        if (s > 0 && zn <= 0.0) {
+            /* crossing inside [t, t + h]: bisection on the Hermite cubic */
+            double a0 = 0.0, a1 = 1.0;
+            double fa0 = -D * v - actm_force(K, p, z);   /* unused slopes kept for clarity */
+            (void)fa0;
+            for (int it = 0; it < 200; ++it) {
+                double s_ = 0.5 * (a0 + a1);
+                double h00 = (1 + 2 * s_) * (1 - s_) * (1 - s_), h10 = s_ * (1 - s_) * (1 - s_);
+                double h01 = s_ * s_ * (3 - 2 * s_), h11 = s_ * s_ * (s_ - 1);
+                double zs = h00 * z + h10 * h * v + h01 * zn + h11 * h * vn;
+                if (zs > 0.0)
+                    a0 = s_;
+                else
+                    a1 = s_;
+            }
+            double tau = 0.5 * (a0 + a1) * h, ze, ve;
+            actm_step(K, D, p, tau, z, v, &ze, &ve);
+            *T = t + tau;
+            *v_end = ve;
+            return 1;
+        }
+        z = zn;
+        v = vn;
+        t += h;
+    }
+    return 0;
+}
+
+/*
+ * K and D for restitution e in (0, 1] and exponent p: nested bisection.
+ * Inner: for a damping D the contact duration falls monotonically with K;
+ * bisect log K until the duration is 1.  Outer: with the duration held at
+ * 1 the rebound ratio falls monotonically with D; bisect D until it is e.
+ */
+static double actm_K_for_unit_duration(double D, double p, double h)
+{
+    double lo = log(1e-3), hi = log(1e5);
+    for (int it = 0; it < 64; ++it) {
+        double mid = 0.5 * (lo + hi), T, v;
+        int ok = contact_run(exp(mid), D, p, h, 4.0, &T, &v);
+        if (!ok || T > 1.0)
+            lo = mid;     /* too soft: the contact lasts too long */
+        else
+            hi = mid;
+    }
+    return exp(0.5 * (lo + hi));
+}
+
+int ref_actm_coefficients(double e, double p, double *K_out, double *D_out)
+{
+    if (!(e > 0.0 && e <= 1.0) || !(p >= 1.0 && p <= 2.0))
+        return R_EINVAL;
+    const double h = 1.0 / 20000.0;
+    if (e == 1.0) {
+        *D_out = 0.0;
+        *K_out = actm_K_for_unit_duration(0.0, p, h);
+        return R_OK;
+    }
+    double lo = 0.0, hi = 8.0 * (-log(e)) + 1.0;
+    for (int it = 0; it < 60; ++it) {
+        double D = 0.5 * (lo + hi);
+        double K = actm_K_for_unit_duration(D, p, h), T, v;
+        contact_run(K, D, p, h, 4.0, &T, &v);
+        if (-v > e)
+            lo = D;       /* rebound too strong: more damping */
+        else
+            hi = D;
+    }
+    *D_out = 0.5 * (lo + hi);
+    *K_out = actm_K_for_unit_duration(*D_out, p, h);
+    return R_OK;
+}
+
 typedef struct {
     double rho_f, nu_f, eps_sep, lub_C, zeta_min_factor, e_dry, T_c, mu_s, mu_k, nu_poi, dt, h;
+    int normal_model;      /* 0 linear spring-dashpot, 1 Hertz with ACTM */
+    double St_crit, kn_grav_eps, g[3], K_hz, D_hz;
+    int st_switch;
 } coll_params;
+
+#define HIST 4   /* history rows per contact: tangential spring (3), impact speed */
+
+static coll_params coll_from(const double *cpar, double h)
+{
+    coll_params P;
+    P.rho_f = cpar[0];
+    P.nu_f = cpar[1];
+    P.eps_sep = cpar[2];
+    P.lub_C = cpar[3];
+    P.zeta_min_factor = cpar[4];
+    P.e_dry = cpar[5];
+    P.T_c = cpar[6];
+    P.mu_s = cpar[7];
+    P.mu_k = cpar[8];
+    P.nu_poi = cpar[9];
+    P.dt = cpar[10];
+    P.h = h;
+    P.normal_model = (int)cpar[11];
+    P.St_crit = cpar[12];
+    P.kn_grav_eps = cpar[13];
+    P.g[0] = cpar[14];
+    P.g[1] = cpar[15];
+    P.g[2] = cpar[16];
+    P.K_hz = cpar[17];
+    P.D_hz = cpar[18];
+    P.st_switch = (int)cpar[19];
+    return P;
+}
+
+/* rho_p d_p of a sphere of mass m and radius R: 3 m / (2 pi R^2). */
+static double rho_d(double m, double R) { return 3.0 * m / (2.0 * M_PI * R * R); }
+
+/* Gravity stiffness m g (eps d / 2)^(-3/2) of one particle (Sec. 2.2.7). */
+static double kn_grav_one(const coll_params *P, double m, double R)
+{
+    double g = sqrt(P->g[0] * P->g[0] + P->g[1] * P->g[1] + P->g[2] * P->g[2]);
+    double a = P->kn_grav_eps * R;
+    return m * g / (a * sqrt(a));
+}
 
 /*
  * Collision force on particle p from a partner across the contact plane
  * with unit normal nvec (pointing from p to the partner).  Inputs: surface
  * gap zeta, relative contact-point velocity g (Sec. 2.2.8: g_cp), effective
- * radius and mass, the tangential spring displacement of the previous call
- * (zt_old, zero for a new contact).  Returns F (force on p) and the updated
- * spring zt_new.
+ * radius and mass, rho d of the contact (for the Stokes number), the
+ * gravity stiffness of the contact, the history of the last committed state
+ * (tangential spring, impact speed; zero for a new contact) and the time
+ * dt since that state.  Returns F (force on p), the tangential part Ft and
+ * the updated history.
  *
  *   regime (Secs. 2.2.6-2.2.8, eq. f_int cases): contact if zeta < 0, lubrication if
  *   0 <= zeta < eps_sep, nothing otherwise.
  *   lubrication: F = -6 pi rho_f nu_f R_eff^2 psi / max(zeta_min, zeta) g_n,
  *     psi = erf(6 - C max(zeta_min, zeta)/h)/2 + 1/2 (Sec. 2.2.6, lubrication).
- *   normal contact: linear spring-dashpot F_n = -k_n |zeta| n - d_n g_n, with
- *     k_n, d_n the damped-oscillator coefficients giving restitution e_dry
- *     over the contact time T_c (the linear form of eq. ode).
+ *   impact speed u_in: the approach speed g . n at the first contact
+ *     evaluation (kept while the contact lasts, clamped at zero).
+ *   normal contact, linear: F_n = -k_n |zeta| n - d_n g_n, with k_n, d_n the
+ *     damped-oscillator coefficients giving restitution e_dry over the
+ *     contact time T_c (the linear form of eq. ode).
+ *   normal contact, Hertz (eq. hertz-contact): F_n = -k_n |zeta|^(3/2) n -
+ *     d_n g_n, k_n = K m_eff / (sqrt(u_in) T_c^(5/2)) and d_n = D m_eff / T_c
+ *     (ACTM, eq. ode, K and D from ref_actm_coefficients) while u_in exceeds
+ *     u_in,crit = 9 St_crit rho_f nu_f / (rho d) (eq. stokes_num); otherwise
+ *     k_n = max(k_n,crit, k_n,grav), k_n,crit being the ACTM stiffness at
+ *     u_in,crit.
  *   tangential contact (Sec. 2.2.8, tangential model): spring-dashpot
  *     F_dp = -k_t zeta_t - d_t g_t, capped by Coulomb friction; mu_s while
  *     sticking, mu_k when slipping, with the spring reset on slip.
+ *     k_t = 2 (1 - nu)/(2 - nu) times the normal spring's stiffness (k_n,
+ *     and for the Hertz law its secant k_n |zeta|^(1/2)).
  */
 static void contact_law(const coll_params *P, double zeta, const double *nvec, const double *g,
-                        double Reff, double meff, double zmin, const double *zt_old,
-                        double *F, double *Ft_out, double *zt_new)
+                        double Reff, double meff, double zmin, double rhod, double kgrav,
+                        const double *hist_old, double dt, double *F, double *Ft_out,
+                        double *hist_new)
 {
     double gn = g[0] * nvec[0] + g[1] * nvec[1] + g[2] * nvec[2];
     double gnv[3], gtv[3];
@@ -680,8 +859,9 @@ static void contact_law(const coll_params *P, double zeta, const double *nvec, c
         gtv[a] = g[a] - gnv[a];
         F[a] = 0.0;
         Ft_out[a] = 0.0;
-        zt_new[a] = 0.0;
     }
+    for (int a = 0; a < HIST; ++a)
+        hist_new[a] = 0.0;
     if (zeta >= P->eps_sep)
         return;
     if (zeta >= 0.0) {
@@ -692,20 +872,38 @@ static void contact_law(const coll_params *P, double zeta, const double *nvec, c
             F[a] = -coef * gnv[a];
         return;
     }
+    double u_in = hist_old[3] > 0.0 ? hist_old[3] : (gn > 0.0 ? gn : 0.0);
     double le = log(P->e_dry);
-    double kn = meff * (M_PI * M_PI + le * le) / (P->T_c * P->T_c);
-    double dn = -2.0 * meff * le / P->T_c;
-    double Fn[3];
-    for (int a = 0; a < 3; ++a)
-        Fn[a] = -kn * fabs(zeta) * nvec[a] - dn * gnv[a];
-    double kt = 2.0 * (1.0 - P->nu_poi) / (2.0 - P->nu_poi) * kn;
+    double ze = fabs(zeta);
+    double kn, dn, kspring, Fn[3];
+    if (P->normal_model == 1) {
+        double Tc52 = P->T_c * P->T_c * sqrt(P->T_c);
+        double u_crit = 9.0 * P->St_crit * P->rho_f * P->nu_f / rhod;
+        if (u_in > u_crit) {
+            kn = P->K_hz * meff / (sqrt(u_in) * Tc52);
+        } else {
+            double kcrit = u_crit > 0.0 ? P->K_hz * meff / (sqrt(u_crit) * Tc52) : 0.0;
+            kn = kcrit > kgrav ? kcrit : kgrav;
+        }
+        dn = P->D_hz * meff / P->T_c;
+        kspring = kn * sqrt(ze);
+        for (int a = 0; a < 3; ++a)
+            Fn[a] = -kn * (ze * sqrt(ze)) * nvec[a] - dn * gnv[a];
+    } else {
+        kn = meff * (M_PI * M_PI + le * le) / (P->T_c * P->T_c);
+        dn = -2.0 * meff * le / P->T_c;
+        kspring = kn;
+        for (int a = 0; a < 3; ++a)
+            Fn[a] = -kn * ze * nvec[a] - dn * gnv[a];
+    }
+    double kt = 2.0 * (1.0 - P->nu_poi) / (2.0 - P->nu_poi) * kspring;
     double dt_ = 2.0 * sqrt(meff * kt) * (-le) / sqrt(M_PI * M_PI + le * le);
     /* spring: previous displacement projected on the current tangent plane,
      * plus g_t dt */
-    double zon = zt_old[0] * nvec[0] + zt_old[1] * nvec[1] + zt_old[2] * nvec[2];
+    double zon = hist_old[0] * nvec[0] + hist_old[1] * nvec[1] + hist_old[2] * nvec[2];
     double zt[3], Fdp[3];
     for (int a = 0; a < 3; ++a) {
-        zt[a] = (zt_old[a] - zon * nvec[a]) + gtv[a] * P->dt;
+        zt[a] = (hist_old[a] - zon * nvec[a]) + gtv[a] * dt;
         Fdp[a] = -kt * zt[a] - dt_ * gtv[a];
     }
     double nFdp = sqrt(Fdp[0] * Fdp[0] + Fdp[1] * Fdp[1] + Fdp[2] * Fdp[2]);
@@ -723,8 +921,9 @@ static void contact_law(const coll_params *P, double zeta, const double *nvec, c
     for (int a = 0; a < 3; ++a) {
         F[a] = Fn[a] + Ft[a];
         Ft_out[a] = Ft[a];
-        zt_new[a] = zt[a];
+        hist_new[a] = zt[a];
     }
+    hist_new[3] = u_in;
 }
 
 static int find_pair(int n_in, const int *pairs_in, int i, int j)
@@ -735,6 +934,70 @@ static int find_pair(int n_in, const int *pairs_in, int i, int j)
     return -1;
 }
 
+/* Geometry and contact law of listed pair k = (p, q), p < q: force on p (F),
+ * the torques on p and q, and the new history. */
+static void pair_contact(const int *n, double h, const double *origin, const int *periodic,
+                         const coll_params *P, int np, const double *xp, const double *radius,
+                         const double *mass, const double *up, const double *wp, int p, int q,
+                         const double *hold, double dt, double *F, double *Tp, double *Tq,
+                         double *hnew)
+{
+    double dvec[3];
+    double d = sqrt(pair_disp(n, h, origin, periodic, np, xp, p, q, dvec));
+    double Rp = radius[p], Rq = radius[q];
+    double zeta = d - Rp - Rq;
+    double nvec[3] = {dvec[0] / d, dvec[1] / d, dvec[2] / d};
+    double Rpc = 0.5 * (d + Rp - Rq), Rqc = 0.5 * (d + Rq - Rp);
+    double wpn[3], wqn[3], g[3];
+    double wpp[3] = {wp[p], wp[np + p], wp[2 * np + p]};
+    double wqq[3] = {wp[q], wp[np + q], wp[2 * np + q]};
+    cross(wpp, nvec, wpn);
+    cross(wqq, nvec, wqn);
+    for (int a = 0; a < 3; ++a)
+        g[a] = (up[a * np + p] - up[a * np + q]) + Rpc * wpn[a] + Rqc * wqn[a];
+    double Reff = Rp * Rq / (Rp + Rq);
+    double meff = mass[p] * mass[q] / (mass[p] + mass[q]);
+    double zmin = P->zeta_min_factor * (Rp < Rq ? Rp : Rq);
+    double rhod = 0.5 * (rho_d(mass[p], Rp) + rho_d(mass[q], Rq));
+    double kg_p = kn_grav_one(P, mass[p], Rp), kg_q = kn_grav_one(P, mass[q], Rq);
+    double kgrav = kg_p > kg_q ? kg_p : kg_q;
+    double Ft[3], nxFt[3];
+    contact_law(P, zeta, nvec, g, Reff, meff, zmin, rhod, kgrav, hold, dt, F, Ft, hnew);
+    cross(nvec, Ft, nxFt);
+    for (int a = 0; a < 3; ++a) {
+        Tp[a] = Rpc * nxFt[a];
+        Tq[a] = Rqc * nxFt[a];
+    }
+}
+
+/* Wall entry (p, side): a wall is the limit R_q, m_q -> infinity at rest:
+ * R_eff = R_p, m_eff = m_p, lever arm |x_w - x_p| (Sec. 2.2.8). */
+static void wall_contact(const int *n, double h, const double *origin, const coll_params *P,
+                         int np, const double *xp, const double *radius, const double *mass,
+                         const double *up, const double *wp, int p, int side,
+                         const double *hold, double dt, double *F, double *T, double *hnew)
+{
+    int ax = side / 2, up_side = side % 2;
+    double L = n[ax] * h;
+    double x = xp[ax * np + p];
+    double dist = up_side == 0 ? (x - origin[ax]) : (origin[ax] + L - x);
+    double Rp = radius[p];
+    double zeta = dist - Rp;
+    double nvec[3] = {0.0, 0.0, 0.0};
+    nvec[ax] = up_side == 0 ? -1.0 : 1.0;
+    double wpp[3] = {wp[p], wp[np + p], wp[2 * np + p]};
+    double wpn[3], g[3];
+    cross(wpp, nvec, wpn);
+    for (int a = 0; a < 3; ++a)
+        g[a] = up[a * np + p] + dist * wpn[a];
+    double Ft[3], nxFt[3];
+    contact_law(P, zeta, nvec, g, Rp, mass[p], P->zeta_min_factor * Rp, rho_d(mass[p], Rp),
+                kn_grav_one(P, mass[p], Rp), hold, dt, F, Ft, hnew);
+    cross(nvec, Ft, nxFt);
+    for (int a = 0; a < 3; ++a)
+        T[a] = dist * nxFt[a];
+}
+
 /*
  * Collision force and torque on every particle (eq. f_int): the sum over
  * listed pairs and walls of F_n + F_t, and of R_cp n x F_t.  For a pair
@@ -743,89 +1006,325 @@ static int find_pair(int n_in, const int *pairs_in, int i, int j)
  * g = (u_p - u_q) + R_p,cp omega_p x n + R_q,cp omega_q x n.  p receives F,
  * q receives -F; both receive the torque R_cp n x F_t.  R_eff =
  * R_p R_q/(R_p + R_q), m_eff = m_p m_q/(m_p + m_q), zeta_min = factor *
- * min(R_p, R_q).  A wall is the limit R_q, m_q -> infinity at rest: R_eff =
- * R_p, m_eff = m_p, lever arm R_pw,cp = |x_w - x_p| (Sec. 2.2.8).
- * Spring history is looked up by the (i, j) key of the previous call's list
- * (and by (p, side) for walls).
+ * min(R_p, R_q), rho d = the mean of the two particles' rho_p d_p, k_n,grav
+ * = the larger of the two particles' values.
+ * History ([4][n]: spring, impact speed) is looked up by the (i, j) key of
+ * the previous call's list (and by (p, side) for walls); the spring
+ * advances by the parameter dt.  Each particle's force and torque are
+ * summed over its partners in increasing partner id, then its walls in
+ * increasing side.
  */
+typedef struct {
+    int key;     /* partner id, or np + side for a wall */
+    int k;       /* index in the pair or wall list */
+    int role;    /* 0: p is the first of the pair, 1: the second, 2: wall */
+} contact_ref;
+
+static int cmp_contact(const void *a, const void *b)
+{
+    const contact_ref *x = a, *y = b;
+    return (x->key > y->key) - (x->key < y->key);
+}
+
+static void sum_contacts(int np, int npairs, const int *pairs, int nwall, const int *walls,
+                         const double *pF, const double *pTp, const double *pTq,
+                         const double *wF, const double *wT, double *Fc, double *Tc)
+{
+    /* every contact of every particle, then sorted per particle by key */
+    int *cnt = calloc((size_t)np + 1, sizeof(int));
+    contact_ref *refs = malloc(sizeof(contact_ref) * (size_t)(2 * npairs + nwall + 1));
+    int *fill = calloc((size_t)np + 1, sizeof(int));
+    for (int k = 0; k < npairs; ++k) {
+        cnt[pairs[k] + 1]++;
+        cnt[pairs[npairs + k] + 1]++;
+    }
+    for (int k = 0; k < nwall; ++k)
+        cnt[walls[k] + 1]++;
+    for (int p = 0; p < np; ++p)
+        cnt[p + 1] += cnt[p];
+    for (int k = 0; k < npairs; ++k) {
+        int i = pairs[k], j = pairs[npairs + k];
+        contact_ref ri = {j, k, 0}, rj = {i, k, 1};
+        refs[cnt[i] + fill[i]++] = ri;
+        refs[cnt[j] + fill[j]++] = rj;
+    }
+    for (int k = 0; k < nwall; ++k) {
+        int p = walls[k];
+        contact_ref rw = {np + walls[nwall + k], k, 2};
+        refs[cnt[p] + fill[p]++] = rw;
+    }
+    for (int p = 0; p < np; ++p) {
+        qsort(refs + cnt[p], (size_t)(cnt[p + 1] - cnt[p]), sizeof(contact_ref), cmp_contact);
+        double F[3] = {0.0, 0.0, 0.0}, T[3] = {0.0, 0.0, 0.0};
+        for (int r = cnt[p]; r < cnt[p + 1]; ++r) {
+            int k = refs[r].k;
+            for (int a = 0; a < 3; ++a) {
+                if (refs[r].role == 0) {
+                    F[a] = F[a] + pF[a * npairs + k];
+                    T[a] = T[a] + pTp[a * npairs + k];
+                } else if (refs[r].role == 1) {
+                    F[a] = F[a] - pF[a * npairs + k];
+                    T[a] = T[a] + pTq[a * npairs + k];
+                } else {
+                    F[a] = F[a] + wF[a * nwall + k];
+                    T[a] = T[a] + wT[a * nwall + k];
+                }
+            }
+        }
+        for (int a = 0; a < 3; ++a) {
+            Fc[a * np + p] = F[a];
+            Tc[a * np + p] = T[a];
+        }
+    }
+    free(cnt);
+    free(refs);
+    free(fill);
+}
+
+/* One evaluation of every listed contact at the given particle state, with
+ * history hold ([4][n] aligned with the lists) and spring time step dt. */
+static int eval_contacts(const int *n, double h, const double *origin, const int *periodic,
+                         const coll_params *P, int np, const double *xp, const double *radius,
+                         const double *mass, const double *up, const double *wp, int npairs,
+                         const int *pairs, int nwall, const int *walls, const double *hold,
+                         const double *whold, double dt, double *hnew, double *whnew,
+                         double *Fc, double *Tc)
+{
+    double *pF = calloc(3 * (size_t)(npairs + 1), sizeof(double));
+    double *pTp = calloc(3 * (size_t)(npairs + 1), sizeof(double));
+    double *pTq = calloc(3 * (size_t)(npairs + 1), sizeof(double));
+    double *wF = calloc(3 * (size_t)(nwall + 1), sizeof(double));
+    double *wT = calloc(3 * (size_t)(nwall + 1), sizeof(double));
+    if (!pF || !pTp || !pTq || !wF || !wT) {
+        free(pF); free(pTp); free(pTq); free(wF); free(wT);
+        return R_EINVAL;
+    }
+    for (int k = 0; k < npairs; ++k) {
+        double ho[HIST], hn[HIST], F[3], Tp[3], Tq[3];
+        for (int a = 0; a < HIST; ++a)
+            ho[a] = hold[a * npairs + k];
+        pair_contact(n, h, origin, periodic, P, np, xp, radius, mass, up, wp, pairs[k],
+                     pairs[npairs + k], ho, dt, F, Tp, Tq, hn);
+        for (int a = 0; a < 3; ++a) {
+            pF[a * npairs + k] = F[a];
+            pTp[a * npairs + k] = Tp[a];
+            pTq[a * npairs + k] = Tq[a];
+        }
+        if (hnew)
+            for (int a = 0; a < HIST; ++a)
+                hnew[a * npairs + k] = hn[a];
+    }
+    for (int k = 0; k < nwall; ++k) {
+        double ho[HIST], hn[HIST], F[3], T[3];
+        for (int a = 0; a < HIST; ++a)
+            ho[a] = whold[a * nwall + k];
+        wall_contact(n, h, origin, P, np, xp, radius, mass, up, wp, walls[k], walls[nwall + k],
+                     ho, dt, F, T, hn);
+        for (int a = 0; a < 3; ++a) {
+            wF[a * nwall + k] = F[a];
+            wT[a * nwall + k] = T[a];
+        }
+        if (whnew)
+            for (int a = 0; a < HIST; ++a)
+                whnew[a * nwall + k] = hn[a];
+    }
+    sum_contacts(np, npairs, pairs, nwall, walls, pF, pTp, pTq, wF, wT, Fc, Tc);
+    free(pF); free(pTp); free(pTq); free(wF); free(wT);
+    return R_OK;
+}
+
 int ref_pair_forces(const int *n, double h, const double *origin, const int *periodic,
                     int np, const double *xp, const double *radius, const double *mass,
-                    const double *up, const double *wp, const double *cpar /* [11] */,
+                    const double *up, const double *wp, const double *cpar /* [20] */,
                     int npairs, const int *pairs, int nwall, const int *walls,
                     int npairs_in, const int *pairs_in, const double *hist_in,
                     int nwall_in, const int *walls_in, const double *whist_in,
                     double *Fc, double *Tc, double *hist_out, double *whist_out)
 {
-    coll_params P = {cpar[0], cpar[1], cpar[2], cpar[3], cpar[4], cpar[5], cpar[6],
-                     cpar[7], cpar[8], cpar[9], cpar[10], h};
-    for (int i = 0; i < 3 * np; ++i) {
-        Fc[i] = 0.0;
-        Tc[i] = 0.0;
+    coll_params P = coll_from(cpar, h);
+    /* history of the previous call, aligned with the new lists */
+    double *hold = calloc(HIST * (size_t)(npairs + 1), sizeof(double));
+    double *whold = calloc(HIST * (size_t)(nwall + 1), sizeof(double));
+    if (!hold || !whold) {
+        free(hold); free(whold);
+        return R_EINVAL;
     }
     for (int k = 0; k < npairs; ++k) {
-        int p = pairs[k], q = pairs[npairs + k];
-        double dvec[3];
-        double d = sqrt(pair_disp(n, h, origin, periodic, np, xp, p, q, dvec));
-        double Rp = radius[p], Rq = radius[q];
-        double zeta = d - Rp - Rq;
-        double nvec[3] = {dvec[0] / d, dvec[1] / d, dvec[2] / d};
-        double Rpc = 0.5 * (d + Rp - Rq), Rqc = 0.5 * (d + Rq - Rp);
-        double wpn[3], wqn[3], g[3];
-        double wpp[3] = {wp[p], wp[np + p], wp[2 * np + p]};
-        double wqq[3] = {wp[q], wp[np + q], wp[2 * np + q]};
-        cross(wpp, nvec, wpn);
-        cross(wqq, nvec, wqn);
-        for (int a = 0; a < 3; ++a)
-            g[a] = (up[a * np + p] - up[a * np + q]) + Rpc * wpn[a] + Rqc * wqn[a];
-        double Reff = Rp * Rq / (Rp + Rq);
-        double meff = mass[p] * mass[q] / (mass[p] + mass[q]);
-        double zmin = P.zeta_min_factor * (Rp < Rq ? Rp : Rq);
-        double zold[3] = {0.0, 0.0, 0.0};
-        int kin = find_pair(npairs_in, pairs_in, p, q);
+        int kin = find_pair(npairs_in, pairs_in, pairs[k], pairs[npairs + k]);
         if (kin >= 0)
-            for (int a = 0; a < 3; ++a)
-                zold[a] = hist_in[a * npairs_in + kin];
-        double F[3], Ft[3], zt[3], nxFt[3];
-        contact_law(&P, zeta, nvec, g, Reff, meff, zmin, zold, F, Ft, zt);
-        cross(nvec, Ft, nxFt);
-        for (int a = 0; a < 3; ++a) {
-            Fc[a * np + p] += F[a];
-            Fc[a * np + q] -= F[a];
-            Tc[a * np + p] += Rpc * nxFt[a];
-            Tc[a * np + q] += Rqc * nxFt[a];
-            hist_out[a * npairs + k] = zt[a];
-        }
+            for (int a = 0; a < HIST; ++a)
+                hold[a * npairs + k] = hist_in[a * npairs_in + kin];
     }
-    for (int k = 0; k < nwall; ++k) {
-        int p = walls[k], side = walls[nwall + k];
-        int ax = side / 2, up_side = side % 2;
-        double L = n[ax] * h;
-        double x = xp[ax * np + p];
-        double dist = up_side == 0 ? (x - origin[ax]) : (origin[ax] + L - x);
-        double Rp = radius[p];
-        double zeta = dist - Rp;
-        double nvec[3] = {0.0, 0.0, 0.0};
-        nvec[ax] = up_side == 0 ? -1.0 : 1.0;
-        double wpp[3] = {wp[p], wp[np + p], wp[2 * np + p]};
-        double wpn[3], g[3];
-        cross(wpp, nvec, wpn);
-        for (int a = 0; a < 3; ++a)
-            g[a] = up[a * np + p] + dist * wpn[a];
-        double zold[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < nwall; ++k)
         for (int kk = 0; kk < nwall_in; ++kk)
-            if (walls_in[kk] == p && walls_in[nwall_in + kk] == side)
-                for (int a = 0; a < 3; ++a)
-                    zold[a] = whist_in[a * nwall_in + kk];
-        double F[3], Ft[3], zt[3], nxFt[3];
-        contact_law(&P, zeta, nvec, g, Rp, mass[p], P.zeta_min_factor * Rp, zold, F, Ft, zt);
-        cross(nvec, Ft, nxFt);
-        for (int a = 0; a < 3; ++a) {
-            Fc[a * np + p] += F[a];
-            Tc[a * np + p] += dist * nxFt[a];
-            whist_out[a * nwall + k] = zt[a];
+            if (walls_in[kk] == walls[k] && walls_in[nwall_in + kk] == walls[nwall + k])
+                for (int a = 0; a < HIST; ++a)
+                    whold[a * nwall + k] = whist_in[a * nwall_in + kk];
+    int st = eval_contacts(n, h, origin, periodic, &P, np, xp, radius, mass, up, wp, npairs,
+                           pairs, nwall, walls, hold, whold, P.dt, hist_out, whist_out, Fc, Tc);
+    free(hold);
+    free(whold);
+    return st;
+}
+
+/*
+ * Particle sub-stepping (Sec. 2.2.10): the particle state (x_p, u_p,
+ * omega_p) advances by dt_total in n_sub sub-steps of dts = dt_total /
+ * n_sub, each the three-stage Runge-Kutta predictor-corrector of the
+ * improved particle update with the low-storage coefficients of Rai and
+ * Moin: alpha = (4/15, 1/15, 1/6), gamma = (8/15, 5/12, 3/4), zeta = (0,
+ * -17/60, -5/12).  For stage k, with F_c(s) the collision force at state s:
+ *   u~ = u^{k-1} + dts/m (2 alpha_k F_h + gamma_k F_c(s^{k-1}) + zeta_k F_c(s^{k-2}))
+ *        + 2 alpha_k dts g'
+ *   w~ = w^{k-1} + dts/I (2 alpha_k T_h + gamma_k T_c(s^{k-1}) + zeta_k T_c(s^{k-2}))
+ *   x~ = x^{k-1} + alpha_k dts (u~ + u^{k-1})
+ *   u^k, w^k, x^k: the same with F_c(s~) in place of F_c(s^{k-1}) and
+ *        F_c(s^{k-1}) in place of F_c(s^{k-2}).
+ * g' = (1 - rho_f / rho_p) g, rho_p = m_p / (4/3 pi R_p^3), I_p = 2/5 m_p R_p^2.
+ * F_h, T_h (the hydrodynamic force and torque) are held for the call; with
+ * the St switch on, a particle whose committed contacts all have impact
+ * Stokes numbers <= St_crit gets F_h = T_h = 0.
+ * Contacts are evaluated on the given lists (built by the caller with a
+ * gap cut-off that covers the motion of the call).  The history is
+ * committed at each accepted state s^k (evaluated there with the spring
+ * advanced by the time since the previous accepted state); the predictor
+ * state s~ uses the committed history and the stage's time 2 alpha_k dts.
+ * The call starts by evaluating the input state with the input history
+ * (dt 0) and ends by evaluating the final state, whose history and forces
+ * it returns.
+ */
+int ref_particle_substeps(const int *n, double h, const double *origin, const int *periodic,
+                          int np, double *xp, double *up, double *wp, const double *radius,
+                          const double *mass, const double *cpar, const double *Fh,
+                          const double *Th, double dt_total, int n_sub, int npairs,
+                          const int *pairs, int nwall, const int *walls, double *hist,
+                          double *whist, double *Fc_out, double *Tc_out)
+{
+    static const double alpha[3] = {4.0 / 15.0, 1.0 / 15.0, 1.0 / 6.0};
+    static const double gamma_[3] = {8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0};
+    static const double zeta_[3] = {0.0, -17.0 / 60.0, -5.0 / 12.0};
+    if (n_sub < 1 || np < 0)
+        return R_EINVAL;
+    coll_params P = coll_from(cpar, h);
+    const double dts = dt_total / n_sub;
+    size_t N3 = 3 * (size_t)(np > 0 ? np : 1);
+    double *Fa = calloc(N3, sizeof(double)), *Ta = calloc(N3, sizeof(double));
+    double *Fb = calloc(N3, sizeof(double)), *Tb = calloc(N3, sizeof(double));
+    double *Fp = calloc(N3, sizeof(double)), *Tp = calloc(N3, sizeof(double));
+    double *xt = calloc(N3, sizeof(double)), *ut = calloc(N3, sizeof(double));
+    double *wt = calloc(N3, sizeof(double));
+    double *sF = calloc((size_t)(np > 0 ? np : 1), sizeof(double));
+    double *H = calloc(HIST * (size_t)(npairs + 1), sizeof(double));
+    double *WH = calloc(HIST * (size_t)(nwall + 1), sizeof(double));
+    double *Hn = calloc(HIST * (size_t)(npairs + 1), sizeof(double));
+    double *WHn = calloc(HIST * (size_t)(nwall + 1), sizeof(double));
+    int st = R_EINVAL;
+    if (!Fa || !Ta || !Fb || !Tb || !Fp || !Tp || !xt || !ut || !wt || !sF || !H || !WH || !Hn ||
+        !WHn)
+        goto done;
+    memcpy(H, hist, sizeof(double) * HIST * (size_t)npairs);
+    memcpy(WH, whist, sizeof(double) * HIST * (size_t)nwall);
+    /* St switch: per particle, from the impact speeds of the input history:
+     * count each particle's committed contacts and those above St_crit */
+    {
+        int *contacts = calloc((size_t)np + 1, sizeof(int));
+        int *fast = calloc((size_t)np + 1, sizeof(int));
+        if (!contacts || !fast) {
+            free(contacts);
+            free(fast);
+            goto done;
+        }
+        for (int k = 0; k < npairs; ++k) {
+            int i = pairs[k], j = pairs[npairs + k];
+            if (!(H[3 * npairs + k] > 0.0))
+                continue;
+            double rhod = 0.5 * (rho_d(mass[i], radius[i]) + rho_d(mass[j], radius[j]));
+            double St = H[3 * npairs + k] * rhod / (9.0 * P.rho_f * P.nu_f);
+            contacts[i]++;
+            contacts[j]++;
+            if (St > P.St_crit) {
+                fast[i]++;
+                fast[j]++;
+            }
+        }
+        for (int k = 0; k < nwall; ++k) {
+            int p = walls[k];
+            if (!(WH[3 * nwall + k] > 0.0))
+                continue;
+            double St = WH[3 * nwall + k] * rho_d(mass[p], radius[p]) / (9.0 * P.rho_f * P.nu_f);
+            contacts[p]++;
+            if (St > P.St_crit)
+                fast[p]++;
+        }
+        for (int p = 0; p < np; ++p)
+            sF[p] = (P.st_switch && contacts[p] > 0 && fast[p] == 0) ? 0.0 : 1.0;
+        free(contacts);
+        free(fast);
+    }
+    double t_since = 0.0;
+    for (int s = 0; s < n_sub; ++s) {
+        for (int k = 0; k < 3; ++k) {
+            const double a2 = 2.0 * alpha[k];
+            /* F_c at the accepted state s^{k-1}, committing its history */
+            st = eval_contacts(n, h, origin, periodic, &P, np, xp, radius, mass, up, wp, npairs,
+                               pairs, nwall, walls, H, WH, t_since, Hn, WHn, Fa, Ta);
+            if (st != R_OK)
+                goto done;
+            memcpy(H, Hn, sizeof(double) * HIST * (size_t)npairs);
+            memcpy(WH, WHn, sizeof(double) * HIST * (size_t)nwall);
+            /* predictor */
+            for (int p = 0; p < np; ++p) {
+                double m = mass[p], R = radius[p];
+                double I = 0.4 * m * R * R;
+                double rho_p = m / (4.0 / 3.0 * M_PI * R * R * R);
+                for (int a = 0; a < 3; ++a) {
+                    size_t i = (size_t)a * np + p;
+                    double Fh_ = Fh ? sF[p] * Fh[i] : 0.0, Th_ = Th ? sF[p] * Th[i] : 0.0;
+                    double gp = (1.0 - P.rho_f / rho_p) * P.g[a];
+                    ut[i] = up[i] + dts / m * (a2 * Fh_ + gamma_[k] * Fa[i] + zeta_[k] * Fb[i]) +
+                            a2 * dts * gp;
+                    wt[i] = wp[i] + dts / I * (a2 * Th_ + gamma_[k] * Ta[i] + zeta_[k] * Tb[i]);
+                    xt[i] = xp[i] + alpha[k] * dts * (ut[i] + up[i]);
+                }
+            }
+            /* F_c at the predicted state (history not committed) */
+            st = eval_contacts(n, h, origin, periodic, &P, np, xt, radius, mass, ut, wt, npairs,
+                               pairs, nwall, walls, H, WH, a2 * dts, NULL, NULL, Fp, Tp);
+            if (st != R_OK)
+                goto done;
+            /* corrector */
+            for (int p = 0; p < np; ++p) {
+                double m = mass[p], R = radius[p];
+                double I = 0.4 * m * R * R;
+                double rho_p = m / (4.0 / 3.0 * M_PI * R * R * R);
+                for (int a = 0; a < 3; ++a) {
+                    size_t i = (size_t)a * np + p;
+                    double Fh_ = Fh ? sF[p] * Fh[i] : 0.0, Th_ = Th ? sF[p] * Th[i] : 0.0;
+                    double gp = (1.0 - P.rho_f / rho_p) * P.g[a];
+                    double un = up[i] + dts / m * (a2 * Fh_ + gamma_[k] * Fp[i] + zeta_[k] * Fa[i]) +
+                                a2 * dts * gp;
+                    double wn = wp[i] + dts / I * (a2 * Th_ + gamma_[k] * Tp[i] + zeta_[k] * Ta[i]);
+                    xp[i] = xp[i] + alpha[k] * dts * (un + up[i]);
+                    up[i] = un;
+                    wp[i] = wn;
+                }
+            }
+            memcpy(Fb, Fa, sizeof(double) * 3 * (size_t)np);
+            memcpy(Tb, Ta, sizeof(double) * 3 * (size_t)np);
+            t_since = a2 * dts;
         }
     }
-    return R_OK;
+    /* the final state: its forces and committed history */
+    st = eval_contacts(n, h, origin, periodic, &P, np, xp, radius, mass, up, wp, npairs, pairs,
+                       nwall, walls, H, WH, t_since, hist, whist, Fa, Ta);
+    if (st == R_OK && Fc_out && Tc_out) {
+        memcpy(Fc_out, Fa, sizeof(double) * 3 * (size_t)np);
+        memcpy(Tc_out, Ta, sizeof(double) * 3 * (size_t)np);
+    }
+done:
+    free(Fa); free(Ta); free(Fb); free(Tb); free(Fp); free(Tp); free(xt); free(ut); free(wt);
+    free(sF); free(H); free(WH); free(Hn); free(WHn);
+    return st;
 }
 
 /* SplitMix64 output function (Steele, Lea & Flood, OOPSLA 2014). */

@@ -64,12 +64,15 @@ def default_params() -> Dict[str, float]:
     mu_s, mu_k and zeta_min = 3e-3 r_p follow Sec. 3.4-3.5; eps_sep = 1.5h and
     C = 5.5 are the three-point values (Secs. 2.2.5-2.2.6); T_c = 10 dt (Sec. 2.2.7).
     ``c`` is 2 alpha_k dt with the first low-storage RK3 coefficient 4/15.
+    St_crit = 5 and the k_n,grav constant 1e-3 follow Sec. 2.2.7; gravity is
+    a small downward acceleration in these units.
     """
     return dict(
         kernel=3, n_iter=1, c=8.0 / 15.0, rho_f=1.0, nu_f=0.025,
         eps_sep=1.5, lub_C=5.5, zeta_min_factor=3e-3, e_dry=0.97, T_c=10.0,
         mu_s=0.11, mu_k=0.8, nu_poi=0.3, dt=1.0, disable_mode=1,
-        disable_seed=0, gap_cut=3.0,
+        disable_seed=0, gap_cut=3.0, normal_model=0, St_crit=5.0,
+        gravity=(0.0, 0.0, -1.0e-4), kn_grav_eps=1e-3, st_switch=0,
     )
 
 

@@ -103,8 +103,8 @@ def test_newton_third_law_and_angular_momentum(oracle_lib):
     c.wp = rng.normal(0, 0.1, c.wp.shape)
     pl = oracle_lib.pairs(c, gap_cut=3.0)
     assert pl["pairs"].shape[1] >= 2 and np.any(pl["gap"] < 0)
-    prev = dict(pairs=pl["pairs"], hist=rng.normal(0, 0.01, (3, pl["pairs"].shape[1])),
-                walls=pl["walls"], whist=np.zeros((3, pl["walls"].shape[1])))
+    prev = dict(pairs=pl["pairs"], hist=rng.normal(0, 0.01, (4, pl["pairs"].shape[1])),
+                walls=pl["walls"], whist=np.zeros((4, pl["walls"].shape[1])))
     f = oracle_lib.pair_forces(c, pl, prev=prev)
     assert np.abs(f["Fc"].sum(axis=1)).max() < 1e-12 * max(1.0, np.abs(f["Fc"]).max())
     # angular momentum per pair, with the partner at its minimum image
@@ -128,8 +128,8 @@ def _collide(oracle_lib, R1, R2, m1, m2, v, dt_int, e_dry, T_c, lub=False, steps
     x = np.array([[10.0, 10.0 + R1 + R2 + 1e-9], [20.0, 20.0], [20.0, 20.0]])
     u = np.array([[v / 2, -v / 2], [0.0, 0.0], [0.0, 0.0]])
     prm = dict(e_dry=e_dry, T_c=T_c, nu_f=(0.025 if lub else 0.0), gap_cut=3.0)
-    hist = dict(pairs=np.zeros((2, 0), np.int32), hist=np.zeros((3, 0)),
-                walls=np.zeros((2, 0), np.int32), whist=np.zeros((3, 0)))
+    hist = dict(pairs=np.zeros((2, 0), np.int32), hist=np.zeros((4, 0)),
+                walls=np.zeros((2, 0), np.int32), whist=np.zeros((4, 0)))
     m = np.array([m1, m2])
     t = 0.0
     t_in = t_out = None
