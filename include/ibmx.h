@@ -28,13 +28,15 @@
  *     or writes it inside the call, asynchronously on the plan's stream, so
  *     buffers must stay valid until the stream reaches the call.
  *   * Compute calls never synchronise the stream and allocate nothing, with
- *     three exceptions that allocate (and so may synchronise the device):
+ *     four exceptions that allocate (and so may synchronise the device):
  *     the first ibmx_forcing_backward call on a plan sizes its replay
- *     workspace, ibmx_pairs grows its cell workspace the first time the
- *     cell grid (set by radius_max and gap_cut) has more cells than on
- *     earlier calls, and ibmx_tune.  ibmx_forcing can be captured into a
- *     HIP graph (ibmx_forcing_graph does that), and so can ibmx_pairs once
- *     its cell workspace has been sized.  Errors that only the device can
+ *     workspace, ibmx_pairs grows its cell and contact workspace the first
+ *     time the cell grid (set by radius_max and gap_cut) or the list
+ *     capacities exceed those of earlier calls, ibmx_particle_substeps
+ *     likewise for its contact and stage workspace, and ibmx_tune.
+ *     ibmx_forcing can be captured into a HIP graph (ibmx_forcing_graph
+ *     does that), and so can ibmx_pairs and ibmx_particle_substeps once
+ *     their workspace has been sized.  Errors that only the device can
  *     see (a delta support crossing a wall, a list capacity exceeded) are
  *     recorded in the plan and returned by ibmx_plan_status().
  *   * A plan is used by one host thread at a time; calls on one plan are
@@ -66,7 +68,7 @@ typedef enum {
     IBMX_ESTATE = -5,       /* plan not ready (markers not set)               */
     IBMX_ECAPACITY = -6,    /* pair or wall list longer than its capacity
                                (deferred; counts are still written)           */
-    IBMX_EUNSUPPORTED = -7  /* option not built (e.g. Hertz normal contact)   */
+    IBMX_EUNSUPPORTED = -7  /* option not built (e.g. a delta other than 3/4)  */
 } ibmx_status;
 
 typedef enum {
@@ -105,9 +107,23 @@ typedef struct {
     double dt;               /* time step for the tangential spring            */
     double gap_cut;          /* pair/wall list cut-off on the surface gap      */
     int32_t disable_mode;    /* 0 none, 1 local markers, 2 whole particle      */
-    int32_t normal_model;    /* 0 linear spring-dashpot (1 Hertz: not built)   */
+    int32_t normal_model;    /* 0 linear spring-dashpot, 1 Hertz law with ACTM
+                                coefficients (Sec. 2.2.7)                      */
     uint64_t disable_seed;   /* seed of the per-pair random choice             */
+    double St_crit;          /* critical Stokes number of a contact [5]        */
+    double gravity[3];       /* gravitational acceleration g                   */
+    double kn_grav_eps;      /* eps of the gravity stiffness k_n,grav [1e-3]   */
+    int32_t st_switch;       /* 1: particle sub-stepping drops F_h, T_h of a
+                                particle whose contacts all have St <= St_crit */
+    int32_t reserved;        /* 0                                              */
 } ibmx_params;
+
+/* Rows of the per-contact history arrays: the tangential spring
+ * displacement zeta_t (3 rows) and the impact speed u_in of the contact
+ * (the approach speed g_cp . n at its first evaluation, clamped at zero;
+ * zero for a contact that has not begun).  A history array for n contacts
+ * is double[IBMX_HIST][n]. */
+#define IBMX_HIST 4
 
 typedef struct ibmx_plan_s *ibmx_plan;
 
@@ -153,7 +169,9 @@ enum {
  *   hip_stream          hipStream_t (NULL = default stream) used by every
  *                       call on this plan.
  * Allocates all device workspace.  Returns EINVAL, ENOMEM, EDEVICE or
- * EUNSUPPORTED (kernel other than 3/4, normal_model != 0).
+ * EUNSUPPORTED (kernel other than 3/4, normal_model other than 0/1).
+ * With normal_model 1 the plan solves the ACTM equation for e_dry on the
+ * host (a few milliseconds), here and in ibmx_plan_set_params.
  */
 IBMX_API ibmx_status ibmx_plan_create(ibmx_plan *out, const ibmx_grid *grid, const ibmx_params *params,
                              int32_t np, const int32_t *marker_offset_host,
@@ -261,11 +279,27 @@ IBMX_API ibmx_status ibmx_forcing_backward(ibmx_plan plan, const void *u0,
  *  - wall list: (p, side) with side = 2 axis + (0 lower, 1 upper) for walls
  *    closer than gap_cut, int32[2][wall_cap] in (p, side) order, wall_gap;
  *  - collision force and torque (eq. f_int): Fc, Tc double[3][np]
- *    (overwritten): lubrication for 0 <= gap < eps_sep, linear spring-dashpot
- *    normal contact and capped tangential spring-dashpot for gap < 0;
- *  - spring history: hist_in double[3][npairs_in] keyed by pairs_in (the
- *    previous call's pair list, may be empty), whist_in likewise for walls;
- *    hist_out double[3][pair_cap], whist_out double[3][wall_cap];
+ *    (overwritten): lubrication for 0 <= gap < eps_sep, normal contact
+ *    (params.normal_model) and capped tangential spring-dashpot for gap < 0;
+ *    each particle's contacts are summed in increasing partner id, then its
+ *    walls by side, so the sums do not depend on scheduling;
+ *      linear: F_n = -k_n |gap| n - d_n g_n, k_n = m_eff (pi^2 + ln^2 e_dry)
+ *        / T_c^2, d_n = -2 m_eff ln e_dry / T_c;
+ *      Hertz (eq. hertz-contact): F_n = -k_n |gap|^(3/2) n - d_n g_n with the
+ *        ACTM coefficients k_n = K m_eff / (sqrt(u_in) T_c^(5/2)), d_n =
+ *        D m_eff / T_c (eq. ode: K, D make a contact last T_c and rebound
+ *        with e_dry, solved once per e_dry by the plan) while u_in exceeds
+ *        u_crit = 9 St_crit rho_f nu_f / (rho d); otherwise k_n =
+ *        max(k_n,crit, k_n,grav), k_n,crit the ACTM value at u_crit,
+ *        k_n,grav = max over the two particles of m |g| (kn_grav_eps R)^(-3/2);
+ *        rho d = mean over the two particles of 3 m / (2 pi R^2);
+ *      tangential stiffness 2 (1 - nu)/(2 - nu) times the normal spring's
+ *        (k_n, for the Hertz law its secant k_n |gap|^(1/2));
+ *  - contact history (IBMX_HIST rows): hist_in double[IBMX_HIST][npairs_in]
+ *    keyed by pairs_in (the previous call's pair list in its (i, j) order,
+ *    may be empty), whist_in likewise for walls (keyed by (p, side) in that
+ *    order); hist_out double[IBMX_HIST][pair_cap], whist_out
+ *    double[IBMX_HIST][wall_cap]; the spring advances by params.dt;
  *  - marker_active uint8[nm] (overwritten): the disable rule of
  *    params.disable_mode (1: the randomly chosen particle of each pair closer
  *    than 2 eps_sep loses the markers within 2 eps_sep of its partner's
@@ -279,6 +313,8 @@ IBMX_API ibmx_status ibmx_forcing_backward(ibmx_plan plan, const void *u0,
  * Deferred error: ECAPACITY if a list exceeds its capacity (entries beyond
  * it are dropped, forces of dropped entries are not applied).
  * The body offsets set with ibmx_plan_set_markers are needed for the mask.
+ * Allocates plan workspace when the cell count or the list capacities grow
+ * beyond those of earlier calls.
  */
 IBMX_API ibmx_status ibmx_pairs(ibmx_plan plan, const double *xp, const double *radius,
                        double radius_max, const double *mass, const double *up, const double *wp,
@@ -351,6 +387,52 @@ IBMX_API ibmx_status ibmx_particle_integrals(ibmx_plan plan, const void *u, cons
  * Partial sums over fixed chunks, added in a fixed order.
  */
 IBMX_API ibmx_status ibmx_grid_mean(ibmx_plan plan, const void *f, double *mean);
+
+/*
+ * Particle sub-stepping (Sec. 2.2.10): advance every particle's centre,
+ * velocity and angular velocity by dt_total in n_sub sub-steps of dts =
+ * dt_total / n_sub, each the three-stage Runge-Kutta predictor-corrector of
+ * the particle update with the low-storage coefficients of Rai and Moin,
+ * alpha = (4/15, 1/15, 1/6), gamma = (8/15, 5/12, 3/4), zeta = (0, -17/60,
+ * -5/12).  Stage k, with F_c(s) the collision force of the pair pass at
+ * particle state s (and T_c its torque):
+ *   u~ = u^{k-1} + dts/m (2 alpha_k F_h + gamma_k F_c(s^{k-1}) + zeta_k F_c(s^{k-2}))
+ *        + 2 alpha_k dts g',
+ *   w~ = w^{k-1} + dts/I (2 alpha_k T_h + gamma_k T_c(s^{k-1}) + zeta_k T_c(s^{k-2})),
+ *   x~ = x^{k-1} + alpha_k dts (u~ + u^{k-1}),
+ * then u^k, w^k, x^k the same with F_c(s~) for F_c(s^{k-1}) and F_c(s^{k-1})
+ * for F_c(s^{k-2}).  g' = (1 - rho_f/rho_p) g, rho_p = m / (4/3 pi R^3),
+ * I = 2/5 m R^2.  15 sub-steps of dt/15 are the paper's setting (45 stages).
+ * The collision law is ibmx_pairs's (params.normal_model), evaluated on the
+ * given lists (pair and wall lists of an ibmx_pairs call, with gap_cut
+ * covering the motion of this call); contacts beyond the lists are not seen.
+ * History: hist / whist double[IBMX_HIST][pair_cap / wall_cap], aligned
+ * with the lists, in: the history of the input state; out: the history of
+ * the final state.  It is committed at each accepted stage state (the
+ * spring advancing by the time since the previous one); predicted states
+ * use the committed history and the stage's time 2 alpha_k dts.
+ *   xp, up, wp  double[3][np], in/out (centres are not wrapped).
+ *   radius, mass double[np].
+ *   Fh, Th      double[3][np] hydrodynamic force and torque held over the
+ *               call (e.g. -rho_f S_p plus the rate of change of the fluid
+ *               integrals), or NULL for zero.  With params.st_switch, a
+ *               particle whose input history holds at least one contact and
+ *               only contacts with St = u_in rho d / (9 rho_f nu_f) <=
+ *               St_crit gets F_h = T_h = 0.
+ *   counts      device int32[2]: listed pairs, walls (an ibmx_pairs
+ *               counts_out; clamped to the capacities).
+ *   Fc, Tc      double[3][np] or NULL: collision force and torque at the
+ *               final state, overwritten.
+ * Each particle's contacts are summed in increasing partner id, then its
+ * walls by side: the results do not depend on scheduling.  Allocates plan
+ * workspace when np or the list capacities exceed those of earlier calls.
+ */
+IBMX_API ibmx_status ibmx_particle_substeps(ibmx_plan plan, double dt_total, int32_t n_sub,
+                                   double *xp, double *up, double *wp, const double *radius,
+                                   const double *mass, const double *Fh, const double *Th,
+                                   const int32_t *counts, int32_t pair_cap, const int32_t *pairs,
+                                   int32_t wall_cap, const int32_t *walls, double *hist,
+                                   double *whist, double *Fc, double *Tc);
 
 /* Static description of a status code. */
 IBMX_API const char *ibmx_status_string(ibmx_status status);

@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libibmx.so")
 BUILD = os.path.join(ROOT, "_build", "ibmx")
 
 SOURCES = ["ibmx_util.hip", "ibmx_plan.hip", "ibmx_forcing.hip", "ibmx_graph.hip", "ibmx_pairs.hip",
-           "ibmx_particle.hip"]
+           "ibmx_particle.hip", "ibmx_substep.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -39,7 +39,7 @@ def hipcc() -> str:
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    extra = ["-ffp-contract=off"] if src == "ibmx_pairs.hip" else []
+    extra = ["-ffp-contract=off"] if src in ("ibmx_pairs.hip", "ibmx_substep.hip") else []
     cmd = [hipcc(), *HIPCC_FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

@@ -104,6 +104,21 @@ struct ibmx_plan_s {
     int *p_wcount;        // [np + 1]
     int *p_woff;          // [np + 1]
 
+    // contact workspace (pair pass and particle sub-stepping): per-particle
+    // adjacency of the contact lists, history of the previous pair call
+    // aligned with the new lists, stage states and forces of the sub-steps
+    double actm_K, actm_D;  // ACTM coefficients for prm.e_dry (Hertz law)
+    double actm_e;          // e_dry they were solved for (0: none)
+    int *c_deg;           // [np + 1]
+    int *c_off;           // [np + 1]
+    int *c_cur;           // [np]
+    int *c_adj;           // [c_adj_cap]
+    long long c_adj_cap;
+    double *c_hist;       // [c_hist_cap] history buffers
+    long long c_hist_cap;
+    double *s_buf;        // [s_cap] sub-step states, stage forces, F_h factors
+    long long s_cap;
+
     // last-call statistics
     ibmx_stats stats;
 
@@ -156,6 +171,16 @@ int ibmx_mean_blocks();
 // exclusive scan of n ints, out[n] = total; aux holds ibmx_scan_aux_size(n)
 // ints of workspace
 int ibmx_scan_aux_size(long long n);
+// ACTM coefficients (K, D) of the Hertz law for restitution e (Sec. 2.2.7):
+// in contact-time units z'' + D z' + K z^(3/2) = 0 closes at t = 1 with
+// z'(1) = -e z'(0).  Host computation.
+ibmx_status ibmx_actm_coefficients(double e, double *K, double *D);
+// Solve the ACTM coefficients for the plan's e_dry when its normal model
+// needs them (no-op otherwise or when already solved for that e_dry).
+ibmx_status ibmx_plan_actm(ibmx_plan p);
+// Grow the contact workspace to list capacities (pair_cap, wall_cap) with
+// `hist_sets` history buffers of IBMX_HIST rows each.
+ibmx_status ibmx_contact_reserve(ibmx_plan p, int pair_cap, int wall_cap, int hist_sets);
 void ibmx_exclusive_scan(const int *in, int *out, int n, int *aux, hipStream_t s);
 void ibmx_fill_i32(int *p, int v, long long n, hipStream_t s);
 void ibmx_fill_f64(double *p, double v, long long n, hipStream_t s);

@@ -17,57 +17,9 @@
 
 #include <math.h>
 
-#include "ibmx_internal.hpp"
+#include "ibmx_contact.hpp"
 
 namespace {
-
-struct PairC {
-    double rho_f, nu_f, eps_sep, lub_C, zeta_min_factor, e_dry, T_c, mu_s, mu_k, nu_poi, dt;
-    double gap_cut;
-    double h;
-    double L[3];
-    double origin[3];
-    double edge[3];
-    int nc[3];
-    int periodic[3];
-    int ncell;
-};
-
-__device__ __forceinline__ double wrap_pos(double x, double o, double L)
-{
-    double t = floor((x - o) / L);
-    return x - t * L;
-}
-
-__device__ __forceinline__ double min_image(double d, double L)
-{
-    while (d > 0.5 * L)
-        d = d - L;
-    while (d < -0.5 * L)
-        d = d + L;
-    return d;
-}
-
-__device__ __forceinline__ void centre(const PairC &P, int np, const double *xp, int p, double *x)
-{
-    for (int a = 0; a < 3; ++a) {
-        double v = xp[(size_t)a * np + p];
-        x[a] = P.periodic[a] ? wrap_pos(v, P.origin[a], P.L[a]) : v;
-    }
-}
-
-__device__ __forceinline__ double disp2(const PairC &P, const double *a_, const double *b_, double *d)
-{
-    for (int a = 0; a < 3; ++a) {
-        d[a] = b_[a] - a_[a];
-        if (P.periodic[a])
-            d[a] = min_image(d[a], P.L[a]);
-    }
-    double d2 = d[0] * d[0];
-    d2 = d2 + d[1] * d[1];
-    d2 = d2 + d[2] * d[2];
-    return d2;
-}
 
 __device__ __forceinline__ void cell_coords(const PairC &P, const double *x, int *ci)
 {
@@ -288,63 +240,6 @@ __global__ void k_list_totals(const int *poff, const int *woff, int np, int pair
         atomicCAS(err, 0, (int)IBMX_ECAPACITY);
 }
 
-// ---------------------------------------------------------------------------
-// collision law for one contact (force on p; n points from p to the partner)
-// ---------------------------------------------------------------------------
-__device__ void contact_law(const PairC &P, double zeta, const double *n, const double *g,
-                            double Reff, double meff, double zmin, const double *zt_old,
-                            double *F, double *Ft, double *zt_new)
-{
-    double gn = g[0] * n[0] + g[1] * n[1] + g[2] * n[2];
-    double gnv[3], gtv[3];
-    for (int a = 0; a < 3; ++a) {
-        gnv[a] = gn * n[a];
-        gtv[a] = g[a] - gnv[a];
-        F[a] = 0.0;
-        Ft[a] = 0.0;
-        zt_new[a] = 0.0;
-    }
-    if (zeta >= P.eps_sep)
-        return;
-    if (zeta >= 0.0) {
-        double zz = zeta > zmin ? zeta : zmin;
-        double psi = 0.5 * erf(6.0 - P.lub_C * zz / P.h) + 0.5;
-        double coef = 6.0 * M_PI * P.rho_f * P.nu_f * Reff * Reff * psi / zz;
-        for (int a = 0; a < 3; ++a)
-            F[a] = -coef * gnv[a];
-        return;
-    }
-    double le = log(P.e_dry);
-    double kn = meff * (M_PI * M_PI + le * le) / (P.T_c * P.T_c);
-    double dn = -2.0 * meff * le / P.T_c;
-    double Fn[3];
-    for (int a = 0; a < 3; ++a)
-        Fn[a] = -kn * fabs(zeta) * n[a] - dn * gnv[a];
-    double kt = 2.0 * (1.0 - P.nu_poi) / (2.0 - P.nu_poi) * kn;
-    double dtc = 2.0 * sqrt(meff * kt) * (-le) / sqrt(M_PI * M_PI + le * le);
-    double zon = zt_old[0] * n[0] + zt_old[1] * n[1] + zt_old[2] * n[2];
-    double zt[3], Fdp[3];
-    for (int a = 0; a < 3; ++a) {
-        zt[a] = (zt_old[a] - zon * n[a]) + gtv[a] * P.dt;
-        Fdp[a] = -kt * zt[a] - dtc * gtv[a];
-    }
-    double nFdp = sqrt(Fdp[0] * Fdp[0] + Fdp[1] * Fdp[1] + Fdp[2] * Fdp[2]);
-    double nFn = sqrt(Fn[0] * Fn[0] + Fn[1] * Fn[1] + Fn[2] * Fn[2]);
-    if (nFdp <= P.mu_s * nFn) {
-        for (int a = 0; a < 3; ++a)
-            Ft[a] = Fdp[a];
-    } else {
-        for (int a = 0; a < 3; ++a) {
-            Ft[a] = P.mu_k * nFn * Fdp[a] / nFdp;
-            zt[a] = -(Ft[a] + dtc * gtv[a]) / kt;
-        }
-    }
-    for (int a = 0; a < 3; ++a) {
-        F[a] = Fn[a] + Ft[a];
-        zt_new[a] = zt[a];
-    }
-}
-
 // previous-call history of pair (i, j): binary search in the (i, j)-sorted list
 __device__ int find_pair(int n_in, const int *pairs_in, int i, int j)
 {
@@ -363,98 +258,66 @@ __device__ int find_pair(int n_in, const int *pairs_in, int i, int j)
     return -1;
 }
 
-__global__ void k_pair_forces(PairC P, int np, const double *xp, const double *radius,
-                              const double *mass, const double *up, const double *wp,
-                              const int *counts, int cap, const int *pairs, int n_in,
-                              const int *pairs_in, const double *hist_in, double *hist_out,
-                              double *Fc, double *Tc)
+// previous-call history of wall entry (p, side): binary search in the
+// (p, side)-sorted list
+__device__ int find_wall(int n_in, const int *walls_in, int p, int side)
 {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    int npairs = min(counts[0], cap);
-    if (k >= npairs)
-        return;
-    int p = pairs[k], q = pairs[cap + k];
-    double xa[3], xb[3], dvec[3];
-    centre(P, np, xp, p, xa);
-    centre(P, np, xp, q, xb);
-    double d = sqrt(disp2(P, xa, xb, dvec));
-    double Rp = radius[p], Rq = radius[q];
-    double zeta = d - Rp - Rq;
-    double n[3] = {dvec[0] / d, dvec[1] / d, dvec[2] / d};
-    double Rpc = 0.5 * (d + Rp - Rq), Rqc = 0.5 * (d + Rq - Rp);
-    double wpp[3], wqq[3];
-    for (int a = 0; a < 3; ++a) {
-        wpp[a] = wp[(size_t)a * np + p];
-        wqq[a] = wp[(size_t)a * np + q];
+    long long key = (long long)p * 8 + side;
+    int lo = 0, hi = n_in - 1;
+    while (lo <= hi) {
+        int mid = (lo + hi) >> 1;
+        long long k = (long long)walls_in[mid] * 8 + walls_in[n_in + mid];
+        if (k == key)
+            return mid;
+        if (k < key)
+            lo = mid + 1;
+        else
+            hi = mid - 1;
     }
-    double wpn[3] = {wpp[1] * n[2] - wpp[2] * n[1], wpp[2] * n[0] - wpp[0] * n[2],
-                     wpp[0] * n[1] - wpp[1] * n[0]};
-    double wqn[3] = {wqq[1] * n[2] - wqq[2] * n[1], wqq[2] * n[0] - wqq[0] * n[2],
-                     wqq[0] * n[1] - wqq[1] * n[0]};
-    double g[3];
-    for (int a = 0; a < 3; ++a)
-        g[a] = (up[(size_t)a * np + p] - up[(size_t)a * np + q]) + Rpc * wpn[a] + Rqc * wqn[a];
-    double Reff = Rp * Rq / (Rp + Rq);
-    double meff = mass[p] * mass[q] / (mass[p] + mass[q]);
-    double zmin = P.zeta_min_factor * (Rp < Rq ? Rp : Rq);
-    double zold[3] = {0.0, 0.0, 0.0};
-    int kin = n_in > 0 ? find_pair(n_in, pairs_in, p, q) : -1;
-    if (kin >= 0)
-        for (int a = 0; a < 3; ++a)
-            zold[a] = hist_in[(size_t)a * n_in + kin];
-    double F[3], Ft[3], zt[3];
-    contact_law(P, zeta, n, g, Reff, meff, zmin, zold, F, Ft, zt);
-    double nxFt[3] = {n[1] * Ft[2] - n[2] * Ft[1], n[2] * Ft[0] - n[0] * Ft[2],
-                      n[0] * Ft[1] - n[1] * Ft[0]};
-    for (int a = 0; a < 3; ++a) {
-        atomicAdd(&Fc[(size_t)a * np + p], F[a]);
-        atomicAdd(&Fc[(size_t)a * np + q], -F[a]);
-        atomicAdd(&Tc[(size_t)a * np + p], Rpc * nxFt[a]);
-        atomicAdd(&Tc[(size_t)a * np + q], Rqc * nxFt[a]);
-        hist_out[(size_t)a * cap + k] = zt[a];
+    return -1;
+}
+
+// history of the previous call, aligned with the new lists (zero for new
+// contacts)
+__global__ void k_hist_align(ContactLists C, int n_in, const int *pairs_in, const double *hist_in,
+                             int nw_in, const int *walls_in, const double *whist_in, Hist hold)
+{
+    const int npairs = n_pairs(C), nwall = n_walls(C);
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < npairs + nwall;
+         k += gridDim.x * blockDim.x) {
+        if (k < npairs) {
+            const int kin = n_in > 0 ? find_pair(n_in, pairs_in, C.pairs[k], C.pairs[C.pair_cap + k])
+                                     : -1;
+            for (int a = 0; a < kHist; ++a)
+                hold.pair[(size_t)a * C.pair_cap + k] =
+                    kin >= 0 ? hist_in[(size_t)a * n_in + kin] : 0.0;
+        } else {
+            const int kw = k - npairs;
+            const int kin =
+                nw_in > 0 ? find_wall(nw_in, walls_in, C.walls[kw], C.walls[C.wall_cap + kw]) : -1;
+            for (int a = 0; a < kHist; ++a)
+                hold.wall[(size_t)a * C.wall_cap + kw] =
+                    kin >= 0 ? whist_in[(size_t)a * nw_in + kin] : 0.0;
+        }
     }
 }
 
-__global__ void k_wall_forces(PairC P, int np, const double *xp, const double *radius,
-                              const double *mass, const double *up, const double *wp,
-                              const int *counts, int cap, const int *walls, int n_in,
-                              const int *walls_in, const double *whist_in, double *whist_out,
-                              double *Fc, double *Tc)
+// collision force and torque of every particle, one thread per particle
+__global__ __launch_bounds__(64) void k_contact_forces(PairC P, int np, ContactLists C,
+                                                       const int *off, const int *adj,
+                                                       const double *xp, const double *up,
+                                                       const double *wp, const double *radius,
+                                                       const double *mass, HistC hold, Hist hnew,
+                                                       double *Fc, double *Tc)
 {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    int nwall = min(counts[1], cap);
-    if (k >= nwall)
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np)
         return;
-    int p = walls[k], side = walls[cap + k];
-    int ax = side / 2, upper = side % 2;
-    double x = xp[(size_t)ax * np + p];
-    double top = P.origin[ax] + P.L[ax];
-    double dist = upper == 0 ? (x - P.origin[ax]) : (top - x);
-    double Rp = radius[p];
-    double zeta = dist - Rp;
-    double n[3] = {0.0, 0.0, 0.0};
-    n[ax] = upper == 0 ? -1.0 : 1.0;
-    double wpp[3];
-    for (int a = 0; a < 3; ++a)
-        wpp[a] = wp[(size_t)a * np + p];
-    double wpn[3] = {wpp[1] * n[2] - wpp[2] * n[1], wpp[2] * n[0] - wpp[0] * n[2],
-                     wpp[0] * n[1] - wpp[1] * n[0]};
-    double g[3];
-    for (int a = 0; a < 3; ++a)
-        g[a] = up[(size_t)a * np + p] + dist * wpn[a];
-    double zold[3] = {0.0, 0.0, 0.0};
-    for (int kk = 0; kk < n_in; ++kk)
-        if (walls_in[kk] == p && walls_in[n_in + kk] == side)
-            for (int a = 0; a < 3; ++a)
-                zold[a] = whist_in[(size_t)a * n_in + kk];
-    double F[3], Ft[3], zt[3];
-    contact_law(P, zeta, n, g, Rp, mass[p], P.zeta_min_factor * Rp, zold, F, Ft, zt);
-    double nxFt[3] = {n[1] * Ft[2] - n[2] * Ft[1], n[2] * Ft[0] - n[0] * Ft[2],
-                      n[0] * Ft[1] - n[1] * Ft[0]};
+    double F[3], T[3];
+    particle_contacts(P, np, p, C, off, adj, xp, up, wp, radius, mass, hold, P.dt, hnew, F, T);
     for (int a = 0; a < 3; ++a) {
-        atomicAdd(&Fc[(size_t)a * np + p], F[a]);
-        atomicAdd(&Tc[(size_t)a * np + p], dist * nxFt[a]);
-        whist_out[(size_t)a * cap + k] = zt[a];
+        Fc[(size_t)a * np + p] = F[a];
+        Tc[(size_t)a * np + p] = T[a];
     }
 }
 
@@ -569,26 +432,11 @@ extern "C" ibmx_status ibmx_pairs(ibmx_plan p, const double *xp, const double *r
         return IBMX_ESTATE;
     const ibmx_params &prm = p->prm;
     PairC P;
-    P.rho_f = prm.rho_f;
-    P.nu_f = prm.nu_f;
-    P.eps_sep = prm.eps_sep;
-    P.lub_C = prm.lub_C;
-    P.zeta_min_factor = prm.zeta_min_factor;
-    P.e_dry = prm.e_dry;
-    P.T_c = prm.T_c;
-    P.mu_s = prm.mu_s;
-    P.mu_k = prm.mu_k;
-    P.nu_poi = prm.nu_poi;
-    P.dt = prm.dt;
-    P.gap_cut = prm.gap_cut;
-    P.h = p->g.h;
+    contact_constants(p, &P);
     if (np > 0 && !(rmax > 0.0 && isfinite(rmax)))
         return IBMX_EINVAL;
     long long ncell = 1;
     for (int a = 0; a < 3; ++a) {
-        P.L[a] = p->g.n[a] * p->g.h;
-        P.origin[a] = p->g.origin[a];
-        P.periodic[a] = p->g.periodic[a];
         int k = (int)floor(P.L[a] / (2.0 * rmax + P.gap_cut));
         P.nc[a] = k < 1 ? 1 : k;
         P.edge[a] = P.L[a] / P.nc[a];
@@ -605,7 +453,8 @@ extern "C" ibmx_status ibmx_pairs(ibmx_plan p, const double *xp, const double *r
             return IBMX_ENOMEM;
         p->p_cell_cap = (int)ncell;
     }
-    if (ibmx_plan_scan_reserve(p, ncell) != IBMX_OK)
+    if (ibmx_plan_scan_reserve(p, ncell) != IBMX_OK ||
+        ibmx_contact_reserve(p, pair_cap, wall_cap, 1) != IBMX_OK)
         return IBMX_ENOMEM;
     hipStream_t s = p->stream;
     ProfScope ps(p, IBMX_K_PAIRS);
@@ -639,17 +488,21 @@ extern "C" ibmx_status ibmx_pairs(ibmx_plan p, const double *xp, const double *r
     }
     hipLaunchKernelGGL(k_list_totals, dim3(1), dim3(1), 0, s, p->p_off, p->p_woff, np, pair_cap,
                        wall_cap, counts_out, p->d_err);
-    // forces
-    ibmx_fill_f64(Fc, 0.0, 3LL * np, s);
-    ibmx_fill_f64(Tc, 0.0, 3LL * np, s);
-    if (pair_cap > 0)
-        hipLaunchKernelGGL(k_pair_forces, dim3(blocks(pair_cap)), dim3(256), 0, s, P, np, xp,
-                           radius, mass, up, wp, counts_out, pair_cap, pairs_out, npairs_in,
-                           pairs_in, hist_in, hist_out, Fc, Tc);
-    if (wall_cap > 0)
-        hipLaunchKernelGGL(k_wall_forces, dim3(blocks(wall_cap)), dim3(256), 0, s, P, np, xp,
-                           radius, mass, up, wp, counts_out, wall_cap, walls_out, nwall_in,
-                           walls_in, whist_in, whist_out, Fc, Tc);
+    // forces: previous history aligned with the new lists, per-particle
+    // adjacency, then one thread per particle
+    const ContactLists C{pair_cap, wall_cap, pairs_out, walls_out, counts_out};
+    const Hist hold{p->c_hist, p->c_hist + (size_t)kHist * pair_cap};
+    {
+        const long long nmax = (long long)pair_cap + wall_cap;
+        const int g = blocks(nmax) < 4096 ? blocks(nmax) : 4096;
+        hipLaunchKernelGGL(k_hist_align, dim3(g), dim3(256), 0, s, C, npairs_in, pairs_in, hist_in,
+                           nwall_in, walls_in, whist_in, hold);
+    }
+    contact_adjacency(p, C, s);
+    if (np > 0)
+        hipLaunchKernelGGL(k_contact_forces, dim3(blocks(np, 64)), dim3(64), 0, s, P, np, C,
+                           (const int *)p->c_off, (const int *)p->c_adj, xp, up, wp, radius, mass,
+                           HistC{hold.pair, hold.wall}, Hist{hist_out, whist_out}, Fc, Tc);
     // mask
     if (marker_active && nm > 0) {
         ibmx_fill_u8(marker_active, 1, nm, s);

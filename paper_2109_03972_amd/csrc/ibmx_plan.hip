@@ -23,7 +23,9 @@ void free_plan(ibmx_plan p)
                     p->rec_tn,      p->rec_ud,      p->rec_src,      p->rec_Gp,    p->rec_G,
                     p->m_key,       p->m_inv,       p->tile_count, p->tile_start,
                     p->tile_cursor, p->halo_count,  p->halo_start,   p->halo_cursor,
-                    p->halo_list,   p->tile_gmax,   p->scan_aux,     p->mean_part,    p->bw_u,         p->p_cell_of, p->p_cursor,
+                    p->halo_list,   p->tile_gmax,   p->scan_aux,     p->mean_part,    p->bw_u,
+                    p->c_deg,       p->c_off,       p->c_cur,        p->c_adj,        p->c_hist,
+                    p->s_buf,         p->p_cell_of, p->p_cursor,
                     p->p_count,     p->p_off,       p->p_wcount,     p->p_woff};
     for (void *q : ptrs)
         if (q)
@@ -58,8 +60,15 @@ ibmx_status check_params(const ibmx_grid *g, const ibmx_params *prm)
         return IBMX_EINVAL;
     if (prm->kernel != 3 && prm->kernel != 4)
         return IBMX_EUNSUPPORTED;
-    if (prm->normal_model != 0)
+    if (prm->normal_model != 0 && prm->normal_model != 1)
         return IBMX_EUNSUPPORTED;
+    if (!(prm->St_crit >= 0.0) || !isfinite(prm->St_crit) || !(prm->kn_grav_eps > 0.0) ||
+        !isfinite(prm->kn_grav_eps) || (prm->st_switch != 0 && prm->st_switch != 1) ||
+        prm->reserved != 0)
+        return IBMX_EINVAL;
+    for (int a = 0; a < 3; ++a)
+        if (!isfinite(prm->gravity[a]))
+            return IBMX_EINVAL;
     if (prm->n_iter < 1 || prm->n_iter > 64)
         return IBMX_EINVAL;
     if (!(prm->two_alpha_dt != 0.0) || !isfinite(prm->two_alpha_dt))
@@ -158,6 +167,9 @@ ibmx_status check_params(const ibmx_grid *g, const ibmx_params *prm)
     A((void **)&p->p_off, sizeof(int) * (npz + 1));
     A((void **)&p->p_wcount, sizeof(int) * (npz + 1));
     A((void **)&p->p_woff, sizeof(int) * (npz + 1));
+    A((void **)&p->c_deg, sizeof(int) * (npz + 1));
+    A((void **)&p->c_off, sizeof(int) * (npz + 1));
+    A((void **)&p->c_cur, sizeof(int) * npz);
     if (!ok) {
         free_plan(p);
         return IBMX_ENOMEM;
@@ -191,6 +203,11 @@ ibmx_status check_params(const ibmx_grid *g, const ibmx_params *prm)
     }
     p->block = 256;
     p->stats.n_markers = nm;
+    st = ibmx_plan_actm(p);
+    if (st != IBMX_OK) {
+        free_plan(p);
+        return st;
+    }
     // default tiles: 16 x 16 x 8 nodes
     st = ibmx_plan_scan_reserve(p, np);
     if (st == IBMX_OK)
@@ -333,7 +350,13 @@ extern "C" ibmx_status ibmx_plan_set_params(ibmx_plan p, const ibmx_params *prm)
         return st;
     if (prm->n_iter > p->n_iter_cap)
         return IBMX_EINVAL;
+    const ibmx_params old = p->prm;
     p->prm = *prm;
+    st = ibmx_plan_actm(p);
+    if (st != IBMX_OK) {
+        p->prm = old;
+        return st;
+    }
     ibmx_plan_drop_graph(p);
     return IBMX_OK;
 }
@@ -436,5 +459,44 @@ extern "C" ibmx_status ibmx_plan_profile(ibmx_plan p, int32_t enable)
         p->acc_n[k] = 0;
     }
     p->prof = enable ? 1 : 0;
+    return IBMX_OK;
+}
+
+ibmx_status ibmx_plan_actm(ibmx_plan p)
+{
+    if (p->prm.normal_model != 1 || p->actm_e == p->prm.e_dry)
+        return IBMX_OK;
+    double K = 0.0, D = 0.0;
+    const ibmx_status st = ibmx_actm_coefficients(p->prm.e_dry, &K, &D);
+    if (st != IBMX_OK)
+        return st;
+    p->actm_K = K;
+    p->actm_D = D;
+    p->actm_e = p->prm.e_dry;
+    return IBMX_OK;
+}
+
+ibmx_status ibmx_contact_reserve(ibmx_plan p, int pair_cap, int wall_cap, int hist_sets)
+{
+    const long long nadj = 2LL * pair_cap + wall_cap;
+    if (nadj > p->c_adj_cap || !p->c_adj) {
+        if (p->c_adj)
+            (void)hipFree(p->c_adj);
+        p->c_adj = nullptr;
+        p->c_adj_cap = 0;
+        if (hipMalloc((void **)&p->c_adj, sizeof(int) * (size_t)(nadj > 0 ? nadj : 1)) != hipSuccess)
+            return IBMX_ENOMEM;
+        p->c_adj_cap = nadj;
+    }
+    const long long nh = (long long)hist_sets * IBMX_HIST * ((long long)pair_cap + wall_cap);
+    if (nh > p->c_hist_cap || (nh > 0 && !p->c_hist)) {
+        if (p->c_hist)
+            (void)hipFree(p->c_hist);
+        p->c_hist = nullptr;
+        p->c_hist_cap = 0;
+        if (hipMalloc((void **)&p->c_hist, sizeof(double) * (size_t)nh) != hipSuccess)
+            return IBMX_ENOMEM;
+        p->c_hist_cap = nh;
+    }
     return IBMX_OK;
 }

@@ -26,8 +26,10 @@ API = (
     "ibmx_plan_profile",
     "ibmx_forcing", "ibmx_forcing_graph",
     "ibmx_forcing_backward", "ibmx_pairs", "ibmx_tune", "ibmx_particle_integrals",
-    "ibmx_grid_mean", "ibmx_status_string", "ibmx_version",
+    "ibmx_grid_mean", "ibmx_particle_substeps", "ibmx_status_string", "ibmx_version",
 )
+
+HIST = 4   # rows of a contact history array (IBMX_HIST)
 
 
 class IbmxError(RuntimeError):
@@ -49,7 +51,10 @@ class ibmx_params(ctypes.Structure):
                 ("e_dry", ctypes.c_double), ("T_c", ctypes.c_double), ("mu_s", ctypes.c_double),
                 ("mu_k", ctypes.c_double), ("nu_poi", ctypes.c_double), ("dt", ctypes.c_double),
                 ("gap_cut", ctypes.c_double), ("disable_mode", ctypes.c_int32),
-                ("normal_model", ctypes.c_int32), ("disable_seed", ctypes.c_uint64)]
+                ("normal_model", ctypes.c_int32), ("disable_seed", ctypes.c_uint64),
+                ("St_crit", ctypes.c_double), ("gravity", ctypes.c_double * 3),
+                ("kn_grav_eps", ctypes.c_double), ("st_switch", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class ibmx_stats(ctypes.Structure):
@@ -107,6 +112,9 @@ def lib():
         L.ibmx_particle_integrals.argtypes = [P] * 7
         L.ibmx_grid_mean.restype = St
         L.ibmx_grid_mean.argtypes = [P] * 3
+        L.ibmx_particle_substeps.restype = St
+        L.ibmx_particle_substeps.argtypes = [P, ctypes.c_double, i32, P, P, P, P, P, P, P, P, i32,
+                                             P, i32, P, P, P, P, P]
         L.ibmx_status_string.restype = ctypes.c_char_p
         L.ibmx_status_string.argtypes = [St]
         L.ibmx_version.restype = ctypes.c_char_p
@@ -153,6 +161,13 @@ def make_params(prm: Dict) -> ibmx_params:
     p.disable_mode = int(prm.get("disable_mode", 0))
     p.normal_model = int(prm.get("normal_model", 0))
     p.disable_seed = int(prm.get("disable_seed", 0)) & 0xFFFFFFFFFFFFFFFF
+    p.St_crit = float(prm.get("St_crit", 5.0))
+    g = prm.get("gravity", (0.0, 0.0, 0.0))
+    for a in range(3):
+        p.gravity[a] = float(g[a])
+    p.kn_grav_eps = float(prm.get("kn_grav_eps", 1e-3))
+    p.st_switch = int(prm.get("st_switch", 0))
+    p.reserved = 0
     return p
 
 
@@ -330,10 +345,10 @@ class Plan:
         cellp = torch.empty(max(self.np, 1), dtype=i32, device=dev)
         pairs = torch.empty((2, pair_cap), dtype=i32, device=dev)
         pgap = torch.empty(pair_cap, dtype=f64, device=dev)
-        hist = torch.empty((3, pair_cap), dtype=f64, device=dev)
+        hist = torch.empty((HIST, pair_cap), dtype=f64, device=dev)
         walls = torch.empty((2, wall_cap), dtype=i32, device=dev)
         wgap = torch.empty(wall_cap, dtype=f64, device=dev)
-        whist = torch.empty((3, wall_cap), dtype=f64, device=dev)
+        whist = torch.empty((HIST, wall_cap), dtype=f64, device=dev)
         counts = torch.zeros(2, dtype=i32, device=dev)
         Fc = torch.empty((3, self.np), dtype=f64, device=dev)
         Tc = torch.empty_like(Fc)
@@ -341,14 +356,16 @@ class Plan:
             mask = torch.empty(max(self.nm, 1), dtype=torch.uint8, device=dev)
         if prev is None:
             pin = torch.zeros((2, 1), dtype=i32, device=dev)
-            hin = torch.zeros((3, 1), dtype=f64, device=dev)
+            hin = torch.zeros((HIST, 1), dtype=f64, device=dev)
             win = torch.zeros((2, 1), dtype=i32, device=dev)
-            whin = torch.zeros((3, 1), dtype=f64, device=dev)
+            whin = torch.zeros((HIST, 1), dtype=f64, device=dev)
             n_in, nw_in = 0, 0
         else:
             pin, hin = prev["pairs"].contiguous(), prev["hist"].contiguous()
             win, whin = prev["walls"].contiguous(), prev["whist"].contiguous()
             n_in, nw_in = int(pin.shape[1]), int(win.shape[1])
+            _want(hin, f64, (HIST, n_in), "prev hist")
+            _want(whin, f64, (HIST, nw_in), "prev whist")
         self._sync_stream()
         st = lib().ibmx_pairs(self.handle, _ptr(xp), _ptr(radius), float(radius_max), _ptr(mass),
                               _ptr(up), _ptr(wp),
@@ -360,6 +377,40 @@ class Plan:
         return dict(cell_start=cell_start, cell_particles=cellp, pairs=pairs, gap=pgap, hist=hist,
                     walls=walls, wgap=wgap, whist=whist, counts=counts, Fc=Fc, Tc=Tc, mask=mask,
                     pair_cap=pair_cap, wall_cap=wall_cap)
+
+    def particle_substeps(self, dt_total, n_sub, xp, up, wp, radius, mass, lists, hist, whist,
+                          Fh=None, Th=None, want_forces=True):
+        """ibmx_particle_substeps: advances xp, up, wp (double[3][np] device
+        tensors, in place) over the contact lists of a pairs() result
+        (``lists``: its pairs, walls, counts and caps); ``hist``/``whist``
+        double[4][cap] are updated in place.  Returns (Fc, Tc) at the final
+        state, or None."""
+        import torch
+        f64 = torch.float64
+        for t, nme in ((xp, "xp"), (up, "up"), (wp, "wp")):
+            _want(t, f64, (3, self.np), nme)
+        _want(radius, f64, (self.np,), "radius")
+        _want(mass, f64, (self.np,), "mass")
+        _want(Fh, f64, (3, self.np), "Fh")
+        _want(Th, f64, (3, self.np), "Th")
+        pc, wc = int(lists["pair_cap"]), int(lists["wall_cap"])
+        _want(lists["pairs"], torch.int32, (2, pc), "pairs")
+        _want(lists["walls"], torch.int32, (2, wc), "walls")
+        _want(lists["counts"], torch.int32, (2,), "counts")
+        _want(hist, f64, (HIST, pc), "hist")
+        _want(whist, f64, (HIST, wc), "whist")
+        Fc = Tc = None
+        if want_forces:
+            Fc = torch.empty((3, self.np), dtype=f64, device=xp.device)
+            Tc = torch.empty_like(Fc)
+        self._sync_stream()
+        st = lib().ibmx_particle_substeps(self.handle, float(dt_total), int(n_sub), _ptr(xp),
+                                          _ptr(up), _ptr(wp), _ptr(radius), _ptr(mass), _ptr(Fh),
+                                          _ptr(Th), _ptr(lists["counts"]), pc, _ptr(lists["pairs"]),
+                                          wc, _ptr(lists["walls"]), _ptr(hist), _ptr(whist),
+                                          _ptr(Fc), _ptr(Tc))
+        _check(st, "ibmx_particle_substeps")
+        return (Fc, Tc) if want_forces else None
 
     def particle_integrals(self, u, xp, radius, alpha=None):
         """ibmx_particle_integrals: returns (Iu, Ir), double[3][np]; fills the

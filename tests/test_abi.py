@@ -36,11 +36,30 @@ def test_status_strings_and_version():
     assert "gfx950" in ibmx.version()
 
 
-def test_struct_layouts_match_header():
-    """Field offsets of the ctypes mirrors follow the C declarations."""
+def test_struct_layouts_match_header(tmp_path):
+    """Size and field offsets of the ctypes mirrors equal what the C
+    compiler lays out for include/ibmx.h."""
+    import subprocess
     from paper_2109_03972_amd import ibmx
-    assert ctypes.sizeof(ibmx.ibmx_grid) == 4 * 6 + 8 * 4
-    assert ibmx.ibmx_params.two_alpha_dt.offset == 8
-    assert ibmx.ibmx_params.disable_mode.offset == 8 + 8 * 13
-    assert ibmx.ibmx_params.disable_seed.offset == 8 + 8 * 13 + 8
-    assert ctypes.sizeof(ibmx.ibmx_params) == 8 + 8 * 13 + 8 + 8
+    structs = (ibmx.ibmx_grid, ibmx.ibmx_params, ibmx.ibmx_stats)
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "ibmx.h"', "int main(void) {"]
+    for S in structs:
+        nme = S.__name__
+        lines.append(f'printf("{nme} size %zu\\n", sizeof({nme}));')
+        for f in S._fields_:
+            lines.append(f'printf("{nme} {f[0]} %zu\\n", offsetof({nme}, {f[0]}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                           str(exe)])
+    got = subprocess.check_output([str(exe)], text=True).split("\n")
+    for row in got:
+        if not row:
+            continue
+        nme, field, val = row.split()
+        S = getattr(ibmx, nme)
+        want = ctypes.sizeof(S) if field == "size" else getattr(S, field).offset
+        assert int(val) == want, (nme, field, int(val), want)
+    assert sum(1 for r in got if r) == sum(len(S._fields_) + 1 for S in structs)
