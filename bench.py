@@ -187,6 +187,20 @@ def run_gpu(case, precision, steps, warmup, profile=True, tune=True, tile=None):
         lambda: plan.forcing_backward(u, D["xp"], D["up"], D["wp"], mask, f, None, g_S, None),
         reps=2)
     plan.check("backward")
+    # particle sub-stepping over the step's contact lists: Hertz law with
+    # ACTM coefficients, the paper's 15 sub-steps of dt/15 (90 stage launches)
+    prm = dict(case.params)
+    prm["normal_model"] = 1
+    plan.set_params(prm)
+    xs, us, ws = D["xp"].clone(), D["up"].clone(), D["wp"].clone()
+    hist, whist = res["hist"].clone(), res["whist"].clone()
+    n_sub = 15
+    extras["substeps_ms"] = time_call(
+        lambda: plan.particle_substeps(float(prm["dt"]), n_sub, xs, us, ws, D["radius"],
+                                       D["mass"], res, hist, whist, want_forces=False), reps=5)
+    extras["substeps_n_sub"] = n_sub
+    plan.check("substeps")
+    plan.set_params(case.params)
     if not profile:
         st = plan.stats()
     out = dict(ms_per_step=ms, ms_per_step_graph=ms_graph, wall_s=wall, stats=st, n_iter=n_iter,
@@ -217,6 +231,19 @@ def copy_bandwidth(torch, gib: float = 2.0, reps: int = 5) -> float:
     del src, dst
     torch.cuda.empty_cache()
     return 2 * n * 4 / best / 1e9
+
+
+def cpu_substeps(case, pl):
+    """The oracle's sub-stepping of one call (bed particles, Hertz law, 15
+    sub-steps) on the host, for scale; pl = the oracle's lists."""
+    import oracle
+    prm = dict(case.params)
+    prm["normal_model"] = 1
+    ref = oracle.pair_forces(case, pl, params=prm)
+    t0 = time.perf_counter()
+    oracle.particle_substeps(case, pl, float(prm["dt"]), 15, hist=ref["hist"], whist=ref["whist"],
+                             params=prm)
+    return (time.perf_counter() - t0) * 1e3
 
 
 def cpu_baseline(case, mask_np):
@@ -309,12 +336,14 @@ def main():
                                           for k, n in r64["stats"]["kernel_launches"].items()})
 
     cpu = None
+    cpu_sub_ms = None
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline")
         import oracle
         pl = oracle.pairs(case)
         mask_np = oracle.marker_mask(case, pl)
         cpu = cpu_baseline(case, mask_np)
+        cpu_sub_ms = cpu_substeps(case, pl)
 
     line = dict(
         metric="marker-updates/s per forcing iter (FP32 batched vs FP64) at stated tol; HBM GB/s",
@@ -334,6 +363,11 @@ def main():
             note="level-set fluid integrals over all particles (one call, FP32 grid, "
                  "FP64 geometry and sums); not part of the step"),
         grid_mean_ms=r32["extras"]["grid_mean_ms"],
+        substeps=dict(ms=r32["extras"]["substeps_ms"], n_sub=r32["extras"]["substeps_n_sub"],
+                      particles=case.np_, cpu_oracle_ms=cpu_sub_ms,
+                      note="ibmx_particle_substeps of one time step (Hertz/ACTM contacts, "
+                           "15 three-stage sub-steps, FP64) on the step's contact lists; "
+                           "not part of the step"),
         backward=dict(ms=r32["extras"]["backward_ms"],
                       note="ibmx_forcing_backward of one call (FP32): binning, replay of the "
                            "passes with the Jacobians, adjoint passes; not part of the step"),

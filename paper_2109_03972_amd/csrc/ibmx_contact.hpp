@@ -249,8 +249,9 @@ __device__ void wall_contact(const PairC &P, int np, const double *xp, const dou
 }
 
 // ---------------------------------------------------------------------------
-// per-particle adjacency of the contact lists
-//   entry  pair k, p first:  2k;  pair k, p second: 2k + 1;  wall k: -(k + 1)
+// per-particle adjacency of the contact lists, int2 {code, aux} per entry
+//   code   pair k, p first:  2k;  pair k, p second: 2k + 1;  wall k: -(k + 1)
+//   aux    the partner's id (pairs) or the wall's side (walls)
 //   order  increasing partner id, then walls by side
 // ---------------------------------------------------------------------------
 struct ContactLists {
@@ -277,42 +278,38 @@ __global__ void k_adj_count(ContactLists C, int *deg)
     }
 }
 
-__global__ void k_adj_fill(ContactLists C, const int *off, int *cursor, int *adj)
+__global__ void k_adj_fill(ContactLists C, const int *off, int *cursor, int2 *adj)
 {
     const int npairs = n_pairs(C), nwall = n_walls(C);
     for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < npairs + nwall;
          k += gridDim.x * blockDim.x) {
         if (k < npairs) {
             const int i = C.pairs[k], j = C.pairs[C.pair_cap + k];
-            adj[off[i] + atomicAdd(&cursor[i], 1)] = 2 * k;
-            adj[off[j] + atomicAdd(&cursor[j], 1)] = 2 * k + 1;
+            adj[off[i] + atomicAdd(&cursor[i], 1)] = make_int2(2 * k, j);
+            adj[off[j] + atomicAdd(&cursor[j], 1)] = make_int2(2 * k + 1, i);
         } else {
             const int kw = k - npairs;
             const int p = C.walls[kw];
-            adj[off[p] + atomicAdd(&cursor[p], 1)] = -(kw + 1);
+            adj[off[p] + atomicAdd(&cursor[p], 1)] = make_int2(-(kw + 1), C.walls[C.wall_cap + kw]);
         }
     }
 }
 
-__device__ __forceinline__ int adj_key(const ContactLists &C, int np, int e)
-{
-    if (e >= 0)
-        return (e & 1) ? C.pairs[e >> 1] : C.pairs[C.pair_cap + (e >> 1)];
-    return np + C.walls[C.wall_cap + (-e - 1)];
-}
+__device__ __forceinline__ int adj_key(int np, int2 e) { return e.x >= 0 ? e.y : np + e.y; }
 
 // insertion sort of each particle's entries by key (a few dozen at most)
-__global__ void k_adj_sort(ContactLists C, int np, const int *off, int *adj)
+__global__ void k_adj_sort(int np, const int *off, int2 *adj)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= np)
         return;
-    int *a = adj + off[p];
+    int2 *a = adj + off[p];
     const int n = off[p + 1] - off[p];
     for (int i = 1; i < n; ++i) {
-        const int v = a[i], kv = adj_key(C, np, v);
+        const int2 v = a[i];
+        const int kv = adj_key(np, v);
         int j = i - 1;
-        while (j >= 0 && adj_key(C, np, a[j]) > kv) {
+        while (j >= 0 && adj_key(np, a[j]) > kv) {
             a[j + 1] = a[j];
             --j;
         }
@@ -331,56 +328,187 @@ struct HistC {
     const double *wall;
 };
 
-// Collision force and torque on particle p at state (xp, up, wp): its
-// contacts evaluated with history hold and spring step dt, summed in
-// adjacency order.  With hnew set, the contacts p owns (the pairs it is
-// first of, its walls) write their new history there.
-__device__ void particle_contacts(const PairC &P, int np, int p, const ContactLists &C,
-                                  const int *off, const int *adj, const double *xp,
-                                  const double *up, const double *wp, const double *radius,
-                                  const double *mass, HistC hold, double dt, Hist hnew, double *F,
-                                  double *T)
+// ---------------------------------------------------------------------------
+// one contact evaluation of every particle, optionally followed by a stage
+// of the particle update
+//
+// kContactLanes lanes serve one particle: lane j evaluates the particle's
+// adjacency entries j, j + kContactLanes, ... (the pair in its canonical
+// orientation, so both particles of a pair obtain identical values), the
+// particle's first lane sums the results in adjacency order (increasing
+// partner id, walls after) and applies the update.  With hnew set, each
+// pair's first particle and each wall's particle write the new history.
+// ---------------------------------------------------------------------------
+constexpr int kContactLanes = 8;
+constexpr int kContactBlock = 256;
+
+enum { kStageForces = 0, kStagePredict = 1, kStageCorrect = 2 };
+
+struct Stage {
+    double dts;       // sub-step length
+    double a2;        // 2 alpha_k
+    double alpha;     // alpha_k
+    double gamma;     // gamma_k
+    double zeta;      // zeta_k
+};
+
+struct Body {
+    const double *radius, *mass;
+    const double *Fh, *Th;   // or null
+    const double *sF;        // per-particle factor of F_h, T_h
+};
+
+struct StageIO {
+    const double *xs, *us, *ws;   // state the contacts are evaluated at
+    double *xa, *ua, *wa;         // accepted state (own entries updated by the corrector)
+    double *xt, *ut, *wt;         // predicted state (written by the predictor)
+    double *Fcur;                 // [6][np] force and torque at the accepted state
+    const double *Fprev;          // [6][np] the same one stage earlier
+    double *Fc, *Tc;              // forces mode: outputs (or null)
+};
+
+// the contribution of adjacency entry ea to particle p: F (3), T (3)
+__device__ __forceinline__ void entry_contact(const PairC &P, int np, const ContactLists &C,
+                                              int p, int2 ea, const double *xs, const double *us,
+                                              const double *ws, const double *radius,
+                                              const double *mass, HistC hold, double dt,
+                                              Hist hnew, double *f6)
 {
-    for (int a = 0; a < 3; ++a) {
-        F[a] = 0.0;
-        T[a] = 0.0;
-    }
-    for (int r = off[p]; r < off[p + 1]; ++r) {
-        const int e = adj[r];
-        double ho[kHist], hn[kHist], f[3], t1[3], t2[3];
-        if (e >= 0) {
-            const int k = e >> 1;
-            for (int a = 0; a < kHist; ++a)
-                ho[a] = hold.pair[(size_t)a * C.pair_cap + k];
-            pair_contact(P, np, xp, up, wp, radius, mass, C.pairs[k], C.pairs[C.pair_cap + k], ho,
-                         dt, f, t1, t2, hn);
-            if (e & 1) {
-                for (int a = 0; a < 3; ++a) {
-                    F[a] = F[a] - f[a];
-                    T[a] = T[a] + t2[a];
-                }
-            } else {
-                for (int a = 0; a < 3; ++a) {
-                    F[a] = F[a] + f[a];
-                    T[a] = T[a] + t1[a];
-                }
-                if (hnew.pair)
-                    for (int a = 0; a < kHist; ++a)
-                        hnew.pair[(size_t)a * C.pair_cap + k] = hn[a];
+    double ho[kHist], hn[kHist], f[3], t1[3], t2[3];
+    const int e = ea.x;
+    if (e >= 0) {
+        const int k = e >> 1;
+        for (int a = 0; a < kHist; ++a)
+            ho[a] = hold.pair[(size_t)a * C.pair_cap + k];
+        const int i = (e & 1) ? ea.y : p, j = (e & 1) ? p : ea.y;
+        pair_contact(P, np, xs, us, ws, radius, mass, i, j, ho, dt, f, t1, t2, hn);
+        if (e & 1) {
+            for (int a = 0; a < 3; ++a) {
+                f6[a] = -f[a];
+                f6[3 + a] = t2[a];
             }
         } else {
-            const int k = -e - 1;
-            for (int a = 0; a < kHist; ++a)
-                ho[a] = hold.wall[(size_t)a * C.wall_cap + k];
-            wall_contact(P, np, xp, up, wp, radius, mass, C.walls[k], C.walls[C.wall_cap + k], ho,
-                         dt, f, t1, hn);
             for (int a = 0; a < 3; ++a) {
-                F[a] = F[a] + f[a];
-                T[a] = T[a] + t1[a];
+                f6[a] = f[a];
+                f6[3 + a] = t1[a];
             }
-            if (hnew.wall)
+            if (hnew.pair)
                 for (int a = 0; a < kHist; ++a)
-                    hnew.wall[(size_t)a * C.wall_cap + k] = hn[a];
+                    hnew.pair[(size_t)a * C.pair_cap + k] = hn[a];
+        }
+    } else {
+        const int k = -e - 1;
+        for (int a = 0; a < kHist; ++a)
+            ho[a] = hold.wall[(size_t)a * C.wall_cap + k];
+        wall_contact(P, np, xs, us, ws, radius, mass, p, ea.y, ho, dt, f, t1, hn);
+        for (int a = 0; a < 3; ++a) {
+            f6[a] = f[a];
+            f6[3 + a] = t1[a];
+        }
+        if (hnew.wall)
+            for (int a = 0; a < kHist; ++a)
+                hnew.wall[(size_t)a * C.wall_cap + k] = hn[a];
+    }
+}
+
+// particle constants: I = 2/5 m R^2, g' = (1 - rho_f / rho_p) g
+__device__ __forceinline__ void body_terms(const PairC &P, const Body &B, int p, double &m,
+                                           double &I, double *gp)
+{
+    m = B.mass[p];
+    const double R = B.radius[p];
+    I = 0.4 * m * R * R;
+    const double rho_p = m / (4.0 / 3.0 * M_PI * R * R * R);
+    for (int a = 0; a < 3; ++a)
+        gp[a] = (1.0 - P.rho_f / rho_p) * P.g[a];
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kContactBlock) void k_contact_stage(PairC P, int np, ContactLists C,
+                                                                const int *off, const int2 *adj,
+                                                                Body B, HistC hold, double dt,
+                                                                Hist hnew, StageIO io, Stage S)
+{
+    __shared__ double part[kContactBlock][6];
+    __shared__ int chunks;
+    const int g = threadIdx.x / kContactLanes, j = threadIdx.x % kContactLanes;
+    const int p = blockIdx.x * (kContactBlock / kContactLanes) + g;
+    int lo = 0, deg = 0;
+    if (p < np) {
+        lo = off[p];
+        deg = off[p + 1] - lo;
+    }
+    if (threadIdx.x == 0)
+        chunks = 0;
+    __syncthreads();
+    if (j == 0 && deg > 0)
+        atomicMax(&chunks, (deg + kContactLanes - 1) / kContactLanes);
+    __syncthreads();
+    const int nch = chunks;
+    double F[3] = {0.0, 0.0, 0.0}, T[3] = {0.0, 0.0, 0.0};
+    for (int c = 0; c < nch; ++c) {
+        const int r = c * kContactLanes + j;
+        if (r < deg) {
+            double f6[6];
+            entry_contact(P, np, C, p, adj[lo + r], io.xs, io.us, io.ws, B.radius, B.mass, hold,
+                          dt, hnew, f6);
+            for (int q = 0; q < 6; ++q)
+                part[threadIdx.x][q] = f6[q];
+        }
+        __syncthreads();
+        if (j == 0) {
+            const int n = min(kContactLanes, deg - c * kContactLanes);
+            for (int t = 0; t < n; ++t)
+                for (int a = 0; a < 3; ++a) {
+                    F[a] = F[a] + part[threadIdx.x + t][a];
+                    T[a] = T[a] + part[threadIdx.x + t][3 + a];
+                }
+        }
+        __syncthreads();
+    }
+    if (j != 0 || p >= np)
+        return;
+    if (MODE == kStageForces) {
+        if (io.Fc)
+            for (int a = 0; a < 3; ++a) {
+                io.Fc[(size_t)a * np + p] = F[a];
+                io.Tc[(size_t)a * np + p] = T[a];
+            }
+        return;
+    }
+    // the particle's own inputs are loaded only now: loading them before the
+    // contacts raises the register count past three waves per SIMD
+    double m, I, gp[3];
+    body_terms(P, B, p, m, I, gp);
+    const double sF = B.sF[p];
+    for (int a = 0; a < 3; ++a) {
+        const size_t i = (size_t)a * np + p;
+        const double Fh = B.Fh ? sF * B.Fh[i] : 0.0, Th = B.Th ? sF * B.Th[i] : 0.0;
+        const double u0 = io.ua[i], w0 = io.wa[i], x0 = io.xa[i];
+        if (MODE == kStagePredict) {
+            // F, T: the accepted state's force, kept for the corrector and
+            // the next stage
+            io.Fcur[i] = F[a];
+            io.Fcur[(size_t)3 * np + i] = T[a];
+            double fs = S.a2 * Fh + S.gamma * F[a];
+            double ts = S.a2 * Th + S.gamma * T[a];
+            if (S.zeta != 0.0) {
+                fs = fs + S.zeta * io.Fprev[i];
+                ts = ts + S.zeta * io.Fprev[(size_t)3 * np + i];
+            }
+            const double u1 = u0 + S.dts / m * fs + S.a2 * S.dts * gp[a];
+            io.ut[i] = u1;
+            io.wt[i] = w0 + S.dts / I * ts;
+            io.xt[i] = x0 + S.alpha * S.dts * (u1 + u0);
+        } else {
+            // F, T: the predicted state's force
+            const double fs = S.a2 * Fh + S.gamma * F[a] + S.zeta * io.Fcur[i];
+            const double ts = S.a2 * Th + S.gamma * T[a] + S.zeta * io.Fcur[(size_t)3 * np + i];
+            const double u1 = u0 + S.dts / m * fs + S.a2 * S.dts * gp[a];
+            const double w1 = w0 + S.dts / I * ts;
+            io.xa[i] = x0 + S.alpha * S.dts * (u1 + u0);
+            io.ua[i] = u1;
+            io.wa[i] = w1;
         }
     }
 }
@@ -425,6 +553,20 @@ inline void contact_constants(const ibmx_plan p, PairC *P)
 
 inline int contact_blocks(long long n, int b) { return n > 0 ? (int)((n + b - 1) / b) : 1; }
 
+// One contact evaluation of every particle (and a stage update with MODE
+// kStagePredict / kStageCorrect).
+template <int MODE>
+inline void contact_stage(const PairC &P, int np, const ContactLists &C, const int *off,
+                          const int2 *adj, const Body &B, HistC hold, double dt, Hist hnew,
+                          const StageIO &io, const Stage &S, hipStream_t s)
+{
+    if (np <= 0)
+        return;
+    const int per = kContactBlock / kContactLanes;
+    hipLaunchKernelGGL(k_contact_stage<MODE>, dim3((np + per - 1) / per), dim3(kContactBlock), 0,
+                       s, P, np, C, off, adj, B, hold, dt, hnew, io, S);
+}
+
 // Adjacency of the lists in C into the plan's contact workspace (c_off,
 // c_adj), which holds np + 1 offsets and 2 pair_cap + wall_cap entries.
 inline void contact_adjacency(ibmx_plan p, const ContactLists &C, hipStream_t s)
@@ -438,7 +580,7 @@ inline void contact_adjacency(ibmx_plan p, const ContactLists &C, hipStream_t s)
     ibmx_exclusive_scan(p->c_deg, p->c_off, np, p->scan_aux, s);
     hipLaunchKernelGGL(k_adj_fill, dim3(g), dim3(256), 0, s, C, (const int *)p->c_off, p->c_cur,
                        p->c_adj);
-    hipLaunchKernelGGL(k_adj_sort, dim3(contact_blocks(np, 64)), dim3(64), 0, s, C, np,
+    hipLaunchKernelGGL(k_adj_sort, dim3(contact_blocks(np, 64)), dim3(64), 0, s, np,
                        (const int *)p->c_off, p->c_adj);
 }
 

@@ -112,7 +112,7 @@ struct ibmx_plan_s {
     int *c_deg;           // [np + 1]
     int *c_off;           // [np + 1]
     int *c_cur;           // [np]
-    int *c_adj;           // [c_adj_cap]
+    int2 *c_adj;          // [c_adj_cap] {code, partner or side}
     long long c_adj_cap;
     double *c_hist;       // [c_hist_cap] history buffers
     long long c_hist_cap;

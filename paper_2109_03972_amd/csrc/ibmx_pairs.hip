@@ -6,8 +6,9 @@
 //               particle's partners sorted by id, so the list is in (i, j)
 //               order and independent of thread scheduling;
 //   wall list   (p, side) for every wall closer than gap_cut;
-//   forces      lubrication, linear spring-dashpot normal contact and capped
-//               tangential spring-dashpot (eq. f_int), one thread per entry;
+//   forces      lubrication, normal contact (linear or Hertz) and capped
+//               tangential spring-dashpot (eq. f_int): a group of lanes per
+//               particle evaluates its contacts, summed in partner order;
 //   mask        the marker-disable rule, one workgroup per close pair/wall.
 //
 // Distances, gaps and cell indices are computed with the operation order
@@ -302,25 +303,6 @@ __global__ void k_hist_align(ContactLists C, int n_in, const int *pairs_in, cons
     }
 }
 
-// collision force and torque of every particle, one thread per particle
-__global__ __launch_bounds__(64) void k_contact_forces(PairC P, int np, ContactLists C,
-                                                       const int *off, const int *adj,
-                                                       const double *xp, const double *up,
-                                                       const double *wp, const double *radius,
-                                                       const double *mass, HistC hold, Hist hnew,
-                                                       double *Fc, double *Tc)
-{
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= np)
-        return;
-    double F[3], T[3];
-    particle_contacts(P, np, p, C, off, adj, xp, up, wp, radius, mass, hold, P.dt, hnew, F, T);
-    for (int a = 0; a < 3; ++a) {
-        Fc[(size_t)a * np + p] = F[a];
-        Tc[(size_t)a * np + p] = T[a];
-    }
-}
-
 // ---------------------------------------------------------------------------
 // marker-disable mask
 // ---------------------------------------------------------------------------
@@ -499,10 +481,16 @@ extern "C" ibmx_status ibmx_pairs(ibmx_plan p, const double *xp, const double *r
                            nwall_in, walls_in, whist_in, hold);
     }
     contact_adjacency(p, C, s);
-    if (np > 0)
-        hipLaunchKernelGGL(k_contact_forces, dim3(blocks(np, 64)), dim3(64), 0, s, P, np, C,
-                           (const int *)p->c_off, (const int *)p->c_adj, xp, up, wp, radius, mass,
-                           HistC{hold.pair, hold.wall}, Hist{hist_out, whist_out}, Fc, Tc);
+    StageIO io{};
+    io.xs = xp;
+    io.us = up;
+    io.ws = wp;
+    io.Fc = Fc;
+    io.Tc = Tc;
+    contact_stage<kStageForces>(P, np, C, p->c_off, (const int2 *)p->c_adj,
+                                Body{radius, mass, nullptr, nullptr, nullptr},
+                                HistC{hold.pair, hold.wall}, P.dt, Hist{hist_out, whist_out}, io,
+                                Stage{}, s);
     // mask
     if (marker_active && nm > 0) {
         ibmx_fill_u8(marker_active, 1, nm, s);

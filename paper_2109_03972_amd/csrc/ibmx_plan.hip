@@ -484,7 +484,7 @@ ibmx_status ibmx_contact_reserve(ibmx_plan p, int pair_cap, int wall_cap, int hi
             (void)hipFree(p->c_adj);
         p->c_adj = nullptr;
         p->c_adj_cap = 0;
-        if (hipMalloc((void **)&p->c_adj, sizeof(int) * (size_t)(nadj > 0 ? nadj : 1)) != hipSuccess)
+        if (hipMalloc((void **)&p->c_adj, sizeof(int2) * (size_t)(nadj > 0 ? nadj : 1)) != hipSuccess)
             return IBMX_ENOMEM;
         p->c_adj_cap = nadj;
     }

@@ -2,15 +2,15 @@
 // Hertz normal contact (Sec. 2.2.7).
 //
 // One call advances the particles by n_sub sub-steps of three Runge-Kutta
-// stages; each stage is two launches of one thread per particle:
-//   predictor  collision force at the accepted state s^{k-1} (committing
-//              the contact history of that state), then s~;
-//   corrector  collision force at s~ (history not committed), then s^k.
-// Both read the partners' state from a buffer no launch writes to at the
-// same time: the predictor reads the accepted states and writes the
-// predicted ones, the corrector the other way round, each particle writing
-// only its own entries.  The stage forces of s^{k-1} and s^{k-2} are kept
-// per particle in two alternating buffers.
+// stages; each stage is two launches of a lane group per particle:
+//   predictor  contacts at the accepted state s^{k-1} (committing the
+//              contact history of that state), then s~ into a separate
+//              state buffer;
+//   corrector  contacts at s~ (history not committed), then s^k over the
+//              particle's own s^{k-1}.
+// Contacts read the partners' state from a buffer no launch in flight
+// writes; the stage forces of s^{k-1} and s^{k-2} are kept per particle in
+// two alternating buffers.
 #include <float.h>
 
 #include "ibmx_contact.hpp"
@@ -110,24 +110,10 @@ namespace {
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
-struct Stage {
-    double dts;       // sub-step length
-    double a2;        // 2 alpha_k
-    double alpha;     // alpha_k
-    double gamma;     // gamma_k
-    double zeta;      // zeta_k
-};
-
-struct Body {
-    const double *radius, *mass;
-    const double *Fh, *Th;   // or null
-    const double *sF;        // per-particle factor of F_h, T_h
-};
-
 // F_h, T_h factor of each particle: 0 when the switch is on and the input
 // history holds at least one contact of the particle, all with St <= St_crit
 __global__ __launch_bounds__(64) void k_st_factor(PairC P, int np, ContactLists C, const int *off,
-                                                  const int *adj, const double *radius,
+                                                  const int2 *adj, const double *radius,
                                                   const double *mass, HistC h0, int on,
                                                   double *sF)
 {
@@ -136,11 +122,11 @@ __global__ __launch_bounds__(64) void k_st_factor(PairC P, int np, ContactLists 
         return;
     int contacts = 0, fast = 0;
     for (int r = off[p]; r < off[p + 1]; ++r) {
-        const int e = adj[r];
+        const int e = adj[r].x;
         double u_in, rhod;
         if (e >= 0) {
             const int k = e >> 1;
-            const int i = C.pairs[k], j = C.pairs[C.pair_cap + k];
+            const int i = (e & 1) ? adj[r].y : p, j = (e & 1) ? p : adj[r].y;
             u_in = h0.pair[(size_t)3 * C.pair_cap + k];
             rhod = 0.5 * (rho_d(mass[i], radius[i]) + rho_d(mass[j], radius[j]));
         } else {
@@ -155,107 +141,6 @@ __global__ __launch_bounds__(64) void k_st_factor(PairC P, int np, ContactLists 
         fast += St > P.St_crit;
     }
     sF[p] = (on && contacts > 0 && fast == 0) ? 0.0 : 1.0;
-}
-
-// particle constants: I = 2/5 m R^2, g' = (1 - rho_f / rho_p) g
-__device__ __forceinline__ void body_terms(const PairC &P, const Body &B, int p, double &m,
-                                           double &I, double *gp)
-{
-    m = B.mass[p];
-    const double R = B.radius[p];
-    I = 0.4 * m * R * R;
-    const double rho_p = m / (4.0 / 3.0 * M_PI * R * R * R);
-    for (int a = 0; a < 3; ++a)
-        gp[a] = (1.0 - P.rho_f / rho_p) * P.g[a];
-}
-
-// predictor: collision force at the accepted state (committed to hnew and
-// kept in Fcur), then the predicted state
-__global__ __launch_bounds__(64) void k_stage_predict(PairC P, int np, ContactLists C,
-                                                      const int *off, const int *adj,
-                                                      const double *xp, const double *up,
-                                                      const double *wp, double *xt, double *ut,
-                                                      double *wt, Body B, HistC hold, Hist hnew,
-                                                      double dt_h, double *Fcur,
-                                                      const double *Fprev, Stage S)
-{
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= np)
-        return;
-    double Fa[3], Ta[3];
-    particle_contacts(P, np, p, C, off, adj, xp, up, wp, B.radius, B.mass, hold, dt_h, hnew, Fa,
-                      Ta);
-    double m, I, gp[3];
-    body_terms(P, B, p, m, I, gp);
-    const double sF = B.sF[p];
-    for (int a = 0; a < 3; ++a) {
-        const size_t i = (size_t)a * np + p;
-        Fcur[i] = Fa[a];
-        Fcur[(size_t)3 * np + i] = Ta[a];
-        const double Fh = B.Fh ? sF * B.Fh[i] : 0.0, Th = B.Th ? sF * B.Th[i] : 0.0;
-        double fs = S.a2 * Fh + S.gamma * Fa[a];
-        double ts = S.a2 * Th + S.gamma * Ta[a];
-        if (S.zeta != 0.0) {
-            fs = fs + S.zeta * Fprev[i];
-            ts = ts + S.zeta * Fprev[(size_t)3 * np + i];
-        }
-        const double u0 = up[i];
-        const double u1 = u0 + S.dts / m * fs + S.a2 * S.dts * gp[a];
-        ut[i] = u1;
-        wt[i] = wp[i] + S.dts / I * ts;
-        xt[i] = xp[i] + S.alpha * S.dts * (u1 + u0);
-    }
-}
-
-// corrector: collision force at the predicted state, then the accepted
-// state s^k written over the particle's own s^{k-1}
-__global__ __launch_bounds__(64) void k_stage_correct(PairC P, int np, ContactLists C,
-                                                      const int *off, const int *adj, double *xp,
-                                                      double *up, double *wp, const double *xt,
-                                                      const double *ut, const double *wt, Body B,
-                                                      HistC hold, const double *Fcur, Stage S)
-{
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= np)
-        return;
-    double Fp[3], Tp[3];
-    particle_contacts(P, np, p, C, off, adj, xt, ut, wt, B.radius, B.mass, hold, S.a2 * S.dts,
-                      Hist{nullptr, nullptr}, Fp, Tp);
-    double m, I, gp[3];
-    body_terms(P, B, p, m, I, gp);
-    const double sF = B.sF[p];
-    for (int a = 0; a < 3; ++a) {
-        const size_t i = (size_t)a * np + p;
-        const double Fh = B.Fh ? sF * B.Fh[i] : 0.0, Th = B.Th ? sF * B.Th[i] : 0.0;
-        const double fs = S.a2 * Fh + S.gamma * Fp[a] + S.zeta * Fcur[i];
-        const double ts = S.a2 * Th + S.gamma * Tp[a] + S.zeta * Fcur[(size_t)3 * np + i];
-        const double u0 = up[i];
-        const double u1 = u0 + S.dts / m * fs + S.a2 * S.dts * gp[a];
-        const double w1 = wp[i] + S.dts / I * ts;
-        xp[i] = xp[i] + S.alpha * S.dts * (u1 + u0);
-        up[i] = u1;
-        wp[i] = w1;
-    }
-}
-
-// the final state: its collision force and committed history
-__global__ __launch_bounds__(64) void k_stage_final(PairC P, int np, ContactLists C,
-                                                    const int *off, const int *adj,
-                                                    const double *xp, const double *up,
-                                                    const double *wp, Body B, HistC hold,
-                                                    Hist hnew, double dt_h, double *Fc,
-                                                    double *Tc)
-{
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= np)
-        return;
-    double F[3], T[3];
-    particle_contacts(P, np, p, C, off, adj, xp, up, wp, B.radius, B.mass, hold, dt_h, hnew, F, T);
-    if (Fc)
-        for (int a = 0; a < 3; ++a) {
-            Fc[(size_t)a * np + p] = F[a];
-            Tc[(size_t)a * np + p] = T[a];
-        }
 }
 
 }  // namespace
@@ -318,37 +203,54 @@ extern "C" ibmx_status ibmx_particle_substeps(ibmx_plan p, double dt_total, int3
         ibmx_fill_i32(p->c_off, 0, np + 1, s);
     }
     hipLaunchKernelGGL(k_st_factor, dim3(nb), dim3(64), 0, s, P, np, C, (const int *)p->c_off,
-                       (const int *)p->c_adj, radius, mass, HistC{H[0].pair, H[0].wall},
+                       (const int2 *)p->c_adj, radius, mass, HistC{H[0].pair, H[0].wall},
                        p->prm.st_switch, sF);
     static const double alpha[3] = {4.0 / 15.0, 1.0 / 15.0, 1.0 / 6.0};
     static const double gamma_[3] = {8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0};
     static const double zeta_[3] = {0.0, -17.0 / 60.0, -5.0 / 12.0};
     const double dts = dt_total / n_sub;
     const Body B{radius, mass, Fh, Th, sF};
+    const int *off = p->c_off;
+    const int2 *adj = p->c_adj;
+    StageIO io{};
+    io.xa = xp;
+    io.ua = up;
+    io.wa = wp;
+    io.xt = xt;
+    io.ut = ut;
+    io.wt = wt;
     int cur = 0;
     double t_since = 0.0;
     long long gs = 0;
     for (int sub = 0; sub < n_sub; ++sub)
         for (int k = 0; k < 3; ++k, ++gs) {
             const Stage S{dts, 2.0 * alpha[k], alpha[k], gamma_[k], zeta_[k]};
-            double *Fcur = Fbuf[gs & 1];
-            const double *Fprev = Fbuf[(gs + 1) & 1];
-            hipLaunchKernelGGL(k_stage_predict, dim3(nb), dim3(64), 0, s, P, np, C,
-                               (const int *)p->c_off, (const int *)p->c_adj, (const double *)xp,
-                               (const double *)up, (const double *)wp, xt, ut, wt, B,
-                               HistC{H[cur].pair, H[cur].wall}, H[1 - cur], t_since, Fcur, Fprev,
-                               S);
-            hipLaunchKernelGGL(k_stage_correct, dim3(nb), dim3(64), 0, s, P, np, C,
-                               (const int *)p->c_off, (const int *)p->c_adj, xp, up, wp,
-                               (const double *)xt, (const double *)ut, (const double *)wt, B,
-                               HistC{H[1 - cur].pair, H[1 - cur].wall}, (const double *)Fcur, S);
+            io.Fcur = Fbuf[gs & 1];
+            io.Fprev = Fbuf[(gs + 1) & 1];
+            // contacts at the accepted state (committing its history), then s~
+            io.xs = xp;
+            io.us = up;
+            io.ws = wp;
+            contact_stage<kStagePredict>(P, np, C, off, adj, B, HistC{H[cur].pair, H[cur].wall},
+                                         t_since, H[1 - cur], io, S, s);
+            // contacts at s~, then s^k
+            io.xs = xt;
+            io.us = ut;
+            io.ws = wt;
+            contact_stage<kStageCorrect>(P, np, C, off, adj, B,
+                                         HistC{H[1 - cur].pair, H[1 - cur].wall}, S.a2 * dts,
+                                         Hist{nullptr, nullptr}, io, S, s);
             cur = 1 - cur;
             t_since = S.a2 * dts;
         }
-    hipLaunchKernelGGL(k_stage_final, dim3(nb), dim3(64), 0, s, P, np, C, (const int *)p->c_off,
-                       (const int *)p->c_adj, (const double *)xp, (const double *)up,
-                       (const double *)wp, B, HistC{H[cur].pair, H[cur].wall},
-                       Hist{pair_cap > 0 ? hist : nullptr, wall_cap > 0 ? whist : nullptr},
-                       t_since, Fc, Tc);
+    // the final state: committed history and collision force
+    io.xs = xp;
+    io.us = up;
+    io.ws = wp;
+    io.Fc = Fc;
+    io.Tc = Tc;
+    contact_stage<kStageForces>(P, np, C, off, adj, B, HistC{H[cur].pair, H[cur].wall}, t_since,
+                                Hist{pair_cap > 0 ? hist : nullptr, wall_cap > 0 ? whist : nullptr},
+                                io, Stage{}, s);
     return ibmx_launch_check();
 }
