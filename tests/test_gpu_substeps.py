@@ -43,7 +43,8 @@ def _device_lists(plan, D, case, ref_l, ref_f, pair_cap=None, wall_cap=None):
     return res, hist, whist, k, kw
 
 
-def _run_both(case, dt_total, n_sub, seed=0, with_fh=True, pair_cap=None, wall_cap=None):
+def _run_both(case, dt_total, n_sub, seed=0, with_fh=True, pair_cap=None, wall_cap=None,
+              precision="f64"):
     import torch
     rng = np.random.default_rng(seed)
     Fh = rng.normal(0, 1e-3, (3, case.np_)) if with_fh else None
@@ -52,7 +53,7 @@ def _run_both(case, dt_total, n_sub, seed=0, with_fh=True, pair_cap=None, wall_c
     ref = oracle.particle_substeps(case, ref_l, dt_total, n_sub, Fh=Fh, Th=Th,
                                    hist=ref_f["hist"], whist=ref_f["whist"])
     D = dev_case(case, "f64")
-    plan = ibmx.Plan.from_case(case, "f64")
+    plan = ibmx.Plan.from_case(case, precision)
     res, hist, whist, k, kw = _device_lists(plan, D, case, ref_l, ref_f, pair_cap, wall_cap)
     dev = D["xp"].device
     Fh_d = None if Fh is None else torch.as_tensor(Fh).to(dev).contiguous()
@@ -128,6 +129,15 @@ def test_wall_contacts(model):
     got, ref, ref_l = _run_both(c, 1.0, 15, seed=6)
     got["x0"] = x0
     assert np.any(ref_l["wgap"] < 0) and np.any(ref_l["gap"] < 0)
+    _compare(got, ref)
+
+
+def test_fp32_plan():
+    """The contact pass is FP64 whatever the plan's grid precision."""
+    c = _wall_layer(308)
+    x0 = c.xp.copy()
+    got, ref, _ = _run_both(c, 1.0, 15, seed=7, precision="f32")
+    got["x0"] = x0
     _compare(got, ref)
 
 
