@@ -201,6 +201,13 @@ def run_gpu(case, precision, steps, warmup, profile=True, tune=True, tile=None):
     extras["substeps_n_sub"] = n_sub
     plan.check("substeps")
     plan.set_params(case.params)
+    # pressure projection of the fluid solver on the same grid (FP64 solve)
+    if precision == "f32":
+        uc = u.clone()
+        P = torch.zeros(u.shape[1:], dtype=u.dtype, device=dev)
+        extras["project_ms"] = time_call(lambda: plan.project(uc, P, 0.0, want_phi=False), reps=3)
+        plan.check("project")
+        del uc, P
     if not profile:
         st = plan.stats()
     out = dict(ms_per_step=ms, ms_per_step_graph=ms_graph, wall_s=wall, stats=st, n_iter=n_iter,
@@ -363,6 +370,9 @@ def main():
             note="level-set fluid integrals over all particles (one call, FP32 grid, "
                  "FP64 geometry and sums); not part of the step"),
         grid_mean_ms=r32["extras"]["grid_mean_ms"],
+        project=dict(ms=r32["extras"]["project_ms"],
+                     note="ibmx_project on the workload's grid (face interpolation, FP64 "
+                          "FFT/tridiagonal Poisson solve, corrections); not part of the step"),
         substeps=dict(ms=r32["extras"]["substeps_ms"], n_sub=r32["extras"]["substeps_n_sub"],
                       particles=case.np_, cpu_oracle_ms=cpu_sub_ms,
                       note="ibmx_particle_substeps of one time step (Hertz/ACTM contacts, "

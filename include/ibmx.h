@@ -28,12 +28,13 @@
  *     or writes it inside the call, asynchronously on the plan's stream, so
  *     buffers must stay valid until the stream reaches the call.
  *   * Compute calls never synchronise the stream and allocate nothing, with
- *     four exceptions that allocate (and so may synchronise the device):
+ *     five exceptions that allocate (and so may synchronise the device):
  *     the first ibmx_forcing_backward call on a plan sizes its replay
  *     workspace, ibmx_pairs grows its cell and contact workspace the first
  *     time the cell grid (set by radius_max and gap_cut) or the list
  *     capacities exceed those of earlier calls, ibmx_particle_substeps
- *     likewise for its contact and stage workspace, and ibmx_tune.
+ *     likewise for its contact and stage workspace, the first
+ *     ibmx_project call, and ibmx_tune.
  *     ibmx_forcing can be captured into a HIP graph (ibmx_forcing_graph
  *     does that), and so can ibmx_pairs and ibmx_particle_substeps once
  *     their workspace has been sized.  Errors that only the device can
@@ -433,6 +434,31 @@ IBMX_API ibmx_status ibmx_particle_substeps(ibmx_plan plan, double dt_total, int
                                    const int32_t *counts, int32_t pair_cap, const int32_t *pairs,
                                    int32_t wall_cap, const int32_t *walls, double *hist,
                                    double *whist, double *Fc, double *Tc);
+
+/*
+ * Pressure projection of one Runge-Kutta stage of the collocated fluid
+ * solver (Sec. 2.2.1 and eq. fluid-solver, steps f-i), with c =
+ * params.two_alpha_dt and nu = params.nu_f:
+ *   u_f* = the mean of the two cells next to each face (walls: 0);
+ *   L phi = div(u_f*) / c, L the compact Laplacian (phi_+ - 2 phi + phi_-)/h^2
+ *     per axis with zero normal gradient at walls, phi of zero mean;
+ *   u   = u* - c grad(phi), grad the mean of the cell's two face gradients;
+ *   u_f = u_f* - c (phi_+ - phi)/h on every interior face;
+ *   P   = (1 - theta) P_prev + phi - (c/2) nu L phi (theta 0: pressure
+ *     projection, incremental; theta 1: pressure correction).
+ * u      T[3][nz][ny][nx] (the plan's precision), in: u*, out: u at the end of
+ *        the stage.
+ * uf     T[3][nz][ny][nx], out: normal velocity on the +x, +y, +z face of
+ *        each cell (0 on a wall face).
+ * P      T[nz][ny][nx], in/out.  phi: T[nz][ny][nx] or NULL, out.
+ * The solve is direct and FP64: FFTs along x and y (and z when periodic),
+ * across walls in z a tridiagonal elimination per Fourier mode.  Needs
+ * periodic x and y with power-of-two sizes up to 1024 (and the same for z
+ * when periodic), else EUNSUPPORTED.  The first call allocates the plan's
+ * projection workspace (a complex FP64 grid, an FP64 grid when z has walls).
+ */
+IBMX_API ibmx_status ibmx_project(ibmx_plan plan, void *u, void *uf, void *P, void *phi,
+                                  double theta);
 
 /* Static description of a status code. */
 IBMX_API const char *ibmx_status_string(ibmx_status status);

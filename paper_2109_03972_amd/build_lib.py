@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libibmx.so")
 BUILD = os.path.join(ROOT, "_build", "ibmx")
 
 SOURCES = ["ibmx_util.hip", "ibmx_plan.hip", "ibmx_forcing.hip", "ibmx_graph.hip", "ibmx_pairs.hip",
-           "ibmx_particle.hip", "ibmx_substep.hip"]
+           "ibmx_particle.hip", "ibmx_substep.hip", "ibmx_fluid.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

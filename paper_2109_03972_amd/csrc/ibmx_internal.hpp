@@ -119,6 +119,12 @@ struct ibmx_plan_s {
     double *s_buf;        // [s_cap] sub-step states, stage forces, F_h factors
     long long s_cap;
 
+    // projection workspace (first ibmx_project call): complex grid, the
+    // elimination scratch for walls in z, FFT twiddles per axis
+    double2 *fl_z;
+    double *fl_cp;
+    double2 *fl_tw[3];
+
     // last-call statistics
     ibmx_stats stats;
 

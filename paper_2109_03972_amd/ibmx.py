@@ -26,7 +26,8 @@ API = (
     "ibmx_plan_profile",
     "ibmx_forcing", "ibmx_forcing_graph",
     "ibmx_forcing_backward", "ibmx_pairs", "ibmx_tune", "ibmx_particle_integrals",
-    "ibmx_grid_mean", "ibmx_particle_substeps", "ibmx_status_string", "ibmx_version",
+    "ibmx_grid_mean", "ibmx_particle_substeps", "ibmx_project", "ibmx_status_string",
+    "ibmx_version",
 )
 
 HIST = 4   # rows of a contact history array (IBMX_HIST)
@@ -112,6 +113,8 @@ def lib():
         L.ibmx_particle_integrals.argtypes = [P] * 7
         L.ibmx_grid_mean.restype = St
         L.ibmx_grid_mean.argtypes = [P] * 3
+        L.ibmx_project.restype = St
+        L.ibmx_project.argtypes = [P, P, P, P, P, ctypes.c_double]
         L.ibmx_particle_substeps.restype = St
         L.ibmx_particle_substeps.argtypes = [P, ctypes.c_double, i32, P, P, P, P, P, P, P, P, i32,
                                              P, i32, P, P, P, P, P]
@@ -411,6 +414,20 @@ class Plan:
                                           _ptr(Fc), _ptr(Tc))
         _check(st, "ibmx_particle_substeps")
         return (Fc, Tc) if want_forces else None
+
+    def project(self, u, P, theta=0.0, want_phi=True):
+        """ibmx_project: projects u (the plan's precision, [3][nz][ny][nx]) in
+        place and updates P ([nz][ny][nx]) in place; returns (uf, phi)."""
+        import torch
+        shape = (self.n[2], self.n[1], self.n[0])
+        _want(u, self.dtype, (3,) + shape, "u")
+        _want(P, self.dtype, shape, "P")
+        uf = torch.empty_like(u)
+        phi = torch.empty_like(P) if want_phi else None
+        self._sync_stream()
+        st = lib().ibmx_project(self.handle, _ptr(u), _ptr(uf), _ptr(P), _ptr(phi), float(theta))
+        _check(st, "ibmx_project")
+        return uf, phi
 
     def particle_integrals(self, u, xp, radius, alpha=None):
         """ibmx_particle_integrals: returns (Iu, Ir), double[3][np]; fills the
