@@ -201,13 +201,24 @@ def run_gpu(case, precision, steps, warmup, profile=True, tune=True, tile=None):
     extras["substeps_n_sub"] = n_sub
     plan.check("substeps")
     plan.set_params(case.params)
-    # pressure projection of the fluid solver on the same grid (FP64 solve)
+    # the other steps of a fluid Runge-Kutta stage on the same grid: the
+    # predictor (stencils), the implicit viscous step and the projection
+    # (FP64 FFT / tridiagonal solves)
     if precision == "f32":
         uc = u.clone()
         P = torch.zeros(u.shape[1:], dtype=u.dtype, device=dev)
+        Nb = torch.zeros_like(u)
+        ut = torch.empty_like(u)
+        lapnu = torch.empty_like(u)
+        dt = 1.0
+        extras["predictor_ms"] = time_call(
+            lambda: plan.fluid_predictor(uc, Nb, P, dt, 8.0 / 15.0, 0.0, u_out=ut, lapnu=lapnu),
+            reps=3)
+        extras["helmholtz_ms"] = time_call(lambda: plan.fluid_helmholtz(ut, lapnu, P, dt, 0.0),
+                                           reps=3)
         extras["project_ms"] = time_call(lambda: plan.project(uc, P, 0.0, want_phi=False), reps=3)
-        plan.check("project")
-        del uc, P
+        plan.check("fluid stage")
+        del uc, P, Nb, ut, lapnu
     if not profile:
         st = plan.stats()
     out = dict(ms_per_step=ms, ms_per_step_graph=ms_graph, wall_s=wall, stats=st, n_iter=n_iter,
@@ -370,9 +381,13 @@ def main():
             note="level-set fluid integrals over all particles (one call, FP32 grid, "
                  "FP64 geometry and sums); not part of the step"),
         grid_mean_ms=r32["extras"]["grid_mean_ms"],
-        project=dict(ms=r32["extras"]["project_ms"],
-                     note="ibmx_project on the workload's grid (face interpolation, FP64 "
-                          "FFT/tridiagonal Poisson solve, corrections); not part of the step"),
+        fluid_stage=dict(predictor_ms=r32["extras"]["predictor_ms"],
+                         helmholtz_ms=r32["extras"]["helmholtz_ms"],
+                         project_ms=r32["extras"]["project_ms"],
+                         note="the collocated solver's other steps of one Runge-Kutta stage on "
+                              "the workload's grid (FP32 fields): ibmx_fluid_predictor, "
+                              "ibmx_fluid_helmholtz and ibmx_project (FP64 FFT/tridiagonal "
+                              "solves); not part of the step"),
         substeps=dict(ms=r32["extras"]["substeps_ms"], n_sub=r32["extras"]["substeps_n_sub"],
                       particles=case.np_, cpu_oracle_ms=cpu_sub_ms,
                       note="ibmx_particle_substeps of one time step (Hertz/ACTM contacts, "

@@ -34,7 +34,7 @@
  *     time the cell grid (set by radius_max and gap_cut) or the list
  *     capacities exceed those of earlier calls, ibmx_particle_substeps
  *     likewise for its contact and stage workspace, the first
- *     ibmx_project call, and ibmx_tune.
+ *     ibmx_project or ibmx_fluid_helmholtz call, and ibmx_tune.
  *     ibmx_forcing can be captured into a HIP graph (ibmx_forcing_graph
  *     does that), and so can ibmx_pairs and ibmx_particle_substeps once
  *     their workspace has been sized.  Errors that only the device can
@@ -459,6 +459,43 @@ IBMX_API ibmx_status ibmx_particle_substeps(ibmx_plan plan, double dt_total, int
  */
 IBMX_API ibmx_status ibmx_project(ibmx_plan plan, void *u, void *uf, void *P, void *phi,
                                   double theta);
+
+/*
+ * Predictor of one Runge-Kutta stage of the collocated fluid solver (eq.
+ * fluid-solver, step a), with alpha_k = params.two_alpha_dt / (2 dt):
+ *   u~ = u + dt (2 alpha_k nu L u - 2 alpha_k grad P - gamma_k N - zeta_k N_prev),
+ *   N  = (u . grad) u,
+ * L the 7-point Laplacian, N by central differences, grad P the mean of the
+ * cell's two face gradients; velocity vanishes on wall faces (ghost -u),
+ * pressure has zero normal gradient there.
+ * u       T[3][nz][ny][nx], the stage's input velocity (not modified).
+ * u_out   T[3][nz][ny][nx], out: u~ (must not alias u).
+ * N       T[3][nz][ny][nx], in: N of the previous stage (any finite values
+ *         when zeta_k = 0), out: N of u.
+ * lapnu   T[3][nz][ny][nx], out: nu L u (input of ibmx_fluid_helmholtz).
+ * P       T[nz][ny][nx], the pressure of the previous stage.
+ * Any grid.  Allocates nothing.
+ */
+IBMX_API ibmx_status ibmx_fluid_predictor(ibmx_plan plan, const void *u, void *u_out, void *N,
+                                          void *lapnu, const void *P, double dt, double gamma,
+                                          double zeta);
+
+/*
+ * Implicit viscous step of one stage (eq. fluid-solver, step e, Crank-
+ * Nicolson): with c = params.two_alpha_dt and alpha_k = c / (2 dt), solves
+ *   (I - alpha_k dt nu L) u* = u - c fbar + dt (-alpha_k lapnu + 2 alpha_k theta grad P)
+ * per component, where u is the velocity after the forcing loop (u~ + c
+ * f_IBM, as ibmx_forcing leaves it), lapnu = nu L of the stage's input
+ * velocity (from ibmx_fluid_predictor), fbar the mean IBM force (device
+ * double[3], e.g. from ibmx_grid_mean of f_tot, for triply periodic cases;
+ * NULL for 0) and theta 0 (pressure projection) or 1 (pressure correction).
+ * u is overwritten by u*.  The solve is FP64: FFTs along x and y (and z when
+ * periodic), across walls in z a tridiagonal elimination per Fourier mode
+ * with velocity 0 on the wall faces.  Same grid conditions and workspace as
+ * ibmx_project.
+ */
+IBMX_API ibmx_status ibmx_fluid_helmholtz(ibmx_plan plan, void *u, const void *lapnu, const void *P,
+                                          const double *fbar, double dt, double theta);
 
 /* Static description of a status code. */
 IBMX_API const char *ibmx_status_string(ibmx_status status);

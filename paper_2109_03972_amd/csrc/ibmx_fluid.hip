@@ -1,14 +1,16 @@
-// Pressure projection of the collocated fluid solver (Sec. 2.2.1 and eq.
-// fluid-solver, steps f-i): face interpolation, compact Poisson equation,
-// cell and face corrections, pressure update.
+// The collocated fluid solver's steps around the forcing loop (Sec. 2.2.1
+// and eq. fluid-solver): the predictor (step a), the implicit viscous step
+// (step e) and the pressure projection (steps f-i: face interpolation,
+// compact Poisson equation, cell and face corrections, pressure update).
 //
-// The Poisson equation L phi = div(u_f*) / c, with L the compact Laplacian
-// of the face gradients, is solved directly: complex FFTs along the periodic
-// x and y axes (and z when periodic, then a division by the eigenvalues), or
-// per (kx, ky) mode a tridiagonal elimination across the walls in z.  FFTs
-// are radix-2 passes in place in LDS, several short lines per workgroup,
-// loaded so that each wave reads contiguous memory; everything is FP64,
-// whatever the grid precision.
+// Both implicit systems, (I - beta L) u* = r per velocity component and the
+// compact Poisson equation L phi = div(u_f*) / c, are solved directly in
+// FP64: complex FFTs along the periodic x and y axes (and z when periodic,
+// then a division by the eigenvalues), or per (kx, ky) mode a tridiagonal
+// elimination across the walls in z.  FFTs are radix-2 passes in place in
+// LDS, several short lines per workgroup, loaded so that each wave reads
+// contiguous memory.  Stencil kernels take one thread per cell with x along
+// the block and y, z along the grid.
 #include <math.h>
 #include <vector>
 
@@ -19,6 +21,7 @@ namespace {
 constexpr int kFftThreads = 256;
 constexpr int kFftElems = 512;      // elements per workgroup, contiguous lines
 constexpr int kFftElemsStrided = 2048;   // strided lines: 32 KB of LDS, 4 lines of 512
+constexpr int kFftMaxLines = 1024;       // lines per workgroup (lines of 2 elements and up)
 
 struct FluidC {
     int n[3];
@@ -51,10 +54,11 @@ __global__ __launch_bounds__(256) void k_face_div(FluidC F, const T *__restrict_
                                                   T *__restrict__ uf, double2 *__restrict__ Z)
 {
     const long long N = (long long)F.n[0] * F.n[1] * F.n[2];
-    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < N;
-         c += (long long)gridDim.x * blockDim.x) {
-        const int i = (int)(c % F.n[0]), j = (int)((c / F.n[0]) % F.n[1]),
-                  k = (int)(c / ((long long)F.n[0] * F.n[1]));
+    {
+        const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+        if (i >= F.n[0])
+            return;
+        const long long c = cell_index(F, i, j, k);
         double div = 0.0;
         for (int a = 0; a < 3; ++a) {
             const T *ua = u + (size_t)a * N;
@@ -88,12 +92,15 @@ __global__ __launch_bounds__(kFftThreads) void k_fft(double2 *__restrict__ Z, in
                                                      long long S, const double2 *__restrict__ tw)
 {
     extern __shared__ double2 buf[];
+    __shared__ long long lbase[kFftMaxLines];
     const int total = lpw * n, half_n = n / 2;
     const long long line0 = (long long)blockIdx.x * lpw;
-    auto addr = [&](int l, int s) -> long long {
+    for (int l = threadIdx.x; l < lpw; l += blockDim.x) {
         const long long line = line0 + l;
-        return (line / A) * B + (line % A) * C + (long long)s * S;
-    };
+        lbase[l] = (line / A) * B + (line % A) * C;
+    }
+    __syncthreads();
+    auto addr = [&](int l, int s) -> long long { return lbase[l] + (long long)s * S; };
     for (int e = threadIdx.x; e < total; e += blockDim.x) {
         const int l = S == 1 ? e / n : e % lpw, s = S == 1 ? e % n : e / lpw;
         const int r = logn > 0 ? (int)(__brev((unsigned)s) >> (32 - logn)) : 0;
@@ -126,27 +133,31 @@ __device__ __forceinline__ double lam(int m, int n, double h)
     return (2.0 * cospi(2.0 * m / (double)n) - 2.0) / (h * h);
 }
 
-// triply periodic: divide every mode by its eigenvalue (the mean mode is 0)
-__global__ __launch_bounds__(256) void k_divide(FluidC F, double2 *__restrict__ Z)
+// triply periodic: mode by mode x = d / (s0 + s1 lambda); with s0 = 0 the
+// mean mode is 0
+__global__ __launch_bounds__(256) void k_divide(FluidC F, double s0, double s1,
+                                                double2 *__restrict__ Z)
 {
-    const long long N = (long long)F.n[0] * F.n[1] * F.n[2];
-    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < N;
-         c += (long long)gridDim.x * blockDim.x) {
-        const int i = (int)(c % F.n[0]), j = (int)((c / F.n[0]) % F.n[1]),
-                  k = (int)(c / ((long long)F.n[0] * F.n[1]));
-        const double L = lam(i, F.n[0], F.h) + lam(j, F.n[1], F.h) + lam(k, F.n[2], F.h);
+    {
+        const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+        if (i >= F.n[0])
+            return;
+        const long long c = cell_index(F, i, j, k);
+        const double L = s0 + s1 * (lam(i, F.n[0], F.h) + lam(j, F.n[1], F.h) + lam(k, F.n[2], F.h));
         const double2 z = Z[c];
-        Z[c] = c == 0 ? make_double2(0.0, 0.0) : make_double2(z.x / L, z.y / L);
+        Z[c] = (c == 0 && s0 == 0.0) ? make_double2(0.0, 0.0) : make_double2(z.x / L, z.y / L);
     }
 }
 
-// walls in z: per (kx, ky) mode the system (1/h^2)(phi_{k+1} - 2 phi_k +
-// phi_{k-1}) + lambda_xy phi_k = rhs_k with zero-gradient ends, by
-// elimination from the bottom; the (0, 0) mode is singular: its top value is
-// pinned to 0, then its z-mean removed (the grid mean of phi).  cp holds the
-// eliminated super-diagonal.
-__global__ __launch_bounds__(256) void k_tridiag(FluidC F, double2 *__restrict__ Z,
-                                                 double *__restrict__ cp)
+// walls in z: per (kx, ky) mode the system s0 x + s1 (D_z + lambda_xy) x =
+// rhs, D_z the second difference (1/h^2)(x_{k+1} - 2 x_k + x_{k-1}) closed
+// at the walls by a zero gradient (Neumann, the pressure) or by the ghost
+// -x (no slip, the velocity), solved by elimination from the bottom.  The
+// Neumann system with s0 = 0 is singular in the (0, 0) mode: its top value
+// is pinned to 0, then its z-mean removed (the grid mean of phi).  cp holds
+// the eliminated super-diagonal.
+__global__ __launch_bounds__(256) void k_tridiag(FluidC F, double s0, double s1, int dirichlet,
+                                                 double2 *__restrict__ Z, double *__restrict__ cp)
 {
     const int nxy = F.n[0] * F.n[1], nz = F.n[2];
     const int col = blockIdx.x * blockDim.x + threadIdx.x;
@@ -155,13 +166,16 @@ __global__ __launch_bounds__(256) void k_tridiag(FluidC F, double2 *__restrict__
     const int i = col % F.n[0], j = col / F.n[0];
     const double ih2 = 1.0 / (F.h * F.h);
     const double lxy = lam(i, F.n[0], F.h) + lam(j, F.n[1], F.h);
-    const bool singular = col == 0;
+    const bool singular = col == 0 && s0 == 0.0 && !dirichlet;
     double cprev = 0.0;
     double2 dprev = make_double2(0.0, 0.0);
     for (int k = 0; k < nz; ++k) {
         const size_t c = (size_t)k * nxy + col;
-        double a = k > 0 ? ih2 : 0.0, sup = k < nz - 1 ? ih2 : 0.0;
-        double b = lxy - (a + sup);
+        const bool lo = k > 0, hi = k < nz - 1;
+        const double dz = dirichlet ? -2.0 * ih2 - (lo ? 0.0 : ih2) - (hi ? 0.0 : ih2)
+                                    : -((lo ? ih2 : 0.0) + (hi ? ih2 : 0.0));
+        double a = lo ? s1 * ih2 : 0.0, sup = hi ? s1 * ih2 : 0.0;
+        double b = s0 + s1 * (lxy + dz);
         double2 d = Z[c];
         if (singular && k == nz - 1) {
             a = 0.0;
@@ -203,10 +217,11 @@ __global__ __launch_bounds__(256) void k_correct(FluidC F, const double2 *__rest
                                                  T *__restrict__ phi_out)
 {
     const long long N = (long long)F.n[0] * F.n[1] * F.n[2];
-    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < N;
-         c += (long long)gridDim.x * blockDim.x) {
-        const int i = (int)(c % F.n[0]), j = (int)((c / F.n[0]) % F.n[1]),
-                  k = (int)(c / ((long long)F.n[0] * F.n[1]));
+    {
+        const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+        if (i >= F.n[0])
+            return;
+        const long long c = cell_index(F, i, j, k);
         const double ph = Z[c].x * scale;
         double lap = 0.0;
         for (int a = 0; a < 3; ++a) {
@@ -224,7 +239,124 @@ __global__ __launch_bounds__(256) void k_correct(FluidC F, const double2 *__rest
     }
 }
 
+// value of field f at the neighbour (d = +1 / -1 along axis a) of cell c:
+// behind a wall the no-slip ghost -f(c)
+template <typename T>
+__device__ __forceinline__ double nb_noslip(const FluidC &F, const T *f, long long c, int i, int j,
+                                            int k, int a, int d)
+{
+    const long long q = neighbour(F, i, j, k, a, d);
+    return q >= 0 ? (double)f[q] : -(double)f[c];
+}
+
+// mean of the two face gradients of P along axis a (zero on wall faces)
+template <typename T>
+__device__ __forceinline__ double cell_grad(const FluidC &F, const T *P, long long c, int i, int j,
+                                            int k, int a)
+{
+    const double pc = (double)P[c];
+    const long long up = neighbour(F, i, j, k, a, 1), dn = neighbour(F, i, j, k, a, -1);
+    const double gp = up >= 0 ? ((double)P[up] - pc) / F.h : 0.0;
+    const double gm = dn >= 0 ? (pc - (double)P[dn]) / F.h : 0.0;
+    return 0.5 * (gp + gm);
+}
+
+// step a: u~ = u + dt (2 alpha nu L u - 2 alpha grad P - gamma N - zeta N_prev),
+// N = (u . grad) u; N holds N_prev on entry and N on exit, lapnu = nu L u
+template <typename T>
+__global__ __launch_bounds__(256) void k_predict(FluidC F, const T *__restrict__ u,
+                                                 T *__restrict__ ut, T *__restrict__ Nbuf,
+                                                 T *__restrict__ lapnu, const T *__restrict__ P,
+                                                 double dt, double alpha, double gamma,
+                                                 double zeta)
+{
+    const long long N = (long long)F.n[0] * F.n[1] * F.n[2];
+    {
+        const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+        if (i >= F.n[0])
+            return;
+        const long long c = cell_index(F, i, j, k);
+        double ua[3];
+        for (int a = 0; a < 3; ++a)
+            ua[a] = (double)u[(size_t)a * N + c];
+        for (int b = 0; b < 3; ++b) {
+            const T *ub = u + (size_t)b * N;
+            double lap = 0.0, adv = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                const double up = nb_noslip(F, ub, c, i, j, k, a, 1);
+                const double dn = nb_noslip(F, ub, c, i, j, k, a, -1);
+                lap = lap + (up - 2.0 * ua[b] + dn) / (F.h * F.h);
+                adv = adv + ua[a] * ((up - dn) / (2.0 * F.h));
+            }
+            const size_t ib = (size_t)b * N + c;
+            const double ln = F.nu * lap;
+            const double gP = cell_grad(F, P, c, i, j, k, b);
+            const double Np = (double)Nbuf[ib];
+            ut[ib] = (T)(ua[b] + dt * (2.0 * alpha * ln - 2.0 * alpha * gP - gamma * adv - zeta * Np));
+            Nbuf[ib] = (T)adv;
+            lapnu[ib] = (T)ln;
+        }
+    }
+}
+
+// step e: the right-hand side u_f - c fbar + dt (-alpha lapnu + 2 alpha
+// theta grad P) of component b0 into the real part of Z and of component b1
+// (if >= 0) into the imaginary part: the operator is real, so one complex
+// solve serves both
+template <typename T>
+__device__ __forceinline__ double helm_rhs(const FluidC &F, const T *u, const T *lapnu, const T *P,
+                                           const double *fbar, int b, long long c, int i, int j,
+                                           int k, double dt, double alpha)
+{
+    const long long N = (long long)F.n[0] * F.n[1] * F.n[2];
+    const double fb = fbar ? fbar[b] : 0.0;
+    const double gP = cell_grad(F, P, c, i, j, k, b);
+    return (double)u[(size_t)b * N + c] - F.c * fb +
+           dt * (-alpha * (double)lapnu[(size_t)b * N + c] + 2.0 * alpha * F.theta * gP);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_helm_rhs(FluidC F, const T *__restrict__ u,
+                                                  const T *__restrict__ lapnu,
+                                                  const T *__restrict__ P,
+                                                  const double *__restrict__ fbar, int b0, int b1,
+                                                  double dt, double alpha, double2 *__restrict__ Z)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+    if (i >= F.n[0])
+        return;
+    const long long c = cell_index(F, i, j, k);
+    const double r0 = helm_rhs(F, u, lapnu, P, fbar, b0, c, i, j, k, dt, alpha);
+    const double r1 = b1 >= 0 ? helm_rhs(F, u, lapnu, P, fbar, b1, c, i, j, k, dt, alpha) : 0.0;
+    Z[c] = make_double2(r0, r1);
+}
+
+// the solution: real part into component b0, imaginary part into b1
+template <typename T>
+__global__ __launch_bounds__(256) void k_take(long long N, const double2 *__restrict__ Z,
+                                              double scale, T *__restrict__ out0,
+                                              T *__restrict__ out1)
+{
+    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < N;
+         c += (long long)gridDim.x * blockDim.x) {
+        const double2 z = Z[c];
+        out0[c] = (T)(z.x * scale);
+        if (out1)
+            out1[c] = (T)(z.y * scale);
+    }
+}
+
 int grid_blocks(long long n) { return (int)(n / 256 + 1 < 16384 ? n / 256 + 1 : 16384); }
+
+// one thread per cell: x along the block, y and z along the grid
+struct CellLaunch {
+    dim3 grid, block;
+};
+CellLaunch cells(const FluidC &F)
+{
+    const int bx = F.n[0] >= 256 ? 256 : ((F.n[0] + 63) / 64) * 64;
+    return CellLaunch{dim3((F.n[0] + bx - 1) / bx, F.n[1], F.n[2]), dim3(bx)};
+}
 
 bool pow2(int n) { return n >= 2 && (n & (n - 1)) == 0; }
 
@@ -260,8 +392,7 @@ void fft_axis(ibmx_plan p, const FluidC &F, int a, hipStream_t s)
                        p->fl_z, n, log2i(n), lpw, A, B, C, S, (const double2 *)p->fl_tw[a]);
 }
 
-template <typename T>
-ibmx_status run_project(ibmx_plan p, T *u, T *uf, T *P, T *phi, double theta)
+FluidC fluid_constants(const ibmx_plan p, double theta)
 {
     const ibmx_grid &g = p->grid;
     FluidC F;
@@ -273,29 +404,84 @@ ibmx_status run_project(ibmx_plan p, T *u, T *uf, T *P, T *phi, double theta)
     F.c = p->prm.two_alpha_dt;
     F.nu = p->prm.nu_f;
     F.theta = theta;
-    const long long N = p->g.nodes;
-    hipStream_t s = p->stream;
-    ProfScope ps(p, IBMX_K_OTHER);
-    hipLaunchKernelGGL((k_face_div<T>), dim3(grid_blocks(N)), dim3(256), 0, s, F, (const T *)u, uf,
-                       p->fl_z);
+    return F;
+}
+
+// Z (a right-hand side in the cell layout) -> the solution of (s0 + s1 L) x
+// = Z, times the returned scale (the inverse FFTs are unnormalised)
+double solve_modes(ibmx_plan p, const FluidC &F, double s0, double s1, int dirichlet,
+                   hipStream_t s)
+{
     fft_axis<false>(p, F, 0, s);
     fft_axis<false>(p, F, 1, s);
     double scale = 1.0 / ((double)F.n[0] * F.n[1]);
     if (F.periodic[2]) {
         fft_axis<false>(p, F, 2, s);
-        hipLaunchKernelGGL(k_divide, dim3(grid_blocks(N)), dim3(256), 0, s, F, p->fl_z);
+        hipLaunchKernelGGL(k_divide, cells(F).grid, cells(F).block, 0, s, F, s0, s1, p->fl_z);
         fft_axis<true>(p, F, 2, s);
         scale /= F.n[2];
     } else {
         const int nxy = F.n[0] * F.n[1];
-        hipLaunchKernelGGL(k_tridiag, dim3((nxy + 255) / 256), dim3(256), 0, s, F, p->fl_z,
-                           p->fl_cp);
+        hipLaunchKernelGGL(k_tridiag, dim3((nxy + 255) / 256), dim3(256), 0, s, F, s0, s1,
+                           dirichlet, p->fl_z, p->fl_cp);
     }
     fft_axis<true>(p, F, 1, s);
     fft_axis<true>(p, F, 0, s);
-    hipLaunchKernelGGL((k_correct<T>), dim3(grid_blocks(N)), dim3(256), 0, s, F,
+    return scale;
+}
+
+template <typename T>
+ibmx_status run_project(ibmx_plan p, T *u, T *uf, T *P, T *phi, double theta)
+{
+    const FluidC F = fluid_constants(p, theta);
+    hipStream_t s = p->stream;
+    ProfScope ps(p, IBMX_K_OTHER);
+    hipLaunchKernelGGL((k_face_div<T>), cells(F).grid, cells(F).block, 0, s, F, (const T *)u, uf,
+                       p->fl_z);
+    const double scale = solve_modes(p, F, 0.0, 1.0, 0, s);
+    hipLaunchKernelGGL((k_correct<T>), cells(F).grid, cells(F).block, 0, s, F,
                        (const double2 *)p->fl_z, scale, u, uf, P, phi);
     return ibmx_launch_check();
+}
+
+template <typename T>
+ibmx_status run_predict(ibmx_plan p, const T *u, T *ut, T *Nbuf, T *lapnu, const T *P, double dt,
+                        double gamma, double zeta)
+{
+    const FluidC F = fluid_constants(p, 0.0);
+    const double alpha = F.c / (2.0 * dt);
+    ProfScope ps(p, IBMX_K_OTHER);
+    hipLaunchKernelGGL((k_predict<T>), cells(F).grid, cells(F).block, 0, p->stream, F,
+                       u, ut, Nbuf, lapnu, P, dt, alpha, gamma, zeta);
+    return ibmx_launch_check();
+}
+
+template <typename T>
+ibmx_status run_helmholtz(ibmx_plan p, T *u, const T *lapnu, const T *P, const double *fbar,
+                          double dt, double theta)
+{
+    const FluidC F = fluid_constants(p, theta);
+    const double alpha = F.c / (2.0 * dt);
+    const long long N = p->g.nodes;
+    hipStream_t s = p->stream;
+    ProfScope ps(p, IBMX_K_OTHER);
+    // x and y together, then z
+    for (int b0 = 0; b0 < 3; b0 += 2) {
+        const int b1 = b0 == 0 ? 1 : -1;
+        hipLaunchKernelGGL((k_helm_rhs<T>), cells(F).grid, cells(F).block, 0, s, F, (const T *)u,
+                           lapnu, P, fbar, b0, b1, dt, alpha, p->fl_z);
+        const double scale = solve_modes(p, F, 1.0, -alpha * dt * F.nu, 1, s);
+        hipLaunchKernelGGL((k_take<T>), dim3(grid_blocks(N)), dim3(256), 0, s, N,
+                           (const double2 *)p->fl_z, scale, u + (size_t)b0 * N,
+                           b1 >= 0 ? u + (size_t)b1 * N : (T *)nullptr);
+    }
+    return ibmx_launch_check();
+}
+
+bool solver_grid_ok(const ibmx_grid &g)
+{
+    return g.periodic[0] && g.periodic[1] && pow2(g.n[0]) && pow2(g.n[1]) && g.n[0] <= 1024 &&
+           g.n[1] <= 1024 && (!g.periodic[2] || (pow2(g.n[2]) && g.n[2] <= 1024));
 }
 
 // workspace: the complex grid, the elimination scratch (walls in z) and
@@ -331,9 +517,7 @@ extern "C" ibmx_status ibmx_project(ibmx_plan p, void *u, void *uf, void *P, voi
 {
     if (!p || !u || !uf || !P || !isfinite(theta))
         return IBMX_EINVAL;
-    const ibmx_grid &g = p->grid;
-    if (!g.periodic[0] || !g.periodic[1] || !pow2(g.n[0]) || !pow2(g.n[1]) || g.n[0] > 1024 ||
-        g.n[1] > 1024 || (g.periodic[2] && (!pow2(g.n[2]) || g.n[2] > 1024)))
+    if (!solver_grid_ok(p->grid))
         return IBMX_EUNSUPPORTED;
     const ibmx_status st = fluid_reserve(p);
     if (st != IBMX_OK)
@@ -341,4 +525,35 @@ extern "C" ibmx_status ibmx_project(ibmx_plan p, void *u, void *uf, void *P, voi
     if (p->prec == IBMX_F64)
         return run_project<double>(p, (double *)u, (double *)uf, (double *)P, (double *)phi, theta);
     return run_project<float>(p, (float *)u, (float *)uf, (float *)P, (float *)phi, theta);
+}
+
+extern "C" ibmx_status ibmx_fluid_predictor(ibmx_plan p, const void *u, void *u_out, void *N,
+                                            void *lapnu, const void *P, double dt, double gamma,
+                                            double zeta)
+{
+    if (!p || !u || !u_out || !N || !lapnu || !P || u == u_out || !(dt > 0.0) ||
+        !isfinite(gamma) || !isfinite(zeta))
+        return IBMX_EINVAL;
+    if (p->prec == IBMX_F64)
+        return run_predict<double>(p, (const double *)u, (double *)u_out, (double *)N,
+                                   (double *)lapnu, (const double *)P, dt, gamma, zeta);
+    return run_predict<float>(p, (const float *)u, (float *)u_out, (float *)N, (float *)lapnu,
+                              (const float *)P, dt, gamma, zeta);
+}
+
+extern "C" ibmx_status ibmx_fluid_helmholtz(ibmx_plan p, void *u, const void *lapnu, const void *P,
+                                            const double *fbar, double dt, double theta)
+{
+    if (!p || !u || !lapnu || !P || !(dt > 0.0) || !isfinite(theta))
+        return IBMX_EINVAL;
+    if (!solver_grid_ok(p->grid))
+        return IBMX_EUNSUPPORTED;
+    const ibmx_status st = fluid_reserve(p);
+    if (st != IBMX_OK)
+        return st;
+    if (p->prec == IBMX_F64)
+        return run_helmholtz<double>(p, (double *)u, (const double *)lapnu, (const double *)P, fbar,
+                                     dt, theta);
+    return run_helmholtz<float>(p, (float *)u, (const float *)lapnu, (const float *)P, fbar, dt,
+                                theta);
 }

@@ -26,8 +26,8 @@ API = (
     "ibmx_plan_profile",
     "ibmx_forcing", "ibmx_forcing_graph",
     "ibmx_forcing_backward", "ibmx_pairs", "ibmx_tune", "ibmx_particle_integrals",
-    "ibmx_grid_mean", "ibmx_particle_substeps", "ibmx_project", "ibmx_status_string",
-    "ibmx_version",
+    "ibmx_grid_mean", "ibmx_particle_substeps", "ibmx_project", "ibmx_fluid_predictor",
+    "ibmx_fluid_helmholtz", "ibmx_status_string", "ibmx_version",
 )
 
 HIST = 4   # rows of a contact history array (IBMX_HIST)
@@ -113,6 +113,11 @@ def lib():
         L.ibmx_particle_integrals.argtypes = [P] * 7
         L.ibmx_grid_mean.restype = St
         L.ibmx_grid_mean.argtypes = [P] * 3
+        L.ibmx_fluid_predictor.restype = St
+        L.ibmx_fluid_predictor.argtypes = [P, P, P, P, P, P, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_double]
+        L.ibmx_fluid_helmholtz.restype = St
+        L.ibmx_fluid_helmholtz.argtypes = [P, P, P, P, P, ctypes.c_double, ctypes.c_double]
         L.ibmx_project.restype = St
         L.ibmx_project.argtypes = [P, P, P, P, P, ctypes.c_double]
         L.ibmx_particle_substeps.restype = St
@@ -414,6 +419,34 @@ class Plan:
                                           _ptr(Fc), _ptr(Tc))
         _check(st, "ibmx_particle_substeps")
         return (Fc, Tc) if want_forces else None
+
+    def fluid_predictor(self, u, N, P, dt, gamma, zeta, u_out=None, lapnu=None):
+        """ibmx_fluid_predictor: returns (u~, lapnu); N is updated in place."""
+        import torch
+        shape = (self.n[2], self.n[1], self.n[0])
+        for t, nme in ((u, "u"), (N, "N"), (u_out, "u_out"), (lapnu, "lapnu")):
+            _want(t, self.dtype, (3,) + shape, nme)
+        _want(P, self.dtype, shape, "P")
+        u_out = torch.empty_like(u) if u_out is None else u_out
+        lapnu = torch.empty_like(u) if lapnu is None else lapnu
+        self._sync_stream()
+        st = lib().ibmx_fluid_predictor(self.handle, _ptr(u), _ptr(u_out), _ptr(N), _ptr(lapnu),
+                                        _ptr(P), float(dt), float(gamma), float(zeta))
+        _check(st, "ibmx_fluid_predictor")
+        return u_out, lapnu
+
+    def fluid_helmholtz(self, u, lapnu, P, dt, theta=0.0, fbar=None):
+        """ibmx_fluid_helmholtz: u (forced velocity) is overwritten by u*."""
+        import torch
+        shape = (self.n[2], self.n[1], self.n[0])
+        _want(u, self.dtype, (3,) + shape, "u")
+        _want(lapnu, self.dtype, (3,) + shape, "lapnu")
+        _want(P, self.dtype, shape, "P")
+        _want(fbar, torch.float64, (3,), "fbar")
+        self._sync_stream()
+        st = lib().ibmx_fluid_helmholtz(self.handle, _ptr(u), _ptr(lapnu), _ptr(P), _ptr(fbar),
+                                        float(dt), float(theta))
+        _check(st, "ibmx_fluid_helmholtz")
 
     def project(self, u, P, theta=0.0, want_phi=True):
         """ibmx_project: projects u (the plan's precision, [3][nz][ny][nx]) in

@@ -113,3 +113,106 @@ def test_bed_512_divergence_free():
     assert div.abs().max().item() <= 1e-5 * scale
     assert torch.all(uf[2][-1] == 0)
     plan.close()
+
+
+def _stage_inputs(shape, seed):
+    rng = np.random.default_rng(seed)
+    return (rng.normal(0.0, 1.0, (3,) + shape), rng.normal(0.0, 1.0, (3,) + shape),
+            rng.normal(0.0, 1.0, shape), rng.normal(0.0, 0.1, (3,) + shape))
+
+
+@pytest.mark.parametrize("n,periodic", [((16, 8, 8), (1, 1, 1)), ((32, 16, 13), (1, 1, 0)),
+                                        ((8, 32, 1), (1, 1, 0)), ((64, 32, 20), (1, 1, 0))])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_predictor_helmholtz_parity(n, periodic, precision):
+    """Steps a and e of one stage (alpha, gamma, zeta of the second RK stage)
+    against the oracle; the forcing between them is stood in for by an
+    arbitrary increment of u~."""
+    import torch
+    from oracle import fluid_stage as fs
+    dev = require_gpu()
+    T = torch.float64 if precision == "f64" else torch.float32
+    shape = (n[2], n[1], n[0])
+    u0, Np, P, df = _stage_inputs(shape, sum(n))
+    if precision == "f32":
+        u0, Np, P, df = (a.astype(np.float32).astype(np.float64) for a in (u0, Np, P, df))
+    alpha, gamma, zeta, dt = 1.0 / 15.0, 5.0 / 12.0, -17.0 / 60.0, 0.4
+    case = _case(n, periodic, seed=2)
+    prm = dict(case.params)
+    prm["c"] = 2.0 * alpha * dt
+    prm["nu_f"] = 0.3
+    case.params = prm
+    fbar = np.array([0.05, -0.02, 0.01]) if all(periodic) else None
+    theta = 1.0
+    ref_a = fs.predictor(u0, Np, P, case.h, prm["nu_f"], alpha, gamma, zeta, dt, periodic)
+    plan = ibmx.Plan.from_case(case, precision)
+    tu = lambda a: torch.as_tensor(a).to(dev).to(T).contiguous()
+    u_d, N_d, P_d = tu(u0), tu(Np), tu(P)
+    ut, lapnu = plan.fluid_predictor(u_d, N_d, P_d, dt, gamma, zeta)
+    plan.check("predictor")
+    tol = 1e-12 if precision == "f64" else 2e-6
+    for k, got in (("u", ut), ("N", N_d), ("lapnu", lapnu)):
+        e = rel_err(got.double().cpu().numpy(), ref_a[k])
+        assert e <= tol, f"predictor {k}: {e:.3e}"
+    # step e from the oracle's u~ plus a forcing increment
+    uf_in = ref_a["u"] + df
+    if precision == "f32":
+        uf_in = uf_in.astype(np.float32).astype(np.float64)
+    lap_in = ref_a["lapnu"].astype(np.float32).astype(np.float64) if precision == "f32" else ref_a["lapnu"]
+    ref_e = fs.helmholtz(uf_in, lap_in, P, fbar, case.h, prm["nu_f"], alpha, theta, dt, periodic)
+    us = tu(uf_in)
+    fb_d = None if fbar is None else torch.as_tensor(fbar, dtype=torch.float64).to(dev)
+    plan.fluid_helmholtz(us, tu(lap_in), P_d, dt, theta, fbar=fb_d)
+    plan.check("helmholtz")
+    torch.cuda.synchronize()
+    e = rel_err(us.double().cpu().numpy(), ref_e)
+    assert e <= (1e-12 if precision == "f64" else 1e-5), f"helmholtz: {e:.3e}"
+    plan.close()
+
+
+@pytest.mark.parametrize("theta", [0.0, 1.0])
+def test_full_stage_chain(theta):
+    """One Runge-Kutta stage of the collocated solver end to end (eq.
+    fluid-solver a-i): predictor, the forcing loop on the particles, the
+    implicit viscous step and the projection, each through the C ABI,
+    against the same chain of oracle steps."""
+    import torch
+    import oracle
+    from oracle import fluid_stage as fs
+    dev = require_gpu()
+    case = synth.small_case(41, n=(32, 32, 28), periodic=(1, 1, 0), n_iter=2, touch=0.3)
+    alpha, gamma, zeta, dt = 4.0 / 15.0, 8.0 / 15.0, 0.0, 0.5
+    prm = dict(case.params)
+    prm["c"] = 2.0 * alpha * dt
+    case.params = prm
+    shape = (case.n[2], case.n[1], case.n[0])
+    rng = np.random.default_rng(12)
+    u0 = case.u0
+    P0 = rng.normal(0.0, 0.01, shape)
+    Np = np.zeros((3,) + shape)
+    mask = oracle.marker_mask(case, oracle.pairs(case))
+    # oracle chain
+    a = fs.predictor(u0, Np, P0, case.h, prm["nu_f"], alpha, gamma, zeta, dt, (1, 1, 0))
+    fo = oracle.forcing(case, u0=a["u"], mask=mask)
+    us = fs.helmholtz(fo["u"], a["lapnu"], P0, None, case.h, prm["nu_f"], alpha, theta, dt,
+                      (1, 1, 0))
+    ref = pj.project(us, P0, case.h, prm["c"], prm["nu_f"], theta, (1, 1, 0))
+    # HIP chain
+    f64 = torch.float64
+    tu = lambda x: torch.as_tensor(x, dtype=f64).to(dev).contiguous()
+    plan = ibmx.Plan.from_case(case, "f64")
+    D = {k: tu(getattr(case, k)) for k in ("xp", "up", "wp", "body", "dV")}
+    plan.set_markers(D["body"], D["dV"])
+    u_d, N_d, P_d = tu(u0), tu(Np), tu(P0)
+    ut, lapnu = plan.fluid_predictor(u_d, N_d, P_d, dt, gamma, zeta)
+    f = torch.zeros_like(ut)
+    S, Tq = plan.forcing(ut, f, D["xp"], D["up"], D["wp"], mask=tu(mask).to(torch.uint8))
+    plan.fluid_helmholtz(ut, lapnu, P_d, dt, theta)
+    uf, phi = plan.project(ut, P_d, theta)
+    plan.check("stage")
+    torch.cuda.synchronize()
+    for k, got, want in (("f_tot", f, fo["f_tot"]), ("S", S, fo["S"]), ("u", ut, ref["u"]),
+                         ("uf", uf, ref["uf"]), ("P", P_d, ref["P"]), ("phi", phi, ref["phi"])):
+        e = rel_err(got.cpu().numpy(), want)
+        assert e <= 1e-11, f"{k}: {e:.3e}"
+    plan.close()
