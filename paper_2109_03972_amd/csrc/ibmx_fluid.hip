@@ -488,24 +488,34 @@ bool solver_grid_ok(const ibmx_grid &g)
 // one twiddle table per axis
 ibmx_status fluid_reserve(ibmx_plan p)
 {
-    if (p->fl_z)
-        return IBMX_OK;
     const size_t N = (size_t)p->g.nodes;
-    if (hipMalloc((void **)&p->fl_z, sizeof(double2) * N) != hipSuccess)
+    if (!p->fl_z && hipMalloc((void **)&p->fl_z, sizeof(double2) * N) != hipSuccess) {
+        p->fl_z = nullptr;
         return IBMX_ENOMEM;
-    if (!p->grid.periodic[2] && hipMalloc((void **)&p->fl_cp, sizeof(double) * N) != hipSuccess)
+    }
+    if (!p->grid.periodic[2] && !p->fl_cp &&
+        hipMalloc((void **)&p->fl_cp, sizeof(double) * N) != hipSuccess) {
+        p->fl_cp = nullptr;
         return IBMX_ENOMEM;
+    }
     for (int a = 0; a < 3; ++a) {
+        if (p->fl_tw[a])
+            continue;
         const int n = p->grid.n[a];
         std::vector<double2> tw((size_t)(n / 2 > 0 ? n / 2 : 1));
         for (int m = 0; m < n / 2; ++m) {
             const double ang = -2.0 * M_PI * (double)m / (double)n;
             tw[m] = make_double2(cos(ang), sin(ang));
         }
-        if (hipMalloc((void **)&p->fl_tw[a], sizeof(double2) * tw.size()) != hipSuccess ||
-            hipMemcpy(p->fl_tw[a], tw.data(), sizeof(double2) * tw.size(),
-                      hipMemcpyHostToDevice) != hipSuccess)
+        double2 *d = nullptr;
+        if (hipMalloc((void **)&d, sizeof(double2) * tw.size()) != hipSuccess)
             return IBMX_ENOMEM;
+        if (hipMemcpy(d, tw.data(), sizeof(double2) * tw.size(), hipMemcpyHostToDevice) !=
+            hipSuccess) {
+            (void)hipFree(d);
+            return IBMX_EDEVICE;
+        }
+        p->fl_tw[a] = d;
     }
     return IBMX_OK;
 }
