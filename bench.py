@@ -67,6 +67,34 @@ KERNEL_SOURCES = ("paper_2109_03972_amd/csrc/ibmx_forcing.hip",
                   "paper_2109_03972_amd/csrc/ibmx_delta.hpp", "paper_2109_03972_amd/build_lib.py")
 
 
+def fluid_bytes(kind: str, s: int, nodes: int, walls_z: bool = True) -> float:
+    """Bytes one fluid call must move (s = bytes of the field type; the
+    solves work on an FP64 complex grid, 16 B per node).
+
+    predictor: reads u, N (3s each) and P (s); writes u~, N and nu L u (3s each).
+    solve (one complex right-hand side): FFT passes along x and y, forward and
+           inverse (4 x 32 B), and across walls the elimination (read and
+           write the grid twice, the eliminated coefficient once each way:
+           80 B), or along a periodic z two more FFT passes and the division.
+    project: face values and divergence (reads 3s, writes 3s + 16 B), the
+           solve, then the correction (reads the grid, u, u_f, P; writes u,
+           u_f, P, phi: 16 B + 15s).
+    helmholtz: x and y in one complex solve, z in a second: right-hand sides
+           (2 components: 4s + s + 16 B, one: 2s + s + 16 B), two solves, and
+           the unpacking (16 B + 2s, 16 B + s).
+    """
+    solve = 4 * 32 + (80 if walls_z else 96)
+    if kind == "predictor":
+        per = 16 * s
+    elif kind == "project":
+        per = (6 * s + 16) + solve + (16 + 15 * s)
+    elif kind == "helmholtz":
+        per = (5 * s + 16) + (3 * s + 16) + 2 * solve + (16 + 2 * s) + (16 + s)
+    else:
+        raise KeyError(kind)
+    return float(per) * nodes
+
+
 def measured_traffic(workload: str, kind: str, tile) -> "float | None":
     """HBM bytes per launch of a kernel class from the committed counter
     summary (FETCH_SIZE and WRITE_SIZE passes, copy-calibrated), or None when
@@ -327,6 +355,7 @@ def main():
     st = r32["stats"]
     n_act, shell, n_iter = int(st["n_active"]), int(st["shell_nodes"]), r32["n_iter"]
     value = n_act * n_iter / (r32["ms_per_step"] * 1e-3)
+    nodes = int(case.n[0]) * int(case.n[1]) * int(case.n[2])
     value_graph = n_act * n_iter / (r32["ms_per_step_graph"] * 1e-3)
     km, kn = st["kernel_ms"], st["kernel_launches"]
     steps_done = args.steps
@@ -384,6 +413,14 @@ def main():
         fluid_stage=dict(predictor_ms=r32["extras"]["predictor_ms"],
                          helmholtz_ms=r32["extras"]["helmholtz_ms"],
                          project_ms=r32["extras"]["project_ms"],
+                         roofline={k: dict(
+                             bytes=fluid_bytes(k, 4, nodes, not case.periodic[2]),
+                             achieved_GBs=round(fluid_bytes(k, 4, nodes, not case.periodic[2])
+                                                / (r32["extras"][k + "_ms"] * 1e-3) / 1e9, 1),
+                             frac=round(fluid_bytes(k, 4, nodes, not case.periodic[2])
+                                        / (r32["extras"][k + "_ms"] * 1e-3) / 1e9
+                                        / HBM_PEAK_GBS, 4))
+                             for k in ("predictor", "helmholtz", "project")},
                          note="the collocated solver's other steps of one Runge-Kutta stage on "
                               "the workload's grid (FP32 fields): ibmx_fluid_predictor, "
                               "ibmx_fluid_helmholtz and ibmx_project (FP64 FFT/tridiagonal "

@@ -79,7 +79,8 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b)
 }
 
 // Batched complex FFT of lines of length n = 2^logn: iterative radix-2
-// Cooley-Tukey in place in LDS (elements loaded in bit-reversed order).
+// Cooley-Tukey in place in LDS (elements loaded in bit-reversed order), two
+// stages per pass.
 // Line l of the batch starts at (l / A) * B + (l % A) * C and has element
 // stride S; a workgroup takes `lpw` consecutive lines.  Contiguous lines
 // (S = 1) are loaded line by line, strided ones element-major across the
@@ -107,7 +108,40 @@ __global__ __launch_bounds__(kFftThreads) void k_fft(double2 *__restrict__ Z, in
         buf[l * n + r] = Z[addr(l, s)];
     }
     __syncthreads();
-    for (int len = 2; len <= n; len <<= 1) {
+    // stages in pairs (len, 2 len): the four elements i, i + half, i + len,
+    // i + len + half close under both stages, so a thread takes them through
+    // both with one LDS read and write each; a last single stage when logn is
+    // odd
+    int len = 2;
+    for (; 2 * len <= n; len <<= 2) {
+        const int half = len >> 1, quarter_n = n / 4;
+        for (int b = threadIdx.x; b < lpw * quarter_n; b += blockDim.x) {
+            const int l = b / quarter_n, q = b % quarter_n, pos = q % half;
+            const int i0 = l * n + (q / half) * (2 * len) + pos;
+            double2 w1 = tw[pos * (n / len)], w2 = tw[pos * (n / (2 * len))],
+                    w3 = tw[(pos + half) * (n / (2 * len))];
+            if (INV) {
+                w1.y = -w1.y;
+                w2.y = -w2.y;
+                w3.y = -w3.y;
+            }
+            const double2 a0 = buf[i0], a1 = cmul(buf[i0 + half], w1);
+            const double2 a2 = buf[i0 + len], a3 = cmul(buf[i0 + len + half], w1);
+            // stage len
+            const double2 b0 = make_double2(a0.x + a1.x, a0.y + a1.y);
+            const double2 b1 = make_double2(a0.x - a1.x, a0.y - a1.y);
+            const double2 b2 = make_double2(a2.x + a3.x, a2.y + a3.y);
+            const double2 b3 = make_double2(a2.x - a3.x, a2.y - a3.y);
+            // stage 2 len: (i0, i0 + len) with w2, (i0 + half, i0 + len + half) with w3
+            const double2 c2 = cmul(b2, w2), c3 = cmul(b3, w3);
+            buf[i0] = make_double2(b0.x + c2.x, b0.y + c2.y);
+            buf[i0 + len] = make_double2(b0.x - c2.x, b0.y - c2.y);
+            buf[i0 + half] = make_double2(b1.x + c3.x, b1.y + c3.y);
+            buf[i0 + len + half] = make_double2(b1.x - c3.x, b1.y - c3.y);
+        }
+        __syncthreads();
+    }
+    if (len <= n) {
         const int half = len >> 1, step = n / len;
         for (int b = threadIdx.x; b < lpw * half_n; b += blockDim.x) {
             const int l = b / half_n, jj = b % half_n, pos = jj % half;

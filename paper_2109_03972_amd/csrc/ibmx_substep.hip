@@ -11,7 +11,6 @@
 // Contacts read the partners' state from a buffer no launch in flight
 // writes; the stage forces of s^{k-1} and s^{k-2} are kept per particle in
 // two alternating buffers.
-#include <float.h>
 
 #include "ibmx_contact.hpp"
 
