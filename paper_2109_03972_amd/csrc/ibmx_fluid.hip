@@ -296,39 +296,127 @@ __device__ __forceinline__ double cell_grad(const FluidC &F, const T *P, long lo
 }
 
 // step a: u~ = u + dt (2 alpha nu L u - 2 alpha grad P - gamma N - zeta N_prev),
-// N = (u . grad) u; N holds N_prev on entry and N on exit, lapnu = nu L u
+// N = (u . grad) u; N holds N_prev on entry and N on exit, lapnu = nu L u.
+// A workgroup takes a PX x PY column of cells and marches it up in z: each
+// plane of u and P is staged in LDS with a one-cell rim for the x and y
+// neighbours, the planes below and above are kept in registers, so each
+// value is read from memory about once.
+constexpr int PX = 64, PY = 4;
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_predict(FluidC F, const T *__restrict__ u,
-                                                 T *__restrict__ ut, T *__restrict__ Nbuf,
-                                                 T *__restrict__ lapnu, const T *__restrict__ P,
-                                                 double dt, double alpha, double gamma,
-                                                 double zeta)
+__global__ __launch_bounds__(PX * PY) void k_predict(FluidC F, const T *__restrict__ u,
+                                                     T *__restrict__ ut, T *__restrict__ Nbuf,
+                                                     T *__restrict__ lapnu,
+                                                     const T *__restrict__ P, double dt,
+                                                     double alpha, double gamma, double zeta)
 {
+    __shared__ double tile[4][PY + 2][PX + 2];
     const long long N = (long long)F.n[0] * F.n[1] * F.n[2];
-    {
-        const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
-        if (i >= F.n[0])
-            return;
-        const long long c = cell_index(F, i, j, k);
+    const int nx = F.n[0], ny = F.n[1], nz = F.n[2];
+    const int tx = threadIdx.x % PX, ty = threadIdx.x / PX;
+    const int i0 = blockIdx.x * PX, j0 = blockIdx.y * PY;
+    const int i = i0 + tx, j = j0 + ty;
+    const bool live = i < nx && j < ny;
+    const T *fld[4] = {u, u + N, u + 2 * N, P};
+    // value of field q at (i, j, kk) (kk already inside the grid)
+    auto at = [&](int q, int ii, int jj, int kk) -> double {
+        return (double)fld[q][((long long)kk * ny + jj) * nx + ii];
+    };
+    double zc[4] = {0, 0, 0, 0}, zn[4] = {0, 0, 0, 0}, zp[4] = {0, 0, 0, 0}, z0[4] = {0, 0, 0, 0};
+    if (live)
+        for (int q = 0; q < 4; ++q) {
+            zc[q] = at(q, i, j, 0);
+            z0[q] = zc[q];
+            if (F.periodic[2])
+                zp[q] = at(q, i, j, nz - 1);
+        }
+    // the rim-extended plane is loaded into registers one plane ahead
+    // (each thread holds up to kPre of its slots), stored to LDS after the
+    // previous plane's compute: the loads of plane k + 1 overlap the compute
+    // of plane k
+    constexpr int kSlots = (PY + 2) * (PX + 2), kPre = (kSlots + PX * PY - 1) / (PX * PY);
+    double pre[kPre][4];
+    auto load_plane = [&](int kk) {
+        for (int r = 0; r < kPre; ++r) {
+            const int e = threadIdx.x + r * PX * PY;
+            if (e >= kSlots)
+                break;
+            const int ry = e / (PX + 2), rx = e % (PX + 2);
+            int gi = i0 + rx - 1, gj = j0 + ry - 1;
+            if (F.periodic[0])
+                gi = gi < 0 ? gi + nx : (gi >= nx ? gi - nx : gi);
+            if (F.periodic[1])
+                gj = gj < 0 ? gj + ny : (gj >= ny ? gj - ny : gj);
+            const bool in = gi >= 0 && gi < nx && gj >= 0 && gj < ny;
+            for (int q = 0; q < 4; ++q)
+                pre[r][q] = in ? at(q, gi, gj, kk) : 0.0;
+        }
+    };
+    load_plane(0);
+    for (int k = 0; k < nz; ++k) {
+        __syncthreads();
+        for (int r = 0; r < kPre; ++r) {
+            const int e = threadIdx.x + r * PX * PY;
+            if (e >= kSlots)
+                break;
+            const int ry = e / (PX + 2), rx = e % (PX + 2);
+            for (int q = 0; q < 4; ++q)
+                tile[q][ry][rx] = pre[r][q];
+        }
+        __syncthreads();
+        const bool has_up = k + 1 < nz, has_dn = k > 0;
+        // the plane above at this cell first (needed now), then the prefetch
+        if (live)
+            for (int q = 0; q < 4; ++q)
+                zn[q] = has_up ? at(q, i, j, k + 1) : (F.periodic[2] ? z0[q] : 0.0);
+        if (has_up)
+            load_plane(k + 1);
+        if (!live)
+            continue;
+        const bool in_xm = F.periodic[0] || i > 0, in_xp = F.periodic[0] || i + 1 < nx;
+        const bool in_ym = F.periodic[1] || j > 0, in_yp = F.periodic[1] || j + 1 < ny;
+        const bool in_zm = F.periodic[2] || has_dn, in_zp = F.periodic[2] || has_up;
+        const long long c = ((long long)k * ny + j) * nx + i;
         double ua[3];
-        for (int a = 0; a < 3; ++a)
-            ua[a] = (double)u[(size_t)a * N + c];
+        for (int q = 0; q < 3; ++q)
+            ua[q] = zc[q];
         for (int b = 0; b < 3; ++b) {
-            const T *ub = u + (size_t)b * N;
+            // neighbours of component b along x, y, z (no-slip ghost -u behind a wall)
+            const double ub = ua[b];
+            const double nbr[3][2] = {
+                {in_xp ? tile[b][ty + 1][tx + 2] : -ub, in_xm ? tile[b][ty + 1][tx] : -ub},
+                {in_yp ? tile[b][ty + 2][tx + 1] : -ub, in_ym ? tile[b][ty][tx + 1] : -ub},
+                {in_zp ? zn[b] : -ub, in_zm ? zp[b] : -ub}};
             double lap = 0.0, adv = 0.0;
             for (int a = 0; a < 3; ++a) {
-                const double up = nb_noslip(F, ub, c, i, j, k, a, 1);
-                const double dn = nb_noslip(F, ub, c, i, j, k, a, -1);
-                lap = lap + (up - 2.0 * ua[b] + dn) / (F.h * F.h);
+                const double up = nbr[a][0], dn = nbr[a][1];
+                lap = lap + (up - 2.0 * ub + dn) / (F.h * F.h);
                 adv = adv + ua[a] * ((up - dn) / (2.0 * F.h));
             }
+            // pressure gradient along b: mean of the two face gradients
+            const double pc = zc[3];
+            double pp, pm;
+            bool hp, hm;
+            if (b == 0) {
+                pp = tile[3][ty + 1][tx + 2], pm = tile[3][ty + 1][tx], hp = in_xp, hm = in_xm;
+            } else if (b == 1) {
+                pp = tile[3][ty + 2][tx + 1], pm = tile[3][ty][tx + 1], hp = in_yp, hm = in_ym;
+            } else {
+                pp = zn[3], pm = zp[3], hp = in_zp, hm = in_zm;
+            }
+            const double gp = hp ? (pp - pc) / F.h : 0.0;
+            const double gm = hm ? (pc - pm) / F.h : 0.0;
+            const double gP = 0.5 * (gp + gm);
             const size_t ib = (size_t)b * N + c;
             const double ln = F.nu * lap;
-            const double gP = cell_grad(F, P, c, i, j, k, b);
             const double Np = (double)Nbuf[ib];
-            ut[ib] = (T)(ua[b] + dt * (2.0 * alpha * ln - 2.0 * alpha * gP - gamma * adv - zeta * Np));
+            ut[ib] = (T)(ub + dt * (2.0 * alpha * ln - 2.0 * alpha * gP - gamma * adv - zeta * Np));
             Nbuf[ib] = (T)adv;
             lapnu[ib] = (T)ln;
+        }
+        for (int q = 0; q < 4; ++q) {
+            zp[q] = zc[q];
+            zc[q] = zn[q];
         }
     }
 }
@@ -485,7 +573,8 @@ ibmx_status run_predict(ibmx_plan p, const T *u, T *ut, T *Nbuf, T *lapnu, const
     const FluidC F = fluid_constants(p, 0.0);
     const double alpha = F.c / (2.0 * dt);
     ProfScope ps(p, IBMX_K_OTHER);
-    hipLaunchKernelGGL((k_predict<T>), cells(F).grid, cells(F).block, 0, p->stream, F,
+    hipLaunchKernelGGL((k_predict<T>), dim3((F.n[0] + PX - 1) / PX, (F.n[1] + PY - 1) / PY),
+                       dim3(PX * PY), 0, p->stream, F,
                        u, ut, Nbuf, lapnu, P, dt, alpha, gamma, zeta);
     return ibmx_launch_check();
 }
