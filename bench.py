@@ -62,9 +62,22 @@ def algorithmic_bytes(kind: str, s: int, n_act: int, shell: int, n_iter: int = 2
 COUNTER_FILES = {
     "polydisperse_bed_512": "profiles/k_interp_k_spread_polydisperse_bed_512_f32_hbm_counters.md",
 }
+# what the forcing kernels' machine code is built from: their sources and
+# the compiler flags
 KERNEL_SOURCES = ("paper_2109_03972_amd/csrc/ibmx_forcing.hip",
-                  "paper_2109_03972_amd/csrc/ibmx_internal.hpp",
-                  "paper_2109_03972_amd/csrc/ibmx_delta.hpp", "paper_2109_03972_amd/build_lib.py")
+                  "paper_2109_03972_amd/csrc/ibmx_device.hpp",
+                  "paper_2109_03972_amd/csrc/ibmx_delta.hpp")
+
+
+def kernel_sources_hash() -> str:
+    import hashlib
+    from paper_2109_03972_amd import build_lib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    h.update(" ".join(build_lib.HIPCC_FLAGS).encode())
+    return h.hexdigest()
 
 
 def fluid_bytes(kind: str, s: int, nodes: int, walls_z: bool = True) -> float:
@@ -100,14 +113,9 @@ def measured_traffic(workload: str, kind: str, tile) -> "float | None":
     summary (FETCH_SIZE and WRITE_SIZE passes, copy-calibrated), or None when
     there is none for this workload and tile, or the kernel sources changed
     since the counters were taken."""
-    import hashlib
     rel = COUNTER_FILES.get(workload)
     if rel is None or not os.path.exists(os.path.join(ROOT, rel)):
         return None
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
     fields = {}
     with open(os.path.join(ROOT, rel)) as fh:
         for line in fh:
@@ -115,7 +123,7 @@ def measured_traffic(workload: str, kind: str, tile) -> "float | None":
                     "traffic_per_launch_bytes", "tile", "kernel_sources_sha256"):
                 k, v = line.split(":", 1)
                 fields[k] = v.strip()
-    if fields.get("kernel_sources_sha256") != h.hexdigest():
+    if fields.get("kernel_sources_sha256") != kernel_sources_hash():
         return None
     if fields.get("tile") != ",".join(str(int(t)) for t in tile):
         return None
