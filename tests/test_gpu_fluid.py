@@ -216,3 +216,77 @@ def test_full_stage_chain(theta):
         e = rel_err(got.cpu().numpy(), want)
         assert e <= 1e-11, f"{k}: {e:.3e}"
     plan.close()
+
+
+def test_bed_512_predictor_planes_and_helmholtz_residual():
+    """The bed's 512^3 grid, FP32 fields.  The predictor is local, so whole
+    planes (the wall planes, their neighbours, one in the middle) are
+    checked against the oracle run on the three-plane slab around each.  The
+    implicit step is global: its equation's residual, evaluated in FP64 from
+    the FP32 result, must be at FP32 rounding."""
+    import torch
+    from oracle import fluid_stage as fs
+    dev = require_gpu()
+    case = synth.make_case("polydisperse_bed_512", lazy_field=True)
+    nx, ny, nz = case.n
+    alpha, gamma, zeta, dt = 1.0 / 15.0, 5.0 / 12.0, -17.0 / 60.0, 1.0
+    prm = dict(case.params)
+    prm["c"] = 2.0 * alpha * dt
+    prm["nu_f"] = 0.3
+    case.params = prm
+    plan = ibmx.Plan.from_case(case, "f32")
+    u = case.field(device=dev).to(torch.float32).contiguous()
+    g = torch.Generator(device=dev).manual_seed(3)
+    Nb = (0.1 * torch.randn(u.shape, device=dev, generator=g)).contiguous()
+    P = (0.01 * torch.randn(u.shape[1:], device=dev, generator=g)).contiguous()
+    N0 = Nb.clone()
+    ut, lapnu = plan.fluid_predictor(u, Nb, P, dt, gamma, zeta)
+    plan.check("predictor bed")
+    torch.cuda.synchronize()
+    for k in (0, 1, nz // 2, nz - 2, nz - 1):
+        lo, hi = max(k - 1, 0), min(k + 2, nz)
+        sl = slice(lo, hi)
+        slab = (1, 1, 0)
+        uk = u[:, sl].double().cpu().numpy()
+        ref = fs.predictor(uk, N0[:, sl].double().cpu().numpy(), P[sl].double().cpu().numpy(),
+                           case.h, prm["nu_f"], alpha, gamma, zeta, dt, slab)
+        m = k - lo
+        # a slab edge that is not a real wall: only the middle plane counts
+        for name, got in (("u", ut), ("N", Nb), ("lapnu", lapnu)):
+            e = rel_err(got[:, k].double().cpu().numpy(), ref[name][:, m])
+            assert e <= 2e-6, f"plane {k} {name}: {e:.3e}"
+    # implicit step on the predictor's result; residual of
+    # u* - beta L u* = rhs with rhs from the same inputs
+    rhs_u = ut.clone()
+    plan.fluid_helmholtz(ut, lapnu, P, dt, 1.0)
+    plan.check("helmholtz bed")
+    torch.cuda.synchronize()
+    beta = alpha * dt * prm["nu_f"]
+    us = ut.double()
+    Pd = P.double()
+    h = case.h
+    worst = 0.0
+    for b in range(3):
+        ub = us[b]
+        lap = torch.zeros_like(ub)
+        for ax, periodic in ((2, True), (1, True), (0, False)):
+            upn = torch.roll(ub, -1, dims=ax)
+            dnn = torch.roll(ub, 1, dims=ax)
+            if not periodic:
+                upn[-1] = -ub[-1]
+                dnn[0] = -ub[0]
+            lap += (upn - 2.0 * ub + dnn) / (h * h)
+        # grad P along b: mean of the face gradients, zero on wall faces
+        axb = (2, 1, 0)[b]
+        gp = (torch.roll(Pd, -1, dims=axb) - Pd) / h
+        gm = (Pd - torch.roll(Pd, 1, dims=axb)) / h
+        if b == 2:
+            gp[-1] = 0.0
+            gm[0] = 0.0
+        gP = 0.5 * (gp + gm)
+        rhs = rhs_u[b].double() + dt * (-alpha * lapnu[b].double() + 2.0 * alpha * gP)
+        res = (ub - beta * lap - rhs).abs().max().item()
+        worst = max(worst, res / rhs.abs().max().item())
+    print(f"bed: Helmholtz relative residual {worst:.3e}", flush=True)
+    assert worst <= 1e-5
+    plan.close()
