@@ -421,7 +421,10 @@ IBMX_API ibmx_status ibmx_grid_mean(ibmx_plan plan, const void *f, double *mean)
  *               only contacts with St = u_in rho d / (9 rho_f nu_f) <=
  *               St_crit gets F_h = T_h = 0.
  *   counts      device int32[2]: listed pairs, walls (an ibmx_pairs
- *               counts_out; clamped to the capacities).
+ *               counts_out; clamped to the capacities).  List entries that
+ *               are not pairs i < j of particles 0 .. np-1, or wall entries
+ *               of such a particle on a wall axis, are skipped and reported
+ *               as a deferred EINVAL.
  *   Fc, Tc      double[3][np] or NULL: collision force and torque at the
  *               final state, overwritten.
  * Each particle's contacts are summed in increasing partner id, then its

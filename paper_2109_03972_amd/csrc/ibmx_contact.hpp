@@ -264,31 +264,62 @@ struct ContactLists {
 __device__ __forceinline__ int n_pairs(const ContactLists &C) { return min(C.counts[0], C.pair_cap); }
 __device__ __forceinline__ int n_walls(const ContactLists &C) { return min(C.counts[1], C.wall_cap); }
 
-__global__ void k_adj_count(ContactLists C, int *deg)
+// list entries the adjacency can hold: pairs i < j of particles in range,
+// wall entries of a particle in range on a wall axis; others are skipped
+// (and reported as EINVAL)
+__device__ __forceinline__ bool pair_ok(const ContactLists &C, int np, int k)
+{
+    const int i = C.pairs[k], j = C.pairs[C.pair_cap + k];
+    return i >= 0 && j < np && i < j;
+}
+__device__ __forceinline__ bool wall_ok(const ContactLists &C, int np, const int *periodic, int k)
+{
+    const int p = C.walls[k], side = C.walls[C.wall_cap + k];
+    return p >= 0 && p < np && side >= 0 && side < 6 && !periodic[side / 2];
+}
+
+struct Periodic {
+    int p[3];
+};
+
+__global__ void k_adj_count(ContactLists C, int np, Periodic per, int *deg, int *err)
 {
     const int npairs = n_pairs(C), nwall = n_walls(C);
     for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < npairs + nwall;
          k += gridDim.x * blockDim.x) {
         if (k < npairs) {
+            if (!pair_ok(C, np, k)) {
+                atomicCAS(err, 0, (int)IBMX_EINVAL);
+                continue;
+            }
             atomicAdd(&deg[C.pairs[k]], 1);
             atomicAdd(&deg[C.pairs[C.pair_cap + k]], 1);
         } else {
+            if (!wall_ok(C, np, per.p, k - npairs)) {
+                atomicCAS(err, 0, (int)IBMX_EINVAL);
+                continue;
+            }
             atomicAdd(&deg[C.walls[k - npairs]], 1);
         }
     }
 }
 
-__global__ void k_adj_fill(ContactLists C, const int *off, int *cursor, int2 *adj)
+__global__ void k_adj_fill(ContactLists C, int np, Periodic per, const int *off, int *cursor,
+                           int2 *adj)
 {
     const int npairs = n_pairs(C), nwall = n_walls(C);
     for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < npairs + nwall;
          k += gridDim.x * blockDim.x) {
         if (k < npairs) {
+            if (!pair_ok(C, np, k))
+                continue;
             const int i = C.pairs[k], j = C.pairs[C.pair_cap + k];
             adj[off[i] + atomicAdd(&cursor[i], 1)] = make_int2(2 * k, j);
             adj[off[j] + atomicAdd(&cursor[j], 1)] = make_int2(2 * k + 1, i);
         } else {
             const int kw = k - npairs;
+            if (!wall_ok(C, np, per.p, kw))
+                continue;
             const int p = C.walls[kw];
             adj[off[p] + atomicAdd(&cursor[p], 1)] = make_int2(-(kw + 1), C.walls[C.wall_cap + kw]);
         }
@@ -576,10 +607,11 @@ inline void contact_adjacency(ibmx_plan p, const ContactLists &C, hipStream_t s)
     const int g = contact_blocks(nmax, 256) < 4096 ? contact_blocks(nmax, 256) : 4096;
     ibmx_fill_i32(p->c_deg, 0, np + 1, s);
     ibmx_fill_i32(p->c_cur, 0, np, s);
-    hipLaunchKernelGGL(k_adj_count, dim3(g), dim3(256), 0, s, C, p->c_deg);
+    const Periodic per{{p->grid.periodic[0], p->grid.periodic[1], p->grid.periodic[2]}};
+    hipLaunchKernelGGL(k_adj_count, dim3(g), dim3(256), 0, s, C, np, per, p->c_deg, p->d_err);
     ibmx_exclusive_scan(p->c_deg, p->c_off, np, p->scan_aux, s);
-    hipLaunchKernelGGL(k_adj_fill, dim3(g), dim3(256), 0, s, C, (const int *)p->c_off, p->c_cur,
-                       p->c_adj);
+    hipLaunchKernelGGL(k_adj_fill, dim3(g), dim3(256), 0, s, C, np, per, (const int *)p->c_off,
+                       p->c_cur, p->c_adj);
     hipLaunchKernelGGL(k_adj_sort, dim3(contact_blocks(np, 64)), dim3(64), 0, s, np,
                        (const int *)p->c_off, p->c_adj);
 }

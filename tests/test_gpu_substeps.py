@@ -238,3 +238,25 @@ def test_polydisperse_bed_512_parity():
     print(f"bed: np {c.np_} pairs {ref_l['pairs'].shape[1]} walls {ref_l['walls'].shape[1]} "
           f"contacts {int((ref_l['gap'] < 0).sum())}", flush=True)
     _compare(got, ref)
+
+
+def test_bad_list_entries_are_skipped_and_reported():
+    """Entries outside the particle range or on a periodic axis are skipped
+    and latched as EINVAL; the valid ones still act."""
+    import torch
+    c = _wall_layer(309)
+    ref_l, ref_f = _oracle_lists(c)
+    D = dev_case(c, "f64")
+    plan = ibmx.Plan.from_case(c, "f64")
+    res, hist, whist, k, kw = _device_lists(plan, D, c, ref_l, ref_f)
+    bad = dict(res)
+    pairs = res["pairs"].clone()
+    pairs[1, 0] = c.np_ + 5            # partner out of range
+    walls = res["walls"].clone()
+    walls[1, 0] = 0                    # x is periodic: no wall there
+    bad["pairs"], bad["walls"] = pairs, walls
+    plan.particle_substeps(1.0, 3, D["xp"], D["up"], D["wp"], D["radius"], D["mass"], bad, hist,
+                           whist, want_forces=False)
+    torch.cuda.synchronize()
+    assert plan.status() == ibmx.EINVAL
+    assert torch.isfinite(D["xp"]).all() and torch.isfinite(D["up"]).all()
