@@ -83,27 +83,28 @@ def kernel_sources_hash() -> str:
 
 def fluid_bytes(kind: str, s: int, nodes: int, walls_z: bool = True) -> float:
     """Bytes one fluid call must move (s = bytes of the field type; the
-    solves work on an FP64 complex grid, 16 B per node).
+    solves work in FP64 on a real grid, 8 B per node, and its half spectrum of
+    nx/2 + 1 complex modes per row, about 8 B per node).
 
+    solve (one real right-hand side): the real-to-complex pass along x
+           (read 8, write 8), the y pass forward and back (16 each), the
+           complex-to-real pass (16), and across walls the elimination (read
+           and write the spectrum twice, the eliminated coefficient once each
+           way: 40) or along a periodic z two more passes and the division (48).
     predictor: reads u, N (3s each) and P (s); writes u~, N and nu L u (3s each).
-    solve (one complex right-hand side): FFT passes along x and y, forward and
-           inverse (4 x 32 B), and across walls the elimination (read and
-           write the grid twice, the eliminated coefficient once each way:
-           80 B), or along a periodic z two more FFT passes and the division.
-    project: face values and divergence (reads 3s, writes 3s + 16 B), the
-           solve, then the correction (reads the grid, u, u_f, P; writes u,
-           u_f, P, phi: 16 B + 15s).
-    helmholtz: x and y in one complex solve, z in a second: right-hand sides
-           (2 components: 4s + s + 16 B, one: 2s + s + 16 B), two solves, and
-           the unpacking (16 B + 2s, 16 B + s).
+    project: face values and divergence (reads 3s, writes 3s + 8), the solve,
+           the correction (reads the solution, u, u_f, P; writes u, u_f, P,
+           phi: 8 + 15s).
+    helmholtz: per component the right-hand side (reads 3s, writes 8), the
+           solve and the result (reads 8, writes s).
     """
-    solve = 4 * 32 + (80 if walls_z else 96)
+    solve = 16 + 16 + 16 + 16 + (40 if walls_z else 48)
     if kind == "predictor":
         per = 16 * s
     elif kind == "project":
-        per = (6 * s + 16) + solve + (16 + 15 * s)
+        per = (6 * s + 8) + solve + (8 + 15 * s)
     elif kind == "helmholtz":
-        per = (5 * s + 16) + (3 * s + 16) + 2 * solve + (16 + 2 * s) + (16 + s)
+        per = 3 * ((3 * s + 8) + solve + (8 + s))
     else:
         raise KeyError(kind)
     return float(per) * nodes

@@ -5,7 +5,8 @@
 //
 // Both implicit systems, (I - beta L) u* = r per velocity component and the
 // compact Poisson equation L phi = div(u_f*) / c, are solved directly in
-// FP64: complex FFTs along the periodic x and y axes (and z when periodic,
+// FP64 for a real right-hand side: a real-to-complex FFT along x (the
+// nx/2 + 1 modes of each row), complex FFTs along y (and z when periodic,
 // then a division by the eigenvalues), or per (kx, ky) mode a tridiagonal
 // elimination across the walls in z.  FFTs are radix-2 passes in place in
 // LDS, several short lines per workgroup, loaded so that each wave reads
@@ -19,9 +20,8 @@
 namespace {
 
 constexpr int kFftThreads = 256;
-constexpr int kFftElems = 512;      // elements per workgroup, contiguous lines
+constexpr int kRowElems = 256;      // complex elements per workgroup in the x passes
 constexpr int kFftElemsStrided = 2048;   // strided lines: 32 KB of LDS, 4 lines of 512
-constexpr int kFftMaxLines = 1024;       // lines per workgroup (lines of 2 elements and up)
 
 struct FluidC {
     int n[3];
@@ -48,10 +48,10 @@ __device__ __forceinline__ long long neighbour(const FluidC &F, int i, int j, in
 }
 
 // u_f* = mean of the two cells of each +a face (wall faces 0), and the
-// right-hand side div(u_f*) / c as a complex field with zero imaginary part
+// right-hand side div(u_f*) / c
 template <typename T>
 __global__ __launch_bounds__(256) void k_face_div(FluidC F, const T *__restrict__ u,
-                                                  T *__restrict__ uf, double2 *__restrict__ Z)
+                                                  T *__restrict__ uf, double *__restrict__ R)
 {
     const long long N = (long long)F.n[0] * F.n[1] * F.n[2];
     {
@@ -69,7 +69,7 @@ __global__ __launch_bounds__(256) void k_face_div(FluidC F, const T *__restrict_
             uf[(size_t)a * N + c] = (T)out;
             div = div + (out - in) / F.h;
         }
-        Z[c] = make_double2(div / F.c, 0.0);
+        R[c] = div / F.c;
     }
 }
 
@@ -78,61 +78,43 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b)
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// Batched complex FFT of lines of length n = 2^logn: iterative radix-2
-// Cooley-Tukey in place in LDS (elements loaded in bit-reversed order), two
-// stages per pass.
-// Line l of the batch starts at (l / A) * B + (l % A) * C and has element
-// stride S; a workgroup takes `lpw` consecutive lines.  Contiguous lines
-// (S = 1) are loaded line by line, strided ones element-major across the
-// lines, so the loads of a wave are contiguous either way.  tw[m] =
-// exp(-2 pi i m / n), m < n / 2, read through the cache; INV uses the
-// conjugate (no 1/n scaling).
-template <bool INV>
-__global__ __launch_bounds__(kFftThreads) void k_fft(double2 *__restrict__ Z, int n, int logn,
-                                                     int lpw, long long A, long long B, long long C,
-                                                     long long S, const double2 *__restrict__ tw)
+__device__ __forceinline__ int log2i_dev(int n)
 {
-    extern __shared__ double2 buf[];
-    __shared__ long long lbase[kFftMaxLines];
-    const int total = lpw * n, half_n = n / 2;
-    const long long line0 = (long long)blockIdx.x * lpw;
-    for (int l = threadIdx.x; l < lpw; l += blockDim.x) {
-        const long long line = line0 + l;
-        lbase[l] = (line / A) * B + (line % A) * C;
-    }
-    __syncthreads();
-    auto addr = [&](int l, int s) -> long long { return lbase[l] + (long long)s * S; };
-    for (int e = threadIdx.x; e < total; e += blockDim.x) {
-        const int l = S == 1 ? e / n : e % lpw, s = S == 1 ? e % n : e / lpw;
-        const int r = logn > 0 ? (int)(__brev((unsigned)s) >> (32 - logn)) : 0;
-        buf[l * n + r] = Z[addr(l, s)];
-    }
-    __syncthreads();
-    // stages in pairs (len, 2 len): the four elements i, i + half, i + len,
-    // i + len + half close under both stages, so a thread takes them through
-    // both with one LDS read and write each; a last single stage when logn is
-    // odd
+    int l = 0;
+    while ((1 << l) < n)
+        ++l;
+    return l;
+}
+
+// In-place complex FFT of `lines` lines of length n = 2^logn held in LDS in
+// bit-reversed order: iterative radix-2 Cooley-Tukey, two stages per pass
+// (the four elements i, i + half, i + len, i + len + half close under both
+// stages), a last single stage when logn is odd.  w(m) = tw[m * ts] =
+// exp(-2 pi i m / n); INV uses the conjugate (no 1/n scaling).
+template <bool INV>
+__device__ void fft_lds(double2 *buf, int n, int lines, const double2 *__restrict__ tw, int ts)
+{
+    const int half_n = n / 2;
+    auto w = [&](int m) {
+        double2 v = tw[(size_t)m * ts];
+        if (INV)
+            v.y = -v.y;
+        return v;
+    };
     int len = 2;
     for (; 2 * len <= n; len <<= 2) {
         const int half = len >> 1, quarter_n = n / 4;
-        for (int b = threadIdx.x; b < lpw * quarter_n; b += blockDim.x) {
+        for (int b = threadIdx.x; b < lines * quarter_n; b += blockDim.x) {
             const int l = b / quarter_n, q = b % quarter_n, pos = q % half;
             const int i0 = l * n + (q / half) * (2 * len) + pos;
-            double2 w1 = tw[pos * (n / len)], w2 = tw[pos * (n / (2 * len))],
-                    w3 = tw[(pos + half) * (n / (2 * len))];
-            if (INV) {
-                w1.y = -w1.y;
-                w2.y = -w2.y;
-                w3.y = -w3.y;
-            }
+            const double2 w1 = w(pos * (n / len)), w2 = w(pos * (n / (2 * len))),
+                          w3 = w((pos + half) * (n / (2 * len)));
             const double2 a0 = buf[i0], a1 = cmul(buf[i0 + half], w1);
             const double2 a2 = buf[i0 + len], a3 = cmul(buf[i0 + len + half], w1);
-            // stage len
             const double2 b0 = make_double2(a0.x + a1.x, a0.y + a1.y);
             const double2 b1 = make_double2(a0.x - a1.x, a0.y - a1.y);
             const double2 b2 = make_double2(a2.x + a3.x, a2.y + a3.y);
             const double2 b3 = make_double2(a2.x - a3.x, a2.y - a3.y);
-            // stage 2 len: (i0, i0 + len) with w2, (i0 + half, i0 + len + half) with w3
             const double2 c2 = cmul(b2, w2), c3 = cmul(b3, w3);
             buf[i0] = make_double2(b0.x + c2.x, b0.y + c2.y);
             buf[i0 + len] = make_double2(b0.x - c2.x, b0.y - c2.y);
@@ -142,22 +124,118 @@ __global__ __launch_bounds__(kFftThreads) void k_fft(double2 *__restrict__ Z, in
         __syncthreads();
     }
     if (len <= n) {
-        const int half = len >> 1, step = n / len;
-        for (int b = threadIdx.x; b < lpw * half_n; b += blockDim.x) {
+        const int half = len >> 1;
+        for (int b = threadIdx.x; b < lines * half_n; b += blockDim.x) {
             const int l = b / half_n, jj = b % half_n, pos = jj % half;
             const int i0 = l * n + (jj / half) * len + pos, i1 = i0 + half;
-            double2 wk = tw[pos * step];
-            if (INV)
-                wk.y = -wk.y;
+            const double2 wk = w(pos * (n / len));
             const double2 v0 = buf[i0], v1 = cmul(buf[i1], wk);
             buf[i0] = make_double2(v0.x + v1.x, v0.y + v1.y);
             buf[i1] = make_double2(v0.x - v1.x, v0.y - v1.y);
         }
         __syncthreads();
     }
-    for (int e = threadIdx.x; e < total; e += blockDim.x) {
-        const int l = S == 1 ? e / n : e % lpw, s = S == 1 ? e % n : e / lpw;
-        Z[addr(l, s)] = buf[l * n + s];
+}
+
+__device__ __forceinline__ int bitrev(int s, int logn)
+{
+    return logn > 0 ? (int)(__brev((unsigned)s) >> (32 - logn)) : 0;
+}
+
+// Real-to-complex transform of rows along x (nx = 2 N2): each row's values
+// r[2m] + i r[2m + 1] form N2 complex values whose FFT Z gives the row's
+// modes X[k] = (Z[k] + Z*[N2 - k])/2 - i w^k (Z[k] - Z*[N2 - k])/2, k = 0..N2,
+// w = exp(-2 pi i / nx); H holds N2 + 1 modes per row.  `rows` rows per
+// workgroup.
+__global__ __launch_bounds__(kFftThreads) void k_rfft_x(const double *__restrict__ R,
+                                                        double2 *__restrict__ H, int nx, int rows,
+                                                        long long nrows,
+                                                        const double2 *__restrict__ tw)
+{
+    extern __shared__ double2 buf[];
+    const int N2 = nx / 2, logn = log2i_dev(N2), mx = N2 + 1;
+    const long long row0 = (long long)blockIdx.x * rows;
+    const int nr = (int)(nrows - row0 < rows ? nrows - row0 : rows);
+    const double2 *Rc = reinterpret_cast<const double2 *>(R);
+    for (int e = threadIdx.x; e < nr * N2; e += blockDim.x) {
+        const int l = e / N2, m = e % N2;
+        buf[l * N2 + bitrev(m, logn)] = Rc[(row0 + l) * N2 + m];
+    }
+    __syncthreads();
+    fft_lds<false>(buf, N2, nr, tw, 2);
+    for (int e = threadIdx.x; e < nr * mx; e += blockDim.x) {
+        const int l = e / mx, k = e % mx;
+        const double2 zk = buf[l * N2 + (k == N2 ? 0 : k)];
+        const double2 zc = buf[l * N2 + (k == 0 ? 0 : N2 - k)];
+        const double2 sum = make_double2(0.5 * (zk.x + zc.x), 0.5 * (zk.y - zc.y));
+        const double2 dif = make_double2(0.5 * (zk.x - zc.x), 0.5 * (zk.y + zc.y));
+        // -i w^k dif, w^k = tw[k] of the nx-point table (k <= N2: its last entry
+        // is -1 = w^(nx/2))
+        const double2 wk = k < N2 ? tw[k] : make_double2(-1.0, 0.0);
+        const double2 t = cmul(wk, dif);
+        H[(row0 + l) * mx + k] = make_double2(sum.x + t.y, sum.y - t.x);
+    }
+}
+
+// Complex-to-real inverse of k_rfft_x (unnormalised: the rows come back
+// multiplied by N2): Z[k] = E + i O with E = (X[k] + X*[N2 - k])/2 and O =
+// (X[k] - X*[N2 - k]) w^-k / 2, inverse FFT, r[2m] = Re z[m], r[2m + 1] =
+// Im z[m].
+__global__ __launch_bounds__(kFftThreads) void k_irfft_x(const double2 *__restrict__ H,
+                                                         double *__restrict__ R, int nx, int rows,
+                                                         long long nrows,
+                                                         const double2 *__restrict__ tw)
+{
+    extern __shared__ double2 buf[];
+    const int N2 = nx / 2, logn = log2i_dev(N2), mx = N2 + 1;
+    const long long row0 = (long long)blockIdx.x * rows;
+    const int nr = (int)(nrows - row0 < rows ? nrows - row0 : rows);
+    for (int e = threadIdx.x; e < nr * N2; e += blockDim.x) {
+        const int l = e / N2, k = e % N2;
+        const double2 xk = H[(row0 + l) * mx + k];
+        const double2 xc = H[(row0 + l) * mx + (N2 - k)];
+        const double2 E = make_double2(0.5 * (xk.x + xc.x), 0.5 * (xk.y - xc.y));
+        const double2 D = make_double2(0.5 * (xk.x - xc.x), 0.5 * (xk.y + xc.y));
+        double2 wk = tw[k];
+        wk.y = -wk.y;
+        const double2 O = cmul(D, wk);
+        buf[l * N2 + bitrev(k, logn)] = make_double2(E.x - O.y, E.y + O.x);
+    }
+    __syncthreads();
+    fft_lds<true>(buf, N2, nr, tw, 2);
+    double2 *Rc = reinterpret_cast<double2 *>(R);
+    for (int e = threadIdx.x; e < nr * N2; e += blockDim.x) {
+        const int l = e / N2, m = e % N2;
+        Rc[(row0 + l) * N2 + m] = buf[l * N2 + m];
+    }
+}
+
+// Complex FFT along a strided axis: each plane holds `A` lines, line a of
+// plane q starting at q * B + a * C with element stride S; a workgroup takes
+// up to `lpw` consecutive lines of one plane (fewer at the plane's end) and
+// loads them element-major, so a wave reads lpw contiguous values per row.
+template <bool INV>
+__global__ __launch_bounds__(kFftThreads) void k_fft_strided(double2 *__restrict__ Z, int n,
+                                                             int lpw, int A, long long B,
+                                                             long long C, long long S,
+                                                             const double2 *__restrict__ tw)
+{
+    extern __shared__ double2 buf[];
+    const int logn = log2i_dev(n);
+    const int groups = (A + lpw - 1) / lpw;
+    const long long q = blockIdx.x / groups;
+    const int a0 = (int)(blockIdx.x % groups) * lpw;
+    const int nl = A - a0 < lpw ? A - a0 : lpw;
+    const long long base = q * B + (long long)a0 * C;
+    for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
+        const int l = e % nl, sidx = e / nl;
+        buf[l * n + bitrev(sidx, logn)] = Z[base + l * C + sidx * S];
+    }
+    __syncthreads();
+    fft_lds<INV>(buf, n, nl, tw, 1);
+    for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
+        const int l = e % nl, sidx = e / nl;
+        Z[base + l * C + sidx * S] = buf[l * n + sidx];
     }
 }
 
@@ -167,23 +245,24 @@ __device__ __forceinline__ double lam(int m, int n, double h)
     return (2.0 * cospi(2.0 * m / (double)n) - 2.0) / (h * h);
 }
 
-// triply periodic: mode by mode x = d / (s0 + s1 lambda); with s0 = 0 the
-// mean mode is 0
+// triply periodic: mode by mode x = d / (s0 + s1 lambda) over the modes
+// kx = 0 .. nx/2 held for real fields; with s0 = 0 the mean mode is 0
 __global__ __launch_bounds__(256) void k_divide(FluidC F, double s0, double s1,
                                                 double2 *__restrict__ Z)
 {
+    const int mx = F.n[0] / 2 + 1;
     {
         const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
-        if (i >= F.n[0])
+        if (i >= mx)
             return;
-        const long long c = cell_index(F, i, j, k);
+        const long long c = ((long long)k * F.n[1] + j) * mx + i;
         const double L = s0 + s1 * (lam(i, F.n[0], F.h) + lam(j, F.n[1], F.h) + lam(k, F.n[2], F.h));
         const double2 z = Z[c];
         Z[c] = (c == 0 && s0 == 0.0) ? make_double2(0.0, 0.0) : make_double2(z.x / L, z.y / L);
     }
 }
 
-// walls in z: per (kx, ky) mode the system s0 x + s1 (D_z + lambda_xy) x =
+// walls in z: per (kx, ky) mode (kx = 0 .. nx/2) the system s0 x + s1 (D_z + lambda_xy) x =
 // rhs, D_z the second difference (1/h^2)(x_{k+1} - 2 x_k + x_{k-1}) closed
 // at the walls by a zero gradient (Neumann, the pressure) or by the ghost
 // -x (no slip, the velocity), solved by elimination from the bottom.  The
@@ -193,11 +272,11 @@ __global__ __launch_bounds__(256) void k_divide(FluidC F, double s0, double s1,
 __global__ __launch_bounds__(256) void k_tridiag(FluidC F, double s0, double s1, int dirichlet,
                                                  double2 *__restrict__ Z, double *__restrict__ cp)
 {
-    const int nxy = F.n[0] * F.n[1], nz = F.n[2];
+    const int mx = F.n[0] / 2 + 1, nxy = mx * F.n[1], nz = F.n[2];
     const int col = blockIdx.x * blockDim.x + threadIdx.x;
     if (col >= nxy)
         return;
-    const int i = col % F.n[0], j = col / F.n[0];
+    const int i = col % mx, j = col / mx;
     const double ih2 = 1.0 / (F.h * F.h);
     const double lxy = lam(i, F.n[0], F.h) + lam(j, F.n[1], F.h);
     const bool singular = col == 0 && s0 == 0.0 && !dirichlet;
@@ -241,11 +320,11 @@ __global__ __launch_bounds__(256) void k_tridiag(FluidC F, double s0, double s1,
     }
 }
 
-// phi = Re(Z) / scale; u = u* - c grad(phi) (mean of the cell's two face
+// phi = R * scale; u = u* - c grad(phi) (mean of the cell's two face
 // gradients), u_f = u_f* - c (phi_+ - phi)/h, P = (1 - theta) P + phi -
 // (c/2) nu L phi
 template <typename T>
-__global__ __launch_bounds__(256) void k_correct(FluidC F, const double2 *__restrict__ Z,
+__global__ __launch_bounds__(256) void k_correct(FluidC F, const double *__restrict__ Z,
                                                  double scale, T *__restrict__ u,
                                                  T *__restrict__ uf, T *__restrict__ P,
                                                  T *__restrict__ phi_out)
@@ -256,12 +335,12 @@ __global__ __launch_bounds__(256) void k_correct(FluidC F, const double2 *__rest
         if (i >= F.n[0])
             return;
         const long long c = cell_index(F, i, j, k);
-        const double ph = Z[c].x * scale;
+        const double ph = Z[c] * scale;
         double lap = 0.0;
         for (int a = 0; a < 3; ++a) {
             const long long up = neighbour(F, i, j, k, a, 1), dn = neighbour(F, i, j, k, a, -1);
-            const double gp = up >= 0 ? (Z[up].x * scale - ph) / F.h : 0.0;
-            const double gm = dn >= 0 ? (ph - Z[dn].x * scale) / F.h : 0.0;
+            const double gp = up >= 0 ? (Z[up] * scale - ph) / F.h : 0.0;
+            const double gm = dn >= 0 ? (ph - Z[dn] * scale) / F.h : 0.0;
             const size_t ia = (size_t)a * N + c;
             u[ia] = (T)((double)u[ia] - F.c * (0.5 * (gp + gm)));
             uf[ia] = (T)((double)uf[ia] - F.c * gp);
@@ -421,51 +500,34 @@ __global__ __launch_bounds__(PX * PY) void k_predict(FluidC F, const T *__restri
     }
 }
 
-// step e: the right-hand side u_f - c fbar + dt (-alpha lapnu + 2 alpha
-// theta grad P) of component b0 into the real part of Z and of component b1
-// (if >= 0) into the imaginary part: the operator is real, so one complex
-// solve serves both
-template <typename T>
-__device__ __forceinline__ double helm_rhs(const FluidC &F, const T *u, const T *lapnu, const T *P,
-                                           const double *fbar, int b, long long c, int i, int j,
-                                           int k, double dt, double alpha)
-{
-    const long long N = (long long)F.n[0] * F.n[1] * F.n[2];
-    const double fb = fbar ? fbar[b] : 0.0;
-    const double gP = cell_grad(F, P, c, i, j, k, b);
-    return (double)u[(size_t)b * N + c] - F.c * fb +
-           dt * (-alpha * (double)lapnu[(size_t)b * N + c] + 2.0 * alpha * F.theta * gP);
-}
-
+// step e, component b: the right-hand side u_f - c fbar + dt (-alpha lapnu
+// + 2 alpha theta grad P) into R
 template <typename T>
 __global__ __launch_bounds__(256) void k_helm_rhs(FluidC F, const T *__restrict__ u,
                                                   const T *__restrict__ lapnu,
                                                   const T *__restrict__ P,
-                                                  const double *__restrict__ fbar, int b0, int b1,
-                                                  double dt, double alpha, double2 *__restrict__ Z)
+                                                  const double *__restrict__ fbar, int b,
+                                                  double dt, double alpha, double *__restrict__ R)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
     if (i >= F.n[0])
         return;
+    const long long N = (long long)F.n[0] * F.n[1] * F.n[2];
     const long long c = cell_index(F, i, j, k);
-    const double r0 = helm_rhs(F, u, lapnu, P, fbar, b0, c, i, j, k, dt, alpha);
-    const double r1 = b1 >= 0 ? helm_rhs(F, u, lapnu, P, fbar, b1, c, i, j, k, dt, alpha) : 0.0;
-    Z[c] = make_double2(r0, r1);
+    const double fb = fbar ? fbar[b] : 0.0;
+    const double gP = cell_grad(F, P, c, i, j, k, b);
+    R[c] = (double)u[(size_t)b * N + c] - F.c * fb +
+           dt * (-alpha * (double)lapnu[(size_t)b * N + c] + 2.0 * alpha * F.theta * gP);
 }
 
-// the solution: real part into component b0, imaginary part into b1
+// the solution R * scale into out
 template <typename T>
-__global__ __launch_bounds__(256) void k_take(long long N, const double2 *__restrict__ Z,
-                                              double scale, T *__restrict__ out0,
-                                              T *__restrict__ out1)
+__global__ __launch_bounds__(256) void k_take(long long N, const double *__restrict__ R,
+                                              double scale, T *__restrict__ out)
 {
     for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < N;
-         c += (long long)gridDim.x * blockDim.x) {
-        const double2 z = Z[c];
-        out0[c] = (T)(z.x * scale);
-        if (out1)
-            out1[c] = (T)(z.y * scale);
-    }
+         c += (long long)gridDim.x * blockDim.x)
+        out[c] = (T)(R[c] * scale);
 }
 
 int grid_blocks(long long n) { return (int)(n / 256 + 1 < 16384 ? n / 256 + 1 : 16384); }
@@ -482,36 +544,46 @@ CellLaunch cells(const FluidC &F)
 
 bool pow2(int n) { return n >= 2 && (n & (n - 1)) == 0; }
 
-int log2i(int n)
+
+// strided complex FFT along y (a = 1) or z (a = 2) over the half spectrum
+// (nx/2 + 1 columns)
+template <bool INV>
+void fft_strided(ibmx_plan p, const FluidC &F, int a, hipStream_t s)
 {
-    int l = 0;
-    while ((1 << l) < n)
-        ++l;
-    return l;
+    const int mx = F.n[0] / 2 + 1, ny = F.n[1], nz = F.n[2], n = F.n[a];
+    int A;
+    long long B, S, planes;
+    if (a == 1) {
+        A = mx, B = (long long)mx * ny, S = mx, planes = nz;
+    } else {
+        A = mx * ny, B = 0, S = (long long)mx * ny, planes = 1;
+    }
+    int lpw = n >= kFftElemsStrided ? 1 : kFftElemsStrided / n;
+    if (lpw > A)
+        lpw = A;
+    const long long blocks = planes * ((A + lpw - 1) / lpw);
+    hipLaunchKernelGGL((k_fft_strided<INV>), dim3((unsigned)blocks), dim3(kFftThreads),
+                       sizeof(double2) * (size_t)lpw * n, s, p->fl_z, n, lpw, A, B, 1LL, S,
+                       (const double2 *)p->fl_tw[a]);
 }
 
-// one FFT pass along axis a over the whole grid
+// rows along x: forward real-to-complex from fl_r into fl_z, or back
 template <bool INV>
-void fft_axis(ibmx_plan p, const FluidC &F, int a, hipStream_t s)
+void fft_rows(ibmx_plan p, const FluidC &F, hipStream_t s)
 {
-    const int nx = F.n[0], ny = F.n[1], nz = F.n[2], n = F.n[a];
-    long long A, B, C, S, lines;
-    int lim;   // lines of one group must share the pattern below
-    if (a == 0) {
-        A = 1, B = nx, C = 0, S = 1, lines = (long long)ny * nz, lim = ny * nz;
-    } else if (a == 1) {
-        A = nx, B = (long long)nx * ny, C = 1, S = nx, lines = (long long)nx * nz, lim = nx;
-    } else {
-        A = (long long)nx * ny, B = 0, C = 1, S = (long long)nx * ny, lines = (long long)nx * ny,
-        lim = nx * ny;
-    }
-    const int elems = a == 0 ? kFftElems : kFftElemsStrided;
-    int lpw = n >= elems ? 1 : elems / n;
-    while (lpw > 1 && (lpw > lim || lim % lpw != 0))
-        lpw >>= 1;
-    const size_t lds = sizeof(double2) * (size_t)lpw * n;
-    hipLaunchKernelGGL((k_fft<INV>), dim3((unsigned)(lines / lpw)), dim3(kFftThreads), lds, s,
-                       p->fl_z, n, log2i(n), lpw, A, B, C, S, (const double2 *)p->fl_tw[a]);
+    const int N2 = F.n[0] / 2;
+    const long long nrows = (long long)F.n[1] * F.n[2];
+    const int rows = N2 >= kRowElems ? 1 : kRowElems / N2;
+    const unsigned blocks = (unsigned)((nrows + rows - 1) / rows);
+    const size_t lds = sizeof(double2) * (size_t)rows * N2;
+    if (INV)
+        hipLaunchKernelGGL(k_irfft_x, dim3(blocks), dim3(kFftThreads), lds, s,
+                           (const double2 *)p->fl_z, p->fl_r, F.n[0], rows, nrows,
+                           (const double2 *)p->fl_tw[0]);
+    else
+        hipLaunchKernelGGL(k_rfft_x, dim3(blocks), dim3(kFftThreads), lds, s,
+                           (const double *)p->fl_r, p->fl_z, F.n[0], rows, nrows,
+                           (const double2 *)p->fl_tw[0]);
 }
 
 FluidC fluid_constants(const ibmx_plan p, double theta)
@@ -529,26 +601,29 @@ FluidC fluid_constants(const ibmx_plan p, double theta)
     return F;
 }
 
-// Z (a right-hand side in the cell layout) -> the solution of (s0 + s1 L) x
-// = Z, times the returned scale (the inverse FFTs are unnormalised)
+// fl_r (a real right-hand side in the cell layout) -> the solution of
+// (s0 + s1 L) x = r in fl_r, times the returned scale (the inverse passes
+// are unnormalised)
 double solve_modes(ibmx_plan p, const FluidC &F, double s0, double s1, int dirichlet,
                    hipStream_t s)
 {
-    fft_axis<false>(p, F, 0, s);
-    fft_axis<false>(p, F, 1, s);
-    double scale = 1.0 / ((double)F.n[0] * F.n[1]);
+    const int mx = F.n[0] / 2 + 1;
+    fft_rows<false>(p, F, s);
+    fft_strided<false>(p, F, 1, s);
+    double scale = 1.0 / ((double)(F.n[0] / 2) * F.n[1]);
     if (F.periodic[2]) {
-        fft_axis<false>(p, F, 2, s);
-        hipLaunchKernelGGL(k_divide, cells(F).grid, cells(F).block, 0, s, F, s0, s1, p->fl_z);
-        fft_axis<true>(p, F, 2, s);
+        fft_strided<false>(p, F, 2, s);
+        hipLaunchKernelGGL(k_divide, dim3((mx + 255) / 256, F.n[1], F.n[2]), dim3(256), 0, s, F,
+                           s0, s1, p->fl_z);
+        fft_strided<true>(p, F, 2, s);
         scale /= F.n[2];
     } else {
-        const int nxy = F.n[0] * F.n[1];
+        const int nxy = mx * F.n[1];
         hipLaunchKernelGGL(k_tridiag, dim3((nxy + 255) / 256), dim3(256), 0, s, F, s0, s1,
                            dirichlet, p->fl_z, p->fl_cp);
     }
-    fft_axis<true>(p, F, 1, s);
-    fft_axis<true>(p, F, 0, s);
+    fft_strided<true>(p, F, 1, s);
+    fft_rows<true>(p, F, s);
     return scale;
 }
 
@@ -559,10 +634,10 @@ ibmx_status run_project(ibmx_plan p, T *u, T *uf, T *P, T *phi, double theta)
     hipStream_t s = p->stream;
     ProfScope ps(p, IBMX_K_OTHER);
     hipLaunchKernelGGL((k_face_div<T>), cells(F).grid, cells(F).block, 0, s, F, (const T *)u, uf,
-                       p->fl_z);
+                       p->fl_r);
     const double scale = solve_modes(p, F, 0.0, 1.0, 0, s);
     hipLaunchKernelGGL((k_correct<T>), cells(F).grid, cells(F).block, 0, s, F,
-                       (const double2 *)p->fl_z, scale, u, uf, P, phi);
+                       (const double *)p->fl_r, scale, u, uf, P, phi);
     return ibmx_launch_check();
 }
 
@@ -588,15 +663,12 @@ ibmx_status run_helmholtz(ibmx_plan p, T *u, const T *lapnu, const T *P, const d
     const long long N = p->g.nodes;
     hipStream_t s = p->stream;
     ProfScope ps(p, IBMX_K_OTHER);
-    // x and y together, then z
-    for (int b0 = 0; b0 < 3; b0 += 2) {
-        const int b1 = b0 == 0 ? 1 : -1;
+    for (int b = 0; b < 3; ++b) {
         hipLaunchKernelGGL((k_helm_rhs<T>), cells(F).grid, cells(F).block, 0, s, F, (const T *)u,
-                           lapnu, P, fbar, b0, b1, dt, alpha, p->fl_z);
+                           lapnu, P, fbar, b, dt, alpha, p->fl_r);
         const double scale = solve_modes(p, F, 1.0, -alpha * dt * F.nu, 1, s);
         hipLaunchKernelGGL((k_take<T>), dim3(grid_blocks(N)), dim3(256), 0, s, N,
-                           (const double2 *)p->fl_z, scale, u + (size_t)b0 * N,
-                           b1 >= 0 ? u + (size_t)b1 * N : (T *)nullptr);
+                           (const double *)p->fl_r, scale, u + (size_t)b * N);
     }
     return ibmx_launch_check();
 }
@@ -607,17 +679,23 @@ bool solver_grid_ok(const ibmx_grid &g)
            g.n[1] <= 1024 && (!g.periodic[2] || (pow2(g.n[2]) && g.n[2] <= 1024));
 }
 
-// workspace: the complex grid, the elimination scratch (walls in z) and
-// one twiddle table per axis
+// workspace: the real right-hand side / solution grid, the half spectrum
+// (nx/2 + 1 modes along x), the elimination scratch (walls in z) and one
+// twiddle table per axis
 ibmx_status fluid_reserve(ibmx_plan p)
 {
     const size_t N = (size_t)p->g.nodes;
-    if (!p->fl_z && hipMalloc((void **)&p->fl_z, sizeof(double2) * N) != hipSuccess) {
+    const size_t M = (size_t)(p->grid.n[0] / 2 + 1) * p->grid.n[1] * p->grid.n[2];
+    if (!p->fl_r && hipMalloc((void **)&p->fl_r, sizeof(double) * N) != hipSuccess) {
+        p->fl_r = nullptr;
+        return IBMX_ENOMEM;
+    }
+    if (!p->fl_z && hipMalloc((void **)&p->fl_z, sizeof(double2) * M) != hipSuccess) {
         p->fl_z = nullptr;
         return IBMX_ENOMEM;
     }
     if (!p->grid.periodic[2] && !p->fl_cp &&
-        hipMalloc((void **)&p->fl_cp, sizeof(double) * N) != hipSuccess) {
+        hipMalloc((void **)&p->fl_cp, sizeof(double) * M) != hipSuccess) {
         p->fl_cp = nullptr;
         return IBMX_ENOMEM;
     }

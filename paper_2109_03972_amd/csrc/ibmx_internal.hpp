@@ -97,10 +97,10 @@ struct ibmx_plan_s {
     double *s_buf;        // [s_cap] sub-step states, stage forces, F_h factors
     long long s_cap;
 
-    // projection workspace (first ibmx_project call): complex grid, the
-    // elimination scratch for walls in z, FFT twiddles per axis
-    double2 *fl_z;
-    double *fl_cp;
+    // fluid-solve workspace (first ibmx_project / ibmx_fluid_helmholtz call)
+    double *fl_r;         // real right-hand side / solution [nodes]
+    double2 *fl_z;        // half spectrum [nz][ny][nx/2 + 1]
+    double *fl_cp;        // elimination scratch [nz][ny][nx/2 + 1]
     double2 *fl_tw[3];
 
     // last-call statistics

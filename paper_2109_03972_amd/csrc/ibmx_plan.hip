@@ -25,7 +25,7 @@ void free_plan(ibmx_plan p)
                     p->tile_cursor, p->halo_count,  p->halo_start,   p->halo_cursor,
                     p->halo_list,   p->tile_gmax,   p->scan_aux,     p->mean_part,    p->bw_u,
                     p->c_deg,       p->c_off,       p->c_cur,        p->c_adj,        p->c_hist,
-                    p->s_buf,       p->fl_z,        p->fl_cp,        p->fl_tw[0],     p->fl_tw[1],
+                    p->s_buf,       p->fl_r,        p->fl_z,        p->fl_cp,        p->fl_tw[0],     p->fl_tw[1],
                     p->fl_tw[2],         p->p_cell_of, p->p_cursor,
                     p->p_count,     p->p_off,       p->p_wcount,     p->p_woff};
     for (void *q : ptrs)
