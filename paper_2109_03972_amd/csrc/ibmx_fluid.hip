@@ -376,11 +376,15 @@ __device__ __forceinline__ double cell_grad(const FluidC &F, const T *P, long lo
 
 // step a: u~ = u + dt (2 alpha nu L u - 2 alpha grad P - gamma N - zeta N_prev),
 // N = (u . grad) u; N holds N_prev on entry and N on exit, lapnu = nu L u.
-// A workgroup takes a PX x PY column of cells and marches it up in z: each
-// plane of u and P is staged in LDS with a one-cell rim for the x and y
-// neighbours, the planes below and above are kept in registers, so each
-// value is read from memory about once.
-constexpr int PX = 64, PY = 4;
+// A workgroup takes a PX x PY column of cells over a run of kPlanes planes
+// and marches it up in z.  Each plane of u and P, with a one-cell rim for the
+// x and y neighbours, goes through a ring of kRing planes in LDS: while plane
+// k is computed from planes k - 1, k and k + 1, plane k + 2 is loaded into
+// registers (and N_prev of plane k + 1), so each value is read from memory
+// about once (a run adds one plane at each end).  With four slots the store
+// of plane k + 1 cannot meet a read of the slot it reuses (last read while
+// computing plane k - 2), so one barrier per plane suffices.
+constexpr int PX = 64, PY = 4, kPlanes = 32, kRing = 4;
 
 template <typename T>
 __global__ __launch_bounds__(PX * PY) void k_predict(FluidC F, const T *__restrict__ u,
@@ -389,32 +393,24 @@ __global__ __launch_bounds__(PX * PY) void k_predict(FluidC F, const T *__restri
                                                      const T *__restrict__ P, double dt,
                                                      double alpha, double gamma, double zeta)
 {
-    __shared__ double tile[4][PY + 2][PX + 2];
+    // values are held in T and widened to double where they are used
+    __shared__ T tile[kRing][4][PY + 2][PX + 2];
     const long long N = (long long)F.n[0] * F.n[1] * F.n[2];
     const int nx = F.n[0], ny = F.n[1], nz = F.n[2];
     const int tx = threadIdx.x % PX, ty = threadIdx.x / PX;
     const int i0 = blockIdx.x * PX, j0 = blockIdx.y * PY;
+    const int k0 = blockIdx.z * kPlanes, k1 = min(nz, k0 + kPlanes);
     const int i = i0 + tx, j = j0 + ty;
     const bool live = i < nx && j < ny;
     const T *fld[4] = {u, u + N, u + 2 * N, P};
-    // value of field q at (i, j, kk) (kk already inside the grid)
-    auto at = [&](int q, int ii, int jj, int kk) -> double {
-        return (double)fld[q][((long long)kk * ny + jj) * nx + ii];
-    };
-    double zc[4] = {0, 0, 0, 0}, zn[4] = {0, 0, 0, 0}, zp[4] = {0, 0, 0, 0}, z0[4] = {0, 0, 0, 0};
-    if (live)
-        for (int q = 0; q < 4; ++q) {
-            zc[q] = at(q, i, j, 0);
-            z0[q] = zc[q];
-            if (F.periodic[2])
-                zp[q] = at(q, i, j, nz - 1);
-        }
-    // the rim-extended plane is loaded into registers one plane ahead
-    // (each thread holds up to kPre of its slots), stored to LDS after the
-    // previous plane's compute: the loads of plane k + 1 overlap the compute
-    // of plane k
+    // plane above / below kk, -1 behind a wall
+    auto z_up = [&](int kk) { return kk + 1 < nz ? kk + 1 : (F.periodic[2] ? 0 : -1); };
+    auto z_dn = [&](int kk) { return kk > 0 ? kk - 1 : (F.periodic[2] ? nz - 1 : -1); };
+    // ring slot of plane kk (kk >= k0 - 1)
+    auto slot = [&](int kk) { return (kk - k0 + 1) & (kRing - 1); };
     constexpr int kSlots = (PY + 2) * (PX + 2), kPre = (kSlots + PX * PY - 1) / (PX * PY);
-    double pre[kPre][4];
+    T pre[kPre][4];
+    // the rim-extended plane kk into registers (zeros behind a wall, kk < 0)
     auto load_plane = [&](int kk) {
         for (int r = 0; r < kPre; ++r) {
             const int e = threadIdx.x + r * PX * PY;
@@ -426,77 +422,95 @@ __global__ __launch_bounds__(PX * PY) void k_predict(FluidC F, const T *__restri
                 gi = gi < 0 ? gi + nx : (gi >= nx ? gi - nx : gi);
             if (F.periodic[1])
                 gj = gj < 0 ? gj + ny : (gj >= ny ? gj - ny : gj);
-            const bool in = gi >= 0 && gi < nx && gj >= 0 && gj < ny;
+            const bool in = kk >= 0 && gi >= 0 && gi < nx && gj >= 0 && gj < ny;
+            const long long o = ((long long)kk * ny + gj) * nx + gi;
             for (int q = 0; q < 4; ++q)
-                pre[r][q] = in ? at(q, gi, gj, kk) : 0.0;
+                pre[r][q] = in ? fld[q][o] : T(0);
         }
     };
-    load_plane(0);
-    for (int k = 0; k < nz; ++k) {
-        __syncthreads();
+    auto store_plane = [&](int sl) {
         for (int r = 0; r < kPre; ++r) {
             const int e = threadIdx.x + r * PX * PY;
             if (e >= kSlots)
                 break;
             const int ry = e / (PX + 2), rx = e % (PX + 2);
             for (int q = 0; q < 4; ++q)
-                tile[q][ry][rx] = pre[r][q];
+                tile[sl][q][ry][rx] = pre[r][q];
         }
+    };
+    // N_prev of the own cell on plane kk
+    auto own_n = [&](T *v, int kk) {
+        const long long c = ((long long)kk * ny + j) * nx + i;
+        for (int b = 0; b < 3; ++b)
+            v[b] = live ? Nbuf[(size_t)b * N + c] : T(0);
+    };
+    T Np[3], Nq[3] = {0, 0, 0};
+    load_plane(z_dn(k0));
+    store_plane(slot(k0 - 1));
+    load_plane(k0);
+    store_plane(slot(k0));
+    load_plane(z_up(k0));
+    own_n(Np, k0);
+    const bool in_xm = F.periodic[0] || i > 0, in_xp = F.periodic[0] || i + 1 < nx;
+    const bool in_ym = F.periodic[1] || j > 0, in_yp = F.periodic[1] || j + 1 < ny;
+    for (int k = k0; k < k1; ++k) {
+        store_plane(slot(k + 1));
         __syncthreads();
-        const bool has_up = k + 1 < nz, has_dn = k > 0;
-        // the plane above at this cell first (needed now), then the prefetch
-        if (live)
-            for (int q = 0; q < 4; ++q)
-                zn[q] = has_up ? at(q, i, j, k + 1) : (F.periodic[2] ? z0[q] : 0.0);
-        if (has_up)
-            load_plane(k + 1);
-        if (!live)
-            continue;
-        const bool in_xm = F.periodic[0] || i > 0, in_xp = F.periodic[0] || i + 1 < nx;
-        const bool in_ym = F.periodic[1] || j > 0, in_yp = F.periodic[1] || j + 1 < ny;
-        const bool in_zm = F.periodic[2] || has_dn, in_zp = F.periodic[2] || has_up;
-        const long long c = ((long long)k * ny + j) * nx + i;
-        double ua[3];
-        for (int q = 0; q < 3; ++q)
-            ua[q] = zc[q];
-        for (int b = 0; b < 3; ++b) {
-            // neighbours of component b along x, y, z (no-slip ghost -u behind a wall)
-            const double ub = ua[b];
-            const double nbr[3][2] = {
-                {in_xp ? tile[b][ty + 1][tx + 2] : -ub, in_xm ? tile[b][ty + 1][tx] : -ub},
-                {in_yp ? tile[b][ty + 2][tx + 1] : -ub, in_ym ? tile[b][ty][tx + 1] : -ub},
-                {in_zp ? zn[b] : -ub, in_zm ? zp[b] : -ub}};
-            double lap = 0.0, adv = 0.0;
-            for (int a = 0; a < 3; ++a) {
-                const double up = nbr[a][0], dn = nbr[a][1];
-                lap = lap + (up - 2.0 * ub + dn) / (F.h * F.h);
-                adv = adv + ua[a] * ((up - dn) / (2.0 * F.h));
-            }
-            // pressure gradient along b: mean of the two face gradients
-            const double pc = zc[3];
-            double pp, pm;
-            bool hp, hm;
-            if (b == 0) {
-                pp = tile[3][ty + 1][tx + 2], pm = tile[3][ty + 1][tx], hp = in_xp, hm = in_xm;
-            } else if (b == 1) {
-                pp = tile[3][ty + 2][tx + 1], pm = tile[3][ty][tx + 1], hp = in_yp, hm = in_ym;
-            } else {
-                pp = zn[3], pm = zp[3], hp = in_zp, hm = in_zm;
-            }
-            const double gp = hp ? (pp - pc) / F.h : 0.0;
-            const double gm = hm ? (pc - pm) / F.h : 0.0;
-            const double gP = 0.5 * (gp + gm);
-            const size_t ib = (size_t)b * N + c;
-            const double ln = F.nu * lap;
-            const double Np = (double)Nbuf[ib];
-            ut[ib] = (T)(ub + dt * (2.0 * alpha * ln - 2.0 * alpha * gP - gamma * adv - zeta * Np));
-            Nbuf[ib] = (T)adv;
-            lapnu[ib] = (T)ln;
+        if (k + 1 < k1) {
+            load_plane(z_up(k + 1));
+            own_n(Nq, k + 1);
         }
-        for (int q = 0; q < 4; ++q) {
-            zp[q] = zc[q];
-            zc[q] = zn[q];
+        if (live) {
+            const bool in_zm = z_dn(k) >= 0, in_zp = z_up(k) >= 0;
+            const int sd = slot(k - 1), sc = slot(k), su = slot(k + 1);
+            const long long c = ((long long)k * ny + j) * nx + i;
+            double ua[3];
+            for (int q = 0; q < 3; ++q)
+                ua[q] = (double)tile[sc][q][ty + 1][tx + 1];
+            for (int b = 0; b < 3; ++b) {
+                // neighbours of component b along x, y, z (no-slip ghost -u
+                // behind a wall)
+                const double ub = ua[b];
+                const double nbr[3][2] = {
+                    {in_xp ? (double)tile[sc][b][ty + 1][tx + 2] : -ub,
+                     in_xm ? (double)tile[sc][b][ty + 1][tx] : -ub},
+                    {in_yp ? (double)tile[sc][b][ty + 2][tx + 1] : -ub,
+                     in_ym ? (double)tile[sc][b][ty][tx + 1] : -ub},
+                    {in_zp ? (double)tile[su][b][ty + 1][tx + 1] : -ub,
+                     in_zm ? (double)tile[sd][b][ty + 1][tx + 1] : -ub}};
+                double lap = 0.0, adv = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    const double up = nbr[a][0], dn = nbr[a][1];
+                    lap = lap + (up - 2.0 * ub + dn) / (F.h * F.h);
+                    adv = adv + ua[a] * ((up - dn) / (2.0 * F.h));
+                }
+                // pressure gradient along b: mean of the two face gradients
+                const double pc = (double)tile[sc][3][ty + 1][tx + 1];
+                double pp, pm;
+                bool hp, hm;
+                if (b == 0) {
+                    pp = tile[sc][3][ty + 1][tx + 2], pm = tile[sc][3][ty + 1][tx];
+                    hp = in_xp, hm = in_xm;
+                } else if (b == 1) {
+                    pp = tile[sc][3][ty + 2][tx + 1], pm = tile[sc][3][ty][tx + 1];
+                    hp = in_yp, hm = in_ym;
+                } else {
+                    pp = tile[su][3][ty + 1][tx + 1], pm = tile[sd][3][ty + 1][tx + 1];
+                    hp = in_zp, hm = in_zm;
+                }
+                const double gp = hp ? (pp - pc) / F.h : 0.0;
+                const double gm = hm ? (pc - pm) / F.h : 0.0;
+                const double gP = 0.5 * (gp + gm);
+                const size_t ib = (size_t)b * N + c;
+                const double ln = F.nu * lap;
+                ut[ib] = (T)(ub + dt * (2.0 * alpha * ln - 2.0 * alpha * gP - gamma * adv -
+                                        zeta * (double)Np[b]));
+                Nbuf[ib] = (T)adv;
+                lapnu[ib] = (T)ln;
+            }
         }
+        for (int b = 0; b < 3; ++b)
+            Np[b] = Nq[b];
     }
 }
 
@@ -648,7 +662,9 @@ ibmx_status run_predict(ibmx_plan p, const T *u, T *ut, T *Nbuf, T *lapnu, const
     const FluidC F = fluid_constants(p, 0.0);
     const double alpha = F.c / (2.0 * dt);
     ProfScope ps(p, IBMX_K_OTHER);
-    hipLaunchKernelGGL((k_predict<T>), dim3((F.n[0] + PX - 1) / PX, (F.n[1] + PY - 1) / PY),
+    hipLaunchKernelGGL((k_predict<T>),
+                       dim3((F.n[0] + PX - 1) / PX, (F.n[1] + PY - 1) / PY,
+                            (F.n[2] + kPlanes - 1) / kPlanes),
                        dim3(PX * PY), 0, p->stream, F,
                        u, ut, Nbuf, lapnu, P, dt, alpha, gamma, zeta);
     return ibmx_launch_check();

@@ -170,6 +170,42 @@ def test_predictor_helmholtz_parity(n, periodic, precision):
     plan.close()
 
 
+@pytest.mark.parametrize("n,periodic", [((20, 9, 67), (1, 1, 1)), ((70, 7, 70), (0, 1, 0)),
+                                        ((8, 8, 64), (1, 0, 1)), ((3, 2, 33), (0, 0, 0))])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_predictor_parity_ragged(n, periodic, precision):
+    """Step a alone on grids whose columns and z runs do not divide the
+    kernel's blocking (ragged x and y edges, several runs of planes with a
+    ragged last one), with walls on any axis."""
+    import torch
+    from oracle import fluid_stage as fs
+    dev = require_gpu()
+    T = torch.float64 if precision == "f64" else torch.float32
+    shape = (n[2], n[1], n[0])
+    u0, Np, P, _ = _stage_inputs(shape, 7 + sum(n))
+    if precision == "f32":
+        u0, Np, P = (a.astype(np.float32).astype(np.float64) for a in (u0, Np, P))
+    alpha, gamma, zeta, dt = 4.0 / 15.0, 8.0 / 15.0, -17.0 / 60.0, 0.7
+    case = _case(n, periodic, seed=1)
+    prm = dict(case.params)
+    prm["c"] = 2.0 * alpha * dt
+    prm["nu_f"] = 0.2
+    case.params = prm
+    ref = fs.predictor(u0, Np, P, case.h, prm["nu_f"], alpha, gamma, zeta, dt, periodic)
+    plan = ibmx.Plan.from_case(case, precision)
+    tu = lambda a: torch.as_tensor(a).to(dev).to(T).contiguous()
+    u_d, N_d, P_d = tu(u0), tu(Np), tu(P)
+    ut, lapnu = plan.fluid_predictor(u_d, N_d, P_d, dt, gamma, zeta)
+    plan.check("predictor")
+    torch.cuda.synchronize()
+    tol = 1e-12 if precision == "f64" else 2e-6
+    for k, got in (("u", ut), ("N", N_d), ("lapnu", lapnu)):
+        e = rel_err(got.double().cpu().numpy(), ref[k])
+        assert e <= tol, f"predictor {k}: {e:.3e}"
+    assert torch.equal(u_d, tu(u0))
+    plan.close()
+
+
 @pytest.mark.parametrize("theta", [0.0, 1.0])
 def test_full_stage_chain(theta):
     """One Runge-Kutta stage of the collocated solver end to end (eq.
