@@ -93,18 +93,19 @@ def fluid_bytes(kind: str, s: int, nodes: int, walls_z: bool = True) -> float:
            way: 40) or along a periodic z two more passes and the division (48).
     predictor: reads u, N (3s each) and P (s); writes u~, N and nu L u (3s each).
     project: face values and divergence (reads 3s, writes 3s + 8), the solve,
-           the correction (reads the solution, u, u_f, P; writes u, u_f, P,
-           phi: 8 + 15s).
-    helmholtz: per component the right-hand side (reads 3s, writes 8), the
-           solve and the result (reads 8, writes s).
+           the correction (reads the solution, u, u_f, P; writes u, u_f, P:
+           8 + 14s; phi is not asked for).
+    helmholtz (theta = 0, no pressure term): per component the right-hand
+           side (reads u and nu L u: 2s, writes 8), the solve and the result
+           (reads 8, writes s).
     """
     solve = 16 + 16 + 16 + 16 + (40 if walls_z else 48)
     if kind == "predictor":
         per = 16 * s
     elif kind == "project":
-        per = (6 * s + 8) + solve + (8 + 15 * s)
+        per = (6 * s + 8) + solve + (8 + 14 * s)
     elif kind == "helmholtz":
-        per = 3 * ((3 * s + 8) + solve + (8 + s))
+        per = 3 * ((2 * s + 8) + solve + (8 + s))
     else:
         raise KeyError(kind)
     return float(per) * nodes

@@ -34,38 +34,144 @@ __device__ __forceinline__ long long cell_index(const FluidC &F, int i, int j, i
     return ((long long)k * F.n[1] + j) * F.n[0] + i;
 }
 
-// neighbour index along axis a (d = +1 / -1); -1 past a wall
-__device__ __forceinline__ long long neighbour(const FluidC &F, int i, int j, int k, int a, int d)
+// Stencil kernels that need neighbours in all three axes march a PX x PY
+// column of cells up in z over a run of kPlanes planes.  The fields' planes,
+// with a one-cell rim for the x and y neighbours, pass through a ring of
+// kRing planes in LDS: plane k + 1 is stored, then, while plane k is
+// computed from planes k - 1, k and k + 1, plane k + 2 is loaded into
+// registers, so each value is read from memory about once (a run adds one
+// plane at each end).  With four slots the store of plane k + 1 cannot meet
+// a read of the slot it reuses (last read while computing plane k - 2), so
+// one barrier per plane suffices.
+constexpr int PX = 64, PY = 4, kPlanes = 32, kRing = 4;
+
+// plane above / below kk, -1 behind a wall
+__device__ __forceinline__ int z_up(const FluidC &F, int kk)
 {
-    int q[3] = {i, j, k};
-    q[a] += d;
-    if (q[a] < 0 || q[a] >= F.n[a]) {
-        if (!F.periodic[a])
-            return -1;
-        q[a] = q[a] < 0 ? q[a] + F.n[a] : q[a] - F.n[a];
+    return kk + 1 < F.n[2] ? kk + 1 : (F.periodic[2] ? 0 : -1);
+}
+__device__ __forceinline__ int z_dn(const FluidC &F, int kk)
+{
+    return kk > 0 ? kk - 1 : (F.periodic[2] ? F.n[2] - 1 : -1);
+}
+
+struct Column {
+    int tx, ty, i0, j0, k0, k1, i, j;
+    bool live;
+    bool in_p[2], in_m[2];   // x and y neighbours inside the grid (or periodic)
+    __device__ explicit Column(const FluidC &F)
+    {
+        tx = threadIdx.x % PX, ty = threadIdx.x / PX;
+        i0 = blockIdx.x * PX, j0 = blockIdx.y * PY;
+        k0 = blockIdx.z * kPlanes, k1 = min(F.n[2], k0 + kPlanes);
+        i = i0 + tx, j = j0 + ty;
+        live = i < F.n[0] && j < F.n[1];
+        in_m[0] = F.periodic[0] || i > 0, in_p[0] = F.periodic[0] || i + 1 < F.n[0];
+        in_m[1] = F.periodic[1] || j > 0, in_p[1] = F.periodic[1] || j + 1 < F.n[1];
     }
-    return cell_index(F, q[0], q[1], q[2]);
+    // ring slot of plane kk (kk >= k0 - 1)
+    __device__ int slot(int kk) const { return (kk - k0 + 1) & (kRing - 1); }
+};
+
+// NF fields of one rim-extended plane, in registers between the load from
+// memory and the store into a ring slot; zeros outside the grid (kk < 0 is
+// the plane behind a wall)
+template <typename T, int NF>
+struct PlaneStage {
+    static constexpr int kSlots = (PY + 2) * (PX + 2), kPre = (kSlots + PX * PY - 1) / (PX * PY);
+    T pre[kPre][NF];
+    __device__ void load(const FluidC &F, const T *const *fld, const Column &col, int kk)
+    {
+        const int nx = F.n[0], ny = F.n[1];
+        for (int r = 0; r < kPre; ++r) {
+            const int e = threadIdx.x + r * PX * PY;
+            if (e >= kSlots)
+                break;
+            const int ry = e / (PX + 2), rx = e % (PX + 2);
+            int gi = col.i0 + rx - 1, gj = col.j0 + ry - 1;
+            if (F.periodic[0])
+                gi = gi < 0 ? gi + nx : (gi >= nx ? gi - nx : gi);
+            if (F.periodic[1])
+                gj = gj < 0 ? gj + ny : (gj >= ny ? gj - ny : gj);
+            const bool in = kk >= 0 && gi >= 0 && gi < nx && gj >= 0 && gj < ny;
+            const long long o = ((long long)kk * ny + gj) * nx + gi;
+            for (int q = 0; q < NF; ++q)
+                pre[r][q] = in ? fld[q][o] : T(0);
+        }
+    }
+    __device__ void store(T (*ring)[NF][PY + 2][PX + 2], int sl) const
+    {
+        for (int r = 0; r < kPre; ++r) {
+            const int e = threadIdx.x + r * PX * PY;
+            if (e >= kSlots)
+                break;
+            const int ry = e / (PX + 2), rx = e % (PX + 2);
+            for (int q = 0; q < NF; ++q)
+                ring[sl][q][ry][rx] = pre[r][q];
+        }
+    }
+    // fill slots of planes k0 - 1 and k0, leave plane k0 + 1 in registers
+    __device__ void prologue(const FluidC &F, const T *const *fld, const Column &col,
+                             T (*ring)[NF][PY + 2][PX + 2])
+    {
+        load(F, fld, col, z_dn(F, col.k0));
+        store(ring, col.slot(col.k0 - 1));
+        load(F, fld, col, col.k0);
+        store(ring, col.slot(col.k0));
+        load(F, fld, col, z_up(F, col.k0));
+    }
+};
+
+// the value of field q at the own cell's neighbour along axis a (d = +1 /
+// -1) from the ring (sd, sc, su: slots of planes k - 1, k, k + 1)
+template <typename T, int NF>
+__device__ __forceinline__ T ring_nb(const T (*ring)[NF][PY + 2][PX + 2], const Column &col,
+                                     int sd, int sc, int su, int q, int a, int d)
+{
+    if (a == 0)
+        return ring[sc][q][col.ty + 1][col.tx + 1 + d];
+    if (a == 1)
+        return ring[sc][q][col.ty + 1 + d][col.tx + 1];
+    return ring[d > 0 ? su : sd][q][col.ty + 1][col.tx + 1];
+}
+
+dim3 column_grid(const FluidC &F)
+{
+    return dim3((F.n[0] + PX - 1) / PX, (F.n[1] + PY - 1) / PY, (F.n[2] + kPlanes - 1) / kPlanes);
 }
 
 // u_f* = mean of the two cells of each +a face (wall faces 0), and the
 // right-hand side div(u_f*) / c
 template <typename T>
-__global__ __launch_bounds__(256) void k_face_div(FluidC F, const T *__restrict__ u,
-                                                  T *__restrict__ uf, double *__restrict__ R)
+__global__ __launch_bounds__(PX * PY) void k_face_div(FluidC F, const T *__restrict__ u,
+                                                      T *__restrict__ uf, double *__restrict__ R)
 {
+    __shared__ T ring[kRing][3][PY + 2][PX + 2];
     const long long N = (long long)F.n[0] * F.n[1] * F.n[2];
-    {
-        const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
-        if (i >= F.n[0])
-            return;
-        const long long c = cell_index(F, i, j, k);
+    const Column col(F);
+    const T *fld[3] = {u, u + N, u + 2 * N};
+    PlaneStage<T, 3> st;
+    st.prologue(F, fld, col, ring);
+    for (int k = col.k0; k < col.k1; ++k) {
+        st.store(ring, col.slot(k + 1));
+        __syncthreads();
+        if (k + 1 < col.k1)
+            st.load(F, fld, col, z_up(F, k + 1));
+        if (!col.live)
+            continue;
+        const int sd = col.slot(k - 1), sc = col.slot(k), su = col.slot(k + 1);
+        const bool in_p[3] = {col.in_p[0], col.in_p[1], z_up(F, k) >= 0};
+        const bool in_m[3] = {col.in_m[0], col.in_m[1], z_dn(F, k) >= 0};
+        const long long c = cell_index(F, col.i, col.j, k);
         double div = 0.0;
         for (int a = 0; a < 3; ++a) {
-            const T *ua = u + (size_t)a * N;
-            const double uc = (double)ua[c];
-            const long long up = neighbour(F, i, j, k, a, 1), dn = neighbour(F, i, j, k, a, -1);
-            const double out = up >= 0 ? 0.5 * (uc + (double)ua[up]) : 0.0;
-            const double in = dn >= 0 ? 0.5 * ((double)ua[dn] + uc) : 0.0;
+            const double uc = (double)ring[sc][a][col.ty + 1][col.tx + 1];
+            const double out =
+                in_p[a] ? 0.5 * (uc + (double)ring_nb<T, 3>(ring, col, sd, sc, su, a, a, 1))
+                        : 0.0;
+            const double in =
+                in_m[a] ? 0.5 * ((double)ring_nb<T, 3>(ring, col, sd, sc, su, a, a, -1) + uc)
+                        : 0.0;
             uf[(size_t)a * N + c] = (T)out;
             div = div + (out - in) / F.h;
         }
@@ -322,70 +428,71 @@ __global__ __launch_bounds__(256) void k_tridiag(FluidC F, double s0, double s1,
 
 // phi = R * scale; u = u* - c grad(phi) (mean of the cell's two face
 // gradients), u_f = u_f* - c (phi_+ - phi)/h, P = (1 - theta) P + phi -
-// (c/2) nu L phi
+// (c/2) nu L phi.  phi passes through the plane ring; the own cell's u,
+// u_f and P of the next plane are loaded while a plane is computed.
 template <typename T>
-__global__ __launch_bounds__(256) void k_correct(FluidC F, const double *__restrict__ Z,
-                                                 double scale, T *__restrict__ u,
-                                                 T *__restrict__ uf, T *__restrict__ P,
-                                                 T *__restrict__ phi_out)
+__global__ __launch_bounds__(PX * PY) void k_correct(FluidC F, const double *__restrict__ Z,
+                                                     double scale, T *__restrict__ u,
+                                                     T *__restrict__ uf, T *__restrict__ P,
+                                                     T *__restrict__ phi_out)
 {
+    __shared__ double ring[kRing][1][PY + 2][PX + 2];
     const long long N = (long long)F.n[0] * F.n[1] * F.n[2];
-    {
-        const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
-        if (i >= F.n[0])
-            return;
-        const long long c = cell_index(F, i, j, k);
-        const double ph = Z[c] * scale;
-        double lap = 0.0;
+    const Column col(F);
+    const double *fld[1] = {Z};
+    PlaneStage<double, 1> st;
+    st.prologue(F, fld, col, ring);
+    // own u (3), u_f (3) and P of plane kk
+    auto own = [&](T *v, int kk) {
+        const long long c = cell_index(F, col.i, col.j, kk);
         for (int a = 0; a < 3; ++a) {
-            const long long up = neighbour(F, i, j, k, a, 1), dn = neighbour(F, i, j, k, a, -1);
-            const double gp = up >= 0 ? (Z[up] * scale - ph) / F.h : 0.0;
-            const double gm = dn >= 0 ? (ph - Z[dn] * scale) / F.h : 0.0;
-            const size_t ia = (size_t)a * N + c;
-            u[ia] = (T)((double)u[ia] - F.c * (0.5 * (gp + gm)));
-            uf[ia] = (T)((double)uf[ia] - F.c * gp);
-            lap = lap + (gp - gm) / F.h;
+            v[a] = col.live ? u[(size_t)a * N + c] : T(0);
+            v[3 + a] = col.live ? uf[(size_t)a * N + c] : T(0);
         }
-        P[c] = (T)((1.0 - F.theta) * (double)P[c] + ph - 0.5 * F.c * F.nu * lap);
-        if (phi_out)
-            phi_out[c] = (T)ph;
+        v[6] = col.live ? P[c] : T(0);
+    };
+    T ow[7], oq[7] = {0, 0, 0, 0, 0, 0, 0};
+    own(ow, col.k0);
+    for (int k = col.k0; k < col.k1; ++k) {
+        st.store(ring, col.slot(k + 1));
+        __syncthreads();
+        if (k + 1 < col.k1) {
+            st.load(F, fld, col, z_up(F, k + 1));
+            own(oq, k + 1);
+        }
+        if (col.live) {
+            const int sd = col.slot(k - 1), sc = col.slot(k), su = col.slot(k + 1);
+            const bool in_p[3] = {col.in_p[0], col.in_p[1], z_up(F, k) >= 0};
+            const bool in_m[3] = {col.in_m[0], col.in_m[1], z_dn(F, k) >= 0};
+            const long long c = cell_index(F, col.i, col.j, k);
+            const double ph = ring[sc][0][col.ty + 1][col.tx + 1] * scale;
+            double lap = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                const double gp =
+                    in_p[a] ? (ring_nb<double, 1>(ring, col, sd, sc, su, 0, a, 1) * scale - ph) / F.h
+                            : 0.0;
+                const double gm =
+                    in_m[a] ? (ph - ring_nb<double, 1>(ring, col, sd, sc, su, 0, a, -1) * scale) / F.h
+                            : 0.0;
+                const size_t ia = (size_t)a * N + c;
+                u[ia] = (T)((double)ow[a] - F.c * (0.5 * (gp + gm)));
+                uf[ia] = (T)((double)ow[3 + a] - F.c * gp);
+                lap = lap + (gp - gm) / F.h;
+            }
+            P[c] = (T)((1.0 - F.theta) * (double)ow[6] + ph - 0.5 * F.c * F.nu * lap);
+            if (phi_out)
+                phi_out[c] = (T)ph;
+        }
+        for (int q = 0; q < 7; ++q)
+            ow[q] = oq[q];
     }
-}
-
-// value of field f at the neighbour (d = +1 / -1 along axis a) of cell c:
-// behind a wall the no-slip ghost -f(c)
-template <typename T>
-__device__ __forceinline__ double nb_noslip(const FluidC &F, const T *f, long long c, int i, int j,
-                                            int k, int a, int d)
-{
-    const long long q = neighbour(F, i, j, k, a, d);
-    return q >= 0 ? (double)f[q] : -(double)f[c];
-}
-
-// mean of the two face gradients of P along axis a (zero on wall faces)
-template <typename T>
-__device__ __forceinline__ double cell_grad(const FluidC &F, const T *P, long long c, int i, int j,
-                                            int k, int a)
-{
-    const double pc = (double)P[c];
-    const long long up = neighbour(F, i, j, k, a, 1), dn = neighbour(F, i, j, k, a, -1);
-    const double gp = up >= 0 ? ((double)P[up] - pc) / F.h : 0.0;
-    const double gm = dn >= 0 ? (pc - (double)P[dn]) / F.h : 0.0;
-    return 0.5 * (gp + gm);
 }
 
 // step a: u~ = u + dt (2 alpha nu L u - 2 alpha grad P - gamma N - zeta N_prev),
 // N = (u . grad) u; N holds N_prev on entry and N on exit, lapnu = nu L u.
-// A workgroup takes a PX x PY column of cells over a run of kPlanes planes
-// and marches it up in z.  Each plane of u and P, with a one-cell rim for the
-// x and y neighbours, goes through a ring of kRing planes in LDS: while plane
-// k is computed from planes k - 1, k and k + 1, plane k + 2 is loaded into
-// registers (and N_prev of plane k + 1), so each value is read from memory
-// about once (a run adds one plane at each end).  With four slots the store
-// of plane k + 1 cannot meet a read of the slot it reuses (last read while
-// computing plane k - 2), so one barrier per plane suffices.
-constexpr int PX = 64, PY = 4, kPlanes = 32, kRing = 4;
-
+// u and P pass through the plane ring (values held in T, widened to double
+// where they are used); N_prev of the next plane is loaded while a plane is
+// computed.
 template <typename T>
 __global__ __launch_bounds__(PX * PY) void k_predict(FluidC F, const T *__restrict__ u,
                                                      T *__restrict__ ut, T *__restrict__ Nbuf,
@@ -393,113 +500,55 @@ __global__ __launch_bounds__(PX * PY) void k_predict(FluidC F, const T *__restri
                                                      const T *__restrict__ P, double dt,
                                                      double alpha, double gamma, double zeta)
 {
-    // values are held in T and widened to double where they are used
-    __shared__ T tile[kRing][4][PY + 2][PX + 2];
+    __shared__ T ring[kRing][4][PY + 2][PX + 2];
     const long long N = (long long)F.n[0] * F.n[1] * F.n[2];
-    const int nx = F.n[0], ny = F.n[1], nz = F.n[2];
-    const int tx = threadIdx.x % PX, ty = threadIdx.x / PX;
-    const int i0 = blockIdx.x * PX, j0 = blockIdx.y * PY;
-    const int k0 = blockIdx.z * kPlanes, k1 = min(nz, k0 + kPlanes);
-    const int i = i0 + tx, j = j0 + ty;
-    const bool live = i < nx && j < ny;
+    const Column col(F);
     const T *fld[4] = {u, u + N, u + 2 * N, P};
-    // plane above / below kk, -1 behind a wall
-    auto z_up = [&](int kk) { return kk + 1 < nz ? kk + 1 : (F.periodic[2] ? 0 : -1); };
-    auto z_dn = [&](int kk) { return kk > 0 ? kk - 1 : (F.periodic[2] ? nz - 1 : -1); };
-    // ring slot of plane kk (kk >= k0 - 1)
-    auto slot = [&](int kk) { return (kk - k0 + 1) & (kRing - 1); };
-    constexpr int kSlots = (PY + 2) * (PX + 2), kPre = (kSlots + PX * PY - 1) / (PX * PY);
-    T pre[kPre][4];
-    // the rim-extended plane kk into registers (zeros behind a wall, kk < 0)
-    auto load_plane = [&](int kk) {
-        for (int r = 0; r < kPre; ++r) {
-            const int e = threadIdx.x + r * PX * PY;
-            if (e >= kSlots)
-                break;
-            const int ry = e / (PX + 2), rx = e % (PX + 2);
-            int gi = i0 + rx - 1, gj = j0 + ry - 1;
-            if (F.periodic[0])
-                gi = gi < 0 ? gi + nx : (gi >= nx ? gi - nx : gi);
-            if (F.periodic[1])
-                gj = gj < 0 ? gj + ny : (gj >= ny ? gj - ny : gj);
-            const bool in = kk >= 0 && gi >= 0 && gi < nx && gj >= 0 && gj < ny;
-            const long long o = ((long long)kk * ny + gj) * nx + gi;
-            for (int q = 0; q < 4; ++q)
-                pre[r][q] = in ? fld[q][o] : T(0);
-        }
-    };
-    auto store_plane = [&](int sl) {
-        for (int r = 0; r < kPre; ++r) {
-            const int e = threadIdx.x + r * PX * PY;
-            if (e >= kSlots)
-                break;
-            const int ry = e / (PX + 2), rx = e % (PX + 2);
-            for (int q = 0; q < 4; ++q)
-                tile[sl][q][ry][rx] = pre[r][q];
-        }
-    };
+    PlaneStage<T, 4> st;
+    st.prologue(F, fld, col, ring);
     // N_prev of the own cell on plane kk
     auto own_n = [&](T *v, int kk) {
-        const long long c = ((long long)kk * ny + j) * nx + i;
+        const long long c = cell_index(F, col.i, col.j, kk);
         for (int b = 0; b < 3; ++b)
-            v[b] = live ? Nbuf[(size_t)b * N + c] : T(0);
+            v[b] = col.live ? Nbuf[(size_t)b * N + c] : T(0);
     };
     T Np[3], Nq[3] = {0, 0, 0};
-    load_plane(z_dn(k0));
-    store_plane(slot(k0 - 1));
-    load_plane(k0);
-    store_plane(slot(k0));
-    load_plane(z_up(k0));
-    own_n(Np, k0);
-    const bool in_xm = F.periodic[0] || i > 0, in_xp = F.periodic[0] || i + 1 < nx;
-    const bool in_ym = F.periodic[1] || j > 0, in_yp = F.periodic[1] || j + 1 < ny;
-    for (int k = k0; k < k1; ++k) {
-        store_plane(slot(k + 1));
+    own_n(Np, col.k0);
+    for (int k = col.k0; k < col.k1; ++k) {
+        st.store(ring, col.slot(k + 1));
         __syncthreads();
-        if (k + 1 < k1) {
-            load_plane(z_up(k + 1));
+        if (k + 1 < col.k1) {
+            st.load(F, fld, col, z_up(F, k + 1));
             own_n(Nq, k + 1);
         }
-        if (live) {
-            const bool in_zm = z_dn(k) >= 0, in_zp = z_up(k) >= 0;
-            const int sd = slot(k - 1), sc = slot(k), su = slot(k + 1);
-            const long long c = ((long long)k * ny + j) * nx + i;
+        if (col.live) {
+            const int sd = col.slot(k - 1), sc = col.slot(k), su = col.slot(k + 1);
+            const bool in_p[3] = {col.in_p[0], col.in_p[1], z_up(F, k) >= 0};
+            const bool in_m[3] = {col.in_m[0], col.in_m[1], z_dn(F, k) >= 0};
+            const long long c = cell_index(F, col.i, col.j, k);
             double ua[3];
             for (int q = 0; q < 3; ++q)
-                ua[q] = (double)tile[sc][q][ty + 1][tx + 1];
+                ua[q] = (double)ring[sc][q][col.ty + 1][col.tx + 1];
+            const double pc = (double)ring[sc][3][col.ty + 1][col.tx + 1];
             for (int b = 0; b < 3; ++b) {
-                // neighbours of component b along x, y, z (no-slip ghost -u
-                // behind a wall)
+                // neighbours of component b (no-slip ghost -u behind a wall)
                 const double ub = ua[b];
-                const double nbr[3][2] = {
-                    {in_xp ? (double)tile[sc][b][ty + 1][tx + 2] : -ub,
-                     in_xm ? (double)tile[sc][b][ty + 1][tx] : -ub},
-                    {in_yp ? (double)tile[sc][b][ty + 2][tx + 1] : -ub,
-                     in_ym ? (double)tile[sc][b][ty][tx + 1] : -ub},
-                    {in_zp ? (double)tile[su][b][ty + 1][tx + 1] : -ub,
-                     in_zm ? (double)tile[sd][b][ty + 1][tx + 1] : -ub}};
                 double lap = 0.0, adv = 0.0;
                 for (int a = 0; a < 3; ++a) {
-                    const double up = nbr[a][0], dn = nbr[a][1];
+                    const double up =
+                        in_p[a] ? (double)ring_nb<T, 4>(ring, col, sd, sc, su, b, a, 1) : -ub;
+                    const double dn =
+                        in_m[a] ? (double)ring_nb<T, 4>(ring, col, sd, sc, su, b, a, -1) : -ub;
                     lap = lap + (up - 2.0 * ub + dn) / (F.h * F.h);
                     adv = adv + ua[a] * ((up - dn) / (2.0 * F.h));
                 }
                 // pressure gradient along b: mean of the two face gradients
-                const double pc = (double)tile[sc][3][ty + 1][tx + 1];
-                double pp, pm;
-                bool hp, hm;
-                if (b == 0) {
-                    pp = tile[sc][3][ty + 1][tx + 2], pm = tile[sc][3][ty + 1][tx];
-                    hp = in_xp, hm = in_xm;
-                } else if (b == 1) {
-                    pp = tile[sc][3][ty + 2][tx + 1], pm = tile[sc][3][ty][tx + 1];
-                    hp = in_yp, hm = in_ym;
-                } else {
-                    pp = tile[su][3][ty + 1][tx + 1], pm = tile[sd][3][ty + 1][tx + 1];
-                    hp = in_zp, hm = in_zm;
-                }
-                const double gp = hp ? (pp - pc) / F.h : 0.0;
-                const double gm = hm ? (pc - pm) / F.h : 0.0;
+                const double gp =
+                    in_p[b] ? ((double)ring_nb<T, 4>(ring, col, sd, sc, su, 3, b, 1) - pc) / F.h
+                            : 0.0;
+                const double gm =
+                    in_m[b] ? (pc - (double)ring_nb<T, 4>(ring, col, sd, sc, su, 3, b, -1)) / F.h
+                            : 0.0;
                 const double gP = 0.5 * (gp + gm);
                 const size_t ib = (size_t)b * N + c;
                 const double ln = F.nu * lap;
@@ -515,23 +564,71 @@ __global__ __launch_bounds__(PX * PY) void k_predict(FluidC F, const T *__restri
 }
 
 // step e, component b: the right-hand side u_f - c fbar + dt (-alpha lapnu
-// + 2 alpha theta grad P) into R
+// + 2 alpha theta grad P) into R.  With theta = 0 the pressure term vanishes
+// and the kernel is elementwise (k_helm_rhs_local); otherwise P passes
+// through the plane ring and the own u_f and lapnu of the next plane are
+// loaded while a plane is computed.
 template <typename T>
-__global__ __launch_bounds__(256) void k_helm_rhs(FluidC F, const T *__restrict__ u,
-                                                  const T *__restrict__ lapnu,
-                                                  const T *__restrict__ P,
-                                                  const double *__restrict__ fbar, int b,
-                                                  double dt, double alpha, double *__restrict__ R)
+__global__ __launch_bounds__(256) void k_helm_rhs_local(long long N, const T *__restrict__ u,
+                                                        const T *__restrict__ lapnu,
+                                                        const double *__restrict__ fbar, int b,
+                                                        double c2, double dt, double alpha,
+                                                        double *__restrict__ R)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
-    if (i >= F.n[0])
-        return;
-    const long long N = (long long)F.n[0] * F.n[1] * F.n[2];
-    const long long c = cell_index(F, i, j, k);
     const double fb = fbar ? fbar[b] : 0.0;
-    const double gP = cell_grad(F, P, c, i, j, k, b);
-    R[c] = (double)u[(size_t)b * N + c] - F.c * fb +
-           dt * (-alpha * (double)lapnu[(size_t)b * N + c] + 2.0 * alpha * F.theta * gP);
+    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < N;
+         c += (long long)gridDim.x * blockDim.x)
+        R[c] = (double)u[c] - c2 * fb + dt * (-alpha * (double)lapnu[c]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(PX * PY) void k_helm_rhs(FluidC F, const T *__restrict__ u,
+                                                      const T *__restrict__ lapnu,
+                                                      const T *__restrict__ P,
+                                                      const double *__restrict__ fbar, int b,
+                                                      double dt, double alpha,
+                                                      double *__restrict__ R)
+{
+    __shared__ T ring[kRing][1][PY + 2][PX + 2];
+    const long long N = (long long)F.n[0] * F.n[1] * F.n[2];
+    const Column col(F);
+    const T *fld[1] = {P};
+    PlaneStage<T, 1> st;
+    st.prologue(F, fld, col, ring);
+    const T *ub = u + (size_t)b * N, *lb = lapnu + (size_t)b * N;
+    auto own = [&](T *v, int kk) {
+        const long long c = cell_index(F, col.i, col.j, kk);
+        v[0] = col.live ? ub[c] : T(0);
+        v[1] = col.live ? lb[c] : T(0);
+    };
+    const double fb = fbar ? fbar[b] : 0.0;
+    T ow[2], oq[2] = {0, 0};
+    own(ow, col.k0);
+    for (int k = col.k0; k < col.k1; ++k) {
+        st.store(ring, col.slot(k + 1));
+        __syncthreads();
+        if (k + 1 < col.k1) {
+            st.load(F, fld, col, z_up(F, k + 1));
+            own(oq, k + 1);
+        }
+        if (col.live) {
+            const int sd = col.slot(k - 1), sc = col.slot(k), su = col.slot(k + 1);
+            const bool hp = b < 2 ? col.in_p[b] : z_up(F, k) >= 0;
+            const bool hm = b < 2 ? col.in_m[b] : z_dn(F, k) >= 0;
+            const double pc = (double)ring[sc][0][col.ty + 1][col.tx + 1];
+            // mean of the two face gradients along b (zero on wall faces)
+            const double gp =
+                hp ? ((double)ring_nb<T, 1>(ring, col, sd, sc, su, 0, b, 1) - pc) / F.h : 0.0;
+            const double gm =
+                hm ? (pc - (double)ring_nb<T, 1>(ring, col, sd, sc, su, 0, b, -1)) / F.h : 0.0;
+            const double gP = 0.5 * (gp + gm);
+            R[cell_index(F, col.i, col.j, k)] =
+                (double)ow[0] - F.c * fb +
+                dt * (-alpha * (double)ow[1] + 2.0 * alpha * F.theta * gP);
+        }
+        ow[0] = oq[0];
+        ow[1] = oq[1];
+    }
 }
 
 // the solution R * scale into out
@@ -545,16 +642,6 @@ __global__ __launch_bounds__(256) void k_take(long long N, const double *__restr
 }
 
 int grid_blocks(long long n) { return (int)(n / 256 + 1 < 16384 ? n / 256 + 1 : 16384); }
-
-// one thread per cell: x along the block, y and z along the grid
-struct CellLaunch {
-    dim3 grid, block;
-};
-CellLaunch cells(const FluidC &F)
-{
-    const int bx = F.n[0] >= 256 ? 256 : ((F.n[0] + 63) / 64) * 64;
-    return CellLaunch{dim3((F.n[0] + bx - 1) / bx, F.n[1], F.n[2]), dim3(bx)};
-}
 
 bool pow2(int n) { return n >= 2 && (n & (n - 1)) == 0; }
 
@@ -647,10 +734,10 @@ ibmx_status run_project(ibmx_plan p, T *u, T *uf, T *P, T *phi, double theta)
     const FluidC F = fluid_constants(p, theta);
     hipStream_t s = p->stream;
     ProfScope ps(p, IBMX_K_OTHER);
-    hipLaunchKernelGGL((k_face_div<T>), cells(F).grid, cells(F).block, 0, s, F, (const T *)u, uf,
+    hipLaunchKernelGGL((k_face_div<T>), column_grid(F), dim3(PX * PY), 0, s, F, (const T *)u, uf,
                        p->fl_r);
     const double scale = solve_modes(p, F, 0.0, 1.0, 0, s);
-    hipLaunchKernelGGL((k_correct<T>), cells(F).grid, cells(F).block, 0, s, F,
+    hipLaunchKernelGGL((k_correct<T>), column_grid(F), dim3(PX * PY), 0, s, F,
                        (const double *)p->fl_r, scale, u, uf, P, phi);
     return ibmx_launch_check();
 }
@@ -662,10 +749,7 @@ ibmx_status run_predict(ibmx_plan p, const T *u, T *ut, T *Nbuf, T *lapnu, const
     const FluidC F = fluid_constants(p, 0.0);
     const double alpha = F.c / (2.0 * dt);
     ProfScope ps(p, IBMX_K_OTHER);
-    hipLaunchKernelGGL((k_predict<T>),
-                       dim3((F.n[0] + PX - 1) / PX, (F.n[1] + PY - 1) / PY,
-                            (F.n[2] + kPlanes - 1) / kPlanes),
-                       dim3(PX * PY), 0, p->stream, F,
+    hipLaunchKernelGGL((k_predict<T>), column_grid(F), dim3(PX * PY), 0, p->stream, F,
                        u, ut, Nbuf, lapnu, P, dt, alpha, gamma, zeta);
     return ibmx_launch_check();
 }
@@ -680,8 +764,13 @@ ibmx_status run_helmholtz(ibmx_plan p, T *u, const T *lapnu, const T *P, const d
     hipStream_t s = p->stream;
     ProfScope ps(p, IBMX_K_OTHER);
     for (int b = 0; b < 3; ++b) {
-        hipLaunchKernelGGL((k_helm_rhs<T>), cells(F).grid, cells(F).block, 0, s, F, (const T *)u,
-                           lapnu, P, fbar, b, dt, alpha, p->fl_r);
+        if (F.theta != 0.0)
+            hipLaunchKernelGGL((k_helm_rhs<T>), column_grid(F), dim3(PX * PY), 0, s, F,
+                               (const T *)u, lapnu, P, fbar, b, dt, alpha, p->fl_r);
+        else
+            hipLaunchKernelGGL((k_helm_rhs_local<T>), dim3(grid_blocks(N)), dim3(256), 0, s, N,
+                               (const T *)u + (size_t)b * N, lapnu + (size_t)b * N, fbar, b, F.c,
+                               dt, alpha, p->fl_r);
         const double scale = solve_modes(p, F, 1.0, -alpha * dt * F.nu, 1, s);
         hipLaunchKernelGGL((k_take<T>), dim3(grid_blocks(N)), dim3(256), 0, s, N,
                            (const double *)p->fl_r, scale, u + (size_t)b * N);

@@ -39,7 +39,7 @@ def _run(case, precision, u_np, P_np, theta):
 
 @pytest.mark.parametrize("n,periodic", [((16, 8, 8), (1, 1, 1)), ((32, 16, 13), (1, 1, 0)),
                                         ((8, 32, 1), (1, 1, 0)), ((8, 8, 64), (1, 1, 1)),
-                                        ((64, 32, 20), (1, 1, 0))])
+                                        ((64, 32, 20), (1, 1, 0)), ((16, 8, 70), (1, 1, 0))])
 @pytest.mark.parametrize("theta", [0.0, 1.0])
 def test_projection_parity_f64(n, periodic, theta):
     case = _case(n, periodic, seed=sum(n))
@@ -122,9 +122,11 @@ def _stage_inputs(shape, seed):
 
 
 @pytest.mark.parametrize("n,periodic", [((16, 8, 8), (1, 1, 1)), ((32, 16, 13), (1, 1, 0)),
-                                        ((8, 32, 1), (1, 1, 0)), ((64, 32, 20), (1, 1, 0))])
+                                        ((8, 32, 1), (1, 1, 0)), ((64, 32, 20), (1, 1, 0)),
+                                        ((16, 8, 70), (1, 1, 0))])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-def test_predictor_helmholtz_parity(n, periodic, precision):
+@pytest.mark.parametrize("theta", [0.0, 1.0])
+def test_predictor_helmholtz_parity(n, periodic, precision, theta):
     """Steps a and e of one stage (alpha, gamma, zeta of the second RK stage)
     against the oracle; the forcing between them is stood in for by an
     arbitrary increment of u~."""
@@ -143,7 +145,6 @@ def test_predictor_helmholtz_parity(n, periodic, precision):
     prm["nu_f"] = 0.3
     case.params = prm
     fbar = np.array([0.05, -0.02, 0.01]) if all(periodic) else None
-    theta = 1.0
     ref_a = fs.predictor(u0, Np, P, case.h, prm["nu_f"], alpha, gamma, zeta, dt, periodic)
     plan = ibmx.Plan.from_case(case, precision)
     tu = lambda a: torch.as_tensor(a).to(dev).to(T).contiguous()
