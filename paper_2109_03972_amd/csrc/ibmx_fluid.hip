@@ -8,9 +8,11 @@
 // FP64 for a real right-hand side: a real-to-complex FFT along x (the
 // nx/2 + 1 modes of each row), complex FFTs along y (and z when periodic,
 // then a division by the eigenvalues), or per (kx, ky) mode a tridiagonal
-// elimination across the walls in z.  FFTs are radix-2 passes in place in
-// LDS, several short lines per workgroup, loaded so that each wave reads
-// contiguous memory.  Stencil kernels take one thread per cell with x along
+// elimination across the walls in z.  The half spectrum is stored with y
+// fastest, mode (kx, y, z) at (z (nx/2 + 1) + kx) ny + y, so that the y
+// passes read whole contiguous lines and the x passes, taking 8 or more
+// consecutive rows per workgroup, read and write runs of consecutive y.  FFTs
+// are radix-2 passes in place in LDS, several lines per workgroup.  Stencil kernels take one thread per cell with x along
 // the block and y, z along the grid.
 #include <math.h>
 #include <vector>
@@ -21,6 +23,7 @@ namespace {
 
 constexpr int kFftThreads = 256;
 constexpr int kRowElems = 256;      // complex elements per workgroup in the x passes
+constexpr int kMinRows = 8;         // and at least this many rows
 constexpr int kFftElemsStrided = 2048;   // strided lines: 32 KB of LDS, 4 lines of 512
 
 struct FluidC {
@@ -193,12 +196,13 @@ __device__ __forceinline__ int log2i_dev(int n)
 }
 
 // In-place complex FFT of `lines` lines of length n = 2^logn held in LDS in
-// bit-reversed order: iterative radix-2 Cooley-Tukey, two stages per pass
-// (the four elements i, i + half, i + len, i + len + half close under both
-// stages), a last single stage when logn is odd.  w(m) = tw[m * ts] =
-// exp(-2 pi i m / n); INV uses the conjugate (no 1/n scaling).
+// bit-reversed order, line l at buf + l * ls: iterative radix-2 Cooley-Tukey,
+// two stages per pass (the four elements i, i + half, i + len, i + len + half
+// close under both stages), a last single stage when logn is odd.  w(m) =
+// tw[m * ts] = exp(-2 pi i m / n); INV uses the conjugate (no 1/n scaling).
 template <bool INV>
-__device__ void fft_lds(double2 *buf, int n, int lines, const double2 *__restrict__ tw, int ts)
+__device__ void fft_lds(double2 *buf, int n, int ls, int lines, const double2 *__restrict__ tw,
+                        int ts)
 {
     const int half_n = n / 2;
     auto w = [&](int m) {
@@ -212,7 +216,7 @@ __device__ void fft_lds(double2 *buf, int n, int lines, const double2 *__restric
         const int half = len >> 1, quarter_n = n / 4;
         for (int b = threadIdx.x; b < lines * quarter_n; b += blockDim.x) {
             const int l = b / quarter_n, q = b % quarter_n, pos = q % half;
-            const int i0 = l * n + (q / half) * (2 * len) + pos;
+            const int i0 = l * ls + (q / half) * (2 * len) + pos;
             const double2 w1 = w(pos * (n / len)), w2 = w(pos * (n / (2 * len))),
                           w3 = w((pos + half) * (n / (2 * len)));
             const double2 a0 = buf[i0], a1 = cmul(buf[i0 + half], w1);
@@ -233,7 +237,7 @@ __device__ void fft_lds(double2 *buf, int n, int lines, const double2 *__restric
         const int half = len >> 1;
         for (int b = threadIdx.x; b < lines * half_n; b += blockDim.x) {
             const int l = b / half_n, jj = b % half_n, pos = jj % half;
-            const int i0 = l * n + (jj / half) * len + pos, i1 = i0 + half;
+            const int i0 = l * ls + (jj / half) * len + pos, i1 = i0 + half;
             const double2 wk = w(pos * (n / len));
             const double2 v0 = buf[i0], v1 = cmul(buf[i1], wk);
             buf[i0] = make_double2(v0.x + v1.x, v0.y + v1.y);
@@ -251,69 +255,97 @@ __device__ __forceinline__ int bitrev(int s, int logn)
 // Real-to-complex transform of rows along x (nx = 2 N2): each row's values
 // r[2m] + i r[2m + 1] form N2 complex values whose FFT Z gives the row's
 // modes X[k] = (Z[k] + Z*[N2 - k])/2 - i w^k (Z[k] - Z*[N2 - k])/2, k = 0..N2,
-// w = exp(-2 pi i / nx); H holds N2 + 1 modes per row.  `rows` rows per
-// workgroup.
+// w = exp(-2 pi i / nx).  `rows` consecutive rows per workgroup (row r = z ny
+// + y), held in LDS with a stride of N2 + 1; the modes go out y-fastest, mode
+// k of row r at (z mx + k) ny + y, consecutive threads taking consecutive
+// rows.
 __global__ __launch_bounds__(kFftThreads) void k_rfft_x(const double *__restrict__ R,
-                                                        double2 *__restrict__ H, int nx, int rows,
-                                                        long long nrows,
+                                                        double2 *__restrict__ H, int nx,
+                                                        int logny, int rows, long long nrows,
                                                         const double2 *__restrict__ tw)
 {
     extern __shared__ double2 buf[];
-    const int N2 = nx / 2, logn = log2i_dev(N2), mx = N2 + 1;
+    const int N2 = nx / 2, logn = log2i_dev(N2), mx = N2 + 1, ls = N2 + 1;
     const long long row0 = (long long)blockIdx.x * rows;
     const int nr = (int)(nrows - row0 < rows ? nrows - row0 : rows);
+    const long long ymask = (1LL << logny) - 1;
     const double2 *Rc = reinterpret_cast<const double2 *>(R);
     for (int e = threadIdx.x; e < nr * N2; e += blockDim.x) {
-        const int l = e / N2, m = e % N2;
-        buf[l * N2 + bitrev(m, logn)] = Rc[(row0 + l) * N2 + m];
+        const int l = e >> logn, m = e & (N2 - 1);
+        buf[l * ls + bitrev(m, logn)] = Rc[row0 * N2 + e];
     }
     __syncthreads();
-    fft_lds<false>(buf, N2, nr, tw, 2);
+    fft_lds<false>(buf, N2, ls, nr, tw, 2);
     for (int e = threadIdx.x; e < nr * mx; e += blockDim.x) {
-        const int l = e / mx, k = e % mx;
-        const double2 zk = buf[l * N2 + (k == N2 ? 0 : k)];
-        const double2 zc = buf[l * N2 + (k == 0 ? 0 : N2 - k)];
+        const int k = e / nr, l = e - k * nr;
+        const double2 zk = buf[l * ls + (k == N2 ? 0 : k)];
+        const double2 zc = buf[l * ls + (k == 0 ? 0 : N2 - k)];
         const double2 sum = make_double2(0.5 * (zk.x + zc.x), 0.5 * (zk.y - zc.y));
         const double2 dif = make_double2(0.5 * (zk.x - zc.x), 0.5 * (zk.y + zc.y));
         // -i w^k dif, w^k = tw[k] of the nx-point table (k <= N2: its last entry
         // is -1 = w^(nx/2))
         const double2 wk = k < N2 ? tw[k] : make_double2(-1.0, 0.0);
         const double2 t = cmul(wk, dif);
-        H[(row0 + l) * mx + k] = make_double2(sum.x + t.y, sum.y - t.x);
+        const long long r = row0 + l, z = r >> logny, y = r & ymask;
+        H[((z * mx + k) << logny) + y] = make_double2(sum.x + t.y, sum.y - t.x);
     }
 }
 
 // Complex-to-real inverse of k_rfft_x (unnormalised: the rows come back
 // multiplied by N2): Z[k] = E + i O with E = (X[k] + X*[N2 - k])/2 and O =
 // (X[k] - X*[N2 - k]) w^-k / 2, inverse FFT, r[2m] = Re z[m], r[2m + 1] =
-// Im z[m].
+// Im z[m].  Modes are read y-fastest as k_rfft_x writes them.
 __global__ __launch_bounds__(kFftThreads) void k_irfft_x(const double2 *__restrict__ H,
-                                                         double *__restrict__ R, int nx, int rows,
-                                                         long long nrows,
+                                                         double *__restrict__ R, int nx,
+                                                         int logny, int rows, long long nrows,
                                                          const double2 *__restrict__ tw)
 {
     extern __shared__ double2 buf[];
-    const int N2 = nx / 2, logn = log2i_dev(N2), mx = N2 + 1;
+    const int N2 = nx / 2, logn = log2i_dev(N2), mx = N2 + 1, ls = N2 + 1;
     const long long row0 = (long long)blockIdx.x * rows;
     const int nr = (int)(nrows - row0 < rows ? nrows - row0 : rows);
+    const long long ymask = (1LL << logny) - 1;
     for (int e = threadIdx.x; e < nr * N2; e += blockDim.x) {
-        const int l = e / N2, k = e % N2;
-        const double2 xk = H[(row0 + l) * mx + k];
-        const double2 xc = H[(row0 + l) * mx + (N2 - k)];
+        const int k = e / nr, l = e - k * nr;
+        const long long r = row0 + l, z = r >> logny, y = r & ymask;
+        const long long base = ((z * mx) << logny) + y;
+        const double2 xk = H[base + ((long long)k << logny)];
+        const double2 xc = H[base + ((long long)(N2 - k) << logny)];
         const double2 E = make_double2(0.5 * (xk.x + xc.x), 0.5 * (xk.y - xc.y));
         const double2 D = make_double2(0.5 * (xk.x - xc.x), 0.5 * (xk.y + xc.y));
         double2 wk = tw[k];
         wk.y = -wk.y;
         const double2 O = cmul(D, wk);
-        buf[l * N2 + bitrev(k, logn)] = make_double2(E.x - O.y, E.y + O.x);
+        buf[l * ls + bitrev(k, logn)] = make_double2(E.x - O.y, E.y + O.x);
     }
     __syncthreads();
-    fft_lds<true>(buf, N2, nr, tw, 2);
+    fft_lds<true>(buf, N2, ls, nr, tw, 2);
     double2 *Rc = reinterpret_cast<double2 *>(R);
     for (int e = threadIdx.x; e < nr * N2; e += blockDim.x) {
-        const int l = e / N2, m = e % N2;
-        Rc[(row0 + l) * N2 + m] = buf[l * N2 + m];
+        const int l = e >> logn, m = e & (N2 - 1);
+        Rc[row0 * N2 + e] = buf[l * ls + m];
     }
+}
+
+// Complex FFT of contiguous lines of n values (line L at Z + L n): a
+// workgroup takes lpw consecutive lines (fewer at the end), read and written
+// in memory order.
+template <bool INV>
+__global__ __launch_bounds__(kFftThreads) void k_fft_lines(double2 *__restrict__ Z, int n,
+                                                           int lpw, long long nlines,
+                                                           const double2 *__restrict__ tw)
+{
+    extern __shared__ double2 buf[];
+    const int logn = log2i_dev(n);
+    const long long L0 = (long long)blockIdx.x * lpw;
+    const int nl = (int)(nlines - L0 < lpw ? nlines - L0 : lpw);
+    double2 *Zb = Z + L0 * n;
+    for (int e = threadIdx.x; e < nl * n; e += blockDim.x)
+        buf[(e >> logn) * n + bitrev(e & (n - 1), logn)] = Zb[e];
+    __syncthreads();
+    fft_lds<INV>(buf, n, n, nl, tw, 1);
+    for (int e = threadIdx.x; e < nl * n; e += blockDim.x)
+        Zb[e] = buf[e];
 }
 
 // Complex FFT along a strided axis: each plane holds `A` lines, line a of
@@ -338,7 +370,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_strided(double2 *__restrict
         buf[l * n + bitrev(sidx, logn)] = Z[base + l * C + sidx * S];
     }
     __syncthreads();
-    fft_lds<INV>(buf, n, nl, tw, 1);
+    fft_lds<INV>(buf, n, n, nl, tw, 1);
     for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
         const int l = e % nl, sidx = e / nl;
         Z[base + l * C + sidx * S] = buf[l * n + sidx];
@@ -352,23 +384,24 @@ __device__ __forceinline__ double lam(int m, int n, double h)
 }
 
 // triply periodic: mode by mode x = d / (s0 + s1 lambda) over the modes
-// kx = 0 .. nx/2 held for real fields; with s0 = 0 the mean mode is 0
+// kx = 0 .. nx/2 held for real fields (y fastest); with s0 = 0 the mean mode
+// is 0
 __global__ __launch_bounds__(256) void k_divide(FluidC F, double s0, double s1,
                                                 double2 *__restrict__ Z)
 {
     const int mx = F.n[0] / 2 + 1;
     {
-        const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
-        if (i >= mx)
+        const int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y, k = blockIdx.z;
+        if (j >= F.n[1])
             return;
-        const long long c = ((long long)k * F.n[1] + j) * mx + i;
+        const long long c = ((long long)k * mx + i) * F.n[1] + j;
         const double L = s0 + s1 * (lam(i, F.n[0], F.h) + lam(j, F.n[1], F.h) + lam(k, F.n[2], F.h));
         const double2 z = Z[c];
         Z[c] = (c == 0 && s0 == 0.0) ? make_double2(0.0, 0.0) : make_double2(z.x / L, z.y / L);
     }
 }
 
-// walls in z: per (kx, ky) mode (kx = 0 .. nx/2) the system s0 x + s1 (D_z + lambda_xy) x =
+// walls in z: per (kx, ky) mode (kx = 0 .. nx/2; modes y-fastest) the system s0 x + s1 (D_z + lambda_xy) x =
 // rhs, D_z the second difference (1/h^2)(x_{k+1} - 2 x_k + x_{k-1}) closed
 // at the walls by a zero gradient (Neumann, the pressure) or by the ghost
 // -x (no slip, the velocity), solved by elimination from the bottom.  The
@@ -382,7 +415,7 @@ __global__ __launch_bounds__(256) void k_tridiag(FluidC F, double s0, double s1,
     const int col = blockIdx.x * blockDim.x + threadIdx.x;
     if (col >= nxy)
         return;
-    const int i = col % mx, j = col / mx;
+    const int i = col / F.n[1], j = col % F.n[1];
     const double ih2 = 1.0 / (F.h * F.h);
     const double lxy = lam(i, F.n[0], F.h) + lam(j, F.n[1], F.h);
     const bool singular = col == 0 && s0 == 0.0 && !dirichlet;
@@ -646,26 +679,28 @@ int grid_blocks(long long n) { return (int)(n / 256 + 1 < 16384 ? n / 256 + 1 : 
 bool pow2(int n) { return n >= 2 && (n & (n - 1)) == 0; }
 
 
-// strided complex FFT along y (a = 1) or z (a = 2) over the half spectrum
-// (nx/2 + 1 columns)
+// complex FFT over the half spectrum along y (a = 1: contiguous lines) or
+// along z (a = 2: lines of stride mx ny, consecutive lines adjacent)
 template <bool INV>
-void fft_strided(ibmx_plan p, const FluidC &F, int a, hipStream_t s)
+void fft_axis(ibmx_plan p, const FluidC &F, int a, hipStream_t s)
 {
     const int mx = F.n[0] / 2 + 1, ny = F.n[1], nz = F.n[2], n = F.n[a];
-    int A;
-    long long B, S, planes;
-    if (a == 1) {
-        A = mx, B = (long long)mx * ny, S = mx, planes = nz;
-    } else {
-        A = mx * ny, B = 0, S = (long long)mx * ny, planes = 1;
-    }
     int lpw = n >= kFftElemsStrided ? 1 : kFftElemsStrided / n;
+    if (a == 1) {
+        const long long nlines = (long long)mx * nz;
+        if (lpw > nlines)
+            lpw = (int)nlines;
+        hipLaunchKernelGGL((k_fft_lines<INV>), dim3((unsigned)((nlines + lpw - 1) / lpw)),
+                           dim3(kFftThreads), sizeof(double2) * (size_t)lpw * n, s, p->fl_z, n,
+                           lpw, nlines, (const double2 *)p->fl_tw[1]);
+        return;
+    }
+    const int A = mx * ny;
     if (lpw > A)
         lpw = A;
-    const long long blocks = planes * ((A + lpw - 1) / lpw);
-    hipLaunchKernelGGL((k_fft_strided<INV>), dim3((unsigned)blocks), dim3(kFftThreads),
-                       sizeof(double2) * (size_t)lpw * n, s, p->fl_z, n, lpw, A, B, 1LL, S,
-                       (const double2 *)p->fl_tw[a]);
+    hipLaunchKernelGGL((k_fft_strided<INV>), dim3((unsigned)((A + lpw - 1) / lpw)),
+                       dim3(kFftThreads), sizeof(double2) * (size_t)lpw * n, s, p->fl_z, n, lpw,
+                       A, 0LL, 1LL, (long long)A, (const double2 *)p->fl_tw[2]);
 }
 
 // rows along x: forward real-to-complex from fl_r into fl_z, or back
@@ -674,16 +709,24 @@ void fft_rows(ibmx_plan p, const FluidC &F, hipStream_t s)
 {
     const int N2 = F.n[0] / 2;
     const long long nrows = (long long)F.n[1] * F.n[2];
-    const int rows = N2 >= kRowElems ? 1 : kRowElems / N2;
+    // at least kMinRows rows (each mode's writes cover that many consecutive
+    // y), within 64 KB of LDS
+    int rows = N2 * kMinRows >= kRowElems ? kMinRows : kRowElems / N2;
+    const int fit = (int)(65536 / (sizeof(double2) * (N2 + 1)));
+    if (rows > fit)
+        rows = fit;
     const unsigned blocks = (unsigned)((nrows + rows - 1) / rows);
-    const size_t lds = sizeof(double2) * (size_t)rows * N2;
+    const size_t lds = sizeof(double2) * (size_t)rows * (N2 + 1);
+    int logny = 0;
+    while ((1 << logny) < F.n[1])
+        ++logny;
     if (INV)
         hipLaunchKernelGGL(k_irfft_x, dim3(blocks), dim3(kFftThreads), lds, s,
-                           (const double2 *)p->fl_z, p->fl_r, F.n[0], rows, nrows,
+                           (const double2 *)p->fl_z, p->fl_r, F.n[0], logny, rows, nrows,
                            (const double2 *)p->fl_tw[0]);
     else
         hipLaunchKernelGGL(k_rfft_x, dim3(blocks), dim3(kFftThreads), lds, s,
-                           (const double *)p->fl_r, p->fl_z, F.n[0], rows, nrows,
+                           (const double *)p->fl_r, p->fl_z, F.n[0], logny, rows, nrows,
                            (const double2 *)p->fl_tw[0]);
 }
 
@@ -710,20 +753,20 @@ double solve_modes(ibmx_plan p, const FluidC &F, double s0, double s1, int diric
 {
     const int mx = F.n[0] / 2 + 1;
     fft_rows<false>(p, F, s);
-    fft_strided<false>(p, F, 1, s);
+    fft_axis<false>(p, F, 1, s);
     double scale = 1.0 / ((double)(F.n[0] / 2) * F.n[1]);
     if (F.periodic[2]) {
-        fft_strided<false>(p, F, 2, s);
-        hipLaunchKernelGGL(k_divide, dim3((mx + 255) / 256, F.n[1], F.n[2]), dim3(256), 0, s, F,
+        fft_axis<false>(p, F, 2, s);
+        hipLaunchKernelGGL(k_divide, dim3((F.n[1] + 255) / 256, mx, F.n[2]), dim3(256), 0, s, F,
                            s0, s1, p->fl_z);
-        fft_strided<true>(p, F, 2, s);
+        fft_axis<true>(p, F, 2, s);
         scale /= F.n[2];
     } else {
         const int nxy = mx * F.n[1];
         hipLaunchKernelGGL(k_tridiag, dim3((nxy + 255) / 256), dim3(256), 0, s, F, s0, s1,
                            dirichlet, p->fl_z, p->fl_cp);
     }
-    fft_strided<true>(p, F, 1, s);
+    fft_axis<true>(p, F, 1, s);
     fft_rows<true>(p, F, s);
     return scale;
 }
