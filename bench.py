@@ -83,29 +83,32 @@ def kernel_sources_hash() -> str:
 
 def fluid_bytes(kind: str, s: int, nodes: int, walls_z: bool = True) -> float:
     """Bytes one fluid call must move (s = bytes of the field type; the
-    solves work in FP64 on a real grid, 8 B per node, and its half spectrum of
-    nx/2 + 1 complex modes per row, about 8 B per node).
+    solves work in FP64 on the half spectrum of nx/2 + 1 complex modes per
+    row, about 8 B per node, and on an FP64 real grid, 8 B per node).
 
-    solve (one real right-hand side): the real-to-complex pass along x
-           (read 8, write 8), the y pass forward and back (16 each), the
-           complex-to-real pass (16), and across walls the elimination (read
-           and write the spectrum twice, the eliminated coefficient once each
-           way: 40) or along a periodic z two more passes and the division (48).
+    spectrum (one solve between the x passes): the y pass forward and back
+           (read and write 8 each: 16 + 16), and across walls the elimination
+           (read and write the spectrum twice, the eliminated coefficient
+           once each way: 40) or along a periodic z two more passes and the
+           division (48).
     predictor: reads u, N (3s each) and P (s); writes u~, N and nu L u (3s each).
-    project: face values and divergence (reads 3s, writes 3s + 8), the solve,
-           the correction (reads the solution, u, u_f, P; writes u, u_f, P:
-           8 + 14s; phi is not asked for).
-    helmholtz (theta = 0, no pressure term): per component the right-hand
-           side (reads u and nu L u: 2s, writes 8), the solve and the result
-           (reads 8, writes s).
+    project: face values and divergence (reads 3s, writes 3s + 8), the
+           forward x pass from the real grid (read 8, write 8), the spectrum,
+           the inverse x pass into the real grid (16), the correction (reads
+           the solution, u, u_f, P; writes u, u_f, P: 8 + 14s; phi is not
+           asked for).
+    helmholtz (theta = 0, no pressure term): per component the forward x
+           pass computing the right-hand side from u and nu L u as it reads
+           (2s + 8), the spectrum, the inverse x pass writing the result
+           (8 + s).
     """
-    solve = 16 + 16 + 16 + 16 + (40 if walls_z else 48)
+    spectrum = 16 + 16 + (40 if walls_z else 48)
     if kind == "predictor":
         per = 16 * s
     elif kind == "project":
-        per = (6 * s + 8) + solve + (8 + 14 * s)
+        per = (6 * s + 8) + 16 + spectrum + 16 + (8 + 14 * s)
     elif kind == "helmholtz":
-        per = 3 * ((2 * s + 8) + solve + (8 + s))
+        per = 3 * ((2 * s + 8) + spectrum + (8 + s))
     else:
         raise KeyError(kind)
     return float(per) * nodes

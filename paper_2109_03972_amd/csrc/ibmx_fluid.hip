@@ -252,6 +252,50 @@ __device__ __forceinline__ int bitrev(int s, int logn)
     return logn > 0 ? (int)(__brev((unsigned)s) >> (32 - logn)) : 0;
 }
 
+// What the x passes read and write, as pairs of consecutive real values
+// (complex index m = real index / 2): the FP64 real grid, or (forward) the
+// implicit step's right-hand side of one component without a pressure term,
+// computed from u and nu L u as it is read, or (inverse) the solution scaled
+// and rounded into the caller's field (caller fields are accessed by
+// element: they need only the alignment of T).
+
+struct RealIn {
+    const double *R;
+    __device__ void prepare() {}
+    __device__ double2 operator()(long long m) const { return reinterpret_cast<const double2 *>(R)[m]; }
+};
+
+template <typename T>
+struct HelmRhsIn {
+    const T *u, *lapnu;
+    const double *fbar;   // device double[3] or NULL
+    int b;
+    double c, dt, alpha, fb;
+    __device__ void prepare() { fb = fbar ? fbar[b] : 0.0; }
+    __device__ double2 operator()(long long m) const
+    {
+        const long long r = 2 * m;
+        return make_double2((double)u[r] - c * fb + dt * (-alpha * (double)lapnu[r]),
+                            (double)u[r + 1] - c * fb + dt * (-alpha * (double)lapnu[r + 1]));
+    }
+};
+
+struct RealOut {
+    double *R;
+    __device__ void operator()(long long m, double2 v) const { reinterpret_cast<double2 *>(R)[m] = v; }
+};
+
+template <typename T>
+struct ScaledOut {
+    T *out;
+    double scale;
+    __device__ void operator()(long long m, double2 v) const
+    {
+        out[2 * m] = (T)(v.x * scale);
+        out[2 * m + 1] = (T)(v.y * scale);
+    }
+};
+
 // Real-to-complex transform of rows along x (nx = 2 N2): each row's values
 // r[2m] + i r[2m + 1] form N2 complex values whose FFT Z gives the row's
 // modes X[k] = (Z[k] + Z*[N2 - k])/2 - i w^k (Z[k] - Z*[N2 - k])/2, k = 0..N2,
@@ -259,8 +303,8 @@ __device__ __forceinline__ int bitrev(int s, int logn)
 // + y), held in LDS with a stride of N2 + 1; the modes go out y-fastest, mode
 // k of row r at (z mx + k) ny + y, consecutive threads taking consecutive
 // rows.
-__global__ __launch_bounds__(kFftThreads) void k_rfft_x(const double *__restrict__ R,
-                                                        double2 *__restrict__ H, int nx,
+template <class Src>
+__global__ __launch_bounds__(kFftThreads) void k_rfft_x(Src src, double2 *__restrict__ H, int nx,
                                                         int logny, int rows, long long nrows,
                                                         const double2 *__restrict__ tw)
 {
@@ -269,10 +313,10 @@ __global__ __launch_bounds__(kFftThreads) void k_rfft_x(const double *__restrict
     const long long row0 = (long long)blockIdx.x * rows;
     const int nr = (int)(nrows - row0 < rows ? nrows - row0 : rows);
     const long long ymask = (1LL << logny) - 1;
-    const double2 *Rc = reinterpret_cast<const double2 *>(R);
+    src.prepare();
     for (int e = threadIdx.x; e < nr * N2; e += blockDim.x) {
         const int l = e >> logn, m = e & (N2 - 1);
-        buf[l * ls + bitrev(m, logn)] = Rc[row0 * N2 + e];
+        buf[l * ls + bitrev(m, logn)] = src(row0 * N2 + e);
     }
     __syncthreads();
     fft_lds<false>(buf, N2, ls, nr, tw, 2);
@@ -295,9 +339,10 @@ __global__ __launch_bounds__(kFftThreads) void k_rfft_x(const double *__restrict
 // multiplied by N2): Z[k] = E + i O with E = (X[k] + X*[N2 - k])/2 and O =
 // (X[k] - X*[N2 - k]) w^-k / 2, inverse FFT, r[2m] = Re z[m], r[2m + 1] =
 // Im z[m].  Modes are read y-fastest as k_rfft_x writes them.
-__global__ __launch_bounds__(kFftThreads) void k_irfft_x(const double2 *__restrict__ H,
-                                                         double *__restrict__ R, int nx,
-                                                         int logny, int rows, long long nrows,
+template <class Dst>
+__global__ __launch_bounds__(kFftThreads) void k_irfft_x(const double2 *__restrict__ H, Dst dst,
+                                                         int nx, int logny, int rows,
+                                                         long long nrows,
                                                          const double2 *__restrict__ tw)
 {
     extern __shared__ double2 buf[];
@@ -320,10 +365,9 @@ __global__ __launch_bounds__(kFftThreads) void k_irfft_x(const double2 *__restri
     }
     __syncthreads();
     fft_lds<true>(buf, N2, ls, nr, tw, 2);
-    double2 *Rc = reinterpret_cast<double2 *>(R);
     for (int e = threadIdx.x; e < nr * N2; e += blockDim.x) {
         const int l = e >> logn, m = e & (N2 - 1);
-        Rc[row0 * N2 + e] = buf[l * ls + m];
+        dst(row0 * N2 + e, buf[l * ls + m]);
     }
 }
 
@@ -597,23 +641,10 @@ __global__ __launch_bounds__(PX * PY) void k_predict(FluidC F, const T *__restri
 }
 
 // step e, component b: the right-hand side u_f - c fbar + dt (-alpha lapnu
-// + 2 alpha theta grad P) into R.  With theta = 0 the pressure term vanishes
-// and the kernel is elementwise (k_helm_rhs_local); otherwise P passes
-// through the plane ring and the own u_f and lapnu of the next plane are
-// loaded while a plane is computed.
-template <typename T>
-__global__ __launch_bounds__(256) void k_helm_rhs_local(long long N, const T *__restrict__ u,
-                                                        const T *__restrict__ lapnu,
-                                                        const double *__restrict__ fbar, int b,
-                                                        double c2, double dt, double alpha,
-                                                        double *__restrict__ R)
-{
-    const double fb = fbar ? fbar[b] : 0.0;
-    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < N;
-         c += (long long)gridDim.x * blockDim.x)
-        R[c] = (double)u[c] - c2 * fb + dt * (-alpha * (double)lapnu[c]);
-}
-
+// + 2 alpha theta grad P) into R, P through the plane ring, the own u_f and
+// lapnu of the next plane loaded while a plane is computed.  (With theta = 0
+// there is no pressure term and the x pass computes the right-hand side as
+// it reads: HelmRhsIn.)
 template <typename T>
 __global__ __launch_bounds__(PX * PY) void k_helm_rhs(FluidC F, const T *__restrict__ u,
                                                       const T *__restrict__ lapnu,
@@ -664,17 +695,6 @@ __global__ __launch_bounds__(PX * PY) void k_helm_rhs(FluidC F, const T *__restr
     }
 }
 
-// the solution R * scale into out
-template <typename T>
-__global__ __launch_bounds__(256) void k_take(long long N, const double *__restrict__ R,
-                                              double scale, T *__restrict__ out)
-{
-    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < N;
-         c += (long long)gridDim.x * blockDim.x)
-        out[c] = (T)(R[c] * scale);
-}
-
-int grid_blocks(long long n) { return (int)(n / 256 + 1 < 16384 ? n / 256 + 1 : 16384); }
 
 bool pow2(int n) { return n >= 2 && (n & (n - 1)) == 0; }
 
@@ -703,31 +723,47 @@ void fft_axis(ibmx_plan p, const FluidC &F, int a, hipStream_t s)
                        A, 0LL, 1LL, (long long)A, (const double2 *)p->fl_tw[2]);
 }
 
-// rows along x: forward real-to-complex from fl_r into fl_z, or back
-template <bool INV>
-void fft_rows(ibmx_plan p, const FluidC &F, hipStream_t s)
+// rows along x: forward real-to-complex from src into fl_z, or back into dst
+struct RowLaunch {
+    int rows, logny;
+    unsigned blocks;
+    size_t lds;
+    long long nrows;
+};
+RowLaunch row_launch(const FluidC &F)
 {
     const int N2 = F.n[0] / 2;
-    const long long nrows = (long long)F.n[1] * F.n[2];
+    RowLaunch r;
+    r.nrows = (long long)F.n[1] * F.n[2];
     // at least kMinRows rows (each mode's writes cover that many consecutive
     // y), within 64 KB of LDS
-    int rows = N2 * kMinRows >= kRowElems ? kMinRows : kRowElems / N2;
+    r.rows = N2 * kMinRows >= kRowElems ? kMinRows : kRowElems / N2;
     const int fit = (int)(65536 / (sizeof(double2) * (N2 + 1)));
-    if (rows > fit)
-        rows = fit;
-    const unsigned blocks = (unsigned)((nrows + rows - 1) / rows);
-    const size_t lds = sizeof(double2) * (size_t)rows * (N2 + 1);
-    int logny = 0;
-    while ((1 << logny) < F.n[1])
-        ++logny;
-    if (INV)
-        hipLaunchKernelGGL(k_irfft_x, dim3(blocks), dim3(kFftThreads), lds, s,
-                           (const double2 *)p->fl_z, p->fl_r, F.n[0], logny, rows, nrows,
-                           (const double2 *)p->fl_tw[0]);
-    else
-        hipLaunchKernelGGL(k_rfft_x, dim3(blocks), dim3(kFftThreads), lds, s,
-                           (const double *)p->fl_r, p->fl_z, F.n[0], logny, rows, nrows,
-                           (const double2 *)p->fl_tw[0]);
+    if (r.rows > fit)
+        r.rows = fit;
+    r.blocks = (unsigned)((r.nrows + r.rows - 1) / r.rows);
+    r.lds = sizeof(double2) * (size_t)r.rows * (N2 + 1);
+    r.logny = 0;
+    while ((1 << r.logny) < F.n[1])
+        ++r.logny;
+    return r;
+}
+
+template <class Src>
+void rows_forward(ibmx_plan p, const FluidC &F, Src src, hipStream_t s)
+{
+    const RowLaunch r = row_launch(F);
+    hipLaunchKernelGGL((k_rfft_x<Src>), dim3(r.blocks), dim3(kFftThreads), r.lds, s, src, p->fl_z,
+                       F.n[0], r.logny, r.rows, r.nrows, (const double2 *)p->fl_tw[0]);
+}
+
+template <class Dst>
+void rows_inverse(ibmx_plan p, const FluidC &F, Dst dst, hipStream_t s)
+{
+    const RowLaunch r = row_launch(F);
+    hipLaunchKernelGGL((k_irfft_x<Dst>), dim3(r.blocks), dim3(kFftThreads), r.lds, s,
+                       (const double2 *)p->fl_z, dst, F.n[0], r.logny, r.rows, r.nrows,
+                       (const double2 *)p->fl_tw[0]);
 }
 
 FluidC fluid_constants(const ibmx_plan p, double theta)
@@ -745,29 +781,32 @@ FluidC fluid_constants(const ibmx_plan p, double theta)
     return F;
 }
 
-// fl_r (a real right-hand side in the cell layout) -> the solution of
-// (s0 + s1 L) x = r in fl_r, times the returned scale (the inverse passes
-// are unnormalised)
-double solve_modes(ibmx_plan p, const FluidC &F, double s0, double s1, int dirichlet,
-                   hipStream_t s)
+// the half spectrum in fl_z (after rows_forward) -> that of the solution of
+// (s0 + s1 L) x = r (before rows_inverse); the passes are unnormalised, the
+// result comes back multiplied by 1 / spectrum_scale
+void solve_spectrum(ibmx_plan p, const FluidC &F, double s0, double s1, int dirichlet,
+                    hipStream_t s)
 {
     const int mx = F.n[0] / 2 + 1;
-    fft_rows<false>(p, F, s);
     fft_axis<false>(p, F, 1, s);
-    double scale = 1.0 / ((double)(F.n[0] / 2) * F.n[1]);
     if (F.periodic[2]) {
         fft_axis<false>(p, F, 2, s);
         hipLaunchKernelGGL(k_divide, dim3((F.n[1] + 255) / 256, mx, F.n[2]), dim3(256), 0, s, F,
                            s0, s1, p->fl_z);
         fft_axis<true>(p, F, 2, s);
-        scale /= F.n[2];
     } else {
         const int nxy = mx * F.n[1];
         hipLaunchKernelGGL(k_tridiag, dim3((nxy + 255) / 256), dim3(256), 0, s, F, s0, s1,
                            dirichlet, p->fl_z, p->fl_cp);
     }
     fft_axis<true>(p, F, 1, s);
-    fft_rows<true>(p, F, s);
+}
+
+double spectrum_scale(const FluidC &F)
+{
+    double scale = 1.0 / ((double)(F.n[0] / 2) * F.n[1]);
+    if (F.periodic[2])
+        scale /= F.n[2];
     return scale;
 }
 
@@ -779,9 +818,11 @@ ibmx_status run_project(ibmx_plan p, T *u, T *uf, T *P, T *phi, double theta)
     ProfScope ps(p, IBMX_K_OTHER);
     hipLaunchKernelGGL((k_face_div<T>), column_grid(F), dim3(PX * PY), 0, s, F, (const T *)u, uf,
                        p->fl_r);
-    const double scale = solve_modes(p, F, 0.0, 1.0, 0, s);
+    rows_forward(p, F, RealIn{p->fl_r}, s);
+    solve_spectrum(p, F, 0.0, 1.0, 0, s);
+    rows_inverse(p, F, RealOut{p->fl_r}, s);
     hipLaunchKernelGGL((k_correct<T>), column_grid(F), dim3(PX * PY), 0, s, F,
-                       (const double *)p->fl_r, scale, u, uf, P, phi);
+                       (const double *)p->fl_r, spectrum_scale(F), u, uf, P, phi);
     return ibmx_launch_check();
 }
 
@@ -807,16 +848,26 @@ ibmx_status run_helmholtz(ibmx_plan p, T *u, const T *lapnu, const T *P, const d
     hipStream_t s = p->stream;
     ProfScope ps(p, IBMX_K_OTHER);
     for (int b = 0; b < 3; ++b) {
-        if (F.theta != 0.0)
+        // the right-hand side: with a pressure term through the plane ring
+        // into the real grid, without it computed by the x pass as it reads
+        if (F.theta != 0.0) {
             hipLaunchKernelGGL((k_helm_rhs<T>), column_grid(F), dim3(PX * PY), 0, s, F,
                                (const T *)u, lapnu, P, fbar, b, dt, alpha, p->fl_r);
-        else
-            hipLaunchKernelGGL((k_helm_rhs_local<T>), dim3(grid_blocks(N)), dim3(256), 0, s, N,
-                               (const T *)u + (size_t)b * N, lapnu + (size_t)b * N, fbar, b, F.c,
-                               dt, alpha, p->fl_r);
-        const double scale = solve_modes(p, F, 1.0, -alpha * dt * F.nu, 1, s);
-        hipLaunchKernelGGL((k_take<T>), dim3(grid_blocks(N)), dim3(256), 0, s, N,
-                           (const double *)p->fl_r, scale, u + (size_t)b * N);
+            rows_forward(p, F, RealIn{p->fl_r}, s);
+        } else {
+            HelmRhsIn<T> in;
+            in.u = u + (size_t)b * N;
+            in.lapnu = lapnu + (size_t)b * N;
+            in.fbar = fbar;
+            in.b = b;
+            in.c = F.c;
+            in.dt = dt;
+            in.alpha = alpha;
+            in.fb = 0.0;
+            rows_forward(p, F, in, s);
+        }
+        solve_spectrum(p, F, 1.0, -alpha * dt * F.nu, 1, s);
+        rows_inverse(p, F, ScaledOut<T>{u + (size_t)b * N, spectrum_scale(F)}, s);
     }
     return ibmx_launch_check();
 }
