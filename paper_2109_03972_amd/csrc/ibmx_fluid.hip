@@ -24,7 +24,7 @@ namespace {
 constexpr int kFftThreads = 256;
 constexpr int kRowElems = 256;      // complex elements per workgroup in the x passes
 constexpr int kMinRows = 8;         // and at least this many rows
-constexpr int kFftElemsStrided = 2048;   // strided lines: 32 KB of LDS, 4 lines of 512
+constexpr int kFftElemsStrided = 1024;   // y and z lines: 16 KB of LDS, 2 lines of 512
 
 struct FluidC {
     int n[3];
