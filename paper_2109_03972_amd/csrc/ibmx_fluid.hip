@@ -313,13 +313,17 @@ __global__ __launch_bounds__(kFftThreads) void k_rfft_x(Src src, double2 *__rest
     const long long row0 = (long long)blockIdx.x * rows;
     const int nr = (int)(nrows - row0 < rows ? nrows - row0 : rows);
     const long long ymask = (1LL << logny) - 1;
+    // the first N2 entries of the nx-point table, after the rows
+    double2 *twl = buf + (size_t)rows * ls;
+    for (int e = threadIdx.x; e < N2; e += blockDim.x)
+        twl[e] = tw[e];
     src.prepare();
     for (int e = threadIdx.x; e < nr * N2; e += blockDim.x) {
         const int l = e >> logn, m = e & (N2 - 1);
         buf[l * ls + bitrev(m, logn)] = src(row0 * N2 + e);
     }
     __syncthreads();
-    fft_lds<false>(buf, N2, ls, nr, tw, 2);
+    fft_lds<false>(buf, N2, ls, nr, twl, 2);
     for (int e = threadIdx.x; e < nr * mx; e += blockDim.x) {
         const int k = e / nr, l = e - k * nr;
         const double2 zk = buf[l * ls + (k == N2 ? 0 : k)];
@@ -328,7 +332,7 @@ __global__ __launch_bounds__(kFftThreads) void k_rfft_x(Src src, double2 *__rest
         const double2 dif = make_double2(0.5 * (zk.x - zc.x), 0.5 * (zk.y + zc.y));
         // -i w^k dif, w^k = tw[k] of the nx-point table (k <= N2: its last entry
         // is -1 = w^(nx/2))
-        const double2 wk = k < N2 ? tw[k] : make_double2(-1.0, 0.0);
+        const double2 wk = k < N2 ? twl[k] : make_double2(-1.0, 0.0);
         const double2 t = cmul(wk, dif);
         const long long r = row0 + l, z = r >> logny, y = r & ymask;
         H[((z * mx + k) << logny) + y] = make_double2(sum.x + t.y, sum.y - t.x);
@@ -350,6 +354,9 @@ __global__ __launch_bounds__(kFftThreads) void k_irfft_x(const double2 *__restri
     const long long row0 = (long long)blockIdx.x * rows;
     const int nr = (int)(nrows - row0 < rows ? nrows - row0 : rows);
     const long long ymask = (1LL << logny) - 1;
+    double2 *twl = buf + (size_t)rows * ls;
+    for (int e = threadIdx.x; e < N2; e += blockDim.x)
+        twl[e] = tw[e];
     for (int e = threadIdx.x; e < nr * N2; e += blockDim.x) {
         const int k = e / nr, l = e - k * nr;
         const long long r = row0 + l, z = r >> logny, y = r & ymask;
@@ -364,7 +371,7 @@ __global__ __launch_bounds__(kFftThreads) void k_irfft_x(const double2 *__restri
         buf[l * ls + bitrev(k, logn)] = make_double2(E.x - O.y, E.y + O.x);
     }
     __syncthreads();
-    fft_lds<true>(buf, N2, ls, nr, tw, 2);
+    fft_lds<true>(buf, N2, ls, nr, twl, 2);
     for (int e = threadIdx.x; e < nr * N2; e += blockDim.x) {
         const int l = e >> logn, m = e & (N2 - 1);
         dst(row0 * N2 + e, buf[l * ls + m]);
@@ -384,10 +391,14 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_lines(double2 *__restrict__
     const long long L0 = (long long)blockIdx.x * lpw;
     const int nl = (int)(nlines - L0 < lpw ? nlines - L0 : lpw);
     double2 *Zb = Z + L0 * n;
+    // the n/2 twiddles the transform uses, after the lines
+    double2 *twl = buf + (size_t)lpw * n;
+    for (int e = threadIdx.x; e < n / 2; e += blockDim.x)
+        twl[e] = tw[e];
     for (int e = threadIdx.x; e < nl * n; e += blockDim.x)
         buf[(e >> logn) * n + bitrev(e & (n - 1), logn)] = Zb[e];
     __syncthreads();
-    fft_lds<INV>(buf, n, n, nl, tw, 1);
+    fft_lds<INV>(buf, n, n, nl, twl, 1);
     for (int e = threadIdx.x; e < nl * n; e += blockDim.x)
         Zb[e] = buf[e];
 }
@@ -409,12 +420,15 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_strided(double2 *__restrict
     const int a0 = (int)(blockIdx.x % groups) * lpw;
     const int nl = A - a0 < lpw ? A - a0 : lpw;
     const long long base = q * B + (long long)a0 * C;
+    double2 *twl = buf + (size_t)lpw * n;
+    for (int e = threadIdx.x; e < n / 2; e += blockDim.x)
+        twl[e] = tw[e];
     for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
         const int l = e % nl, sidx = e / nl;
         buf[l * n + bitrev(sidx, logn)] = Z[base + l * C + sidx * S];
     }
     __syncthreads();
-    fft_lds<INV>(buf, n, n, nl, tw, 1);
+    fft_lds<INV>(buf, n, n, nl, twl, 1);
     for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
         const int l = e % nl, sidx = e / nl;
         Z[base + l * C + sidx * S] = buf[l * n + sidx];
@@ -711,7 +725,7 @@ void fft_axis(ibmx_plan p, const FluidC &F, int a, hipStream_t s)
         if (lpw > nlines)
             lpw = (int)nlines;
         hipLaunchKernelGGL((k_fft_lines<INV>), dim3((unsigned)((nlines + lpw - 1) / lpw)),
-                           dim3(kFftThreads), sizeof(double2) * (size_t)lpw * n, s, p->fl_z, n,
+                           dim3(kFftThreads), sizeof(double2) * ((size_t)lpw * n + n / 2), s, p->fl_z, n,
                            lpw, nlines, (const double2 *)p->fl_tw[1]);
         return;
     }
@@ -719,7 +733,7 @@ void fft_axis(ibmx_plan p, const FluidC &F, int a, hipStream_t s)
     if (lpw > A)
         lpw = A;
     hipLaunchKernelGGL((k_fft_strided<INV>), dim3((unsigned)((A + lpw - 1) / lpw)),
-                       dim3(kFftThreads), sizeof(double2) * (size_t)lpw * n, s, p->fl_z, n, lpw,
+                       dim3(kFftThreads), sizeof(double2) * ((size_t)lpw * n + n / 2), s, p->fl_z, n, lpw,
                        A, 0LL, 1LL, (long long)A, (const double2 *)p->fl_tw[2]);
 }
 
@@ -736,13 +750,13 @@ RowLaunch row_launch(const FluidC &F)
     RowLaunch r;
     r.nrows = (long long)F.n[1] * F.n[2];
     // at least kMinRows rows (each mode's writes cover that many consecutive
-    // y), within 64 KB of LDS
+    // y), within 64 KB of LDS with the N2 twiddles
     r.rows = N2 * kMinRows >= kRowElems ? kMinRows : kRowElems / N2;
-    const int fit = (int)(65536 / (sizeof(double2) * (N2 + 1)));
+    const int fit = (int)((65536 / sizeof(double2) - N2) / (N2 + 1));
     if (r.rows > fit)
         r.rows = fit;
     r.blocks = (unsigned)((r.nrows + r.rows - 1) / r.rows);
-    r.lds = sizeof(double2) * (size_t)r.rows * (N2 + 1);
+    r.lds = sizeof(double2) * ((size_t)r.rows * (N2 + 1) + N2);
     r.logny = 0;
     while ((1 << r.logny) < F.n[1])
         ++r.logny;
