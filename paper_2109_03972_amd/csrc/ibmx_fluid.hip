@@ -30,6 +30,7 @@ struct FluidC {
     int n[3];
     int periodic[3];
     double h, c, nu, theta;
+    double ih, ih2, i2h, ic;   // 1/h, 1/h^2, 1/(2h), 1/c: the stencils multiply
 };
 
 __device__ __forceinline__ long long cell_index(const FluidC &F, int i, int j, int k)
@@ -176,9 +177,9 @@ __global__ __launch_bounds__(PX * PY) void k_face_div(FluidC F, const T *__restr
                 in_m[a] ? 0.5 * ((double)ring_nb<T, 3>(ring, col, sd, sc, su, a, a, -1) + uc)
                         : 0.0;
             uf[(size_t)a * N + c] = (T)out;
-            div = div + (out - in) / F.h;
+            div = div + (out - in) * F.ih;
         }
-        R[c] = div / F.c;
+        R[c] = div * F.ic;
     }
 }
 
@@ -560,15 +561,15 @@ __global__ __launch_bounds__(PX * PY) void k_correct(FluidC F, const double *__r
             double lap = 0.0;
             for (int a = 0; a < 3; ++a) {
                 const double gp =
-                    in_p[a] ? (ring_nb<double, 1>(ring, col, sd, sc, su, 0, a, 1) * scale - ph) / F.h
+                    in_p[a] ? (ring_nb<double, 1>(ring, col, sd, sc, su, 0, a, 1) * scale - ph) * F.ih
                             : 0.0;
                 const double gm =
-                    in_m[a] ? (ph - ring_nb<double, 1>(ring, col, sd, sc, su, 0, a, -1) * scale) / F.h
+                    in_m[a] ? (ph - ring_nb<double, 1>(ring, col, sd, sc, su, 0, a, -1) * scale) * F.ih
                             : 0.0;
                 const size_t ia = (size_t)a * N + c;
                 u[ia] = (T)((double)ow[a] - F.c * (0.5 * (gp + gm)));
                 uf[ia] = (T)((double)ow[3 + a] - F.c * gp);
-                lap = lap + (gp - gm) / F.h;
+                lap = lap + (gp - gm) * F.ih;
             }
             P[c] = (T)((1.0 - F.theta) * (double)ow[6] + ph - 0.5 * F.c * F.nu * lap);
             if (phi_out)
@@ -630,15 +631,15 @@ __global__ __launch_bounds__(PX * PY) void k_predict(FluidC F, const T *__restri
                         in_p[a] ? (double)ring_nb<T, 4>(ring, col, sd, sc, su, b, a, 1) : -ub;
                     const double dn =
                         in_m[a] ? (double)ring_nb<T, 4>(ring, col, sd, sc, su, b, a, -1) : -ub;
-                    lap = lap + (up - 2.0 * ub + dn) / (F.h * F.h);
-                    adv = adv + ua[a] * ((up - dn) / (2.0 * F.h));
+                    lap = lap + (up - 2.0 * ub + dn) * F.ih2;
+                    adv = adv + ua[a] * ((up - dn) * F.i2h);
                 }
                 // pressure gradient along b: mean of the two face gradients
                 const double gp =
-                    in_p[b] ? ((double)ring_nb<T, 4>(ring, col, sd, sc, su, 3, b, 1) - pc) / F.h
+                    in_p[b] ? ((double)ring_nb<T, 4>(ring, col, sd, sc, su, 3, b, 1) - pc) * F.ih
                             : 0.0;
                 const double gm =
-                    in_m[b] ? (pc - (double)ring_nb<T, 4>(ring, col, sd, sc, su, 3, b, -1)) / F.h
+                    in_m[b] ? (pc - (double)ring_nb<T, 4>(ring, col, sd, sc, su, 3, b, -1)) * F.ih
                             : 0.0;
                 const double gP = 0.5 * (gp + gm);
                 const size_t ib = (size_t)b * N + c;
@@ -696,9 +697,9 @@ __global__ __launch_bounds__(PX * PY) void k_helm_rhs(FluidC F, const T *__restr
             const double pc = (double)ring[sc][0][col.ty + 1][col.tx + 1];
             // mean of the two face gradients along b (zero on wall faces)
             const double gp =
-                hp ? ((double)ring_nb<T, 1>(ring, col, sd, sc, su, 0, b, 1) - pc) / F.h : 0.0;
+                hp ? ((double)ring_nb<T, 1>(ring, col, sd, sc, su, 0, b, 1) - pc) * F.ih : 0.0;
             const double gm =
-                hm ? (pc - (double)ring_nb<T, 1>(ring, col, sd, sc, su, 0, b, -1)) / F.h : 0.0;
+                hm ? (pc - (double)ring_nb<T, 1>(ring, col, sd, sc, su, 0, b, -1)) * F.ih : 0.0;
             const double gP = 0.5 * (gp + gm);
             R[cell_index(F, col.i, col.j, k)] =
                 (double)ow[0] - F.c * fb +
@@ -789,7 +790,11 @@ FluidC fluid_constants(const ibmx_plan p, double theta)
         F.periodic[a] = g.periodic[a];
     }
     F.h = g.h;
+    F.ih = 1.0 / g.h;
+    F.ih2 = 1.0 / (g.h * g.h);
+    F.i2h = 1.0 / (2.0 * g.h);
     F.c = p->prm.two_alpha_dt;
+    F.ic = 1.0 / F.c;
     F.nu = p->prm.nu_f;
     F.theta = theta;
     return F;
