@@ -97,9 +97,12 @@ __device__ __forceinline__ bool marker_geometry(const GridC &g, const double *X,
         t[a] = s - fl;
         long long bb = (long long)fl - 1;
         if (g.periodic[a]) {
-            bb %= g.n[a];
-            if (bb < 0)
-                bb += g.n[a];
+            // the 64-bit remainder only for a base outside [0, n)
+            if (bb < 0 || bb >= g.n[a]) {
+                bb %= g.n[a];
+                if (bb < 0)
+                    bb += g.n[a];
+            }
         } else {
             long long last = (t[a] == 0.0) ? bb + W - 2 : bb + W - 1;
             if (bb < 0 || last > g.n[a] - 1) {
