@@ -377,7 +377,10 @@ def main():
     km, kn = st["kernel_ms"], st["kernel_launches"]
     steps_done = args.steps
     per_launch = {k: (km[k] / kn[k] if kn[k] else None) for k in km}
-    dom = max(("interp", "spread", "ftot"), key=lambda k: km[k] / max(kn[k], 1))
+    # the kernel with the largest share of the step (the spreading pass: n_iter
+    # launches; the f_tot spreading, one launch of the same kernel, is
+    # reported per launch beside it)
+    dom = max(("interp", "spread", "ftot"), key=lambda k: km[k])
     bytes_launch = algorithmic_bytes(dom, 4, n_act, shell, n_iter)
     achieved = bytes_launch / (per_launch[dom] * 1e-3) / 1e9
     traffic = measured_traffic(args.workload, dom, r32["tile"])
