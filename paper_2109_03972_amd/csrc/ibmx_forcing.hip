@@ -1009,7 +1009,18 @@ struct SpreadAcc<double> {
 // workgroup, owner of its nodes, applies u += c f (add_u) and f_tot += f
 // (add_f) with plain loads and stores.
 // ---------------------------------------------------------------------------
-template <typename T, int W>
+// element i of a grid component: with O32 (every component spans less than
+// 4 GB) a 32-bit byte offset from the component's uniform base, which the
+// loads and stores take as is; otherwise a 64-bit index
+template <typename T, bool O32>
+__device__ __forceinline__ T &grid_at(T *base, unsigned i)
+{
+    if (O32)
+        return *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + i * (unsigned)sizeof(T));
+    return base[(size_t)i];
+}
+
+template <typename T, int W, bool O32>
 __global__ __launch_bounds__(256) void k_spread(GridC g, TileC tc, T c, int add_u, int add_f,
                                                 int count_shell,
                                                 const int *__restrict__ tile_start,
@@ -1131,9 +1142,8 @@ __global__ __launch_bounds__(256) void k_spread(GridC g, TileC tc, T c, int add_
                     const int lx = ix[0][i] - box.o[0];
                     if ((unsigned)lx >= (unsigned)box.e[0])
                         continue;
+                    // a zero weight adds an integer 0: no test for it
                     const T ww = wzy * w[0][i];
-                    if (ww == T(0))
-                        continue;
                     const int li = rowl + lx;
                     SpreadAcc<T>::add(acc, V, li, ww * Gs[0], ww * Gs[1], ww * Gs[2]);
                 }
@@ -1145,8 +1155,11 @@ __global__ __launch_bounds__(256) void k_spread(GridC g, TileC tc, T c, int add_
     int touched = 0;
     const int wave = threadIdx.x / IBMX_WAVE;
     const TileWalk tw(tc, box.e[0]);
+    // component bases (node indices fit 32 bits: the grid has < 2^31 nodes)
+    T *const ub[3] = {u, u ? u + N : nullptr, u ? u + 2 * N : nullptr};
+    T *const fb[3] = {f_tot, f_tot ? f_tot + N : nullptr, f_tot ? f_tot + 2 * N : nullptr};
     for (int r0 = wave * tw.rpi + tw.sub; r0 < tw.rows; r0 += UNR * tw.nw * tw.rpi) {
-        long long gi[UNR];
+        unsigned gi[UNR];
         bool act[UNR];
         T fv[UNR][3], fo[UNR][3], uo[UNR][3];
 #pragma unroll
@@ -1156,21 +1169,20 @@ __global__ __launch_bounds__(256) void k_spread(GridC g, TileC tc, T c, int add_
             tw.yz(r, tc.B[1], ly, lz);
             const int li = (lz * tc.B[1] + ly) * tc.B[0] + tw.lx;
             act[q] = tw.lane_ok && r < tw.rows && ly < box.e[1] && lz < box.e[2];
-            gi[q] = ((long long)(box.o[2] + lz) * g.n[1] + (box.o[1] + ly)) * g.n[0] +
-                    (box.o[0] + tw.lx);
+            gi[q] = ((unsigned)(box.o[2] + lz) * (unsigned)g.n[1] + (unsigned)(box.o[1] + ly)) *
+                        (unsigned)g.n[0] +
+                    (unsigned)(box.o[0] + tw.lx);
             if (act[q])
                 act[q] = SpreadAcc<T>::get(acc, V, li, unscale, fv[q]);
             if (act[q]) {
-                if (add_f) {
-                    fo[q][0] = f_tot[gi[q]];
-                    fo[q][1] = f_tot[N + gi[q]];
-                    fo[q][2] = f_tot[2 * N + gi[q]];
-                }
-                if (add_u) {
-                    uo[q][0] = u[gi[q]];
-                    uo[q][1] = u[N + gi[q]];
-                    uo[q][2] = u[2 * N + gi[q]];
-                }
+                if (add_f)
+#pragma unroll
+                    for (int a = 0; a < 3; ++a)
+                        fo[q][a] = grid_at<T, O32>(fb[a], gi[q]);
+                if (add_u)
+#pragma unroll
+                    for (int a = 0; a < 3; ++a)
+                        uo[q][a] = grid_at<T, O32>(ub[a], gi[q]);
             }
         }
 #pragma unroll
@@ -1178,16 +1190,14 @@ __global__ __launch_bounds__(256) void k_spread(GridC g, TileC tc, T c, int add_
             if (!act[q])
                 continue;
             ++touched;
-            if (add_f) {
-                f_tot[gi[q]] = fo[q][0] + fv[q][0];
-                f_tot[N + gi[q]] = fo[q][1] + fv[q][1];
-                f_tot[2 * N + gi[q]] = fo[q][2] + fv[q][2];
-            }
-            if (add_u) {
-                u[gi[q]] = uo[q][0] + c * fv[q][0];
-                u[N + gi[q]] = uo[q][1] + c * fv[q][1];
-                u[2 * N + gi[q]] = uo[q][2] + c * fv[q][2];
-            }
+            if (add_f)
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    grid_at<T, O32>(fb[a], gi[q]) = fo[q][a] + fv[q][a];
+            if (add_u)
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    grid_at<T, O32>(ub[a], gi[q]) = uo[q][a] + c * fv[q][a];
         }
     }
     if (count_shell)
@@ -1513,6 +1523,16 @@ void bin_markers(ibmx_plan p, const double *xp, const double *up, const double *
     }
 }
 
+// k_spread with 32-bit grid offsets when every component spans less than 4 GB
+template <typename T, int W, typename... A>
+void spread_launch(ibmx_plan p, size_t lds, hipStream_t s, A... args)
+{
+    if ((unsigned long long)p->g.nodes * sizeof(T) < (1ULL << 32))
+        hipLaunchKernelGGL((k_spread<T, W, true>), dim3(p->tc.ntiles), dim3(256), lds, s, args...);
+    else
+        hipLaunchKernelGGL((k_spread<T, W, false>), dim3(p->tc.ntiles), dim3(256), lds, s, args...);
+}
+
 template <typename T, int W>
 ibmx_status run_forcing(ibmx_plan p, T *u, T *f_tot, const double *xp, const double *up,
                         const double *wp, const uint8_t *mask, double *S_out, double *T_out,
@@ -1551,7 +1571,7 @@ ibmx_status run_forcing(ibmx_plan p, T *u, T *f_tot, const double *xp, const dou
                                    tmax);
         }
         ProfScope ps(p, IBMX_K_SPREAD);
-        hipLaunchKernelGGL((k_spread<T, W>), dim3(ntiles), dim3(256), lds_s, s, p->g, tc, (T)c, 1,
+        spread_launch<T, W>(p, lds_s, s, p->g, tc, (T)c, 1,
                            n_iter == 1 ? 1 : 0, m == 0 ? 1 : 0, p->tile_start, p->halo_start,
                            p->halo_list, (const T4 *)rec_tn, (const T4 *)rec_Gp, tmax_pass, u,
                            f_tot, p->d_count);
@@ -1559,7 +1579,7 @@ ibmx_status run_forcing(ibmx_plan p, T *u, T *f_tot, const double *xp, const dou
     if (n_iter >= 2 && nm > 0) {
         // f_tot += spread of the amplitudes summed over the passes
         ProfScope ps(p, IBMX_K_FTOT);
-        hipLaunchKernelGGL((k_spread<T, W>), dim3(ntiles), dim3(256), lds_s, s, p->g, tc, (T)c, 0,
+        spread_launch<T, W>(p, lds_s, s, p->g, tc, (T)c, 0,
                            1, 0, p->tile_start, p->halo_start, p->halo_list, (const T4 *)rec_tn,
                            (const T4 *)rec_Gs, tmax_sum, u, f_tot, p->d_count);
     }
@@ -1637,7 +1657,7 @@ ibmx_status run_backward(ibmx_plan p, const T *u0, const double *xp, const doubl
                                c, p->tile_start, (const T4 *)rec_tn, (const T4 *)rec_ud,
                                (const T *)us, GJm);
             if (m < n_iter - 1)
-                hipLaunchKernelGGL((k_spread<T, W>), dim3(ntiles), dim3(256), lds_s, s, p->g, tc,
+                spread_launch<T, W>(p, lds_s, s, p->g, tc,
                                    (T)c, 1, 0, 0, p->tile_start, p->halo_start, p->halo_list,
                                    (const T4 *)rec_tn, (const T4 *)GJm, (const float4 *)nullptr,
                                    us, (T *)nullptr, p->d_count);
@@ -1654,7 +1674,7 @@ ibmx_status run_backward(ibmx_plan p, const T *u0, const double *xp, const doubl
                                    tc, nm, np, c, p->tile_start, (const T4 *)rec_tn,
                                    p->rec_src, p->body, p->d_pid, p->dV, g_S, g_T,
                                    (const T *)gu0, g_f, GJm, rec_Ub, accA, accB);
-            hipLaunchKernelGGL((k_spread<T, W>), dim3(ntiles), dim3(256), lds_s, s, p->g, tc, T(1), 1,
+            spread_launch<T, W>(p, lds_s, s, p->g, tc, T(1), 1,
                                0, 0, p->tile_start, p->halo_start, p->halo_list, (const T4 *)rec_tn,
                                (const T4 *)rec_Ub, (const float4 *)nullptr, gu0, (T *)nullptr,
                                p->d_count);
@@ -1671,9 +1691,11 @@ template <typename T, int W>
 hipError_t allow_lds_w(int bytes_interp, int bytes_spread)
 {
     hipError_t e;
-    if ((e = hipFuncSetAttribute((const void *)k_spread<T, W>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, bytes_spread)) != hipSuccess)
-        return e;
+    const void *spreads[] = {(const void *)k_spread<T, W, true>, (const void *)k_spread<T, W, false>};
+    for (const void *f : spreads)
+        if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes_spread)) !=
+            hipSuccess)
+            return e;
     const void *interps[] = {(const void *)k_interp<T, W, 0>,     (const void *)k_interp<T, W, 1>,
                              (const void *)k_interp<T, W, 2>,     (const void *)k_interp_jac<T, W>,
                              (const void *)k_interp_adj<T, W, 0>, (const void *)k_interp_adj<T, W, 1>};
