@@ -488,6 +488,26 @@ __device__ __forceinline__ V block_max(V v)
     return r;   // valid in every thread
 }
 
+// Element i of a grid component: with O32 (every component spans less than
+// 4 GB) a 32-bit byte offset from the component's uniform base, which the
+// loads and stores take as is; otherwise a 64-bit index.  Node indices fit 32
+// bits (the grid has fewer than 2^31 nodes).
+template <typename T, bool O32>
+__device__ __forceinline__ T &grid_at(T *base, unsigned i)
+{
+    if (O32)
+        return *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + i * (unsigned)sizeof(T));
+    return base[(size_t)i];
+}
+template <typename V, typename T, bool O32>
+__device__ __forceinline__ const V &grid_at_as(const T *base, unsigned i)
+{
+    if (O32)
+        return *reinterpret_cast<const V *>(reinterpret_cast<const char *>(base) +
+                                            i * (unsigned)sizeof(T));
+    return *reinterpret_cast<const V *>(base + (size_t)i);
+}
+
 // LDS layout of a staged region of RV nodes: (x, y) pairs of every node,
 // then the z components, so that a node is read with two LDS loads
 template <typename T>
@@ -524,7 +544,7 @@ __device__ __forceinline__ void reg_get(const T *reg, int RV, int idx, T &x, T &
 // [o - 1, o + B + W - 2) per axis into LDS (nodes beyond a wall read 0),
 // element by element: each wave loads 64 / R0 rows of R0 nodes per step, and
 // every thread issues SUNR steps of loads before its LDS stores.
-template <typename T, int W>
+template <typename T, int W, bool O32>
 __device__ __forceinline__ void stage_region_rows(const GridC &g, const TileC &tc,
                                                   const TileBox &box, const T *__restrict__ src,
                                                   T scale, const T *__restrict__ src2, T *reg)
@@ -532,6 +552,8 @@ __device__ __forceinline__ void stage_region_rows(const GridC &g, const TileC &t
     const int R0 = tc.B[0] + W - 1, R1 = tc.B[1] + W - 1, R2 = tc.B[2] + W - 1;
     const int RV = R0 * R1 * R2;
     const long long N = g.nodes;
+    const T *const s1[3] = {src, src + N, src + 2 * N};
+    const T *const s2[3] = {src2, src2 ? src2 + N : nullptr, src2 ? src2 + 2 * N : nullptr};
     const int lane = threadIdx.x & (IBMX_WAVE - 1), wave = threadIdx.x / IBMX_WAVE;
     const int nw = blockDim.x / IBMX_WAVE;
     const int rpi = IBMX_WAVE / R0;
@@ -563,14 +585,13 @@ __device__ __forceinline__ void stage_region_rows(const GridC &g, const TileC &t
                 ok = ok && gz >= 0 && gz < g.n[2];
             v[q][0] = v[q][1] = v[q][2] = T(0);
             if (ok) {
-                const long long gi = ((long long)gz * g.n[1] + gy) * g.n[0] + gx;
-                v[q][0] = scale * src[gi];
-                v[q][1] = scale * src[N + gi];
-                v[q][2] = scale * src[2 * N + gi];
-                if (src2) {
-                    v[q][0] += src2[gi];
-                    v[q][1] += src2[N + gi];
-                    v[q][2] += src2[2 * N + gi];
+                const unsigned gi =
+                    ((unsigned)gz * (unsigned)g.n[1] + (unsigned)gy) * (unsigned)g.n[0] + (unsigned)gx;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    v[q][c] = scale * grid_at_as<T, T, O32>(s1[c], gi);
+                    if (src2)
+                        v[q][c] += grid_at_as<T, T, O32>(s2[c], gi);
                 }
             }
         }
@@ -595,7 +616,7 @@ struct alignas(16) Pack16 {
 // edge value by value (wrapped on a periodic axis, 0 beyond a wall).  Needs
 // n_x and the field pointers to be multiples of E values / 16 bytes.
 constexpr int VUNR = 5;   // row groups per vector staging step
-template <typename T, int W>
+template <typename T, int W, bool O32>
 __device__ __forceinline__ void stage_region_vec(const GridC &g, const TileC &tc,
                                                  const TileBox &box, const T *__restrict__ src,
                                                  T scale, const T *__restrict__ src2, T *reg)
@@ -604,6 +625,8 @@ __device__ __forceinline__ void stage_region_vec(const GridC &g, const TileC &tc
     const int R0 = tc.B[0] + W - 1, R1 = tc.B[1] + W - 1, R2 = tc.B[2] + W - 1;
     const int RV = R0 * R1 * R2;
     const long long N = g.nodes;
+    const T *const s1[3] = {src, src + N, src + 2 * N};
+    const T *const s2[3] = {src2, src2 ? src2 + N : nullptr, src2 ? src2 + 2 * N : nullptr};
     const int xs = box.o[0] - 1, xe = box.o[0] + R0 - 1;   // needed x range
     const int X0 = xs >= 0 ? xs - xs % E : -E;               // xs >= -1
     const int nch = (xe + E - 1 - X0) / E;                 // packets per row (xe > 0)
@@ -640,14 +663,13 @@ __device__ __forceinline__ void stage_region_vec(const GridC &g, const TileC &tc
                     v[q][c].e[k] = T(0);
             if (!ok)
                 continue;
-            const long long row = ((long long)gz * g.n[1] + gy) * g.n[0];
+            const unsigned row = ((unsigned)gz * (unsigned)g.n[1] + (unsigned)gy) * (unsigned)g.n[0];
             if (whole) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    v[q][c] = *reinterpret_cast<const Pack16<T> *>(src + c * N + row + x);
+                    v[q][c] = grid_at_as<Pack16<T>, T, O32>(s1[c], row + (unsigned)x);
                     if (src2) {
-                        const Pack16<T> w2 =
-                            *reinterpret_cast<const Pack16<T> *>(src2 + c * N + row + x);
+                        const Pack16<T> w2 = grid_at_as<Pack16<T>, T, O32>(s2[c], row + (unsigned)x);
 #pragma unroll
                         for (int k = 0; k < E; ++k)
                             v[q][c].e[k] = scale * v[q][c].e[k] + w2.e[k];
@@ -669,9 +691,9 @@ __device__ __forceinline__ void stage_region_vec(const GridC &g, const TileC &tc
                         continue;
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                        T val = scale * src[c * N + row + gx];
+                        T val = scale * grid_at_as<T, T, O32>(s1[c], row + (unsigned)gx);
                         if (src2)
-                            val += src2[c * N + row + gx];
+                            val += grid_at_as<T, T, O32>(s2[c], row + (unsigned)gx);
                         v[q][c].e[k] = val;
                     }
                 }
@@ -692,7 +714,7 @@ __device__ __forceinline__ void stage_region_vec(const GridC &g, const TileC &tc
     }
 }
 
-template <typename T, int W>
+template <typename T, int W, bool O32 = false>
 __device__ __forceinline__ void stage_region(const GridC &g, const TileC &tc, const TileBox &box,
                                              const T *__restrict__ src, T scale,
                                              const T *__restrict__ src2, T *reg)
@@ -701,9 +723,9 @@ __device__ __forceinline__ void stage_region(const GridC &g, const TileC &tc, co
     const bool vec = g.n[0] % E == 0 && ((size_t)src & 15) == 0 &&
                      (!src2 || ((size_t)src2 & 15) == 0);
     if (vec)
-        stage_region_vec<T, W>(g, tc, box, src, scale, src2, reg);
+        stage_region_vec<T, W, O32>(g, tc, box, src, scale, src2, reg);
     else
-        stage_region_rows<T, W>(g, tc, box, src, scale, src2, reg);
+        stage_region_rows<T, W, O32>(g, tc, box, src, scale, src2, reg);
 }
 
 // Region index of a marker's base node per axis: the centre node b + 1 lies
@@ -757,7 +779,7 @@ __device__ __forceinline__ void block_max6(V *v)   // result in thread 0
         }
 }
 
-template <typename T, int W, int MODE>
+template <typename T, int W, int MODE, bool O32>
 __global__ __launch_bounds__(256) void k_interp(
     GridC g, TileC tc, int nm, int pass, double c, const int *__restrict__ tile_start,
     const typename V4<T>::type *__restrict__ rec_tn, const typename V4<T>::type *__restrict__ rec_ud,
@@ -789,7 +811,7 @@ __global__ __launch_bounds__(256) void k_interp(
         if (MODE == 1)
             gs = rec_Gs[a0 + threadIdx.x];
     }
-    stage_region<T, W>(g, tc, box, u, T(1), (const T *)nullptr, reg);
+    stage_region<T, W, O32>(g, tc, box, u, T(1), (const T *)nullptr, reg);
     __syncthreads();
     double rsq = 0.0;
     float gmax[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -1009,17 +1031,6 @@ struct SpreadAcc<double> {
 // workgroup, owner of its nodes, applies u += c f (add_u) and f_tot += f
 // (add_f) with plain loads and stores.
 // ---------------------------------------------------------------------------
-// element i of a grid component: with O32 (every component spans less than
-// 4 GB) a 32-bit byte offset from the component's uniform base, which the
-// loads and stores take as is; otherwise a 64-bit index
-template <typename T, bool O32>
-__device__ __forceinline__ T &grid_at(T *base, unsigned i)
-{
-    if (O32)
-        return *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + i * (unsigned)sizeof(T));
-    return base[(size_t)i];
-}
-
 template <typename T, int W, bool O32>
 __global__ __launch_bounds__(256) void k_spread(GridC g, TileC tc, T c, int add_u, int add_f,
                                                 int count_shell,
@@ -1523,14 +1534,32 @@ void bin_markers(ibmx_plan p, const double *xp, const double *up, const double *
     }
 }
 
-// k_spread with 32-bit grid offsets when every component spans less than 4 GB
+// k_spread and k_interp with 32-bit grid offsets when every component spans
+// less than 4 GB
+template <typename T>
+bool offsets32(ibmx_plan p)
+{
+    return (unsigned long long)p->g.nodes * sizeof(T) < (1ULL << 32);
+}
+
 template <typename T, int W, typename... A>
 void spread_launch(ibmx_plan p, size_t lds, hipStream_t s, A... args)
 {
-    if ((unsigned long long)p->g.nodes * sizeof(T) < (1ULL << 32))
+    if (offsets32<T>(p))
         hipLaunchKernelGGL((k_spread<T, W, true>), dim3(p->tc.ntiles), dim3(256), lds, s, args...);
     else
         hipLaunchKernelGGL((k_spread<T, W, false>), dim3(p->tc.ntiles), dim3(256), lds, s, args...);
+}
+
+template <typename T, int W, int MODE, typename... A>
+void interp_launch(ibmx_plan p, size_t lds, hipStream_t s, A... args)
+{
+    if (offsets32<T>(p))
+        hipLaunchKernelGGL((k_interp<T, W, MODE, true>), dim3(p->tc.ntiles), dim3(256), lds, s,
+                           args...);
+    else
+        hipLaunchKernelGGL((k_interp<T, W, MODE, false>), dim3(p->tc.ntiles), dim3(256), lds, s,
+                           args...);
 }
 
 template <typename T, int W>
@@ -1560,12 +1589,12 @@ ibmx_status run_forcing(ibmx_plan p, T *u, T *f_tot, const double *xp, const dou
         {
             ProfScope ps(p, IBMX_K_INTERP);
             if (m == 0)
-                hipLaunchKernelGGL((k_interp<T, W, 0>), dim3(ntiles), dim3(256), lds_i, s, p->g, tc,
+                interp_launch<T, W, 0>(p, lds_i, s, p->g, tc,
                                    nm, m, c, p->tile_start, (const T4 *)rec_tn, (const T4 *)rec_ud,
                                    p->rec_src, (const T *)u, rec_Gp, rec_Gs, p->d_acc, U_dbg,
                                    tmax);
             else
-                hipLaunchKernelGGL((k_interp<T, W, 1>), dim3(ntiles), dim3(256), lds_i, s, p->g, tc,
+                interp_launch<T, W, 1>(p, lds_i, s, p->g, tc,
                                    nm, m, c, p->tile_start, (const T4 *)rec_tn, (const T4 *)rec_ud,
                                    p->rec_src, (const T *)u, rec_Gp, rec_Gs, p->d_acc, U_dbg,
                                    tmax);
@@ -1593,7 +1622,7 @@ ibmx_status run_forcing(ibmx_plan p, T *u, T *f_tot, const double *xp, const dou
     if (resid_out) {
         if (nm > 0) {
             ProfScope ps(p, IBMX_K_OTHER);
-            hipLaunchKernelGGL((k_interp<T, W, 2>), dim3(ntiles), dim3(256), lds_i, s, p->g, tc, nm,
+            interp_launch<T, W, 2>(p, lds_i, s, p->g, tc, nm,
                                n_iter, c, p->tile_start, (const T4 *)rec_tn, (const T4 *)rec_ud,
                                p->rec_src, (const T *)u, rec_Gp, rec_Gs, p->d_acc, (T *)nullptr,
                                (float4 *)nullptr);
@@ -1696,8 +1725,13 @@ hipError_t allow_lds_w(int bytes_interp, int bytes_spread)
         if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes_spread)) !=
             hipSuccess)
             return e;
-    const void *interps[] = {(const void *)k_interp<T, W, 0>,     (const void *)k_interp<T, W, 1>,
-                             (const void *)k_interp<T, W, 2>,     (const void *)k_interp_jac<T, W>,
+    const void *interps[] = {(const void *)k_interp<T, W, 0, true>,
+                             (const void *)k_interp<T, W, 1, true>,
+                             (const void *)k_interp<T, W, 2, true>,
+                             (const void *)k_interp<T, W, 0, false>,
+                             (const void *)k_interp<T, W, 1, false>,
+                             (const void *)k_interp<T, W, 2, false>,
+                             (const void *)k_interp_jac<T, W>,
                              (const void *)k_interp_adj<T, W, 0>, (const void *)k_interp_adj<T, W, 1>};
     for (const void *f : interps)
         if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes_interp)) !=
