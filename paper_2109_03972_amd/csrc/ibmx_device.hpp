@@ -27,7 +27,14 @@ struct TileC {
     int B[3];
     int nt[3];
     int ntiles;
+    int sh[3];   // log2 B[a] when B[a] is a power of two, else -1
 };
+
+// tile coordinate of node x along axis a
+__device__ __forceinline__ int tile_of(const TileC &tc, int a, int x)
+{
+    return tc.sh[a] >= 0 ? x >> tc.sh[a] : x / tc.B[a];
+}
 
 // ---------------------------------------------------------------------------
 // device helpers

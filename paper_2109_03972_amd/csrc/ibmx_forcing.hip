@@ -120,7 +120,7 @@ __device__ __forceinline__ int home_tile(const GridC &g, const TileC &tc, const 
 {
     int ti[3];
     for (int a = 0; a < 3; ++a)
-        ti[a] = axis_node(g, a, b[a], 1) / tc.B[a];
+        ti[a] = tile_of(tc, a, axis_node(g, a, b[a], 1));
     return ti[0] + tc.nt[0] * (ti[1] + tc.nt[1] * ti[2]);
 }
 
@@ -222,9 +222,9 @@ __device__ __forceinline__ int halo_tiles(const GridC &g, const TileC &tc, const
     int tl[3][2], nt[3], home[3];
     for (int a = 0; a < 3; ++a) {
         const int last = tt[a] == T(0) ? W - 2 : W - 1;
-        home[a] = axis_node(g, a, b[a], 1) / tc.B[a];
-        const int t0 = axis_node(g, a, b[a], 0) / tc.B[a];
-        const int t1 = axis_node(g, a, b[a], last) / tc.B[a];
+        home[a] = tile_of(tc, a, axis_node(g, a, b[a], 1));
+        const int t0 = tile_of(tc, a, axis_node(g, a, b[a], 0));
+        const int t1 = tile_of(tc, a, axis_node(g, a, b[a], last));
         tl[a][0] = t0;
         tl[a][1] = t1;
         nt[a] = t1 == t0 ? 1 : 2;

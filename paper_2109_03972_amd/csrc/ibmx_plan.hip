@@ -298,6 +298,10 @@ ibmx_status ibmx_plan_alloc_tiles(ibmx_plan p, int tx, int ty, int tz)
     for (int a = 0; a < 3; ++a) {
         p->tc.B[a] = t[a];
         p->tc.nt[a] = nt[a];
+        p->tc.sh[a] = -1;
+        for (int k = 0; k < 31; ++k)
+            if ((1 << k) == t[a])
+                p->tc.sh[a] = k;
         p->stats.tile[a] = t[a];
     }
     p->tc.ntiles = (int)ntiles;
