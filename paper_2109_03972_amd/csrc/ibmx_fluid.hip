@@ -196,6 +196,13 @@ __device__ __forceinline__ int log2i_dev(int n)
     return l;
 }
 
+// LDS lines are padded by one element every 16: element j of a line sits at
+// pad16(j), so that the bit-reversed stores and the short-span butterflies,
+// whose addresses are multiples of large powers of two apart, spread over the
+// banks; a line of n elements takes plen(n).
+__host__ __device__ __forceinline__ int pad16(int j) { return j + (j >> 4); }
+__host__ __device__ __forceinline__ int plen(int n) { return n + (n >> 4); }
+
 // In-place complex FFT of `lines` lines of length n = 2^logn held in LDS in
 // bit-reversed order, line l at buf + l * ls: iterative radix-2 Cooley-Tukey,
 // two stages per pass (the four elements i, i + half, i + len, i + len + half
@@ -217,20 +224,23 @@ __device__ void fft_lds(double2 *buf, int n, int ls, int lines, const double2 *_
         const int half = len >> 1, quarter_n = n / 4;
         for (int b = threadIdx.x; b < lines * quarter_n; b += blockDim.x) {
             const int l = b / quarter_n, q = b % quarter_n, pos = q % half;
-            const int i0 = l * ls + (q / half) * (2 * len) + pos;
+            const int j0 = (q / half) * (2 * len) + pos;
+            double2 *lb = buf + l * ls;
+            const int p0 = pad16(j0), p1 = pad16(j0 + half), p2 = pad16(j0 + len),
+                      p3 = pad16(j0 + len + half);
             const double2 w1 = w(pos * (n / len)), w2 = w(pos * (n / (2 * len))),
                           w3 = w((pos + half) * (n / (2 * len)));
-            const double2 a0 = buf[i0], a1 = cmul(buf[i0 + half], w1);
-            const double2 a2 = buf[i0 + len], a3 = cmul(buf[i0 + len + half], w1);
+            const double2 a0 = lb[p0], a1 = cmul(lb[p1], w1);
+            const double2 a2 = lb[p2], a3 = cmul(lb[p3], w1);
             const double2 b0 = make_double2(a0.x + a1.x, a0.y + a1.y);
             const double2 b1 = make_double2(a0.x - a1.x, a0.y - a1.y);
             const double2 b2 = make_double2(a2.x + a3.x, a2.y + a3.y);
             const double2 b3 = make_double2(a2.x - a3.x, a2.y - a3.y);
             const double2 c2 = cmul(b2, w2), c3 = cmul(b3, w3);
-            buf[i0] = make_double2(b0.x + c2.x, b0.y + c2.y);
-            buf[i0 + len] = make_double2(b0.x - c2.x, b0.y - c2.y);
-            buf[i0 + half] = make_double2(b1.x + c3.x, b1.y + c3.y);
-            buf[i0 + len + half] = make_double2(b1.x - c3.x, b1.y - c3.y);
+            lb[p0] = make_double2(b0.x + c2.x, b0.y + c2.y);
+            lb[p2] = make_double2(b0.x - c2.x, b0.y - c2.y);
+            lb[p1] = make_double2(b1.x + c3.x, b1.y + c3.y);
+            lb[p3] = make_double2(b1.x - c3.x, b1.y - c3.y);
         }
         __syncthreads();
     }
@@ -238,11 +248,13 @@ __device__ void fft_lds(double2 *buf, int n, int ls, int lines, const double2 *_
         const int half = len >> 1;
         for (int b = threadIdx.x; b < lines * half_n; b += blockDim.x) {
             const int l = b / half_n, jj = b % half_n, pos = jj % half;
-            const int i0 = l * ls + (jj / half) * len + pos, i1 = i0 + half;
+            const int j0 = (jj / half) * len + pos;
+            double2 *lb = buf + l * ls;
+            const int p0 = pad16(j0), p1 = pad16(j0 + half);
             const double2 wk = w(pos * (n / len));
-            const double2 v0 = buf[i0], v1 = cmul(buf[i1], wk);
-            buf[i0] = make_double2(v0.x + v1.x, v0.y + v1.y);
-            buf[i1] = make_double2(v0.x - v1.x, v0.y - v1.y);
+            const double2 v0 = lb[p0], v1 = cmul(lb[p1], wk);
+            lb[p0] = make_double2(v0.x + v1.x, v0.y + v1.y);
+            lb[p1] = make_double2(v0.x - v1.x, v0.y - v1.y);
         }
         __syncthreads();
     }
@@ -301,7 +313,7 @@ struct ScaledOut {
 // r[2m] + i r[2m + 1] form N2 complex values whose FFT Z gives the row's
 // modes X[k] = (Z[k] + Z*[N2 - k])/2 - i w^k (Z[k] - Z*[N2 - k])/2, k = 0..N2,
 // w = exp(-2 pi i / nx).  `rows` consecutive rows per workgroup (row r = z ny
-// + y), held in LDS with a stride of N2 + 1; the modes go out y-fastest, mode
+// + y), held in LDS with a stride of plen(N2) + 1; the modes go out y-fastest, mode
 // k of row r at (z mx + k) ny + y, consecutive threads taking consecutive
 // rows.
 template <class Src>
@@ -310,7 +322,7 @@ __global__ __launch_bounds__(kFftThreads) void k_rfft_x(Src src, double2 *__rest
                                                         const double2 *__restrict__ tw)
 {
     extern __shared__ double2 buf[];
-    const int N2 = nx / 2, logn = log2i_dev(N2), mx = N2 + 1, ls = N2 + 1;
+    const int N2 = nx / 2, logn = log2i_dev(N2), mx = N2 + 1, ls = plen(N2) + 1;
     const long long row0 = (long long)blockIdx.x * rows;
     const int nr = (int)(nrows - row0 < rows ? nrows - row0 : rows);
     const long long ymask = (1LL << logny) - 1;
@@ -321,14 +333,14 @@ __global__ __launch_bounds__(kFftThreads) void k_rfft_x(Src src, double2 *__rest
     src.prepare();
     for (int e = threadIdx.x; e < nr * N2; e += blockDim.x) {
         const int l = e >> logn, m = e & (N2 - 1);
-        buf[l * ls + bitrev(m, logn)] = src(row0 * N2 + e);
+        buf[l * ls + pad16(bitrev(m, logn))] = src(row0 * N2 + e);
     }
     __syncthreads();
     fft_lds<false>(buf, N2, ls, nr, twl, 2);
     for (int e = threadIdx.x; e < nr * mx; e += blockDim.x) {
         const int k = e / nr, l = e - k * nr;
-        const double2 zk = buf[l * ls + (k == N2 ? 0 : k)];
-        const double2 zc = buf[l * ls + (k == 0 ? 0 : N2 - k)];
+        const double2 zk = buf[l * ls + pad16(k == N2 ? 0 : k)];
+        const double2 zc = buf[l * ls + pad16(k == 0 ? 0 : N2 - k)];
         const double2 sum = make_double2(0.5 * (zk.x + zc.x), 0.5 * (zk.y - zc.y));
         const double2 dif = make_double2(0.5 * (zk.x - zc.x), 0.5 * (zk.y + zc.y));
         // -i w^k dif, w^k = tw[k] of the nx-point table (k <= N2: its last entry
@@ -351,7 +363,7 @@ __global__ __launch_bounds__(kFftThreads) void k_irfft_x(const double2 *__restri
                                                          const double2 *__restrict__ tw)
 {
     extern __shared__ double2 buf[];
-    const int N2 = nx / 2, logn = log2i_dev(N2), mx = N2 + 1, ls = N2 + 1;
+    const int N2 = nx / 2, logn = log2i_dev(N2), mx = N2 + 1, ls = plen(N2) + 1;
     const long long row0 = (long long)blockIdx.x * rows;
     const int nr = (int)(nrows - row0 < rows ? nrows - row0 : rows);
     const long long ymask = (1LL << logny) - 1;
@@ -369,13 +381,13 @@ __global__ __launch_bounds__(kFftThreads) void k_irfft_x(const double2 *__restri
         double2 wk = tw[k];
         wk.y = -wk.y;
         const double2 O = cmul(D, wk);
-        buf[l * ls + bitrev(k, logn)] = make_double2(E.x - O.y, E.y + O.x);
+        buf[l * ls + pad16(bitrev(k, logn))] = make_double2(E.x - O.y, E.y + O.x);
     }
     __syncthreads();
     fft_lds<true>(buf, N2, ls, nr, twl, 2);
     for (int e = threadIdx.x; e < nr * N2; e += blockDim.x) {
         const int l = e >> logn, m = e & (N2 - 1);
-        dst(row0 * N2 + e, buf[l * ls + m]);
+        dst(row0 * N2 + e, buf[l * ls + pad16(m)]);
     }
 }
 
@@ -392,16 +404,17 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_lines(double2 *__restrict__
     const long long L0 = (long long)blockIdx.x * lpw;
     const int nl = (int)(nlines - L0 < lpw ? nlines - L0 : lpw);
     double2 *Zb = Z + L0 * n;
+    const int ls = plen(n);
     // the n/2 twiddles the transform uses, after the lines
-    double2 *twl = buf + (size_t)lpw * n;
+    double2 *twl = buf + (size_t)lpw * ls;
     for (int e = threadIdx.x; e < n / 2; e += blockDim.x)
         twl[e] = tw[e];
     for (int e = threadIdx.x; e < nl * n; e += blockDim.x)
-        buf[(e >> logn) * n + bitrev(e & (n - 1), logn)] = Zb[e];
+        buf[(e >> logn) * ls + pad16(bitrev(e & (n - 1), logn))] = Zb[e];
     __syncthreads();
-    fft_lds<INV>(buf, n, n, nl, twl, 1);
+    fft_lds<INV>(buf, n, ls, nl, twl, 1);
     for (int e = threadIdx.x; e < nl * n; e += blockDim.x)
-        Zb[e] = buf[e];
+        Zb[e] = buf[(e >> logn) * ls + pad16(e & (n - 1))];
 }
 
 // Complex FFT along a strided axis: each plane holds `A` lines, line a of
@@ -421,18 +434,19 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_strided(double2 *__restrict
     const int a0 = (int)(blockIdx.x % groups) * lpw;
     const int nl = A - a0 < lpw ? A - a0 : lpw;
     const long long base = q * B + (long long)a0 * C;
-    double2 *twl = buf + (size_t)lpw * n;
+    const int ls = plen(n);
+    double2 *twl = buf + (size_t)lpw * ls;
     for (int e = threadIdx.x; e < n / 2; e += blockDim.x)
         twl[e] = tw[e];
     for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
         const int l = e % nl, sidx = e / nl;
-        buf[l * n + bitrev(sidx, logn)] = Z[base + l * C + sidx * S];
+        buf[l * ls + pad16(bitrev(sidx, logn))] = Z[base + l * C + sidx * S];
     }
     __syncthreads();
-    fft_lds<INV>(buf, n, n, nl, twl, 1);
+    fft_lds<INV>(buf, n, ls, nl, twl, 1);
     for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
         const int l = e % nl, sidx = e / nl;
-        Z[base + l * C + sidx * S] = buf[l * n + sidx];
+        Z[base + l * C + sidx * S] = buf[l * ls + pad16(sidx)];
     }
 }
 
@@ -726,7 +740,7 @@ void fft_axis(ibmx_plan p, const FluidC &F, int a, hipStream_t s)
         if (lpw > nlines)
             lpw = (int)nlines;
         hipLaunchKernelGGL((k_fft_lines<INV>), dim3((unsigned)((nlines + lpw - 1) / lpw)),
-                           dim3(kFftThreads), sizeof(double2) * ((size_t)lpw * n + n / 2), s, p->fl_z, n,
+                           dim3(kFftThreads), sizeof(double2) * ((size_t)lpw * plen(n) + n / 2), s, p->fl_z, n,
                            lpw, nlines, (const double2 *)p->fl_tw[1]);
         return;
     }
@@ -734,7 +748,7 @@ void fft_axis(ibmx_plan p, const FluidC &F, int a, hipStream_t s)
     if (lpw > A)
         lpw = A;
     hipLaunchKernelGGL((k_fft_strided<INV>), dim3((unsigned)((A + lpw - 1) / lpw)),
-                       dim3(kFftThreads), sizeof(double2) * ((size_t)lpw * n + n / 2), s, p->fl_z, n, lpw,
+                       dim3(kFftThreads), sizeof(double2) * ((size_t)lpw * plen(n) + n / 2), s, p->fl_z, n, lpw,
                        A, 0LL, 1LL, (long long)A, (const double2 *)p->fl_tw[2]);
 }
 
@@ -753,11 +767,11 @@ RowLaunch row_launch(const FluidC &F)
     // at least kMinRows rows (each mode's writes cover that many consecutive
     // y), within 64 KB of LDS with the N2 twiddles
     r.rows = N2 * kMinRows >= kRowElems ? kMinRows : kRowElems / N2;
-    const int fit = (int)((65536 / sizeof(double2) - N2) / (N2 + 1));
+    const int fit = (int)((65536 / sizeof(double2) - N2) / (plen(N2) + 1));
     if (r.rows > fit)
         r.rows = fit;
     r.blocks = (unsigned)((r.nrows + r.rows - 1) / r.rows);
-    r.lds = sizeof(double2) * ((size_t)r.rows * (N2 + 1) + N2);
+    r.lds = sizeof(double2) * ((size_t)r.rows * (plen(N2) + 1) + N2);
     r.logny = 0;
     while ((1 << r.logny) < F.n[1])
         ++r.logny;
