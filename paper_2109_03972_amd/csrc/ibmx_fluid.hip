@@ -33,9 +33,29 @@ struct FluidC {
     double ih, ih2, i2h, ic;   // 1/h, 1/h^2, 1/(2h), 1/c: the stencils multiply
 };
 
-__device__ __forceinline__ long long cell_index(const FluidC &F, int i, int j, int k)
+// index of cell (i, j, k) (solver grids have fewer than 2^31 cells)
+__device__ __forceinline__ unsigned cell32(const FluidC &F, int i, int j, int k)
 {
-    return ((long long)k * F.n[1] + j) * F.n[0] + i;
+    return ((unsigned)k * (unsigned)F.n[1] + (unsigned)j) * (unsigned)F.n[0] + (unsigned)i;
+}
+
+// element i of a field: with O32 (every field spans less than 4 GB) a 32-bit
+// byte offset from the field's uniform base, which the loads and stores take
+// as is; otherwise a 64-bit index
+template <bool O32, typename T>
+__device__ __forceinline__ T &fat(T *base, unsigned i)
+{
+    if (O32)
+        return *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + i * (unsigned)sizeof(T));
+    return base[(size_t)i];
+}
+template <bool O32, typename T>
+__device__ __forceinline__ const T &fat(const T *base, unsigned i)
+{
+    if (O32)
+        return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) +
+                                            i * (unsigned)sizeof(T));
+    return base[(size_t)i];
 }
 
 // Stencil kernels that need neighbours in all three axes march a PX x PY
@@ -80,7 +100,7 @@ struct Column {
 // NF fields of one rim-extended plane, in registers between the load from
 // memory and the store into a ring slot; zeros outside the grid (kk < 0 is
 // the plane behind a wall)
-template <typename T, int NF>
+template <typename T, int NF, bool O32>
 struct PlaneStage {
     static constexpr int kSlots = (PY + 2) * (PX + 2), kPre = (kSlots + PX * PY - 1) / (PX * PY);
     T pre[kPre][NF];
@@ -98,9 +118,9 @@ struct PlaneStage {
             if (F.periodic[1])
                 gj = gj < 0 ? gj + ny : (gj >= ny ? gj - ny : gj);
             const bool in = kk >= 0 && gi >= 0 && gi < nx && gj >= 0 && gj < ny;
-            const long long o = ((long long)kk * ny + gj) * nx + gi;
+            const unsigned o = ((unsigned)kk * (unsigned)ny + (unsigned)gj) * (unsigned)nx + (unsigned)gi;
             for (int q = 0; q < NF; ++q)
-                pre[r][q] = in ? fld[q][o] : T(0);
+                pre[r][q] = in ? fat<O32>(fld[q], o) : T(0);
         }
     }
     __device__ void store(T (*ring)[NF][PY + 2][PX + 2], int sl) const
@@ -146,7 +166,7 @@ dim3 column_grid(const FluidC &F)
 
 // u_f* = mean of the two cells of each +a face (wall faces 0), and the
 // right-hand side div(u_f*) / c
-template <typename T>
+template <typename T, bool O32>
 __global__ __launch_bounds__(PX * PY) void k_face_div(FluidC F, const T *__restrict__ u,
                                                       T *__restrict__ uf, double *__restrict__ R)
 {
@@ -154,7 +174,8 @@ __global__ __launch_bounds__(PX * PY) void k_face_div(FluidC F, const T *__restr
     const long long N = (long long)F.n[0] * F.n[1] * F.n[2];
     const Column col(F);
     const T *fld[3] = {u, u + N, u + 2 * N};
-    PlaneStage<T, 3> st;
+    T *const ufb[3] = {uf, uf + N, uf + 2 * N};
+    PlaneStage<T, 3, O32> st;
     st.prologue(F, fld, col, ring);
     for (int k = col.k0; k < col.k1; ++k) {
         st.store(ring, col.slot(k + 1));
@@ -166,7 +187,7 @@ __global__ __launch_bounds__(PX * PY) void k_face_div(FluidC F, const T *__restr
         const int sd = col.slot(k - 1), sc = col.slot(k), su = col.slot(k + 1);
         const bool in_p[3] = {col.in_p[0], col.in_p[1], z_up(F, k) >= 0};
         const bool in_m[3] = {col.in_m[0], col.in_m[1], z_dn(F, k) >= 0};
-        const long long c = cell_index(F, col.i, col.j, k);
+        const unsigned c = cell32(F, col.i, col.j, k);
         double div = 0.0;
         for (int a = 0; a < 3; ++a) {
             const double uc = (double)ring[sc][a][col.ty + 1][col.tx + 1];
@@ -176,10 +197,10 @@ __global__ __launch_bounds__(PX * PY) void k_face_div(FluidC F, const T *__restr
             const double in =
                 in_m[a] ? 0.5 * ((double)ring_nb<T, 3>(ring, col, sd, sc, su, a, a, -1) + uc)
                         : 0.0;
-            uf[(size_t)a * N + c] = (T)out;
+            fat<O32>(ufb[a], c) = (T)out;
             div = div + (out - in) * F.ih;
         }
-        R[c] = div * F.ic;
+        fat<O32>(R, c) = div * F.ic;
     }
 }
 
@@ -536,7 +557,7 @@ __global__ __launch_bounds__(256) void k_tridiag(FluidC F, double s0, double s1,
 // gradients), u_f = u_f* - c (phi_+ - phi)/h, P = (1 - theta) P + phi -
 // (c/2) nu L phi.  phi passes through the plane ring; the own cell's u,
 // u_f and P of the next plane are loaded while a plane is computed.
-template <typename T>
+template <typename T, bool O32>
 __global__ __launch_bounds__(PX * PY) void k_correct(FluidC F, const double *__restrict__ Z,
                                                      double scale, T *__restrict__ u,
                                                      T *__restrict__ uf, T *__restrict__ P,
@@ -546,16 +567,17 @@ __global__ __launch_bounds__(PX * PY) void k_correct(FluidC F, const double *__r
     const long long N = (long long)F.n[0] * F.n[1] * F.n[2];
     const Column col(F);
     const double *fld[1] = {Z};
-    PlaneStage<double, 1> st;
+    T *const ub[3] = {u, u + N, u + 2 * N}, *const ufb[3] = {uf, uf + N, uf + 2 * N};
+    PlaneStage<double, 1, O32> st;
     st.prologue(F, fld, col, ring);
     // own u (3), u_f (3) and P of plane kk
     auto own = [&](T *v, int kk) {
-        const long long c = cell_index(F, col.i, col.j, kk);
+        const unsigned c = cell32(F, col.i, col.j, kk);
         for (int a = 0; a < 3; ++a) {
-            v[a] = col.live ? u[(size_t)a * N + c] : T(0);
-            v[3 + a] = col.live ? uf[(size_t)a * N + c] : T(0);
+            v[a] = col.live ? fat<O32>(ub[a], c) : T(0);
+            v[3 + a] = col.live ? fat<O32>(ufb[a], c) : T(0);
         }
-        v[6] = col.live ? P[c] : T(0);
+        v[6] = col.live ? fat<O32>(P, c) : T(0);
     };
     T ow[7], oq[7] = {0, 0, 0, 0, 0, 0, 0};
     own(ow, col.k0);
@@ -570,7 +592,7 @@ __global__ __launch_bounds__(PX * PY) void k_correct(FluidC F, const double *__r
             const int sd = col.slot(k - 1), sc = col.slot(k), su = col.slot(k + 1);
             const bool in_p[3] = {col.in_p[0], col.in_p[1], z_up(F, k) >= 0};
             const bool in_m[3] = {col.in_m[0], col.in_m[1], z_dn(F, k) >= 0};
-            const long long c = cell_index(F, col.i, col.j, k);
+            const unsigned c = cell32(F, col.i, col.j, k);
             const double ph = ring[sc][0][col.ty + 1][col.tx + 1] * scale;
             double lap = 0.0;
             for (int a = 0; a < 3; ++a) {
@@ -580,14 +602,13 @@ __global__ __launch_bounds__(PX * PY) void k_correct(FluidC F, const double *__r
                 const double gm =
                     in_m[a] ? (ph - ring_nb<double, 1>(ring, col, sd, sc, su, 0, a, -1) * scale) * F.ih
                             : 0.0;
-                const size_t ia = (size_t)a * N + c;
-                u[ia] = (T)((double)ow[a] - F.c * (0.5 * (gp + gm)));
-                uf[ia] = (T)((double)ow[3 + a] - F.c * gp);
+                fat<O32>(ub[a], c) = (T)((double)ow[a] - F.c * (0.5 * (gp + gm)));
+                fat<O32>(ufb[a], c) = (T)((double)ow[3 + a] - F.c * gp);
                 lap = lap + (gp - gm) * F.ih;
             }
-            P[c] = (T)((1.0 - F.theta) * (double)ow[6] + ph - 0.5 * F.c * F.nu * lap);
+            fat<O32>(P, c) = (T)((1.0 - F.theta) * (double)ow[6] + ph - 0.5 * F.c * F.nu * lap);
             if (phi_out)
-                phi_out[c] = (T)ph;
+                fat<O32>(phi_out, c) = (T)ph;
         }
         for (int q = 0; q < 7; ++q)
             ow[q] = oq[q];
@@ -599,7 +620,7 @@ __global__ __launch_bounds__(PX * PY) void k_correct(FluidC F, const double *__r
 // u and P pass through the plane ring (values held in T, widened to double
 // where they are used); N_prev of the next plane is loaded while a plane is
 // computed.
-template <typename T>
+template <typename T, bool O32>
 __global__ __launch_bounds__(PX * PY) void k_predict(FluidC F, const T *__restrict__ u,
                                                      T *__restrict__ ut, T *__restrict__ Nbuf,
                                                      T *__restrict__ lapnu,
@@ -610,13 +631,15 @@ __global__ __launch_bounds__(PX * PY) void k_predict(FluidC F, const T *__restri
     const long long N = (long long)F.n[0] * F.n[1] * F.n[2];
     const Column col(F);
     const T *fld[4] = {u, u + N, u + 2 * N, P};
-    PlaneStage<T, 4> st;
+    T *const nb[3] = {Nbuf, Nbuf + N, Nbuf + 2 * N};
+    T *const utb[3] = {ut, ut + N, ut + 2 * N}, *const lb[3] = {lapnu, lapnu + N, lapnu + 2 * N};
+    PlaneStage<T, 4, O32> st;
     st.prologue(F, fld, col, ring);
     // N_prev of the own cell on plane kk
     auto own_n = [&](T *v, int kk) {
-        const long long c = cell_index(F, col.i, col.j, kk);
+        const unsigned c = cell32(F, col.i, col.j, kk);
         for (int b = 0; b < 3; ++b)
-            v[b] = col.live ? Nbuf[(size_t)b * N + c] : T(0);
+            v[b] = col.live ? fat<O32>(nb[b], c) : T(0);
     };
     T Np[3], Nq[3] = {0, 0, 0};
     own_n(Np, col.k0);
@@ -631,7 +654,7 @@ __global__ __launch_bounds__(PX * PY) void k_predict(FluidC F, const T *__restri
             const int sd = col.slot(k - 1), sc = col.slot(k), su = col.slot(k + 1);
             const bool in_p[3] = {col.in_p[0], col.in_p[1], z_up(F, k) >= 0};
             const bool in_m[3] = {col.in_m[0], col.in_m[1], z_dn(F, k) >= 0};
-            const long long c = cell_index(F, col.i, col.j, k);
+            const unsigned c = cell32(F, col.i, col.j, k);
             double ua[3];
             for (int q = 0; q < 3; ++q)
                 ua[q] = (double)ring[sc][q][col.ty + 1][col.tx + 1];
@@ -656,12 +679,11 @@ __global__ __launch_bounds__(PX * PY) void k_predict(FluidC F, const T *__restri
                     in_m[b] ? (pc - (double)ring_nb<T, 4>(ring, col, sd, sc, su, 3, b, -1)) * F.ih
                             : 0.0;
                 const double gP = 0.5 * (gp + gm);
-                const size_t ib = (size_t)b * N + c;
                 const double ln = F.nu * lap;
-                ut[ib] = (T)(ub + dt * (2.0 * alpha * ln - 2.0 * alpha * gP - gamma * adv -
-                                        zeta * (double)Np[b]));
-                Nbuf[ib] = (T)adv;
-                lapnu[ib] = (T)ln;
+                fat<O32>(utb[b], c) = (T)(ub + dt * (2.0 * alpha * ln - 2.0 * alpha * gP -
+                                                     gamma * adv - zeta * (double)Np[b]));
+                fat<O32>(nb[b], c) = (T)adv;
+                fat<O32>(lb[b], c) = (T)ln;
             }
         }
         for (int b = 0; b < 3; ++b)
@@ -674,7 +696,7 @@ __global__ __launch_bounds__(PX * PY) void k_predict(FluidC F, const T *__restri
 // lapnu of the next plane loaded while a plane is computed.  (With theta = 0
 // there is no pressure term and the x pass computes the right-hand side as
 // it reads: HelmRhsIn.)
-template <typename T>
+template <typename T, bool O32>
 __global__ __launch_bounds__(PX * PY) void k_helm_rhs(FluidC F, const T *__restrict__ u,
                                                       const T *__restrict__ lapnu,
                                                       const T *__restrict__ P,
@@ -686,13 +708,13 @@ __global__ __launch_bounds__(PX * PY) void k_helm_rhs(FluidC F, const T *__restr
     const long long N = (long long)F.n[0] * F.n[1] * F.n[2];
     const Column col(F);
     const T *fld[1] = {P};
-    PlaneStage<T, 1> st;
+    PlaneStage<T, 1, O32> st;
     st.prologue(F, fld, col, ring);
     const T *ub = u + (size_t)b * N, *lb = lapnu + (size_t)b * N;
     auto own = [&](T *v, int kk) {
-        const long long c = cell_index(F, col.i, col.j, kk);
-        v[0] = col.live ? ub[c] : T(0);
-        v[1] = col.live ? lb[c] : T(0);
+        const unsigned c = cell32(F, col.i, col.j, kk);
+        v[0] = col.live ? fat<O32>(ub, c) : T(0);
+        v[1] = col.live ? fat<O32>(lb, c) : T(0);
     };
     const double fb = fbar ? fbar[b] : 0.0;
     T ow[2], oq[2] = {0, 0};
@@ -715,7 +737,7 @@ __global__ __launch_bounds__(PX * PY) void k_helm_rhs(FluidC F, const T *__restr
             const double gm =
                 hm ? (pc - (double)ring_nb<T, 1>(ring, col, sd, sc, su, 0, b, -1)) * F.ih : 0.0;
             const double gP = 0.5 * (gp + gm);
-            R[cell_index(F, col.i, col.j, k)] =
+            fat<O32>(R, cell32(F, col.i, col.j, k)) =
                 (double)ow[0] - F.c * fb +
                 dt * (-alpha * (double)ow[1] + 2.0 * alpha * F.theta * gP);
         }
@@ -843,19 +865,33 @@ double spectrum_scale(const FluidC &F)
     return scale;
 }
 
+// stencil kernels with 32-bit field offsets when every field (the FP64 real
+// grid included) spans less than 4 GB
+bool fields32(const FluidC &F)
+{
+    return (unsigned long long)F.n[0] * F.n[1] * F.n[2] * sizeof(double) < (1ULL << 32);
+}
+
+#define IBMX_STENCIL_LAUNCH(K, T, F, s, ...)                                                     \
+    do {                                                                                        \
+        if (fields32(F))                                                                         \
+            hipLaunchKernelGGL((K<T, true>), column_grid(F), dim3(PX * PY), 0, s, F, __VA_ARGS__);  \
+        else                                                                                     \
+            hipLaunchKernelGGL((K<T, false>), column_grid(F), dim3(PX * PY), 0, s, F, __VA_ARGS__); \
+    } while (0)
+
 template <typename T>
 ibmx_status run_project(ibmx_plan p, T *u, T *uf, T *P, T *phi, double theta)
 {
     const FluidC F = fluid_constants(p, theta);
     hipStream_t s = p->stream;
     ProfScope ps(p, IBMX_K_OTHER);
-    hipLaunchKernelGGL((k_face_div<T>), column_grid(F), dim3(PX * PY), 0, s, F, (const T *)u, uf,
-                       p->fl_r);
+    IBMX_STENCIL_LAUNCH(k_face_div, T, F, s, (const T *)u, uf, p->fl_r);
     rows_forward(p, F, RealIn{p->fl_r}, s);
     solve_spectrum(p, F, 0.0, 1.0, 0, s);
     rows_inverse(p, F, RealOut{p->fl_r}, s);
-    hipLaunchKernelGGL((k_correct<T>), column_grid(F), dim3(PX * PY), 0, s, F,
-                       (const double *)p->fl_r, spectrum_scale(F), u, uf, P, phi);
+    IBMX_STENCIL_LAUNCH(k_correct, T, F, s, (const double *)p->fl_r, spectrum_scale(F), u, uf, P,
+                        phi);
     return ibmx_launch_check();
 }
 
@@ -866,8 +902,7 @@ ibmx_status run_predict(ibmx_plan p, const T *u, T *ut, T *Nbuf, T *lapnu, const
     const FluidC F = fluid_constants(p, 0.0);
     const double alpha = F.c / (2.0 * dt);
     ProfScope ps(p, IBMX_K_OTHER);
-    hipLaunchKernelGGL((k_predict<T>), column_grid(F), dim3(PX * PY), 0, p->stream, F,
-                       u, ut, Nbuf, lapnu, P, dt, alpha, gamma, zeta);
+    IBMX_STENCIL_LAUNCH(k_predict, T, F, p->stream, u, ut, Nbuf, lapnu, P, dt, alpha, gamma, zeta);
     return ibmx_launch_check();
 }
 
@@ -884,8 +919,8 @@ ibmx_status run_helmholtz(ibmx_plan p, T *u, const T *lapnu, const T *P, const d
         // the right-hand side: with a pressure term through the plane ring
         // into the real grid, without it computed by the x pass as it reads
         if (F.theta != 0.0) {
-            hipLaunchKernelGGL((k_helm_rhs<T>), column_grid(F), dim3(PX * PY), 0, s, F,
-                               (const T *)u, lapnu, P, fbar, b, dt, alpha, p->fl_r);
+            IBMX_STENCIL_LAUNCH(k_helm_rhs, T, F, s, (const T *)u, lapnu, P, fbar, b, dt, alpha,
+                                p->fl_r);
             rows_forward(p, F, RealIn{p->fl_r}, s);
         } else {
             HelmRhsIn<T> in;

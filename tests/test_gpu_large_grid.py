@@ -114,3 +114,89 @@ def test_component_over_4gb_matches_periodic_window(precision, n):
     for name, got in (("u", u_s), ("f_tot", f_s), ("S", S_s), ("T", T_s)):
         e = rel_err(got.double().cpu().numpy(), ref[name])
         assert e <= tol, f"{name}: {e:.3e}"
+
+
+def test_fluid_steps_over_4gb():
+    """The fluid stencils on a 1024 x 1024 x 512 grid with walls in z (FP32
+    fields; the FP64 real grid spans 4 GB, so they address by 64-bit
+    offsets): predictor planes at the walls and in the middle against the
+    oracle run on the three-plane slab around each, the projected faces
+    divergence-free to FP32 rounding, and the implicit step (pressure term
+    included) leaving the real-space residual of its equation at FP32
+    rounding on sampled planes."""
+    import torch
+    from oracle import fluid_stage as fs
+    dev = require_gpu()
+    n = (1024, 1024, 512)
+    nx, ny, nz = n
+    assert nx * ny * nz * 8 >= 1 << 32
+    case = _case(n, [100.5, 200.5, 300.5])
+    case.periodic = (1, 1, 0)
+    alpha, gamma, zeta, dt = 1.0 / 15.0, 5.0 / 12.0, -17.0 / 60.0, 1.0
+    prm = dict(case.params)
+    prm["c"] = 2.0 * alpha * dt
+    prm["nu_f"] = 0.3
+    case.params = prm
+    plan = ibmx.Plan.from_case(case, "f32")
+    g = torch.Generator(device=dev).manual_seed(5)
+    u = torch.randn((3, nz, ny, nx), device=dev, generator=g)
+    Nb = (0.1 * torch.randn((3, nz, ny, nx), device=dev, generator=g)).contiguous()
+    P = (0.01 * torch.randn((nz, ny, nx), device=dev, generator=g)).contiguous()
+    N0 = Nb.clone()
+    ut, lapnu = plan.fluid_predictor(u, Nb, P, dt, gamma, zeta)
+    plan.check("predictor")
+    torch.cuda.synchronize()
+    for k in (0, 1, nz // 2, nz - 2, nz - 1):
+        lo, hi = max(k - 1, 0), min(k + 2, nz)
+        ref = fs.predictor(u[:, lo:hi].double().cpu().numpy(), N0[:, lo:hi].double().cpu().numpy(),
+                           P[lo:hi].double().cpu().numpy(), case.h, prm["nu_f"], alpha, gamma,
+                           zeta, dt, (1, 1, 0))
+        for name, got in (("u", ut), ("N", Nb), ("lapnu", lapnu)):
+            e = rel_err(got[:, k].double().cpu().numpy(), ref[name][:, k - lo])
+            assert e <= 2e-6, f"plane {k} {name}: {e:.3e}"
+    del N0, Nb
+    # implicit step with the pressure term; residual on sampled planes
+    rhs_u = ut.clone()
+    plan.fluid_helmholtz(ut, lapnu, P, dt, 1.0)
+    plan.check("helmholtz")
+    torch.cuda.synchronize()
+    beta = alpha * dt * prm["nu_f"]
+    for k in (0, nz // 3, nz - 1):
+        lo, hi = max(k - 1, 0), min(k + 2, nz)
+        for b in range(3):
+            us = ut[b, lo:hi].double()
+            m = k - lo
+            lap = torch.zeros_like(us[m])
+            for ax in (0, 1):
+                lap += (torch.roll(us[m], -1, dims=ax) - 2.0 * us[m] + torch.roll(us[m], 1, dims=ax))
+            up = us[m + 1] if k + 1 < nz else -us[m]
+            dn = us[m - 1] if k > 0 else -us[m]
+            lap += up - 2.0 * us[m] + dn
+            Pd = P[lo:hi].double()
+            if b == 2:
+                gp = (Pd[m + 1] - Pd[m]) if k + 1 < nz else torch.zeros_like(Pd[m])
+                gm = (Pd[m] - Pd[m - 1]) if k > 0 else torch.zeros_like(Pd[m])
+            else:
+                ax = 1 - b   # x is the last axis of a plane, y the first
+                gp = torch.roll(Pd[m], -1, dims=ax) - Pd[m]
+                gm = Pd[m] - torch.roll(Pd[m], 1, dims=ax)
+            rhs = rhs_u[b, k].double() + dt * (-alpha * lapnu[b, k].double() + alpha * (gp + gm))
+            res = (us[m] - beta * lap - rhs).abs().max().item() / rhs.abs().max().item()
+            assert res <= 1e-5, f"helmholtz plane {k} component {b}: {res:.3e}"
+    del rhs_u, lapnu, ut
+    # projection of the first velocity: faces divergence-free
+    Pz = torch.zeros((nz, ny, nx), device=dev)
+    uf, _ = plan.project(u, Pz, 0.0, want_phi=False)
+    plan.check("project")
+    torch.cuda.synchronize()
+    worst = 0.0
+    for k in (0, nz // 2, nz - 1):
+        div = torch.zeros((ny, nx), dtype=torch.float64, device=dev)
+        div += uf[0, k].double() - torch.roll(uf[0, k].double(), 1, dims=1)
+        div += uf[1, k].double() - torch.roll(uf[1, k].double(), 1, dims=0)
+        div += uf[2, k].double() - (uf[2, k - 1].double() if k > 0 else 0.0)
+        worst = max(worst, div.abs().max().item())
+    scale = uf.abs().max().item()
+    assert worst <= 1e-5 * scale, f"max |div u_f| {worst:.3e} (scale {scale:.3e})"
+    assert torch.all(uf[2][-1] == 0)
+    plan.close()
