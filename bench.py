@@ -4,8 +4,9 @@ One step = the pair pass (cell/pair/wall lists, collision forces, marker
 mask) + one ibmx_forcing call (marker geometry, then n_iter passes of
 interpolate -> force -> spread -> update) on the resident synthetic workload.
 The tile shape is autotuned first (ibmx_tune, untimed).  The steps are timed
-twice: as eager calls with per-kernel HIP events (the headline value and the
-roofline), then with the forcing call replayed as one HIP graph.
+three times: as eager calls with per-kernel HIP events (the roofline's kernel
+durations), with the forcing call replayed as one HIP graph, and as eager
+calls without the events (the headline value).
 The reported value is whole-step throughput in marker-updates/s
 (active markers x passes / step time).  Also reported: the FP64 instance of
 the same kernels, per-kernel durations from HIP events recorded by the
