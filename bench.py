@@ -325,7 +325,27 @@ def cpu_baseline(case, mask_np):
     del u0
     return dict(value=n_act / t, unit="marker-updates/s", cores=1, kind="oracle",
                 sample=f"1 forcing pass over all {n_act} active markers of the workload on its "
-                       f"full {case.n[0]}x{case.n[1]}x{case.n[2]} grid ({t:.1f} s)")
+                       f"full {case.n[0]}x{case.n[1]}x{case.n[2]} grid ({t:.1f} s)",
+                host=host_cpu())
+
+
+def host_cpu():
+    """The host the CPU baseline ran on: threads this process may use and the
+    processor model."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        threads = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        threads = os.cpu_count()
+    return dict(threads_available=threads, cpu_model=model)
 
 
 def main():
