@@ -12,8 +12,9 @@
 // fastest, mode (kx, y, z) at (z (nx/2 + 1) + kx) ny + y, so that the y
 // passes read whole contiguous lines and the x passes, taking 8 or more
 // consecutive rows per workgroup, read and write runs of consecutive y.  FFTs
-// are radix-2 passes in place in LDS, several lines per workgroup.  Stencil kernels take one thread per cell with x along
-// the block and y, z along the grid.
+// are radix-2 passes in place in LDS, several lines per workgroup.  The
+// stencil kernels march columns of cells up in z through a ring of planes in
+// LDS.
 #include <math.h>
 #include <vector>
 
@@ -33,7 +34,7 @@ struct FluidC {
     double ih, ih2, i2h, ic;   // 1/h, 1/h^2, 1/(2h), 1/c: the stencils multiply
 };
 
-// index of cell (i, j, k) (solver grids have fewer than 2^31 cells)
+// index of cell (i, j, k) (a plan's grid has fewer than 2^31 cells)
 __device__ __forceinline__ unsigned cell32(const FluidC &F, int i, int j, int k)
 {
     return ((unsigned)k * (unsigned)F.n[1] + (unsigned)j) * (unsigned)F.n[0] + (unsigned)i;
@@ -334,9 +335,9 @@ struct ScaledOut {
 // r[2m] + i r[2m + 1] form N2 complex values whose FFT Z gives the row's
 // modes X[k] = (Z[k] + Z*[N2 - k])/2 - i w^k (Z[k] - Z*[N2 - k])/2, k = 0..N2,
 // w = exp(-2 pi i / nx).  `rows` consecutive rows per workgroup (row r = z ny
-// + y), held in LDS with a stride of plen(N2) + 1; the modes go out y-fastest, mode
-// k of row r at (z mx + k) ny + y, consecutive threads taking consecutive
-// rows.
+// + y), held in LDS with a stride of plen(N2) + 1; the modes go out
+// y-fastest, mode k of row r at (z mx + k) ny + y, consecutive threads taking
+// consecutive rows.
 template <class Src>
 __global__ __launch_bounds__(kFftThreads) void k_rfft_x(Src src, double2 *__restrict__ H, int nx,
                                                         int logny, int rows, long long nrows,
@@ -495,8 +496,9 @@ __global__ __launch_bounds__(256) void k_divide(FluidC F, double s0, double s1,
     }
 }
 
-// walls in z: per (kx, ky) mode (kx = 0 .. nx/2; modes y-fastest) the system s0 x + s1 (D_z + lambda_xy) x =
-// rhs, D_z the second difference (1/h^2)(x_{k+1} - 2 x_k + x_{k-1}) closed
+// walls in z: per (kx, ky) mode (kx = 0 .. nx/2; modes y-fastest) the system
+// s0 x + s1 (D_z + lambda_xy) x = rhs, D_z the second difference
+// (1/h^2)(x_{k+1} - 2 x_k + x_{k-1}) closed
 // at the walls by a zero gradient (Neumann, the pressure) or by the ghost
 // -x (no slip, the velocity), solved by elimination from the bottom.  The
 // Neumann system with s0 = 0 is singular in the (0, 0) mode: its top value
