@@ -89,9 +89,9 @@ def fluid_bytes(kind: str, s: int, nodes: int, walls_z: bool = True) -> float:
 
     spectrum (one solve between the x passes): the y pass forward and back
            (read and write 8 each: 16 + 16), and across walls the elimination
-           (read and write the spectrum twice, the eliminated coefficient
-           once each way: 40) or along a periodic z two more passes and the
-           division (48).
+           (read and write the spectrum twice: 32; the eliminated coefficient
+           is stored only until it becomes constant along z, not counted) or
+           along a periodic z two more passes and the division (48).
     predictor: reads u, N (3s each) and P (s); writes u~, N and nu L u (3s each).
     project: face values and divergence (reads 3s, writes 3s + 8), the
            forward x pass from the real grid (read 8, write 8), the spectrum,
@@ -103,7 +103,7 @@ def fluid_bytes(kind: str, s: int, nodes: int, walls_z: bool = True) -> float:
            (2s + 8), the spectrum, the inverse x pass writing the result
            (8 + s).
     """
-    spectrum = 16 + 16 + (40 if walls_z else 48)
+    spectrum = 16 + 16 + (32 if walls_z else 48)
     if kind == "predictor":
         per = 16 * s
     elif kind == "project":

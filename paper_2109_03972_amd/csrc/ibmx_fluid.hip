@@ -503,7 +503,10 @@ __global__ __launch_bounds__(256) void k_divide(FluidC F, double s0, double s1,
 // -x (no slip, the velocity), solved by elimination from the bottom.  The
 // Neumann system with s0 = 0 is singular in the (0, 0) mode: its top value
 // is pinned to 0, then its z-mean removed (the grid mean of phi).  cp holds
-// the eliminated super-diagonal.
+// the eliminated super-diagonal.  The interior rows have the same
+// coefficients, so once the eliminated super-diagonal repeats exactly on an
+// interior row it keeps that value up to the last interior row: it is stored
+// only up to there and the back substitution takes the constant beyond.
 __global__ __launch_bounds__(256) void k_tridiag(FluidC F, double s0, double s1, int dirichlet,
                                                  double2 *__restrict__ Z, double *__restrict__ cp)
 {
@@ -515,7 +518,8 @@ __global__ __launch_bounds__(256) void k_tridiag(FluidC F, double s0, double s1,
     const double ih2 = 1.0 / (F.h * F.h);
     const double lxy = lam(i, F.n[0], F.h) + lam(j, F.n[1], F.h);
     const bool singular = col == 0 && s0 == 0.0 && !dirichlet;
-    double cprev = 0.0;
+    double cprev = 0.0, cconv = 0.0;
+    int kconv = nz;   // first row of the constant super-diagonal
     double2 dprev = make_double2(0.0, 0.0);
     for (int k = 0; k < nz; ++k) {
         const size_t c = (size_t)k * nxy + col;
@@ -531,9 +535,16 @@ __global__ __launch_bounds__(256) void k_tridiag(FluidC F, double s0, double s1,
             d = make_double2(0.0, 0.0);
         }
         const double den = b - a * cprev;
-        cprev = sup / den;
+        const double cnew = sup / den;
         dprev = make_double2((d.x - a * dprev.x) / den, (d.y - a * dprev.y) / den);
-        cp[c] = cprev;
+        if (k < kconv) {
+            cp[c] = cnew;
+            if (k >= 2 && k <= nz - 2 && cnew == cprev) {
+                kconv = k;
+                cconv = cnew;
+            }
+        }
+        cprev = cnew;
         Z[c] = dprev;
     }
     double2 x = dprev;
@@ -541,7 +552,8 @@ __global__ __launch_bounds__(256) void k_tridiag(FluidC F, double s0, double s1,
     for (int k = nz - 2; k >= 0; --k) {
         const size_t c = (size_t)k * nxy + col;
         const double2 d = Z[c];
-        x = make_double2(d.x - cp[c] * x.x, d.y - cp[c] * x.y);
+        const double ck = k > kconv ? cconv : cp[c];
+        x = make_double2(d.x - ck * x.x, d.y - ck * x.y);
         Z[c] = x;
         sum.x += x.x;
         sum.y += x.y;
