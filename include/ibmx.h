@@ -458,7 +458,9 @@ IBMX_API ibmx_status ibmx_particle_substeps(ibmx_plan plan, double dt_total, int
  * across walls in z a tridiagonal elimination per Fourier mode.  Needs
  * periodic x and y with power-of-two sizes up to 1024 (and the same for z
  * when periodic), else EUNSUPPORTED.  The first call allocates the plan's
- * projection workspace (a complex FP64 grid, an FP64 grid when z has walls).
+ * solver workspace: an FP64 real grid, the FP64 complex half spectrum
+ * (nx/2 + 1 modes per row), with walls in z an FP64 grid of elimination
+ * coefficients of the same shape, and one twiddle table per axis.
  */
 IBMX_API ibmx_status ibmx_project(ibmx_plan plan, void *u, void *uf, void *P, void *phi,
                                   double theta);
