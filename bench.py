@@ -364,7 +364,7 @@ def main():
                          "hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (--gpus 1); the forcing loop is not "
+        print("bench.py: the library runs on one GPU only (--gpus 1); the forcing loop is not "
               "sharded across GPUs", file=sys.stderr)
         sys.exit(2)
     import numpy as np
