@@ -123,3 +123,27 @@ def test_hertz_model_and_impact_history(e_dry):
                      whist=ref_f["whist"])
     second = _gpu_pairs(c, prev=first["dev"], plan=first["plan"])
     _check(c, second, prev_host=prev_host, ftol=1e-11)
+
+
+@pytest.mark.parametrize("layout", ["one_near_wall", "one_overlapping_wall", "two_apart"])
+def test_lists_without_pairs(layout):
+    """Degenerate pair passes: a single particle (no pair possible) near or
+    pressed into the lower wall, and two particles farther apart than the
+    cut-off in a periodic box (empty pair and wall lists, zero forces, no
+    marker disabled)."""
+    if layout == "two_apart":
+        c = synth.small_case(204, n=(48, 40, 44), periodic=(1, 1, 1), diameters=(10.0, 8.0),
+                             min_gap=6.0)
+    else:
+        c = synth.small_case(205, n=(40, 36, 44), periodic=(1, 1, 0), diameters=(10.0,))
+        c.xp[2, 0] = float(c.radius[0]) + (0.6 if layout == "one_near_wall" else -0.2)
+    got = _gpu_pairs(c)
+    ref_l, _ = _check(c, got)
+    assert got["pairs"].shape[1] == 0
+    if layout == "two_apart":
+        assert got["walls"].shape[1] == 0
+        assert np.all(got["Fc"] == 0.0) and np.all(got["Tc"] == 0.0)
+        assert np.all(got["mask"] == 1)
+    else:
+        assert got["walls"].shape[1] == 1
+        assert (got["wgap"][0] < 0) == (layout == "one_overlapping_wall")
