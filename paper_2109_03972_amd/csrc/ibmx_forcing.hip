@@ -139,30 +139,6 @@ __device__ __forceinline__ void stencil(const GridC &g, unsigned node, const T *
     }
 }
 
-// U = sum over the W^3 stencil of w u (one velocity grid, three components)
-template <typename T, int W>
-__device__ __forceinline__ void gather(const GridC &g, const int ix[3][W], const T w[3][W],
-                                       const T *__restrict__ u, T *U)
-{
-    const long long N = g.nodes;
-    U[0] = U[1] = U[2] = T(0);
-#pragma unroll
-    for (int k = 0; k < W; ++k)
-#pragma unroll
-        for (int jj = 0; jj < W; ++jj) {
-            const T wzy = w[2][k] * w[1][jj];
-            const long long row = ((long long)ix[2][k] * g.n[1] + ix[1][jj]) * g.n[0];
-#pragma unroll
-            for (int i = 0; i < W; ++i) {
-                const T ww = wzy * w[0][i];
-                const long long nd = row + ix[0][i];
-                U[0] += ww * u[nd];
-                U[1] += ww * u[N + nd];
-                U[2] += ww * u[2 * N + nd];
-            }
-        }
-}
-
 // Marker force from the interpolated velocity: F = (U^d - U)/c in FP64 with
 // U^d = u_p + omega_p x o and dV taken from the marker's record; rsq
 // receives dV |U^d - U|^2 and G = F dV / h^3 is returned.
