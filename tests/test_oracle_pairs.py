@@ -277,3 +277,76 @@ def test_whole_mode_removes_all_markers_of_one(oracle_lib):
     assert (m1[50 * loser:50 * loser + 50] == 0).sum() > 0
     assert (m1[50 * (1 - loser):50 * (1 - loser) + 50] == 0).sum() == 0
     assert np.all(oracle_lib.marker_mask(c, pl, mode=0) == 1)
+
+
+def _wall_slide(oracle_lib, v0, steps, dt_int, nu_poi, overlap=0.05, mass=1.0, R=4.0,
+                hold_velocity=False):
+    """A sphere pressed into the lower z wall by a fixed overlap, rotation
+    frozen, moving along x: only the tangential force changes its velocity
+    (the normal one is balanced by holding the height).  Returns the time
+    series of (x-velocity, tangential spring, F_x, F_z) over the evaluations,
+    with the history passed from each evaluation to the next."""
+    x = np.array([[10.0], [10.0], [R - overlap]])
+    wl = dict(pairs=np.zeros((2, 0), np.int32), gap=np.zeros(0),
+              walls=np.array([[0], [4]], np.int32), wgap=np.array([-overlap]))
+    prev = dict(pairs=np.zeros((2, 0), np.int32), hist=np.zeros((4, 0)),
+                walls=np.zeros((2, 0), np.int32), whist=np.zeros((4, 0)))
+    u = v0
+    out = []
+    for _ in range(steps):
+        c = _pcase(x, [R], periodic=(1, 1, 0), mass=[mass],
+                   up=np.array([[u], [0.0], [0.0]]), dt=dt_int, nu_poi=nu_poi, nu_f=0.0)
+        f = oracle_lib.pair_forces(c, wl, prev=prev)
+        prev = dict(pairs=prev["pairs"], hist=prev["hist"], walls=wl["walls"], whist=f["whist"])
+        out.append((u, f["whist"][0, 0], f["Fc"][0, 0], f["Fc"][2, 0]))
+        if not hold_velocity:
+            u = u + dt_int * f["Fc"][0, 0] / mass
+    return np.array(out)
+
+
+@pytest.mark.parametrize("nu_poi", [0.0, 0.3, 0.45])
+def test_tangential_stick_is_damped_oscillator(oracle_lib, nu_poi):
+    """Stick branch of the tangential model (Sec. 2.2.8; readings c-20, c-21):
+    while |F_t| stays below mu_s |F_n| the tangential force is a linear
+    spring-dashpot on the integrated slip, so the tangential motion obeys
+    m zeta'' + d_t zeta' + k_t zeta = 0 with k_t = kappa k_n, kappa =
+    2(1 - nu)/(2 - nu), and d_t = 2 sqrt(m k_t) (-ln e)/sqrt(pi^2 + ln^2 e).
+    Its solution from zeta = 0 returns to zero after half a period
+    pi / omega_d = T_c / sqrt(kappa), with velocity -e times the initial one:
+    a dropped kappa, a k_t without the k_n factor, a d_t off by any factor or a
+    sign error in the spring update each move one of the two numbers."""
+    Tc, e = 10.0, 0.97
+    kappa = 2.0 * (1.0 - nu_poi) / (2.0 - nu_poi)
+    half = Tc / math.sqrt(kappa)
+    dt_int = half / 4000.0
+    v0 = 1e-3   # small enough that |F_t| << mu_s |F_n|: the contact sticks
+    s = _wall_slide(oracle_lib, v0, 4400, dt_int, nu_poi)
+    u, zt, Fx, Fz = s.T
+    assert np.all(np.abs(Fx) <= 0.11 * Fz)          # never slips
+    # first return of the spring to zero
+    k = int(np.nonzero((zt[:-1] > 0) & (zt[1:] <= 0))[0][0])
+    frac = zt[k] / (zt[k] - zt[k + 1])
+    t_cross = (k + frac + 1) * dt_int   # zt[i] is the spring after i + 1 increments
+    u_cross = u[k] + frac * (u[k + 1] - u[k])
+    assert t_cross == pytest.approx(half, rel=2e-3)
+    assert -u_cross / v0 == pytest.approx(e, rel=2e-3)
+
+
+def test_tangential_slip_caps_and_resets_spring(oracle_lib):
+    """Slip branch of the tangential model (Sec. 2.2.8; reading c-22): under a
+    constant normal force and a constant tangential slip speed the tangential
+    force is mu_k |F_n| at every evaluation, opposed to the slip, and the
+    spring is reset to -(F_t + d_t g_t)/k_t each time, so it does not grow
+    after the first slip."""
+    Tc, e, nu_poi, g = 10.0, 0.97, 0.3, 0.05
+    s = _wall_slide(oracle_lib, g, 50, 0.1, nu_poi, hold_velocity=True)
+    u, zt, Fx, Fz = s.T
+    assert np.all(Fz > 0)
+    assert np.allclose(Fx, -0.8 * Fz, rtol=1e-12, atol=0.0)
+    le = math.log(e)
+    kn = (math.pi ** 2 + le * le) / Tc ** 2         # m_eff = m_p = 1 for a wall
+    kt = 2.0 * (1.0 - nu_poi) / (2.0 - nu_poi) * kn
+    dt_ = 2.0 * math.sqrt(kt) * (-le) / math.sqrt(math.pi ** 2 + le * le)
+    reset = -(Fx[0] + dt_ * g) / kt
+    assert np.allclose(zt, reset, rtol=1e-12, atol=0.0)
+    assert zt[-1] == zt[1]
