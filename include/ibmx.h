@@ -106,7 +106,10 @@ typedef struct {
     double mu_k;             /* kinetic friction [0.8]                         */
     double nu_poi;           /* Poisson ratio of the particles                 */
     double dt;               /* time step for the tangential spring            */
-    double gap_cut;          /* pair/wall list cut-off on the surface gap      */
+    double gap_cut;          /* pair/wall list cut-off on the surface gap; at
+                                least 2 eps_sep when disable_mode != 0 (the
+                                disable rule acts on gaps below 2 eps_sep),
+                                else EINVAL                                    */
     int32_t disable_mode;    /* 0 none, 1 local markers, 2 whole particle      */
     int32_t normal_model;    /* 0 linear spring-dashpot, 1 Hertz law with ACTM
                                 coefficients (Sec. 2.2.7)                      */

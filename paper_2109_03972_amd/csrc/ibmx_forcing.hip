@@ -536,11 +536,13 @@ __device__ __forceinline__ void stage_region_rows(const GridC &g, const TileC &t
     const int sub = lane / R0, rx = lane - sub * R0;
     const int step = nw * rpi, rows = R1 * R2;
     int gx = box.o[0] - 1 + rx;
-    bool okx = sub < rpi;
+    const bool lane_ok = sub < rpi;
+    // a node beyond an x wall is stored as 0 like those beyond y and z walls
+    bool inx = true;
     if (g.periodic[0])
         gx = gx < 0 ? gx + g.n[0] : (gx >= g.n[0] ? gx - g.n[0] : gx);
     else
-        okx = okx && gx >= 0 && gx < g.n[0];
+        inx = gx >= 0 && gx < g.n[0];
     for (int r0 = wave * rpi + sub; r0 < rows; r0 += SUNR * step) {
         T v[SUNR][3];
         int li[SUNR];
@@ -549,8 +551,9 @@ __device__ __forceinline__ void stage_region_rows(const GridC &g, const TileC &t
             const int r = r0 + q * step;
             const int rz = r / R1, ry = r - rz * R1;
             int gy = box.o[1] - 1 + ry, gz = box.o[2] - 1 + rz;
-            bool ok = okx && r < rows;
+            bool ok = lane_ok && r < rows;
             li[q] = ok ? (rz * R1 + ry) * R0 + rx : -1;
+            ok = ok && inx;
             if (g.periodic[1])
                 gy = gy < 0 ? gy + g.n[1] : (gy >= g.n[1] ? gy - g.n[1] : gy);
             else

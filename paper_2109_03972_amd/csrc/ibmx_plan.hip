@@ -76,6 +76,10 @@ ibmx_status check_params(const ibmx_grid *g, const ibmx_params *prm)
         return IBMX_EINVAL;
     if (prm->disable_mode < 0 || prm->disable_mode > 2)
         return IBMX_EINVAL;
+    // the disable rule (Sec. 2.2.5) acts on every pair closer than 2 eps_sep:
+    // the pair list must reach that far
+    if (prm->disable_mode != 0 && !(prm->gap_cut >= 2.0 * prm->eps_sep))
+        return IBMX_EINVAL;
     if (!(prm->eps_sep >= 0.0) || !(prm->gap_cut >= 0.0) || !(prm->T_c > 0.0) ||
         !(prm->e_dry > 0.0 && prm->e_dry <= 1.0) || !(prm->dt > 0.0))
         return IBMX_EINVAL;

@@ -112,7 +112,7 @@ def _wall_layer(seed):
     x[2] = np.minimum(x[2], R + rng.uniform(-0.2, 0.05, R.size))
     mass = 2.5 * 4.0 / 3.0 * np.pi * R ** 3
     prm = synth.default_params()
-    prm.update(gap_cut=2.0, normal_model=1, gravity=(0.0, 0.0, -2e-3))
+    prm.update(gap_cut=2.0, normal_model=1, gravity=(0.0, 0.0, -2e-3), disable_mode=0)
     npart = R.size
     return synth.Case(name="wall_layer", n=(48, 40, 32), h=1.0, origin=(0.0, 0.0, 0.0),
                       periodic=(1, 1, 0), xp=np.ascontiguousarray(x),
@@ -196,7 +196,7 @@ def test_no_contacts():
     """Particles far apart: only F_h, T_h and gravity act."""
     c = synth.small_case(304, n=(64, 64, 64), periodic=(1, 1, 1), diameters=(8.0, 6.0, 7.0),
                          min_gap=12.0)
-    c.params.update(gap_cut=1.0, gravity=(1e-3, 0.0, -2e-3))
+    c.params.update(gap_cut=1.0, gravity=(1e-3, 0.0, -2e-3), disable_mode=0)
     ref_l, _ = _oracle_lists(c)
     assert ref_l["pairs"].shape[1] == 0
     x0 = c.xp.copy()
