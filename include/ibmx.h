@@ -393,6 +393,29 @@ IBMX_API ibmx_status ibmx_particle_integrals(ibmx_plan plan, const void *u, cons
 IBMX_API ibmx_status ibmx_grid_mean(ibmx_plan plan, const void *f, double *mean);
 
 /*
+ * ibmx_grid_mean for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * It needs no plan and allocates nothing: its partial sums live in a static
+ * device array of the library, [3][4096] doubles (96 KB on every device the
+ * library runs on, held until the process ends).  Same kernels, result and
+ * summation order as ibmx_grid_mean.
+ *   f          device T[3][n_nodes] (T = double for IBMX_F64, float for
+ *              IBMX_F32), the three components one after the other.
+ *   n_nodes    nodes per component, 1 <= n_nodes < 2^31 (the library's grid
+ *              limit), else EINVAL.
+ *   mean       device double[3], overwritten: sum_x f_a(x) / n_nodes.
+ *   hip_stream stream of the current device (NULL = default stream); the
+ *              call is asynchronous on it.
+ * Every call on one device shares that device's array: calls that overlap
+ * on one device (different streams, or host threads) race and must be
+ * ordered by the caller.  Returns EINVAL, EDEVICE (the array's address could
+ * not be found) or EUNSUPPORTED (device index above 63).
+ */
+IBMX_API ibmx_status ibmx_grid_mean_noalloc(const void *f, int64_t n_nodes,
+                                            ibmx_precision precision, double *mean,
+                                            void *hip_stream);
+
+/*
  * Particle sub-stepping (Sec. 2.2.10): advance every particle's centre,
  * velocity and angular velocity by dt_total in n_sub sub-steps of dts =
  * dt_total / n_sub, each the three-stage Runge-Kutta predictor-corrector of

@@ -2,6 +2,8 @@
 // (Sec. 2.2.9), and the volume average of a grid field (Sec. 2.2.4).
 #include <math.h>
 
+#include <mutex>
+
 #include "ibmx_internal.hpp"
 
 namespace {
@@ -232,6 +234,66 @@ ibmx_status run_mean(ibmx_plan p, const T *f, double *mean)
 }  // namespace
 
 int ibmx_mean_blocks() { return MEAN_BLOCKS; }
+
+// Partial sums of ibmx_grid_mean_noalloc: [3][MEAN_BLOCKS] doubles (96 KB)
+// in every device's copy of the library's code object, held until the
+// process ends.  Host code never passes this name to a kernel: it stands for
+// a host-side shadow, not the device address; the address comes from
+// hipGetSymbolAddress per device.
+static __device__ __align__(256) double scratch[3 * MEAN_BLOCKS];
+
+namespace {
+
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[SCRATCH_DEVICES];   // address of scratch on each device
+
+// Device address of scratch on the current device, looked up once per
+// device with that device current.
+ibmx_status scratch_on_current_device(double **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return IBMX_EDEVICE;
+    if (dev < 0 || dev >= SCRATCH_DEVICES)
+        return IBMX_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr)
+            return IBMX_EDEVICE;
+        g_scratch_ptr[dev] = (double *)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return IBMX_OK;
+}
+
+}  // namespace
+
+extern "C" ibmx_status ibmx_grid_mean_noalloc(const void *f, int64_t n_nodes,
+                                              ibmx_precision precision, double *mean,
+                                              void *hip_stream)
+{
+    if (!f || !mean || n_nodes < 1 || n_nodes >= (1LL << 31) ||
+        (precision != IBMX_F64 && precision != IBMX_F32))
+        return IBMX_EINVAL;
+    double *part = nullptr;
+    const ibmx_status st = scratch_on_current_device(&part);
+    if (st != IBMX_OK)
+        return st;
+    hipStream_t s = (hipStream_t)hip_stream;
+    // every partial slot is written by k_mean_partial before k_mean_finish
+    // reads it: nothing to clear between calls
+    if (precision == IBMX_F64)
+        hipLaunchKernelGGL((k_mean_partial<double>), dim3(MEAN_BLOCKS), dim3(256), 0, s,
+                           (const double *)f, (long long)n_nodes, part);
+    else
+        hipLaunchKernelGGL((k_mean_partial<float>), dim3(MEAN_BLOCKS), dim3(256), 0, s,
+                           (const float *)f, (long long)n_nodes, part);
+    hipLaunchKernelGGL(k_mean_finish, dim3(1), dim3(256), 0, s, (const double *)part, MEAN_BLOCKS,
+                       (long long)n_nodes, mean);
+    return ibmx_launch_check();
+}
 
 extern "C" ibmx_status ibmx_particle_integrals(ibmx_plan p, const void *u, const double *xp,
                                                const double *radius, double *Iu, double *Ir,

@@ -27,7 +27,7 @@ API = (
     "ibmx_forcing", "ibmx_forcing_graph",
     "ibmx_forcing_backward", "ibmx_pairs", "ibmx_tune", "ibmx_particle_integrals",
     "ibmx_grid_mean", "ibmx_particle_substeps", "ibmx_project", "ibmx_fluid_predictor",
-    "ibmx_fluid_helmholtz", "ibmx_status_string", "ibmx_version",
+    "ibmx_fluid_helmholtz", "ibmx_grid_mean_noalloc", "ibmx_status_string", "ibmx_version",
 )
 
 HIST = 4   # rows of a contact history array (IBMX_HIST)
@@ -113,6 +113,8 @@ def lib():
         L.ibmx_particle_integrals.argtypes = [P] * 7
         L.ibmx_grid_mean.restype = St
         L.ibmx_grid_mean.argtypes = [P] * 3
+        L.ibmx_grid_mean_noalloc.restype = St
+        L.ibmx_grid_mean_noalloc.argtypes = [P, ctypes.c_int64, St, P, P]
         L.ibmx_fluid_predictor.restype = St
         L.ibmx_fluid_predictor.argtypes = [P, P, P, P, P, P, ctypes.c_double, ctypes.c_double,
                                            ctypes.c_double]
@@ -494,6 +496,24 @@ class Plan:
                              _ptr(mask))
         _check(st, "ibmx_tune")
         return self.stats()
+
+
+def grid_mean_noalloc(f, mean=None):
+    """ibmx_grid_mean_noalloc: per-component mean of a [3][...] device
+    tensor (float32 or float64) without a plan; returns double[3] on the
+    device (``mean`` is written if given)."""
+    import torch
+    if not isinstance(f, torch.Tensor) or not f.is_cuda or not f.is_contiguous():
+        raise TypeError("f must be a contiguous device tensor")
+    if f.dtype not in (torch.float32, torch.float64) or f.dim() < 1 or f.shape[0] != 3:
+        raise ValueError("f must be float32 or float64 with 3 components in its first dimension")
+    if mean is None:
+        mean = torch.empty(3, dtype=torch.float64, device=f.device)
+    _want(mean, torch.float64, (3,), "mean")
+    prec = F64 if f.dtype == torch.float64 else F32
+    _check(lib().ibmx_grid_mean_noalloc(_ptr(f), f.numel() // 3, prec, _ptr(mean), _stream()),
+           "ibmx_grid_mean_noalloc")
+    return mean
 
 
 def trim_pairs(res: Dict) -> Dict:
