@@ -17,7 +17,10 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ibmx_oracle.c")
-_LIB = os.path.join(_HERE, "libibmx_oracle.so")
+# IBMX_ORACLE_SANITIZE=1 selects a build with AddressSanitizer and
+# UndefinedBehaviorSanitizer (the process must preload the ASan runtime)
+_SANITIZE = os.environ.get("IBMX_ORACLE_SANITIZE", "") == "1"
+_LIB = os.path.join(_HERE, "libibmx_oracle_san.so" if _SANITIZE else "libibmx_oracle.so")
 _lib = None
 
 OK, EINVAL, EDOMAIN, ECAPACITY = 0, -1, -2, -6
@@ -27,8 +30,11 @@ def build(force: bool = True) -> str:
     """Compile the oracle (gcc -O2 -ffp-contract=off)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
+        san = (["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+                "-fno-omit-frame-pointer", "-g"] if _SANITIZE else [])
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99",
-                               "-D_DEFAULT_SOURCE", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+                               "-D_DEFAULT_SOURCE", "-fPIC", "-shared", *san, "-o", tmp, _SRC,
+                               "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
