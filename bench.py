@@ -34,31 +34,51 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(kind: str, s: int, n_act: int, shell: int, n_iter: int = 2) -> float:
-    """Bytes a kernel must move per launch (s = bytes of the grid type).
+def pass_bytes(s: int, n_act: int, shell: int) -> float:
+    """Algorithmic bytes of one forcing pass (interpolation + spreading), the
+    roofline's numerator (s = bytes of the grid type).
 
-    Marker records: packed base node and fractions (4 + 3s), rigid-body
-    velocity and volume (4s).  Shell = distinct grid nodes in the delta
-    support of the active markers; every access below touches each of them
-    once.
+    Per marker-update a record of 20 B (FP32: base cell, three fractions,
+    particle id) or 32 B (FP64); per shell node (a node in the delta support
+    of an active marker) the three velocity components read twice in the
+    interpolation (u^0 and the accumulated correction) and the accumulator
+    read and written in the spreading: 4 x 3s bytes.
+    """
+    b_rec = 20 if s == 4 else 32
+    return float(n_act * b_rec + 12 * s * shell)
 
-    interp (one pass): records (4 + 7s), write of the pass amplitude G (3s)
-           and read-modify-write of its sum over passes (6s); per shell node
-           one read of the three velocity components (3s).
-    spread (one pass): packed node and fractions (4 B + 3s) and G (3s); per
-           shell node a read-modify-write of u (6s), and of f_tot as well
-           (6s more) when the call has a single pass.
-    ftot   (once per call with two or more passes): packed node, fractions and
-           summed G (4 B + 6s); per shell node a read-modify-write of f_tot.
+
+def design_bytes(kind: str, s: int, n_act: int, shell: int, halo: int) -> float:
+    """Bytes this build's kernels must move per launch (reported beside the
+    roofline): records of T4 = 4s bytes, 2-byte tile-local indices of the
+    compact shell entries, halo = (marker, neighbouring tile) entries.
+
+    interp: per own marker the fractions and base node (4s) and the
+            rigid-body velocity and volume (4s) read, the amplitude G (4s)
+            written; the tile's own compact shell values and indices read
+            (3s + 2 per shell node; the halo values the region needs come
+            from the neighbours' runs and are not counted).
+    spread: per own and halo entry the fractions and base node (4s) and G
+            (4s) read, plus the halo list (4 B); per shell node the compact
+            values read and written and the index read (6s + 2).
     """
     if kind == "interp":
-        return n_act * (4 + 16 * s) + shell * 3 * s
+        return float(n_act * 12 * s + shell * (3 * s + 2))
     if kind == "spread":
-        return n_act * (4 + 6 * s) + shell * (6 * s if n_iter > 1 else 12 * s)
-    if kind == "ftot":
-        return n_act * (4 + 6 * s) + shell * 6 * s
+        return float((n_act + halo) * 8 * s + halo * 4 + shell * (6 * s + 2))
     raise KeyError(kind)
 
+
+# what the roofline of the smaller workloads means
+ROOFLINE_NOTES = {
+    "single_sphere_64": "805 markers: launch and latency bound, no roofline claim",
+    "suspension_128": "90,600 markers, about 20 MB per pass: launch and latency bound, "
+                      "no roofline claim",
+    "gradient_suspension_128": "90,600 markers: launch and latency bound, no roofline claim",
+    "bidisperse_bed_256x256x512": "the shell's working set (about 70 MB per component "
+                                  "array) fits the 256 MB Infinity Cache: the rate is a "
+                                  "fabric bandwidth, not an HBM one",
+}
 
 COUNTER_FILES = {
     "polydisperse_bed_512": "profiles/k_interp_k_spread_polydisperse_bed_512_f32_hbm_counters.md",
@@ -141,7 +161,7 @@ def measured_traffic(workload: str, kind: str, tile) -> "float | None":
     return None
 
 
-def run_gpu(case, precision, steps, warmup, profile=True, tune=True, tile=None):
+def run_gpu(case, precision, steps, warmup, profile=True, tune=True, tile=None, launch=None):
     import torch
     from paper_2109_03972_amd import ibmx
 
@@ -166,10 +186,14 @@ def run_gpu(case, precision, steps, warmup, profile=True, tune=True, tile=None):
     tuned = None
     if tile is not None:
         plan.set_tiles(*tile)
+        if launch is not None:
+            plan.set_launch(*launch)
     elif tune:
-        tuned = plan.tune(u, f, D["xp"], D["up"], D["wp"], mask=mask)["tile"]
+        ts = plan.tune(u, f, D["xp"], D["up"], D["wp"], mask=mask)
         plan.check("tune")
-        log(f"bench: {precision} tuned tile {tuned}")
+        tuned = ts["tile"]
+        log(f"bench: {precision} tuned tile {tuned}, {ts['block']} threads, "
+            f"{'persistent' if ts['persistent'] else 'one workgroup per tile'}")
 
     def step(graph):
         r = plan.pairs(D["xp"], D["radius"], D["mass"], D["up"], D["wp"], prev=prev, mask=mask,
@@ -269,7 +293,8 @@ def run_gpu(case, precision, steps, warmup, profile=True, tune=True, tile=None):
     out = dict(ms_per_step=ms, ms_per_step_profiled=ms_prof, ms_per_step_graph=ms_graph,
                wall_s=wall, stats=st, n_iter=n_iter,
                extras=extras,
-               resid=resid.cpu().numpy().tolist(), tile=tuned or list(plan.stats()["tile"]))
+               resid=resid.cpu().numpy().tolist(), tile=tuned or list(plan.stats()["tile"]),
+               block=plan.stats()["block"], persistent=plan.stats()["persistent"])
     del u, f, D
     plan.close()
     torch.cuda.empty_cache()
@@ -359,6 +384,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile shape")
     ap.add_argument("--tile", default=None,
                     help="FP32 tile shape tx,ty,tz instead of tuning (for counter runs)")
+    ap.add_argument("--launch", default=None,
+                    help="with --tile: threads per workgroup and persistence, e.g. 256,0")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 1 GiB device-to-device copy (reference kernel for "
                          "hardware byte counters)")
@@ -389,7 +416,9 @@ def main():
 
     log("bench: FP32 run")
     tile = None if args.tile is None else [int(v) for v in args.tile.split(",")]
-    r32 = run_gpu(case, "f32", args.steps, args.warmup, tune=not args.no_tune, tile=tile)
+    launch = None if args.launch is None else [int(v) for v in args.launch.split(",")]
+    r32 = run_gpu(case, "f32", args.steps, args.warmup, tune=not args.no_tune, tile=tile,
+                  launch=launch)
     st = r32["stats"]
     n_act, shell, n_iter = int(st["n_active"]), int(st["shell_nodes"]), r32["n_iter"]
     value = n_act * n_iter / (r32["ms_per_step"] * 1e-3)
@@ -398,19 +427,26 @@ def main():
     km, kn = st["kernel_ms"], st["kernel_launches"]
     steps_done = args.steps
     per_launch = {k: (km[k] / kn[k] if kn[k] else None) for k in km}
-    # the kernel with the largest share of the step (the spreading pass: n_iter
-    # launches; the f_tot spreading, one launch of the same kernel, is
-    # reported per launch beside it)
-    dom = max(("interp", "spread", "ftot"), key=lambda k: km[k])
-    bytes_launch = algorithmic_bytes(dom, 4, n_act, shell, n_iter)
-    achieved = bytes_launch / (per_launch[dom] * 1e-3) / 1e9
-    traffic = measured_traffic(args.workload, dom, r32["tile"])
-    roof = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
-                unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                bytes_per_launch=bytes_launch, ms_per_launch=per_launch[dom],
+    # roofline of the forcing pass: one interpolation and one spreading launch
+    # (n_iter of each per step), algorithmic bytes over their average durations
+    halo = int(st["halo_entries"])
+    t_pass = per_launch["interp"] + per_launch["spread"]
+    b_pass = pass_bytes(4, n_act, shell)
+    achieved = b_pass / (t_pass * 1e-3) / 1e9
+    tr = [measured_traffic(args.workload, k, r32["tile"]) for k in ("interp", "spread")]
+    traffic = None if None in tr else tr[0] + tr[1]
+    roof = dict(bound="hbm", kernel="k_interp_sh + k_spread_sh (one forcing pass)",
+                achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                bytes_per_pass=b_pass, ms_per_pass=t_pass,
+                ms_per_launch=dict(interp=per_launch["interp"], spread=per_launch["spread"]),
+                design_bytes=dict(interp=design_bytes("interp", 4, n_act, shell, halo),
+                                  spread=design_bytes("spread", 4, n_act, shell, halo)),
                 copy_GBs=round(copy_gbs, 1))
     if traffic is not None:
-        roof["traffic_GBs"] = round(traffic / (per_launch[dom] * 1e-3) / 1e9, 1)
+        roof["traffic_GBs"] = round(traffic / (t_pass * 1e-3) / 1e9, 1)
+    if args.workload != "polydisperse_bed_512":
+        roof["note"] = ROOFLINE_NOTES.get(args.workload, "")
     log(f"bench: FP32 {r32['ms_per_step']:.3f} ms/step, {value:.3e} marker-updates/s")
 
     fp64 = None
@@ -442,7 +478,7 @@ def main():
                     markers=case.nm, active_markers=n_act, shell_nodes=shell, n_iter=n_iter,
                     precision="FP32 grid/delta, FP64 geometry, particle sums and pair pass",
                     step="pair pass + marker geometry + n_iter forcing passes",
-                    tile=r32["tile"]),
+                    tile=r32["tile"], block=r32["block"], persistent=r32["persistent"]),
         roofline=roof, cpu_baseline=cpu, fp64=fp64,
         kernel_ms_per_launch=per_launch,
         graph=dict(ms_per_step=r32["ms_per_step_graph"], value=value_graph),

@@ -27,19 +27,16 @@
  *     named *_host.  The caller owns every buffer; the library only reads
  *     or writes it inside the call, asynchronously on the plan's stream, so
  *     buffers must stay valid until the stream reaches the call.
- *   * Compute calls never synchronise the stream and allocate nothing, with
- *     five exceptions that allocate (and so may synchronise the device):
- *     the first ibmx_forcing_backward call on a plan sizes its replay
- *     workspace, ibmx_pairs grows its cell and contact workspace the first
- *     time the cell grid (set by radius_max and gap_cut) or the list
- *     capacities exceed those of earlier calls, ibmx_particle_substeps
- *     likewise for its contact and stage workspace, the first
- *     ibmx_project or ibmx_fluid_helmholtz call, and ibmx_tune.
- *     ibmx_forcing can be captured into a HIP graph (ibmx_forcing_graph
- *     does that), and so can ibmx_pairs and ibmx_particle_substeps once
- *     their workspace has been sized.  Errors that only the device can
- *     see (a delta support crossing a wall, a list capacity exceeded) are
- *     recorded in the plan and returned by ibmx_plan_status().
+ *   * Compute calls never synchronise the stream and never allocate, so
+ *     every one of them can be captured into a HIP graph from its first
+ *     call (ibmx_forcing_graph does that for ibmx_forcing).  The plan owns
+ *     all workspace: the forcing loop's is sized by ibmx_plan_create and
+ *     ibmx_plan_set_tiles; the pair pass, the particle sub-stepping, the
+ *     adjoint and the fluid solves take theirs from ibmx_plan_reserve and
+ *     return ESTATE when it is missing or too small.  Only ibmx_tune
+ *     allocates (its scratch copies) and synchronises.  Errors that only the
+ *     device can see (a delta support crossing a wall, a list capacity
+ *     exceeded) are recorded in the plan and returned by ibmx_plan_status().
  *   * A plan is used by one host thread at a time; calls on one plan are
  *     ordered by its stream.
  *   * No exception, abort or exit crosses this interface.
@@ -66,7 +63,8 @@ typedef enum {
                                grid through a wall (deferred)                 */
     IBMX_ENOMEM = -3,       /* device allocation failed (plan creation only)  */
     IBMX_EDEVICE = -4,      /* a HIP runtime call failed                      */
-    IBMX_ESTATE = -5,       /* plan not ready (markers not set)               */
+    IBMX_ESTATE = -5,       /* plan not ready: markers not set, or workspace
+                               not reserved for the call (ibmx_plan_reserve) */
     IBMX_ECAPACITY = -6,    /* pair or wall list longer than its capacity
                                (deferred; counts are still written)           */
     IBMX_EUNSUPPORTED = -7  /* option not built (e.g. a delta other than 3/4)  */
@@ -141,7 +139,9 @@ typedef struct {
     int64_t tiles;            /* spatial tiles of the spreading pass          */
     int64_t halo_entries;     /* (marker, neighbour tile) spreading entries    */
     int32_t tile[3];          /* tile edge in nodes                            */
-    int32_t block;            /* threads per workgroup of the marker passes   */
+    int32_t block;            /* threads per workgroup of the forcing passes  */
+    int32_t persistent;       /* 1: the passes run as a persistent grid        */
+    int32_t reserved;
     /* Kernel timings accumulated while profiling is on (ibmx_plan_profile):
      * total milliseconds and launch counts per kernel class
      * IBMX_K_GEOMETRY .. IBMX_K_FTOT. */
@@ -190,6 +190,33 @@ IBMX_API ibmx_status ibmx_plan_destroy(ibmx_plan plan);
  * used. */
 IBMX_API ibmx_status ibmx_plan_set_markers(ibmx_plan plan, const double *body_offset, const double *dV);
 
+/* Flags of ibmx_plan_reserve. */
+#define IBMX_RESERVE_BACKWARD 1   /* replay workspace of ibmx_forcing_backward  */
+#define IBMX_RESERVE_FLUID 2      /* FFT / elimination workspace of ibmx_project
+                                     and ibmx_fluid_helmholtz                   */
+
+/*
+ * Size the workspace of the calls that need more than the forcing loop, so
+ * that they allocate nothing:
+ *   ibmx_pairs               a cell list of up to cell_cap - 1 cells and lists
+ *                            of up to pair_cap pairs and wall_cap wall entries
+ *                            (the capacities the call is given);
+ *   ibmx_particle_substeps   lists of up to pair_cap / wall_cap entries, the
+ *                            stage states of the plan's particles;
+ *   IBMX_RESERVE_BACKWARD    ibmx_forcing_backward (the replay grid T[3][nodes]
+ *                            and T4[n_iter][3][nm] of per-pass data);
+ *   IBMX_RESERVE_FLUID       ibmx_project and ibmx_fluid_helmholtz (an FP64
+ *                            real grid, the FP64 half spectrum, with walls in z
+ *                            an FP64 elimination grid, twiddle tables);
+ *                            EUNSUPPORTED on grids the solves do not take.
+ * Workspace only grows; a call whose needs exceed the reservation returns
+ * ESTATE.  Synchronises the plan's stream.  Growing it moves the workspace,
+ * so graphs captured before must be captured again.  EINVAL for negative
+ * sizes or unknown flags, ENOMEM.
+ */
+IBMX_API ibmx_status ibmx_plan_reserve(ibmx_plan plan, int32_t pair_cap, int32_t wall_cap,
+                                       int32_t cell_cap, int32_t flags);
+
 /* Change the parameters (n_iter may not exceed the value the plan was
  * created with). */
 IBMX_API ibmx_status ibmx_plan_set_params(ibmx_plan plan, const ibmx_params *params);
@@ -205,6 +232,15 @@ IBMX_API ibmx_status ibmx_plan_set_stream(ibmx_plan plan, void *hip_stream);
  * length.  EUNSUPPORTED if the tile's LDS footprint is too large for the
  * precision.  Synchronises the stream; reallocates tile workspace. */
 IBMX_API ibmx_status ibmx_plan_set_tiles(ibmx_plan plan, int32_t tx, int32_t ty, int32_t tz);
+
+/* Set the launch form of the forcing passes, as ibmx_tune does for its
+ * choice: block = threads per workgroup (64, 128 or 256; a thread takes one
+ * marker at a time, so this is the number of markers a tile's workgroup
+ * works on at once), persistent = 0 for one workgroup per tile, 1 for a
+ * fixed grid (as many workgroups as the CUs hold at once) whose workgroups
+ * loop over the tiles.  Results do not depend on either choice.  EINVAL for
+ * other values. */
+IBMX_API ibmx_status ibmx_plan_set_launch(ibmx_plan plan, int32_t block, int32_t persistent);
 
 /* Synchronise the plan's stream and return (and clear) the first deferred
  * device error of the calls since the last ibmx_plan_status: EDOMAIN,
@@ -262,7 +298,8 @@ IBMX_API ibmx_status ibmx_forcing(ibmx_plan plan, void *u, void *f_tot,
  * g_u = dL/du^{n_iter} (T grid or NULL), g_S = dL/dS_out and g_T = dL/dT_out
  * (double[3][np] or NULL).  Outputs (overwritten): gu0 (T grid), gxp, gup,
  * gwp (double[3][np]).  The forward passes are recomputed, not stored by the
- * forward call; plan workspace holds the per-marker pass data.
+ * forward call; plan workspace holds the per-marker pass data
+ * (ibmx_plan_reserve with IBMX_RESERVE_BACKWARD, else ESTATE).
  */
 IBMX_API ibmx_status ibmx_forcing_backward(ibmx_plan plan, const void *u0,
                                   const double *xp, const double *up, const double *wp,
@@ -317,8 +354,8 @@ IBMX_API ibmx_status ibmx_forcing_backward(ibmx_plan plan, const void *u0,
  * Deferred error: ECAPACITY if a list exceeds its capacity (entries beyond
  * it are dropped, forces of dropped entries are not applied).
  * The body offsets set with ibmx_plan_set_markers are needed for the mask.
- * Allocates plan workspace when the cell count or the list capacities grow
- * beyond those of earlier calls.
+ * ESTATE if ibmx_plan_reserve has not reserved the cell count (ncell above
+ * its cell_cap - 1) or these list capacities.
  */
 IBMX_API ibmx_status ibmx_pairs(ibmx_plan plan, const double *xp, const double *radius,
                        double radius_max, const double *mass, const double *up, const double *wp,
@@ -345,14 +382,17 @@ IBMX_API ibmx_status ibmx_forcing_graph(ibmx_plan plan, void *u, void *f_tot,
                                double *S_out, double *T_out, double *resid_out, void *U_debug);
 
 /*
- * Autotune the tile shape of the forcing passes on the given inputs: runs
- * ibmx_forcing with each candidate shape that fits the LDS (edges 4..32,
- * x-edge <= 32), times it with HIP events on the plan's stream and keeps the
- * fastest in the plan (a candidate must beat the earlier ones by 2%).  Candidates that raise a deferred error are skipped.
+ * Autotune the launch of the forcing passes on the given inputs: runs
+ * ibmx_forcing with each candidate tile shape that fits the LDS (edges
+ * 4..32, x-edge <= 32) at 256 threads per workgroup, then, for the fastest
+ * shape, with 128 and 64 threads and as a persistent grid (ibmx_plan_set_launch);
+ * times each with HIP events on the plan's stream and keeps the fastest in
+ * the plan (a candidate must beat the earlier ones by 2%).  Candidates that
+ * raise a deferred error are skipped.
  * u and f_tot are restored after every trial, so the call leaves them
  * unchanged.  Allocates and frees its own scratch (copies of u and f_tot)
  * and synchronises the stream; not capturable.  The choice is reported by
- * ibmx_plan_stats (tile, block).
+ * ibmx_plan_stats (tile, block, persistent).
  */
 IBMX_API ibmx_status ibmx_tune(ibmx_plan plan, void *u, void *f_tot,
                       const double *xp, const double *up, const double *wp,
@@ -454,8 +494,8 @@ IBMX_API ibmx_status ibmx_grid_mean_noalloc(const void *f, int64_t n_nodes,
  *   Fc, Tc      double[3][np] or NULL: collision force and torque at the
  *               final state, overwritten.
  * Each particle's contacts are summed in increasing partner id, then its
- * walls by side: the results do not depend on scheduling.  Allocates plan
- * workspace when np or the list capacities exceed those of earlier calls.
+ * walls by side: the results do not depend on scheduling.  ESTATE if
+ * ibmx_plan_reserve has not reserved these list capacities.
  */
 IBMX_API ibmx_status ibmx_particle_substeps(ibmx_plan plan, double dt_total, int32_t n_sub,
                                    double *xp, double *up, double *wp, const double *radius,
@@ -483,10 +523,11 @@ IBMX_API ibmx_status ibmx_particle_substeps(ibmx_plan plan, double dt_total, int
  * The solve is direct and FP64: FFTs along x and y (and z when periodic),
  * across walls in z a tridiagonal elimination per Fourier mode.  Needs
  * periodic x and y with power-of-two sizes up to 1024 (and the same for z
- * when periodic), else EUNSUPPORTED.  The first call allocates the plan's
- * solver workspace: an FP64 real grid, the FP64 complex half spectrum
- * (nx/2 + 1 modes per row), with walls in z an FP64 grid of elimination
- * coefficients of the same shape, and one twiddle table per axis.
+ * when periodic), else EUNSUPPORTED.  The solver workspace (an FP64 real
+ * grid, the FP64 complex half spectrum of nx/2 + 1 modes per row, with walls
+ * in z an FP64 grid of elimination coefficients of the same shape, and one
+ * twiddle table per axis) comes from ibmx_plan_reserve with
+ * IBMX_RESERVE_FLUID, else ESTATE.
  */
 IBMX_API ibmx_status ibmx_project(ibmx_plan plan, void *u, void *uf, void *P, void *phi,
                                   double theta);
@@ -523,7 +564,7 @@ IBMX_API ibmx_status ibmx_fluid_predictor(ibmx_plan plan, const void *u, void *u
  * u is overwritten by u*.  The solve is FP64: FFTs along x and y (and z when
  * periodic), across walls in z a tridiagonal elimination per Fourier mode
  * with velocity 0 on the wall faces.  Same grid conditions and workspace as
- * ibmx_project.
+ * ibmx_project (ESTATE without it).
  */
 IBMX_API ibmx_status ibmx_fluid_helmholtz(ibmx_plan plan, void *u, const void *lapnu, const void *P,
                                           const double *fbar, double dt, double theta);

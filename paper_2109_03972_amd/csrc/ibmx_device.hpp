@@ -7,6 +7,7 @@
 
 #define IBMX_WAVE 64
 #define IBMX_RSLOTS 1024          // spread-out accumulation slots per counter
+#define IBMX_MAX_PASSES 64        // largest n_iter of a plan
 
 // ---------------------------------------------------------------------------
 // grid constants passed by value to kernels

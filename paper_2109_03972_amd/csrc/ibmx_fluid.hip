@@ -960,10 +960,20 @@ bool solver_grid_ok(const ibmx_grid &g)
            g.n[1] <= 1024 && (!g.periodic[2] || (pow2(g.n[2]) && g.n[2] <= 1024));
 }
 
+}  // namespace
+
 // workspace: the real right-hand side / solution grid, the half spectrum
 // (nx/2 + 1 modes along x), the elimination scratch (walls in z) and one
 // twiddle table per axis
-ibmx_status fluid_reserve(ibmx_plan p)
+bool ibmx_fluid_ready(ibmx_plan p)
+{
+    return p->fl_r && p->fl_z && (p->grid.periodic[2] || p->fl_cp) && p->fl_tw[0] &&
+           p->fl_tw[1] && p->fl_tw[2];
+}
+
+bool ibmx_fluid_grid_ok(ibmx_plan p) { return solver_grid_ok(p->grid); }
+
+ibmx_status ibmx_fluid_reserve(ibmx_plan p)
 {
     const size_t N = (size_t)p->g.nodes;
     const size_t M = (size_t)(p->grid.n[0] / 2 + 1) * p->grid.n[1] * p->grid.n[2];
@@ -1002,8 +1012,6 @@ ibmx_status fluid_reserve(ibmx_plan p)
     return IBMX_OK;
 }
 
-}  // namespace
-
 extern "C" ibmx_status ibmx_project(ibmx_plan p, void *u, void *uf, void *P, void *phi,
                                     double theta)
 {
@@ -1011,9 +1019,8 @@ extern "C" ibmx_status ibmx_project(ibmx_plan p, void *u, void *uf, void *P, voi
         return IBMX_EINVAL;
     if (!solver_grid_ok(p->grid))
         return IBMX_EUNSUPPORTED;
-    const ibmx_status st = fluid_reserve(p);
-    if (st != IBMX_OK)
-        return st;
+    if (!ibmx_fluid_ready(p))
+        return IBMX_ESTATE;   // workspace not reserved (ibmx_plan_reserve)
     if (p->prec == IBMX_F64)
         return run_project<double>(p, (double *)u, (double *)uf, (double *)P, (double *)phi, theta);
     return run_project<float>(p, (float *)u, (float *)uf, (float *)P, (float *)phi, theta);
@@ -1040,9 +1047,8 @@ extern "C" ibmx_status ibmx_fluid_helmholtz(ibmx_plan p, void *u, const void *la
         return IBMX_EINVAL;
     if (!solver_grid_ok(p->grid))
         return IBMX_EUNSUPPORTED;
-    const ibmx_status st = fluid_reserve(p);
-    if (st != IBMX_OK)
-        return st;
+    if (!ibmx_fluid_ready(p))
+        return IBMX_ESTATE;   // workspace not reserved (ibmx_plan_reserve)
     if (p->prec == IBMX_F64)
         return run_helmholtz<double>(p, (double *)u, (const double *)lapnu, (const double *)P, fbar,
                                      dt, theta);

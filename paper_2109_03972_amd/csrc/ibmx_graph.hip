@@ -142,13 +142,15 @@ extern "C" ibmx_status ibmx_tune(ibmx_plan p, void *u, void *f_tot, const double
     const int prof = p->prof;
     p->prof = 0;
     const int orig[3] = {p->tc.B[0], p->tc.B[1], p->tc.B[2]};
+    const int orig_block = p->block, orig_persist = p->persist;
     int best[3] = {orig[0], orig[1], orig[2]};
+    int best_block = orig_block, best_persist = orig_persist;
     float best_ms = FLT_MAX;
     ibmx_status st = IBMX_OK;
     int last_err = 0;
-    for (const auto &cand : kTileCandidates) {
-        if (ibmx_plan_alloc_tiles(p, cand[0], cand[1], cand[2]) != IBMX_OK)
-            continue;
+    // time the current launch form: the best of three calls after a warm-up
+    // (false when the call raised a deferred error)
+    auto trial = [&](float *t_out) -> bool {
         float t_min = FLT_MAX;
         bool ok = true;
         for (int rep = 0; rep < 4 && ok; ++rep) {
@@ -157,16 +159,16 @@ extern "C" ibmx_status ibmx_tune(ibmx_plan p, void *u, void *f_tot, const double
                               nullptr);
             (void)hipEventRecord(sc.e1, s);
             if (st != IBMX_OK)
-                break;
+                return false;
             if (hipMemcpyAsync(u, sc.u, gbytes, hipMemcpyDeviceToDevice, s) != hipSuccess ||
                 hipMemcpyAsync(f_tot, sc.f, gbytes, hipMemcpyDeviceToDevice, s) != hipSuccess) {
                 st = IBMX_EDEVICE;
-                break;
+                return false;
             }
             const int err = take_error(p);
             if (err == (int)IBMX_EDEVICE) {
                 st = IBMX_EDEVICE;
-                break;
+                return false;
             }
             ok = err == 0;
             if (!ok)
@@ -175,14 +177,45 @@ extern "C" ibmx_status ibmx_tune(ibmx_plan p, void *u, void *f_tot, const double
             if (ok && rep > 0 && hipEventElapsedTime(&ms, sc.e0, sc.e1) == hipSuccess)
                 t_min = ms < t_min ? ms : t_min;
         }
+        *t_out = t_min;
+        return ok;
+    };
+    // tile shapes at 256 threads per workgroup, one workgroup per tile; a
+    // later candidate must win by 2% (timing noise keeps the earlier, larger
+    // shapes)
+    p->block = 256;
+    p->persist = 0;
+    for (const auto &cand : kTileCandidates) {
+        if (ibmx_plan_alloc_tiles(p, cand[0], cand[1], cand[2]) != IBMX_OK)
+            continue;
+        float t = FLT_MAX;
+        const bool ok = trial(&t);
         if (st != IBMX_OK)
             break;
-        // a later candidate must win by 2% (timing noise keeps the earlier,
-        // larger shapes)
-        if (ok && t_min < 0.98f * best_ms) {
-            best_ms = t_min;
+        if (ok && t < 0.98f * best_ms) {
+            best_ms = t;
             for (int a = 0; a < 3; ++a)
                 best[a] = cand[a];
+            best_block = 256;
+            best_persist = 0;
+        }
+    }
+    // the launch form for the chosen shape: workgroup size and persistence
+    if (st == IBMX_OK && best_ms < FLT_MAX &&
+        ibmx_plan_alloc_tiles(p, best[0], best[1], best[2]) == IBMX_OK) {
+        const int forms[][2] = {{256, 1}, {128, 0}, {128, 1}, {64, 0}, {64, 1}};
+        for (const auto &fm : forms) {
+            p->block = fm[0];
+            p->persist = fm[1];
+            float t = FLT_MAX;
+            const bool ok = trial(&t);
+            if (st != IBMX_OK)
+                break;
+            if (ok && t < 0.98f * best_ms) {
+                best_ms = t;
+                best_block = fm[0];
+                best_persist = fm[1];
+            }
         }
     }
     p->prof = prof;
@@ -191,10 +224,14 @@ extern "C" ibmx_status ibmx_tune(ibmx_plan p, void *u, void *f_tot, const double
     (void)hipMemcpyAsync(f_tot, sc.f, gbytes, hipMemcpyDeviceToDevice, s);
     if (st == IBMX_OK && best_ms == FLT_MAX && last_err != 0)
         st = (ibmx_status)last_err;   // no candidate ran cleanly
+    if (best_ms == FLT_MAX) {
+        best_block = orig_block;
+        best_persist = orig_persist;
+    }
     ibmx_status st2 = ibmx_plan_alloc_tiles(p, best[0], best[1], best[2]);
     if (st2 != IBMX_OK)
         st2 = ibmx_plan_alloc_tiles(p, orig[0], orig[1], orig[2]);
-    p->stats.block = 256;
+    (void)ibmx_plan_set_launch(p, best_block, best_persist);
     if (pending != 0)
         (void)hipMemcpy(p->d_err, &pending, sizeof(int), hipMemcpyHostToDevice);
     if (hipStreamSynchronize(s) != hipSuccess)

@@ -30,15 +30,15 @@ struct ibmx_plan_s {
     int *d_moff;          // [np + 1]
     int *d_pid;           // [nm] marker -> particle
     int *d_err;           // [1] first deferred error (0 = none)
-    double *d_acc;        // [n_iter_cap + 2][IBMX_RSLOTS] residual partial sums
-    long long *d_count;   // [8][IBMX_RSLOTS] counters (active markers, shell
-                          // nodes, halo entries) as partial sums
+    long long *d_count;   // [8][IBMX_RSLOTS] counters (active markers, halo
+                          // entries) as partial sums
 
     // marker records, sorted by spreading tile (T4 = float4 / double4)
     void *rec_tn;         // T4[nm] {t_x, t_y, t_z, packed base node (bits)}
     void *rec_ud;         // T4[nm] {U^d_x, U^d_y, U^d_z, dV}: rigid-body velocity
                           // u_p + omega_p x o at the marker and its volume
-    void *rec_Gp;         // T4[nm] spreading amplitude G = F dV / h^3 of the pass
+    void *rec_Gp;         // T4[n_iter_cap][nm] spreading amplitude G = F dV / h^3
+                          // of each pass (the adjoint keeps Ub in its first nm)
     void *rec_G;          // T4[nm] G summed over the passes
     int *rec_src;         // [nm] original marker index
     int *m_key;           // [nm] per-marker tile slot (binning scratch)
@@ -47,6 +47,7 @@ struct ibmx_plan_s {
     // tiles
     TileC tc;
     long long tile_cap;   // tiles the tile arrays are sized for
+    long long occ_cap;    // occupancy words sh_occ is sized for
     int *tile_count;      // [ntiles + 1]
     int *tile_start;      // [ntiles + 1]
     int *tile_cursor;     // [ntiles]
@@ -57,10 +58,27 @@ struct ibmx_plan_s {
     double *mean_part;    // [3][ibmx_mean_blocks()] partial sums of ibmx_grid_mean
     int *scan_aux;        // exclusive-scan workspace (ibmx_scan_aux_size ints)
     long long scan_cap;   // elements the workspace serves
-    float4 *tile_gmax;    // [2][ntiles] largest |G| of the pass and |pass sum|
-                          // over each tile's own markers (FP32 spreading scale)
+    float4 *tile_gmax;    // [2][ntiles] largest |G| of the pass over each tile's
+                          // own markers, and its sum over the passes so far
+                          // (fixed-point spreading scales)
+    int2 *halo_tab;       // halo positions of a full tile away from walls, for
+                          // the three- then the four-point support
+    int halo_tab_n[2];
+    int *halo_words;      // the neighbours' occupancy words the table names
+    int halo_words_n[2];
+    // shell (nodes in the supports of the active markers), per tile
+    int *sh_count;        // [ntiles + 1] shell nodes of the tile
+    int *sh_start;        // [ntiles + 1] first compact entry of the tile
+    int *sh_cmax;         // [ntiles] largest number of supports covering a node
+    uint2 *sh_occ;        // [ntiles][ceil(V/32)] {occupancy bits, earlier set bits}
+    double *rpart;        // [n_iter_cap + 1][np] residual partials per particle
+    // compact shell values, in tile order
+    void *sh_u;           // T[3][sh_cap]
+    unsigned short *sh_pos;  // [sh_cap] tile-local index of each entry
+    long long sh_cap;     // min(nodes, 64 nm): shell nodes a call can have
     long long halo_cap;
-    int block;            // threads per workgroup of marker passes
+    int block;            // threads per workgroup of the forcing passes
+    int persist;          // 1: passes as a persistent grid looping over tiles
 
     // backward workspace (allocated by the first backward call): replay
     // grid T[3][nodes], per-pass amplitude and Jacobian T4[n_iter][3][nm],
@@ -165,6 +183,16 @@ ibmx_status ibmx_plan_actm(ibmx_plan p);
 // Grow the contact workspace to list capacities (pair_cap, wall_cap) with
 // `hist_sets` history buffers of IBMX_HIST rows each.
 ibmx_status ibmx_contact_reserve(ibmx_plan p, int pair_cap, int wall_cap, int hist_sets);
+// whether the contact workspace serves these capacities
+bool ibmx_contact_ready(ibmx_plan p, int pair_cap, int wall_cap, int hist_sets);
+// doubles of sub-stepping state for np particles
+long long ibmx_substep_doubles(int np);
+// bytes of the adjoint's workspace
+size_t ibmx_backward_bytes(ibmx_plan p);
+// fluid-solve workspace: grid support, presence, allocation
+bool ibmx_fluid_grid_ok(ibmx_plan p);
+bool ibmx_fluid_ready(ibmx_plan p);
+ibmx_status ibmx_fluid_reserve(ibmx_plan p);
 void ibmx_exclusive_scan(const int *in, int *out, int n, int *aux, hipStream_t s);
 void ibmx_fill_i32(int *p, int v, long long n, hipStream_t s);
 void ibmx_fill_f64(double *p, double v, long long n, hipStream_t s);

@@ -427,17 +427,10 @@ extern "C" ibmx_status ibmx_pairs(ibmx_plan p, const double *xp, const double *r
     if (ncell + 1 > cell_cap)
         return IBMX_ECAPACITY;
     P.ncell = (int)ncell;
-    if (!p->p_cursor || p->p_cell_cap < ncell) {
-        if (p->p_cursor)
-            (void)hipFree(p->p_cursor);
-        p->p_cursor = nullptr;
-        if (hipMalloc((void **)&p->p_cursor, sizeof(int) * (size_t)ncell) != hipSuccess)
-            return IBMX_ENOMEM;
-        p->p_cell_cap = (int)ncell;
-    }
-    if (ibmx_plan_scan_reserve(p, ncell) != IBMX_OK ||
-        ibmx_contact_reserve(p, pair_cap, wall_cap, 1) != IBMX_OK)
-        return IBMX_ENOMEM;
+    // the workspace comes from ibmx_plan_reserve: this call allocates nothing
+    if (!p->p_cursor || p->p_cell_cap < ncell || p->scan_cap < ncell || p->scan_cap < np ||
+        !ibmx_contact_ready(p, pair_cap, wall_cap, 1))
+        return IBMX_ESTATE;
     hipStream_t s = p->stream;
     ProfScope ps(p, IBMX_K_PAIRS);
     // cell list

@@ -3,6 +3,9 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <map>
+#include <vector>
+
 #include "ibmx_internal.hpp"
 
 namespace {
@@ -19,7 +22,9 @@ void free_plan(ibmx_plan p)
 {
     if (!p)
         return;
-    void *ptrs[] = {p->d_moff,      p->d_pid,       p->d_err,        p->d_acc,     p->d_count,
+    void *ptrs[] = {p->d_moff,      p->d_pid,       p->d_err,        p->sh_u,      p->d_count,
+                    p->sh_pos,      p->sh_count,    p->sh_start,     p->sh_cmax,   p->sh_occ,
+                    p->rpart,       p->halo_tab,    p->halo_words,
                     p->rec_tn,      p->rec_ud,      p->rec_src,      p->rec_Gp,    p->rec_G,
                     p->m_key,       p->m_inv,       p->tile_count, p->tile_start,
                     p->tile_cursor, p->halo_count,  p->halo_start,   p->halo_cursor,
@@ -157,13 +162,18 @@ ibmx_status check_params(const ibmx_grid *g, const ibmx_params *prm)
     A((void **)&p->d_moff, sizeof(int) * (npz + 1));
     A((void **)&p->d_pid, sizeof(int) * nmz);
     A((void **)&p->d_err, sizeof(int) * 4);
-    A((void **)&p->d_acc, sizeof(double) * (p->n_iter_cap + 2) * IBMX_RSLOTS);
     A((void **)&p->d_count, sizeof(long long) * 8 * IBMX_RSLOTS);
     A((void **)&p->mean_part, sizeof(double) * 3 * ibmx_mean_blocks());
     A(&p->rec_tn, Ts * 4 * nmz);
     A(&p->rec_ud, Ts * 4 * nmz);
     A(&p->rec_G, Ts * 4 * nmz);
-    A(&p->rec_Gp, Ts * 4 * nmz);
+    A(&p->rec_Gp, Ts * 4 * nmz * (size_t)p->n_iter_cap);
+    // a call's shell has at most one node per grid node and W^3 <= 64 per
+    // active marker
+    p->sh_cap = nodes < 64LL * (long long)nmz ? nodes : 64LL * (long long)nmz;
+    A(&p->sh_u, Ts * 3 * (size_t)p->sh_cap);
+    A((void **)&p->sh_pos, sizeof(unsigned short) * (size_t)p->sh_cap);
+    A((void **)&p->rpart, sizeof(double) * (size_t)(p->n_iter_cap + 1) * npz);
     A((void **)&p->rec_src, sizeof(int) * nmz);
     A((void **)&p->m_key, sizeof(int) * nmz);
     A((void **)&p->m_inv, sizeof(int) * nmz);
@@ -268,16 +278,22 @@ ibmx_status ibmx_plan_alloc_tiles(ibmx_plan p, int tx, int ty, int tz)
     const size_t Ts = p->prec == IBMX_F64 ? sizeof(double) : sizeof(float);
     if ((size_t)3 * t[0] * t[1] * t[2] * Ts > 160 * 1024)
         return IBMX_EUNSUPPORTED;
-    if (!p->tile_count || ntiles > p->tile_cap) {
+    const long long words = ntiles * (((long long)t[0] * t[1] * t[2] + 31) / 32);
+    if (!p->tile_count || ntiles > p->tile_cap || words > p->occ_cap) {
         void *ptrs[] = {p->tile_count, p->tile_start, p->tile_cursor, p->halo_count,
-                        p->halo_start, p->halo_cursor, p->tile_gmax};
+                        p->halo_start, p->halo_cursor, p->tile_gmax, p->sh_count,
+                        p->sh_start,   p->sh_cmax,     p->sh_occ};
         for (void *q : ptrs)
             if (q)
                 (void)hipFree(q);
         p->tile_count = p->tile_start = p->tile_cursor = nullptr;
         p->halo_count = p->halo_start = p->halo_cursor = nullptr;
+        p->sh_count = p->sh_start = p->sh_cmax = nullptr;
+        p->sh_occ = nullptr;
         p->tile_gmax = nullptr;
         p->tc.ntiles = 0;
+        p->tile_cap = 0;
+        p->occ_cap = 0;
         size_t b = sizeof(int) * (size_t)(ntiles + 1);
         if (hipMalloc((void **)&p->tile_count, b) != hipSuccess ||
             hipMalloc((void **)&p->tile_start, b) != hipSuccess ||
@@ -285,9 +301,16 @@ ibmx_status ibmx_plan_alloc_tiles(ibmx_plan p, int tx, int ty, int tz)
             hipMalloc((void **)&p->halo_count, b) != hipSuccess ||
             hipMalloc((void **)&p->halo_start, b) != hipSuccess ||
             hipMalloc((void **)&p->halo_cursor, b) != hipSuccess ||
+            hipMalloc((void **)&p->sh_count, b) != hipSuccess ||
+            hipMalloc((void **)&p->sh_start, b) != hipSuccess ||
+            hipMalloc((void **)&p->sh_cmax, b) != hipSuccess ||
+            hipMalloc((void **)&p->sh_occ, sizeof(uint2) * (size_t)words) != hipSuccess ||
             hipMalloc((void **)&p->tile_gmax, sizeof(float4) * 2 * (size_t)ntiles) != hipSuccess)
             return IBMX_ENOMEM;
         p->tile_cap = ntiles;
+        p->occ_cap = words;
+        if (hipMemset(p->sh_start, 0, b) != hipSuccess)
+            return IBMX_EDEVICE;
     }
     // every marker reaches at most 7 tiles besides its own
     long long cap = 7LL * (p->nm > 0 ? p->nm : 1);
@@ -298,6 +321,72 @@ ibmx_status ibmx_plan_alloc_tiles(ibmx_plan p, int tx, int ty, int tz)
         if (hipMalloc((void **)&p->halo_list, sizeof(int) * (size_t)cap) != hipSuccess)
             return IBMX_ENOMEM;
         p->halo_cap = cap;
+    }
+    // halo table of the region staging, for the three- and four-point
+    // supports: for a full tile away from walls, every region position outside
+    // the tile as {region index | neighbour << 16, slot | bit << 16}, slot
+    // naming the neighbour's occupancy word among the words the table needs
+    // (listed as neighbour | word << 5), bit the node's bit in that word
+    {
+        std::vector<int2> tab;
+        std::vector<int> words;
+        int counts[2] = {0, 0}, wcounts[2] = {0, 0};
+        for (int wi = 0; wi < 2; ++wi) {
+            const int W = 3 + wi;
+            const int R[3] = {t[0] + W - 1, t[1] + W - 1, t[2] + W - 1};
+            std::map<int, int> slot;
+            const size_t w0 = words.size();
+            for (int rz = 0; rz < R[2]; ++rz)
+                for (int ry = 0; ry < R[1]; ++ry)
+                    for (int rx = 0; rx < R[0]; ++rx) {
+                        const int r[3] = {rx, ry, rz};
+                        int d[3], l[3];
+                        bool inner = true;
+                        for (int a = 0; a < 3; ++a) {
+                            const int off = r[a] - 1;
+                            d[a] = off < 0 ? -1 : (off >= t[a] ? 1 : 0);
+                            l[a] = off - d[a] * t[a];
+                            inner = inner && d[a] == 0;
+                        }
+                        if (inner)
+                            continue;
+                        const int ri = (rz * R[1] + ry) * R[0] + rx;
+                        const int ni = (d[0] + 1) + 3 * (d[1] + 1) + 9 * (d[2] + 1);
+                        const int li = (l[2] * t[1] + l[1]) * t[0] + l[0];
+                        const int key = ni | ((li >> 5) << 5);
+                        auto it = slot.find(key);
+                        int sl;
+                        if (it == slot.end()) {
+                            sl = (int)(words.size() - w0);
+                            slot[key] = sl;
+                            words.push_back(key);
+                        } else {
+                            sl = it->second;
+                        }
+                        tab.push_back(make_int2(ri | (ni << 16), li));
+                        (void)sl;
+                        ++counts[wi];
+                    }
+            wcounts[wi] = (int)(words.size() - w0);
+        }
+        if (p->halo_tab)
+            (void)hipFree(p->halo_tab);
+        if (p->halo_words)
+            (void)hipFree(p->halo_words);
+        p->halo_tab = nullptr;
+        p->halo_words = nullptr;
+        if (hipMalloc((void **)&p->halo_tab, sizeof(int2) * tab.size()) != hipSuccess ||
+            hipMalloc((void **)&p->halo_words, sizeof(int) * words.size()) != hipSuccess)
+            return IBMX_ENOMEM;
+        if (hipMemcpy(p->halo_tab, tab.data(), sizeof(int2) * tab.size(), hipMemcpyHostToDevice) !=
+                hipSuccess ||
+            hipMemcpy(p->halo_words, words.data(), sizeof(int) * words.size(),
+                      hipMemcpyHostToDevice) != hipSuccess)
+            return IBMX_EDEVICE;
+        for (int wi = 0; wi < 2; ++wi) {
+            p->halo_tab_n[wi] = counts[wi];
+            p->halo_words_n[wi] = wcounts[wi];
+        }
     }
     for (int a = 0; a < 3; ++a) {
         p->tc.B[a] = t[a];
@@ -383,6 +472,18 @@ extern "C" ibmx_status ibmx_plan_set_tiles(ibmx_plan p, int32_t tx, int32_t ty, 
     return st;
 }
 
+extern "C" ibmx_status ibmx_plan_set_launch(ibmx_plan p, int32_t block, int32_t persistent)
+{
+    if (!p || (block != 64 && block != 128 && block != 256) || (persistent != 0 && persistent != 1))
+        return IBMX_EINVAL;
+    p->block = block;
+    p->persist = persistent;
+    p->stats.block = block;
+    p->stats.persistent = persistent;
+    ibmx_plan_drop_graph(p);
+    return IBMX_OK;
+}
+
 extern "C" ibmx_status ibmx_plan_set_stream(ibmx_plan p, void *stream)
 {
     if (!p)
@@ -425,9 +526,16 @@ extern "C" ibmx_status ibmx_plan_stats(ibmx_plan p, ibmx_stats *out)
             tot[k] += c[k * IBMX_RSLOTS + i];
     free(c);
     p->stats.n_active = tot[0];
-    p->stats.shell_nodes = tot[1];
     p->stats.halo_entries = tot[2];
+    // shell nodes of the last call: the end of the compact entries
+    int shell = 0;
+    if (p->sh_start && p->tc.ntiles > 0 &&
+        hipMemcpy(&shell, p->sh_start + p->tc.ntiles, sizeof(int), hipMemcpyDeviceToHost) !=
+            hipSuccess)
+        return IBMX_EDEVICE;
+    p->stats.shell_nodes = shell;
     p->stats.block = p->block;
+    p->stats.persistent = p->persist;
     for (int i = 0; i < p->ev_used; ++i) {
         float ms = 0.0f;
         if (hipEventElapsedTime(&ms, p->ev[2 * i], p->ev[2 * i + 1]) != hipSuccess)
@@ -482,6 +590,71 @@ ibmx_status ibmx_plan_actm(ibmx_plan p)
     p->actm_K = K;
     p->actm_D = D;
     p->actm_e = p->prm.e_dry;
+    return IBMX_OK;
+}
+
+long long ibmx_substep_doubles(int np) { return 22LL * (np > 0 ? np : 1); }
+
+bool ibmx_contact_ready(ibmx_plan p, int pair_cap, int wall_cap, int hist_sets)
+{
+    const long long nadj = 2LL * pair_cap + wall_cap;
+    const long long nh = (long long)hist_sets * IBMX_HIST * ((long long)pair_cap + wall_cap);
+    return p->c_adj && p->c_adj_cap >= nadj && (nh == 0 || (p->c_hist && p->c_hist_cap >= nh));
+}
+
+extern "C" ibmx_status ibmx_plan_reserve(ibmx_plan p, int32_t pair_cap, int32_t wall_cap,
+                                         int32_t cell_cap, int32_t flags)
+{
+    if (!p || pair_cap < 0 || wall_cap < 0 || cell_cap < 0 ||
+        (flags & ~(IBMX_RESERVE_BACKWARD | IBMX_RESERVE_FLUID)) != 0)
+        return IBMX_EINVAL;
+    if ((flags & IBMX_RESERVE_FLUID) && !ibmx_fluid_grid_ok(p))
+        return IBMX_EUNSUPPORTED;
+    if (hipStreamSynchronize(p->stream) != hipSuccess)
+        return IBMX_EDEVICE;
+    // cell list of the pair pass: cell_cap - 1 cells
+    const long long cells = cell_cap > 1 ? (long long)cell_cap - 1 : 1;
+    if (!p->p_cursor || p->p_cell_cap < cells) {
+        if (p->p_cursor)
+            (void)hipFree(p->p_cursor);
+        p->p_cursor = nullptr;
+        p->p_cell_cap = 0;
+        if (hipMalloc((void **)&p->p_cursor, sizeof(int) * (size_t)cells) != hipSuccess)
+            return IBMX_ENOMEM;
+        p->p_cell_cap = (int)cells;
+    }
+    if (ibmx_plan_scan_reserve(p, cells > p->np ? cells : p->np) != IBMX_OK)
+        return IBMX_ENOMEM;
+    // contact adjacency and two history sets (the sub-steps alternate them)
+    if (ibmx_contact_reserve(p, pair_cap, wall_cap, 2) != IBMX_OK)
+        return IBMX_ENOMEM;
+    const long long need = ibmx_substep_doubles(p->np);
+    if (!p->s_buf || p->s_cap < need) {
+        if (p->s_buf)
+            (void)hipFree(p->s_buf);
+        p->s_buf = nullptr;
+        p->s_cap = 0;
+        if (hipMalloc((void **)&p->s_buf, sizeof(double) * (size_t)need) != hipSuccess)
+            return IBMX_ENOMEM;
+        p->s_cap = need;
+    }
+    if (flags & IBMX_RESERVE_BACKWARD) {
+        const size_t nb = ibmx_backward_bytes(p);
+        if (!p->bw_u || p->bw_bytes < nb) {
+            if (p->bw_u)
+                (void)hipFree(p->bw_u);
+            p->bw_u = nullptr;
+            p->bw_bytes = 0;
+            if (hipMalloc(&p->bw_u, nb) != hipSuccess)
+                return IBMX_ENOMEM;
+            p->bw_bytes = nb;
+        }
+    }
+    if (flags & IBMX_RESERVE_FLUID) {
+        const ibmx_status st = ibmx_fluid_reserve(p);
+        if (st != IBMX_OK)
+            return st;
+    }
     return IBMX_OK;
 }
 

@@ -165,18 +165,10 @@ extern "C" ibmx_status ibmx_particle_substeps(ibmx_plan p, double dt_total, int3
         return IBMX_EINVAL;
     if (np == 0)
         return IBMX_OK;
-    if (ibmx_contact_reserve(p, pair_cap, wall_cap, 2) != IBMX_OK)
-        return IBMX_ENOMEM;
-    const long long need = 22LL * np;
-    if (need > p->s_cap) {
-        if (p->s_buf)
-            (void)hipFree(p->s_buf);
-        p->s_buf = nullptr;
-        p->s_cap = 0;
-        if (hipMalloc((void **)&p->s_buf, sizeof(double) * (size_t)need) != hipSuccess)
-            return IBMX_ENOMEM;
-        p->s_cap = need;
-    }
+    // the workspace comes from ibmx_plan_reserve: this call allocates nothing
+    if (!ibmx_contact_ready(p, pair_cap, wall_cap, 2) || !p->s_buf ||
+        p->s_cap < ibmx_substep_doubles(np))
+        return IBMX_ESTATE;
     hipStream_t s = p->stream;
     ProfScope ps(p, IBMX_K_PAIRS);
     PairC P;

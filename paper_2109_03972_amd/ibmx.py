@@ -18,12 +18,13 @@ LIB_PATH = os.path.join(_HERE, "libibmx.so")
 
 OK, EINVAL, EDOMAIN, ENOMEM, EDEVICE, ESTATE, ECAPACITY, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 F64, F32 = 0, 1
+RESERVE_BACKWARD, RESERVE_FLUID = 1, 2
 
 # every entry point declared in include/ibmx.h
 API = (
     "ibmx_plan_create", "ibmx_plan_destroy", "ibmx_plan_set_markers", "ibmx_plan_set_params",
     "ibmx_plan_set_stream", "ibmx_plan_set_tiles", "ibmx_plan_status", "ibmx_plan_stats",
-    "ibmx_plan_profile",
+    "ibmx_plan_profile", "ibmx_plan_set_launch", "ibmx_plan_reserve",
     "ibmx_forcing", "ibmx_forcing_graph",
     "ibmx_forcing_backward", "ibmx_pairs", "ibmx_tune", "ibmx_particle_integrals",
     "ibmx_grid_mean", "ibmx_particle_substeps", "ibmx_project", "ibmx_fluid_predictor",
@@ -62,7 +63,8 @@ class ibmx_stats(ctypes.Structure):
     _fields_ = [("n_markers", ctypes.c_int64), ("n_active", ctypes.c_int64),
                 ("shell_nodes", ctypes.c_int64), ("tiles", ctypes.c_int64),
                 ("halo_entries", ctypes.c_int64), ("tile", ctypes.c_int32 * 3),
-                ("block", ctypes.c_int32), ("kernel_ms", ctypes.c_double * 8),
+                ("block", ctypes.c_int32), ("persistent", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("kernel_ms", ctypes.c_double * 8),
                 ("kernel_launches", ctypes.c_int64 * 8)]
 
 KERNEL_CLASSES = ("geometry", "interp", "spread", "backward", "pairs", "other", "ftot", "graph")
@@ -98,6 +100,10 @@ def lib():
         L.ibmx_plan_stats.argtypes = [P, ctypes.POINTER(ibmx_stats)]
         L.ibmx_plan_profile.restype = St
         L.ibmx_plan_profile.argtypes = [P, i32]
+        L.ibmx_plan_set_launch.restype = St
+        L.ibmx_plan_set_launch.argtypes = [P, i32, i32]
+        L.ibmx_plan_reserve.restype = St
+        L.ibmx_plan_reserve.argtypes = [P, i32, i32, i32, i32]
         L.ibmx_forcing.restype = St
         L.ibmx_forcing.argtypes = [P] * 11
         L.ibmx_forcing_graph.restype = St
@@ -229,6 +235,9 @@ class Plan:
         _check(st, "ibmx_plan_create")
         self.handle = h_
         self._markers = None
+        # workspace reserved with ibmx_plan_reserve: pair, wall, cell
+        # capacities and flags
+        self._res = [0, 0, 0, 0]
 
     @classmethod
     def from_case(cls, case, precision="f64", params=None):
@@ -266,6 +275,41 @@ class Plan:
         _check(lib().ibmx_plan_set_tiles(self.handle, int(tx), int(ty), int(tz)),
                "ibmx_plan_set_tiles")
 
+    def reserve(self, pair_cap: int = 0, wall_cap: int = 0, cell_cap: int = 0,
+                backward: bool = False, fluid: bool = False):
+        """ibmx_plan_reserve: grow the workspace of the pair pass, the
+        sub-stepping, the adjoint and the fluid solves (synchronises; call it
+        outside graph capture)."""
+        flags = (RESERVE_BACKWARD if backward else 0) | (RESERVE_FLUID if fluid else 0)
+        _check(lib().ibmx_plan_reserve(self.handle, int(pair_cap), int(wall_cap), int(cell_cap),
+                                       flags), "ibmx_plan_reserve")
+        r = self._res
+        self._res = [max(r[0], int(pair_cap)), max(r[1], int(wall_cap)), max(r[2], int(cell_cap)),
+                     r[3] | flags]
+
+    def _ensure(self, pair_cap=0, wall_cap=0, cell_cap=0, flags=0):
+        """Reserve what a call needs beyond the current reservation."""
+        r = self._res
+        if pair_cap > r[0] or wall_cap > r[1] or cell_cap > r[2] or (flags & ~r[3]):
+            self.reserve(max(r[0], pair_cap), max(r[1], wall_cap), max(r[2], cell_cap),
+                         backward=bool((flags | r[3]) & RESERVE_BACKWARD),
+                         fluid=bool((flags | r[3]) & RESERVE_FLUID))
+
+    def _ensure_fluid(self):
+        """Reserve the solver workspace before the first solve; on grids the
+        solves do not take, leave it to the call to report EUNSUPPORTED."""
+        if self._res[3] & RESERVE_FLUID:
+            return
+        try:
+            self._ensure(flags=RESERVE_FLUID)
+        except IbmxError as e:
+            if e.code != EUNSUPPORTED:
+                raise
+
+    def set_launch(self, block: int = 256, persistent: bool = False):
+        _check(lib().ibmx_plan_set_launch(self.handle, int(block), int(persistent)),
+               "ibmx_plan_set_launch")
+
     def status(self) -> int:
         return int(lib().ibmx_plan_status(self.handle))
 
@@ -277,6 +321,7 @@ class Plan:
         _check(lib().ibmx_plan_stats(self.handle, ctypes.byref(s)), "ibmx_plan_stats")
         return dict(n_markers=s.n_markers, n_active=s.n_active, shell_nodes=s.shell_nodes,
                     tiles=s.tiles, halo_entries=s.halo_entries, tile=tuple(s.tile), block=s.block,
+                    persistent=s.persistent,
                     kernel_ms={k: s.kernel_ms[i] for i, k in enumerate(KERNEL_CLASSES)},
                     kernel_launches={k: s.kernel_launches[i] for i, k in enumerate(KERNEL_CLASSES)})
 
@@ -321,6 +366,7 @@ class Plan:
         _want(g_T, torch.float64, (3, self.np), "g_T")
         _want(mask, torch.uint8, (self.nm,), "mask")
         dev = u0.device
+        self._ensure(flags=RESERVE_BACKWARD)
         if gu0 is None:
             gu0 = torch.empty(grid_shape, dtype=self.dtype, device=dev)
         gxp = torch.empty((3, self.np), dtype=torch.float64, device=dev)
@@ -350,6 +396,7 @@ class Plan:
         pair_cap = int(pair_cap or max(64, 16 * self.np))
         wall_cap = int(wall_cap or max(64, 2 * self.np))
         cell_cap = int(cell_cap or (1 << 20))
+        self._ensure(pair_cap, wall_cap, cell_cap)
         i32, f64 = torch.int32, torch.float64
         cell_start = torch.empty(cell_cap, dtype=i32, device=dev)
         cellp = torch.empty(max(self.np, 1), dtype=i32, device=dev)
@@ -404,6 +451,7 @@ class Plan:
         _want(Fh, f64, (3, self.np), "Fh")
         _want(Th, f64, (3, self.np), "Th")
         pc, wc = int(lists["pair_cap"]), int(lists["wall_cap"])
+        self._ensure(pc, wc)
         _want(lists["pairs"], torch.int32, (2, pc), "pairs")
         _want(lists["walls"], torch.int32, (2, wc), "walls")
         _want(lists["counts"], torch.int32, (2,), "counts")
@@ -445,6 +493,7 @@ class Plan:
         _want(lapnu, self.dtype, (3,) + shape, "lapnu")
         _want(P, self.dtype, shape, "P")
         _want(fbar, torch.float64, (3,), "fbar")
+        self._ensure_fluid()
         self._sync_stream()
         st = lib().ibmx_fluid_helmholtz(self.handle, _ptr(u), _ptr(lapnu), _ptr(P), _ptr(fbar),
                                         float(dt), float(theta))
@@ -459,6 +508,7 @@ class Plan:
         _want(P, self.dtype, shape, "P")
         uf = torch.empty_like(u)
         phi = torch.empty_like(P) if want_phi else None
+        self._ensure_fluid()
         self._sync_stream()
         st = lib().ibmx_project(self.handle, _ptr(u), _ptr(uf), _ptr(P), _ptr(phi), float(theta))
         _check(st, "ibmx_project")

@@ -1,5 +1,6 @@
 """Host logic of bench.py: the one-GPU refusal and the algorithmic byte
-counts its roofline divides by (records per marker, values per shell node)."""
+counts its roofline divides by (records per marker-update, values per shell
+node)."""
 import os
 import subprocess
 import sys
@@ -20,18 +21,19 @@ def test_more_than_one_gpu_is_refused():
 
 
 @pytest.mark.parametrize("s", [4, 8])
-def test_forcing_bytes_per_launch(s):
-    n, S = 1000, 7000
-    # interpolation: packed node + fractions (4 + 3s), U^d and dV (4s), G written (3s),
-    # pass sum read and written (6s); the shell read once (3s per node)
-    assert bench.algorithmic_bytes("interp", s, n, S) == n * (4 + 3 * s + 4 * s + 3 * s + 6 * s) + S * 3 * s
-    # spreading: node + fractions and G per record; u read and written per shell node,
-    # f_tot as well when the call has a single pass
-    assert bench.algorithmic_bytes("spread", s, n, S, n_iter=5) == n * (4 + 6 * s) + S * 6 * s
-    assert bench.algorithmic_bytes("spread", s, n, S, n_iter=1) == n * (4 + 6 * s) + S * 12 * s
-    assert bench.algorithmic_bytes("ftot", s, n, S) == n * (4 + 6 * s) + S * 6 * s
+def test_pass_bytes(s):
+    n, S, H = 1000, 4100, 600
+    # the roofline's bytes per pass: a 20 B (FP32) or 32 B (FP64) record per
+    # marker-update, four accesses of the three components per shell node
+    rec = 20 if s == 4 else 32
+    assert bench.pass_bytes(s, n, S) == n * rec + S * 4 * 3 * s
+    # FP32 at S/N = 4.08: about 216 B per marker-update
+    assert 215 < bench.pass_bytes(4, 1000, 4080) / 1000 < 217
+    # the build's own launches: T4 records (4s), 2-byte entry indices
+    assert bench.design_bytes("interp", s, n, S, H) == n * 3 * 4 * s + S * (3 * s + 2)
+    assert bench.design_bytes("spread", s, n, S, H) == (n + H) * 2 * 4 * s + H * 4 + S * (6 * s + 2)
     with pytest.raises(KeyError):
-        bench.algorithmic_bytes("other", s, n, S)
+        bench.design_bytes("other", s, n, S, H)
 
 
 def test_fluid_bytes_per_call():

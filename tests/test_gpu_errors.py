@@ -42,7 +42,7 @@ def test_list_capacity_exceeded_reports_and_counts():
     plan's status, the counts are the full lengths, the entries that fit
     are the first ones of the canonical order."""
     import torch
-    case = _small()
+    case = synth.make_case("bidisperse_bed_256x256x512", lazy_field=True)
     ref = oracle.pairs(case)
     npairs, nwall = ref["pairs"].shape[1], ref["walls"].shape[1]
     assert npairs >= 3 and nwall >= 1, (npairs, nwall)

@@ -119,3 +119,34 @@ def test_no_particles(precision):
                      z, z, radius_max=1.0)
     plan.check("no particles pairs")
     assert res["counts"].cpu().tolist() == [0, 0]
+
+
+@pytest.mark.parametrize("name", ["suspension_128", "small"])
+def test_f32_arithmetic_and_end_to_end_errors(name):
+    """FP32 forward errors of every output measured two ways (reading c-25):
+    (i) against the oracle on the FP32-rounded velocity the kernels start
+    from (the arithmetic error of the FP32 path) and (ii) against the oracle
+    on the FP64 inputs (end to end, including the rounding of u0).  Both
+    are held to the FP32 tolerances; (i) is the smaller."""
+    if name == "small":
+        c = synth.small_case(109, n=(41, 37, 45), periodic=(1, 1, 0), n_iter=3, touch=0.3)
+    else:
+        c = synth.make_case(name)
+    mask = _mask_for(c)
+    u32 = c.u0.astype(np.float32).astype(np.float64)
+    ref_e2e = oracle.forcing(c, mask=mask, want_U=True)
+    ref_ari = oracle.forcing(c, u0=u32, mask=mask, want_U=True)
+    got = gpu_forcing(c, "f32", mask=mask, want_U=True)
+    assert got["status"] == 0
+    act = np.ones(c.nm, dtype=bool) if mask is None else mask.astype(bool)
+    out = {}
+    for k in ("U", "u", "f_tot", "S", "T", "resid"):
+        g = got[k][:, :, act] if k == "U" else got[k]
+        ra = ref_ari[k][:, :, act] if k == "U" else ref_ari[k]
+        re = ref_e2e[k][:, :, act] if k == "U" else ref_e2e[k]
+        out[k] = (rel_err(g, ra), rel_err(g, re))
+        print(f"{name} f32 {k}: arithmetic {out[k][0]:.2e}  end-to-end {out[k][1]:.2e}",
+              flush=True)
+    assert out["U"][0] <= 1e-5 and out["U"][1] <= 1e-5
+    for k in ("u", "f_tot", "S", "T", "resid"):
+        assert out[k][0] <= 1e-4 and out[k][1] <= 1e-4, (k, out[k])

@@ -33,8 +33,11 @@ def _run(plan, D, u0, mk, graph, resid=None):
                         graph=graph)
     plan.check("graph" if graph else "eager")
     torch.cuda.synchronize()
-    return dict(u=D["u"].double().cpu().numpy(), f_tot=D["f"].double().cpu().numpy(),
-                S=S.cpu().numpy(), T=T.cpu().numpy())
+    out = dict(u=D["u"].double().cpu().numpy(), f_tot=D["f"].double().cpu().numpy(),
+               S=S.cpu().numpy(), T=T.cpu().numpy())
+    if resid is not None:
+        out["resid"] = resid.cpu().numpy().copy()
+    return out
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
@@ -50,13 +53,15 @@ def test_graph_replays_match_eager_and_oracle(oracle_lib, precision):
     ref = oracle_lib.forcing(case, mask=m_np)
     tol = 1e-12 if precision == "f64" else 1e-4
     for rep in range(4):
+        resid.fill_(-1.0)
         got = _run(plan, D, u0, mk, True, resid)
         # eager torch work between replays
         _ = (D["u"] * 2.0).sum().item()
-        for k in ("u", "f_tot", "S", "T"):
+        for k in ("u", "f_tot", "S", "T", "resid"):
             e = rel_err(got[k], ref[k])
             assert e <= tol, f"replay {rep} {k}: {e:.3e}"
-            # integer fixed-point spreading and ordered sums: replays are
+            # integer fixed-point spreading, per-tile residual partials added
+            # in tile order, particle sums in marker order: replays are
             # bit-identical to the eager call in both precisions
             np.testing.assert_array_equal(got[k], eager[k], err_msg=f"replay {rep} {k}")
 
@@ -117,9 +122,11 @@ def test_tune_keeps_inputs_and_results(oracle_lib, precision):
     f_before = D["f"].clone()
     st = plan.tune(D["u"], D["f"], D["xp"], D["up"], D["wp"], mask=mk)
     plan.check("tune")
-    print(f"{precision}: tuned tile {st['tile']} block {st['block']}", flush=True)
+    print(f"{precision}: tuned tile {st['tile']} block {st['block']} persistent "
+          f"{st['persistent']}", flush=True)
     assert torch.equal(D["u"], u_before) and torch.equal(D["f"], f_before)
     assert all(4 <= t <= 32 for t in st["tile"])
+    assert st["block"] in (64, 128, 256) and st["persistent"] in (0, 1)
     got = _run(plan, D, u_before, mk, False)
     got_g = _run(plan, D, u_before, mk, True)
     ref = oracle_lib.forcing(case, mask=m_np)
@@ -160,3 +167,38 @@ def test_set_tiles_rejects_bad_shapes():
         with pytest.raises(ibmx.IbmxError):
             plan.set_tiles(*bad)
         assert plan.stats()["tile"] == before
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_launch_forms_bit_identical(oracle_lib, precision):
+    """Every workgroup size the tuner tries (64, 128, 256 threads: the markers
+    a tile's workgroup takes at once) and both launch forms (one workgroup
+    per tile; a persistent grid looping over the tiles) give the same bits,
+    eager and replayed as a graph, and match the oracle."""
+    import torch
+    dev = require_gpu()
+    case = synth.small_case(76, n=(44, 40, 46), periodic=(1, 1, 0), n_iter=3, touch=0.4)
+    m_np, mk = _mask(case, dev)
+    ref = oracle_lib.forcing(case, mask=m_np)
+    plan, D = _setup(case, precision)
+    plan.set_tiles(8, 8, 8)
+    u0 = D["u"].clone()
+    resid = torch.zeros(int(case.params["n_iter"]) + 1, dtype=torch.float64, device=dev)
+    base = _run(plan, D, u0, mk, False, resid)
+    tol = 1e-12 if precision == "f64" else 1e-4
+    for k in ("u", "f_tot", "S", "T", "resid"):
+        assert rel_err(base[k], ref[k]) <= tol, k
+    for block in (64, 128, 256):
+        for persistent in (False, True):
+            plan.set_launch(block, persistent)
+            st = plan.stats()
+            assert (st["block"], st["persistent"]) == (block, int(persistent))
+            for graph in (False, True):
+                got = _run(plan, D, u0, mk, graph, resid)
+                for k in ("u", "f_tot", "S", "T", "resid"):
+                    np.testing.assert_array_equal(
+                        got[k], base[k], err_msg=f"block {block} persistent {persistent} {k}")
+    from paper_2109_03972_amd import ibmx
+    for bad in ((32, 0), (512, 0), (256, 2)):
+        with pytest.raises(ibmx.IbmxError):
+            plan.set_launch(*bad)

@@ -147,3 +147,97 @@ def test_lists_without_pairs(layout):
     else:
         assert got["walls"].shape[1] == 1
         assert (got["wgap"][0] < 0) == (layout == "one_overlapping_wall")
+
+
+def test_pair_pass_captured_on_its_first_call():
+    """With its workspace reserved beforehand (ibmx_plan_reserve), the pair
+    pass allocates nothing and synchronises nothing, so its very first call
+    can be captured into a HIP graph.  Each replay, with eager work and
+    synchronisations between them, gives the oracle's lists and mask and the
+    bits of an eager call."""
+    import torch
+    case = synth.make_case("bidisperse_bed_256x256x512", lazy_field=True)
+    D = dev_case(case, "f64")
+    npart = case.np_
+    caps = dict(pair_cap=16 * npart, wall_cap=2 * npart, cell_cap=1 << 16,
+                radius_max=float(case.radius.max()))
+    eager_plan = ibmx.Plan.from_case(case, "f64")
+    eager_plan.set_markers(D["body"], D["dV"])
+    eager = eager_plan.pairs(D["xp"], D["radius"], D["mass"], D["up"], D["wp"], **caps)
+    eager_plan.check("eager pairs")
+    plan = ibmx.Plan.from_case(case, "f64")
+    plan.set_markers(D["body"], D["dV"])
+    plan.reserve(caps["pair_cap"], caps["wall_cap"], caps["cell_cap"])
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        res = plan.pairs(D["xp"], D["radius"], D["mass"], D["up"], D["wp"], **caps)
+    ref_l = oracle.pairs(case)
+    ref_m = oracle.marker_mask(case, ref_l)
+    k = ref_l["pairs"].shape[1]
+    for rep in range(3):
+        for key in ("pairs", "Fc", "mask"):
+            res[key].fill_(-1 if key != "mask" else 7)
+        g.replay()
+        torch.cuda.synchronize()
+        assert plan.status() == 0
+        _ = (D["xp"] * 2.0).sum().item()     # eager work between replays
+        kw = ref_l["walls"].shape[1]
+        assert res["counts"].cpu().tolist() == [k, kw]
+        assert np.array_equal(res["pairs"][:, :k].cpu().numpy(), ref_l["pairs"])
+        assert np.array_equal(res["mask"][:case.nm].cpu().numpy(), ref_m)
+        ncell = int(oracle.cell_list(case)["cell_start"].shape[0])
+        got = dict(pairs=res["pairs"][:, :k], gap=res["gap"][:k], hist=res["hist"][:, :k],
+                   walls=res["walls"][:, :kw], whist=res["whist"][:, :kw], Fc=res["Fc"],
+                   Tc=res["Tc"], mask=res["mask"][:case.nm], cell=res["cell_start"][:ncell])
+        want = dict(pairs=eager["pairs"][:, :k], gap=eager["gap"][:k], hist=eager["hist"][:, :k],
+                    walls=eager["walls"][:, :kw], whist=eager["whist"][:, :kw], Fc=eager["Fc"],
+                    Tc=eager["Tc"], mask=eager["mask"][:case.nm],
+                    cell=eager["cell_start"][:ncell])
+        for key in got:
+            assert torch.equal(got[key], want[key]), f"replay {rep} {key}"
+
+
+def test_unreserved_workspace_is_estate():
+    """Without ibmx_plan_reserve the pair pass, the sub-stepping, the adjoint
+    and the fluid solves refuse to run (ESTATE) instead of allocating."""
+    import ctypes
+    import torch
+    case = synth.small_case(206, n=(32, 32, 32), periodic=(1, 1, 1), diameters=(8.0, 7.0))
+    D = dev_case(case, "f64")
+    plan = ibmx.Plan.from_case(case, "f64")
+    plan.set_markers(D["body"], D["dV"])
+    L = ibmx.lib()
+    i32 = torch.int32
+    cs = torch.zeros(4096, dtype=i32, device=D["xp"].device)
+    cp = torch.zeros(case.np_, dtype=i32, device=D["xp"].device)
+    lst = torch.zeros((2, 64), dtype=i32, device=D["xp"].device)
+    gap = torch.zeros(64, dtype=torch.float64, device=D["xp"].device)
+    hist = torch.zeros((4, 64), dtype=torch.float64, device=D["xp"].device)
+    cnt = torch.zeros(2, dtype=i32, device=D["xp"].device)
+    F = torch.zeros((3, case.np_), dtype=torch.float64, device=D["xp"].device)
+    V = ctypes.c_void_p
+    st = L.ibmx_pairs(plan.handle, V(D["xp"].data_ptr()), V(D["radius"].data_ptr()), 4.0,
+                      V(D["mass"].data_ptr()), V(D["up"].data_ptr()), V(D["wp"].data_ptr()),
+                      0, None, None, 0, None, None, V(cs.data_ptr()), 4096, V(cp.data_ptr()),
+                      V(lst.data_ptr()), V(gap.data_ptr()), V(hist.data_ptr()), 64,
+                      V(lst.data_ptr()), V(gap.data_ptr()), V(hist.data_ptr()), 64,
+                      V(cnt.data_ptr()), V(F.data_ptr()), V(F.data_ptr()), None)
+    assert st == ibmx.ESTATE
+    st = L.ibmx_particle_substeps(plan.handle, 1.0, 2, V(D["xp"].data_ptr()),
+                                  V(D["up"].data_ptr()), V(D["wp"].data_ptr()),
+                                  V(D["radius"].data_ptr()), V(D["mass"].data_ptr()), None, None,
+                                  V(cnt.data_ptr()), 64, V(lst.data_ptr()), 64,
+                                  V(lst.data_ptr()), V(hist.data_ptr()), V(hist.data_ptr()),
+                                  None, None)
+    assert st == ibmx.ESTATE
+    u = torch.zeros((3, 32, 32, 32), dtype=torch.float64, device=D["xp"].device)
+    P = torch.zeros((32, 32, 32), dtype=torch.float64, device=D["xp"].device)
+    assert L.ibmx_project(plan.handle, V(u.data_ptr()), V(u.data_ptr()), V(P.data_ptr()), None,
+                          0.0) == ibmx.ESTATE
+    st = L.ibmx_forcing_backward(plan.handle, V(u.data_ptr()), V(D["xp"].data_ptr()),
+                                 V(D["up"].data_ptr()), V(D["wp"].data_ptr()), None, None, None,
+                                 None, None, V(u.data_ptr()), V(F.data_ptr()), V(F.data_ptr()),
+                                 V(F.data_ptr()))
+    assert st == ibmx.ESTATE
+    torch.cuda.synchronize()
+    plan.close()
