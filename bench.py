@@ -49,23 +49,24 @@ def pass_bytes(s: int, n_act: int, shell: int) -> float:
 
 
 def design_bytes(kind: str, s: int, n_act: int, shell: int, halo: int) -> float:
-    """Bytes this build's kernels must move per launch (reported beside the
-    roofline): records of T4 = 4s bytes, 2-byte tile-local indices of the
-    compact shell entries, halo = (marker, neighbouring tile) entries.
+    """Bytes the tile kernels must move per launch at least (reported beside
+    the roofline): marker records of T4 = 4s bytes, halo = (marker,
+    neighbouring tile) entries.
 
     interp: per own marker the fractions and base node (4s) and the
             rigid-body velocity and volume (4s) read, the amplitude G (4s)
-            written; the tile's own compact shell values and indices read
-            (3s + 2 per shell node; the halo values the region needs come
-            from the neighbours' runs and are not counted).
+            written; the three velocity components of every shell node read
+            (3s).  Each tile stages its whole region, shell or not, with a
+            margin of W - 1 nodes shared with its neighbours: its reads
+            exceed this bound.
     spread: per own and halo entry the fractions and base node (4s) and G
-            (4s) read, plus the halo list (4 B); per shell node the compact
-            values read and written and the index read (6s + 2).
+            (4s) read, plus the halo list (4 B); per shell node the three
+            components read and written (6s).
     """
     if kind == "interp":
-        return float(n_act * 12 * s + shell * (3 * s + 2))
+        return float(n_act * 12 * s + shell * 3 * s)
     if kind == "spread":
-        return float((n_act + halo) * 8 * s + halo * 4 + shell * (6 * s + 2))
+        return float((n_act + halo) * 8 * s + halo * 4 + shell * 6 * s)
     raise KeyError(kind)
 
 
@@ -435,7 +436,7 @@ def main():
     achieved = b_pass / (t_pass * 1e-3) / 1e9
     tr = [measured_traffic(args.workload, k, r32["tile"]) for k in ("interp", "spread")]
     traffic = None if None in tr else tr[0] + tr[1]
-    roof = dict(bound="hbm", kernel="k_interp_sh + k_spread_sh (one forcing pass)",
+    roof = dict(bound="hbm", kernel="k_interp + k_spread (one forcing pass)",
                 achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                 bytes_per_pass=b_pass, ms_per_pass=t_pass,

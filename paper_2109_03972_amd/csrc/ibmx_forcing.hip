@@ -4,24 +4,25 @@
 //   binning (once)  marker geometry in FP64 (X_l = x_p + o_l -> base node,
 //                   fractional offsets, periodic wrap, wall check), then a
 //                   counting sort of the active markers by the spatial tile of
-//                   their centre node (markers of one particle stay contiguous
-//                   and in index order inside a tile), and per tile a halo list
-//                   of the neighbouring tiles' markers whose delta support
-//                   reaches into it.
-//   passes          one workgroup per tile.  Every marker whose support
-//                   reaches the tile (own + halo) is interpolated from
-//                   u^{m-1}, gets F = (U^d - U)/c and the spreading amplitude
-//                   G = F dV / h^3, and adds w G into an LDS copy of the tile.
-//                   The workgroup owns its tile's nodes and writes
-//                   u^m = u^{m-1} + c f into a second grid (ping-pong: the
-//                   neighbours still read u^{m-1} during the pass).  Own
-//                   markers also feed the FP64 particle sums, the residual and
-//                   the per-marker sum of G over the passes.
+//                   their centre node, and per tile a halo list of the
+//                   neighbouring tiles' markers whose delta support reaches
+//                   into it.
+//   passes          two launches per pass, one workgroup per tile.  The
+//                   interpolation stages the tile's region of u^{m-1} in LDS,
+//                   gives every own marker U, F = (U^d - U)/c in FP64 and the
+//                   spreading amplitude G = F dV / h^3 (kept per pass), and
+//                   its residual term.  The spreading adds w G of every marker
+//                   whose support reaches the tile (own + halo) into an LDS
+//                   copy of the tile in integer fixed point, and the
+//                   workgroup, sole owner of its nodes, writes u^m = u^{m-1} +
+//                   c f^m in place (the interpolation of the pass has ended).
+//   sums (once)     per particle, in marker order, the FP64 sums over markers
+//                   and passes of G and o x G (S_p, T_p), the residual terms,
+//                   and every marker's pass-summed amplitude.
 //   f_tot (once)    spreading is linear and the markers do not move during the
 //                   call, so sum_m f^m is the spread of the summed amplitudes:
 //                   one last tile pass adds it to f_tot.
-// With a single pass the interpolation runs marker-parallel and the final
-// tile pass updates u and f_tot together.
+// With a single pass that pass's spreading updates u and f_tot together.
 #include <math.h>
 
 #include "ibmx_internal.hpp"
@@ -725,21 +726,22 @@ __device__ __forceinline__ void region_base(const GridC &g, const TileBox &box, 
 // integer add 9 and a 64-bit integer add 15, so both precisions accumulate
 // integers, and the integer sums do not depend on the order of the additions.
 // Per component a power-of-two scale bounds every node's sum: with m the
-// largest |G| that can reach the tile (m < 2^ex), n the largest number of
-// supports covering one node of the tile and w_max = 8/27 the largest weight
-// product of the delta (phi(0)^3; 1/8 for the four-point delta), a node's sum
-// is below n w_max m, so the scale 2^(30 - ex - cb) with 2^cb >= n w_max keeps
-// it below 2^30 (FP32: 32-bit sums) and 2^(62 - ex - cb) below 2^62 (FP64:
-// 64-bit sums).  No sum can wrap, however dense the markers; the rounding of
-// each term is at most half an integer, 2^(ex + cb - 31) (2^(ex + cb - 63)) of
-// m.  FP32 keeps (x, y) of a node in one 64-bit word, y 2^32 + x as a
-// two's-complement sum (exact while both partial sums fit 32 bits, which the
-// bound guarantees), and z in a 32-bit word: two atomics per node.
+// largest |G| that can reach the tile (m < 2^ex), n the number of markers
+// whose supports reach the tile (no node lies in more supports) and w_max =
+// 8/27 the largest weight product of the delta (phi(0)^3; 1/8 for the
+// four-point delta), a node's sum is below n w_max m, so the scale
+// 2^(30 - ex - cb) with 2^cb >= n w_max keeps it below 2^30 (FP32: 32-bit
+// sums) and 2^(62 - ex - cb) below 2^62 (FP64: 64-bit sums).  No sum can
+// wrap, however dense the markers; the rounding of each term is at most half
+// an integer, 2^(ex + cb - 31) (2^(ex + cb - 63)) of m.  FP32 keeps (x, y)
+// of a node in one 64-bit word, y 2^32 + x as a two's-complement sum (exact
+// while both partial sums fit 32 bits, which the bound guarantees), and z in
+// a 32-bit word: two atomics per node.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int cover_bits(int cmax)
+__device__ __forceinline__ int cover_bits(int n)
 {
-    // smallest cb >= 0 with 2^cb >= cmax * 8/27
-    const float bound = (float)cmax * (8.0f / 27.0f);
+    // smallest cb >= 0 with 2^cb >= n * 8/27
+    const float bound = (float)n * (8.0f / 27.0f);
     int cb = 0;
     if (bound > 1.0f) {
         frexpf(bound, &cb);     // bound < 2^cb
@@ -752,11 +754,11 @@ struct SpreadAcc;
 template <>
 struct SpreadAcc<float> {
     static constexpr int BYTES = 12;   // per node
-    __device__ static float scale_for(float m, int cmax)
+    __device__ static float scale_for(float m, int n)
     {
         int ex = 0;
         frexpf(m, &ex);                  // m < 2^ex
-        return m > 0.0f ? ldexpf(1.0f, min(30 - ex - cover_bits(cmax), 126)) : 0.0f;
+        return m > 0.0f ? ldexpf(1.0f, min(30 - ex - cover_bits(n), 126)) : 0.0f;
     }
     __device__ static float unscale_for(float s) { return s > 0.0f ? 1.0f / s : 0.0f; }
     __device__ static void zero(unsigned char *lds, int V)
@@ -790,11 +792,11 @@ struct SpreadAcc<float> {
 template <>
 struct SpreadAcc<double> {
     static constexpr int BYTES = 24;
-    __device__ static double scale_for(float m, int cmax)
+    __device__ static double scale_for(float m, int n)
     {
         int ex = 0;
         frexpf(m, &ex);
-        return m > 0.0f ? ldexp(1.0, min(62 - ex - cover_bits(cmax), 1000)) : 0.0;
+        return m > 0.0f ? ldexp(1.0, min(62 - ex - cover_bits(n), 1000)) : 0.0;
     }
     __device__ static double unscale_for(double s) { return s > 0.0 ? 1.0 / s : 0.0; }
     __device__ static void zero(unsigned char *lds, int V)
@@ -822,27 +824,50 @@ struct SpreadAcc<double> {
     }
 };
 
+// Tile index of neighbour ni = (dx + 1) + 3 (dy + 1) + 9 (dz + 1) of a tile
+// (periodic wrap; -1 beyond a wall).
+__device__ __forceinline__ int neighbour_tile(const GridC &g, const TileC &tc, int tile, int ni)
+{
+    const int d[3] = {ni % 3 - 1, (ni / 3) % 3 - 1, ni / 9 - 1};
+    int t[3] = {tile % tc.nt[0], (tile / tc.nt[0]) % tc.nt[1], tile / (tc.nt[0] * tc.nt[1])};
+    for (int a = 0; a < 3; ++a) {
+        t[a] += d[a];
+        if (t[a] < 0 || t[a] >= tc.nt[a]) {
+            if (!g.periodic[a])
+                return -1;
+            t[a] = t[a] < 0 ? t[a] + tc.nt[a] : t[a] - tc.nt[a];
+        }
+    }
+    return t[0] + tc.nt[0] * (t[1] + tc.nt[1] * t[2]);
+}
+
 // ---------------------------------------------------------------------------
 // spreading, one workgroup per tile.  Every marker whose support reaches
 // the tile (own + halo list) adds w G to the tile's nodes in LDS; then the
 // workgroup, owner of its nodes, applies u += c f (add_u) and f_tot += f
-// (add_f) with plain loads and stores.
+// (add_f) with plain loads and stores.  tile_max (per tile, the largest |G|
+// of its own markers) bounds the amplitudes from the tile and its 26
+// neighbours (a support of at most W <= B nodes reaches one tile further at
+// most); without it the workgroup takes the largest |G| of the markers it
+// adds.  The fixed-point scale also takes the number n of markers the tile
+// receives: no node lies in more than n supports.  count_shell adds the
+// number of nodes that received a nonzero sum to a counter.
 // ---------------------------------------------------------------------------
 template <typename T, int W, bool O32>
-__global__ __launch_bounds__(256) void k_spread(GridC g, TileC tc, T c, int add_u, int add_f,
-                                                const int *__restrict__ sh_cmax,
-                                                const int *__restrict__ tile_start,
-                                                const int *__restrict__ halo_start,
-                                                const int *__restrict__ halo_list,
-                                                const typename V4<T>::type *__restrict__ rec_tn,
-                                                const typename V4<T>::type *__restrict__ rec_G,
-                                                const float4 *__restrict__ tile_max,
-                                                T *__restrict__ u, T *__restrict__ f_tot)
+__device__ __forceinline__ void spread_tile(int tile, const GridC &g, const TileC &tc, T c,
+                                            int add_u, int add_f, int count_shell,
+                                            const int *__restrict__ tile_start,
+                                            const int *__restrict__ halo_start,
+                                            const int *__restrict__ halo_list,
+                                            const typename V4<T>::type *__restrict__ rec_tn,
+                                            const typename V4<T>::type *__restrict__ rec_G,
+                                            const float4 *__restrict__ tile_max,
+                                            T *__restrict__ u, T *__restrict__ f_tot,
+                                            long long *__restrict__ count)
 {
     typedef typename V4<T>::type T4;
     extern __shared__ __align__(16) unsigned char smem[];
     unsigned char *acc = smem;
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
     const int a0 = tile_start[tile], a1 = tile_start[tile + 1];
     const int h0 = halo_start[tile], h1 = halo_start[tile + 1];
     const int n_own = a1 - a0, n_tot = n_own + (h1 - h0);
@@ -858,32 +883,14 @@ __global__ __launch_bounds__(256) void k_spread(GridC g, TileC tc, T c, int add_
         ptn = rec_tn[j];
         pgv = rec_G[j];
     }
-    T scale[3] = {T(1), T(1), T(1)}, unscale[3] = {T(1), T(1), T(1)};
-    SpreadAcc<T>::zero(acc, V);
+    __shared__ float s_gm[3];
     if (tile_max) {
-        // bound on the amplitudes reaching the tile: the largest |G| of the
-        // own markers of the tile and of its 26 neighbours (a support of at
-        // most W <= B nodes reaches one tile further at most)
-        __shared__ float s_gm[3];
         if (threadIdx.x < IBMX_WAVE) {
             float m[3] = {0.f, 0.f, 0.f};
             if (threadIdx.x < 27) {
-                const int dd[3] = {(int)threadIdx.x % 3 - 1, ((int)threadIdx.x / 3) % 3 - 1,
-                                   (int)threadIdx.x / 9 - 1};
-                int t[3] = {tile % tc.nt[0], (tile / tc.nt[0]) % tc.nt[1],
-                            tile / (tc.nt[0] * tc.nt[1])};
-                bool ok = true;
-                for (int a = 0; a < 3; ++a) {
-                    t[a] += dd[a];
-                    if (t[a] < 0 || t[a] >= tc.nt[a]) {
-                        if (g.periodic[a])
-                            t[a] = t[a] < 0 ? t[a] + tc.nt[a] : t[a] - tc.nt[a];
-                        else
-                            ok = false;
-                    }
-                }
-                if (ok) {
-                    const float4 v = tile_max[t[0] + tc.nt[0] * (t[1] + tc.nt[1] * t[2])];
+                const int tt = neighbour_tile(g, tc, tile, threadIdx.x);
+                if (tt >= 0) {
+                    const float4 v = tile_max[tt];
                     m[0] = v.x;
                     m[1] = v.y;
                     m[2] = v.z;
@@ -898,14 +905,7 @@ __global__ __launch_bounds__(256) void k_spread(GridC g, TileC tc, T c, int add_
                 for (int a = 0; a < 3; ++a)
                     s_gm[a] = m[a];
         }
-        __syncthreads();
-        const int cmax = sh_cmax[tile];
-        for (int a = 0; a < 3; ++a) {
-            scale[a] = SpreadAcc<T>::scale_for(s_gm[a], cmax);
-            unscale[a] = SpreadAcc<T>::unscale_for(scale[a]);
-        }
     } else {
-        // largest amplitude reaching the tile, per component
         float gm[3] = {0.f, 0.f, 0.f};
         for (int e = threadIdx.x; e < n_tot; e += blockDim.x) {
             const int j = e < n_own ? a0 + e : halo_list[h0 + e - n_own];
@@ -914,13 +914,19 @@ __global__ __launch_bounds__(256) void k_spread(GridC g, TileC tc, T c, int add_
             gm[1] = fmaxf(gm[1], fabsf((float)gv.y));
             gm[2] = fmaxf(gm[2], fabsf((float)gv.z));
         }
-        const int cmax = sh_cmax[tile];
         for (int a = 0; a < 3; ++a) {
-            scale[a] = SpreadAcc<T>::scale_for(block_max<float>(gm[a]), cmax);
-            unscale[a] = SpreadAcc<T>::unscale_for(scale[a]);
+            gm[a] = block_max<float>(gm[a]);
+            if (threadIdx.x == 0)
+                s_gm[a] = gm[a];
         }
     }
+    SpreadAcc<T>::zero(acc, V);
     __syncthreads();
+    T scale[3], unscale[3];
+    for (int a = 0; a < 3; ++a) {
+        scale[a] = SpreadAcc<T>::scale_for(s_gm[a], n_tot);
+        unscale[a] = SpreadAcc<T>::unscale_for(scale[a]);
+    }
     for (int e = threadIdx.x; e < n_tot; e += blockDim.x) {
         const T4 tn = ptn, gv = pgv;
         if (e + (int)blockDim.x < n_tot) {
@@ -961,6 +967,7 @@ __global__ __launch_bounds__(256) void k_spread(GridC g, TileC tc, T c, int add_
     }
     __syncthreads();
     const long long N = g.nodes;
+    int touched = 0;
     const int wave = threadIdx.x / IBMX_WAVE;
     const TileWalk tw(tc, box.e[0]);
     // component bases (node indices fit 32 bits: the grid has < 2^31 nodes)
@@ -997,6 +1004,7 @@ __global__ __launch_bounds__(256) void k_spread(GridC g, TileC tc, T c, int add_
         for (int q = 0; q < UNR; ++q) {
             if (!act[q])
                 continue;
+            ++touched;
             if (add_f)
 #pragma unroll
                 for (int a = 0; a < 3; ++a)
@@ -1007,435 +1015,70 @@ __global__ __launch_bounds__(256) void k_spread(GridC g, TileC tc, T c, int add_
                     grid_at<T, O32>(ub[a], gi[q]) = uo[q][a] + c * fv[q][a];
         }
     }
+    if (count_shell)
+        slot_add(count + IBMX_RSLOTS, block_sum<long long>(touched));
 }
 
-
-// ---------------------------------------------------------------------------
-// Shell-compacted passes of the forward loop.
-//
-// A pass reads and writes only the shell: the nodes inside the delta
-// supports of the active markers.  In a packed bed they are about a third of
-// the nodes and fall in nearly every 64-byte sector of the grid, so passes
-// over the dense grid move about three times the shell's bytes.  The call
-// therefore gathers the shell values of u into a compact array, tile by tile,
-// runs its passes there, and writes u and f_tot back once at the end.
-//   marking (once)  one workgroup per tile counts, for every node of the
-//       tile, the supports of its own and halo markers that cover it.  The
-//       nonzero counts form the tile's occupancy bitmap, kept as 32-node words
-//       {bits, set bits in the tile's earlier words}; the largest count bounds
-//       the spreading's fixed-point sums.
-//   gather (once)  shell node k of tile t (tile-local index order) is entry
-//       sh_start[t] + k of the compact arrays: its tile-local index (16 bits)
-//       and its three velocity components.
-//   interpolation  stages the tile's own entries (one contiguous run) and
-//       the halo around the tile (found through the neighbours' bitmaps) into
-//       the region box in LDS; the marker loop is the dense one.
-//   spreading  accumulates as the dense pass and updates the tile's own
-//       entries; the last spreading of a call (summed amplitudes into f_tot,
-//       or the only pass) also writes u back.
-// ---------------------------------------------------------------------------
-
-// tile-local index li = (lz B1 + ly) B0 + lx -> (lx, ly, lz)
-__device__ __forceinline__ void local_xyz(const TileC &tc, int li, int &lx, int &ly, int &lz)
+// One workgroup per tile (PERSIST false), or a fixed grid of workgroups (a
+// multiple of the 8 XCDs) each taking tiles blockIdx.x, blockIdx.x +
+// gridDim.x, ... until the tiles run out (PERSIST true).
+template <typename T, int W, bool O32, bool PERSIST>
+__global__ __launch_bounds__(256) void k_spread(GridC g, TileC tc, T c, int add_u, int add_f,
+                                                int count_shell,
+                                                const int *__restrict__ tile_start,
+                                                const int *__restrict__ halo_start,
+                                                const int *__restrict__ halo_list,
+                                                const typename V4<T>::type *__restrict__ rec_tn,
+                                                const typename V4<T>::type *__restrict__ rec_G,
+                                                const float4 *__restrict__ tile_max,
+                                                T *__restrict__ u, T *__restrict__ f_tot,
+                                                long long *__restrict__ count)
 {
-    if (tc.sh[0] >= 0 && tc.sh[1] >= 0) {
-        lx = li & (tc.B[0] - 1);
-        const int r = li >> tc.sh[0];
-        ly = r & (tc.B[1] - 1);
-        lz = r >> tc.sh[1];
+    if (PERSIST) {
+        for (int v = blockIdx.x; v < tc.ntiles; v += gridDim.x) {
+            spread_tile<T, W, O32>(xcd_remap(v, tc.ntiles), g, tc, c, add_u, add_f, count_shell,
+                                   tile_start, halo_start, halo_list, rec_tn, rec_G, tile_max, u,
+                                   f_tot, count);
+            __syncthreads();
+        }
     } else {
-        const int r = li / tc.B[0];
-        lx = li - r * tc.B[0];
-        lz = r / tc.B[1];
-        ly = r - lz * tc.B[1];
+        spread_tile<T, W, O32>(xcd_remap(blockIdx.x, gridDim.x), g, tc, c, add_u, add_f,
+                               count_shell, tile_start, halo_start, halo_list, rec_tn, rec_G,
+                               tile_max, u, f_tot, count);
     }
 }
 
-__device__ __forceinline__ size_t node_index(const GridC &g, const TileBox &box, int lx, int ly,
-                                             int lz)
-{
-    return ((size_t)(box.o[2] + lz) * (size_t)g.n[1] + (size_t)(box.o[1] + ly)) * (size_t)g.n[0] +
-           (size_t)(box.o[0] + lx);
-}
 
-// Marking: per-node support counts of the tile (LDS), occupancy words and
-// the tile's shell count and largest count.
-template <typename T, int W>
-__global__ __launch_bounds__(256) void k_shell_mark(
-    GridC g, TileC tc, int ow, const int *__restrict__ tile_start,
-    const int *__restrict__ halo_start, const int *__restrict__ halo_list,
-    const typename V4<T>::type *__restrict__ rec_tn, int *__restrict__ sh_count,
-    int *__restrict__ sh_cmax, uint2 *__restrict__ sh_occ)
-{
-    typedef typename V4<T>::type T4;
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int V = tc.B[0] * tc.B[1] * tc.B[2];
-    unsigned *cnt = reinterpret_cast<unsigned *>(smem);   // [V]
-    unsigned *wbits = cnt + V;                             // [ow]
-    unsigned *wpre = wbits + ow;                           // [ow]
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
-    const int a0 = tile_start[tile], a1 = tile_start[tile + 1];
-    const int h0 = halo_start[tile], h1 = halo_start[tile + 1];
-    const int n_own = a1 - a0, n_tot = n_own + (h1 - h0);
-    const TileBox box(g, tc, tile);
-    for (int i = threadIdx.x; i < V; i += blockDim.x)
-        cnt[i] = 0u;
-    __syncthreads();
-    for (int e = threadIdx.x; e < n_tot; e += blockDim.x) {
-        const int j = e < n_own ? a0 + e : halo_list[h0 + e - n_own];
-        const T4 tn = rec_tn[j];
-        int b[3];
-        unpack_node(g, V4<T>::to_bits(tn.w), b);
-        int ix[3][W];
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int k = 0; k < W; ++k)
-                ix[a][k] = axis_node(g, a, b[a], k) - box.o[a];
-#pragma unroll
-        for (int k = 0; k < W; ++k) {
-            if ((unsigned)ix[2][k] >= (unsigned)box.e[2])
-                continue;
-#pragma unroll
-            for (int jj = 0; jj < W; ++jj) {
-                if ((unsigned)ix[1][jj] >= (unsigned)box.e[1])
-                    continue;
-                const int row = (ix[2][k] * tc.B[1] + ix[1][jj]) * tc.B[0];
-#pragma unroll
-                for (int i = 0; i < W; ++i)
-                    if ((unsigned)ix[0][i] < (unsigned)box.e[0])
-                        atomicAdd(&cnt[row + ix[0][i]], 1u);
-            }
-        }
-    }
-    __syncthreads();
-    // occupancy bits, 64 nodes per wave and round
-    const int lane = threadIdx.x & (IBMX_WAVE - 1), wave = threadIdx.x / IBMX_WAVE;
-    const int nw = blockDim.x / IBMX_WAVE;
-    unsigned cmax = 0u;
-    for (int base = wave * IBMX_WAVE; base < ow * 32; base += nw * IBMX_WAVE) {
-        const int li = base + lane;
-        const unsigned cv = li < V ? cnt[li] : 0u;
-        cmax = cv > cmax ? cv : cmax;
-        const unsigned long long m = __ballot(cv != 0u);
-        if (lane == 0) {
-            const int w = base / 32;
-            wbits[w] = (unsigned)m;
-            if (w + 1 < ow)
-                wbits[w + 1] = (unsigned)(m >> 32);
-        }
-    }
-    __syncthreads();
-    // exclusive prefix of the words' set bits (first wave, 64 words a round)
-    if (wave == 0) {
-        unsigned carry = 0u;
-        for (int w0 = 0; w0 < ow; w0 += IBMX_WAVE) {
-            const int w = w0 + lane;
-            const unsigned c = w < ow ? (unsigned)__popc(wbits[w]) : 0u;
-            unsigned x = c;
-#pragma unroll
-            for (int off = 1; off < IBMX_WAVE; off <<= 1) {
-                const unsigned y = __shfl_up(x, off, IBMX_WAVE);
-                if (lane >= off)
-                    x += y;
-            }
-            if (w < ow)
-                wpre[w] = carry + x - c;
-            carry += __shfl(x, IBMX_WAVE - 1, IBMX_WAVE);
-        }
-        if (lane == 0)
-            sh_count[tile] = (int)carry;
-    }
-    __syncthreads();
-    for (int w = threadIdx.x; w < ow; w += blockDim.x)
-        sh_occ[(size_t)tile * ow + w] = make_uint2(wbits[w], wpre[w]);
-    const unsigned cm = block_max<unsigned>(cmax);
-    if (threadIdx.x == 0)
-        sh_cmax[tile] = (int)cm;
-}
-
-// Gather of the shell values of u into the compact arrays (and their
-// tile-local indices).
-template <typename T>
-__global__ __launch_bounds__(256) void k_shell_gather(GridC g, TileC tc, int ow,
-                                                      const int *__restrict__ sh_start,
-                                                      const uint2 *__restrict__ sh_occ,
-                                                      const T *__restrict__ u, T *__restrict__ sh_u,
-                                                      long long cap,
-                                                      unsigned short *__restrict__ sh_pos)
-{
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
-    const int s0 = sh_start[tile];
-    if (sh_start[tile + 1] == s0)
-        return;
-    const TileBox box(g, tc, tile);
-    const int V = tc.B[0] * tc.B[1] * tc.B[2];
-    const size_t N = (size_t)g.nodes;
-    constexpr int GU = 8;   // nodes per thread and round: their loads overlap
-    for (int li0 = threadIdx.x; li0 < V; li0 += GU * blockDim.x) {
-        uint2 w[GU];
-#pragma unroll
-        for (int q = 0; q < GU; ++q) {
-            const int li = li0 + q * (int)blockDim.x;
-            w[q] = li < V ? sh_occ[(size_t)tile * ow + (li >> 5)] : make_uint2(0u, 0u);
-        }
-        long long e[GU];
-        T v[GU][3];
-#pragma unroll
-        for (int q = 0; q < GU; ++q) {
-            const int li = li0 + q * (int)blockDim.x;
-            const unsigned bit = 1u << (li & 31);
-            e[q] = -1;
-            if (!(w[q].x & bit))
-                continue;
-            const long long ee = (long long)s0 + w[q].y + __popc(w[q].x & (bit - 1u));
-            if (ee >= cap)
-                continue;   // cannot happen: the shell has at most min(nodes, 64 nm) nodes
-            e[q] = ee;
-            int lx, ly, lz;
-            local_xyz(tc, li, lx, ly, lz);
-            const size_t gi = node_index(g, box, lx, ly, lz);
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                v[q][c] = u[(size_t)c * N + gi];
-        }
-#pragma unroll
-        for (int q = 0; q < GU; ++q) {
-            if (e[q] < 0)
-                continue;
-            sh_pos[e[q]] = (unsigned short)(li0 + q * (int)blockDim.x);
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                sh_u[(size_t)c * cap + e[q]] = v[q][c];
-        }
-    }
-}
-
-// Tile index of neighbour ni = (dx + 1) + 3 (dy + 1) + 9 (dz + 1) of a tile
-// (periodic wrap; -1 beyond a wall).
-__device__ __forceinline__ int neighbour_tile(const GridC &g, const TileC &tc, int tile, int ni)
-{
-    const int d[3] = {ni % 3 - 1, (ni / 3) % 3 - 1, ni / 9 - 1};
-    int t[3] = {tile % tc.nt[0], (tile / tc.nt[0]) % tc.nt[1], tile / (tc.nt[0] * tc.nt[1])};
-    for (int a = 0; a < 3; ++a) {
-        t[a] += d[a];
-        if (t[a] < 0 || t[a] >= tc.nt[a]) {
-            if (!g.periodic[a])
-                return -1;
-            t[a] = t[a] < 0 ? t[a] + tc.nt[a] : t[a] - tc.nt[a];
-        }
-    }
-    return t[0] + tc.nt[0] * (t[1] + tc.nt[1] * t[2]);
-}
-
-// The 27 tiles around a tile and their first compact entries, in LDS;
-// nb_start[27] = the end of the tile's own entries.
-__device__ __forceinline__ void load_neighbours(const GridC &g, const TileC &tc, int tile,
-                                                const int *__restrict__ sh_start, int *nb_tile,
-                                                int *nb_start)
-{
-    if (threadIdx.x == 27)
-        nb_start[27] = sh_start[tile + 1];
-    if (threadIdx.x < 27) {
-        const int tt = neighbour_tile(g, tc, tile, threadIdx.x);
-        nb_tile[threadIdx.x] = tt;
-        nb_start[threadIdx.x] = tt >= 0 ? sh_start[tt] : 0;
-    }
-}
-
-// Whether a tile's halo follows the plan's table: a full tile whose
-// neighbours along every axis are full tiles of the grid (no wall, no short
-// tile across a periodic seam).
-__device__ __forceinline__ bool halo_by_table(const GridC &g, const TileC &tc, int tile,
-                                              const TileBox &box)
-{
-    const int t[3] = {tile % tc.nt[0], (tile / tc.nt[0]) % tc.nt[1], tile / (tc.nt[0] * tc.nt[1])};
-    bool ok = true;
-    for (int a = 0; a < 3; ++a)
-        ok = ok && box.e[a] == tc.B[a] &&
-             ((g.periodic[a] && g.n[a] % tc.B[a] == 0) || (t[a] >= 1 && t[a] <= tc.nt[a] - 2));
-    return ok;
-}
-
-// Stage the compact velocity over the tile's support region [o - 1,
-// o + B + W - 2) per axis into LDS: the tile's own entries [s0, s1) from
-// their contiguous run, every other region node from its owner's entries (0
-// when it is not a shell node or lies beyond a wall).  Region positions
-// inside the tile that are not shell nodes are left unwritten: no own
-// marker's support reaches them.  The halo positions of a tile that
-// halo_by_table accepts come from the plan's table {region index |
-// neighbour << 16, the neighbour's local index} (the same for every such
-// tile); other tiles decode them.  Each thread issues all its loads of one
-// kind before it waits for any (table entries, then occupancy words and the
-// neighbours' first entries, then values), so that their latencies overlap.
-constexpr int SH_UNR = 4;
-constexpr int HB = 8;
-template <typename T, int W>
-__device__ __forceinline__ void stage_shell(const GridC &g, const TileC &tc, int ow, int tile,
-                                            const TileBox &box, bool table, int s0, int s1,
-                                            const int *__restrict__ sh_start,
-                                            const uint2 *__restrict__ sh_occ,
-                                            const unsigned short *__restrict__ sh_pos,
-                                            const T *__restrict__ sh_u, long long cap,
-                                            const int2 *__restrict__ htab, int hn, T *reg)
-{
-    const int R0 = tc.B[0] + W - 1, R1 = tc.B[1] + W - 1, R2 = tc.B[2] + W - 1;
-    const int RV = R0 * R1 * R2;
-    const T *const c0 = sh_u, *const c1 = sh_u + cap, *const c2 = sh_u + 2 * cap;
-    const int e0 = box.e[0], e1 = box.e[1], e2 = box.e[2];
-    const int plane = R0 * R1;
-    const int zout = (R2 - e2) * plane;
-    const int rows_out = (R1 - e1) * R0;
-    const int per_inner = rows_out + e1 * (R0 - e0);
-    const int H = table ? hn : zout + e2 * per_inner;
-    const int bd = blockDim.x;
-    const int rounds_own = (s1 - s0 + SH_UNR * bd - 1) / (SH_UNR * bd);
-    const int rounds_halo = (H + HB * bd - 1) / (HB * bd);
-    const int rounds = rounds_own > rounds_halo ? rounds_own : rounds_halo;
-    for (int rd = 0; rd < rounds; ++rd) {
-        // own entries of this round: indices and values
-        int oli[SH_UNR];
-        T ov[SH_UNR][3];
-#pragma unroll
-        for (int q = 0; q < SH_UNR; ++q) {
-            const int e = s0 + (rd * SH_UNR + q) * bd + (int)threadIdx.x;
-            oli[q] = -1;
-            if (e < s1) {
-                oli[q] = sh_pos[e];
-                ov[q][0] = c0[e];
-                ov[q][1] = c1[e];
-                ov[q][2] = c2[e];
-            }
-        }
-        // halo positions of this round: region index, owner tile and local
-        // index (owner -1: none, the value is 0)
-        int ri[HB], tt[HB], li[HB];
-        int2 te[HB];
-        if (table) {
-#pragma unroll
-            for (int q = 0; q < HB; ++q) {
-                const int k = (rd * HB + q) * bd + (int)threadIdx.x;
-                te[q] = k < H ? htab[k] : make_int2(-1, 0);
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < HB; ++q) {
-            const int k = (rd * HB + q) * bd + (int)threadIdx.x;
-            ri[q] = -1;
-            tt[q] = -1;
-            li[q] = 0;
-            if (k >= H)
-                continue;
-            if (table) {
-                ri[q] = te[q].x & 0xffff;
-                tt[q] = neighbour_tile(g, tc, tile, te[q].x >> 16);
-                li[q] = te[q].y;
-                continue;
-            }
-            int rx, ry, rz;
-            if (k < zout) {
-                const int j = k / plane, rem = k - j * plane;
-                rz = j == 0 ? 0 : e2 + j;
-                ry = rem / R0;
-                rx = rem - ry * R0;
-            } else {
-                const int kk = k - zout;
-                const int j = kk / per_inner, rem = kk - j * per_inner;
-                rz = 1 + j;
-                if (rem < rows_out) {
-                    const int jr = rem / R0;
-                    rx = rem - jr * R0;
-                    ry = jr == 0 ? 0 : e1 + jr;
-                } else {
-                    const int r2 = rem - rows_out, wx = R0 - e0;
-                    const int jr = r2 / wx, xi = r2 - jr * wx;
-                    ry = 1 + jr;
-                    rx = xi == 0 ? 0 : e0 + xi;
-                }
-            }
-            ri[q] = (rz * R1 + ry) * R0 + rx;
-            const int r[3] = {rx, ry, rz};
-            int l[3], t[3];
-            bool ok = true;
-            for (int a = 0; a < 3; ++a) {
-                // offset from the tile's first node; -1 .. B + W - 2
-                int gn = box.o[a] + r[a] - 1;
-                if (gn < 0 || gn >= g.n[a]) {
-                    if (g.periodic[a])
-                        gn = gn < 0 ? gn + g.n[a] : gn - g.n[a];
-                    else
-                        ok = false;
-                }
-                t[a] = tile_of(tc, a, gn);
-                l[a] = gn - t[a] * tc.B[a];
-            }
-            if (ok) {
-                tt[q] = t[0] + tc.nt[0] * (t[1] + tc.nt[1] * t[2]);
-                li[q] = (l[2] * tc.B[1] + l[1]) * tc.B[0] + l[0];
-            }
-        }
-        uint2 w[HB];
-        int ns[HB];
-#pragma unroll
-        for (int q = 0; q < HB; ++q) {
-            w[q] = make_uint2(0u, 0u);
-            ns[q] = 0;
-            if (tt[q] >= 0) {
-                w[q] = sh_occ[(size_t)tt[q] * ow + (li[q] >> 5)];
-                ns[q] = sh_start[tt[q]];
-            }
-        }
-        T hv[HB][3];
-#pragma unroll
-        for (int q = 0; q < HB; ++q) {
-            hv[q][0] = hv[q][1] = hv[q][2] = T(0);
-            const unsigned bit = 1u << (li[q] & 31);
-            if (w[q].x & bit) {
-                const long long e = (long long)ns[q] + w[q].y + __popc(w[q].x & (bit - 1u));
-                hv[q][0] = c0[e];
-                hv[q][1] = c1[e];
-                hv[q][2] = c2[e];
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < SH_UNR; ++q) {
-            if (oli[q] < 0)
-                continue;
-            int lx, ly, lz;
-            local_xyz(tc, oli[q], lx, ly, lz);
-            reg_put<T>(reg, RV, ((lz + 1) * R1 + ly + 1) * R0 + lx + 1, ov[q][0], ov[q][1],
-                       ov[q][2]);
-        }
-#pragma unroll
-        for (int q = 0; q < HB; ++q)
-            if (ri[q] >= 0)
-                reg_put<T>(reg, RV, ri[q], hv[q][0], hv[q][1], hv[q][2]);
-    }
-}
-
-// Interpolation of one pass on the compact velocity, one workgroup per tile.
-// Every own marker gathers its W^3 stencil from the staged region, forms
-// F = (U^d - U)/c in FP64 and G = F dV / h^3.  MODE 0 (a pass): writes
-// {G, dV |U^d - U|^2} per marker and the per-tile largest |G|; MODE 2 (the
-// residual on the final velocity): writes dV |U^d - U|^2 into the w of the
-// marker's record.  The residual terms are summed per particle in marker
-// order afterwards, so the residual does not depend on the order of the
-// markers within a tile.
-template <typename T, int W, int MODE>
-__device__ __forceinline__ void interp_sh_tile(
-    int tile, const GridC &g, const TileC &tc, int ow, int nm, int pass, double c,
-    const int *__restrict__ tile_start, const typename V4<T>::type *__restrict__ rec_tn,
-    const typename V4<T>::type *__restrict__ rec_ud, const int *__restrict__ rec_src,
-    const int *__restrict__ sh_start, const uint2 *__restrict__ sh_occ,
-    const unsigned short *__restrict__ sh_pos, const T *__restrict__ sh_u, long long cap,
-    const int2 *__restrict__ htab, int hn, const int *__restrict__ wtab, int nw,
-    typename V4<T>::type *__restrict__ rec_G, T *__restrict__ U_dbg,
-    float4 *__restrict__ tile_max)
+// ---------------------------------------------------------------------------
+// interpolation of one pass, one workgroup per tile.  The velocity of the
+// tile and of the support halo around it (R[a] = B[a] + W - 1 nodes per
+// axis, starting one node before the tile) is staged in LDS with coalesced
+// row loads; each own marker then gathers its W^3 stencil from LDS, forms
+// F = (U^d - U)/c in FP64 and G = F dV / h^3.  The first marker records of
+// every thread are loaded before the staging so that their latency overlaps
+// it.
+// MODE 0 (a pass): writes {G, dV |U^d - U|^2} per marker into the pass's
+// record, the pass's largest |G| per tile into tile_max[tile] and the sum of
+// the passes' largest |G| (a bound of |sum_m G^m|) into tile_max[ntiles +
+// tile].  MODE 2 (the residual on the final velocity): writes dV |U^d - U|^2
+// into the w of the marker's record.  The residual terms are summed per
+// particle in marker order afterwards, so the residual does not depend on
+// the order of the markers within a tile.
+// ---------------------------------------------------------------------------
+template <typename T, int W, int MODE, bool O32>
+__device__ __forceinline__ void interp_tile(int tile, const GridC &g, const TileC &tc, int nm,
+                                            int pass, double c, const int *__restrict__ tile_start,
+                                            const typename V4<T>::type *__restrict__ rec_tn,
+                                            const typename V4<T>::type *__restrict__ rec_ud,
+                                            const int *__restrict__ rec_src,
+                                            const T *__restrict__ u,
+                                            typename V4<T>::type *__restrict__ rec_G,
+                                            T *__restrict__ U_dbg, float4 *__restrict__ tile_max)
 {
     typedef typename V4<T>::type T4;
     extern __shared__ __align__(16) unsigned char smem[];
     T *reg = reinterpret_cast<T *>(smem);
     const int a0 = tile_start[tile], a1 = tile_start[tile + 1];
-    const int s0 = sh_start[tile], s1 = sh_start[tile + 1];
     const int n_own = a1 - a0;
     if (n_own == 0) {
         if (MODE == 0 && threadIdx.x == 0) {
@@ -1454,8 +1097,7 @@ __device__ __forceinline__ void interp_sh_tile(
         tn = rec_tn[a0 + threadIdx.x];
         ud = rec_ud[a0 + threadIdx.x];
     }
-    stage_shell<T, W>(g, tc, ow, tile, box, halo_by_table(g, tc, tile, box), s0, s1, sh_start,
-                      sh_occ, sh_pos, sh_u, cap, htab, hn, reg);
+    stage_region<T, W, O32>(g, tc, box, u, T(1), (const T *)nullptr, reg);
     __syncthreads();
     float gmax[3] = {0.f, 0.f, 0.f};
     for (int e = threadIdx.x; e < n_own; e += blockDim.x) {
@@ -1516,8 +1158,6 @@ __device__ __forceinline__ void interp_sh_tile(
         for (int a = 0; a < 3; ++a)
             gmax[a] = block_max<float>(gmax[a]);
         if (threadIdx.x == 0) {
-            // the pass's largest |G| and, for the summed amplitudes, the sum
-            // of the passes' largest |G| (a bound of |sum_m G^m|)
             tile_max[tile] = make_float4(gmax[0], gmax[1], gmax[2], 0.f);
             float4 sm = make_float4(gmax[0], gmax[1], gmax[2], 0.f);
             if (pass > 0) {
@@ -1531,250 +1171,24 @@ __device__ __forceinline__ void interp_sh_tile(
     }
 }
 
-// One workgroup per tile (PERSIST false), or a fixed grid of workgroups
-// (a multiple of the XCD count) each taking tiles blockIdx.x,
-// blockIdx.x + gridDim.x, ... until the tiles run out (PERSIST true).
-template <typename T, int W, int MODE, bool PERSIST>
-__global__ __launch_bounds__(256) void k_interp_sh(
-    GridC g, TileC tc, int ow, int nm, int pass, double c, const int *__restrict__ tile_start,
+template <typename T, int W, int MODE, bool O32, bool PERSIST>
+__global__ __launch_bounds__(256) void k_interp(
+    GridC g, TileC tc, int nm, int pass, double c, const int *__restrict__ tile_start,
     const typename V4<T>::type *__restrict__ rec_tn, const typename V4<T>::type *__restrict__ rec_ud,
-    const int *__restrict__ rec_src, const int *__restrict__ sh_start,
-    const uint2 *__restrict__ sh_occ, const unsigned short *__restrict__ sh_pos,
-    const T *__restrict__ sh_u, long long cap, const int2 *__restrict__ htab, int hn,
-    const int *__restrict__ wtab, int nw, typename V4<T>::type *__restrict__ rec_G,
-    T *__restrict__ U_dbg, float4 *__restrict__ tile_max)
+    const int *__restrict__ rec_src, const T *__restrict__ u,
+    typename V4<T>::type *__restrict__ rec_G, T *__restrict__ U_dbg,
+    float4 *__restrict__ tile_max)
 {
     if (PERSIST) {
         for (int v = blockIdx.x; v < tc.ntiles; v += gridDim.x) {
-            interp_sh_tile<T, W, MODE>(xcd_remap(v, tc.ntiles), g, tc, ow, nm, pass, c, tile_start,
-                                       rec_tn, rec_ud, rec_src, sh_start, sh_occ, sh_pos, sh_u,
-                                       cap, htab, hn, wtab, nw, rec_G, U_dbg, tile_max);
+            interp_tile<T, W, MODE, O32>(xcd_remap(v, tc.ntiles), g, tc, nm, pass, c, tile_start,
+                                         rec_tn, rec_ud, rec_src, u, rec_G, U_dbg, tile_max);
             __syncthreads();
         }
     } else {
-        interp_sh_tile<T, W, MODE>(xcd_remap(blockIdx.x, gridDim.x), g, tc, ow, nm, pass, c,
-                                   tile_start, rec_tn, rec_ud, rec_src, sh_start, sh_occ, sh_pos,
-                                   sh_u, cap, htab, hn, wtab, nw, rec_G, U_dbg, tile_max);
-    }
-}
-
-// Spreading on the compact velocity, one workgroup per tile: every marker
-// whose support reaches the tile (own + halo list) adds w G to the tile's
-// nodes in LDS (fixed point); the workgroup then updates its own entries.
-// MODE 0 (a pass): sh_u += c f.  MODE 1 (a call's only pass): sh_u += c f,
-// u = sh_u and f_tot += f at the tile's shell nodes.  MODE 2 (end of a call
-// of several passes; G = the amplitudes summed over the passes): u = sh_u and
-// f_tot += f.  tile_max (per tile, the largest |G| of the own markers) bounds
-// the amplitudes from the tile and its 26 neighbours; without it the
-// workgroup takes the largest |G| of the markers it adds.
-template <typename T, int W, int MODE>
-__device__ __forceinline__ void spread_sh_tile(
-    int tile, const GridC &g, const TileC &tc, T c, const int *__restrict__ tile_start,
-    const int *__restrict__ halo_start, const int *__restrict__ halo_list,
-    const typename V4<T>::type *__restrict__ rec_tn, const typename V4<T>::type *__restrict__ rec_G,
-    const float4 *__restrict__ tile_max, const int *__restrict__ sh_cmax,
-    const int *__restrict__ sh_start, const unsigned short *__restrict__ sh_pos,
-    T *__restrict__ sh_u, long long cap, T *__restrict__ u, T *__restrict__ f_tot)
-{
-    typedef typename V4<T>::type T4;
-    extern __shared__ __align__(16) unsigned char smem[];
-    unsigned char *acc = smem;
-    const int a0 = tile_start[tile], a1 = tile_start[tile + 1];
-    const int h0 = halo_start[tile], h1 = halo_start[tile + 1];
-    const int n_own = a1 - a0, n_tot = n_own + (h1 - h0);
-    if (n_tot == 0)
-        return;
-    const TileBox box(g, tc, tile);
-    const int V = tc.B[0] * tc.B[1] * tc.B[2];
-    T4 ptn = {}, pgv = {};
-    if ((int)threadIdx.x < n_tot) {
-        const int e = threadIdx.x;
-        const int j = e < n_own ? a0 + e : halo_list[h0 + e - n_own];
-        ptn = rec_tn[j];
-        pgv = rec_G[j];
-    }
-    // bound on the amplitudes reaching the tile: the largest |G| of the own
-    // markers of the tile and its 26 neighbours (first wave), or, without
-    // tile bounds, of the markers the workgroup adds
-    __shared__ float s_gm[3];
-    if (tile_max) {
-        if (threadIdx.x < IBMX_WAVE) {
-            float m[3] = {0.f, 0.f, 0.f};
-            if (threadIdx.x < 27) {
-                const int tt = neighbour_tile(g, tc, tile, threadIdx.x);
-                if (tt >= 0) {
-                    const float4 v = tile_max[tt];
-                    m[0] = v.x;
-                    m[1] = v.y;
-                    m[2] = v.z;
-                }
-            }
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int off = IBMX_WAVE / 2; off > 0; off >>= 1)
-                    m[a] = fmaxf(m[a], __shfl_xor(m[a], off, IBMX_WAVE));
-            if (threadIdx.x == 0)
-                for (int a = 0; a < 3; ++a)
-                    s_gm[a] = m[a];
-        }
-    } else {
-        float gm[3] = {0.f, 0.f, 0.f};
-        for (int e = threadIdx.x; e < n_tot; e += blockDim.x) {
-            const int j = e < n_own ? a0 + e : halo_list[h0 + e - n_own];
-            const T4 gv = rec_G[j];
-            gm[0] = fmaxf(gm[0], fabsf((float)gv.x));
-            gm[1] = fmaxf(gm[1], fabsf((float)gv.y));
-            gm[2] = fmaxf(gm[2], fabsf((float)gv.z));
-        }
-        for (int a = 0; a < 3; ++a) {
-            gm[a] = block_max<float>(gm[a]);
-            if (threadIdx.x == 0)
-                s_gm[a] = gm[a];
-        }
-    }
-    SpreadAcc<T>::zero(acc, V);
-    __syncthreads();
-    T scale[3], unscale[3];
-    const int cmax = sh_cmax[tile];
-    for (int a = 0; a < 3; ++a) {
-        scale[a] = SpreadAcc<T>::scale_for(s_gm[a], cmax);
-        unscale[a] = SpreadAcc<T>::unscale_for(scale[a]);
-    }
-    for (int e = threadIdx.x; e < n_tot; e += blockDim.x) {
-        const T4 tn = ptn, gv = pgv;
-        if (e + (int)blockDim.x < n_tot) {
-            const int en = e + blockDim.x;
-            const int jn = en < n_own ? a0 + en : halo_list[h0 + en - n_own];
-            ptn = rec_tn[jn];
-            pgv = rec_G[jn];
-        }
-        const T tt[3] = {tn.x, tn.y, tn.z};
-        const T Gs[3] = {gv.x * scale[0], gv.y * scale[1], gv.z * scale[2]};
-        int ix[3][W];
-        T w[3][W];
-        stencil<T, W>(g, V4<T>::to_bits(tn.w), tt, ix, w);
-#pragma unroll
-        for (int k = 0; k < W; ++k) {
-            const int lz = ix[2][k] - box.o[2];
-            if ((unsigned)lz >= (unsigned)box.e[2])
-                continue;
-#pragma unroll
-            for (int jj = 0; jj < W; ++jj) {
-                const int ly = ix[1][jj] - box.o[1];
-                if ((unsigned)ly >= (unsigned)box.e[1])
-                    continue;
-                const T wzy = w[2][k] * w[1][jj];
-                const int rowl = (lz * tc.B[1] + ly) * tc.B[0];
-#pragma unroll
-                for (int i = 0; i < W; ++i) {
-                    const int lx = ix[0][i] - box.o[0];
-                    if ((unsigned)lx >= (unsigned)box.e[0])
-                        continue;
-                    const T ww = wzy * w[0][i];
-                    SpreadAcc<T>::add(acc, V, rowl + lx, ww * Gs[0], ww * Gs[1], ww * Gs[2]);
-                }
-            }
-        }
-    }
-    __syncthreads();
-    // write-out over the tile's own entries
-    const int s0 = sh_start[tile], s1 = sh_start[tile + 1];
-    T *const c0 = sh_u, *const c1 = sh_u + cap, *const c2 = sh_u + 2 * cap;
-    const size_t N = (size_t)g.nodes;
-    for (int e0 = s0 + (int)threadIdx.x; e0 < s1; e0 += SH_UNR * blockDim.x) {
-        int li[SH_UNR];
-        T uo[SH_UNR][3];
-#pragma unroll
-        for (int q = 0; q < SH_UNR; ++q) {
-            const int e = e0 + q * (int)blockDim.x;
-            li[q] = e < s1 ? (int)sh_pos[e] : -1;
-            if (li[q] >= 0) {
-                uo[q][0] = c0[e];
-                uo[q][1] = c1[e];
-                uo[q][2] = c2[e];
-            }
-        }
-        if (MODE == 0) {
-#pragma unroll
-            for (int q = 0; q < SH_UNR; ++q) {
-                if (li[q] < 0)
-                    continue;
-                const int e = e0 + q * (int)blockDim.x;
-                T f[3];
-                if (SpreadAcc<T>::get(acc, V, li[q], unscale, f)) {
-                    c0[e] = uo[q][0] + c * f[0];
-                    c1[e] = uo[q][1] + c * f[1];
-                    c2[e] = uo[q][2] + c * f[2];
-                }
-            }
-            continue;
-        }
-        // last spreading of the call: the node's place in the grid, its
-        // spread value, f_tot there (all loads of the round in flight), then
-        // the stores
-        size_t gi[SH_UNR];
-        T f[SH_UNR][3], fo[SH_UNR][3];
-        bool nz[SH_UNR];
-#pragma unroll
-        for (int q = 0; q < SH_UNR; ++q) {
-            nz[q] = false;
-            if (li[q] < 0)
-                continue;
-            int lx, ly, lz;
-            local_xyz(tc, li[q], lx, ly, lz);
-            gi[q] = node_index(g, box, lx, ly, lz);
-            nz[q] = SpreadAcc<T>::get(acc, V, li[q], unscale, f[q]);
-            if (nz[q])
-#pragma unroll
-                for (int a = 0; a < 3; ++a)
-                    fo[q][a] = f_tot[(size_t)a * N + gi[q]];
-        }
-#pragma unroll
-        for (int q = 0; q < SH_UNR; ++q) {
-            if (li[q] < 0)
-                continue;
-            const int e = e0 + q * (int)blockDim.x;
-            T un[3] = {uo[q][0], uo[q][1], uo[q][2]};
-            if (MODE == 1 && nz[q]) {
-#pragma unroll
-                for (int a = 0; a < 3; ++a)
-                    un[a] = uo[q][a] + c * f[q][a];
-                c0[e] = un[0];
-                c1[e] = un[1];
-                c2[e] = un[2];
-            }
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-                u[(size_t)a * N + gi[q]] = un[a];
-            if (nz[q])
-#pragma unroll
-                for (int a = 0; a < 3; ++a)
-                    f_tot[(size_t)a * N + gi[q]] = fo[q][a] + f[q][a];
-        }
-    }
-}
-
-template <typename T, int W, int MODE, bool PERSIST>
-__global__ __launch_bounds__(256) void k_spread_sh(
-    GridC g, TileC tc, T c, const int *__restrict__ tile_start, const int *__restrict__ halo_start,
-    const int *__restrict__ halo_list, const typename V4<T>::type *__restrict__ rec_tn,
-    const typename V4<T>::type *__restrict__ rec_G, const float4 *__restrict__ tile_max,
-    const int *__restrict__ sh_cmax, const int *__restrict__ sh_start,
-    const unsigned short *__restrict__ sh_pos, T *__restrict__ sh_u, long long cap,
-    T *__restrict__ u, T *__restrict__ f_tot)
-{
-    if (PERSIST) {
-        for (int v = blockIdx.x; v < tc.ntiles; v += gridDim.x) {
-            spread_sh_tile<T, W, MODE>(xcd_remap(v, tc.ntiles), g, tc, c, tile_start, halo_start,
-                                       halo_list, rec_tn, rec_G, tile_max, sh_cmax, sh_start,
-                                       sh_pos, sh_u, cap, u, f_tot);
-            __syncthreads();
-        }
-    } else {
-        spread_sh_tile<T, W, MODE>(xcd_remap(blockIdx.x, gridDim.x), g, tc, c, tile_start,
-                                   halo_start, halo_list, rec_tn, rec_G, tile_max, sh_cmax,
-                                   sh_start, sh_pos, sh_u, cap, u, f_tot);
+        interp_tile<T, W, MODE, O32>(xcd_remap(blockIdx.x, gridDim.x), g, tc, nm, pass, c,
+                                     tile_start, rec_tn, rec_ud, rec_src, u, rec_G, U_dbg,
+                                     tile_max);
     }
 }
 
@@ -2132,25 +1546,10 @@ size_t interp_lds(const TileC &tc)
     return (size_t)3 * (tc.B[0] + W - 1) * (tc.B[1] + W - 1) * (tc.B[2] + W - 1) * sizeof(T);
 }
 
-// the compact interpolation: the region, then (16-byte aligned) nw
-// occupancy words of the halo table
-template <typename T, int W>
-size_t interp_sh_lds(const TileC &tc, int nw)
-{
-    return ((interp_lds<T, W>(tc) + 15) & ~(size_t)15) + sizeof(uint2) * (size_t)nw;
-}
-
 template <typename T>
 size_t spread_lds(const TileC &tc)
 {
     return (size_t)SpreadAcc<T>::BYTES * tc.B[0] * tc.B[1] * tc.B[2];
-}
-
-int occ_words(const TileC &tc) { return (tc.B[0] * tc.B[1] * tc.B[2] + 31) / 32; }
-
-size_t mark_lds(const TileC &tc)
-{
-    return (size_t)4 * tc.B[0] * tc.B[1] * tc.B[2] + (size_t)8 * occ_words(tc);
 }
 
 // Workgroups of a persistent pass launch: as many as the CUs hold at once
@@ -2165,31 +1564,56 @@ int persist_grid(const ibmx_plan p, size_t lds)
     return (int)(g < nt8 ? g : nt8);
 }
 
-template <typename T, int W, int MODE, typename... A>
-void launch_interp_sh(ibmx_plan p, size_t lds, hipStream_t s, A... args)
+// the tile kernels with 32-bit grid offsets when every component spans
+// less than 4 GB
+template <typename T>
+bool offsets32(ibmx_plan p)
+{
+    return (unsigned long long)p->g.nodes * sizeof(T) < (1ULL << 32);
+}
+
+template <typename T, int W, int MODE, bool O32, typename... A>
+void launch_interp_o(ibmx_plan p, size_t lds, hipStream_t s, A... args)
 {
     if (p->persist)
-        hipLaunchKernelGGL((k_interp_sh<T, W, MODE, true>), dim3(persist_grid(p, lds)),
+        hipLaunchKernelGGL((k_interp<T, W, MODE, O32, true>), dim3(persist_grid(p, lds)),
                            dim3(p->block), lds, s, args...);
     else
-        hipLaunchKernelGGL((k_interp_sh<T, W, MODE, false>), dim3(p->tc.ntiles), dim3(p->block),
-                           lds, s, args...);
+        hipLaunchKernelGGL((k_interp<T, W, MODE, O32, false>), dim3(p->tc.ntiles),
+                           dim3(p->block), lds, s, args...);
 }
 
 template <typename T, int W, int MODE, typename... A>
-void launch_spread_sh(ibmx_plan p, size_t lds, hipStream_t s, A... args)
+void launch_interp(ibmx_plan p, size_t lds, hipStream_t s, A... args)
+{
+    if (offsets32<T>(p))
+        launch_interp_o<T, W, MODE, true>(p, lds, s, args...);
+    else
+        launch_interp_o<T, W, MODE, false>(p, lds, s, args...);
+}
+
+template <typename T, int W, bool O32, typename... A>
+void launch_spread_o(ibmx_plan p, size_t lds, hipStream_t s, A... args)
 {
     if (p->persist)
-        hipLaunchKernelGGL((k_spread_sh<T, W, MODE, true>), dim3(persist_grid(p, lds)),
+        hipLaunchKernelGGL((k_spread<T, W, O32, true>), dim3(persist_grid(p, lds)),
                            dim3(p->block), lds, s, args...);
     else
-        hipLaunchKernelGGL((k_spread_sh<T, W, MODE, false>), dim3(p->tc.ntiles), dim3(p->block),
+        hipLaunchKernelGGL((k_spread<T, W, O32, false>), dim3(p->tc.ntiles), dim3(p->block),
                            lds, s, args...);
+}
+
+template <typename T, int W, typename... A>
+void launch_spread(ibmx_plan p, size_t lds, hipStream_t s, A... args)
+{
+    if (offsets32<T>(p))
+        launch_spread_o<T, W, true>(p, lds, s, args...);
+    else
+        launch_spread_o<T, W, false>(p, lds, s, args...);
 }
 
 // Marker geometry and binning of one call: tile counts, sorted records,
-// halo lists, the zeroed per-call counters, and the shell marking (per-tile
-// occupancy, shell counts and their offsets, largest support counts).
+// halo lists, and the zeroed per-call counters.
 template <typename T, int W>
 void bin_markers(ibmx_plan p, const double *xp, const double *up, const double *wp,
                  const uint8_t *mask)
@@ -2224,10 +1648,6 @@ void bin_markers(ibmx_plan p, const double *xp, const double *up, const double *
         ibmx_exclusive_scan(p->tile_count, p->tile_start, ntiles, p->scan_aux, s);
         ibmx_exclusive_scan(p->halo_count, p->halo_start, ntiles, p->scan_aux, s);
     }
-    hipLaunchKernelGGL((k_shell_mark<T, W>), dim3(ntiles), dim3(256), mark_lds(tc), s, p->g, tc,
-                       occ_words(tc), p->tile_start, p->halo_start, p->halo_list,
-                       (const T4 *)rec_tn, p->sh_count, p->sh_cmax, p->sh_occ);
-    ibmx_exclusive_scan(p->sh_count, p->sh_start, ntiles, p->scan_aux, s);
 }
 
 template <typename T, int W>
@@ -2240,17 +1660,12 @@ ibmx_status run_forcing(ibmx_plan p, T *u, T *f_tot, const double *xp, const dou
     const int nm = p->nm, np = p->np, n_iter = p->prm.n_iter;
     const double c = p->prm.two_alpha_dt;
     const TileC tc = p->tc;
-    const int ntiles = tc.ntiles, ow = occ_words(tc);
-    const long long cap = p->sh_cap;
-    const dim3 blk(p->block);
+    const int ntiles = tc.ntiles;
     T4 *rec_tn = (T4 *)p->rec_tn, *rec_ud = (T4 *)p->rec_ud;
     T4 *rec_Gm = (T4 *)p->rec_Gp, *rec_Gs = (T4 *)p->rec_G;
-    T *sh_u = (T *)p->sh_u;
+    // per-tile amplitude bounds: [0, ntiles) the pass, [ntiles, 2 ntiles)
+    // the sum over the passes so far
     float4 *tmax = p->tile_gmax;
-    const int2 *htab = p->halo_tab + (W == 3 ? 0 : p->halo_tab_n[0]);
-    const int hn = p->halo_tab_n[W == 3 ? 0 : 1];
-    const int *wtab = p->halo_words + (W == 3 ? 0 : p->halo_words_n[0]);
-    const int nw = p->halo_words_n[W == 3 ? 0 : 1];
     if (nm == 0 || np == 0) {
         ProfScope ps(p, IBMX_K_OTHER);
         ibmx_fill_f64(S_out, 0.0, 3LL * np, s);
@@ -2258,54 +1673,33 @@ ibmx_status run_forcing(ibmx_plan p, T *u, T *f_tot, const double *xp, const dou
         if (resid_out)
             ibmx_fill_f64(resid_out, 0.0, n_iter + 1, s);
         ibmx_fill_i32((int *)p->d_count, 0, 16LL * IBMX_RSLOTS, s);
-        ibmx_fill_i32(p->sh_start, 0, ntiles + 1, s);
         return ibmx_launch_check();
     }
     bin_markers<T, W>(p, xp, up, wp, mask);
-    {
-        ProfScope ps(p, IBMX_K_GEOMETRY);
-        hipLaunchKernelGGL((k_shell_gather<T>), dim3(ntiles), blk, 0, s, p->g, tc, ow, p->sh_start,
-                           (const uint2 *)p->sh_occ, (const T *)u, sh_u, cap, p->sh_pos);
-    }
-    const size_t lds_i = interp_lds<T, W>(tc);
-    const size_t lds_s = spread_lds<T>(tc);
+    const size_t lds_i = interp_lds<T, W>(tc), lds_s = spread_lds<T>(tc);
     for (int m = 0; m < n_iter; ++m) {
         T4 *Gm = rec_Gm + (size_t)m * nm;
         {
             ProfScope ps(p, IBMX_K_INTERP);
-            launch_interp_sh<T, W, 0>(p, lds_i, s, p->g, tc, ow, nm, m, c,
-                                      (const int *)p->tile_start, (const T4 *)rec_tn,
-                                      (const T4 *)rec_ud, (const int *)p->rec_src,
-                                      (const int *)p->sh_start, (const uint2 *)p->sh_occ,
-                                      (const unsigned short *)p->sh_pos, (const T *)sh_u, cap,
-                                      (const int2 *)htab, hn, (const int *)wtab, nw, Gm, U_dbg,
-                                      tmax);
+            launch_interp<T, W, 0>(p, lds_i, s, p->g, tc, nm, m, c, (const int *)p->tile_start,
+                                   (const T4 *)rec_tn, (const T4 *)rec_ud, (const int *)p->rec_src,
+                                   (const T *)u, Gm, U_dbg, tmax);
         }
+        // u += c f^m (and, with a single pass, f_tot += f^m)
         ProfScope ps(p, IBMX_K_SPREAD);
-        if (n_iter == 1)
-            launch_spread_sh<T, W, 1>(p, lds_s, s, p->g, tc, (T)c, (const int *)p->tile_start,
-                                      (const int *)p->halo_start, (const int *)p->halo_list,
-                                      (const T4 *)rec_tn, (const T4 *)Gm, (const float4 *)tmax,
-                                      (const int *)p->sh_cmax, (const int *)p->sh_start,
-                                      (const unsigned short *)p->sh_pos, sh_u, cap, u, f_tot);
-        else
-            launch_spread_sh<T, W, 0>(p, lds_s, s, p->g, tc, (T)c, (const int *)p->tile_start,
-                                      (const int *)p->halo_start, (const int *)p->halo_list,
-                                      (const T4 *)rec_tn, (const T4 *)Gm, (const float4 *)tmax,
-                                      (const int *)p->sh_cmax, (const int *)p->sh_start,
-                                      (const unsigned short *)p->sh_pos, sh_u, cap, u, f_tot);
+        launch_spread<T, W>(p, lds_s, s, p->g, tc, (T)c, 1, n_iter == 1 ? 1 : 0,
+                            n_iter == 1 ? 1 : 0, (const int *)p->tile_start,
+                            (const int *)p->halo_start, (const int *)p->halo_list,
+                            (const T4 *)rec_tn, (const T4 *)Gm, (const float4 *)tmax, u, f_tot,
+                            p->d_count);
     }
     if (resid_out) {
         // residual terms on the final velocity, into the w of the summed-
         // amplitude records (read by the particle sums before they write G)
         ProfScope ps(p, IBMX_K_OTHER);
-        launch_interp_sh<T, W, 2>(p, lds_i, s, p->g, tc, ow, nm, n_iter, c,
-                                  (const int *)p->tile_start, (const T4 *)rec_tn,
-                                  (const T4 *)rec_ud, (const int *)p->rec_src,
-                                  (const int *)p->sh_start, (const uint2 *)p->sh_occ,
-                                  (const unsigned short *)p->sh_pos, (const T *)sh_u, cap,
-                                  (const int2 *)htab, hn, (const int *)wtab, nw, rec_Gs,
-                                  (T *)nullptr, (float4 *)nullptr);
+        launch_interp<T, W, 2>(p, lds_i, s, p->g, tc, nm, n_iter, c, (const int *)p->tile_start,
+                               (const T4 *)rec_tn, (const T4 *)rec_ud, (const int *)p->rec_src,
+                               (const T *)u, rec_Gs, (T *)nullptr, (float4 *)nullptr);
     }
     {
         ProfScope ps(p, IBMX_K_OTHER);
@@ -2318,35 +1712,14 @@ ibmx_status run_forcing(ibmx_plan p, T *u, T *f_tot, const double *xp, const dou
                                (const double *)p->rpart, np, resid_out);
     }
     if (n_iter >= 2) {
-        // f_tot += spread of the amplitudes summed over the passes; u written back
+        // f_tot += spread of the amplitudes summed over the passes
         ProfScope ps(p, IBMX_K_FTOT);
-        launch_spread_sh<T, W, 2>(p, lds_s, s, p->g, tc, (T)c, (const int *)p->tile_start,
-                                  (const int *)p->halo_start, (const int *)p->halo_list,
-                                  (const T4 *)rec_tn, (const T4 *)rec_Gs,
-                                  (const float4 *)(tmax + ntiles),
-                                  (const int *)p->sh_cmax, (const int *)p->sh_start,
-                                  (const unsigned short *)p->sh_pos, sh_u, cap, u, f_tot);
+        launch_spread<T, W>(p, lds_s, s, p->g, tc, (T)c, 0, 1, 1, (const int *)p->tile_start,
+                            (const int *)p->halo_start, (const int *)p->halo_list,
+                            (const T4 *)rec_tn, (const T4 *)rec_Gs,
+                            (const float4 *)(tmax + ntiles), u, f_tot, p->d_count);
     }
     return ibmx_launch_check();
-}
-
-// k_spread (the adjoint's dense spreading) with 32-bit grid offsets when
-// every component spans less than 4 GB
-template <typename T>
-bool offsets32(ibmx_plan p)
-{
-    return (unsigned long long)p->g.nodes * sizeof(T) < (1ULL << 32);
-}
-
-template <typename T, int W, typename... A>
-void spread_launch(ibmx_plan p, size_t lds, hipStream_t s, A... args)
-{
-    if (offsets32<T>(p))
-        hipLaunchKernelGGL((k_spread<T, W, true>), dim3(p->tc.ntiles), dim3(p->block), lds, s,
-                           args...);
-    else
-        hipLaunchKernelGGL((k_spread<T, W, false>), dim3(p->tc.ntiles), dim3(p->block), lds, s,
-                           args...);
 }
 
 template <typename T, int W>
@@ -2393,10 +1766,11 @@ ibmx_status run_backward(ibmx_plan p, const T *u0, const double *xp, const doubl
                                c, p->tile_start, (const T4 *)rec_tn, (const T4 *)rec_ud,
                                (const T *)us, GJm);
             if (m < n_iter - 1)
-                spread_launch<T, W>(p, lds_s, s, p->g, tc, (T)c, 1, 0, (const int *)p->sh_cmax,
-                                    p->tile_start, p->halo_start, p->halo_list,
-                                    (const T4 *)rec_tn, (const T4 *)GJm, (const float4 *)nullptr,
-                                    us, (T *)nullptr);
+                launch_spread<T, W>(p, lds_s, s, p->g, tc, (T)c, 1, 0, 0,
+                                    (const int *)p->tile_start, (const int *)p->halo_start,
+                                    (const int *)p->halo_list, (const T4 *)rec_tn,
+                                    (const T4 *)GJm, (const float4 *)nullptr, us, (T *)nullptr,
+                                    p->d_count);
         }
         for (int m = n_iter - 1; m >= 0; --m) {
             const T4 *GJm = GJ + 3 * (size_t)nm * m;
@@ -2410,9 +1784,10 @@ ibmx_status run_backward(ibmx_plan p, const T *u0, const double *xp, const doubl
                                    tc, nm, np, c, p->tile_start, (const T4 *)rec_tn,
                                    p->rec_src, p->body, p->d_pid, p->dV, g_S, g_T,
                                    (const T *)gu0, g_f, GJm, rec_Ub, accA, accB);
-            spread_launch<T, W>(p, lds_s, s, p->g, tc, T(1), 1, 0, (const int *)p->sh_cmax,
-                                p->tile_start, p->halo_start, p->halo_list, (const T4 *)rec_tn,
-                                (const T4 *)rec_Ub, (const float4 *)nullptr, gu0, (T *)nullptr);
+            launch_spread<T, W>(p, lds_s, s, p->g, tc, T(1), 1, 0, 0, (const int *)p->tile_start,
+                                (const int *)p->halo_start, (const int *)p->halo_list,
+                                (const T4 *)rec_tn, (const T4 *)rec_Ub, (const float4 *)nullptr,
+                                gu0, (T *)nullptr, p->d_count);
         }
         if (np > 0)
             hipLaunchKernelGGL(k_particle_grad, dim3(nblocks(np, 4)), dim3(256), 0, s, np, nm,
@@ -2423,30 +1798,32 @@ ibmx_status run_backward(ibmx_plan p, const T *u0, const double *xp, const doubl
 }
 
 template <typename T, int W>
-hipError_t allow_lds_w(int bytes_interp, int bytes_spread, int bytes_mark)
+hipError_t allow_lds_w(int bytes_interp, int bytes_spread)
 {
     hipError_t e;
-    const void *spreads[] = {
-        (const void *)k_spread<T, W, true>,         (const void *)k_spread<T, W, false>,
-        (const void *)k_spread_sh<T, W, 0, false>,  (const void *)k_spread_sh<T, W, 1, false>,
-        (const void *)k_spread_sh<T, W, 2, false>,  (const void *)k_spread_sh<T, W, 0, true>,
-        (const void *)k_spread_sh<T, W, 1, true>,   (const void *)k_spread_sh<T, W, 2, true>};
+    const void *spreads[] = {(const void *)k_spread<T, W, true, false>,
+                             (const void *)k_spread<T, W, false, false>,
+                             (const void *)k_spread<T, W, true, true>,
+                             (const void *)k_spread<T, W, false, true>};
     for (const void *f : spreads)
         if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes_spread)) !=
             hipSuccess)
             return e;
-    const void *interps[] = {(const void *)k_interp_sh<T, W, 0, false>,
-                             (const void *)k_interp_sh<T, W, 2, false>,
-                             (const void *)k_interp_sh<T, W, 0, true>,
-                             (const void *)k_interp_sh<T, W, 2, true>,
+    const void *interps[] = {(const void *)k_interp<T, W, 0, true, false>,
+                             (const void *)k_interp<T, W, 2, true, false>,
+                             (const void *)k_interp<T, W, 0, false, false>,
+                             (const void *)k_interp<T, W, 2, false, false>,
+                             (const void *)k_interp<T, W, 0, true, true>,
+                             (const void *)k_interp<T, W, 2, true, true>,
+                             (const void *)k_interp<T, W, 0, false, true>,
+                             (const void *)k_interp<T, W, 2, false, true>,
                              (const void *)k_interp_jac<T, W>,
                              (const void *)k_interp_adj<T, W, 0>, (const void *)k_interp_adj<T, W, 1>};
     for (const void *f : interps)
         if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes_interp)) !=
             hipSuccess)
             return e;
-    return hipFuncSetAttribute((const void *)k_shell_mark<T, W>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes_mark);
+    return hipSuccess;
 }
 
 }  // namespace
@@ -2470,25 +1847,15 @@ ibmx_status ibmx_spread_allow_lds(ibmx_plan p)
     const size_t l4 = p->prec == IBMX_F64 ? interp_lds<double, 4>(p->tc) : interp_lds<float, 4>(p->tc);
     if (ls > 160 * 1024 || l4 > 160 * 1024)
         return IBMX_EUNSUPPORTED;
-    const size_t lm = mark_lds(p->tc);
-    if (lm > 160 * 1024)
-        return IBMX_EUNSUPPORTED;
-    // the compact interpolation keeps the halo table's occupancy words after
-    // its region
-    const size_t lw = 16 + sizeof(uint2) * (size_t)(p->halo_words_n[0] > p->halo_words_n[1]
-                                                        ? p->halo_words_n[0]
-                                                        : p->halo_words_n[1]);
-    if (l4 + lw > 160 * 1024)
-        return IBMX_EUNSUPPORTED;
     hipError_t e;
     if (p->prec == IBMX_F64) {
-        e = allow_lds_w<double, 3>((int)(l3 + lw), (int)ls, (int)lm);
+        e = allow_lds_w<double, 3>((int)l3, (int)ls);
         if (e == hipSuccess)
-            e = allow_lds_w<double, 4>((int)(l4 + lw), (int)ls, (int)lm);
+            e = allow_lds_w<double, 4>((int)l4, (int)ls);
     } else {
-        e = allow_lds_w<float, 3>((int)(l3 + lw), (int)ls, (int)lm);
+        e = allow_lds_w<float, 3>((int)l3, (int)ls);
         if (e == hipSuccess)
-            e = allow_lds_w<float, 4>((int)(l4 + lw), (int)ls, (int)lm);
+            e = allow_lds_w<float, 4>((int)l4, (int)ls);
     }
     return e == hipSuccess ? IBMX_OK : IBMX_EUNSUPPORTED;
 }

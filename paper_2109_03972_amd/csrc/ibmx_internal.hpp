@@ -30,8 +30,8 @@ struct ibmx_plan_s {
     int *d_moff;          // [np + 1]
     int *d_pid;           // [nm] marker -> particle
     int *d_err;           // [1] first deferred error (0 = none)
-    long long *d_count;   // [8][IBMX_RSLOTS] counters (active markers, halo
-                          // entries) as partial sums
+    long long *d_count;   // [8][IBMX_RSLOTS] counters (active markers, shell
+                          // nodes, halo entries) as partial sums
 
     // marker records, sorted by spreading tile (T4 = float4 / double4)
     void *rec_tn;         // T4[nm] {t_x, t_y, t_z, packed base node (bits)}
@@ -47,7 +47,6 @@ struct ibmx_plan_s {
     // tiles
     TileC tc;
     long long tile_cap;   // tiles the tile arrays are sized for
-    long long occ_cap;    // occupancy words sh_occ is sized for
     int *tile_count;      // [ntiles + 1]
     int *tile_start;      // [ntiles + 1]
     int *tile_cursor;     // [ntiles]
@@ -61,21 +60,7 @@ struct ibmx_plan_s {
     float4 *tile_gmax;    // [2][ntiles] largest |G| of the pass over each tile's
                           // own markers, and its sum over the passes so far
                           // (fixed-point spreading scales)
-    int2 *halo_tab;       // halo positions of a full tile away from walls, for
-                          // the three- then the four-point support
-    int halo_tab_n[2];
-    int *halo_words;      // the neighbours' occupancy words the table names
-    int halo_words_n[2];
-    // shell (nodes in the supports of the active markers), per tile
-    int *sh_count;        // [ntiles + 1] shell nodes of the tile
-    int *sh_start;        // [ntiles + 1] first compact entry of the tile
-    int *sh_cmax;         // [ntiles] largest number of supports covering a node
-    uint2 *sh_occ;        // [ntiles][ceil(V/32)] {occupancy bits, earlier set bits}
     double *rpart;        // [n_iter_cap + 1][np] residual partials per particle
-    // compact shell values, in tile order
-    void *sh_u;           // T[3][sh_cap]
-    unsigned short *sh_pos;  // [sh_cap] tile-local index of each entry
-    long long sh_cap;     // min(nodes, 64 nm): shell nodes a call can have
     long long halo_cap;
     int block;            // threads per workgroup of the forcing passes
     int persist;          // 1: passes as a persistent grid looping over tiles

@@ -3,8 +3,6 @@
 #include <stdlib.h>
 #include <string.h>
 
-#include <map>
-#include <vector>
 
 #include "ibmx_internal.hpp"
 
@@ -22,9 +20,7 @@ void free_plan(ibmx_plan p)
 {
     if (!p)
         return;
-    void *ptrs[] = {p->d_moff,      p->d_pid,       p->d_err,        p->sh_u,      p->d_count,
-                    p->sh_pos,      p->sh_count,    p->sh_start,     p->sh_cmax,   p->sh_occ,
-                    p->rpart,       p->halo_tab,    p->halo_words,
+    void *ptrs[] = {p->d_moff,      p->d_pid,       p->d_err,        p->rpart,     p->d_count,
                     p->rec_tn,      p->rec_ud,      p->rec_src,      p->rec_Gp,    p->rec_G,
                     p->m_key,       p->m_inv,       p->tile_count, p->tile_start,
                     p->tile_cursor, p->halo_count,  p->halo_start,   p->halo_cursor,
@@ -168,11 +164,6 @@ ibmx_status check_params(const ibmx_grid *g, const ibmx_params *prm)
     A(&p->rec_ud, Ts * 4 * nmz);
     A(&p->rec_G, Ts * 4 * nmz);
     A(&p->rec_Gp, Ts * 4 * nmz * (size_t)p->n_iter_cap);
-    // a call's shell has at most one node per grid node and W^3 <= 64 per
-    // active marker
-    p->sh_cap = nodes < 64LL * (long long)nmz ? nodes : 64LL * (long long)nmz;
-    A(&p->sh_u, Ts * 3 * (size_t)p->sh_cap);
-    A((void **)&p->sh_pos, sizeof(unsigned short) * (size_t)p->sh_cap);
     A((void **)&p->rpart, sizeof(double) * (size_t)(p->n_iter_cap + 1) * npz);
     A((void **)&p->rec_src, sizeof(int) * nmz);
     A((void **)&p->m_key, sizeof(int) * nmz);
@@ -278,22 +269,17 @@ ibmx_status ibmx_plan_alloc_tiles(ibmx_plan p, int tx, int ty, int tz)
     const size_t Ts = p->prec == IBMX_F64 ? sizeof(double) : sizeof(float);
     if ((size_t)3 * t[0] * t[1] * t[2] * Ts > 160 * 1024)
         return IBMX_EUNSUPPORTED;
-    const long long words = ntiles * (((long long)t[0] * t[1] * t[2] + 31) / 32);
-    if (!p->tile_count || ntiles > p->tile_cap || words > p->occ_cap) {
+    if (!p->tile_count || ntiles > p->tile_cap) {
         void *ptrs[] = {p->tile_count, p->tile_start, p->tile_cursor, p->halo_count,
-                        p->halo_start, p->halo_cursor, p->tile_gmax, p->sh_count,
-                        p->sh_start,   p->sh_cmax,     p->sh_occ};
+                        p->halo_start, p->halo_cursor, p->tile_gmax};
         for (void *q : ptrs)
             if (q)
                 (void)hipFree(q);
         p->tile_count = p->tile_start = p->tile_cursor = nullptr;
         p->halo_count = p->halo_start = p->halo_cursor = nullptr;
-        p->sh_count = p->sh_start = p->sh_cmax = nullptr;
-        p->sh_occ = nullptr;
         p->tile_gmax = nullptr;
         p->tc.ntiles = 0;
         p->tile_cap = 0;
-        p->occ_cap = 0;
         size_t b = sizeof(int) * (size_t)(ntiles + 1);
         if (hipMalloc((void **)&p->tile_count, b) != hipSuccess ||
             hipMalloc((void **)&p->tile_start, b) != hipSuccess ||
@@ -301,16 +287,9 @@ ibmx_status ibmx_plan_alloc_tiles(ibmx_plan p, int tx, int ty, int tz)
             hipMalloc((void **)&p->halo_count, b) != hipSuccess ||
             hipMalloc((void **)&p->halo_start, b) != hipSuccess ||
             hipMalloc((void **)&p->halo_cursor, b) != hipSuccess ||
-            hipMalloc((void **)&p->sh_count, b) != hipSuccess ||
-            hipMalloc((void **)&p->sh_start, b) != hipSuccess ||
-            hipMalloc((void **)&p->sh_cmax, b) != hipSuccess ||
-            hipMalloc((void **)&p->sh_occ, sizeof(uint2) * (size_t)words) != hipSuccess ||
             hipMalloc((void **)&p->tile_gmax, sizeof(float4) * 2 * (size_t)ntiles) != hipSuccess)
             return IBMX_ENOMEM;
         p->tile_cap = ntiles;
-        p->occ_cap = words;
-        if (hipMemset(p->sh_start, 0, b) != hipSuccess)
-            return IBMX_EDEVICE;
     }
     // every marker reaches at most 7 tiles besides its own
     long long cap = 7LL * (p->nm > 0 ? p->nm : 1);
@@ -321,72 +300,6 @@ ibmx_status ibmx_plan_alloc_tiles(ibmx_plan p, int tx, int ty, int tz)
         if (hipMalloc((void **)&p->halo_list, sizeof(int) * (size_t)cap) != hipSuccess)
             return IBMX_ENOMEM;
         p->halo_cap = cap;
-    }
-    // halo table of the region staging, for the three- and four-point
-    // supports: for a full tile away from walls, every region position outside
-    // the tile as {region index | neighbour << 16, slot | bit << 16}, slot
-    // naming the neighbour's occupancy word among the words the table needs
-    // (listed as neighbour | word << 5), bit the node's bit in that word
-    {
-        std::vector<int2> tab;
-        std::vector<int> words;
-        int counts[2] = {0, 0}, wcounts[2] = {0, 0};
-        for (int wi = 0; wi < 2; ++wi) {
-            const int W = 3 + wi;
-            const int R[3] = {t[0] + W - 1, t[1] + W - 1, t[2] + W - 1};
-            std::map<int, int> slot;
-            const size_t w0 = words.size();
-            for (int rz = 0; rz < R[2]; ++rz)
-                for (int ry = 0; ry < R[1]; ++ry)
-                    for (int rx = 0; rx < R[0]; ++rx) {
-                        const int r[3] = {rx, ry, rz};
-                        int d[3], l[3];
-                        bool inner = true;
-                        for (int a = 0; a < 3; ++a) {
-                            const int off = r[a] - 1;
-                            d[a] = off < 0 ? -1 : (off >= t[a] ? 1 : 0);
-                            l[a] = off - d[a] * t[a];
-                            inner = inner && d[a] == 0;
-                        }
-                        if (inner)
-                            continue;
-                        const int ri = (rz * R[1] + ry) * R[0] + rx;
-                        const int ni = (d[0] + 1) + 3 * (d[1] + 1) + 9 * (d[2] + 1);
-                        const int li = (l[2] * t[1] + l[1]) * t[0] + l[0];
-                        const int key = ni | ((li >> 5) << 5);
-                        auto it = slot.find(key);
-                        int sl;
-                        if (it == slot.end()) {
-                            sl = (int)(words.size() - w0);
-                            slot[key] = sl;
-                            words.push_back(key);
-                        } else {
-                            sl = it->second;
-                        }
-                        tab.push_back(make_int2(ri | (ni << 16), li));
-                        (void)sl;
-                        ++counts[wi];
-                    }
-            wcounts[wi] = (int)(words.size() - w0);
-        }
-        if (p->halo_tab)
-            (void)hipFree(p->halo_tab);
-        if (p->halo_words)
-            (void)hipFree(p->halo_words);
-        p->halo_tab = nullptr;
-        p->halo_words = nullptr;
-        if (hipMalloc((void **)&p->halo_tab, sizeof(int2) * tab.size()) != hipSuccess ||
-            hipMalloc((void **)&p->halo_words, sizeof(int) * words.size()) != hipSuccess)
-            return IBMX_ENOMEM;
-        if (hipMemcpy(p->halo_tab, tab.data(), sizeof(int2) * tab.size(), hipMemcpyHostToDevice) !=
-                hipSuccess ||
-            hipMemcpy(p->halo_words, words.data(), sizeof(int) * words.size(),
-                      hipMemcpyHostToDevice) != hipSuccess)
-            return IBMX_EDEVICE;
-        for (int wi = 0; wi < 2; ++wi) {
-            p->halo_tab_n[wi] = counts[wi];
-            p->halo_words_n[wi] = wcounts[wi];
-        }
     }
     for (int a = 0; a < 3; ++a) {
         p->tc.B[a] = t[a];
@@ -526,14 +439,8 @@ extern "C" ibmx_status ibmx_plan_stats(ibmx_plan p, ibmx_stats *out)
             tot[k] += c[k * IBMX_RSLOTS + i];
     free(c);
     p->stats.n_active = tot[0];
+    p->stats.shell_nodes = tot[1];
     p->stats.halo_entries = tot[2];
-    // shell nodes of the last call: the end of the compact entries
-    int shell = 0;
-    if (p->sh_start && p->tc.ntiles > 0 &&
-        hipMemcpy(&shell, p->sh_start + p->tc.ntiles, sizeof(int), hipMemcpyDeviceToHost) !=
-            hipSuccess)
-        return IBMX_EDEVICE;
-    p->stats.shell_nodes = shell;
     p->stats.block = p->block;
     p->stats.persistent = p->persist;
     for (int i = 0; i < p->ev_used; ++i) {

@@ -29,9 +29,10 @@ def test_pass_bytes(s):
     assert bench.pass_bytes(s, n, S) == n * rec + S * 4 * 3 * s
     # FP32 at S/N = 4.08: about 216 B per marker-update
     assert 215 < bench.pass_bytes(4, 1000, 4080) / 1000 < 217
-    # the build's own launches: T4 records (4s), 2-byte entry indices
-    assert bench.design_bytes("interp", s, n, S, H) == n * 3 * 4 * s + S * (3 * s + 2)
-    assert bench.design_bytes("spread", s, n, S, H) == (n + H) * 2 * 4 * s + H * 4 + S * (6 * s + 2)
+    # the tile kernels' own lower bounds: T4 records (4s) per marker entry,
+    # the halo list, three components per shell node read (and written)
+    assert bench.design_bytes("interp", s, n, S, H) == n * 3 * 4 * s + S * 3 * s
+    assert bench.design_bytes("spread", s, n, S, H) == (n + H) * 2 * 4 * s + H * 4 + S * 6 * s
     with pytest.raises(KeyError):
         bench.design_bytes("other", s, n, S, H)
 
