@@ -853,9 +853,9 @@ __device__ __forceinline__ int neighbour_tile(const GridC &g, const TileC &tc, i
 // receives: no node lies in more than n supports.  count_shell adds the
 // number of nodes that received a nonzero sum to a counter.
 // ---------------------------------------------------------------------------
-template <typename T, int W, bool O32>
+template <typename T, int W, bool O32, bool AU, bool AF>
 __device__ __forceinline__ void spread_tile(int tile, const GridC &g, const TileC &tc, T c,
-                                            int add_u, int add_f, int count_shell,
+                                            int count_shell,
                                             const int *__restrict__ tile_start,
                                             const int *__restrict__ halo_start,
                                             const int *__restrict__ halo_list,
@@ -920,6 +920,44 @@ __device__ __forceinline__ void spread_tile(int tile, const GridC &g, const Tile
                 s_gm[a] = gm[a];
         }
     }
+    // The grid values of every thread's first PF write-out rows are loaded
+    // now: they do not depend on the sums, and the accumulation hides their
+    // latency.  Later rows load as they go.
+    const long long N = g.nodes;
+    const int wave = threadIdx.x / IBMX_WAVE;
+    const TileWalk tw(tc, box.e[0]);
+    const int rstep = tw.nw * tw.rpi, rbase = wave * tw.rpi + tw.sub;
+    // component bases (node indices fit 32 bits: the grid has < 2^31 nodes)
+    T *const ub[3] = {u, u ? u + N : nullptr, u ? u + 2 * N : nullptr};
+    T *const fb[3] = {f_tot, f_tot ? f_tot + N : nullptr, f_tot ? f_tot + 2 * N : nullptr};
+    constexpr int PF = 4;
+    T pu[PF][3], pf[PF][3];
+    // row r of the tile: its LDS index (-1 beyond the tile) and grid index
+    auto row_at = [&](int r, int &li, unsigned &gi) {
+        int ly, lz;
+        tw.yz(r, tc.B[1], ly, lz);
+        const bool ok = tw.lane_ok && r < tw.rows && ly < box.e[1] && lz < box.e[2];
+        li = ok ? (lz * tc.B[1] + ly) * tc.B[0] + tw.lx : -1;
+        gi = ((unsigned)(box.o[2] + lz) * (unsigned)g.n[1] + (unsigned)(box.o[1] + ly)) *
+                 (unsigned)g.n[0] +
+             (unsigned)(box.o[0] + tw.lx);
+    };
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+        int li;
+        unsigned gi;
+        row_at(rbase + q * rstep, li, gi);
+        if (li >= 0) {
+            if (AF)
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    pf[q][a] = grid_at<T, O32>(fb[a], gi);
+            if (AU)
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    pu[q][a] = grid_at<T, O32>(ub[a], gi);
+        }
+    }
     SpreadAcc<T>::zero(acc, V);
     __syncthreads();
     T scale[3], unscale[3];
@@ -966,14 +1004,26 @@ __device__ __forceinline__ void spread_tile(int tile, const GridC &g, const Tile
         }
     }
     __syncthreads();
-    const long long N = g.nodes;
     int touched = 0;
-    const int wave = threadIdx.x / IBMX_WAVE;
-    const TileWalk tw(tc, box.e[0]);
-    // component bases (node indices fit 32 bits: the grid has < 2^31 nodes)
-    T *const ub[3] = {u, u ? u + N : nullptr, u ? u + 2 * N : nullptr};
-    T *const fb[3] = {f_tot, f_tot ? f_tot + N : nullptr, f_tot ? f_tot + 2 * N : nullptr};
-    for (int r0 = wave * tw.rpi + tw.sub; r0 < tw.rows; r0 += UNR * tw.nw * tw.rpi) {
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+        int li;
+        unsigned gi;
+        row_at(rbase + q * rstep, li, gi);
+        T fv[3];
+        if (li < 0 || !SpreadAcc<T>::get(acc, V, li, unscale, fv))
+            continue;
+        ++touched;
+        if (AF)
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                grid_at<T, O32>(fb[a], gi) = pf[q][a] + fv[a];
+        if (AU)
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                grid_at<T, O32>(ub[a], gi) = pu[q][a] + c * fv[a];
+    }
+    for (int r0 = rbase + PF * rstep; r0 < tw.rows; r0 += UNR * rstep) {
         unsigned gi[UNR];
         bool act[UNR];
         T fv[UNR][3], fo[UNR][3], uo[UNR][3];
@@ -990,11 +1040,11 @@ __device__ __forceinline__ void spread_tile(int tile, const GridC &g, const Tile
             if (act[q])
                 act[q] = SpreadAcc<T>::get(acc, V, li, unscale, fv[q]);
             if (act[q]) {
-                if (add_f)
+                if (AF)
 #pragma unroll
                     for (int a = 0; a < 3; ++a)
                         fo[q][a] = grid_at<T, O32>(fb[a], gi[q]);
-                if (add_u)
+                if (AU)
 #pragma unroll
                     for (int a = 0; a < 3; ++a)
                         uo[q][a] = grid_at<T, O32>(ub[a], gi[q]);
@@ -1005,11 +1055,11 @@ __device__ __forceinline__ void spread_tile(int tile, const GridC &g, const Tile
             if (!act[q])
                 continue;
             ++touched;
-            if (add_f)
+            if (AF)
 #pragma unroll
                 for (int a = 0; a < 3; ++a)
                     grid_at<T, O32>(fb[a], gi[q]) = fo[q][a] + fv[q][a];
-            if (add_u)
+            if (AU)
 #pragma unroll
                 for (int a = 0; a < 3; ++a)
                     grid_at<T, O32>(ub[a], gi[q]) = uo[q][a] + c * fv[q][a];
@@ -1022,9 +1072,8 @@ __device__ __forceinline__ void spread_tile(int tile, const GridC &g, const Tile
 // One workgroup per tile (PERSIST false), or a fixed grid of workgroups (a
 // multiple of the 8 XCDs) each taking tiles blockIdx.x, blockIdx.x +
 // gridDim.x, ... until the tiles run out (PERSIST true).
-template <typename T, int W, bool O32, bool PERSIST>
-__global__ __launch_bounds__(256) void k_spread(GridC g, TileC tc, T c, int add_u, int add_f,
-                                                int count_shell,
+template <typename T, int W, bool O32, bool PERSIST, bool AU, bool AF>
+__global__ __launch_bounds__(256) void k_spread(GridC g, TileC tc, T c, int count_shell,
                                                 const int *__restrict__ tile_start,
                                                 const int *__restrict__ halo_start,
                                                 const int *__restrict__ halo_list,
@@ -1036,15 +1085,15 @@ __global__ __launch_bounds__(256) void k_spread(GridC g, TileC tc, T c, int add_
 {
     if (PERSIST) {
         for (int v = blockIdx.x; v < tc.ntiles; v += gridDim.x) {
-            spread_tile<T, W, O32>(xcd_remap(v, tc.ntiles), g, tc, c, add_u, add_f, count_shell,
-                                   tile_start, halo_start, halo_list, rec_tn, rec_G, tile_max, u,
-                                   f_tot, count);
+            spread_tile<T, W, O32, AU, AF>(xcd_remap(v, tc.ntiles), g, tc, c, count_shell,
+                                           tile_start, halo_start, halo_list, rec_tn, rec_G,
+                                           tile_max, u, f_tot, count);
             __syncthreads();
         }
     } else {
-        spread_tile<T, W, O32>(xcd_remap(blockIdx.x, gridDim.x), g, tc, c, add_u, add_f,
-                               count_shell, tile_start, halo_start, halo_list, rec_tn, rec_G,
-                               tile_max, u, f_tot, count);
+        spread_tile<T, W, O32, AU, AF>(xcd_remap(blockIdx.x, gridDim.x), g, tc, c, count_shell,
+                                       tile_start, halo_start, halo_list, rec_tn, rec_G, tile_max,
+                                       u, f_tot, count);
     }
 }
 
@@ -1592,15 +1641,28 @@ void launch_interp(ibmx_plan p, size_t lds, hipStream_t s, A... args)
         launch_interp_o<T, W, MODE, false>(p, lds, s, args...);
 }
 
-template <typename T, int W, bool O32, typename... A>
-void launch_spread_o(ibmx_plan p, size_t lds, hipStream_t s, A... args)
+template <typename T, int W, bool O32, bool AU, bool AF, typename... A>
+void launch_spread_k(ibmx_plan p, size_t lds, hipStream_t s, A... args)
 {
     if (p->persist)
-        hipLaunchKernelGGL((k_spread<T, W, O32, true>), dim3(persist_grid(p, lds)),
+        hipLaunchKernelGGL((k_spread<T, W, O32, true, AU, AF>), dim3(persist_grid(p, lds)),
                            dim3(p->block), lds, s, args...);
     else
-        hipLaunchKernelGGL((k_spread<T, W, O32, false>), dim3(p->tc.ntiles), dim3(p->block),
-                           lds, s, args...);
+        hipLaunchKernelGGL((k_spread<T, W, O32, false, AU, AF>), dim3(p->tc.ntiles),
+                           dim3(p->block), lds, s, args...);
+}
+
+// spreading launch: u += c f (add_u) and / or f_tot += f (add_f)
+template <typename T, int W, bool O32, typename... A>
+void launch_spread_o(ibmx_plan p, size_t lds, hipStream_t s, GridC g, TileC tc, T c, int add_u,
+                     int add_f, A... args)
+{
+    if (add_u && add_f)
+        launch_spread_k<T, W, O32, true, true>(p, lds, s, g, tc, c, args...);
+    else if (add_u)
+        launch_spread_k<T, W, O32, true, false>(p, lds, s, g, tc, c, args...);
+    else
+        launch_spread_k<T, W, O32, false, true>(p, lds, s, g, tc, c, args...);
 }
 
 template <typename T, int W, typename... A>
@@ -1801,10 +1863,19 @@ template <typename T, int W>
 hipError_t allow_lds_w(int bytes_interp, int bytes_spread)
 {
     hipError_t e;
-    const void *spreads[] = {(const void *)k_spread<T, W, true, false>,
-                             (const void *)k_spread<T, W, false, false>,
-                             (const void *)k_spread<T, W, true, true>,
-                             (const void *)k_spread<T, W, false, true>};
+    const void *spreads[] = {
+        (const void *)k_spread<T, W, true, false, true, false>,
+        (const void *)k_spread<T, W, false, false, true, false>,
+        (const void *)k_spread<T, W, true, true, true, false>,
+        (const void *)k_spread<T, W, false, true, true, false>,
+        (const void *)k_spread<T, W, true, false, false, true>,
+        (const void *)k_spread<T, W, false, false, false, true>,
+        (const void *)k_spread<T, W, true, true, false, true>,
+        (const void *)k_spread<T, W, false, true, false, true>,
+        (const void *)k_spread<T, W, true, false, true, true>,
+        (const void *)k_spread<T, W, false, false, true, true>,
+        (const void *)k_spread<T, W, true, true, true, true>,
+        (const void *)k_spread<T, W, false, true, true, true>};
     for (const void *f : spreads)
         if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes_spread)) !=
             hipSuccess)
