@@ -79,7 +79,8 @@ def _dense_helmholtz(shape, h, beta, periodic):
 
 
 @pytest.mark.parametrize("periodic,shape", [((1, 1, 1), (4, 4, 8)), ((1, 1, 0), (5, 4, 4)),
-                                            ((1, 1, 0), (1, 4, 8))])
+                                            ((1, 1, 0), (1, 4, 8)), ((1, 1, 0), (13, 16, 8)),
+                                            ((1, 1, 1), (8, 16, 16))])
 def test_helmholtz_matches_dense_solve(periodic, shape):
     rng = np.random.default_rng(9)
     rhs = rng.normal(size=shape)

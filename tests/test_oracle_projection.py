@@ -55,7 +55,8 @@ def _dense_laplacian(shape, h, periodic):
 
 
 @pytest.mark.parametrize("periodic,shape", [((1, 1, 1), (4, 4, 8)), ((1, 1, 0), (5, 4, 4)),
-                                            ((1, 1, 0), (3, 8, 2))])
+                                            ((1, 1, 0), (3, 8, 2)), ((1, 1, 0), (13, 16, 8)),
+                                            ((1, 1, 1), (8, 16, 16))])
 def test_poisson_matches_dense_solve(periodic, shape):
     rng = np.random.default_rng(3)
     rhs = rng.normal(size=shape)
