@@ -1,9 +1,10 @@
 """Edge cases of the forcing loop on the GPU against the FP64 oracle:
 markers placed exactly on the ties of the delta's support (the marker
-coordinate an integer number of h away from a node's cell face, reading c-26)
+coordinate an integer number of h away from a node's cell face, where the
+last support node has weight exactly zero and counts as outside the support)
 at tile faces, at periodic seams and exactly 1.0h (three-point delta) or
 1.5h (four-point delta) from a wall, where the last support node has zero
-weight and may lie beyond the wall (reading c-11).  The grids have walls in x
+weight and may lie beyond the wall (such a marker is accepted).  The grids have walls in x
 with n_x not a multiple of four, so the velocity is staged element by element
 next to the x walls, in the forward and the adjoint kernels."""
 import numpy as np

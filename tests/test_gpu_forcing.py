@@ -123,7 +123,7 @@ def test_no_particles(precision):
 
 @pytest.mark.parametrize("name", ["suspension_128", "small"])
 def test_f32_arithmetic_and_end_to_end_errors(name):
-    """FP32 forward errors of every output measured two ways (reading c-25):
+    """FP32 forward errors of every output measured two ways:
     (i) against the oracle on the FP32-rounded velocity the kernels start
     from (the arithmetic error of the FP32 path) and (ii) against the oracle
     on the FP64 inputs (end to end, including the rounding of u0).  Both

@@ -306,7 +306,8 @@ def _wall_slide(oracle_lib, v0, steps, dt_int, nu_poi, overlap=0.05, mass=1.0, R
 
 @pytest.mark.parametrize("nu_poi", [0.0, 0.3, 0.45])
 def test_tangential_stick_is_damped_oscillator(oracle_lib, nu_poi):
-    """Stick branch of the tangential model (Sec. 2.2.8; readings c-20, c-21):
+    """Stick branch of the tangential model (Sec. 2.2.8, with k_t = kappa k_n and
+    the damping of the normal law carried over, as the paper leaves them open):
     while |F_t| stays below mu_s |F_n| the tangential force is a linear
     spring-dashpot on the integrated slip, so the tangential motion obeys
     m zeta'' + d_t zeta' + k_t zeta = 0 with k_t = kappa k_n, kappa =
@@ -333,7 +334,8 @@ def test_tangential_stick_is_damped_oscillator(oracle_lib, nu_poi):
 
 
 def test_tangential_slip_caps_and_resets_spring(oracle_lib):
-    """Slip branch of the tangential model (Sec. 2.2.8; reading c-22): under a
+    """Slip branch of the tangential model (Sec. 2.2.8, with the spring reset on
+    slipping): under a
     constant normal force and a constant tangential slip speed the tangential
     force is mu_k |F_n| at every evaluation, opposed to the slip, and the
     spring is reset to -(F_t + d_t g_t)/k_t each time, so it does not grow
