@@ -874,7 +874,10 @@ __device__ __forceinline__ void spread_tile(int tile, const GridC &g, const Tile
     if (n_tot == 0)
         return;
     const TileBox box(g, tc, tile);
-    const int V = tc.B[0] * tc.B[1] * tc.B[2];
+    // accumulator rows padded to B[0] + 1 nodes, so that nodes of one x
+    // position in different rows fall in different LDS banks
+    const int S0 = tc.B[0] + 1;
+    const int V = S0 * tc.B[1] * tc.B[2];
     // first record of this thread, in flight during the set-up
     T4 ptn = {}, pgv = {};
     if ((int)threadIdx.x < n_tot) {
@@ -937,7 +940,7 @@ __device__ __forceinline__ void spread_tile(int tile, const GridC &g, const Tile
         int ly, lz;
         tw.yz(r, tc.B[1], ly, lz);
         const bool ok = tw.lane_ok && r < tw.rows && ly < box.e[1] && lz < box.e[2];
-        li = ok ? (lz * tc.B[1] + ly) * tc.B[0] + tw.lx : -1;
+        li = ok ? (lz * tc.B[1] + ly) * S0 + tw.lx : -1;
         gi = ((unsigned)(box.o[2] + lz) * (unsigned)g.n[1] + (unsigned)(box.o[1] + ly)) *
                  (unsigned)g.n[0] +
              (unsigned)(box.o[0] + tw.lx);
@@ -989,7 +992,7 @@ __device__ __forceinline__ void spread_tile(int tile, const GridC &g, const Tile
                 if ((unsigned)ly >= (unsigned)box.e[1])
                     continue;
                 const T wzy = w[2][k] * w[1][jj];
-                const int rowl = (lz * tc.B[1] + ly) * tc.B[0];
+                const int rowl = (lz * tc.B[1] + ly) * S0;
 #pragma unroll
                 for (int i = 0; i < W; ++i) {
                     const int lx = ix[0][i] - box.o[0];
@@ -1032,7 +1035,7 @@ __device__ __forceinline__ void spread_tile(int tile, const GridC &g, const Tile
             const int r = r0 + q * tw.nw * tw.rpi;
             int ly, lz;
             tw.yz(r, tc.B[1], ly, lz);
-            const int li = (lz * tc.B[1] + ly) * tc.B[0] + tw.lx;
+            const int li = (lz * tc.B[1] + ly) * S0 + tw.lx;
             act[q] = tw.lane_ok && r < tw.rows && ly < box.e[1] && lz < box.e[2];
             gi[q] = ((unsigned)(box.o[2] + lz) * (unsigned)g.n[1] + (unsigned)(box.o[1] + ly)) *
                         (unsigned)g.n[0] +
@@ -1598,7 +1601,7 @@ size_t interp_lds(const TileC &tc)
 template <typename T>
 size_t spread_lds(const TileC &tc)
 {
-    return (size_t)SpreadAcc<T>::BYTES * tc.B[0] * tc.B[1] * tc.B[2];
+    return (size_t)SpreadAcc<T>::BYTES * (tc.B[0] + 1) * tc.B[1] * tc.B[2];
 }
 
 // Workgroups of a persistent pass launch: as many as the CUs hold at once
