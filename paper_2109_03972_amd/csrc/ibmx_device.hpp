@@ -75,13 +75,9 @@ __device__ __forceinline__ V block_sum(V v)
     return r;
 }
 
-// Add a block's partial to one of IBMX_RSLOTS slots of a counter (thread 0),
-// so that workgroups do not all hit one address.
-__device__ __forceinline__ void slot_add(double *slots, double v)
-{
-    if (threadIdx.x == 0 && v != 0.0)
-        atomicAdd(&slots[blockIdx.x & (IBMX_RSLOTS - 1)], v);
-}
+// Add a block's partial to one of IBMX_RSLOTS slots of an integer counter
+// (thread 0), so that workgroups do not all hit one address; integer sums do
+// not depend on the order of the adds.
 __device__ __forceinline__ void slot_add(long long *slots, long long v)
 {
     if (threadIdx.x == 0 && v != 0)

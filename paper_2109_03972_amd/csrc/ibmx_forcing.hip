@@ -19,6 +19,8 @@
 //   sums (once)     per particle, in marker order, the FP64 sums over markers
 //                   and passes of G and o x G (S_p, T_p), the residual terms,
 //                   and every marker's pass-summed amplitude.
+//   residual (once) an interpolation of the final velocity gives the residual
+//                   terms of u^n, before the sums.
 //   f_tot (once)    spreading is linear and the markers do not move during the
 //                   call, so sum_m f^m is the spread of the summed amplitudes:
 //                   one last tile pass adds it to f_tot.
