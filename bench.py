@@ -91,13 +91,22 @@ KERNEL_SOURCES = ("paper_2109_03972_amd/csrc/ibmx_forcing.hip",
                   "paper_2109_03972_amd/csrc/ibmx_delta.hpp")
 
 
+def _strip_comments(src: str) -> str:
+    """C/C++ source without its comments, indentation and blank lines (such
+    edits do not change the kernels)."""
+    import re
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    return "\n".join(line.strip() for line in src.splitlines() if line.strip())
+
+
 def kernel_sources_hash() -> str:
     import hashlib
     from paper_2109_03972_amd import build_lib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f)) as fh:
+            h.update(_strip_comments(fh.read()).encode())
     # the flags, without include paths (they name where the tree sits)
     h.update(" ".join(f for f in build_lib.HIPCC_FLAGS if not f.startswith("-I")).encode())
     return h.hexdigest()

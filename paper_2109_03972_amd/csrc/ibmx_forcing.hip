@@ -34,6 +34,10 @@ namespace {
 
 constexpr int NXCD = 8;              // MI355X: 8 XCDs, workgroups dealt round-robin
 
+// Four-value records.  The w of a {fractions, packed node} record carries
+// the node's bits: it is only ever stored, loaded, copied between registers
+// and bit-cast back (from_bits / to_bits), never an operand of floating-point
+// arithmetic, so no flush of denormal values can touch it.
 template <typename T>
 struct V4;
 template <>

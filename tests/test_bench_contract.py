@@ -46,3 +46,26 @@ def test_fluid_bytes_per_call():
     assert bench.fluid_bytes("helmholtz", 4, N) == 3 * ((2 * 4 + 8) + spec_walls + (8 + 4)) * N
     assert bench.fluid_bytes("helmholtz", 4, N, walls_z=False) == 3 * ((2 * 4 + 8) + spec_per + (8 + 4)) * N
     assert bench.fluid_bytes("project", 8, N) == ((6 * 8 + 8) + 16 + spec_walls + 16 + (8 + 14 * 8)) * N
+
+
+def test_kernel_hash_ignores_comments(tmp_path, monkeypatch):
+    # the counter summary stays valid across comment edits, not code edits
+    src = "int f(int a) { // sum\n  /* twice */ return a + a;\n}\n"
+    assert bench._strip_comments(src) == bench._strip_comments(
+        "// header\nint f(int a) {\n  return a + a;  // same code\n}\n")
+    assert bench._strip_comments(src) != bench._strip_comments(src.replace("a + a", "a * 2"))
+    files = []
+    for i, f in enumerate(bench.KERNEL_SOURCES):
+        p = tmp_path / f"k{i}.hip"
+        with open(bench.os.path.join(bench.ROOT, f)) as fh:
+            p.write_text(fh.read())
+        files.append(str(p))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "KERNEL_SOURCES", tuple(files))
+    h0 = bench.kernel_sources_hash()
+    with open(files[0], "a") as fh:
+        fh.write("\n// a new comment\n")
+    assert bench.kernel_sources_hash() == h0
+    with open(files[0], "a") as fh:
+        fh.write("\nstatic int unused_code = 0;\n")
+    assert bench.kernel_sources_hash() != h0
