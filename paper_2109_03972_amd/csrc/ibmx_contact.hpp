@@ -605,8 +605,10 @@ inline void contact_adjacency(ibmx_plan p, const ContactLists &C, hipStream_t s)
     const int np = p->np;
     const long long nmax = (long long)C.pair_cap + C.wall_cap;
     const int g = contact_blocks(nmax, 256) < 4096 ? contact_blocks(nmax, 256) : 4096;
-    ibmx_fill_i32(p->c_deg, 0, np + 1, s);
-    ibmx_fill_i32(p->c_cur, 0, np, s);
+    ZeroList z = {};
+    z.add(p->c_deg, np + 1);
+    z.add(p->c_cur, np);
+    ibmx_zero_i32_multi(z, s);
     const Periodic per{{p->grid.periodic[0], p->grid.periodic[1], p->grid.periodic[2]}};
     hipLaunchKernelGGL(k_adj_count, dim3(g), dim3(256), 0, s, C, np, per, p->c_deg, p->d_err);
     ibmx_exclusive_scan(p->c_deg, p->c_off, np, p->scan_aux, s);

@@ -1585,8 +1585,8 @@ __global__ void k_zero(T *__restrict__ dst, long long n)
 
 // resid[pass] = sqrt of the sum of the pass's per-particle partials, added
 // in a fixed order (one block per pass)
-__global__ __launch_bounds__(256) void k_finish_resid(const double *__restrict__ rpart, int np,
-                                                      double *__restrict__ resid)
+__global__ __launch_bounds__(1024) void k_finish_resid(const double *__restrict__ rpart, int np,
+                                                       double *__restrict__ resid)
 {
     double v = 0.0;
     for (int i = threadIdx.x; i < np; i += blockDim.x)
@@ -1697,11 +1697,13 @@ void bin_markers(ibmx_plan p, const double *xp, const double *up, const double *
     T4 *rec_tn = (T4 *)p->rec_tn, *rec_ud = (T4 *)p->rec_ud;
     {
         ProfScope ps(p, IBMX_K_OTHER);
-        ibmx_fill_i32((int *)p->d_count, 0, 16LL * IBMX_RSLOTS, s);
-        ibmx_fill_i32(p->tile_count, 0, ntiles + 1, s);
-        ibmx_fill_i32(p->tile_cursor, 0, ntiles + 1, s);
-        ibmx_fill_i32(p->halo_count, 0, ntiles + 1, s);
-        ibmx_fill_i32(p->halo_cursor, 0, ntiles + 1, s);
+        ZeroList z = {};
+        z.add((int *)p->d_count, 16LL * IBMX_RSLOTS);
+        z.add(p->tile_count, ntiles + 1);
+        z.add(p->tile_cursor, ntiles + 1);
+        z.add(p->halo_count, ntiles + 1);
+        z.add(p->halo_cursor, ntiles + 1);
+        ibmx_zero_i32_multi(z, s);
     }
     ProfScope ps(p, IBMX_K_GEOMETRY);
     if (np > 0 && nm > 0) {
@@ -1779,7 +1781,7 @@ ibmx_status run_forcing(ibmx_plan p, T *u, T *f_tot, const double *xp, const dou
                            (const int *)p->d_moff, p->body, (const int *)p->m_inv,
                            (const T4 *)rec_Gm, rec_Gs, S_out, T_out, p->rpart);
         if (resid_out)
-            hipLaunchKernelGGL(k_finish_resid, dim3(n_iter + 1), dim3(256), 0, s,
+            hipLaunchKernelGGL(k_finish_resid, dim3(n_iter + 1), dim3(1024), 0, s,
                                (const double *)p->rpart, np, resid_out);
     }
     if (n_iter >= 2) {

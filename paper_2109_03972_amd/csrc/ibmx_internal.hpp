@@ -180,5 +180,22 @@ bool ibmx_fluid_ready(ibmx_plan p);
 ibmx_status ibmx_fluid_reserve(ibmx_plan p);
 void ibmx_exclusive_scan(const int *in, int *out, int n, int *aux, hipStream_t s);
 void ibmx_fill_i32(int *p, int v, long long n, hipStream_t s);
+// up to eight int arrays cleared by one launch
+struct ZeroList {
+    int *p[8];
+    long long n[8];
+    long long total;
+    int k;
+    void add(int *q, long long m)
+    {
+        if (m > 0 && k < 8) {
+            p[k] = q;
+            n[k] = m;
+            total += m;
+            ++k;
+        }
+    }
+};
+void ibmx_zero_i32_multi(const ZeroList &z, hipStream_t s);
 void ibmx_fill_f64(double *p, double v, long long n, hipStream_t s);
 void ibmx_fill_u8(uint8_t *p, uint8_t v, long long n, hipStream_t s);

@@ -434,8 +434,10 @@ extern "C" ibmx_status ibmx_pairs(ibmx_plan p, const double *xp, const double *r
     hipStream_t s = p->stream;
     ProfScope ps(p, IBMX_K_PAIRS);
     // cell list
-    ibmx_fill_i32(cell_start, 0, ncell + 1, s);
-    ibmx_fill_i32(p->p_cursor, 0, ncell, s);
+    ZeroList z = {};
+    z.add(cell_start, ncell + 1);
+    z.add(p->p_cursor, ncell);
+    ibmx_zero_i32_multi(z, s);
     if (np > 0)
         hipLaunchKernelGGL(k_cell_count, dim3(blocks(np)), dim3(256), 0, s, P, np, xp, radius,
                            rmax, p->p_cell_of, cell_start, p->d_err);

@@ -11,6 +11,23 @@ __global__ void k_fill_i32(int *p, int v, long long n)
         p[i] = v;
 }
 
+// several int arrays cleared to 0 by one launch (their index ranges laid end
+// to end)
+__global__ void k_zero_i32_multi(ZeroList z)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    int k = 0;
+    long long base = 0;
+    for (; i < z.total; i += stride) {
+        while (i >= base + z.n[k]) {
+            base += z.n[k];
+            ++k;
+        }
+        z.p[k][i - base] = 0;
+    }
+}
+
 __global__ void k_fill_f64(double *p, double v, long long n)
 {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -135,6 +152,12 @@ void ibmx_fill_i32(int *p, int v, long long n, hipStream_t s)
 {
     if (n > 0)
         hipLaunchKernelGGL(k_fill_i32, dim3(fill_blocks(n)), dim3(256), 0, s, p, v, n);
+}
+
+void ibmx_zero_i32_multi(const ZeroList &z, hipStream_t s)
+{
+    if (z.total > 0)
+        hipLaunchKernelGGL(k_zero_i32_multi, dim3(fill_blocks(z.total)), dim3(256), 0, s, z);
 }
 
 void ibmx_fill_f64(double *p, double v, long long n, hipStream_t s)
