@@ -738,12 +738,21 @@ __device__ __forceinline__ void region_base(const GridC &g, const TileBox &box, 
 // four-point delta), a node's sum is below n w_max m, so the scale
 // 2^(30 - ex - cb) with 2^cb >= n w_max keeps it below 2^30 (FP32: 32-bit
 // sums) and 2^(62 - ex - cb) below 2^62 (FP64: 64-bit sums).  No sum can
-// wrap, however dense the markers; the rounding of each term is at most half
-// an integer, 2^(ex + cb - 31) (2^(ex + cb - 63)) of m.  FP32 keeps (x, y)
-// of a node in one 64-bit word, y 2^32 + x as a two's-complement sum (exact
-// while both partial sums fit 32 bits, which the bound guarantees), and z in
-// a 32-bit word: two atomics per node.
+// wrap, however dense the markers; each term is rounded to the nearest
+// integer, at most 2^(ex + cb - 31) (2^(ex + cb - 63)) of m.  FP32
+// keeps (x, y) of a node in one 64-bit word, y 2^32 + x as a two's-complement
+// sum (exact while both partial sums fit 32 bits, which the bound
+// guarantees), and z in a 32-bit word: two atomics per node.
 // ---------------------------------------------------------------------------
+// floor(x + 1/2) by the hardware's single conversion instruction (|x| below
+// 2^31)
+__device__ __forceinline__ int round_half_up(float x)
+{
+    int r;
+    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
 __device__ __forceinline__ int cover_bits(int n)
 {
     // smallest cb >= 0 with 2^cb >= n * 8/27
@@ -757,6 +766,9 @@ __device__ __forceinline__ int cover_bits(int n)
 
 template <typename T>
 struct SpreadAcc;
+typedef __attribute__((address_space(3))) unsigned char lds_u8;
+typedef __attribute__((address_space(3))) int lds_i32;
+typedef __attribute__((address_space(3))) unsigned long long lds_u64;
 template <>
 struct SpreadAcc<float> {
     static constexpr int BYTES = 12;   // per node
@@ -775,11 +787,16 @@ struct SpreadAcc<float> {
     }
     __device__ static void add(unsigned char *lds, int V, int li, float vx, float vy, float vz)
     {
-        const int x = __float2int_rn(vx), y = __float2int_rn(vy), z = __float2int_rn(vz);
+        // nearest integer (halves up) in one conversion each; (x, y) as the
+        // 64-bit two's-complement value y 2^32 + x: low word x, high word y
+        // plus the sign extension of x
+        const int x = round_half_up(vx), y = round_half_up(vy), z = round_half_up(vz);
         const unsigned long long xy =
-            ((unsigned long long)(unsigned)y << 32) + (unsigned long long)(long long)x;
-        atomicAdd(&reinterpret_cast<unsigned long long *>(lds)[li], xy);
-        atomicAdd(&reinterpret_cast<int *>(lds)[2 * V + li], z);
+            ((unsigned long long)(unsigned)(y + (x >> 31)) << 32) | (unsigned)x;
+        lds_u64 *axy = (lds_u64 *)lds + li;
+        lds_i32 *az = (lds_i32 *)((lds_u8 *)lds + 8 * V) + li;
+        __hip_atomic_fetch_add(axy, xy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_add(az, z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
     // values of node li; false when all three sums are zero
     __device__ static bool get(const unsigned char *lds, int V, int li, const float *unscale,
