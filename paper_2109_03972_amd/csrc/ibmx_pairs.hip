@@ -315,6 +315,8 @@ __device__ __forceinline__ unsigned long long splitmix64(unsigned long long x)
 }
 
 // one wave per pair (wall entry); lanes take the chosen particle's markers
+constexpr int MUNR = 8;   // marker rounds per batch of offset loads in the mask kernels
+
 __global__ __launch_bounds__(256) void k_mask_pairs(PairC P, int np, int nm, const int *moff,
                                                     const double *body, const double *xp,
                                                     const double *radius, int mode,
@@ -338,22 +340,39 @@ __global__ __launch_bounds__(256) void k_mask_pairs(PairC P, int np, int nm, con
         centre(P, np, xp, partner, xq);
         double lim = radius[partner] + 2.0 * P.eps_sep;
         double lim2 = lim * lim;
-        for (int l = moff[chosen] + lane; l < moff[chosen + 1]; l += IBMX_WAVE) {
-            if (mode == 2) {
+        const int l1 = moff[chosen + 1];
+        if (mode == 2) {
+            for (int l = moff[chosen] + lane; l < l1; l += IBMX_WAVE)
                 mask[l] = 0;
-                continue;
+            continue;
+        }
+        // MUNR rounds of offsets loaded before any test, so that a large
+        // particle's markers cost few memory round trips
+        for (int l0 = moff[chosen] + lane; l0 < l1; l0 += MUNR * IBMX_WAVE) {
+            double o[MUNR][3];
+#pragma unroll
+            for (int r = 0; r < MUNR; ++r) {
+                const int l = l0 + r * IBMX_WAVE;
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    o[r][a] = l < l1 ? body[(size_t)a * nm + l] : 0.0;
             }
-            double d[3];
-            for (int a = 0; a < 3; ++a) {
-                d[a] = (xc[a] + body[(size_t)a * nm + l]) - xq[a];
-                if (P.periodic[a])
-                    d[a] = min_image(d[a], P.L[a]);
+#pragma unroll
+            for (int r = 0; r < MUNR; ++r) {
+                const int l = l0 + r * IBMX_WAVE;
+                double d[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    d[a] = (xc[a] + o[r][a]) - xq[a];
+                    if (P.periodic[a])
+                        d[a] = min_image(d[a], P.L[a]);
+                }
+                double d2 = d[0] * d[0];
+                d2 = d2 + d[1] * d[1];
+                d2 = d2 + d[2] * d[2];
+                if (l < l1 && d2 < lim2)
+                    mask[l] = 0;
             }
-            double d2 = d[0] * d[0];
-            d2 = d2 + d[1] * d[1];
-            d2 = d2 + d[2] * d[2];
-            if (d2 < lim2)
-                mask[l] = 0;
         }
     }
 }
@@ -372,15 +391,28 @@ __global__ __launch_bounds__(256) void k_mask_walls(PairC P, int np, int nm, con
         int p = walls[k], side = walls[cap + k];
         int ax = side / 2, upper = side % 2;
         double top = P.origin[ax] + P.L[ax];
-        for (int l = moff[p] + lane; l < moff[p + 1]; l += IBMX_WAVE) {
-            if (mode == 2) {
+        const int l1 = moff[p + 1];
+        if (mode == 2) {
+            for (int l = moff[p] + lane; l < l1; l += IBMX_WAVE)
                 mask[l] = 0;
-                continue;
+            continue;
+        }
+        const double xa = xp[(size_t)ax * np + p];
+        for (int l0 = moff[p] + lane; l0 < l1; l0 += MUNR * IBMX_WAVE) {
+            double o[MUNR];
+#pragma unroll
+            for (int r = 0; r < MUNR; ++r) {
+                const int l = l0 + r * IBMX_WAVE;
+                o[r] = l < l1 ? body[(size_t)ax * nm + l] : 0.0;
             }
-            double X = xp[(size_t)ax * np + p] + body[(size_t)ax * nm + l];
-            double dist = upper == 0 ? (X - P.origin[ax]) : (top - X);
-            if (dist < P.eps_sep)
-                mask[l] = 0;
+#pragma unroll
+            for (int r = 0; r < MUNR; ++r) {
+                const int l = l0 + r * IBMX_WAVE;
+                double X = xa + o[r];
+                double dist = upper == 0 ? (X - P.origin[ax]) : (top - X);
+                if (l < l1 && dist < P.eps_sep)
+                    mask[l] = 0;
+            }
         }
     }
 }
