@@ -78,11 +78,13 @@ extern "C" ibmx_status ibmx_forcing_graph(ibmx_plan p, void *u, void *f_tot, con
 // ---------------------------------------------------------------------------
 namespace {
 
-// tile shapes tried, largest first; ibmx_plan_alloc_tiles rejects the ones
-// whose LDS footprint does not fit the precision
+// tile shapes tried, the one that wins on dense beds in both precisions
+// first (a later one must beat the best so far by 2%);
+// ibmx_plan_alloc_tiles rejects the ones whose LDS footprint does not fit
+// the precision
 const int kTileCandidates[][3] = {
-    {16, 16, 8}, {16, 16, 16}, {32, 16, 8}, {32, 8, 8},  {32, 16, 4}, {32, 32, 4},
-    {16, 16, 4}, {16, 8, 8},   {8, 16, 8},  {16, 8, 16}, {8, 8, 8},   {32, 8, 16},
+    {32, 8, 8},  {16, 16, 8}, {16, 16, 16}, {32, 16, 8}, {32, 16, 4}, {32, 32, 4},
+    {16, 16, 4}, {16, 8, 8},  {8, 16, 8},   {16, 8, 16}, {8, 8, 8},   {32, 8, 16},
 };
 
 struct TuneScratch {
@@ -181,8 +183,7 @@ extern "C" ibmx_status ibmx_tune(ibmx_plan p, void *u, void *f_tot, const double
         return ok;
     };
     // tile shapes at 256 threads per workgroup, one workgroup per tile; a
-    // later candidate must win by 2% (timing noise keeps the earlier, larger
-    // shapes)
+    // later candidate must win by 2% (timing noise keeps the earlier shapes)
     p->block = 256;
     p->persist = 0;
     for (const auto &cand : kTileCandidates) {

@@ -19,7 +19,7 @@ from _util import rel_err, require_gpu
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
-BENCH_TILE = {"f32": (32, 8, 8), "f64": (16, 16, 8)}
+BENCH_TILE = {"f32": (32, 8, 8), "f64": (32, 8, 8)}
 TOL = {"f64": dict(U=1e-12, u=1e-12, f_tot=1e-12, S=1e-12, T=1e-12, resid=1e-12),
        "f32": dict(U=1e-5, u=1e-4, f_tot=1e-4, S=1e-4, T=1e-4, resid=1e-4)}
 
