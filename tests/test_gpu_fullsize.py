@@ -69,6 +69,39 @@ def test_bidisperse_bed_full_parity(precision):
 
 
 @pytest.fixture(scope="module")
+def bidisperse_kernel4():
+    """The bidisperse bed with the four-point delta (Sec. 2.2.3); its wider
+    support needs markers 2h from the walls, so eps_sep = 2h (and the pair
+    cut-off 2 eps_sep for the disable rule)."""
+    case = synth.make_case("bidisperse_bed_256x256x512")
+    case.params = dict(case.params, kernel=4, eps_sep=2.0, gap_cut=4.0)
+    mask = oracle.marker_mask(case, oracle.pairs(case))
+    ref = oracle.forcing(case, mask=mask, want_U=True)
+    return case, mask, ref
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_bidisperse_bed_kernel4_full_parity(precision, bidisperse_kernel4):
+    """Every output of the four-point path on a full bed (1.47M markers, five
+    passes) in the bench's tiles, element by element against the oracle."""
+    import torch
+    dev = require_gpu()
+    case, mask, ref = bidisperse_kernel4
+    print(f"bidisperse bed, four-point delta: active={int(mask.sum())}", flush=True)
+    u0 = torch.as_tensor(case.u0).to(dev)
+    _, u, f, S, Tq, resid, U = _gpu_run(case, precision, u0, torch.as_tensor(mask).to(dev), True)
+    act = mask.astype(bool)
+    got = dict(u=u.double().cpu().numpy(), f_tot=f.double().cpu().numpy(), S=S.cpu().numpy(),
+               T=Tq.cpu().numpy(), resid=resid.cpu().numpy(),
+               U=U.double().cpu().numpy()[:, :, act])
+    want = dict(ref, U=ref["U"][:, :, act])
+    for k, t in TOL[precision].items():
+        e = rel_err(got[k], want[k])
+        print(f"{precision} kernel 4 {k}: {e:.3e}", flush=True)
+        assert e <= t, f"{precision} kernel 4 {k}: {e:.3e} > {t}"
+
+
+@pytest.fixture(scope="module")
 def bed512():
     import torch
     dev = require_gpu()
