@@ -35,7 +35,7 @@ def _cotangents(case, rng, which=("g_f", "g_u", "g_S", "g_T")):
     return out
 
 
-def _gpu_backward(case, precision, mask, cot, plan=None):
+def _gpu_backward(case, precision, mask, cot, plan=None, tile=None):
     import torch
     from paper_2109_03972_amd import ibmx
     dev = require_gpu()
@@ -44,6 +44,8 @@ def _gpu_backward(case, precision, mask, cot, plan=None):
     if plan is None:
         plan = ibmx.Plan.from_case(case, precision)
         plan.set_markers(D["body"], D["dV"])
+    if tile is not None:
+        plan.set_tiles(*tile)
 
     def to(a, dt):
         return None if a is None else torch.as_tensor(a, dtype=torch.float64).to(dev).to(dt).contiguous()
@@ -131,6 +133,31 @@ def test_backward_small_f32(oracle_lib):
     ref = oracle_lib.forcing_adjoint(case, u0=u0, mask=mask, **cot32)
     got = _gpu_backward(case, "f32", mask, cot)
     _compare(got, ref, TOL32, "f32 small")
+
+
+@pytest.fixture(scope="module")
+def bidisperse_adjoint():
+    """The bidisperse bed (1.47M markers, five passes, walls in z) with its
+    pair-pass mask and seeded cotangents of all four outputs."""
+    case = synth.make_case("bidisperse_bed_256x256x512")
+    return case, _mask_for(case), _cotangents(case, np.random.default_rng(2109))
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_backward_bidisperse_bed_full(oracle_lib, precision, bidisperse_adjoint):
+    """The adjoint of a full bed call in the bench's tiles against the
+    oracle's adjoint: every gradient element by element (FP32: the oracle on
+    the FP32-rounded velocity and grid cotangents the kernels see)."""
+    case, mask, cot = bidisperse_adjoint
+    u0, cot_ref = case.u0, dict(cot)
+    if precision == "f32":
+        u0 = case.u0.astype(np.float32).astype(np.float64)
+        for k in ("g_f", "g_u"):
+            cot_ref[k] = cot[k].astype(np.float32).astype(np.float64)
+    print(f"bidisperse bed adjoint {precision}: nm={case.nm} active={int(mask.sum())}", flush=True)
+    ref = oracle_lib.forcing_adjoint(case, u0=u0, mask=mask, **cot_ref)
+    got = _gpu_backward(case, precision, mask, cot, tile=(32, 8, 8))
+    _compare(got, ref, TOL64 if precision == "f64" else TOL32, f"{precision} bidisperse bed")
 
 
 def _gradient_case():
