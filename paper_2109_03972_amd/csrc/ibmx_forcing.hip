@@ -1970,7 +1970,8 @@ extern "C" ibmx_status ibmx_forcing(ibmx_plan p, void *u, void *f_tot, const dou
         return IBMX_ESTATE;
     if (!u || !f_tot || (p->np > 0 && (!xp || !up || !wp || !S_out || !T_out)))
         return IBMX_EINVAL;
-    if (p->prm.n_iter + 1 > 64)
+    // the particle sums keep n_iter + 1 residual slots per wave in LDS
+    if (p->prm.n_iter < 1 || p->prm.n_iter > IBMX_MAX_PASSES)
         return IBMX_EINVAL;
     const int W = p->prm.kernel;
     if (p->prec == IBMX_F64) {

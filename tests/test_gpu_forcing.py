@@ -70,6 +70,18 @@ def test_small_ragged_cases(seed, periodic, kernel, precision):
     _compare(c, precision, mask=mask)
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_maximum_passes(precision):
+    """The largest pass count a plan takes (64): per-pass amplitude records,
+    residual slots and sums at their full size, on a ragged grid with walls."""
+    c = synth.small_case(106, n=(41, 37, 45), periodic=(1, 1, 0),
+                         diameters=(12.0, 9.0, 7.0, 10.0), n_iter=64, touch=0.3)
+    got, ref = _compare(c, precision, mask=_mask_for(c))
+    assert got["resid"].shape == (65,)
+    # the passes keep reducing the residual (Sec. 2.2.2)
+    assert np.all(np.diff(ref["resid"]) <= 0.0)
+
+
 def test_no_mask_and_all_masked():
     c = synth.small_case(106, n=(33, 35, 31), periodic=(1, 1, 1), disable_mode=0, n_iter=2)
     _compare(c, "f64")
