@@ -90,6 +90,24 @@ def test_backward_small_f64(oracle_lib, seed, n, per, kernel, n_iter, masked):
     _compare(got, ref, TOL64, f"f64 seed {seed}")
 
 
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_backward_maximum_passes(oracle_lib, precision):
+    """The adjoint at the largest pass count a plan takes (64 passes of
+    per-marker amplitudes and Jacobians replayed and reversed)."""
+    case = synth.small_case(46, n=(40, 36, 44), periodic=(1, 1, 0), n_iter=64, touch=0.3)
+    rng = np.random.default_rng(146)
+    cot = _cotangents(case, rng)
+    mask = _mask_for(case)
+    u0, cot_ref = case.u0, dict(cot)
+    if precision == "f32":
+        u0 = case.u0.astype(np.float32).astype(np.float64)
+        for k in ("g_f", "g_u"):
+            cot_ref[k] = cot[k].astype(np.float32).astype(np.float64)
+    ref = oracle_lib.forcing_adjoint(case, u0=u0, mask=mask, **cot_ref)
+    got = _gpu_backward(case, precision, mask, cot)
+    _compare(got, ref, TOL64 if precision == "f64" else TOL32, f"{precision} 64 passes")
+
 @pytest.mark.parametrize("which", [("g_f",), ("g_u",), ("g_S",), ("g_T",), ("g_S", "g_T")])
 def test_backward_cotangent_subsets(oracle_lib, which):
     case = synth.small_case(51, n=(38, 40, 42), periodic=(1, 1, 0), n_iter=2, touch=0.4)
