@@ -157,6 +157,27 @@ def test_tile_shapes_parity(oracle_lib, tile, n):
             assert e <= tol, f"{precision} tile {tile} {k}: {e:.3e}"
 
 
+@pytest.mark.parametrize("tile", [(4, 4, 4), (60, 4, 8), (32, 8, 8)])
+def test_tile_shapes_parity_four_point(oracle_lib, tile):
+    """The four-point delta (a 4-node support on 4-node tile edges, and the
+    whole x extent in one tile) with walls in z; the grid's edges are
+    multiples of 4, so the requested shapes are used as they are."""
+    dev = require_gpu()
+    case = synth.small_case(76, n=(48, 40, 44), periodic=(1, 1, 0), n_iter=2, touch=0.4)
+    case.params.update(kernel=4, eps_sep=2.0, lub_C=4.0, gap_cut=4.0)
+    m_np, mk = _mask(case, dev)
+    ref = oracle_lib.forcing(case, mask=m_np, kernel=4)
+    for precision, tol in (("f64", 1e-12), ("f32", 1e-4)):
+        plan, D = _setup(case, precision)
+        plan.set_tiles(*tile)
+        got = _run(plan, D, D["u"].clone(), mk, False)
+        print(precision, tile, plan.stats()["tile"], flush=True)
+        assert plan.stats()["tile"] == (min(tile[0], 48),) + tuple(tile[1:])
+        for k in ("u", "f_tot", "S", "T"):
+            e = rel_err(got[k], ref[k])
+            assert e <= tol, f"{precision} tile {tile} {k}: {e:.3e}"
+
+
 def test_set_tiles_rejects_bad_shapes():
     from paper_2109_03972_amd import ibmx
     require_gpu()
