@@ -172,8 +172,10 @@ enum {
  *   precision           IBMX_F64 or IBMX_F32.
  *   hip_stream          hipStream_t (NULL = default stream) used by every
  *                       call on this plan.
- * Allocates all device workspace.  Returns EINVAL, ENOMEM, EDEVICE or
- * EUNSUPPORTED (kernel other than 3/4, normal_model other than 0/1).
+ * Allocates all device workspace.  Returns EINVAL (among others for a
+ * periodic axis of fewer than 2 * kernel nodes, where a support would meet
+ * itself across the seam), ENOMEM, EDEVICE or EUNSUPPORTED (kernel other
+ * than 3/4, normal_model other than 0/1).
  * With normal_model 1 the plan solves the ACTM equation for e_dry on the
  * host (a few milliseconds), here and in ibmx_plan_set_params.
  */

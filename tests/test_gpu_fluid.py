@@ -41,7 +41,10 @@ def _run(case, precision, u_np, P_np, theta):
                                         ((8, 32, 1), (1, 1, 0)), ((8, 8, 64), (1, 1, 1)),
                                         ((64, 32, 20), (1, 1, 0)), ((16, 8, 70), (1, 1, 0)),
                                         # the bed's 512-point FFT lines, periodic and walled
-                                        ((512, 512, 8), (1, 1, 1)), ((512, 512, 16), (1, 1, 0))])
+                                        ((512, 512, 8), (1, 1, 1)), ((512, 512, 16), (1, 1, 0)),
+                                        # the longest lines the solver takes (the shortest
+                                        # periodic ones, 8 points, are above)
+                                        ((1024, 8, 8), (1, 1, 1)), ((8, 1024, 5), (1, 1, 0))])
 @pytest.mark.parametrize("theta", [0.0, 1.0])
 def test_projection_parity_f64(n, periodic, theta):
     case = _case(n, periodic, seed=sum(n))
@@ -127,7 +130,8 @@ def _stage_inputs(shape, seed):
 @pytest.mark.parametrize("n,periodic", [((16, 8, 8), (1, 1, 1)), ((32, 16, 13), (1, 1, 0)),
                                         ((8, 32, 1), (1, 1, 0)), ((64, 32, 20), (1, 1, 0)),
                                         ((16, 8, 70), (1, 1, 0)),
-                                        ((512, 512, 8), (1, 1, 1)), ((512, 512, 16), (1, 1, 0))])
+                                        ((512, 512, 8), (1, 1, 1)), ((512, 512, 16), (1, 1, 0)),
+                                        ((1024, 8, 8), (1, 1, 1)), ((8, 1024, 5), (1, 1, 0))])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 @pytest.mark.parametrize("theta", [0.0, 1.0])
 def test_predictor_helmholtz_parity(n, periodic, precision, theta):
