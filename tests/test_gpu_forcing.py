@@ -133,6 +133,28 @@ def test_no_particles(precision):
     assert res["counts"].cpu().tolist() == [0, 0]
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_particles_without_markers(precision):
+    """Particles whose marker range is empty (marker_offset repeats) between
+    particles that have markers: their sums are zero, the rest matches the
+    oracle."""
+    c = synth.small_case(109, n=(40, 36, 44), periodic=(1, 1, 1), n_iter=2)
+    keep = [p for p in range(c.np_) if p % 2 == 0]
+    assert 0 < len(keep) < c.np_
+    segs = [np.arange(c.moff[p], c.moff[p + 1]) if p in keep else np.arange(0)
+            for p in range(c.np_)]
+    moff = np.zeros(c.np_ + 1, dtype=np.int32)
+    moff[1:] = np.cumsum([len(g) for g in segs])
+    idx = np.concatenate(segs)
+    holed = synth.Case(name="holed", n=c.n, h=c.h, origin=c.origin, periodic=c.periodic,
+                       xp=c.xp, up=c.up, wp=c.wp, radius=c.radius, mass=c.mass, moff=moff,
+                       body=np.ascontiguousarray(c.body[:, idx]), dV=c.dV, u0=c.u0,
+                       params=dict(c.params, disable_mode=0))
+    got, ref = _compare(holed, precision)
+    empty = [p for p in range(c.np_) if p not in keep]
+    assert not np.any(got["S"][:, empty]) and not np.any(got["T"][:, empty])
+
+
 @pytest.mark.parametrize("name", ["suspension_128", "small"])
 def test_f32_arithmetic_and_end_to_end_errors(name):
     """FP32 forward errors of every output measured two ways:
