@@ -57,6 +57,49 @@ def _check(case, got, prev_host=None, ftol=1e-12):
     return ref_l, ref_f
 
 
+def test_exact_regime_boundaries():
+    """Gaps exactly on the regime boundaries (Sec. 2.2.5-2.2.7, reading
+    c-13 and the disable threshold): touching spheres (gap 0: lubrication at
+    zeta_min), a gap of exactly eps_sep (no force), exactly 2 eps_sep (the
+    list's cut-off, strict: not listed), a slight overlap, and the same
+    against a wall (gap 0 and eps_sep).  Binary-exact positions make every
+    gap exact in FP64 on both sides."""
+    R = 4.0
+    rows = [(10.0, 18.0), (10.0, 19.5), (10.0, 21.0), (10.0, 17.75)]   # x pairs, gap 0 / 1.5 / 3 / -0.25
+    xs, ys, zs = [], [], []
+    for k, (a, b) in enumerate(rows):
+        for x in (a, b):
+            xs.append(x)
+            ys.append(8.0 + 16.0 * k)
+            zs.append(32.0)
+    for k, z in enumerate((R, R + 1.5)):                                # wall gap 0 and eps_sep
+        xs.append(40.0)
+        ys.append(8.0 + 16.0 * k)
+        zs.append(z)
+    xp = np.array([xs, ys, zs])
+    npart = xp.shape[1]
+    diam = np.full(npart, 2.0 * R)
+    rng = np.random.Generator(np.random.PCG64(211))
+    moff, body, dV = synth.build_markers(diam, 1.0, rng)
+    prm = synth.default_params()
+    prm.update(disable_mode=1, eps_sep=1.5, gap_cut=3.0)
+    case = synth.Case(name="boundaries", n=(64, 64, 64), h=1.0, origin=(0.0, 0.0, 0.0),
+                      periodic=(1, 1, 0), xp=xp, up=rng.normal(0.0, 0.1, (3, npart)),
+                      wp=rng.normal(0.0, 0.05, (3, npart)), radius=0.5 * diam,
+                      mass=1.3 * np.pi / 6.0 * diam ** 3, moff=moff, body=body, dV=dV,
+                      u0=None, params=prm)
+    got = _gpu_pairs(case)
+    ref_l, ref_f = _check(case, got)
+    assert got["pairs"].T.tolist() == [[0, 1], [2, 3], [6, 7]]
+    assert got["gap"].tolist() == [0.0, 1.5, -0.25]
+    assert got["walls"].T.tolist() == [[8, 4], [9, 4]]
+    assert got["wgap"].tolist() == [0.0, 1.5]
+    # forces on the touching pair and the wall contact at gap 0 only
+    # (the overlap also has its contact force); none at exactly eps_sep
+    assert np.all(got["Fc"][:, [2, 3, 9]] == 0.0)
+    assert np.any(got["Fc"][:, [0, 1, 6, 7, 8]] != 0.0, axis=0).all()
+
+
 @pytest.mark.parametrize("name", ["suspension_128", "bidisperse_bed_256x256x512",
                                   "polydisperse_bed_512"])
 def test_workload_pairs(name):
