@@ -100,6 +100,29 @@ def test_exact_regime_boundaries():
     assert np.any(got["Fc"][:, [0, 1, 6, 7, 8]] != 0.0, axis=0).all()
 
 
+def test_half_box_separation():
+    """Two spheres exactly half a periodic box apart along x, and a pair
+    across the x seam: the minimum image (reading c-17) keeps +L/2 as it
+    is, so both sides list the same pair with the same gap."""
+    R = 14.0
+    xp = np.array([[0.5, 32.5, 62.0, 2.5], [16.0, 16.0, 48.0, 48.0], [32.0, 32.0, 32.0, 32.0]])
+    diam = np.array([2.0 * R, 2.0 * R, 4.0, 4.0])
+    npart = xp.shape[1]
+    rng = np.random.Generator(np.random.PCG64(212))
+    moff, body, dV = synth.build_markers(diam, 1.0, rng)
+    prm = synth.default_params()
+    prm.update(disable_mode=1, eps_sep=1.5, gap_cut=5.0)
+    case = synth.Case(name="half_box", n=(64, 64, 64), h=1.0, origin=(0.0, 0.0, 0.0),
+                      periodic=(1, 1, 1), xp=xp, up=rng.normal(0.0, 0.1, (3, npart)),
+                      wp=rng.normal(0.0, 0.05, (3, npart)), radius=0.5 * diam,
+                      mass=1.3 * np.pi / 6.0 * diam ** 3, moff=moff, body=body, dV=dV,
+                      u0=None, params=prm)
+    got = _gpu_pairs(case)
+    _check(case, got)
+    assert got["pairs"].T.tolist() == [[0, 1], [2, 3]]
+    assert got["gap"].tolist() == [32.0 - 2.0 * R, 4.5 - 4.0]
+
+
 @pytest.mark.parametrize("name", ["suspension_128", "bidisperse_bed_256x256x512",
                                   "polydisperse_bed_512"])
 def test_workload_pairs(name):
