@@ -93,6 +93,32 @@ def test_graph_recaptures_on_new_pointers_and_params(oracle_lib):
         assert rel_err(got3[k], ref3[k]) <= 1e-12, k
 
 
+def test_switching_delta_kernel_on_a_plan(oracle_lib):
+    """ibmx_plan_set_params from the three- to the four-point delta and back
+    on one plan (eager and graph calls; the captured graph is dropped with
+    the old parameters): each call matches the oracle with that kernel."""
+    dev = require_gpu()
+    case = synth.small_case(77, n=(40, 36, 44), periodic=(1, 1, 0), n_iter=2, touch=0.4)
+    p3 = dict(case.params)
+    p4 = dict(p3, kernel=4, eps_sep=2.0, lub_C=4.0, gap_cut=4.0)
+    m_np, mk = _mask(case, dev)          # the wider mask of the four-point parameters
+    case.params = p4
+    m4, mk4 = _mask(case, dev)
+    case.params = p3
+    plan, D = _setup(case, "f64")
+    u0 = D["u"].clone()
+    for prm, mask_np, mask_dev in ((p3, m_np, mk), (p4, m4, mk4), (p3, m_np, mk)):
+        plan.set_params(prm)
+        case.params = prm
+        ref = oracle_lib.forcing(case, mask=mask_np)
+        for graph in (False, True):
+            got = _run(plan, D, u0, mask_dev, graph)
+            for k in ("u", "f_tot", "S", "T"):
+                e = rel_err(got[k], ref[k])
+                assert e <= 1e-12, f"kernel {prm['kernel']} graph {graph} {k}: {e:.3e}"
+    case.params = p3
+
+
 def test_graph_profiled_as_one_class():
     dev = require_gpu()
     case = synth.small_case(73, n=(36, 36, 40), periodic=(1, 1, 0), n_iter=2)
