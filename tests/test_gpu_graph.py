@@ -119,6 +119,28 @@ def test_switching_delta_kernel_on_a_plan(oracle_lib):
     case.params = p3
 
 
+def test_new_marker_offsets_drop_the_graph(oracle_lib):
+    """Markers turn with their particle between steps: new body offsets set
+    on a plan whose call was captured must be the ones the next graph call
+    uses."""
+    import torch
+    dev = require_gpu()
+    case = synth.small_case(78, n=(40, 36, 44), periodic=(1, 1, 0), n_iter=2, touch=0.4)
+    m_np, mk = _mask(case, dev)
+    plan, D = _setup(case, "f64")
+    u0 = D["u"].clone()
+    _run(plan, D, u0, mk, True)
+    th = 0.3
+    rot = np.array([[np.cos(th), -np.sin(th), 0.0], [np.sin(th), np.cos(th), 0.0], [0.0, 0.0, 1.0]])
+    body2 = rot @ case.body
+    plan.set_markers(torch.as_tensor(body2).to(dev).contiguous(), D["dV"])
+    got = _run(plan, D, u0, mk, True)
+    case2 = synth.Case(**{**case.__dict__, "body": np.ascontiguousarray(body2)})
+    ref = oracle_lib.forcing(case2, mask=m_np)
+    for k in ("u", "f_tot", "S", "T"):
+        assert rel_err(got[k], ref[k]) <= 1e-12, k
+
+
 def test_graph_profiled_as_one_class():
     dev = require_gpu()
     case = synth.small_case(73, n=(36, 36, 40), periodic=(1, 1, 0), n_iter=2)
