@@ -91,7 +91,7 @@ typedef struct {
     int32_t kernel;          /* 3: three-point delta (Sec. 2.1), 4: four-point
                                 (Sec. 2.2.3)                                   */
     int32_t n_iter;          /* interpolate-force-spread-update passes per
-                                call (n_f + 1 in the paper's count)           */
+                                call (n_f + 1 in the paper's count), 1..64   */
     double two_alpha_dt;     /* c = 2 alpha_k dt of the current RK sub-step    */
     double rho_f;            /* fluid density                                  */
     double nu_f;             /* kinematic viscosity                            */
