@@ -523,6 +523,11 @@ def main():
                            "passes with the Jacobians, adjoint passes; not part of the step"),
         pass_rate=n_act * n_iter / (sum(km[k] for k in ("interp", "spread")) / steps_done
                                     * 1e-3),
+        # the call's rate per pass with its once-per-call work other than the
+        # binning (f_tot, final residual, particle sums) spread over the
+        # passes: N / ((graph step - pair pass - binning) / n_iter)
+        pass_rate_call=n_act * n_iter / ((r32["ms_per_step_graph"] - per_launch["pairs"]
+                                          - per_launch["geometry"]) * 1e-3),
     )
     print(json.dumps(line), flush=True)
 
