@@ -238,19 +238,23 @@ def test_set_tiles_rejects_bad_shapes():
         assert plan.stats()["tile"] == before
 
 
+@pytest.mark.parametrize("kernel,tile", [(3, (8, 8, 8)), (4, (32, 8, 8))])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-def test_launch_forms_bit_identical(oracle_lib, precision):
+def test_launch_forms_bit_identical(oracle_lib, precision, kernel, tile):
     """Every workgroup size the tuner tries (64, 128, 256 threads: the markers
     a tile's workgroup takes at once) and both launch forms (one workgroup
     per tile; a persistent grid looping over the tiles) give the same bits,
-    eager and replayed as a graph, and match the oracle."""
+    eager and replayed as a graph, and match the oracle; with both delta
+    kernels."""
     import torch
     dev = require_gpu()
     case = synth.small_case(76, n=(44, 40, 46), periodic=(1, 1, 0), n_iter=3, touch=0.4)
+    if kernel == 4:
+        case.params.update(kernel=4, eps_sep=2.0, lub_C=4.0, gap_cut=4.0)
     m_np, mk = _mask(case, dev)
     ref = oracle_lib.forcing(case, mask=m_np)
     plan, D = _setup(case, precision)
-    plan.set_tiles(8, 8, 8)
+    plan.set_tiles(*tile)
     u0 = D["u"].clone()
     resid = torch.zeros(int(case.params["n_iter"]) + 1, dtype=torch.float64, device=dev)
     base = _run(plan, D, u0, mk, False, resid)
