@@ -178,6 +178,28 @@ def test_backward_bidisperse_bed_full(oracle_lib, precision, bidisperse_adjoint)
     _compare(got, ref, TOL64 if precision == "f64" else TOL32, f"{precision} bidisperse bed")
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_backward_launch_forms_bit_identical(precision):
+    """The adjoint replays the forward passes and spreads the interpolation
+    cotangents with the plan's launch form: every form gives the same bits."""
+    import torch
+    from paper_2109_03972_amd import ibmx
+    dev = require_gpu()
+    case = synth.small_case(47, n=(44, 40, 46), periodic=(1, 1, 0), n_iter=3, touch=0.4)
+    cot = _cotangents(case, np.random.default_rng(147))
+    mask = _mask_for(case)
+    D = dev_case(case, precision)
+    plan = ibmx.Plan.from_case(case, precision)
+    plan.set_markers(D["body"], D["dV"])
+    plan.set_tiles(8, 8, 8)
+    base = _gpu_backward(case, precision, mask, cot, plan=plan)
+    for block, persistent in ((64, True), (128, False), (256, True)):
+        plan.set_launch(block, persistent)
+        got = _gpu_backward(case, precision, mask, cot, plan=plan)
+        for k in ("gu0", "gxp", "gup", "gwp"):
+            np.testing.assert_array_equal(got[k], base[k], err_msg=f"{block} {persistent} {k}")
+
+
 def _gradient_case():
     case = synth.make_case("gradient_suspension_128")
     assert case.loss_b is not None
