@@ -56,7 +56,7 @@ def test_suspension_128(precision):
 
 @pytest.mark.parametrize("seed,periodic,kernel", [
     (101, (1, 1, 0), 3), (102, (1, 1, 1), 3), (103, (0, 1, 0), 3), (104, (1, 1, 0), 4),
-    (105, (1, 1, 1), 4),
+    (105, (1, 1, 1), 4), (110, (0, 0, 0), 3), (111, (0, 0, 1), 4),
 ])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_small_ragged_cases(seed, periodic, kernel, precision):
